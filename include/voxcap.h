@@ -1,0 +1,167 @@
+/* voxcap.h -- C ABI of the MI355X FFT-accelerated capacitance solver for voxelized
+ * conductor / dielectric structures (VoxCap, Wang, Qian, White, Yucel).
+ *
+ * Problem statement (Sec. II.A): a box of nx*ny*nz cubic voxels of edge dv holds
+ * conductors (dense ids 0..m-1) and non-conductor voxels of relative permittivity
+ * eps_r; outside the box is a background of relative permittivity eps_background.
+ * Charges live on piecewise-constant panels (eq. 3): every voxel face between a
+ * conductor and a non-conductor, and every face between two non-conductors of
+ * different permittivity.  The Galerkin system of eq. (4) -- potentials on conductor
+ * panels (eq. 5), normal-field continuity with the jump term on dielectric panels
+ * (eq. 6, eq. 7) -- is solved once per conductor held at unit potential (text after
+ * eq. 7), and the capacitance matrix follows from eq. (8) with the free-charge
+ * scaling of Sec. II.A.
+ *
+ * Conventions used by every call:
+ *  - Arrays of voxels are C ordered, x slowest: index (i*ny + j)*nz + k.
+ *  - Dimensionless form: voxel edge 1 and 4*pi*eps0 = 1.  The operator A applied by
+ *    vc_apply is the matrix of eq. (4) in that form, in the library's panel order,
+ *    with dielectric rows written for the +axis normal: its diagonal is
+ *    2*pi*(eps_lo+eps_hi)/(eps_lo-eps_hi) and its field integral is taken along
+ *    +axis (this is the paper's row multiplied by +-1, Sec. II.B note 3; the
+ *    solution is the same).  The right-hand side of conductor i is 1 on the panels
+ *    of conductor i and 0 elsewhere.  C_ij = 4*pi*eps0*dv * sum_{k in i} eps_adj(k) *
+ *    rho_k^(j) in farads.
+ *  - Panel order: sorted by (normal axis, i, j, k).
+ *  - "_dev" pointers are device pointers on the problem's device; the caller owns
+ *    them and keeps them alive until the given stream has finished with them.
+ *    "hip_stream" is a hipStream_t (NULL = the null stream).
+ *  - Every call returns a vc_status; on failure vc_last_error() gives a message
+ *    (thread local).  A VC_ERR_HIP failure leaves the problem unusable.
+ *  - One vc_problem must not be used from two threads at once.
+ */
+#ifndef VOXCAP_H
+#define VOXCAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VC_OK = 0,
+  VC_ERR_ARG = -1,           /* bad argument or size                                    */
+  VC_ERR_GEOMETRY = -2,      /* touching conductors, eps <= 0, no conductor, bad ids     */
+  VC_ERR_HIP = -3,           /* HIP runtime error (sticky for the problem)               */
+  VC_ERR_OOM = -4,           /* device or host allocation failed                         */
+  VC_ERR_NOT_CONVERGED = -5, /* iteration limit hit; outputs hold the last iterate       */
+  VC_ERR_NUMERIC = -6,       /* NaN/Inf or breakdown in the iteration                    */
+  VC_ERR_STATE = -7          /* call order violated (e.g. apply before setup)            */
+} vc_status;
+
+typedef enum {
+  VC_FP64 = 0,   /* FFT, block multiply and kernel spectra in double                      */
+  VC_FP32 = 1,   /* FFT and block multiply in float, FP64 in/out and FP64 diagonal term    */
+  VC_MIXED = 2   /* solves only: FP32 inner GMRES inside FP64 iterative refinement        */
+} vc_precision;
+
+typedef struct vc_problem vc_problem;
+
+/* Voxel geometry.  cond_id: nx*ny*nz ids, -1 = not a conductor, else 0..m-1 (every id
+ * used).  eps_r: nx*ny*nz relative permittivities (> 0) of non-conductor voxels (read
+ * only where cond_id == -1).  dv: voxel edge in metres (> 0). */
+typedef struct {
+  int32_t nx, ny, nz;
+  double dv;
+  const int32_t *cond_id;
+  const double *eps_r;
+  double eps_background;
+} vc_geometry;
+
+/* One panel (Sec. II.A eq. 3).  The face lies at coordinate i (dir 0), j (dir 1) or
+ * k (dir 2) along its normal axis and spans [idx, idx+1] along the other two.
+ * kind 0 = conductor (cond = id, eps_adj = permittivity of the non-conductor side),
+ * kind 1 = dielectric (cond = -1, eps_adj = 0).  eps_lo / eps_hi: permittivity on the
+ * -axis / +axis side (0 on a conductor side). */
+typedef struct {
+  int32_t i, j, k;
+  int8_t dir, kind;
+  int16_t pad;
+  int32_t cond;
+  double eps_lo, eps_hi, eps_adj;
+} vc_panel;
+
+/* Setup options.  fft_size[a] = 0 chooses the smallest even 7-smooth size >= 2*n_a+1
+ * (any size >= 2*n_a+1 gives the same product, the paper uses 2*(n_a+1), Sec. II.B).
+ * nv[a] = voxels per preconditioner box along a (Sec. II.D; 0 = 8).  tucker_tol > 0
+ * compresses the kernel spectra (eq. 13) and rebuilds them for each product;
+ * 0 keeps them uncompressed.  precisions: bit mask of (1<<VC_FP64)|(1<<VC_FP32)
+ * spectra to keep (0 = both). */
+typedef struct {
+  int32_t fft_size[3];
+  int32_t nv[3];
+  double tucker_tol;
+  int32_t precisions;
+  int32_t max_rhs;     /* largest nrhs later passed to vc_apply (0 = m)              */
+} vc_setup_opts;
+
+/* Solve options.  GMRES(restart) with the block-diagonal-diagonal preconditioner
+ * (Sec. II.D) applied on the right; stops when ||b - A x|| <= rtol ||b|| per column.
+ * VC_MIXED runs FP32 inner GMRES (inner_rtol) inside FP64 refinement (ir_max outer
+ * steps).  0 picks defaults (rtol 1e-12, restart 35, max_iter 2000, inner_rtol 1e-5,
+ * ir_max 20). */
+typedef struct {
+  vc_precision prec;
+  double rtol;
+  int32_t restart, max_iter;
+  double inner_rtol;
+  int32_t ir_max;
+  int32_t use_precond;   /* 1 = block-diagonal-diagonal (default), 0 = none, 2 = diagonal only */
+} vc_solve_opts;
+
+typedef struct {
+  int32_t iters[64];          /* GMRES iterations per right-hand side (first 64)   */
+  double final_rre[64];       /* true relative residual per right-hand side        */
+  int32_t ir_steps;           /* refinement steps (VC_MIXED)                        */
+  int32_t mvp_count;          /* batched operator applications                      */
+  double t_setup_s, t_solve_s;
+  double spectra_bytes;       /* device bytes held by the kernel spectra            */
+  int32_t tucker_rank_max;
+} vc_stats;
+
+/* Copy the geometry, extract the panels and validate (host only, no GPU work).
+ * device: HIP device ordinal used by later calls. */
+vc_status vc_problem_create(const vc_geometry *geom, int device, vc_problem **out);
+vc_status vc_problem_destroy(vc_problem *p);
+vc_status vc_panel_counts(const vc_problem *p, int64_t *n_cond, int64_t *n_diel, int32_t *m);
+/* out: caller-allocated host array of n_cond + n_diel panels, library order. */
+vc_status vc_panels(const vc_problem *p, vc_panel *out);
+/* FFT grid sizes chosen by vc_setup (or the ones it will choose). */
+vc_status vc_fft_size(const vc_problem *p, int32_t out_m[3]);
+
+/* Build the kernel spectra (App. B tensors, FFT'ed; Sec. II.B), the optional Tucker
+ * compression (Sec. II.C) and the preconditioner blocks (Sec. II.D) on the device. */
+vc_status vc_setup(vc_problem *p, const vc_setup_opts *opts, void *hip_stream);
+
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1), eq. (4) via eq. (11).
+ * x_dev, y_dev: N x nrhs doubles, column-major (column r at offset r*N), N = panels.
+ * prec: VC_FP64 or VC_FP32 arithmetic inside the FFT product. */
+vc_status vc_apply(vc_problem *p, int transpose, vc_precision prec, const double *x_dev,
+                   double *y_dev, int32_t nrhs, void *hip_stream);
+
+/* y = R x with the block-diagonal-diagonal preconditioner R of eq. (14)
+ * (R^T when transpose = 1; the blocks are symmetric). */
+vc_status vc_apply_precond(vc_problem *p, int transpose, const double *x_dev, double *y_dev,
+                           int32_t nrhs, void *hip_stream);
+
+/* Capacitance matrix C (m x m, row-major, farads) by one solve per conductor, all m
+ * right-hand sides advancing together.  rho_dev: optional N x m device output of the
+ * dimensionless charges.  stats: optional. */
+vc_status vc_capacitance(vc_problem *p, const vc_solve_opts *opts, double *C, double *rho_dev,
+                         vc_stats *stats);
+
+/* dC/d(eps_r of block b) for every block (nblocks x m x m, row-major, farads per unit
+ * relative permittivity) by one adjoint solve per conductor (A^T lambda_i = w_i).
+ * block_of_voxel: nx*ny*nz host ids in [-1, nblocks).  C_out: optional m x m. */
+vc_status vc_capacitance_grad_eps(vc_problem *p, const vc_solve_opts *opts,
+                                  const int32_t *block_of_voxel, int32_t nblocks,
+                                  double *dC, double *C_out, vc_stats *stats);
+
+const char *vc_status_string(vc_status s);
+const char *vc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VOXCAP_H */

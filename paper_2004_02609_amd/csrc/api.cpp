@@ -1,0 +1,545 @@
+// C ABI of the solver (include/voxcap.h): problem lifecycle, GMRES driver (restarted,
+// several right-hand sides in lock-step, right-preconditioned with eq. (14)), FP32/FP64
+// iterative refinement, capacitance of eq. (8) and its adjoint permittivity derivative.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mvp_kernels.h"
+#include "problem.h"
+
+namespace vc {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+static const double kEps0 = 8.8541878128e-12;   // F/m
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------------------------ GMRES
+struct SolveSpec {
+  vc_precision mvp;     // VC_FP64 or VC_FP32 product
+  int transpose;
+  int precond;          // 0 none, 1 block-diagonal-diagonal, 2 diagonal
+  double rtol;
+  int restart, max_iter;
+};
+
+static vc_status ensure_workspace(vc_problem* P, int nrhs, int restart) {
+  if (P->s_nrhs >= nrhs && P->s_restart >= restart) return VC_OK;
+  const int64_t N = npanels(P);
+  const int r = std::max(restart, P->s_restart), k = std::max(nrhs, P->s_nrhs);
+  VC_HIP(P->s_V.alloc((size_t)(r + 1) * k * N * sizeof(double)));
+  VC_HIP(P->s_w.alloc((size_t)k * N * sizeof(double)));
+  VC_HIP(P->s_z.alloc((size_t)k * N * sizeof(double)));
+  VC_HIP(P->s_r.alloc((size_t)k * N * sizeof(double)));
+  VC_HIP(P->s_b.alloc((size_t)k * N * sizeof(double)));
+  VC_HIP(P->s_x.alloc((size_t)k * N * sizeof(double)));
+  VC_HIP(P->s_tmp.alloc((size_t)k * N * sizeof(double)));
+  VC_HIP(P->s_h.alloc((size_t)2 * (r + 2) * k * sizeof(double)));
+  VC_HIP(P->s_y2.alloc((size_t)(r + 2) * k * sizeof(double)));
+  VC_HIP(P->s_partial.alloc((size_t)gemv_t_partial_size(N, r + 2, k) * sizeof(double)));
+  VC_HIP(P->s_norm.alloc((size_t)2 * k * sizeof(double)));
+  VC_HIP(P->s_active.alloc((size_t)k * sizeof(int)));
+  P->s_nrhs = k;
+  P->s_restart = r;
+  return VC_OK;
+}
+
+static vc_status op_with_precond(vc_problem* P, const SolveSpec& sp, const double* v, double* z, double* w, int nrhs,
+                                 hipStream_t st) {
+  const double* src = v;
+  if (sp.precond) {
+    P->pc.mode = sp.precond;
+    vc_status s = apply_precond(P, sp.transpose, v, z, nrhs, st);
+    if (s != VC_OK) return s;
+    src = z;
+  }
+  return apply_op(P, sp.transpose, sp.mvp, src, w, nrhs, st);
+}
+
+// r = b - A x
+static vc_status residual(vc_problem* P, const SolveSpec& sp, const double* b, const double* x, double* r, int nrhs,
+                          hipStream_t st) {
+  const int64_t N = npanels(P);
+  vc_status s = apply_op(P, sp.transpose, sp.mvp, x, r, nrhs, st);
+  if (s != VC_OK) return s;
+  VC_HIP(launch_axpy_cols(r, b, N, nrhs, nullptr, 1, st));
+  return VC_OK;
+}
+
+static vc_status col_norms(const double* w, int64_t N, int nrhs, double* d_out, std::vector<double>& h, hipStream_t st) {
+  VC_HIP(launch_colnorm(w, N, N, nrhs, d_out, st));
+  h.resize(nrhs);
+  VC_HIP(hipMemcpyAsync(h.data(), d_out, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+  VC_HIP(hipStreamSynchronize(st));
+  return VC_OK;
+}
+
+// Solve A x = b (x holds the initial guess).  iters/rre: per column outputs.
+static vc_status gmres(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs,
+                       std::vector<int>& iters, std::vector<double>& rre, hipStream_t st) {
+  const int64_t N = npanels(P);
+  const int m = sp.restart;
+  vc_status s = ensure_workspace(P, nrhs, m);
+  if (s != VC_OK) return s;
+  double* V = P->s_V.as<double>();
+  double* w = P->s_w.as<double>();
+  double* z = P->s_z.as<double>();
+  double* r = P->s_r.as<double>();
+  double* hd = P->s_h.as<double>();
+  double* y2 = P->s_y2.as<double>();
+  double* nrm = P->s_norm.as<double>();
+  int* act = P->s_active.as<int>();
+  const int64_t ldv = (int64_t)nrhs * N;   // stride between basis vectors
+  const int ldh = m + 2;
+  std::vector<double> bn, rn;
+  s = col_norms(b, N, nrhs, nrm, bn, st);
+  if (s != VC_OK) return s;
+  iters.assign(nrhs, 0);
+  rre.assign(nrhs, 0.0);
+  std::vector<int> active(nrhs, 1);
+  std::vector<double> H((size_t)(m + 1) * m * nrhs), cs(m * nrhs), sn(m * nrhs), g((m + 1) * nrhs);
+  std::vector<double> h1((size_t)ldh * nrhs), h2((size_t)ldh * nrhs), hn(nrhs), scal(nrhs), yv((size_t)ldh * nrhs);
+  int total = 0;
+  while (true) {
+    s = residual(P, sp, b, x, r, nrhs, st);
+    if (s != VC_OK) return s;
+    s = col_norms(r, N, nrhs, nrm, rn, st);
+    if (s != VC_OK) return s;
+    bool any = false;
+    for (int c = 0; c < nrhs; ++c) {
+      rre[c] = bn[c] > 0.0 ? rn[c] / bn[c] : 0.0;
+      if (!std::isfinite(rre[c])) { set_error("non-finite residual in column %d", c); return VC_ERR_NUMERIC; }
+      active[c] = (bn[c] > 0.0 && rre[c] > sp.rtol) ? 1 : 0;
+      any |= active[c] != 0;
+    }
+    if (!any) return VC_OK;
+    if (total >= sp.max_iter) {
+      set_error("GMRES did not reach rtol %.3g in %d iterations (worst rre %.3g)", sp.rtol, total,
+                *std::max_element(rre.begin(), rre.end()));
+      return VC_ERR_NOT_CONVERGED;
+    }
+    VC_HIP(hipMemcpyAsync(act, active.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+    // V_0 = r / |r| (zero for finished columns)
+    for (int c = 0; c < nrhs; ++c) scal[c] = active[c] ? rn[c] : 0.0;
+    VC_HIP(hipMemcpyAsync(nrm + nrhs, scal.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    VC_HIP(hipMemcpyAsync(V, r, (size_t)nrhs * N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    VC_HIP(launch_scale_cols(V, N, N, nrhs, nrm + nrhs, 1, st));
+    for (int c = 0; c < nrhs; ++c) {
+      std::fill(&g[(size_t)c * (m + 1)], &g[(size_t)c * (m + 1)] + m + 1, 0.0);
+      g[(size_t)c * (m + 1)] = rn[c];
+    }
+    int jend = 0;
+    for (int j = 0; j < m; ++j) {
+      s = op_with_precond(P, sp, V + j * ldv, z, w, nrhs, st);
+      if (s != VC_OK) return s;
+      // classical Gram-Schmidt, twice
+      VC_HIP(launch_gemv_t(V, ldv, N, j + 1, w, N, nrhs, hd, ldh, act, P->s_partial.as<double>(), st));
+      VC_HIP(launch_gemv_n_sub(V, ldv, N, j + 1, hd, ldh, w, N, nrhs, act, 0, st));
+      VC_HIP(launch_gemv_t(V, ldv, N, j + 1, w, N, nrhs, hd + (size_t)ldh * nrhs, ldh, act, P->s_partial.as<double>(), st));
+      VC_HIP(launch_gemv_n_sub(V, ldv, N, j + 1, hd + (size_t)ldh * nrhs, ldh, w, N, nrhs, act, 0, st));
+      VC_HIP(launch_colnorm(w, N, N, nrhs, nrm, st));
+      VC_HIP(hipMemcpyAsync(h1.data(), hd, (size_t)ldh * nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      VC_HIP(hipMemcpyAsync(h2.data(), hd + (size_t)ldh * nrhs, (size_t)ldh * nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      VC_HIP(hipMemcpyAsync(hn.data(), nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      VC_HIP(hipStreamSynchronize(st));
+      ++total;
+      bool all_done = true;
+      for (int c = 0; c < nrhs; ++c) {
+        if (!active[c]) { scal[c] = 0.0; continue; }
+        iters[c]++;
+        double* Hc = &H[(size_t)c * (m + 1) * m];
+        for (int i = 0; i <= j; ++i) Hc[i * m + j] = h1[(size_t)c * ldh + i] + h2[(size_t)c * ldh + i];
+        Hc[(j + 1) * m + j] = hn[c];
+        for (int i = 0; i < j; ++i) {
+          const double a = Hc[i * m + j], bb = Hc[(i + 1) * m + j];
+          Hc[i * m + j] = cs[c * m + i] * a + sn[c * m + i] * bb;
+          Hc[(i + 1) * m + j] = -sn[c * m + i] * a + cs[c * m + i] * bb;
+        }
+        const double a = Hc[j * m + j], bb = Hc[(j + 1) * m + j];
+        const double rr = std::hypot(a, bb);
+        const double cc = rr > 0.0 ? a / rr : 1.0, ss = rr > 0.0 ? bb / rr : 0.0;
+        cs[c * m + j] = cc;
+        sn[c * m + j] = ss;
+        Hc[j * m + j] = rr;
+        Hc[(j + 1) * m + j] = 0.0;
+        double* gc = &g[(size_t)c * (m + 1)];
+        gc[j + 1] = -ss * gc[j];
+        gc[j] = cc * gc[j];
+        const double est = std::fabs(gc[j + 1]) / bn[c];
+        if (!std::isfinite(est)) { set_error("non-finite Arnoldi coefficient"); return VC_ERR_NUMERIC; }
+        const bool breakdown = hn[c] <= 1e-300 || hn[c] <= 1e-14 * std::fabs(rr);
+        scal[c] = breakdown ? 0.0 : hn[c];
+        if (est > sp.rtol * 0.5 && !breakdown) all_done = false;
+      }
+      jend = j;
+      if (all_done || j == m - 1 || total >= sp.max_iter) break;
+      VC_HIP(hipMemcpyAsync(nrm + nrhs, scal.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+      VC_HIP(hipMemcpyAsync(V + (j + 1) * ldv, w, (size_t)nrhs * N * sizeof(double), hipMemcpyDeviceToDevice, st));
+      VC_HIP(launch_scale_cols(V + (j + 1) * ldv, N, N, nrhs, nrm + nrhs, 1, st));
+    }
+    // y = H^{-1} g, x += R V y
+    const int k = jend + 1;
+    for (int c = 0; c < nrhs; ++c) {
+      double* yc = &yv[(size_t)c * ldh];
+      std::fill(yc, yc + ldh, 0.0);
+      if (!active[c]) continue;
+      const double* Hc = &H[(size_t)c * (m + 1) * m];
+      const double* gc = &g[(size_t)c * (m + 1)];
+      for (int i = k - 1; i >= 0; --i) {
+        double t = gc[i];
+        for (int l = i + 1; l < k; ++l) t -= Hc[i * m + l] * yc[l];
+        yc[i] = Hc[i * m + i] != 0.0 ? t / Hc[i * m + i] : 0.0;
+      }
+      for (int i = 0; i < k; ++i) yc[i] = -yc[i];
+    }
+    VC_HIP(hipMemcpyAsync(y2, yv.data(), (size_t)ldh * nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    VC_HIP(hipMemsetAsync(w, 0, (size_t)nrhs * N * sizeof(double), st));
+    VC_HIP(launch_gemv_n_sub(V, ldv, N, k, y2, ldh, w, N, nrhs, act, 0, st));   // w = V y
+    if (sp.precond) {
+      P->pc.mode = sp.precond;
+      s = apply_precond(P, sp.transpose, w, z, nrhs, st);
+      if (s != VC_OK) return s;
+      std::vector<double> ones(nrhs, 1.0);
+      VC_HIP(hipMemcpyAsync(nrm + nrhs, ones.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+      VC_HIP(launch_axpy_cols(x, z, N, nrhs, nrm + nrhs, 0, st));
+    } else {
+      std::vector<double> ones(nrhs, 1.0);
+      VC_HIP(hipMemcpyAsync(nrm + nrhs, ones.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+      VC_HIP(launch_axpy_cols(x, w, N, nrhs, nrm + nrhs, 0, st));
+    }
+  }
+}
+
+// FP64 solve, or FP32-product GMRES inside FP64 refinement (VC_MIXED).
+static vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const double* b, double* x, int nrhs,
+                       vc_stats* stats, hipStream_t st) {
+  const int64_t N = npanels(P);
+  SolveSpec sp{};
+  sp.transpose = transpose;
+  sp.precond = o.use_precond;
+  sp.restart = o.restart;
+  sp.max_iter = o.max_iter;
+  std::vector<int> it;
+  std::vector<double> rre;
+  VC_HIP(hipMemsetAsync(x, 0, (size_t)nrhs * N * sizeof(double), st));
+  int ir_steps = 0;
+  vc_status s;
+  if (o.prec != VC_MIXED) {
+    sp.mvp = o.prec == VC_FP32 ? VC_FP32 : VC_FP64;
+    sp.rtol = o.rtol;
+    s = gmres(P, sp, b, x, nrhs, it, rre, st);
+  } else {
+    // outer FP64 refinement: r = b - A x (FP64 product), inner FP32 GMRES on A d = r, x += d
+    DevMem rr, dd;
+    VC_HIP(rr.alloc((size_t)nrhs * N * sizeof(double)));
+    VC_HIP(dd.alloc((size_t)nrhs * N * sizeof(double)));
+    std::vector<int> tot(nrhs, 0);
+    SolveSpec s64 = sp;
+    s64.mvp = VC_FP64;
+    std::vector<double> bn, rn;
+    s = ensure_workspace(P, nrhs, o.restart);
+    if (s != VC_OK) return s;
+    s = col_norms(b, N, nrhs, P->s_norm.as<double>(), bn, st);
+    if (s != VC_OK) return s;
+    VC_HIP(hipMemcpyAsync(rr.p, b, (size_t)nrhs * N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    s = VC_ERR_NOT_CONVERGED;
+    rre.assign(nrhs, 1.0);
+    for (ir_steps = 0; ir_steps < o.ir_max; ++ir_steps) {
+      SolveSpec s32 = sp;
+      s32.mvp = VC_FP32;
+      s32.rtol = o.inner_rtol;
+      VC_HIP(hipMemsetAsync(dd.p, 0, (size_t)nrhs * N * sizeof(double), st));
+      vc_status si = gmres(P, s32, rr.as<double>(), dd.as<double>(), nrhs, it, rre, st);
+      if (si != VC_OK && si != VC_ERR_NOT_CONVERGED) return si;
+      for (int c = 0; c < nrhs; ++c) tot[c] += it[c];
+      std::vector<double> ones(nrhs, 1.0);
+      VC_HIP(hipMemcpyAsync(P->s_norm.as<double>() + nrhs, ones.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+      VC_HIP(launch_axpy_cols(x, dd.as<double>(), N, nrhs, P->s_norm.as<double>() + nrhs, 0, st));
+      vc_status sr = residual(P, s64, b, x, rr.as<double>(), nrhs, st);
+      if (sr != VC_OK) return sr;
+      sr = col_norms(rr.as<double>(), N, nrhs, P->s_norm.as<double>(), rn, st);
+      if (sr != VC_OK) return sr;
+      bool ok = true;
+      for (int c = 0; c < nrhs; ++c) {
+        rre[c] = bn[c] > 0 ? rn[c] / bn[c] : 0.0;
+        if (rre[c] > o.rtol) ok = false;
+      }
+      if (ok) { s = VC_OK; ++ir_steps; break; }
+    }
+    it = tot;
+    if (s != VC_OK) set_error("refinement did not reach rtol %.3g in %d steps", o.rtol, o.ir_max);
+  }
+  if (stats) {
+    for (int c = 0; c < nrhs && c < 64; ++c) {
+      stats->iters[c] = c < (int)it.size() ? it[c] : 0;
+      stats->final_rre[c] = c < (int)rre.size() ? rre[c] : 0.0;
+    }
+    stats->ir_steps = ir_steps;
+  }
+  return s;
+}
+
+static vc_solve_opts fill_defaults(const vc_solve_opts* in) {
+  vc_solve_opts o{};
+  if (in) o = *in;
+  if (o.rtol <= 0) o.rtol = 1e-12;
+  if (o.restart <= 0) o.restart = 35;
+  if (o.max_iter <= 0) o.max_iter = 2000;
+  if (o.inner_rtol <= 0) o.inner_rtol = 1e-5;
+  if (o.ir_max <= 0) o.ir_max = 20;
+  if (!in) o.use_precond = 1;
+  return o;
+}
+
+}  // namespace vc
+
+using namespace vc;
+
+#define VC_CHECK_PROBLEM(p)                                          \
+  do {                                                               \
+    if (!(p)) { set_error("null problem"); return VC_ERR_ARG; }      \
+    if ((p)->hip_failed) { set_error("problem unusable after a HIP error"); return VC_ERR_HIP; } \
+  } while (0)
+
+static vc_status mark(vc_problem* p, vc_status s) {
+  if (s == VC_ERR_HIP && p) p->hip_failed = true;
+  return s;
+}
+
+extern "C" {
+
+const char* vc_status_string(vc_status s) {
+  switch (s) {
+    case VC_OK: return "ok";
+    case VC_ERR_ARG: return "invalid argument";
+    case VC_ERR_GEOMETRY: return "invalid geometry";
+    case VC_ERR_HIP: return "HIP runtime error";
+    case VC_ERR_OOM: return "out of memory";
+    case VC_ERR_NOT_CONVERGED: return "not converged";
+    case VC_ERR_NUMERIC: return "numerical breakdown";
+    case VC_ERR_STATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char* vc_last_error(void) { return g_err.c_str(); }
+
+vc_status vc_problem_create(const vc_geometry* g, int device, vc_problem** out) {
+  if (!g || !out || !g->cond_id || !g->eps_r) { set_error("null argument"); return VC_ERR_ARG; }
+  *out = nullptr;
+  if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || !(g->dv > 0.0)) { set_error("grid sizes and dv must be > 0"); return VC_ERR_ARG; }
+  const int64_t nv = (int64_t)g->nx * g->ny * g->nz;
+  if (nv > (int64_t)1 << 31) { set_error("grid too large"); return VC_ERR_ARG; }
+  vc_problem* p = new (std::nothrow) vc_problem();
+  if (!p) { set_error("host allocation failed"); return VC_ERR_OOM; }
+  p->device = device;
+  p->nx = g->nx; p->ny = g->ny; p->nz = g->nz;
+  p->dv = g->dv;
+  p->eps_b = g->eps_background > 0 ? g->eps_background : (g->eps_background == 0 ? 1.0 : g->eps_background);
+  p->cond_id.assign(g->cond_id, g->cond_id + nv);
+  p->eps_r.assign(g->eps_r, g->eps_r + nv);
+  vc_status s = panelize(p);
+  if (s == VC_OK) s = choose_sizes(p, nullptr);
+  if (s != VC_OK) { delete p; return s; }
+  *out = p;
+  return VC_OK;
+}
+
+vc_status vc_problem_destroy(vc_problem* p) {
+  if (!p) return VC_OK;
+  if (p->setup_done) (void)hipSetDevice(p->device);
+  delete p;
+  return VC_OK;
+}
+
+vc_status vc_panel_counts(const vc_problem* p, int64_t* n_cond, int64_t* n_diel, int32_t* m) {
+  if (!p) { set_error("null problem"); return VC_ERR_ARG; }
+  if (n_cond) *n_cond = p->n_cond;
+  if (n_diel) *n_diel = p->n_diel;
+  if (m) *m = p->m;
+  return VC_OK;
+}
+
+vc_status vc_panels(const vc_problem* p, vc_panel* out) {
+  if (!p || !out) { set_error("null argument"); return VC_ERR_ARG; }
+  std::memcpy(out, p->panels.data(), p->panels.size() * sizeof(vc_panel));
+  return VC_OK;
+}
+
+vc_status vc_fft_size(const vc_problem* p, int32_t out_m[3]) {
+  if (!p || !out_m) { set_error("null argument"); return VC_ERR_ARG; }
+  for (int a = 0; a < 3; ++a) out_m[a] = p->M[a];
+  return VC_OK;
+}
+
+vc_status vc_setup(vc_problem* p, const vc_setup_opts* opts, void* stream) {
+  VC_CHECK_PROBLEM(p);
+  vc_setup_opts o{};
+  if (opts) o = *opts;
+  if (o.tucker_tol < 0) { set_error("tucker_tol must be >= 0"); return VC_ERR_ARG; }
+  if (o.tucker_tol > 0) { set_error("Tucker compression is not available in this build"); return VC_ERR_ARG; }
+  const double t0 = now_s();
+  VC_HIP(hipSetDevice(p->device));
+  hipStream_t st = (hipStream_t)stream;
+  vc_status s = choose_sizes(p, (o.fft_size[0] || o.fft_size[1] || o.fft_size[2]) ? o.fft_size : nullptr);
+  if (s != VC_OK) return s;
+  for (int a = 0; a < 3; ++a) p->nv[a] = o.nv[a] > 0 ? o.nv[a] : 8;
+  const int prec = o.precisions ? o.precisions : 3;
+  s = build_spectra(p, (prec & 1) != 0, (prec & 2) != 0, st);
+  if (s != VC_OK) return mark(p, s);
+  p->max_rhs = o.max_rhs > 0 ? o.max_rhs : p->m;
+  const bool diel = p->n_diel > 0;
+  p->ncomp_F = diel ? 6 : 3;
+  p->ncomp_O = diel ? 6 : 3;
+  p->rhs_stride = (int64_t)p->n1[0] * p->M[1] * p->H;
+  p->comp_stride = p->rhs_stride * p->max_rhs;
+  const size_t cb = 16;   // complex double
+  VC_HIP(p->work_F.alloc((size_t)p->ncomp_F * p->comp_stride * cb));
+  VC_HIP(p->work_O.alloc((size_t)p->ncomp_O * p->comp_stride * cb));
+  s = build_precond(p, st);
+  if (s != VC_OK) return mark(p, s);
+  VC_HIP(hipStreamSynchronize(st));
+  p->setup_done = true;
+  p->t_setup = now_s() - t0;
+  return VC_OK;
+}
+
+vc_status vc_apply(vc_problem* p, int transpose, vc_precision prec, const double* x, double* y, int32_t nrhs,
+                   void* stream) {
+  VC_CHECK_PROBLEM(p);
+  if (!p->setup_done) { set_error("vc_apply before vc_setup"); return VC_ERR_STATE; }
+  if (!x || !y || nrhs <= 0 || nrhs > p->max_rhs) { set_error("bad x/y or nrhs (1..%d)", p->max_rhs); return VC_ERR_ARG; }
+  if (prec != VC_FP64 && prec != VC_FP32) { set_error("prec must be VC_FP64 or VC_FP32"); return VC_ERR_ARG; }
+  VC_HIP(hipSetDevice(p->device));
+  return mark(p, apply_op(p, transpose, prec, x, y, nrhs, (hipStream_t)stream));
+}
+
+vc_status vc_apply_precond(vc_problem* p, int transpose, const double* x, double* y, int32_t nrhs, void* stream) {
+  VC_CHECK_PROBLEM(p);
+  if (!p->setup_done) { set_error("vc_apply_precond before vc_setup"); return VC_ERR_STATE; }
+  if (!x || !y || nrhs <= 0) { set_error("bad arguments"); return VC_ERR_ARG; }
+  VC_HIP(hipSetDevice(p->device));
+  p->pc.mode = 1;
+  return mark(p, apply_precond(p, transpose, x, y, nrhs, (hipStream_t)stream));
+}
+
+static vc_status capacitance_impl(vc_problem* p, const vc_solve_opts* opts, double* C, double* rho_dev, vc_stats* stats,
+                                  std::vector<double>* rho_host) {
+  VC_CHECK_PROBLEM(p);
+  if (!p->setup_done) { set_error("vc_capacitance before vc_setup"); return VC_ERR_STATE; }
+  if (!C) { set_error("null C"); return VC_ERR_ARG; }
+  vc_solve_opts o = fill_defaults(opts);
+  if ((o.prec == VC_FP32 || o.prec == VC_MIXED) && !p->have32) { set_error("FP32 spectra not built"); return VC_ERR_STATE; }
+  if (p->m > p->max_rhs) { set_error("setup max_rhs < number of conductors"); return VC_ERR_STATE; }
+  VC_HIP(hipSetDevice(p->device));
+  const double t0 = now_s();
+  hipStream_t st = nullptr;
+  const int64_t N = npanels(p);
+  const int m = p->m;
+  p->mvp_count = 0;
+  vc_status s = ensure_workspace(p, m, o.restart);
+  if (s != VC_OK) return mark(p, s);
+  std::vector<double> B((size_t)m * N, 0.0);
+  for (int64_t k = 0; k < N; ++k)
+    if (p->panels[k].kind == 0) B[(size_t)p->panels[k].cond * N + k] = 1.0;
+  VC_HIP(hipMemcpy(p->s_b.p, B.data(), B.size() * sizeof(double), hipMemcpyHostToDevice));
+  if (stats) std::memset(stats, 0, sizeof(vc_stats));
+  s = solve(p, o, 0, p->s_b.as<double>(), p->s_x.as<double>(), m, stats, st);
+  if (s != VC_OK && s != VC_ERR_NOT_CONVERGED) return mark(p, s);
+  DevMem dC;
+  VC_HIP(dC.alloc((size_t)m * m * sizeof(double)));
+  VC_HIP(launch_cap_reduce(p->s_x.as<double>(), N, m, p->d_cond_panels.as<int32_t>(), p->d_cond_ptr.as<int32_t>(),
+                           p->d_weight.as<double>(), 4.0 * M_PI * kEps0 * p->dv, dC.as<double>(), st));
+  VC_HIP(hipMemcpy(C, dC.p, (size_t)m * m * sizeof(double), hipMemcpyDeviceToHost));
+  if (rho_dev) VC_HIP(hipMemcpy(rho_dev, p->s_x.p, (size_t)m * N * sizeof(double), hipMemcpyDeviceToDevice));
+  if (rho_host) {
+    rho_host->resize((size_t)m * N);
+    VC_HIP(hipMemcpy(rho_host->data(), p->s_x.p, (size_t)m * N * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  if (stats) {
+    stats->mvp_count = p->mvp_count;
+    stats->t_setup_s = p->t_setup;
+    stats->t_solve_s = now_s() - t0;
+    stats->spectra_bytes = p->spectra_bytes;
+  }
+  return s;
+}
+
+vc_status vc_capacitance(vc_problem* p, const vc_solve_opts* opts, double* C, double* rho_dev, vc_stats* stats) {
+  return capacitance_impl(p, opts, C, rho_dev, stats, nullptr);
+}
+
+vc_status vc_capacitance_grad_eps(vc_problem* p, const vc_solve_opts* opts, const int32_t* block_of_voxel,
+                                  int32_t nblocks, double* dC, double* C_out, vc_stats* stats) {
+  VC_CHECK_PROBLEM(p);
+  if (!block_of_voxel || nblocks <= 0 || !dC) { set_error("bad gradient arguments"); return VC_ERR_ARG; }
+  const int m = p->m;
+  const int64_t N = npanels(p);
+  std::vector<double> C((size_t)m * m);
+  std::vector<double> rho;
+  vc_status s = capacitance_impl(p, opts, C.data(), nullptr, stats, &rho);
+  if (s != VC_OK) return s;
+  if (C_out) std::memcpy(C_out, C.data(), C.size() * sizeof(double));
+  // adjoint solves A^T lambda_i = w_i, w_i = eps_adj on the panels of conductor i
+  vc_solve_opts o = fill_defaults(opts);
+  std::vector<double> W((size_t)m * N, 0.0);
+  for (int64_t k = 0; k < N; ++k)
+    if (p->panels[k].kind == 0) W[(size_t)p->panels[k].cond * N + k] = p->panels[k].eps_adj;
+  VC_HIP(hipMemcpy(p->s_b.p, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice));
+  s = solve(p, o, 1, p->s_b.as<double>(), p->s_x.as<double>(), m, nullptr, nullptr);
+  if (s != VC_OK) return mark(p, s);
+  std::vector<double> lam((size_t)m * N);
+  VC_HIP(hipMemcpy(lam.data(), p->s_x.p, lam.size() * sizeof(double), hipMemcpyDeviceToHost));
+  // dC_ij/deps_b = scale * [ sum_{k in i, adj in b} rho_kj - sum_{k diel} lam_ki dI_k/deps_b rho_kj ]
+  const double scale = 4.0 * M_PI * kEps0 * p->dv;
+  std::fill(dC, dC + (size_t)nblocks * m * m, 0.0);
+  auto vox = [&](int i, int j, int k) -> int32_t {
+    if (i < 0 || j < 0 || k < 0 || i >= p->nx || j >= p->ny || k >= p->nz) return -1;
+    return block_of_voxel[((int64_t)i * p->ny + j) * p->nz + k];
+  };
+  for (int64_t k = 0; k < N; ++k) {
+    const vc_panel& pn = p->panels[k];
+    int lo[3] = {pn.i, pn.j, pn.k};
+    lo[pn.dir] -= 1;
+    const int32_t blo = vox(lo[0], lo[1], lo[2]);
+    const int32_t bhi = vox(pn.i, pn.j, pn.k);
+    if (pn.kind == 0) {
+      const int32_t b = pn.eps_lo == 0.0 ? bhi : blo;   // non-conductor side
+      if (b < 0 || b >= nblocks) continue;
+      for (int j = 0; j < m; ++j) dC[((size_t)b * m + pn.cond) * m + j] += scale * rho[(size_t)j * N + k];
+    } else {
+      const double el = pn.eps_lo, eh = pn.eps_hi, dd = (el - eh) * (el - eh);
+      const double dlo = -4.0 * M_PI * eh / dd, dhi = 4.0 * M_PI * el / dd;
+      for (int side = 0; side < 2; ++side) {
+        const int32_t b = side == 0 ? blo : bhi;
+        if (b < 0 || b >= nblocks) continue;
+        const double dI = side == 0 ? dlo : dhi;
+        for (int i = 0; i < m; ++i) {
+          const double li = lam[(size_t)i * N + k] * dI * scale;
+          for (int j = 0; j < m; ++j) dC[((size_t)b * m + i) * m + j] -= li * rho[(size_t)j * N + k];
+        }
+      }
+    }
+  }
+  return VC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// The operator of eq. (4) applied through eq. (11) (Sec. II.B), forward and transposed,
+// and the preconditioner of eq. (14) (Sec. II.D).
+//
+// Forward product y = A x, per right-hand side:
+//   1. scatter + z transform of the three panel-charge grids (one per normal axis);
+//   2. y transform;
+//   3. x transform, block multiply (C_alpha = sum_beta P~(alpha,beta) Q~_beta and, with
+//      dielectric panels, D_alpha = sum_beta E~(alpha,beta) Q~_beta), inverse x transform;
+//   4. inverse y transform of the needed rows;
+//   5. inverse z transform, gather C on conductor panels and D + I x on dielectric panels.
+// Transposed product (used by the adjoint solve): the conductor-row and dielectric-row
+// values of x are scattered into six grids, multiplied by the conjugated spectra of the
+// transposed blocks, transformed back into three grids and gathered on every panel.
+#include "mvp_kernels.h"
+#include "problem.h"
+
+namespace vc {
+
+bool pick_tile(int L, int elem_bytes, int emax, int ncols_total, int* ncol, int* nthr, size_t budget);
+int pair_odd_bits(int q);
+
+template <typename T>
+static vc_status run_apply(vc_problem* P, int transpose, const double* x, double* y, int nrhs, hipStream_t st) {
+  PrecTables& tb = (sizeof(T) == 8) ? P->t64 : P->t32;
+  const int n1x = P->n1[0], n1y = P->n1[1];
+  const int Mx = P->M[0], My = P->M[1];
+  const int H = P->H;
+  const int64_t N = npanels(P);
+  const int eb = (int)sizeof(T) * 2;
+  const size_t budget = kLdsBudget;
+  const bool diel = P->n_diel > 0;
+  if (transpose && !diel) transpose = 0;   // without dielectric rows A is symmetric (eq. 5)
+  void* F = P->work_F.p;
+  void* O = P->work_O.p;
+  const int64_t cs = P->comp_stride, rs = P->rhs_stride;
+  const int nitems = (int)P->items.size();
+  const int32_t* items = P->d_items.as<int32_t>();
+  const int32_t* lptr = P->d_line_ptr.as<int32_t>();
+  const int32_t* pk = P->d_pk.as<int32_t>();
+  const int8_t* pkind = P->d_pkind.as<int8_t>();
+  const uint8_t* lflag = P->d_lflag.as<uint8_t>();
+  const uint8_t* pflag = P->d_pflag.as<uint8_t>();
+  int ncol, nthr;
+  // 1. scatter + z transform
+  if (!pick_tile(P->M[2], eb, kEmax, nitems, &ncol, &nthr, budget)) return VC_ERR_ARG;
+  VC_HIP(launch_zfwd<T>(x, N, nrhs, transpose ? 1 : 0, items, nitems, lptr, pk, pkind, F, cs, rs, n1x, n1y, My, H,
+                        tb.ax[2].plan, tb.ax[2].tw.p, ncol, nthr, st));
+  // 2. y transform of the input components
+  CompSet cin{};
+  if (!transpose) {
+    cin.n = 3;
+    for (int a = 0; a < 3; ++a) { cin.comp[a] = a; cin.axis[a] = a; cin.min_[a] = 3; cin.mout[a] = 0; }
+  } else {
+    cin.n = 6;
+    for (int c = 0; c < 6; ++c) { cin.comp[c] = c; cin.axis[c] = c % 3; cin.min_[c] = c < 3 ? 1 : 2; cin.mout[c] = 0; }
+  }
+  StridedArgs sa{};
+  sa.comp_stride = cs; sa.rhs_stride = rs; sa.plane_stride = (int64_t)My * H; sa.row_stride = H;
+  sa.ncols = H; sa.nrhs = nrhs; sa.n1x = n1x; sa.n1y = n1y;
+  if (!pick_tile(My, eb, kEmax, H, &ncol, &nthr, budget)) return VC_ERR_ARG;
+  sa.ncol = ncol; sa.nin = n1y; sa.nout = My; sa.inverse = 0;
+  VC_HIP(launch_strided<T>(F, sa, cin, n1x, tb.ax[1].plan, tb.ax[1].tw.p, lflag, pflag, nthr, st));
+  // 3. x sandwich
+  SandArgs xa{};
+  xa.comp_stride = cs; xa.rhs_stride = rs; xa.pair_stride = (int64_t)P->Hy * H * P->Hx;
+  xa.nrhs = nrhs; xa.n1x = n1x; xa.Mx = Mx; xa.My = My; xa.H = H; xa.Hx = P->Hx; xa.Hy = P->Hy;
+  for (int q = 0; q < 15; ++q) xa.odd[q] = pair_odd_bits(q);
+  xa.adjoint = transpose;
+  CompSet cout{};
+  if (!transpose) {
+    xa.nin = 3;
+    for (int b = 0; b < 3; ++b) { xa.in_comp[b] = b; xa.in_axis[b] = b; xa.in_mask[b] = 3; }
+    xa.nout = diel ? 6 : 3;
+    for (int o = 0; o < xa.nout; ++o) { xa.out_comp[o] = o; xa.out_axis[o] = o % 3; xa.out_mask[o] = o < 3 ? 1 : 2; }
+    cout.n = xa.nout;
+    for (int o = 0; o < xa.nout; ++o) { cout.comp[o] = o; cout.axis[o] = o % 3; cout.min_[o] = 0; cout.mout[o] = o < 3 ? 1 : 2; }
+  } else {
+    xa.nin = 6;
+    for (int c = 0; c < 6; ++c) { xa.in_comp[c] = c; xa.in_axis[c] = c % 3; xa.in_mask[c] = c < 3 ? 1 : 2; }
+    xa.nout = 3;
+    for (int o = 0; o < 3; ++o) { xa.out_comp[o] = o; xa.out_axis[o] = o; xa.out_mask[o] = 3; }
+    cout.n = 3;
+    for (int o = 0; o < 3; ++o) { cout.comp[o] = o; cout.axis[o] = o; cout.min_[o] = 0; cout.mout[o] = 3; }
+  }
+  if (!pick_tile(Mx, eb, kEmaxSand, H, &ncol, &nthr, budget)) return VC_ERR_ARG;
+  xa.ncol = ncol;
+  VC_HIP(launch_sandwich<T>(F, O, tb.R.p, xa, tb.ax[0].plan, tb.ax[0].tw.p, tb.ax[0].ph.p, tb.ax[1].ph.p,
+                            tb.ax[2].ph.p, pflag, nthr, st));
+  // 4. inverse y transform of the outputs (only rows with panels that need them)
+  if (!pick_tile(My, eb, kEmax, H, &ncol, &nthr, budget)) return VC_ERR_ARG;
+  sa.ncol = ncol; sa.nin = My; sa.nout = n1y; sa.inverse = 1;
+  VC_HIP(launch_strided<T>(O, sa, cout, n1x, tb.ax[1].plan, tb.ax[1].tw.p, lflag, pflag, nthr, st));
+  // 5. inverse z transform + gather + jump term
+  if (!pick_tile(P->M[2], eb, kEmax, nitems, &ncol, &nthr, budget)) return VC_ERR_ARG;
+  VC_HIP(launch_zinv<T>(O, y, x, N, nrhs, transpose ? 1 : 0, items, nitems, lptr, pk, pkind, P->d_diag.as<double>(),
+                        lflag, cs, rs, n1x, n1y, My, H, tb.ax[2].plan, tb.ax[2].tw.p, ncol, nthr, st));
+  P->mvp_count++;
+  return VC_OK;
+}
+
+vc_status apply_op(vc_problem* P, int transpose, vc_precision prec, const double* x, double* y, int nrhs,
+                   hipStream_t st) {
+  if (prec == VC_FP32) {
+    if (!P->have32) { set_error("FP32 spectra were not built at setup"); return VC_ERR_STATE; }
+    return run_apply<float>(P, transpose, x, y, nrhs, st);
+  }
+  if (!P->have64) { set_error("FP64 spectra were not built at setup"); return VC_ERR_STATE; }
+  return run_apply<double>(P, transpose, x, y, nrhs, st);
+}
+
+vc_status apply_precond(vc_problem* P, int transpose, const double* x, double* y, int nrhs, hipStream_t st) {
+  (void)transpose;   // the blocks of eq. (5) are symmetric and the diagonal is its own transpose
+  const int64_t N = npanels(P);
+  Precond& pc = P->pc;
+  if (pc.mode == 2) {
+    VC_HIP(launch_diag_scale(x, y, pc.dinv_diag.as<double>(), N, nrhs, st));
+    return VC_OK;
+  }
+  VC_HIP(launch_diag_scale(x, y, pc.dinv.as<double>(), N, nrhs, st));
+  VC_HIP(launch_block_apply(x, y, N, nrhs, pc.box_ptr.as<int32_t>(), pc.box_panels.as<int32_t>(),
+                            pc.box_block.as<int32_t>(), pc.block_off.as<int64_t>(), pc.block_n.as<int32_t>(),
+                            pc.blocks.as<double>(), pc.nbox, st));
+  return VC_OK;
+}
+
+}  // namespace vc

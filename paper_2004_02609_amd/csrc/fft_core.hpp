@@ -1,0 +1,194 @@
+// In-LDS mixed-radix FFT engine for gfx950 (wave64), templated on float / double.
+//
+// A workgroup transforms `ncol` independent lines of length L held in LDS as a
+// [L][ncolp] tile (element i of line c at buf[i*ncolp + c], ncolp = ncol + pad).
+// Each stage of radix R is a Stockham autosort step: butterfly i in [0, L/R) of a
+// line reads x[i + q*L/R] (q < R), multiplies by w^(q*k*L/(pR)) (k = i mod p, p the
+// product of the earlier radices, w = exp(-+2 pi i / L) from a table), does a
+// radix-R DFT and writes y[(i-k)*R + k + q*p].  All reads of a stage are staged in
+// registers before the barrier and all writes follow it, so one LDS tile suffices.
+// Consecutive threads take consecutive columns, which keeps LDS accesses on
+// distinct banks.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vc {
+
+template <typename T> struct C2 { T x, y; };
+
+template <typename T> __device__ __forceinline__ C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T> __device__ __forceinline__ C2<T> csub(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T> __device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T> __device__ __forceinline__ C2<T> cconj(C2<T> a) { return {a.x, -a.y}; }
+template <typename T> __device__ __forceinline__ C2<T> cscale(C2<T> a, T s) { return {a.x * s, a.y * s}; }
+// multiply by -i (fwd) or +i (inv): s = -1 for -i, +1 for +i
+template <typename T> __device__ __forceinline__ C2<T> cmuli(C2<T> a, T s) { return {-s * a.y, s * a.x}; }
+
+// Radices supported by the engine.
+constexpr int kMaxStages = 10;
+struct AxisPlan {
+  int L;
+  int nst;
+  int rad[kMaxStages];
+};
+
+// cos / sin of 2*pi*k/5 and 2*pi*k/7 (k = 1, 2, 3)
+#define VC_C51 0.30901699437494742410
+#define VC_C52 -0.80901699437494742410
+#define VC_S51 0.95105651629515357212
+#define VC_S52 0.58778525229247312917
+#define VC_C71 0.62348980185873353053
+#define VC_C72 -0.22252093395631440429
+#define VC_C73 -0.90096886790241912624
+#define VC_S71 0.78183148246802980871
+#define VC_S72 0.97492791218182360702
+#define VC_S73 0.43388373911755812048
+#define VC_S31 0.86602540378443864676
+
+// Radix-R DFT in registers.  sg = -1 forward (exp(-2 pi i qk/R)), +1 inverse.
+template <typename T, int R> struct Dft;
+
+template <typename T> struct Dft<T, 2> {
+  static __device__ __forceinline__ void run(C2<T>* v, T) {
+    C2<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+template <typename T> struct Dft<T, 3> {
+  static __device__ __forceinline__ void run(C2<T>* v, T sg) {
+    C2<T> s = cadd(v[1], v[2]);
+    C2<T> d = csub(v[1], v[2]);
+    C2<T> m = {v[0].x - T(0.5) * s.x, v[0].y - T(0.5) * s.y};
+    C2<T> r = cmuli(d, sg * T(VC_S31));
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+  }
+};
+template <typename T> struct Dft<T, 4> {
+  static __device__ __forceinline__ void run(C2<T>* v, T sg) {
+    C2<T> a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+    C2<T> c = cadd(v[1], v[3]), d = cmuli(csub(v[1], v[3]), sg);
+    v[0] = cadd(a, c);
+    v[2] = csub(a, c);
+    v[1] = cadd(b, d);
+    v[3] = csub(b, d);
+  }
+};
+template <typename T> struct Dft<T, 5> {
+  static __device__ __forceinline__ void run(C2<T>* v, T sg) {
+    C2<T> s1 = cadd(v[1], v[4]), d1 = csub(v[1], v[4]);
+    C2<T> s2 = cadd(v[2], v[3]), d2 = csub(v[2], v[3]);
+    C2<T> x0 = v[0];
+    C2<T> a1 = {x0.x + T(VC_C51) * s1.x + T(VC_C52) * s2.x, x0.y + T(VC_C51) * s1.y + T(VC_C52) * s2.y};
+    C2<T> a2 = {x0.x + T(VC_C52) * s1.x + T(VC_C51) * s2.x, x0.y + T(VC_C52) * s1.y + T(VC_C51) * s2.y};
+    C2<T> b1 = {T(VC_S51) * d1.x + T(VC_S52) * d2.x, T(VC_S51) * d1.y + T(VC_S52) * d2.y};
+    C2<T> b2 = {T(VC_S52) * d1.x - T(VC_S51) * d2.x, T(VC_S52) * d1.y - T(VC_S51) * d2.y};
+    b1 = cmuli(b1, sg);
+    b2 = cmuli(b2, sg);
+    v[0] = {x0.x + s1.x + s2.x, x0.y + s1.y + s2.y};
+    v[1] = cadd(a1, b1);
+    v[4] = csub(a1, b1);
+    v[2] = cadd(a2, b2);
+    v[3] = csub(a2, b2);
+  }
+};
+template <typename T> struct Dft<T, 7> {
+  static __device__ __forceinline__ void run(C2<T>* v, T sg) {
+    C2<T> s1 = cadd(v[1], v[6]), d1 = csub(v[1], v[6]);
+    C2<T> s2 = cadd(v[2], v[5]), d2 = csub(v[2], v[5]);
+    C2<T> s3 = cadd(v[3], v[4]), d3 = csub(v[3], v[4]);
+    C2<T> x0 = v[0];
+    const T c1 = T(VC_C71), c2 = T(VC_C72), c3 = T(VC_C73);
+    const T n1 = T(VC_S71), n2 = T(VC_S72), n3 = T(VC_S73);
+    C2<T> a1 = {x0.x + c1 * s1.x + c2 * s2.x + c3 * s3.x, x0.y + c1 * s1.y + c2 * s2.y + c3 * s3.y};
+    C2<T> a2 = {x0.x + c2 * s1.x + c3 * s2.x + c1 * s3.x, x0.y + c2 * s1.y + c3 * s2.y + c1 * s3.y};
+    C2<T> a3 = {x0.x + c3 * s1.x + c1 * s2.x + c2 * s3.x, x0.y + c3 * s1.y + c1 * s2.y + c2 * s3.y};
+    // sin(2 pi qk/7): k=1: (n1, n2, n3); k=2: (n2, -n3, -n1); k=3: (n3, -n1, n2)
+    C2<T> b1 = {n1 * d1.x + n2 * d2.x + n3 * d3.x, n1 * d1.y + n2 * d2.y + n3 * d3.y};
+    C2<T> b2 = {n2 * d1.x - n3 * d2.x - n1 * d3.x, n2 * d1.y - n3 * d2.y - n1 * d3.y};
+    C2<T> b3 = {n3 * d1.x - n1 * d2.x + n2 * d3.x, n3 * d1.y - n1 * d2.y + n2 * d3.y};
+    b1 = cmuli(b1, sg);
+    b2 = cmuli(b2, sg);
+    b3 = cmuli(b3, sg);
+    v[0] = {x0.x + s1.x + s2.x + s3.x, x0.y + s1.y + s2.y + s3.y};
+    v[1] = cadd(a1, b1);
+    v[6] = csub(a1, b1);
+    v[2] = cadd(a2, b2);
+    v[5] = csub(a2, b2);
+    v[3] = cadd(a3, b3);
+    v[4] = csub(a3, b3);
+  }
+};
+
+// One Stockham stage of radix R over ncol lines.  EMAX bounds the elements a thread
+// stages per stage: the launch guarantees L*ncol <= EMAX*nthr.
+template <typename T, int R, int EMAX>
+__device__ __forceinline__ void fft_stage(C2<T>* __restrict__ buf, const C2<T>* __restrict__ tw, int L,
+                                          int ncol, int ncolp, int p, T sg) {
+  constexpr int MAXB = EMAX / R + 1;
+  const int nthr = blockDim.x;
+  const int tid = threadIdx.x;
+  const int LR = L / R;
+  const int nb = LR * ncol;
+  const int tstep_base = L / (p * R);
+  C2<T> v[MAXB][R];
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    int b = tid + c * nthr;
+    if (b < nb) {
+      int col = b % ncol, i = b / ncol;
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[c][q] = buf[(i + q * LR) * ncolp + col];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    int b = tid + c * nthr;
+    if (b < nb) {
+      int col = b % ncol, i = b / ncol;
+      int k = i % p;
+      if (p > 1) {
+        int ts = k * tstep_base;
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+          C2<T> w = tw[q * ts];
+          w.y *= -sg;  // table holds exp(-2 pi i t/L); conjugated for the inverse
+          v[c][q] = cmul(v[c][q], w);
+        }
+      }
+      Dft<T, R>::run(v[c], sg);
+      int j = (i - k) * R + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) buf[(j + q * p) * ncolp + col] = v[c][q];
+    }
+  }
+  __syncthreads();
+}
+
+// Full transform of ncol lines (caller synchronizes before: data must be in LDS).
+template <typename T, int EMAX>
+__device__ void lds_fft(C2<T>* __restrict__ buf, const C2<T>* __restrict__ tw, const AxisPlan& pl, int ncol,
+                        int ncolp, bool inverse) {
+  const T sg = inverse ? T(1) : T(-1);
+  int p = 1;
+  for (int s = 0; s < pl.nst; ++s) {
+    const int R = pl.rad[s];
+    switch (R) {
+      case 2: fft_stage<T, 2, EMAX>(buf, tw, pl.L, ncol, ncolp, p, sg); break;
+      case 3: fft_stage<T, 3, EMAX>(buf, tw, pl.L, ncol, ncolp, p, sg); break;
+      case 4: fft_stage<T, 4, EMAX>(buf, tw, pl.L, ncol, ncolp, p, sg); break;
+      case 5: fft_stage<T, 5, EMAX>(buf, tw, pl.L, ncol, ncolp, p, sg); break;
+      case 7: fft_stage<T, 7, EMAX>(buf, tw, pl.L, ncol, ncolp, p, sg); break;
+      default: break;
+    }
+    p *= R;
+  }
+}
+
+}  // namespace vc

@@ -1,0 +1,107 @@
+// Host-visible declarations of the FFT-product pass kernels (see mvp_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_core.hpp"
+
+namespace vc {
+
+// Elements a thread stages per FFT stage (launches keep L*ncol <= kEmax*threads).
+constexpr int kEmax = 16;
+constexpr int kEmaxSand = 8;
+// Dynamic LDS per workgroup kept within the default 64 KiB launch limit.
+constexpr size_t kLdsBudget = 64 * 1024;
+
+// Up to six field components handled by one strided launch (blockIdx.z = comp*nrhs+rhs).
+struct CompSet {
+  int n;
+  int comp[6];   // component index in the work array
+  int axis[6];   // panel normal axis of the component (selects its line/plane flags)
+  int min_[6];   // flag bits a row must have to be loaded (0 = load all rows < nin)
+  int mout[6];   // flag bits a row must have to be stored (0 = store all rows < nout)
+};
+
+struct StridedArgs {
+  int64_t comp_stride, rhs_stride, plane_stride, row_stride;
+  int ncols;      // columns along the contiguous axis (H)
+  int ncol;       // columns per workgroup tile
+  int nin, nout;  // rows loaded (rest zero) / rows stored
+  int nrhs;
+  int inverse;
+  int n1x, n1y;   // flag array extents (planes x rows)
+};
+
+struct SandArgs {
+  int64_t comp_stride, rhs_stride, pair_stride;
+  int nrhs, n1x, Mx, My, H, Hx, Hy;
+  int ncol;
+  int adjoint;
+  int nin, nout;
+  int in_comp[6], in_axis[6], in_mask[6];
+  int out_comp[6], out_axis[6], out_mask[6];
+  int odd[15];    // bit a set: stored spectrum of pair q is odd under k_a -> M_a - k_a
+};
+
+template <typename T>
+hipError_t launch_zfwd(const double* x, int64_t N, int nrhs, int mode, const int32_t* items, int nitems,
+                       const int32_t* line_ptr, const int32_t* pk, const int8_t* pkind, void* F, int64_t comp_stride,
+                       int64_t rhs_stride, int n1x, int n1y, int My, int H, const AxisPlan& pl, const void* tw, int ncol,
+                       int nthr, hipStream_t st);
+template <typename T>
+hipError_t launch_strided(void* data, const StridedArgs& a, const CompSet& cs, int nplanes, const AxisPlan& pl,
+                          const void* tw, const uint8_t* lflag, const uint8_t* pflag, int nthr, hipStream_t st);
+template <typename T>
+hipError_t launch_sandwich(const void* Fin, void* Fout, const void* R, const SandArgs& a, const AxisPlan& pl,
+                           const void* tw, const void* phx, const void* phy, const void* phz, const uint8_t* pflag,
+                           int nthr, hipStream_t st);
+template <typename T>
+hipError_t launch_zinv(const void* O, double* y, const double* x, int64_t N, int nrhs, int mode, const int32_t* items,
+                       int nitems, const int32_t* line_ptr, const int32_t* pk, const int8_t* pkind,
+                       const double* diag, const uint8_t* lflag, int64_t comp_stride, int64_t rhs_stride, int n1x,
+                       int n1y, int My, int H, const AxisPlan& pl, const void* tw, int ncol, int nthr,
+                       hipStream_t st);
+
+// setup kernels (setup_kernels.hip)
+struct FillArgs {
+  int alpha, beta, want;   // want 0 = P (eq. 5), 1 = E (eq. 6)
+  int Mx, My, Mz;
+  int no[3], ns[3];        // observer / source panel counts per axis
+  double scale;            // folded inverse-FFT normalisation 1/(Mx My Mz)
+};
+hipError_t launch_fill_circulant(double* C, const FillArgs& a, const double* gl_nodes, hipStream_t st);
+hipError_t launch_zr2c_dense(const double* in, void* out, int nlines, int H, const AxisPlan& pl, const void* tw,
+                             int ncol, int nthr, hipStream_t st);
+struct ExtractArgs {
+  int Mx, My, Mz, H, Hx, Hy;
+  int kind;                // 0: P diagonal pair, 1: P off-diagonal, 2: E
+  int alpha, beta;
+  int64_t pair_off;        // element offset of this pair in the stored arrays
+};
+hipError_t launch_extract(const void* spec, double* R64, float* R32, const ExtractArgs& a, double* resid,
+                          hipStream_t st);
+// panel-integral kernel for host tables (preconditioner blocks): out[i] = K(alpha,beta,d_i)
+hipError_t launch_kernel_table(const double* d, int n, int alpha, int beta, int want, double* out,
+                               const double* gl_nodes, hipStream_t st);
+
+// solver kernels (solver_kernels.hip)
+hipError_t launch_gemv_t(const double* V, int64_t ldv, int64_t N, int k, const double* w, int64_t ldw, int nrhs,
+                         double* h, int64_t ldh, const int* active, double* partial, hipStream_t st);
+int64_t gemv_t_partial_size(int64_t N, int kmax, int nrhs);
+hipError_t launch_gemv_n_sub(const double* V, int64_t ldv, int64_t N, int k, const double* h, int64_t ldh,
+                             double* w, int64_t ldw, int nrhs, const int* active, int accumulate_into_h2,
+                             hipStream_t st);
+hipError_t launch_colnorm(const double* w, int64_t ldw, int64_t N, int nrhs, double* out, hipStream_t st);
+hipError_t launch_scale_cols(double* w, int64_t ldw, int64_t N, int nrhs, const double* s, int mode,
+                             hipStream_t st);
+hipError_t launch_axpy_cols(double* y, const double* x, int64_t N, int nrhs, const double* a, int sub,
+                            hipStream_t st);
+hipError_t launch_diag_scale(const double* x, double* y, const double* dinv, int64_t N, int nrhs, hipStream_t st);
+hipError_t launch_block_apply(const double* x, double* y, int64_t N, int nrhs, const int32_t* box_ptr,
+                              const int32_t* box_panels, const int32_t* box_block, const int64_t* block_off,
+                              const int32_t* block_n, const double* blocks, int nbox, hipStream_t st);
+hipError_t launch_cap_reduce(const double* rho, int64_t N, int m, const int32_t* cond_panels,
+                             const int32_t* cond_ptr, const double* weight, double scale, double* C,
+                             hipStream_t st);
+
+}  // namespace vc

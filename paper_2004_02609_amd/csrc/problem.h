@@ -1,0 +1,131 @@
+// Internal state of one capacitance problem (host + device) -- not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/voxcap.h"
+#include "fft_core.hpp"
+
+namespace vc {
+
+void set_error(const char* fmt, ...);
+
+// Owning device allocation.
+struct DevMem {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevMem() = default;
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  ~DevMem() { reset(); }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t alloc(size_t n) {
+    reset();
+    if (n == 0) n = 16;
+    hipError_t e = hipMalloc(&p, n);
+    if (e == hipSuccess) bytes = n;
+    else p = nullptr;
+    return e;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// FFT tables of one axis in one precision.
+struct AxisTables {
+  AxisPlan plan{};
+  DevMem tw;   // L complex: exp(-2 pi i t / L)
+  DevMem ph;   // L complex: exp(+i pi k / L), the half-voxel shift
+};
+
+struct PrecTables {
+  AxisTables ax[3];
+  DevMem R;    // [15][Hy][H][Hx] real spectra (or empty for pairs not stored)
+};
+
+struct Precond {
+  int built = 0;
+  int mode = 1;   // 1 = block-diagonal-diagonal, 2 = diagonal only
+  int nbox = 0;
+  int nblock = 0;
+  int64_t block_doubles = 0;
+  DevMem box_ptr, box_panels, box_block, block_off, block_n, blocks, dinv, dinv_diag;
+  std::vector<int32_t> h_box_ptr, h_box_panels, h_box_block, h_block_n;
+  std::vector<int64_t> h_block_off;
+  std::vector<double> h_blocks;
+};
+
+}  // namespace vc
+
+struct vc_problem {
+  int device = 0;
+  int nx = 0, ny = 0, nz = 0;
+  double dv = 0.0, eps_b = 1.0;
+  std::vector<int32_t> cond_id;
+  std::vector<double> eps_r;
+  // panels in library order (sorted by dir, i, j, k)
+  std::vector<vc_panel> panels;
+  int64_t n_cond = 0, n_diel = 0;
+  int m = 0;
+  int n1[3] = {0, 0, 0};
+  int M[3] = {0, 0, 0};
+  int H = 0, Hx = 0, Hy = 0;
+  // host index maps
+  std::vector<int32_t> line_ptr;    // 3*n1x*n1y + 1
+  std::vector<int32_t> items;       // lines holding panels
+  std::vector<uint8_t> lflag;       // per line: 1 conductor panel, 2 dielectric panel
+  std::vector<uint8_t> pflag;       // per (axis, x plane): OR of line flags
+  std::vector<int32_t> pk;          // z index per panel
+  std::vector<int8_t> pkind;
+  std::vector<double> diag;         // eq. (7) term, +axis convention (0 on conductor panels)
+  std::vector<int32_t> cond_ptr, cond_panels;   // conductor panels grouped by id
+  std::vector<double> weight;       // eps_adj on conductor panels
+  // setup state
+  bool setup_done = false;
+  bool hip_failed = false;
+  bool have64 = false, have32 = false;
+  int max_rhs = 0;
+  int nv[3] = {8, 8, 8};
+  double t_setup = 0.0;
+  double spectra_bytes = 0.0;
+  double extract_resid = 0.0;
+  // device mirrors
+  vc::DevMem d_line_ptr, d_items, d_lflag, d_pflag, d_pk, d_pkind, d_diag, d_cond_ptr, d_cond_panels, d_weight, d_gl;
+  vc::PrecTables t64, t32;
+  vc::DevMem work_F, work_O;        // spectral work arrays (sized for FP64, reused by FP32)
+  int64_t rhs_stride = 0, comp_stride = 0;
+  int ncomp_F = 0, ncomp_O = 0;
+  vc::Precond pc;
+  // solver workspace
+  vc::DevMem s_V, s_w, s_z, s_r, s_b, s_x, s_h, s_partial, s_norm, s_active, s_tmp, s_y2;
+  int s_restart = 0, s_nrhs = 0;
+  int mvp_count = 0;
+};
+
+namespace vc {
+inline int64_t npanels(const vc_problem* p) { return (int64_t)p->panels.size(); }
+vc_status panelize(vc_problem* p);
+vc_status choose_sizes(vc_problem* p, const int32_t* fft_size);
+vc_status build_spectra(vc_problem* p, int want64, int want32, hipStream_t st);
+vc_status build_precond(vc_problem* p, hipStream_t st);
+vc_status apply_op(vc_problem* p, int transpose, vc_precision prec, const double* x, double* y, int nrhs,
+                   hipStream_t st);
+vc_status apply_precond(vc_problem* p, int transpose, const double* x, double* y, int nrhs, hipStream_t st);
+AxisPlan make_plan(int L);
+bool smooth7(int n);
+}  // namespace vc
+
+#define VC_HIP(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t _e = (expr);                                                                   \
+    if (_e != hipSuccess) {                                                                   \
+      vc::set_error("HIP error %s at %s:%d (%s)", hipGetErrorString(_e), __FILE__, __LINE__, #expr); \
+      return VC_ERR_HIP;                                                                      \
+    }                                                                                         \
+  } while (0)

@@ -1,0 +1,361 @@
+// Setup of the FFT product (Sec. II.B, App. B) and of the preconditioner (Sec. II.D).
+//
+// Kernel spectra.  For each observer/source normal pair the Toeplitz tensor of App. B
+// (Algorithm 1: the integral of eq. 5 or eq. 6 for every index lag, source centre
+// offset from Tab. VII) is embedded in a circulant of length M_a >= 2 N_a + 1 per axis
+// (lag l at index l mod M_a; Tab. VIII-X are this embedding for M_a = 2(N_a+1)) and
+// transformed in FP64.  Every tensor is even in the lag components (odd along the
+// observer normal for eq. 6), so after removing the half-voxel phase
+// exp(-i pi k_alpha/M_alpha) exp(+i pi k_beta/M_beta) (and a factor i for eq. 6) its
+// spectrum is real and has a definite parity under k_a -> M_a - k_a; only the octant
+// 0 <= k_a <= M_a/2 is stored.  Eq. (12) is the statement that the pair (beta, alpha)
+// is the complex conjugate of (alpha, beta): only 6 of the 9 P spectra are stored.
+//
+// Preconditioner.  The box is cut into nv voxel boxes; the conductor panels owned by a
+// box (those on a conductor voxel of that box) form one dense block of eq. (5) values,
+// which is Cholesky-factored and inverted in FP64.  Identical panel patterns share one
+// inverse.  Dielectric rows use the inverse of the eq. (7) diagonal.
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <vector>
+
+#include "mvp_kernels.h"
+#include "problem.h"
+
+namespace vc {
+
+int pair_index_P(int a, int b) { return a == b ? a : 2 + a + b; }
+int pair_index_E(int a, int b) { return 6 + 3 * a + b; }
+
+int pair_odd_bits(int q) {
+  if (q < 3) return 0;
+  if (q < 6) {
+    const int s = q - 2;   // a + b
+    const int a = (s == 1 || s == 2) ? 0 : 1;
+    const int b = s - a;
+    return (1 << a) | (1 << b);
+  }
+  const int a = (q - 6) / 3, b = (q - 6) % 3;
+  return a == b ? (1 << a) : (1 << b);
+}
+
+void pair_axes(int q, int* a, int* b, int* want) {
+  if (q < 3) { *a = *b = q; *want = 0; return; }
+  if (q < 6) {
+    const int s = q - 2;
+    *a = (s == 1 || s == 2) ? 0 : 1;
+    *b = s - *a;
+    *want = 0;
+    return;
+  }
+  *a = (q - 6) / 3;
+  *b = (q - 6) % 3;
+  *want = 1;
+}
+
+static void gauss_legendre_table(std::vector<double>& gl) {
+  gl.assign(11 * 24, 0.0);
+  for (int n = 1; n <= 10; ++n) {
+    for (int i = 0; i < n; ++i) {
+      long double x = cosl(M_PI * (i + 0.75L) / (n + 0.5L));
+      for (int it = 0; it < 100; ++it) {
+        long double p0 = 1.0L, p1 = x;
+        for (int k = 2; k <= n; ++k) {
+          long double p2 = ((2.0L * k - 1.0L) * x * p1 - (k - 1.0L) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        if (n == 1) { p0 = 1.0L; p1 = x; }
+        long double dp = n * (x * p1 - p0) / (x * x - 1.0L);
+        long double dx = p1 / dp;
+        x -= dx;
+        if (fabsl(dx) < 1e-19L) break;
+      }
+      long double p0 = 1.0L, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        long double p2 = ((2.0L * k - 1.0L) * x * p1 - (k - 1.0L) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p0 = 1.0L; p1 = x; }
+      long double dp = n * (x * p1 - p0) / (x * x - 1.0L);
+      long double w = 2.0L / ((1.0L - x * x) * dp * dp);
+      gl[n * 24 + i] = (double)(0.5L * x);
+      gl[n * 24 + 12 + i] = (double)(0.5L * w);
+    }
+  }
+}
+
+template <typename T>
+static hipError_t upload_axis(AxisTables& t, int L) {
+  t.plan = make_plan(L);
+  std::vector<T> tw(2 * L), ph(2 * L);
+  for (int k = 0; k < L; ++k) {
+    const long double a = 2.0L * (long double)M_PI * k / L;
+    tw[2 * k] = (T)cosl(a);
+    tw[2 * k + 1] = (T)(-sinl(a));
+    const long double b = (long double)M_PI * k / L;
+    ph[2 * k] = (T)cosl(b);
+    ph[2 * k + 1] = (T)sinl(b);
+  }
+  hipError_t e = t.tw.alloc(tw.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  e = hipMemcpy(t.tw.p, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  e = t.ph.alloc(ph.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(t.ph.p, ph.data(), ph.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// Largest tile (columns per workgroup) whose LDS use fits `budget` bytes and whose
+// element count L*ncol stays within emax per thread for at most 1024 threads.
+bool pick_tile(int L, int elem_bytes, int emax, int ncols_total, int* ncol, int* nthr, size_t budget) {
+  int best = 0;
+  for (int c : {32, 16, 8, 4, 2, 1}) {
+    const size_t lds = (size_t)elem_bytes * ((size_t)L + (size_t)L * (c + 1));
+    const int64_t thr = ((int64_t)L * c + emax - 1) / emax;
+    if (lds <= budget && thr <= 1024 && (c == 1 || c <= 2 * ncols_total)) { best = c; break; }
+  }
+  if (best == 0) { set_error("no FFT tile fits length %d", L); return false; }
+  int64_t thr = ((int64_t)L * best + emax - 1) / emax;
+  thr = ((thr + 63) / 64) * 64;
+  if (thr < 64) thr = 64;
+  *ncol = best;
+  *nthr = (int)thr;
+  return (int64_t)L * best <= (int64_t)emax * thr && thr <= 1024;
+}
+
+template <typename T>
+static vc_status upload(DevMem& d, const std::vector<T>& h) {
+  VC_HIP(d.alloc(h.size() * sizeof(T)));
+  if (!h.empty()) VC_HIP(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return VC_OK;
+}
+
+vc_status build_spectra(vc_problem* P, int want64, int want32, hipStream_t st) {
+  const int Mx = P->M[0], My = P->M[1], Mz = P->M[2];
+  const int H = P->H, Hx = P->Hx, Hy = P->Hy;
+  // index maps
+  vc_status s;
+  if ((s = upload(P->d_line_ptr, P->line_ptr)) != VC_OK) return s;
+  if ((s = upload(P->d_items, P->items)) != VC_OK) return s;
+  if ((s = upload(P->d_lflag, P->lflag)) != VC_OK) return s;
+  if ((s = upload(P->d_pflag, P->pflag)) != VC_OK) return s;
+  if ((s = upload(P->d_pk, P->pk)) != VC_OK) return s;
+  if ((s = upload(P->d_pkind, P->pkind)) != VC_OK) return s;
+  if ((s = upload(P->d_diag, P->diag)) != VC_OK) return s;
+  if ((s = upload(P->d_cond_ptr, P->cond_ptr)) != VC_OK) return s;
+  if ((s = upload(P->d_cond_panels, P->cond_panels)) != VC_OK) return s;
+  if ((s = upload(P->d_weight, P->weight)) != VC_OK) return s;
+  std::vector<double> gl;
+  gauss_legendre_table(gl);
+  if ((s = upload(P->d_gl, gl)) != VC_OK) return s;
+  for (int a = 0; a < 3; ++a) {
+    VC_HIP(upload_axis<double>(P->t64.ax[a], P->M[a]));
+    VC_HIP(upload_axis<float>(P->t32.ax[a], P->M[a]));
+    if (P->t64.ax[a].plan.nst < 0) { set_error("FFT size %d not 7-smooth", P->M[a]); return VC_ERR_ARG; }
+  }
+  const int npairs = P->n_diel > 0 ? 15 : 6;
+  const int64_t per_pair = (int64_t)Hy * H * Hx;
+  P->have64 = want64;
+  P->have32 = want32;
+  P->spectra_bytes = 0;
+  if (want64) { VC_HIP(P->t64.R.alloc((size_t)15 * per_pair * sizeof(double))); P->spectra_bytes += (double)npairs * per_pair * 8; }
+  if (want32) { VC_HIP(P->t32.R.alloc((size_t)15 * per_pair * sizeof(float))); P->spectra_bytes += (double)npairs * per_pair * 4; }
+  DevMem circ, spec, resid;
+  VC_HIP(circ.alloc((size_t)Mx * My * Mz * sizeof(double)));
+  VC_HIP(spec.alloc((size_t)Mx * My * H * 2 * sizeof(double)));
+  VC_HIP(resid.alloc(sizeof(double)));
+  VC_HIP(hipMemsetAsync(resid.p, 0, sizeof(double), st));
+  const int n[3] = {P->nx, P->ny, P->nz};
+  const double scale = 1.0 / ((double)Mx * My * Mz);
+  for (int q = 0; q < npairs; ++q) {
+    int a, b, want;
+    pair_axes(q, &a, &b, &want);
+    FillArgs fa{};
+    fa.alpha = a; fa.beta = b; fa.want = want;
+    fa.Mx = Mx; fa.My = My; fa.Mz = Mz;
+    for (int ax = 0; ax < 3; ++ax) {
+      fa.no[ax] = n[ax] + (ax == a);
+      fa.ns[ax] = n[ax] + (ax == b);
+    }
+    fa.scale = scale;
+    VC_HIP(launch_fill_circulant(circ.as<double>(), fa, P->d_gl.as<double>(), st));
+    int ncol, nthr;
+    if (!pick_tile(Mz, 16, kEmax, Mx * My, &ncol, &nthr, kLdsBudget)) return VC_ERR_ARG;
+    VC_HIP(launch_zr2c_dense(circ.as<double>(), spec.p, Mx * My, H, P->t64.ax[2].plan, P->t64.ax[2].tw.p, ncol, nthr, st));
+    CompSet cs{};
+    cs.n = 1;
+    StridedArgs sa{};
+    sa.comp_stride = 0; sa.rhs_stride = 0;
+    sa.ncols = H; sa.nrhs = 1; sa.inverse = 0; sa.n1x = 0; sa.n1y = 0;
+    // y pass over all Mx planes
+    if (!pick_tile(My, 16, kEmax, H, &ncol, &nthr, kLdsBudget)) return VC_ERR_ARG;
+    sa.plane_stride = (int64_t)My * H; sa.row_stride = H; sa.ncol = ncol; sa.nin = My; sa.nout = My;
+    VC_HIP(launch_strided<double>(spec.p, sa, cs, Mx, P->t64.ax[1].plan, P->t64.ax[1].tw.p, nullptr, nullptr, nthr, st));
+    // x pass over all My planes
+    if (!pick_tile(Mx, 16, kEmax, H, &ncol, &nthr, kLdsBudget)) return VC_ERR_ARG;
+    sa.plane_stride = H; sa.row_stride = (int64_t)My * H; sa.ncol = ncol; sa.nin = Mx; sa.nout = Mx;
+    VC_HIP(launch_strided<double>(spec.p, sa, cs, My, P->t64.ax[0].plan, P->t64.ax[0].tw.p, nullptr, nullptr, nthr, st));
+    ExtractArgs ea{};
+    ea.Mx = Mx; ea.My = My; ea.Mz = Mz; ea.H = H; ea.Hx = Hx; ea.Hy = Hy;
+    ea.kind = want == 1 ? 2 : (a == b ? 0 : 1);
+    ea.alpha = a; ea.beta = b;
+    ea.pair_off = (int64_t)q * per_pair;
+    VC_HIP(launch_extract(spec.p, want64 ? P->t64.R.as<double>() : nullptr, want32 ? P->t32.R.as<float>() : nullptr, ea,
+                          resid.as<double>(), st));
+  }
+  double r = 0.0;
+  VC_HIP(hipMemcpyAsync(&r, resid.p, sizeof(double), hipMemcpyDeviceToHost, st));
+  VC_HIP(hipStreamSynchronize(st));
+  P->extract_resid = r;
+  return VC_OK;
+}
+
+// ------------------------------------------------------------------------------ preconditioner
+static bool cholesky_inverse(std::vector<double>& A, int n) {
+  // A (n x n, row-major, symmetric positive definite) -> A^{-1}
+  std::vector<double> L(A);
+  for (int j = 0; j < n; ++j) {
+    double d = L[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    L[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double s = L[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) s -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      L[(size_t)i * n + j] = s / d;
+    }
+  }
+  // inverse of L (lower)
+  std::vector<double> Li((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    Li[(size_t)j * n + j] = 1.0 / L[(size_t)j * n + j];
+    for (int i = j + 1; i < n; ++i) {
+      double s = 0.0;
+      for (int k = j; k < i; ++k) s -= L[(size_t)i * n + k] * Li[(size_t)k * n + j];
+      Li[(size_t)i * n + j] = s / L[(size_t)i * n + i];
+    }
+  }
+  // A^{-1} = Li^T Li
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = 0.0;
+      for (int k = i; k < n; ++k) s += Li[(size_t)k * n + i] * Li[(size_t)k * n + j];
+      A[(size_t)i * n + j] = s;
+      A[(size_t)j * n + i] = s;
+    }
+  return true;
+}
+
+vc_status build_precond(vc_problem* P, hipStream_t st) {
+  Precond& pc = P->pc;
+  const int nvx = P->nv[0], nvy = P->nv[1], nvz = P->nv[2];
+  const int64_t N = npanels(P);
+  // kernel table of eq. (5) for every lag inside a box: lag in [-nv, nv] per axis
+  const int ex = 2 * nvx + 1, ey = 2 * nvy + 1, ez = 2 * nvz + 1;
+  const int64_t nl = (int64_t)ex * ey * ez;
+  std::vector<double> tab(9 * nl);
+  {
+    std::vector<double> d(3 * nl);
+    DevMem dd, dout;
+    VC_HIP(dd.alloc(d.size() * sizeof(double)));
+    VC_HIP(dout.alloc(nl * sizeof(double)));
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        int64_t t = 0;
+        for (int lx = -nvx; lx <= nvx; ++lx)
+          for (int ly = -nvy; ly <= nvy; ++ly)
+            for (int lz = -nvz; lz <= nvz; ++lz, ++t) {
+              double o[3] = {(double)lx, (double)ly, (double)lz};
+              if (a != b) { o[a] -= 0.5; o[b] += 0.5; }
+              d[3 * t] = o[0]; d[3 * t + 1] = o[1]; d[3 * t + 2] = o[2];
+            }
+        VC_HIP(hipMemcpy(dd.p, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice));
+        VC_HIP(launch_kernel_table(dd.as<double>(), (int)nl, a, b, 0, dout.as<double>(), P->d_gl.as<double>(), st));
+        VC_HIP(hipMemcpyAsync(&tab[(size_t)(3 * a + b) * nl], dout.p, nl * sizeof(double), hipMemcpyDeviceToHost, st));
+        VC_HIP(hipStreamSynchronize(st));
+      }
+  }
+  // group conductor panels by owning box
+  const int nbx = (P->nx + nvx - 1) / nvx, nby = (P->ny + nvy - 1) / nvy, nbz = (P->nz + nvz - 1) / nvz;
+  std::map<int64_t, std::vector<int32_t>> boxes;
+  for (int64_t p = 0; p < N; ++p) {
+    const vc_panel& pn = P->panels[p];
+    if (pn.kind != 0) continue;
+    int v[3] = {pn.i, pn.j, pn.k};
+    if (pn.eps_lo == 0.0) v[pn.dir] -= 1;   // conductor on the -axis side
+    const int64_t key = ((int64_t)(v[0] / nvx) * nby + v[1] / nvy) * nbz + v[2] / nvz;
+    boxes[key].push_back((int32_t)p);
+  }
+  (void)nbx;
+  std::map<std::vector<int32_t>, int> uniq;
+  pc.h_box_ptr.assign(1, 0);
+  pc.h_box_panels.clear();
+  pc.h_box_block.clear();
+  pc.h_block_n.clear();
+  pc.h_block_off.clear();
+  pc.h_blocks.clear();
+  for (auto& kv : boxes) {
+    const int64_t key = kv.first;
+    const int bz = (int)(key % nbz), by = (int)((key / nbz) % nby), bx = (int)(key / ((int64_t)nbz * nby));
+    const int ox = bx * nvx, oy = by * nvy, oz = bz * nvz;
+    const auto& pl = kv.second;
+    const int nb = (int)pl.size();
+    if (nb > 4096) { set_error("preconditioner box holds %d panels (> 4096); use smaller nv", nb); return VC_ERR_ARG; }
+    std::vector<int32_t> pat;
+    pat.reserve(4 * nb);
+    for (int32_t p : pl) {
+      const vc_panel& pn = P->panels[p];
+      pat.push_back(pn.dir); pat.push_back(pn.i - ox); pat.push_back(pn.j - oy); pat.push_back(pn.k - oz);
+    }
+    auto it = uniq.find(pat);
+    int blk;
+    if (it == uniq.end()) {
+      std::vector<double> A((size_t)nb * nb);
+      for (int r = 0; r < nb; ++r)
+        for (int c = 0; c < nb; ++c) {
+          const vc_panel& pr = P->panels[pl[r]];
+          const vc_panel& pcn = P->panels[pl[c]];
+          const int lx = pr.i - pcn.i, ly = pr.j - pcn.j, lz = pr.k - pcn.k;
+          const int64_t t = ((int64_t)(lx + nvx) * ey + (ly + nvy)) * ez + (lz + nvz);
+          A[(size_t)r * nb + c] = tab[(size_t)(3 * pr.dir + pcn.dir) * nl + t];
+        }
+      if (!cholesky_inverse(A, nb)) { set_error("preconditioner block not positive definite"); return VC_ERR_NUMERIC; }
+      blk = (int)pc.h_block_n.size();
+      uniq.emplace(std::move(pat), blk);
+      pc.h_block_n.push_back(nb);
+      pc.h_block_off.push_back((int64_t)pc.h_blocks.size());
+      pc.h_blocks.insert(pc.h_blocks.end(), A.begin(), A.end());
+    } else {
+      blk = it->second;
+    }
+    for (int32_t p : pl) pc.h_box_panels.push_back(p);
+    pc.h_box_ptr.push_back((int32_t)pc.h_box_panels.size());
+    pc.h_box_block.push_back(blk);
+  }
+  pc.nbox = (int)pc.h_box_block.size();
+  pc.nblock = (int)pc.h_block_n.size();
+  pc.block_doubles = (int64_t)pc.h_blocks.size();
+  std::vector<double> dinv(N, 0.0), dinv_diag(N, 0.0);
+  const double pself = tab[(size_t)0 * nl + ((int64_t)nvx * ey + nvy) * ez + nvz];
+  for (int64_t p = 0; p < N; ++p) {
+    if (P->panels[p].kind == 1) dinv[p] = dinv_diag[p] = 1.0 / P->diag[p];
+    else dinv_diag[p] = 1.0 / pself;
+  }
+  vc_status s;
+  if ((s = upload(pc.box_ptr, pc.h_box_ptr)) != VC_OK) return s;
+  if ((s = upload(pc.box_panels, pc.h_box_panels)) != VC_OK) return s;
+  if ((s = upload(pc.box_block, pc.h_box_block)) != VC_OK) return s;
+  if ((s = upload(pc.block_off, pc.h_block_off)) != VC_OK) return s;
+  if ((s = upload(pc.block_n, pc.h_block_n)) != VC_OK) return s;
+  if ((s = upload(pc.blocks, pc.h_blocks)) != VC_OK) return s;
+  if ((s = upload(pc.dinv, dinv)) != VC_OK) return s;
+  if ((s = upload(pc.dinv_diag, dinv_diag)) != VC_OK) return s;
+  pc.built = 1;
+  return VC_OK;
+}
+
+}  // namespace vc

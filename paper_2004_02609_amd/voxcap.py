@@ -1,0 +1,265 @@
+"""ctypes binding of libvoxcap.so (include/voxcap.h).  Argument marshalling only:
+every step of the solve runs in the HIP library.  Device buffers are torch tensors
+(PyTorch supplies device memory and streams); host arrays are numpy.
+
+The functions named vc_* mirror the C entry points one to one; `Problem` wraps them.
+If the shared library is missing this module raises at import: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvoxcap.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_2004_02609_amd/build.py "
+                      "(or __graft_entry__.build())")
+_lib = C.CDLL(LIB_PATH)
+
+VC_OK, VC_ERR_ARG, VC_ERR_GEOMETRY, VC_ERR_HIP, VC_ERR_OOM, VC_ERR_NOT_CONVERGED, VC_ERR_NUMERIC, VC_ERR_STATE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+VC_FP64, VC_FP32, VC_MIXED = 0, 1, 2
+_PREC = {"fp64": VC_FP64, "fp32": VC_FP32, "mixed": VC_MIXED}
+
+
+class vc_geometry(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("dv", C.c_double),
+                ("cond_id", C.POINTER(C.c_int32)), ("eps_r", C.POINTER(C.c_double)),
+                ("eps_background", C.c_double)]
+
+
+class vc_panel(C.Structure):
+    _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("k", C.c_int32), ("dir", C.c_int8), ("kind", C.c_int8),
+                ("pad", C.c_int16), ("cond", C.c_int32), ("eps_lo", C.c_double), ("eps_hi", C.c_double),
+                ("eps_adj", C.c_double)]
+
+
+PANEL_DTYPE = np.dtype({"names": ["i", "j", "k", "dir", "kind", "pad", "cond", "eps_lo", "eps_hi", "eps_adj"],
+                        "formats": ["<i4", "<i4", "<i4", "i1", "i1", "<i2", "<i4", "<f8", "<f8", "<f8"],
+                        "offsets": [vc_panel.i.offset, vc_panel.j.offset, vc_panel.k.offset, vc_panel.dir.offset,
+                                    vc_panel.kind.offset, vc_panel.pad.offset, vc_panel.cond.offset,
+                                    vc_panel.eps_lo.offset, vc_panel.eps_hi.offset, vc_panel.eps_adj.offset],
+                        "itemsize": C.sizeof(vc_panel)})
+
+
+class vc_setup_opts(C.Structure):
+    _fields_ = [("fft_size", C.c_int32 * 3), ("nv", C.c_int32 * 3), ("tucker_tol", C.c_double),
+                ("precisions", C.c_int32), ("max_rhs", C.c_int32)]
+
+
+class vc_solve_opts(C.Structure):
+    _fields_ = [("prec", C.c_int), ("rtol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
+                ("inner_rtol", C.c_double), ("ir_max", C.c_int32), ("use_precond", C.c_int32)]
+
+
+class vc_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32 * 64), ("final_rre", C.c_double * 64), ("ir_steps", C.c_int32),
+                ("mvp_count", C.c_int32), ("t_setup_s", C.c_double), ("t_solve_s", C.c_double),
+                ("spectra_bytes", C.c_double), ("tucker_rank_max", C.c_int32)]
+
+
+_P = C.c_void_p
+_sig = {
+    "vc_problem_create": (C.c_int, [C.POINTER(vc_geometry), C.c_int, C.POINTER(_P)]),
+    "vc_problem_destroy": (C.c_int, [_P]),
+    "vc_panel_counts": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    "vc_panels": (C.c_int, [_P, C.c_void_p]),
+    "vc_fft_size": (C.c_int, [_P, C.POINTER(C.c_int32)]),
+    "vc_setup": (C.c_int, [_P, C.POINTER(vc_setup_opts), _P]),
+    "vc_apply": (C.c_int, [_P, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int32, _P]),
+    "vc_apply_precond": (C.c_int, [_P, C.c_int, C.c_void_p, C.c_void_p, C.c_int32, _P]),
+    "vc_capacitance": (C.c_int, [_P, C.POINTER(vc_solve_opts), C.POINTER(C.c_double), C.c_void_p,
+                                 C.POINTER(vc_stats)]),
+    "vc_capacitance_grad_eps": (C.c_int, [_P, C.POINTER(vc_solve_opts), C.POINTER(C.c_int32), C.c_int32,
+                                          C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(vc_stats)]),
+    "vc_status_string": (C.c_char_p, [C.c_int]),
+    "vc_last_error": (C.c_char_p, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+EXPORTED = tuple(_sig)
+
+
+class VoxcapError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.vc_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {_lib.vc_status_string(status).decode()} ({status}): {msg}")
+
+
+def _check(st, where, allow=()):
+    if st != VC_OK and st not in allow:
+        raise VoxcapError(st, where)
+    return st
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+# ------------------------------------------------------------------ one-to-one wrappers
+def vc_problem_create(cond_id, eps_r, dv, eps_background=1.0, device=0):
+    cond_id = np.ascontiguousarray(cond_id, dtype=np.int32)
+    eps_r = np.ascontiguousarray(eps_r, dtype=np.float64)
+    if cond_id.ndim != 3 or cond_id.shape != eps_r.shape:
+        raise ValueError("cond_id and eps_r must be equal 3-D arrays")
+    g = vc_geometry(cond_id.shape[0], cond_id.shape[1], cond_id.shape[2], float(dv),
+                    cond_id.ctypes.data_as(C.POINTER(C.c_int32)), eps_r.ctypes.data_as(C.POINTER(C.c_double)),
+                    float(eps_background))
+    h = _P()
+    _check(_lib.vc_problem_create(C.byref(g), int(device), C.byref(h)), "vc_problem_create")
+    return h
+
+
+def vc_problem_destroy(h):
+    return _lib.vc_problem_destroy(h)
+
+
+def vc_panel_counts(h):
+    nc, nd, m = C.c_int64(), C.c_int64(), C.c_int32()
+    _check(_lib.vc_panel_counts(h, C.byref(nc), C.byref(nd), C.byref(m)), "vc_panel_counts")
+    return nc.value, nd.value, m.value
+
+
+def vc_panels(h):
+    nc, nd, _ = vc_panel_counts(h)
+    out = np.zeros(nc + nd, PANEL_DTYPE)
+    _check(_lib.vc_panels(h, out.ctypes.data_as(C.c_void_p)), "vc_panels")
+    return out
+
+
+def vc_fft_size(h):
+    m = (C.c_int32 * 3)()
+    _check(_lib.vc_fft_size(h, m), "vc_fft_size")
+    return tuple(m)
+
+
+def vc_setup(h, fft_size=None, nv=None, tucker_tol=0.0, precisions=0, max_rhs=0, stream=None):
+    o = vc_setup_opts()
+    if fft_size is not None:
+        o.fft_size[:] = [int(v) for v in fft_size]
+    if nv is not None:
+        o.nv[:] = [int(v) for v in (nv if np.ndim(nv) else (nv, nv, nv))]
+    o.tucker_tol = float(tucker_tol)
+    o.precisions = int(precisions)
+    o.max_rhs = int(max_rhs)
+    _check(_lib.vc_setup(h, C.byref(o), _stream(stream)), "vc_setup")
+
+
+def vc_apply(h, x, y, nrhs, transpose=False, prec="fp64", stream=None):
+    _check(_lib.vc_apply(h, int(bool(transpose)), _PREC[prec], _ptr(x), _ptr(y), int(nrhs), _stream(stream)),
+           "vc_apply")
+
+
+def vc_apply_precond(h, x, y, nrhs, transpose=False, stream=None):
+    _check(_lib.vc_apply_precond(h, int(bool(transpose)), _ptr(x), _ptr(y), int(nrhs), _stream(stream)),
+           "vc_apply_precond")
+
+
+def _solve_opts(prec="fp64", rtol=0.0, restart=0, max_iter=0, inner_rtol=0.0, ir_max=0, use_precond=1):
+    o = vc_solve_opts()
+    o.prec = _PREC[prec]
+    o.rtol = rtol
+    o.restart = restart
+    o.max_iter = max_iter
+    o.inner_rtol = inner_rtol
+    o.ir_max = ir_max
+    o.use_precond = use_precond
+    return o
+
+
+def vc_capacitance(h, m, rho=None, allow_not_converged=False, **solve):
+    o = _solve_opts(**solve)
+    Cm = np.zeros((m, m))
+    st = vc_stats()
+    status = _check(_lib.vc_capacitance(h, C.byref(o), Cm.ctypes.data_as(C.POINTER(C.c_double)), _ptr(rho),
+                                        C.byref(st)), "vc_capacitance",
+                    allow=(VC_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+    return Cm, st, status
+
+
+def vc_capacitance_grad_eps(h, m, block_of_voxel, nblocks, **solve):
+    o = _solve_opts(**solve)
+    blk = np.ascontiguousarray(block_of_voxel, dtype=np.int32)
+    dC = np.zeros((nblocks, m, m))
+    Cm = np.zeros((m, m))
+    st = vc_stats()
+    _check(_lib.vc_capacitance_grad_eps(h, C.byref(o), blk.ctypes.data_as(C.POINTER(C.c_int32)), int(nblocks),
+                                        dC.ctypes.data_as(C.POINTER(C.c_double)),
+                                        Cm.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st)),
+           "vc_capacitance_grad_eps")
+    return dC, Cm, st
+
+
+def stats_dict(st, nrhs):
+    return {"iters": list(st.iters[:nrhs]), "final_rre": list(st.final_rre[:nrhs]), "ir_steps": st.ir_steps,
+            "mvp_count": st.mvp_count, "t_setup_s": st.t_setup_s, "t_solve_s": st.t_solve_s,
+            "spectra_bytes": st.spectra_bytes}
+
+
+class Problem:
+    """Owning wrapper of a vc_problem."""
+
+    def __init__(self, cond_id, eps_r, dv, eps_background=1.0, device=0):
+        self._h = vc_problem_create(cond_id, eps_r, dv, eps_background, device)
+        self.n_cond, self.n_diel, self.m = vc_panel_counts(self._h)
+        self.N = self.n_cond + self.n_diel
+        self.device = device
+
+    @classmethod
+    def from_scene(cls, scene, device=0):
+        return cls(scene["cond_id"], scene["eps_r"], scene["dv"], scene["eps_b"], device)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            vc_problem_destroy(h)
+            self._h = None
+
+    def panels(self):
+        return vc_panels(self._h)
+
+    def fft_size(self):
+        return vc_fft_size(self._h)
+
+    def setup(self, **kw):
+        vc_setup(self._h, **kw)
+        return self
+
+    def apply(self, x, y=None, transpose=False, prec="fp64", stream=None):
+        """y = A x for x a (nrhs, N) float64 cuda tensor."""
+        import torch
+        x = x.contiguous()
+        if y is None:
+            y = torch.empty_like(x)
+        vc_apply(self._h, x, y, x.shape[0], transpose, prec, stream)
+        return y
+
+    def apply_precond(self, x, y=None, transpose=False, stream=None):
+        import torch
+        x = x.contiguous()
+        if y is None:
+            y = torch.empty_like(x)
+        vc_apply_precond(self._h, x, y, x.shape[0], transpose, stream)
+        return y
+
+    def capacitance(self, rho=None, **solve):
+        Cm, st, _ = vc_capacitance(self._h, self.m, rho=rho, **solve)
+        return Cm, stats_dict(st, self.m)
+
+    def capacitance_grad_eps(self, block_of_voxel, nblocks, **solve):
+        dC, Cm, st = vc_capacitance_grad_eps(self._h, self.m, block_of_voxel, nblocks, **solve)
+        return dC, Cm, stats_dict(st, self.m)

@@ -1,0 +1,119 @@
+"""GPU parity of the FFT product, preconditioner and capacitance with the FP64 oracle.
+
+Tolerances: the FP64 product reaches the dense product up to rounding of the
+integrals (~1e-14 relative per entry) and of the FFTs (~1e-15 log2 R); 1e-11 of
+max|y| is a loose bound.  The FP32 product: FP32 FFTs of ~log2(R) stages, ~1e-6.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from helpers import oracle_matrix_library_order
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SCENES = [
+    ("cube5", lambda: scenes.cube(5, 1.0)),
+    ("small_s1", lambda: scenes.random_small(1, n_diel=0)),
+    ("small_s5", lambda: scenes.random_small(5, n_cond=2, n_diel=2)),
+    ("small_s9", lambda: scenes.random_small(9, shape=(11, 7, 13), n_cond=3, n_diel=2)),
+    ("ragged", lambda: scenes.random_small(13, shape=(9, 14, 5), n_cond=2, n_diel=1)),
+]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _problem(s, **kw):
+    from paper_2004_02609_amd import voxcap
+    P = voxcap.Problem.from_scene(s)
+    P.setup(**kw)
+    return P
+
+
+@pytest.mark.parametrize("name,make", SCENES)
+def test_fft_product_matches_dense(dev, name, make):
+    s = make()
+    P = _problem(s, max_rhs=3)
+    A, po, perm = oracle_matrix_library_order(s, P.panels())
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((3, P.N))
+    xt = torch.tensor(x, device=dev)
+    for transpose in (False, True):
+        y = P.apply(xt, transpose=transpose, prec="fp64").cpu().numpy()
+        ref = (A.T if transpose else A) @ x.T
+        err = np.abs(y - ref.T).max() / np.abs(ref).max()
+        print(name, "transpose" if transpose else "forward", "fp64 rel err", err, flush=True)
+        assert err < 1e-11, (name, transpose, err)
+        y32 = P.apply(xt, transpose=transpose, prec="fp32").cpu().numpy()
+        err32 = np.abs(y32 - ref.T).max() / np.abs(ref).max()
+        print(name, "fp32 rel err", err32, flush=True)
+        assert err32 < 2e-5, (name, transpose, err32)
+
+
+def test_precond_blocks_invert_dense_blocks(dev):
+    s = scenes.random_small(9, shape=(11, 7, 13), n_cond=3, n_diel=2)
+    P = _problem(s, nv=4)
+    A, po, perm = oracle_matrix_library_order(s, P.panels())
+    pan = P.panels()
+    N = P.N
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((2, N))
+    y = P.apply_precond(torch.tensor(x, device=dev)).cpu().numpy()
+    # reference: boxes of 4 voxels own the conductor panels of their conductor voxel
+    cond = pan["kind"] == 0
+    vox = np.stack([pan["i"], pan["j"], pan["k"]], 1).astype(int)
+    lo_is_cond = pan["eps_lo"] == 0.0
+    vox[np.arange(N), pan["dir"]] -= lo_is_cond.astype(int)
+    box = (vox // 4)
+    ref = np.zeros_like(x)
+    diel = ~cond
+    ref[:, diel] = x[:, diel] / np.diag(A)[diel]
+    keys = {}
+    for p in np.nonzero(cond)[0]:
+        keys.setdefault(tuple(box[p]), []).append(p)
+    for idx in keys.values():
+        idx = np.array(idx)
+        B = A[np.ix_(idx, idx)]
+        ref[:, idx] = np.linalg.solve(B, x[:, idx].T).T
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    assert err < 1e-10, err
+
+
+@pytest.mark.parametrize("name,make", SCENES)
+def test_capacitance_fp64(dev, name, make):
+    s = make()
+    P = _problem(s)
+    C, st = P.capacitance(prec="fp64", rtol=1e-13)
+    C_ref = oracle.solve_capacitance(s)
+    err = np.abs(C - C_ref).max() / np.abs(np.diag(C_ref)).max()
+    print(name, "C fp64 normwise rel err", err, "iters", st["iters"], flush=True)
+    assert err < 1e-10, (name, err)
+
+
+@pytest.mark.parametrize("name,make", SCENES[2:4])
+def test_capacitance_mixed(dev, name, make):
+    s = make()
+    P = _problem(s)
+    C, st = P.capacitance(prec="mixed", rtol=1e-10)
+    C_ref = oracle.solve_capacitance(s)
+    d = np.abs(np.diag(C_ref)).max()
+    gate = np.abs(C_ref) >= 1e-3 * d
+    rel = np.abs(C - C_ref)[gate] / np.abs(C_ref)[gate]
+    print(name, "C mixed max entry rel err", rel.max(), "ir", st["ir_steps"], st["iters"], flush=True)
+    assert rel.max() < 1e-6
+
+
+def test_unit_cube_16(dev):
+    s = scenes.cube(16)
+    P = _problem(s)
+    C, st = P.capacitance(prec="fp64", rtol=1e-13)
+    C_ref = oracle.solve_capacitance(s)
+    assert abs(C[0, 0] / C_ref[0, 0] - 1) < 1e-10
+    assert abs(C[0, 0] / (4 * np.pi * oracle.EPS0) / 0.66068 - 1) < 0.01
