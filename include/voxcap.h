@@ -158,6 +158,17 @@ vc_status vc_capacitance_grad_eps(vc_problem *p, const vc_solve_opts *opts,
                                   const int32_t *block_of_voxel, int32_t nblocks,
                                   double *dC, double *C_out, vc_stats *stats);
 
+/* Per-pass timing of the product (measurement only).  While enabled, vc_apply records
+ * HIP events on its stream around each of its passes:
+ *   0 scatter + z transform, 1 y transform, 2 x transform + block multiply + inverse x,
+ *   3 inverse y transform, 4 inverse z transform + gather.
+ * vc_pass_times waits for the recorded events and returns, per pass, the summed
+ * milliseconds, the number of launches, and the algorithmic bytes of ONE launch of the
+ * most recent vc_apply (compulsory reads + writes of the pruned pass, counting the
+ * kernel spectra once per launch); it then clears the accumulators. */
+vc_status vc_profile_enable(vc_problem *p, int enable);
+vc_status vc_pass_times(vc_problem *p, double ms[5], int32_t launches[5], double bytes[5]);
+
 const char *vc_status_string(vc_status s);
 const char *vc_last_error(void);
 

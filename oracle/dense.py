@@ -85,6 +85,50 @@ def assemble(p):
     return A
 
 
+def assemble_rows(p, rows):
+    """Rows `rows` (oracle order) of the matrix of eq. (4): the same integrals as
+    assemble(), for a bounded sample of the system."""
+    rows = np.asarray(rows)
+    n = len(p["axis"])
+    A = np.zeros((len(rows), n))
+    for a in range(3):
+        for kind in (0, 1):
+            sel = np.nonzero((p["axis"][rows] == a) & (p["kind"][rows] == kind))[0]
+            if len(sel) == 0:
+                continue
+            scale = None if kind == 0 else p["sign"][rows[sel]].astype(np.float64)
+            for b in range(3):
+                cols = np.nonzero(p["axis"] == b)[0]
+                sub = np.zeros((len(sel), len(cols)))
+                tmp = {"axis": p["axis"], "center": p["center"]}
+                # reuse the block filler on a private matrix indexed 0..len(sel)
+                Ablk = np.zeros((len(sel), n))
+                _block_rows(Ablk, tmp, rows[sel], cols, "P" if kind == 0 else "E", scale)
+                A[sel] += Ablk
+                del sub
+    jump = _jump(p)
+    A[np.arange(len(rows)), rows] += jump[rows]
+    return A
+
+
+def _block_rows(A, p, rows, cols, want, row_scale):
+    """Like _block, but A has one row per entry of `rows` (in that order)."""
+    if len(rows) == 0 or len(cols) == 0:
+        return
+    alpha = int(p["axis"][rows[0]])
+    beta = int(p["axis"][cols[0]])
+    co = p["center"][rows]
+    cs = p["center"][cols]
+    d2 = np.rint(2.0 * (co[:, None, :] - cs[None, :, :])).astype(np.int64)
+    flat = d2.reshape(-1, 3)
+    uniq, inv = np.unique(flat, axis=0, return_inverse=True)
+    vals = integrals.kernel(alpha, beta, uniq / 2.0, want)
+    blk = vals[inv.ravel()].reshape(len(rows), len(cols))
+    if row_scale is not None:
+        blk = blk * row_scale[:, None]
+    A[:, cols] = blk
+
+
 def rhs(p):
     """Unit potential on conductor j, zero on the others and on dielectric rows."""
     n = len(p["axis"])

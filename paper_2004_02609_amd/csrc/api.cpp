@@ -542,4 +542,28 @@ vc_status vc_capacitance_grad_eps(vc_problem* p, const vc_solve_opts* opts, cons
   return VC_OK;
 }
 
+vc_status vc_profile_enable(vc_problem* p, int enable) {
+  VC_CHECK_PROBLEM(p);
+  p->prof = enable != 0;
+  return VC_OK;
+}
+
+vc_status vc_pass_times(vc_problem* p, double ms[5], int32_t launches[5], double bytes[5]) {
+  VC_CHECK_PROBLEM(p);
+  if (!ms || !launches || !bytes) { set_error("null argument"); return VC_ERR_ARG; }
+  for (int i = 0; i < 5; ++i) { ms[i] = 0.0; launches[i] = 0; bytes[i] = p->pass_bytes[i]; }
+  for (auto& ev : p->ev_pending) {
+    VC_HIP(hipEventSynchronize(ev[5]));
+    for (int i = 0; i < 5; ++i) {
+      float t = 0.f;
+      VC_HIP(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+      ms[i] += t;
+      launches[i] += 1;
+    }
+    for (hipEvent_t e : ev) p->ev_free.push_back(e);
+  }
+  p->ev_pending.clear();
+  return VC_OK;
+}
+
 }  // extern "C"

@@ -16,8 +16,57 @@
 
 namespace vc {
 
-bool pick_tile(int L, int elem_bytes, int emax, int ncols_total, int* ncol, int* nthr, size_t budget);
 int pair_odd_bits(int q);
+
+static hipEvent_t take_event(vc_problem* P) {
+  if (!P->ev_free.empty()) {
+    hipEvent_t e = P->ev_free.back();
+    P->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Algorithmic bytes of one launch of each pass (compulsory traffic of the pruned pass
+// structure: every stored line/plane read or written once, kernel spectra read once).
+static void pass_byte_model(vc_problem* P, int transpose, int elem, int nrhs, double* out) {
+  const int n1x = P->n1[0], n1y = P->n1[1];
+  double Lany = 0, Lc = 0, Ld = 0, Pany = 0, Pc = 0, Pd = 0;
+  for (int a = 0; a < 3; ++a) {
+    for (int x = 0; x < n1x; ++x) {
+      const uint8_t pf = P->pflag[a * n1x + x];
+      Pany += pf != 0;
+      Pc += (pf & 1) != 0;
+      Pd += (pf & 2) != 0;
+      for (int y = 0; y < n1y; ++y) {
+        const uint8_t lf = P->lflag[((int64_t)a * n1x + x) * n1y + y];
+        Lany += lf != 0;
+        Lc += (lf & 1) != 0;
+        Ld += (lf & 2) != 0;
+      }
+    }
+  }
+  const double B = nrhs, row = (double)P->H * 2 * elem, plane = row * P->M[1];
+  const double N = (double)npanels(P), Nd = (double)P->n_diel, it = (double)P->items.size();
+  const double npairs = P->n_diel > 0 ? 15 : 6;
+  const double R = npairs * P->Hy * P->H * P->Hx * elem;
+  const double idx = N * 5 + it * 12;
+  if (!transpose) {
+    out[0] = N * B * 8 + idx + Lany * row * B;
+    out[1] = Lany * row * B + Pany * plane * B;
+    out[2] = Pany * plane * B + R + (Pc + Pd) * plane * B;
+    out[3] = (Pc + Pd) * plane * B + (Lc + Ld) * row * B;
+    out[4] = (Lc + Ld) * row * B + idx + N * 8 + Nd * B * 8 + N * B * 8;
+  } else {
+    out[0] = N * B * 8 + idx + 2 * Lany * row * B;
+    out[1] = (Lc + Ld) * row * B + (Pc + Pd) * plane * B;
+    out[2] = (Pc + Pd) * plane * B + R + Pany * plane * B;
+    out[3] = Pany * plane * B + Lany * row * B;
+    out[4] = Lany * row * B + idx + N * 8 + 2 * N * B * 8;
+  }
+}
 
 template <typename T>
 static vc_status run_apply(vc_problem* P, int transpose, const double* x, double* y, int nrhs, hipStream_t st) {
@@ -41,10 +90,20 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
   const uint8_t* lflag = P->d_lflag.as<uint8_t>();
   const uint8_t* pflag = P->d_pflag.as<uint8_t>();
   int ncol, nthr;
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (P->prof) {
+    for (int i = 0; i < 6; ++i)
+      if (!(ev[i] = take_event(P))) { set_error("hipEventCreate failed"); return VC_ERR_HIP; }
+    VC_HIP(hipEventRecord(ev[0], st));
+    pass_byte_model(P, transpose, (int)sizeof(T), nrhs, P->pass_bytes);
+  }
+#define VC_MARK(i) \
+  if (P->prof) VC_HIP(hipEventRecord(ev[i], st))
   // 1. scatter + z transform
-  if (!pick_tile(P->M[2], eb, kEmax, nitems, &ncol, &nthr, budget)) return VC_ERR_ARG;
+  if (!pick_tile(P->M[2], eb, Tune<T>::emax, nitems, &ncol, &nthr, budget, transpose ? nrhs : (nrhs + 1) / 2)) return VC_ERR_ARG;
   VC_HIP(launch_zfwd<T>(x, N, nrhs, transpose ? 1 : 0, items, nitems, lptr, pk, pkind, F, cs, rs, n1x, n1y, My, H,
                         tb.ax[2].plan, tb.ax[2].tw.p, ncol, nthr, st));
+  VC_MARK(1);
   // 2. y transform of the input components
   CompSet cin{};
   if (!transpose) {
@@ -57,43 +116,59 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
   StridedArgs sa{};
   sa.comp_stride = cs; sa.rhs_stride = rs; sa.plane_stride = (int64_t)My * H; sa.row_stride = H;
   sa.ncols = H; sa.nrhs = nrhs; sa.n1x = n1x; sa.n1y = n1y;
-  if (!pick_tile(My, eb, kEmax, H, &ncol, &nthr, budget)) return VC_ERR_ARG;
+  if (!pick_tile(My, eb, Tune<T>::emax, H, &ncol, &nthr, budget, (int64_t)n1x * cin.n * nrhs)) return VC_ERR_ARG;
   sa.ncol = ncol; sa.nin = n1y; sa.nout = My; sa.inverse = 0;
   VC_HIP(launch_strided<T>(F, sa, cin, n1x, tb.ax[1].plan, tb.ax[1].tw.p, lflag, pflag, nthr, st));
+  VC_MARK(2);
   // 3. x sandwich
   SandArgs xa{};
   xa.comp_stride = cs; xa.rhs_stride = rs; xa.pair_stride = (int64_t)P->Hy * H * P->Hx;
   xa.nrhs = nrhs; xa.n1x = n1x; xa.Mx = Mx; xa.My = My; xa.H = H; xa.Hx = P->Hx; xa.Hy = P->Hy;
-  for (int q = 0; q < 15; ++q) xa.odd[q] = pair_odd_bits(q);
+  xa.oddmask = 0;
+  for (int q = 0; q < 15; ++q) xa.oddmask |= (uint64_t)pair_odd_bits(q) << (3 * q);
   xa.adjoint = transpose;
   CompSet cout{};
   if (!transpose) {
     xa.nin = 3;
-    for (int b = 0; b < 3; ++b) { xa.in_comp[b] = b; xa.in_axis[b] = b; xa.in_mask[b] = 3; }
     xa.nout = diel ? 6 : 3;
-    for (int o = 0; o < xa.nout; ++o) { xa.out_comp[o] = o; xa.out_axis[o] = o % 3; xa.out_mask[o] = o < 3 ? 1 : 2; }
     cout.n = xa.nout;
     for (int o = 0; o < xa.nout; ++o) { cout.comp[o] = o; cout.axis[o] = o % 3; cout.min_[o] = 0; cout.mout[o] = o < 3 ? 1 : 2; }
   } else {
     xa.nin = 6;
-    for (int c = 0; c < 6; ++c) { xa.in_comp[c] = c; xa.in_axis[c] = c % 3; xa.in_mask[c] = c < 3 ? 1 : 2; }
     xa.nout = 3;
-    for (int o = 0; o < 3; ++o) { xa.out_comp[o] = o; xa.out_axis[o] = o; xa.out_mask[o] = 3; }
     cout.n = 3;
     for (int o = 0; o < 3; ++o) { cout.comp[o] = o; cout.axis[o] = o; cout.min_[o] = 0; cout.mout[o] = 3; }
   }
-  if (!pick_tile(Mx, eb, kEmaxSand, H, &ncol, &nthr, budget)) return VC_ERR_ARG;
+  {
+    // smallest workgroup (256/512/1024 threads) that still gives rows of >= 32 bytes
+    const int E = Tune<T>::emax_sand, cmin = 32 / eb;
+    ncol = 0;
+    for (int t : {256, 512, 1024}) {
+      int c = 16;
+      while (c > 1 && ((int64_t)Mx * c > (int64_t)E * t || (size_t)eb * ((size_t)Mx * (c + 2)) > budget)) c >>= 1;
+      if ((int64_t)Mx * c > (int64_t)E * t) continue;
+      ncol = c;
+      nthr = t;
+      if (c >= cmin) break;
+    }
+    if (ncol == 0) { set_error("x transform length %d too long for the sandwich kernel", Mx); return VC_ERR_ARG; }
+  }
   xa.ncol = ncol;
   VC_HIP(launch_sandwich<T>(F, O, tb.R.p, xa, tb.ax[0].plan, tb.ax[0].tw.p, tb.ax[0].ph.p, tb.ax[1].ph.p,
                             tb.ax[2].ph.p, pflag, nthr, st));
+  VC_MARK(3);
   // 4. inverse y transform of the outputs (only rows with panels that need them)
-  if (!pick_tile(My, eb, kEmax, H, &ncol, &nthr, budget)) return VC_ERR_ARG;
+  if (!pick_tile(My, eb, Tune<T>::emax, H, &ncol, &nthr, budget, (int64_t)n1x * cout.n * nrhs)) return VC_ERR_ARG;
   sa.ncol = ncol; sa.nin = My; sa.nout = n1y; sa.inverse = 1;
   VC_HIP(launch_strided<T>(O, sa, cout, n1x, tb.ax[1].plan, tb.ax[1].tw.p, lflag, pflag, nthr, st));
+  VC_MARK(4);
   // 5. inverse z transform + gather + jump term
-  if (!pick_tile(P->M[2], eb, kEmax, nitems, &ncol, &nthr, budget)) return VC_ERR_ARG;
+  if (!pick_tile(P->M[2], eb, Tune<T>::emax, nitems, &ncol, &nthr, budget, transpose ? (nrhs + 1) / 2 : nrhs)) return VC_ERR_ARG;
   VC_HIP(launch_zinv<T>(O, y, x, N, nrhs, transpose ? 1 : 0, items, nitems, lptr, pk, pkind, P->d_diag.as<double>(),
                         lflag, cs, rs, n1x, n1y, My, H, tb.ax[2].plan, tb.ax[2].tw.p, ncol, nthr, st));
+  VC_MARK(5);
+#undef VC_MARK
+  if (P->prof) P->ev_pending.push_back(std::vector<hipEvent_t>(ev, ev + 6));
   P->mvp_count++;
   return VC_OK;
 }

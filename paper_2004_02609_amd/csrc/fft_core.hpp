@@ -125,23 +125,28 @@ template <typename T> struct Dft<T, 7> {
   }
 };
 
-// One Stockham stage of radix R over ncol lines.  EMAX bounds the elements a thread
-// stages per stage: the launch guarantees L*ncol <= EMAX*nthr.
+// Exact t / d for 0 <= t < 2^22 and d >= 1 given inv = 1.0f / d: (t + 1/2) / d is at
+// least 1/(2d) away from an integer, and the float product errs by < t * 2^-23 / d.
+__device__ __forceinline__ int fdiv(int t, float inv) { return (int)(((float)t + 0.5f) * inv); }
+
+// One Stockham stage of radix R over ncol = 2^lgc lines.  EMAX bounds the elements a
+// thread stages per stage: the launch guarantees L*ncol <= EMAX*nthr.
 template <typename T, int R, int EMAX>
 __device__ __forceinline__ void fft_stage(C2<T>* __restrict__ buf, const C2<T>* __restrict__ tw, int L,
-                                          int ncol, int ncolp, int p, T sg) {
+                                          int lgc, int ncolp, int p, float invp, T sg) {
   constexpr int MAXB = EMAX / R + 1;
   const int nthr = blockDim.x;
   const int tid = threadIdx.x;
   const int LR = L / R;
-  const int nb = LR * ncol;
+  const int nb = LR << lgc;
+  const int cmask = (1 << lgc) - 1;
   const int tstep_base = L / (p * R);
   C2<T> v[MAXB][R];
 #pragma unroll
   for (int c = 0; c < MAXB; ++c) {
-    int b = tid + c * nthr;
+    const int b = tid + c * nthr;
     if (b < nb) {
-      int col = b % ncol, i = b / ncol;
+      const int col = b & cmask, i = b >> lgc;
 #pragma unroll
       for (int q = 0; q < R; ++q) v[c][q] = buf[(i + q * LR) * ncolp + col];
     }
@@ -149,12 +154,13 @@ __device__ __forceinline__ void fft_stage(C2<T>* __restrict__ buf, const C2<T>* 
   __syncthreads();
 #pragma unroll
   for (int c = 0; c < MAXB; ++c) {
-    int b = tid + c * nthr;
+    const int b = tid + c * nthr;
     if (b < nb) {
-      int col = b % ncol, i = b / ncol;
-      int k = i % p;
+      const int col = b & cmask, i = b >> lgc;
+      const int ip = fdiv(i, invp);
+      const int k = i - ip * p;
       if (p > 1) {
-        int ts = k * tstep_base;
+        const int ts = k * tstep_base;
 #pragma unroll
         for (int q = 1; q < R; ++q) {
           C2<T> w = tw[q * ts];
@@ -163,7 +169,7 @@ __device__ __forceinline__ void fft_stage(C2<T>* __restrict__ buf, const C2<T>* 
         }
       }
       Dft<T, R>::run(v[c], sg);
-      int j = (i - k) * R + k;
+      const int j = ip * p * R + k;
 #pragma unroll
       for (int q = 0; q < R; ++q) buf[(j + q * p) * ncolp + col] = v[c][q];
     }
@@ -171,20 +177,21 @@ __device__ __forceinline__ void fft_stage(C2<T>* __restrict__ buf, const C2<T>* 
   __syncthreads();
 }
 
-// Full transform of ncol lines (caller synchronizes before: data must be in LDS).
+// Full transform of 2^lgc lines (caller synchronizes before: data must be in LDS).
 template <typename T, int EMAX>
-__device__ void lds_fft(C2<T>* __restrict__ buf, const C2<T>* __restrict__ tw, const AxisPlan& pl, int ncol,
+__device__ void lds_fft(C2<T>* __restrict__ buf, const C2<T>* __restrict__ tw, const AxisPlan& pl, int lgc,
                         int ncolp, bool inverse) {
   const T sg = inverse ? T(1) : T(-1);
   int p = 1;
   for (int s = 0; s < pl.nst; ++s) {
     const int R = pl.rad[s];
+    const float invp = 1.0f / (float)p;
     switch (R) {
-      case 2: fft_stage<T, 2, EMAX>(buf, tw, pl.L, ncol, ncolp, p, sg); break;
-      case 3: fft_stage<T, 3, EMAX>(buf, tw, pl.L, ncol, ncolp, p, sg); break;
-      case 4: fft_stage<T, 4, EMAX>(buf, tw, pl.L, ncol, ncolp, p, sg); break;
-      case 5: fft_stage<T, 5, EMAX>(buf, tw, pl.L, ncol, ncolp, p, sg); break;
-      case 7: fft_stage<T, 7, EMAX>(buf, tw, pl.L, ncol, ncolp, p, sg); break;
+      case 2: fft_stage<T, 2, EMAX>(buf, tw, pl.L, lgc, ncolp, p, invp, sg); break;
+      case 3: fft_stage<T, 3, EMAX>(buf, tw, pl.L, lgc, ncolp, p, invp, sg); break;
+      case 4: fft_stage<T, 4, EMAX>(buf, tw, pl.L, lgc, ncolp, p, invp, sg); break;
+      case 5: fft_stage<T, 5, EMAX>(buf, tw, pl.L, lgc, ncolp, p, invp, sg); break;
+      case 7: fft_stage<T, 7, EMAX>(buf, tw, pl.L, lgc, ncolp, p, invp, sg); break;
       default: break;
     }
     p *= R;

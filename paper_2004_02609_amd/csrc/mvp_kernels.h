@@ -7,9 +7,14 @@
 
 namespace vc {
 
-// Elements a thread stages per FFT stage (launches keep L*ncol <= kEmax*threads).
-constexpr int kEmax = 16;
-constexpr int kEmaxSand = 8;
+// Elements a thread stages per FFT stage (launches keep L*ncol <= emax*threads), chosen
+// so no kernel needs scratch memory under a 1024-thread launch bound (128 VGPRs):
+// the x sandwich also keeps its transformed inputs in registers, 4 elements each.
+template <typename T> struct Tune {
+  static constexpr int emax = sizeof(T) == 4 ? 16 : 8;
+  // x sandwich: elements per thread (its transformed inputs stay in registers)
+  static constexpr int emax_sand = 4;
+};
 // Dynamic LDS per workgroup kept within the default 64 KiB launch limit.
 constexpr size_t kLdsBudget = 64 * 1024;
 
@@ -30,17 +35,17 @@ struct StridedArgs {
   int nrhs;
   int inverse;
   int n1x, n1y;   // flag array extents (planes x rows)
+  int lgc;        // log2(ncol), set by the launcher
 };
 
 struct SandArgs {
   int64_t comp_stride, rhs_stride, pair_stride;
   int nrhs, n1x, Mx, My, H, Hx, Hy;
-  int ncol;
+  int ncol, lgc;  // lgc = log2(ncol), set by the launcher
   int adjoint;
   int nin, nout;
-  int in_comp[6], in_axis[6], in_mask[6];
-  int out_comp[6], out_axis[6], out_mask[6];
-  int odd[15];    // bit a set: stored spectrum of pair q is odd under k_a -> M_a - k_a
+  // bits 3q..3q+2: stored spectrum of pair q is odd under k_a -> M_a - k_a (bit a)
+  uint64_t oddmask;
 };
 
 template <typename T>

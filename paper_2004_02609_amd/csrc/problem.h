@@ -106,6 +106,16 @@ struct vc_problem {
   vc::DevMem s_V, s_w, s_z, s_r, s_b, s_x, s_h, s_partial, s_norm, s_active, s_tmp, s_y2;
   int s_restart = 0, s_nrhs = 0;
   int mvp_count = 0;
+  // per-pass timing (measurement)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<std::vector<hipEvent_t>> ev_pending;
+  double pass_bytes[5] = {0, 0, 0, 0, 0};
+  ~vc_problem() {
+    for (auto& v : ev_pending)
+      for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
+  }
 };
 
 namespace vc {
@@ -118,6 +128,8 @@ vc_status apply_op(vc_problem* p, int transpose, vc_precision prec, const double
                    hipStream_t st);
 vc_status apply_precond(vc_problem* p, int transpose, const double* x, double* y, int nrhs, hipStream_t st);
 AxisPlan make_plan(int L);
+bool pick_tile(int L, int elem_bytes, int emax, int ncols_total, int* ncol, int* nthr, size_t budget,
+               int64_t other_blocks, int max_thr = 1024);
 bool smooth7(int n);
 }  // namespace vc
 

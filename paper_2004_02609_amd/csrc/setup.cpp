@@ -110,12 +110,23 @@ static hipError_t upload_axis(AxisTables& t, int L) {
 
 // Largest tile (columns per workgroup) whose LDS use fits `budget` bytes and whose
 // element count L*ncol stays within emax per thread for at most 1024 threads.
-bool pick_tile(int L, int elem_bytes, int emax, int ncols_total, int* ncol, int* nthr, size_t budget) {
+// Among feasible tiles, prefer little padding waste (tiles past the last column) and
+// enough workgroups (other_blocks = product of the other grid dimensions) to fill the
+// chip several times over; then the widest tile.
+bool pick_tile(int L, int elem_bytes, int emax, int ncols_total, int* ncol, int* nthr, size_t budget,
+               int64_t other_blocks, int max_thr) {
   int best = 0;
+  double best_score = -1e30;
   for (int c : {32, 16, 8, 4, 2, 1}) {
     const size_t lds = (size_t)elem_bytes * ((size_t)L + (size_t)L * (c + 1));
     const int64_t thr = ((int64_t)L * c + emax - 1) / emax;
-    if (lds <= budget && thr <= 1024 && (c == 1 || c <= 2 * ncols_total)) { best = c; break; }
+    if (lds > budget || thr > max_thr) continue;
+    const int64_t tiles = (ncols_total + c - 1) / c;
+    const double waste = (double)(tiles * c - ncols_total) / (double)(tiles * c);
+    const double wgs = (double)tiles * (double)(other_blocks > 0 ? other_blocks : 1);
+    double score = std::log2((double)c) - 8.0 * waste;
+    if (wgs < 1024.0) score -= 2.0 * std::log2(1024.0 / wgs);
+    if (score > best_score) { best_score = score; best = c; }
   }
   if (best == 0) { set_error("no FFT tile fits length %d", L); return false; }
   int64_t thr = ((int64_t)L * best + emax - 1) / emax;
@@ -123,7 +134,7 @@ bool pick_tile(int L, int elem_bytes, int emax, int ncols_total, int* ncol, int*
   if (thr < 64) thr = 64;
   *ncol = best;
   *nthr = (int)thr;
-  return (int64_t)L * best <= (int64_t)emax * thr && thr <= 1024;
+  return (int64_t)L * best <= (int64_t)emax * thr && thr <= max_thr;
 }
 
 template <typename T>
@@ -183,7 +194,7 @@ vc_status build_spectra(vc_problem* P, int want64, int want32, hipStream_t st) {
     fa.scale = scale;
     VC_HIP(launch_fill_circulant(circ.as<double>(), fa, P->d_gl.as<double>(), st));
     int ncol, nthr;
-    if (!pick_tile(Mz, 16, kEmax, Mx * My, &ncol, &nthr, kLdsBudget)) return VC_ERR_ARG;
+    if (!pick_tile(Mz, 16, Tune<double>::emax, (Mx * My + 1) / 2, &ncol, &nthr, kLdsBudget, 1)) return VC_ERR_ARG;
     VC_HIP(launch_zr2c_dense(circ.as<double>(), spec.p, Mx * My, H, P->t64.ax[2].plan, P->t64.ax[2].tw.p, ncol, nthr, st));
     CompSet cs{};
     cs.n = 1;
@@ -191,11 +202,11 @@ vc_status build_spectra(vc_problem* P, int want64, int want32, hipStream_t st) {
     sa.comp_stride = 0; sa.rhs_stride = 0;
     sa.ncols = H; sa.nrhs = 1; sa.inverse = 0; sa.n1x = 0; sa.n1y = 0;
     // y pass over all Mx planes
-    if (!pick_tile(My, 16, kEmax, H, &ncol, &nthr, kLdsBudget)) return VC_ERR_ARG;
+    if (!pick_tile(My, 16, Tune<double>::emax, H, &ncol, &nthr, kLdsBudget, Mx)) return VC_ERR_ARG;
     sa.plane_stride = (int64_t)My * H; sa.row_stride = H; sa.ncol = ncol; sa.nin = My; sa.nout = My;
     VC_HIP(launch_strided<double>(spec.p, sa, cs, Mx, P->t64.ax[1].plan, P->t64.ax[1].tw.p, nullptr, nullptr, nthr, st));
     // x pass over all My planes
-    if (!pick_tile(Mx, 16, kEmax, H, &ncol, &nthr, kLdsBudget)) return VC_ERR_ARG;
+    if (!pick_tile(Mx, 16, Tune<double>::emax, H, &ncol, &nthr, kLdsBudget, My)) return VC_ERR_ARG;
     sa.plane_stride = H; sa.row_stride = (int64_t)My * H; sa.ncol = ncol; sa.nin = Mx; sa.nout = Mx;
     VC_HIP(launch_strided<double>(spec.p, sa, cs, My, P->t64.ax[0].plan, P->t64.ax[0].tw.p, nullptr, nullptr, nthr, st));
     ExtractArgs ea{};

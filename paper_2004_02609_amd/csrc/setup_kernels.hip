@@ -193,6 +193,8 @@ k_zr2c_dense(const double* __restrict__ in, C2<double>* __restrict__ out, int nl
              const C2<double>* __restrict__ twg, int ncol) {
   extern __shared__ char smem_raw[];
   const int L = pl.L, ncolp = ncol + 1;
+  int lgc = 0;
+  while ((1 << (lgc + 1)) <= ncol) ++lgc;
   C2<double>* tw = reinterpret_cast<C2<double>*>(smem_raw);
   C2<double>* buf = tw + L;
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -207,7 +209,7 @@ k_zr2c_dense(const double* __restrict__ in, C2<double>* __restrict__ out, int nl
     buf[z * ncolp + c] = v;
   }
   __syncthreads();
-  lds_fft<double, kEmax>(buf, tw, pl, ncol, ncolp, false);
+  lds_fft<double, Tune<double>::emax>(buf, tw, pl, lgc, ncolp, false);
   for (int e = tid; e < H * ncol; e += nthr) {
     const int c = e / H, k = e - c * H;
     const int la = 2 * (pair0 + c), lb = la + 1;

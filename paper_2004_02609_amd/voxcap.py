@@ -76,6 +76,8 @@ _sig = {
                                  C.POINTER(vc_stats)]),
     "vc_capacitance_grad_eps": (C.c_int, [_P, C.POINTER(vc_solve_opts), C.POINTER(C.c_int32), C.c_int32,
                                           C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(vc_stats)]),
+    "vc_profile_enable": (C.c_int, [_P, C.c_int]),
+    "vc_pass_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "vc_status_string": (C.c_char_p, [C.c_int]),
     "vc_last_error": (C.c_char_p, []),
 }
@@ -169,6 +171,21 @@ def vc_apply_precond(h, x, y, nrhs, transpose=False, stream=None):
            "vc_apply_precond")
 
 
+def vc_profile_enable(h, enable=True):
+    _check(_lib.vc_profile_enable(h, int(bool(enable))), "vc_profile_enable")
+
+
+PASS_NAMES = ("zfwd_scatter", "y_forward", "x_sandwich_multiply", "y_inverse", "zinv_gather")
+
+
+def vc_pass_times(h):
+    ms = (C.c_double * 5)()
+    n = (C.c_int32 * 5)()
+    b = (C.c_double * 5)()
+    _check(_lib.vc_pass_times(h, ms, n, b), "vc_pass_times")
+    return list(ms), list(n), list(b)
+
+
 def _solve_opts(prec="fp64", rtol=0.0, restart=0, max_iter=0, inner_rtol=0.0, ir_max=0, use_precond=1):
     o = vc_solve_opts()
     o.prec = _PREC[prec]
@@ -255,6 +272,13 @@ class Problem:
             y = torch.empty_like(x)
         vc_apply_precond(self._h, x, y, x.shape[0], transpose, stream)
         return y
+
+    def profile(self, enable=True):
+        vc_profile_enable(self._h, enable)
+
+    def pass_times(self):
+        """(ms summed, launches, algorithmic bytes of one launch) per pass of the product."""
+        return vc_pass_times(self._h)
 
     def capacitance(self, rho=None, **solve):
         Cm, st, _ = vc_capacitance(self._h, self.m, rho=rho, **solve)
