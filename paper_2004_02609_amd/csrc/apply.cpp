@@ -145,7 +145,7 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
     ncol = 0;
     for (int t : {256, 512, 1024}) {
       int c = 16;
-      while (c > 1 && ((int64_t)Mx * c > (int64_t)E * t || (size_t)eb * ((size_t)Mx * (c + 2)) > budget)) c >>= 1;
+      while (c > 1 && ((int64_t)Mx * c > (int64_t)E * t || (size_t)eb * ((size_t)Mx * (2 * c + 3)) > budget)) c >>= 1;
       if ((int64_t)Mx * c > (int64_t)E * t) continue;
       ncol = c;
       nthr = t;

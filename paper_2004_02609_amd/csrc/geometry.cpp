@@ -20,14 +20,41 @@ bool smooth7(int n) {
   return n == 1;
 }
 
-AxisPlan make_plan(int L) {
+// Radix schedule of one FFT length: the fewest stages from the radices the engine
+// implements (composite ones run as Cooley-Tukey in registers), ties broken towards
+// balanced radices; max_radix bounds per-thread registers.
+static void plan_search(int n, int max_radix, int depth, int* cur, int* best, int* best_n, double* best_score) {
+  static const int kRad[] = {27, 25, 21, 20, 18, 16, 15, 14, 12, 10, 9, 8, 7, 6, 5, 4, 3, 2};
+  if (n == 1) {
+    double score = 0.0;   // prefer fewer stages, then a larger smallest radix
+    int mn = 1 << 30;
+    for (int i = 0; i < depth; ++i) mn = cur[i] < mn ? cur[i] : mn;
+    score = -1000.0 * depth + mn;
+    if (score > *best_score) {
+      *best_score = score;
+      *best_n = depth;
+      for (int i = 0; i < depth; ++i) best[i] = cur[i];
+    }
+    return;
+  }
+  if (depth >= kMaxStages || depth >= 6) return;
+  for (int r : kRad) {
+    if (r > max_radix || n % r) continue;
+    if (depth > 0 && r > cur[depth - 1]) continue;   // non-increasing order: one visit per multiset
+    cur[depth] = r;
+    plan_search(n / r, max_radix, depth + 1, cur, best, best_n, best_score);
+  }
+}
+
+AxisPlan make_plan(int L, int max_radix) {
   AxisPlan pl{};
   pl.L = L;
-  int n = L, s = 0;
-  while (n % 4 == 0 && s < kMaxStages) { pl.rad[s++] = 4; n /= 4; }
-  for (int f : {2, 3, 5, 7})
-    while (n % f == 0 && s < kMaxStages) { pl.rad[s++] = f; n /= f; }
-  pl.nst = (n == 1) ? s : -1;
+  int cur[kMaxStages], best[kMaxStages];
+  int nbest = -1;
+  double score = -1e30;
+  plan_search(L, max_radix, 0, cur, best, &nbest, &score);
+  pl.nst = nbest;
+  for (int i = 0; i < nbest; ++i) pl.rad[i] = best[i];
   return pl;
 }
 

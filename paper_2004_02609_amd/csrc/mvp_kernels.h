@@ -14,6 +14,9 @@ template <typename T> struct Tune {
   static constexpr int emax = sizeof(T) == 4 ? 16 : 8;
   // x sandwich: elements per thread (its transformed inputs stay in registers)
   static constexpr int emax_sand = 4;
+  // largest FFT radix compiled into each kind of kernel (register budget)
+  static constexpr int maxr = sizeof(T) == 4 ? 21 : 12;
+  static constexpr int maxr_sand = sizeof(T) == 4 ? 16 : 8;
 };
 // Dynamic LDS per workgroup kept within the default 64 KiB launch limit.
 constexpr size_t kLdsBudget = 64 * 1024;

@@ -34,6 +34,7 @@ k_zfwd(const double* __restrict__ x, int64_t N, int nrhs, int mode, const int32_
   const int ncol = 1 << lgc, ncolp = ncol + 1;
   C2<T>* tw = reinterpret_cast<C2<T>*>(smem_raw);
   C2<T>* buf = tw + L;
+  C2<T>* buf2 = buf + L * ncolp;
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int t = tid; t < L; t += nthr) tw[t] = twg[t];
   for (int e = tid; e < L * ncolp; e += nthr) buf[e] = C2<T>{T(0), T(0)};
@@ -61,7 +62,7 @@ k_zfwd(const double* __restrict__ x, int64_t N, int nrhs, int mode, const int32_
     }
   }
   __syncthreads();
-  lds_fft<T, EMAX>(buf, tw, pl, lgc, ncolp, false);
+  const C2<T>* res = lds_fft<T, Tune<T>::maxr>(buf, buf2, tw, pl, lgc, ncolp, false);
   const int plane = n1x * n1y;
   const float invH = 1.0f / (float)H, invPl = 1.0f / (float)plane, invN1y = 1.0f / (float)n1y;
   for (int e = tid; e < H * ncol; e += nthr) {
@@ -72,8 +73,8 @@ k_zfwd(const double* __restrict__ x, int64_t N, int nrhs, int mode, const int32_
     const int axis = fdiv(line, invPl);
     const int rem = line - axis * plane;
     const int xi = fdiv(rem, invN1y), yi = rem - xi * n1y;
-    const C2<T> Z = buf[k * ncolp + c];
-    const C2<T> Zc = cconj(buf[(k == 0 ? 0 : L - k) * ncolp + c]);
+    const C2<T> Z = res[k * ncolp + c];
+    const C2<T> Zc = cconj(res[(k == 0 ? 0 : L - k) * ncolp + c]);
     const C2<T> A = {T(0.5) * (Z.x + Zc.x), T(0.5) * (Z.y + Zc.y)};
     const C2<T> B = {T(0.5) * (Z.y - Zc.y), T(-0.5) * (Z.x - Zc.x)};
     const int64_t off = ((int64_t)xi * My + yi) * H + k;
@@ -97,6 +98,7 @@ k_strided(C2<T>* __restrict__ data, StridedArgs a, CompSet cs, AxisPlan pl, cons
   const int lgc = a.lgc, ncol = 1 << lgc, ncolp = ncol + 1, cmask = ncol - 1;
   C2<T>* tw = reinterpret_cast<C2<T>*>(smem_raw);
   C2<T>* buf = tw + L;
+  C2<T>* buf2 = buf + L * ncolp;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int plane = blockIdx.y;
   const int cz = blockIdx.z / a.nrhs, rhs = blockIdx.z - cz * a.nrhs;
@@ -120,13 +122,13 @@ k_strided(C2<T>* __restrict__ data, StridedArgs a, CompSet cs, AxisPlan pl, cons
     buf[r * ncolp + c] = v;
   }
   __syncthreads();
-  lds_fft<T, EMAX>(buf, tw, pl, lgc, ncolp, a.inverse != 0);
+  const C2<T>* res = lds_fft<T, Tune<T>::maxr>(buf, buf2, tw, pl, lgc, ncolp, a.inverse != 0);
   for (int e = tid; e < (a.nout << lgc); e += nthr) {
     const int r = e >> lgc, c = e & cmask;
     const int col = col0 + c;
     if (col >= a.ncols) continue;
     if (lf && mout && !(lf[r] & mout)) continue;
-    base[(int64_t)r * a.row_stride + col] = buf[r * ncolp + c];
+    base[(int64_t)r * a.row_stride + col] = res[r * ncolp + c];
   }
 }
 
@@ -164,7 +166,7 @@ __device__ __forceinline__ int xcd_remap(int lin, int n) {
 // they are in flight while it runs; transformed inputs stay in registers (rows-fastest
 // mapping: thread element j is kx = er[j] of column ec[j]).
 template <typename T, int EMAX, int NIN, int NOUT, int NTHR>
-__global__ void __launch_bounds__(NTHR, 4)
+__global__ void __launch_bounds__(NTHR, (sizeof(T) == 8 || NIN == 6) ? 2 : 4)
 k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __restrict__ R, SandArgs a,
             AxisPlan pl, const C2<T>* __restrict__ twg, const C2<T>* __restrict__ phx, const C2<T>* __restrict__ phy,
             const C2<T>* __restrict__ phz, const uint8_t* __restrict__ pflag) {
@@ -173,6 +175,7 @@ k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __
   const int lgc = a.lgc, ncol = 1 << lgc, ncolp = ncol + 1, cmask = ncol - 1;
   C2<T>* tw = reinterpret_cast<C2<T>*>(smem_raw);
   C2<T>* buf = tw + L;
+  C2<T>* buf2 = buf + L * ncolp;
   const int tid = threadIdx.x;
   const int ntiles = gridDim.x;
   const int work = xcd_remap(blockIdx.y * ntiles + blockIdx.x, ntiles * gridDim.y);
@@ -211,7 +214,7 @@ k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __
     }
     __syncthreads();
     if (b + 1 < NIN) VC_FETCH(b + 1)
-    lds_fft<T, EMAX>(buf, tw, pl, lgc, ncolp, false);
+    const C2<T>* res = lds_fft<T, Tune<T>::maxr_sand>(buf, buf2, tw, pl, lgc, ncolp, false);
 #pragma unroll
     for (int j = 0; j < EMAX; ++j) {            // rows fastest: contiguous spectra reads
       const int e = tid + j * NTHR;
@@ -221,7 +224,7 @@ k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __
         const int ky = fdiv(col, invH), kz = col - ky * a.H;
         // half-voxel phase of the input component (shift to the common lattice)
         const C2<T> ph = axis == 0 ? phx[r] : (axis == 1 ? phy[ky] : phz[kz]);
-        q[b][j] = cmul(buf[r * ncolp + c], ph);
+        q[b][j] = cmul(res[r * ncolp + c], ph);
       } else {
         q[b][j] = C2<T>{T(0), T(0)};
       }
@@ -277,7 +280,7 @@ k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __
       }
     }
     __syncthreads();
-    lds_fft<T, EMAX>(buf, tw, pl, lgc, ncolp, true);
+    const C2<T>* res = lds_fft<T, Tune<T>::maxr_sand>(buf, buf2, tw, pl, lgc, ncolp, true);
     const int axis = o % 3, msk = NIN == 3 ? (o < 3 ? 1 : 2) : 3;
     C2<T>* dst = Fout + o * a.comp_stride + rhs * a.rhs_stride;
     for (int e = tid; e < (a.n1x << lgc); e += NTHR) {
@@ -285,7 +288,7 @@ k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __
       const int col = col0 + c;
       if (col >= ncols) continue;
       if (!(pflag[axis * a.n1x + r] & msk)) continue;
-      dst[r * rowst + col] = buf[r * ncolp + c];
+      dst[r * rowst + col] = res[r * ncolp + c];
     }
   }
 }
@@ -303,6 +306,7 @@ k_zinv(const C2<T>* __restrict__ O, double* __restrict__ y, const double* __rest
   const int ncol = 1 << lgc, ncolp = ncol + 1;
   C2<T>* tw = reinterpret_cast<C2<T>*>(smem_raw);
   C2<T>* buf = tw + L;
+  C2<T>* buf2 = buf + L * ncolp;
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int t = tid; t < L; t += nthr) tw[t] = twg[t];
   const int ra = (mode == 0) ? blockIdx.y : 2 * blockIdx.y;
@@ -334,14 +338,14 @@ k_zinv(const C2<T>* __restrict__ O, double* __restrict__ y, const double* __rest
     if (k > 0 && k < L - k) buf[(L - k) * ncolp + c] = C2<T>{Cv.x + Dv.y, Dv.x - Cv.y};
   }
   __syncthreads();
-  lds_fft<T, EMAX>(buf, tw, pl, lgc, ncolp, true);
+  const C2<T>* res = lds_fft<T, Tune<T>::maxr>(buf, buf2, tw, pl, lgc, ncolp, true);
   for (int c = 0; c < ncol; ++c) {
     const int it = item0 + c;
     if (it >= nitems) break;
     const int line = items[it];
     const int p0 = line_ptr[line], p1 = line_ptr[line + 1];
     for (int p = p0 + tid; p < p1; p += nthr) {
-      const C2<T> Z = buf[pk[p] * ncolp + c];
+      const C2<T> Z = res[pk[p] * ncolp + c];
       const double dg = diag[p];
       if (mode == 0) {
         const int64_t o = (int64_t)ra * N + p;
@@ -367,7 +371,7 @@ static inline int ilog2(int n) {
 // ------------------------------------------------------------------------------ host launchers
 template <typename T>
 static size_t lds_bytes(int L, int ncol) {
-  return sizeof(C2<T>) * ((size_t)L + (size_t)L * (ncol + 1));
+  return sizeof(C2<T>) * ((size_t)L + 2 * (size_t)L * (ncol + 1));   // twiddles + ping-pong tiles
 }
 
 template <typename T>

@@ -127,7 +127,7 @@ vc_status build_precond(vc_problem* p, hipStream_t st);
 vc_status apply_op(vc_problem* p, int transpose, vc_precision prec, const double* x, double* y, int nrhs,
                    hipStream_t st);
 vc_status apply_precond(vc_problem* p, int transpose, const double* x, double* y, int nrhs, hipStream_t st);
-AxisPlan make_plan(int L);
+AxisPlan make_plan(int L, int max_radix);
 bool pick_tile(int L, int elem_bytes, int emax, int ncols_total, int* ncol, int* nthr, size_t budget,
                int64_t other_blocks, int max_thr = 1024);
 bool smooth7(int n);

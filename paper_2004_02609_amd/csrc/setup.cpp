@@ -88,8 +88,9 @@ static void gauss_legendre_table(std::vector<double>& gl) {
 }
 
 template <typename T>
-static hipError_t upload_axis(AxisTables& t, int L) {
-  t.plan = make_plan(L);
+static hipError_t upload_axis(AxisTables& t, int L, int axis) {
+  // the x axis is transformed by the sandwich kernel, which compiles fewer radices
+  t.plan = make_plan(L, axis == 0 ? Tune<T>::maxr_sand : Tune<T>::maxr);
   std::vector<T> tw(2 * L), ph(2 * L);
   for (int k = 0; k < L; ++k) {
     const long double a = 2.0L * (long double)M_PI * k / L;
@@ -118,7 +119,7 @@ bool pick_tile(int L, int elem_bytes, int emax, int ncols_total, int* ncol, int*
   int best = 0;
   double best_score = -1e30;
   for (int c : {32, 16, 8, 4, 2, 1}) {
-    const size_t lds = (size_t)elem_bytes * ((size_t)L + (size_t)L * (c + 1));
+    const size_t lds = (size_t)elem_bytes * ((size_t)L + 2 * (size_t)L * (c + 1));
     const int64_t thr = ((int64_t)L * c + emax - 1) / emax;
     if (lds > budget || thr > max_thr) continue;
     const int64_t tiles = (ncols_total + c - 1) / c;
@@ -163,8 +164,8 @@ vc_status build_spectra(vc_problem* P, int want64, int want32, hipStream_t st) {
   gauss_legendre_table(gl);
   if ((s = upload(P->d_gl, gl)) != VC_OK) return s;
   for (int a = 0; a < 3; ++a) {
-    VC_HIP(upload_axis<double>(P->t64.ax[a], P->M[a]));
-    VC_HIP(upload_axis<float>(P->t32.ax[a], P->M[a]));
+    VC_HIP(upload_axis<double>(P->t64.ax[a], P->M[a], a));
+    VC_HIP(upload_axis<float>(P->t32.ax[a], P->M[a], a));
     if (P->t64.ax[a].plan.nst < 0) { set_error("FFT size %d not 7-smooth", P->M[a]); return VC_ERR_ARG; }
   }
   const int npairs = P->n_diel > 0 ? 15 : 6;

@@ -197,6 +197,7 @@ k_zr2c_dense(const double* __restrict__ in, C2<double>* __restrict__ out, int nl
   while ((1 << (lgc + 1)) <= ncol) ++lgc;
   C2<double>* tw = reinterpret_cast<C2<double>*>(smem_raw);
   C2<double>* buf = tw + L;
+  C2<double>* buf2 = buf + L * ncolp;
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int t = tid; t < L; t += nthr) tw[t] = twg[t];
   const int pair0 = blockIdx.x * ncol;
@@ -209,12 +210,12 @@ k_zr2c_dense(const double* __restrict__ in, C2<double>* __restrict__ out, int nl
     buf[z * ncolp + c] = v;
   }
   __syncthreads();
-  lds_fft<double, Tune<double>::emax>(buf, tw, pl, lgc, ncolp, false);
+  const C2<double>* res = lds_fft<double, Tune<double>::maxr>(buf, buf2, tw, pl, lgc, ncolp, false);
   for (int e = tid; e < H * ncol; e += nthr) {
     const int c = e / H, k = e - c * H;
     const int la = 2 * (pair0 + c), lb = la + 1;
-    const C2<double> Z = buf[k * ncolp + c];
-    const C2<double> Zc = cconj(buf[((L - k) % L) * ncolp + c]);
+    const C2<double> Z = res[k * ncolp + c];
+    const C2<double> Zc = cconj(res[((L - k) % L) * ncolp + c]);
     if (la < nlines) out[(int64_t)la * H + k] = C2<double>{0.5 * (Z.x + Zc.x), 0.5 * (Z.y + Zc.y)};
     if (lb < nlines) out[(int64_t)lb * H + k] = C2<double>{0.5 * (Z.y - Zc.y), -0.5 * (Z.x - Zc.x)};
   }
@@ -223,7 +224,7 @@ k_zr2c_dense(const double* __restrict__ in, C2<double>* __restrict__ out, int nl
 hipError_t launch_zr2c_dense(const double* in, void* out, int nlines, int H, const AxisPlan& pl, const void* tw,
                              int ncol, int nthr, hipStream_t st) {
   const int npairs = (nlines + 1) / 2;
-  const size_t lds = sizeof(C2<double>) * ((size_t)pl.L + (size_t)pl.L * (ncol + 1));
+  const size_t lds = sizeof(C2<double>) * ((size_t)pl.L + 2 * (size_t)pl.L * (ncol + 1));
   hipLaunchKernelGGL(k_zr2c_dense, dim3((npairs + ncol - 1) / ncol), dim3(nthr), lds, st, in, (C2<double>*)out,
                      nlines, H, pl, (const C2<double>*)tw, ncol);
   return hipGetLastError();
