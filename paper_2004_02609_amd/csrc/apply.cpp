@@ -68,6 +68,48 @@ static void pass_byte_model(vc_problem* P, int transpose, int elem, int nrhs, do
   }
 }
 
+// Sandwich launch configurations for one x length: for every register radix RS the
+// plan with the fewest stages, and every power-of-two column tile that fits 512 threads
+// and the LDS budget.
+std::vector<SandCfg> sandwich_candidates(int L, int elem, int nin, int n1x, size_t budget) {
+  std::vector<SandCfg> out;
+  for (int rs = sandwich_rs_max(elem, nin); rs >= 2; --rs) {
+    const AxisPlan sp = make_sandwich_plan(L, sandwich_rmax(elem), sandwich_rmid(elem), rs, 512);
+    if (sp.nst < 1 || sp.rad[sp.nst - 1] != rs) continue;
+    for (int lgc = 0; lgc <= 5; ++lgc) {
+      const int c = 1 << lgc;
+      const int tl = L / rs;
+      if ((int64_t)c * tl > 512 || sandwich_lds_bytes(L, c, elem, n1x) > budget) break;
+      SandCfg g{};
+      g.nst = sp.nst;
+      for (int s2 = 0; s2 < sp.nst; ++s2) g.radpack |= (uint32_t)sp.rad[s2] << (5 * s2);
+      g.tl = tl;
+      g.lgc = lgc;
+      g.nthr = (c * tl + 63) / 64 * 64;
+      out.push_back(g);
+    }
+  }
+  return out;
+}
+
+// Default without timing: fewest stages, then the largest register radix, then the
+// widest tile of at most 256 threads (several workgroups per CU), else the narrowest.
+bool sandwich_default(int L, int elem, int nin, int n1x, size_t budget, SandCfg* cfg) {
+  const std::vector<SandCfg> cand = sandwich_candidates(L, elem, nin, n1x, budget);
+  if (cand.empty()) return false;
+  int best = -1;
+  double bscore = -1e30;
+  for (size_t k = 0; k < cand.size(); ++k) {
+    const SandCfg& g = cand[k];
+    const int rs = (int)((g.radpack >> (5 * (g.nst - 1))) & 31u);
+    const double fit = g.nthr <= 256 ? 10.0 * g.lgc : -10.0 * g.lgc;
+    const double score = -1e6 * g.nst + 1e3 * rs + fit;
+    if (score > bscore) { bscore = score; best = (int)k; }
+  }
+  *cfg = cand[best];
+  return true;
+}
+
 template <typename T>
 static vc_status run_apply(vc_problem* P, int transpose, const double* x, double* y, int nrhs, hipStream_t st) {
   PrecTables& tb = (sizeof(T) == 8) ? P->t64 : P->t32;
@@ -140,22 +182,16 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
     for (int o = 0; o < 3; ++o) { cout.comp[o] = o; cout.axis[o] = o; cout.min_[o] = 0; cout.mout[o] = 3; }
   }
   {
-    // smallest workgroup (256/512/1024 threads) that still gives rows of >= 32 bytes
-    const int E = Tune<T>::emax_sand, cmin = 32 / eb;
-    ncol = 0;
-    for (int t : {256, 512, 1024}) {
-      int c = 16;
-      while (c > 1 && ((int64_t)Mx * c > (int64_t)E * t || (size_t)eb * ((size_t)Mx * (2 * c + 3)) > budget)) c >>= 1;
-      if ((int64_t)Mx * c > (int64_t)E * t) continue;
-      ncol = c;
-      nthr = t;
-      if (c >= cmin) break;
+    SandCfg cfg;
+    if (!sandwich_default(Mx, (int)sizeof(T), xa.nin, n1x, budget, &cfg)) {
+      set_error("x transform length %d too long for the sandwich kernel", Mx);
+      return VC_ERR_ARG;
     }
-    if (ncol == 0) { set_error("x transform length %d too long for the sandwich kernel", Mx); return VC_ERR_ARG; }
+    xa.nst = cfg.nst; xa.radpack = cfg.radpack; xa.tl = cfg.tl; xa.lgc = cfg.lgc;
+    nthr = cfg.nthr;
   }
-  xa.ncol = ncol;
-  VC_HIP(launch_sandwich<T>(F, O, tb.R.p, xa, tb.ax[0].plan, tb.ax[0].tw.p, tb.ax[0].ph.p, tb.ax[1].ph.p,
-                            tb.ax[2].ph.p, pflag, nthr, st));
+  VC_HIP(launch_sandwich<T>(F, O, tb.R.p, xa, tb.ax[0].tw.p, tb.ax[0].ph.p, tb.ax[1].ph.p, tb.ax[2].ph.p, pflag, nthr,
+                            st));
   VC_MARK(3);
   // 4. inverse y transform of the outputs (only rows with panels that need them)
   if (!pick_tile(My, eb, Tune<T>::emax, H, &ncol, &nthr, budget, (int64_t)n1x * cout.n * nrhs)) return VC_ERR_ARG;

@@ -5,10 +5,10 @@
 // Each stage of radix R is a Stockham autosort step: butterfly i in [0, L/R) of a
 // line reads x[i + q*L/R] (q < R), multiplies by w^(q*k*L/(pR)) (k = i mod p, p the
 // product of the earlier radices, w = exp(-+2 pi i / L) from a table), does a
-// radix-R DFT and writes y[(i-k)*R + k + q*p].  All reads of a stage are staged in
-// registers before the barrier and all writes follow it, so one LDS tile suffices.
-// Consecutive threads take consecutive columns, which keeps LDS accesses on
-// distinct banks.
+// radix-R DFT and writes y[(i-k)*R + k + q*p].  Stages alternate between two LDS
+// tiles (read one, write the other), so each needs a single barrier and a thread holds
+// one butterfly in registers at a time.  Consecutive threads take consecutive columns,
+// which keeps LDS accesses on distinct banks.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

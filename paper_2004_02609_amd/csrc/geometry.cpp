@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 
+#include "mvp_kernels.h"
 #include "problem.h"
 
 namespace vc {
@@ -53,6 +54,46 @@ AxisPlan make_plan(int L, int max_radix) {
   int nbest = -1;
   double score = -1e30;
   plan_search(L, max_radix, 0, cur, best, &nbest, &score);
+  pl.nst = nbest;
+  for (int i = 0; i < nbest; ++i) pl.rad[i] = best[i];
+  return pl;
+}
+
+// Sandwich plan: radices in non-increasing order, the last one (the register stage)
+// at most rs_max and leaving at most max_tl butterflies per column; fewest stages,
+// then the largest register radix (fewest threads per column).
+static void sand_search(int n, int rmax, int rmid, int rs_max, int max_tl, int L, int depth, int* cur, int* best,
+                        int* best_n, double* best_score) {
+  static const int kRad[] = {27, 25, 21, 20, 18, 16, 15, 14, 12, 10, 9, 8, 7, 6, 5, 4, 3, 2};
+  if (n == 1) {
+    const int rs = cur[depth - 1];
+    if (rs > rs_max || L / rs > max_tl) return;
+    for (int s = 1; s + 1 < depth; ++s)
+      if (cur[s] > rmid) return;
+    const double score = -1000.0 * depth + 10.0 * rs;
+    if (score > *best_score) {
+      *best_score = score;
+      *best_n = depth;
+      for (int i = 0; i < depth; ++i) best[i] = cur[i];
+    }
+    return;
+  }
+  if (depth >= kSandMaxStages) return;
+  for (int r : kRad) {
+    if (r > rmax || n % r) continue;
+    if (depth > 0 && r > cur[depth - 1]) continue;
+    cur[depth] = r;
+    sand_search(n / r, rmax, rmid, rs_max, max_tl, L, depth + 1, cur, best, best_n, best_score);
+  }
+}
+
+AxisPlan make_sandwich_plan(int L, int rmax, int rmid, int rs_max, int max_tl) {
+  AxisPlan pl{};
+  pl.L = L;
+  int cur[kMaxStages], best[kMaxStages];
+  int nbest = -1;
+  double score = -1e30;
+  if (L >= 2) sand_search(L, rmax, rmid, rs_max, max_tl, L, 0, cur, best, &nbest, &score);
   pl.nst = nbest;
   for (int i = 0; i < nbest; ++i) pl.rad[i] = best[i];
   return pl;

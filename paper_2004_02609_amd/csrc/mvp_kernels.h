@@ -7,16 +7,13 @@
 
 namespace vc {
 
-// Elements a thread stages per FFT stage (launches keep L*ncol <= emax*threads), chosen
-// so no kernel needs scratch memory under a 1024-thread launch bound (128 VGPRs):
-// the x sandwich also keeps its transformed inputs in registers, 4 elements each.
+// Elements a thread stages per FFT stage of the z and strided kernels (launches keep
+// L*ncol <= emax*threads), chosen so no kernel needs scratch memory under a 1024-thread
+// launch bound (128 VGPRs).
 template <typename T> struct Tune {
   static constexpr int emax = sizeof(T) == 4 ? 16 : 8;
-  // x sandwich: elements per thread (its transformed inputs stay in registers)
-  static constexpr int emax_sand = 4;
-  // largest FFT radix compiled into each kind of kernel (register budget)
+  // largest FFT radix compiled into the z and strided kernels (register budget)
   static constexpr int maxr = sizeof(T) == 4 ? 21 : 12;
-  static constexpr int maxr_sand = sizeof(T) == 4 ? 16 : 8;
 };
 // Dynamic LDS per workgroup kept within the default 64 KiB launch limit.
 constexpr size_t kLdsBudget = 64 * 1024;
@@ -44,12 +41,27 @@ struct StridedArgs {
 struct SandArgs {
   int64_t comp_stride, rhs_stride, pair_stride;
   int nrhs, n1x, Mx, My, H, Hx, Hy;
-  int ncol, lgc;  // lgc = log2(ncol), set by the launcher
+  int lgc;        // log2(columns per workgroup)
   int adjoint;
   int nin, nout;
+  // x transform: radices r_0 >= ... >= r_{nst-1} (product Mx), r_s in bits 5s..5s+4
+  // of radpack (a packed word, so the kernel never indexes an argument array); the
+  // last one is the register stage, tl = Mx / r_{nst-1} threads per column
+  int nst, tl;
+  uint32_t radpack;
   // bits 3q..3q+2: stored spectrum of pair q is odd under k_a -> M_a - k_a (bit a)
   uint64_t oddmask;
 };
+// dynamic LDS of the sandwich: twiddle table + one [L][ncol+1] tile + 3 n1x plane flags
+inline size_t sandwich_lds_bytes(int L, int ncol, int elem, int n1x) {
+  return (size_t)2 * elem * ((size_t)L + (size_t)L * (ncol + 1)) + (size_t)3 * n1x;
+}
+// x-transform plan of the sandwich for one precision / variant (see sandwich_impl.hpp):
+// fewest stages with the first radix <= rmax, middle radices <= rmid and the last
+// (smallest) radix <= rs_max, at most max_tl threads per column; nst = -1 when none
+AxisPlan make_sandwich_plan(int L, int rmax, int rmid, int rs_max, int max_tl);
+constexpr int kSandMaxStages = 6;
+constexpr int sandwich_rmid(int elem) { return elem == 4 ? 16 : 10; }
 
 template <typename T>
 hipError_t launch_zfwd(const double* x, int64_t N, int nrhs, int mode, const int32_t* items, int nitems,
@@ -60,9 +72,22 @@ template <typename T>
 hipError_t launch_strided(void* data, const StridedArgs& a, const CompSet& cs, int nplanes, const AxisPlan& pl,
                           const void* tw, const uint8_t* lflag, const uint8_t* pflag, int nthr, hipStream_t st);
 template <typename T>
-hipError_t launch_sandwich(const void* Fin, void* Fout, const void* R, const SandArgs& a, const AxisPlan& pl,
-                           const void* tw, const void* phx, const void* phy, const void* phz, const uint8_t* pflag,
-                           int nthr, hipStream_t st);
+hipError_t launch_sandwich(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
+                           const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
+                           hipStream_t st);
+// a sandwich launch configuration (plan, tile, threads)
+struct SandCfg {
+  int nst, tl, lgc, nthr;
+  uint32_t radpack;
+};
+// one sandwich variant (NIN input / NOUT output components), last-stage radix rs
+template <typename T, int NIN, int NOUT>
+hipError_t launch_sandwich_v(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
+                             const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
+                             size_t lds, int rs, hipStream_t st);
+// largest last-stage radix compiled for each sandwich variant (registers: NIN x RS held values)
+constexpr int sandwich_rs_max(int elem, int nin) { return elem == 4 ? (nin == 3 ? 6 : 9) : (nin == 3 ? 5 : 4); }
+constexpr int sandwich_rmax(int elem) { return elem == 4 ? 16 : 10; }
 template <typename T>
 hipError_t launch_zinv(const void* O, double* y, const double* x, int64_t N, int nrhs, int mode, const int32_t* items,
                        int nitems, const int32_t* line_ptr, const int32_t* pk, const int8_t* pkind,

@@ -10,8 +10,7 @@
 //             two real lines per complex transform
 //  k_strided  C2C along a strided axis (y, or x during setup) on tiles of `ncol`
 //             consecutive kz columns, with row pruning from per-line flags
-//  k_xsandwich forward x transform of the inputs, the per-frequency block multiply,
-//             inverse x transform of each output, all in one LDS tile of (ky, kz) columns
+//  (the x transform with the block multiply is in sandwich_impl.hpp)
 //  k_zinv     inverse z transform (C2R) of the lines that hold panels, fused with the
 //             gather, the jump term of eq. (7) and the FP64 result
 #include "fft_core.hpp"
@@ -132,167 +131,6 @@ k_strided(C2<T>* __restrict__ data, StridedArgs a, CompSet cs, AxisPlan pl, cons
   }
 }
 
-// ------------------------------------------------------------------------------ x sandwich
-// A workgroup owns 2^lgc consecutive (ky, kz) columns of the [x][ky][kz] arrays (for a
-// fixed x they are contiguous, so tiles never straddle a row end) and every kx.
-// Stored kernel spectra are real after a separable half-voxel phase (see setup); the
-// value for frequency (kx, ky, kz) of pair q is par(q, kx) * par(q, ky) * R[q][ky'][kz][kx'],
-// kx' contiguous, so the multiply maps consecutive threads to consecutive kx.
-template <typename T>
-__device__ __forceinline__ T rget(const T* __restrict__ R, const SandArgs& a, int q, int kx, int kyp, int kz,
-                                  int yflip) {
-  int kxp = kx;
-  const unsigned odd = (unsigned)(a.oddmask >> (3 * q)) & 7u;   // bit a: odd in k_a
-  bool neg = yflip && ((odd >> 1) & 1u);
-  if (kx > a.Mx / 2) {
-    kxp = a.Mx - kx;
-    if (odd & 1u) neg = !neg;
-  }
-  const T v = R[(int64_t)q * a.pair_stride + ((int64_t)kyp * a.H + kz) * a.Hx + kxp];
-  return neg ? -v : v;
-}
-
-// Workgroups are dispatched to the 8 XCDs round-robin by linear id; this maps linear id
-// -> work index so that each XCD gets one contiguous range (neighbouring column tiles,
-// which share cache lines and spectra, then meet in the same L2).
-__device__ __forceinline__ int xcd_remap(int lin, int n) {
-  const int xcd = lin & 7, idx = lin >> 3;
-  const int per = n >> 3, rem = n & 7;
-  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-}
-
-// One workgroup = one right-hand side x 2^lgc (ky, kz) columns x all kx.  The inputs'
-// global loads for component b+1 are issued before the transform of component b so
-// they are in flight while it runs; transformed inputs stay in registers (rows-fastest
-// mapping: thread element j is kx = er[j] of column ec[j]).
-template <typename T, int EMAX, int NIN, int NOUT, int NTHR>
-__global__ void __launch_bounds__(NTHR, (sizeof(T) == 8 || NIN == 6) ? 2 : 4)
-k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __restrict__ R, SandArgs a,
-            AxisPlan pl, const C2<T>* __restrict__ twg, const C2<T>* __restrict__ phx, const C2<T>* __restrict__ phy,
-            const C2<T>* __restrict__ phz, const uint8_t* __restrict__ pflag) {
-  extern __shared__ char smem_raw[];
-  const int L = pl.L;  // = Mx
-  const int lgc = a.lgc, ncol = 1 << lgc, ncolp = ncol + 1, cmask = ncol - 1;
-  C2<T>* tw = reinterpret_cast<C2<T>*>(smem_raw);
-  C2<T>* buf = tw + L;
-  C2<T>* buf2 = buf + L * ncolp;
-  const int tid = threadIdx.x;
-  const int ntiles = gridDim.x;
-  const int work = xcd_remap(blockIdx.y * ntiles + blockIdx.x, ntiles * gridDim.y);
-  const int rhs = work / ntiles, tile = work - rhs * ntiles;
-  const int ncols = a.My * a.H;                 // flattened (ky, kz) columns
-  const int col0 = tile * ncol;
-  const int64_t rowst = (int64_t)a.My * a.H;    // stride between x rows
-  const float invL = 1.0f / (float)L, invH = 1.0f / (float)a.H;
-  for (int t = tid; t < L; t += NTHR) tw[t] = twg[t];
-  const int nel = L << lgc;
-  C2<T> q[NIN][EMAX];
-  C2<T> pre[EMAX];
-  // global -> registers for input component b (columns fastest: contiguous reads)
-#define VC_FETCH(b)                                                                                  \
-  {                                                                                                  \
-    const int fax = (b) % 3;                                                                         \
-    const int fmsk = NIN == 3 ? 3 : ((b) < 3 ? 1 : 2);                                               \
-    const C2<T>* src = Fin + (b) * a.comp_stride + rhs * a.rhs_stride;                               \
-    _Pragma("unroll") for (int j = 0; j < EMAX; ++j) {                                               \
-      const int e = tid + j * NTHR;                                                                  \
-      const int r = e >> lgc, col = col0 + (e & cmask);                                              \
-      C2<T> v = {T(0), T(0)};                                                                        \
-      if (e < nel && r < a.n1x && col < ncols && (pflag[fax * a.n1x + r] & fmsk)) v = src[r * rowst + col]; \
-      pre[j] = v;                                                                                    \
-    }                                                                                                \
-  }
-  VC_FETCH(0)
-#pragma unroll
-  for (int b = 0; b < NIN; ++b) {
-    const int axis = b % 3;
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < EMAX; ++j) {
-      const int e = tid + j * NTHR;
-      if (e < nel) buf[(e >> lgc) * ncolp + (e & cmask)] = pre[j];
-    }
-    __syncthreads();
-    if (b + 1 < NIN) VC_FETCH(b + 1)
-    const C2<T>* res = lds_fft<T, Tune<T>::maxr_sand>(buf, buf2, tw, pl, lgc, ncolp, false);
-#pragma unroll
-    for (int j = 0; j < EMAX; ++j) {            // rows fastest: contiguous spectra reads
-      const int e = tid + j * NTHR;
-      if (e < nel) {
-        const int c = fdiv(e, invL), r = e - c * L;
-        const int col = min(col0 + c, ncols - 1);
-        const int ky = fdiv(col, invH), kz = col - ky * a.H;
-        // half-voxel phase of the input component (shift to the common lattice)
-        const C2<T> ph = axis == 0 ? phx[r] : (axis == 1 ? phy[ky] : phz[kz]);
-        q[b][j] = cmul(res[r * ncolp + c], ph);
-      } else {
-        q[b][j] = C2<T>{T(0), T(0)};
-      }
-    }
-  }
-#undef VC_FETCH
-  for (int o = 0; o < NOUT; ++o) {
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < EMAX; ++j) {
-      const int e = tid + j * NTHR;
-      if (e < nel) {
-        const int c = fdiv(e, invL), r = e - c * L;
-        const int col = min(col0 + c, ncols - 1);
-        const int ky = fdiv(col, invH), kz = col - ky * a.H;
-        const int yflip = ky > a.My / 2;
-        const int kyp = yflip ? a.My - ky : ky;
-        C2<T> acc = {T(0), T(0)};
-        int oax;
-        if (NIN == 3) {
-          // o < 3: C_alpha = sum_b P(alpha,b) Q'_b ; o >= 3: D_alpha = i sum_b E(alpha,b) Q'_b
-          const int al = o < 3 ? o : o - 3;
-          oax = al;
-#pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            const int qi = o < 3 ? (al == b ? al : 2 + al + b) : 6 + 3 * al + b;
-            const T rv = rget(R, a, qi, r, kyp, kz, yflip);
-            acc.x += rv * q[b][j].x;
-            acc.y += rv * q[b][j].y;
-          }
-          if (o >= 3) acc = C2<T>{-acc.y, acc.x};
-        } else {
-          // adjoint: out_b = sum_al P(al,b) X'C_al - i sum_al E(al,b) X'D_al
-          const int bb = o;
-          oax = bb;
-          C2<T> accE = {T(0), T(0)};
-#pragma unroll
-          for (int al = 0; al < 3; ++al) {
-            const int qp = al == bb ? al : 2 + al + bb;
-            const T rp = rget(R, a, qp, r, kyp, kz, yflip);
-            acc.x += rp * q[al][j].x;
-            acc.y += rp * q[al][j].y;
-            const T re = rget(R, a, 6 + 3 * al + bb, r, kyp, kz, yflip);
-            accE.x += re * q[(NIN > 3 ? 3 : 0) + al][j].x;
-            accE.y += re * q[(NIN > 3 ? 3 : 0) + al][j].y;
-          }
-          acc.x += accE.y;   // -i * accE
-          acc.y -= accE.x;
-        }
-        // output phase: conj of the half-voxel shift of the output component
-        const C2<T> ph = oax == 0 ? phx[r] : (oax == 1 ? phy[ky] : phz[kz]);
-        buf[r * ncolp + c] = cmul(acc, cconj(ph));
-      }
-    }
-    __syncthreads();
-    const C2<T>* res = lds_fft<T, Tune<T>::maxr_sand>(buf, buf2, tw, pl, lgc, ncolp, true);
-    const int axis = o % 3, msk = NIN == 3 ? (o < 3 ? 1 : 2) : 3;
-    C2<T>* dst = Fout + o * a.comp_stride + rhs * a.rhs_stride;
-    for (int e = tid; e < (a.n1x << lgc); e += NTHR) {
-      const int r = e >> lgc, c = e & cmask;
-      const int col = col0 + c;
-      if (col >= ncols) continue;
-      if (!(pflag[axis * a.n1x + r] & msk)) continue;
-      dst[r * rowst + col] = res[r * ncolp + c];
-    }
-  }
-}
-
 // ------------------------------------------------------------------------------ z inverse + gather
 template <typename T, int EMAX>
 __global__ void __launch_bounds__(1024)
@@ -400,32 +238,34 @@ hipError_t launch_strided(void* data, const StridedArgs& a, const CompSet& cs, i
 }
 
 template <typename T>
-hipError_t launch_sandwich(const void* Fin, void* Fout, const void* R, const SandArgs& a, const AxisPlan& pl,
-                           const void* tw, const void* phx, const void* phy, const void* phz, const uint8_t* pflag,
-                           int nthr, hipStream_t st) {
-  dim3 grid((a.My * a.H + a.ncol - 1) / a.ncol, a.nrhs);
-  size_t lds = lds_bytes<T>(pl.L, a.ncol);
-  SandArgs b = a;
-  b.lgc = ilog2(a.ncol);
-  if ((1 << b.lgc) != a.ncol) return hipErrorInvalidValue;
-  constexpr int E = Tune<T>::emax_sand;
-#define VC_SAND(NI, NO, NT)                                                                                   \
-  hipLaunchKernelGGL((k_xsandwich<T, E, NI, NO, NT>), grid, dim3(NT), lds, st, (const C2<T>*)Fin,            \
-                     (C2<T>*)Fout, (const T*)R, b, pl, (const C2<T>*)tw, (const C2<T>*)phx, (const C2<T>*)phy, \
-                     (const C2<T>*)phz, pflag)
-#define VC_SAND_T(NI, NO)                 \
-  if (nthr == 256) VC_SAND(NI, NO, 256);  \
-  else if (nthr == 512) VC_SAND(NI, NO, 512); \
-  else VC_SAND(NI, NO, 1024);
-  if ((long)pl.L * a.ncol > (long)E * nthr || (nthr != 256 && nthr != 512 && nthr != 1024))
+hipError_t launch_sandwich(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
+                           const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
+                           hipStream_t st) {
+  // the kernel assumes every one of these
+  if (a.nst < 1 || a.nst > kSandMaxStages || a.lgc < 0 || a.lgc > 5 || nthr < 64 || nthr > 512 || (nthr & 63))
     return hipErrorInvalidValue;
-  if (!a.adjoint && a.nout == 6) { VC_SAND_T(3, 6) }
-  else if (!a.adjoint && a.nout == 3) { VC_SAND_T(3, 3) }
-  else if (a.adjoint && a.nin == 6) { VC_SAND_T(6, 3) }
-  else return hipErrorInvalidValue;
-#undef VC_SAND_T
-#undef VC_SAND
-  return hipGetLastError();
+  long prod = 1;
+  int prev = 1 << 30;
+  for (int s = 0; s < a.nst; ++s) {
+    const int r = (int)((a.radpack >> (5 * s)) & 31u);
+    if (r < 2 || r > prev) return hipErrorInvalidValue;
+    if (s == 0 && r > sandwich_rmax((int)sizeof(T))) return hipErrorInvalidValue;
+    if (s > 0 && s < a.nst - 1 && r > sandwich_rmid((int)sizeof(T))) return hipErrorInvalidValue;
+    prev = r;
+    prod *= r;
+  }
+  const int rs = (int)((a.radpack >> (5 * (a.nst - 1))) & 31u);
+  if (prod != a.Mx || (long)a.tl * rs != a.Mx || ((long)a.tl << a.lgc) > nthr) return hipErrorInvalidValue;
+  if (a.nst == 1 && a.tl != 1) return hipErrorInvalidValue;
+  if (rs > sandwich_rs_max((int)sizeof(T), a.nin)) return hipErrorInvalidValue;
+  const size_t lds = sandwich_lds_bytes(a.Mx, 1 << a.lgc, (int)sizeof(T), a.n1x);
+  if (!a.adjoint && a.nin == 3 && a.nout == 6)
+    return launch_sandwich_v<T, 3, 6>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st);
+  if (!a.adjoint && a.nin == 3 && a.nout == 3)
+    return launch_sandwich_v<T, 3, 3>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st);
+  if (a.adjoint && a.nin == 6 && a.nout == 3)
+    return launch_sandwich_v<T, 6, 3>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st);
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -448,9 +288,8 @@ hipError_t launch_zinv(const void* O, double* y, const double* x, int64_t N, int
                                      const AxisPlan&, const void*, int, int, hipStream_t);                         \
   template hipError_t launch_strided<T>(void*, const StridedArgs&, const CompSet&, int, const AxisPlan&,          \
                                         const void*, const uint8_t*, const uint8_t*, int, hipStream_t);            \
-  template hipError_t launch_sandwich<T>(const void*, void*, const void*, const SandArgs&, const AxisPlan&,       \
-                                         const void*, const void*, const void*, const void*, const uint8_t*, int,  \
-                                         hipStream_t);                                                             \
+  template hipError_t launch_sandwich<T>(const void*, void*, const void*, const SandArgs&, const void*, const void*, \
+                                         const void*, const void*, const uint8_t*, int, hipStream_t);              \
   template hipError_t launch_zinv<T>(const void*, double*, const double*, int64_t, int, int, const int32_t*, int, \
                                      const int32_t*, const int32_t*, const int8_t*, const double*, const uint8_t*, \
                                      int64_t, int64_t, int, int, int, int, const AxisPlan&, const void*, int, int, \

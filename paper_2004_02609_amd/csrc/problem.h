@@ -12,6 +12,9 @@
 namespace vc {
 
 void set_error(const char* fmt, ...);
+struct SandCfg;
+std::vector<SandCfg> sandwich_candidates(int L, int elem, int nin, int n1x, size_t budget);
+bool sandwich_default(int L, int elem, int nin, int n1x, size_t budget, SandCfg* cfg);
 
 // Owning device allocation.
 struct DevMem {
@@ -46,7 +49,7 @@ struct AxisTables {
 
 struct PrecTables {
   AxisTables ax[3];
-  DevMem R;    // [15][Hy][H][Hx] real spectra (or empty for pairs not stored)
+  DevMem R;    // [15][Hx][Hy][H] real spectra, kz contiguous (pairs not stored left unset)
 };
 
 struct Precond {

@@ -89,8 +89,8 @@ static void gauss_legendre_table(std::vector<double>& gl) {
 
 template <typename T>
 static hipError_t upload_axis(AxisTables& t, int L, int axis) {
-  // the x axis is transformed by the sandwich kernel, which compiles fewer radices
-  t.plan = make_plan(L, axis == 0 ? Tune<T>::maxr_sand : Tune<T>::maxr);
+  (void)axis;
+  t.plan = make_plan(L, Tune<T>::maxr);
   std::vector<T> tw(2 * L), ph(2 * L);
   for (int k = 0; k < L; ++k) {
     const long double a = 2.0L * (long double)M_PI * k / L;

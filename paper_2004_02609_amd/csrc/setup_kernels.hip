@@ -241,9 +241,10 @@ __global__ void k_extract(const C2<double>* __restrict__ spec, double* __restric
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double bad = 0.0;
   if (id < total) {
-    const int kx = (int)(id % a.Hx);
-    const int kz = (int)((id / a.Hx) % a.H);
-    const int ky = (int)(id / ((int64_t)a.Hx * a.H));
+    // stored layout [kx < Hx][ky < Hy][kz < H], kz contiguous
+    const int kz = (int)(id % a.H);
+    const int ky = (int)((id / a.H) % a.Hy);
+    const int kx = (int)(id / ((int64_t)a.Hy * a.H));
     const C2<double> S = spec[((int64_t)kx * a.My + ky) * a.H + kz];
     const int k[3] = {kx, ky, kz};
     const int M[3] = {a.Mx, a.My, a.Mz};
