@@ -86,6 +86,70 @@ def cpu_baseline(scene, nrhs, budget_s=20.0):
             "assembly_s_per_row": t_asm / nrow}
 
 
+def _pmc_rows(d, counter):
+    """(dispatch id, kernel name, value) of one counter from a rocprofv3 --pmc csv run."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    rows = {}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            k = int(r["Dispatch_Id"])
+            name = r.get("Kernel_Name", "")
+            rows[k] = (name, rows.get(k, (name, 0.0))[1] + float(r["Counter_Value"]))
+    return [(k, v[0], v[1]) for k, v in sorted(rows.items())]
+
+
+def write_traffic(args):
+    """HBM bytes per launch of each pass of the timed steps: FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch) scaled so the calibration copy reads and writes its known size."""
+    fetch = _pmc_rows(args.write_traffic[0], "FETCH_SIZE")
+    write = _pmc_rows(args.write_traffic[1], "WRITE_SIZE")
+    copy_bytes = float(args.calib_copy_mib) * (1 << 20)
+    if copy_bytes <= 0:
+        raise SystemExit("--write-traffic needs the --calib-copy-mib of the profiled runs")
+    tname = "float" if args.prec == "fp32" else "double"
+    kern = {"zfwd_scatter": "k_zfwd<" + tname, "y": "k_strided<" + tname, "x_sandwich_multiply": "k_xsandwich<" + tname,
+            "zinv_gather": "k_zinv<" + tname}
+
+    def per_pass(rows):
+        cp = [v for _, n, v in rows if "copy" in n.lower()]
+        if not cp:
+            raise SystemExit("calibration copy kernel not found")
+        scale = copy_bytes / (max(cp) * 1024.0)
+        out = {}
+        for p, key in kern.items():
+            vals = [v for _, n, v in rows if key in n.replace(" ", "")]
+            if p == "y":
+                last = vals[-2 * args.steps:]
+                out["y_forward"] = sum(last[0::2]) / args.steps * 1024.0 * scale
+                out["y_inverse"] = sum(last[1::2]) / args.steps * 1024.0 * scale
+            else:
+                last = vals[-args.steps:]
+                out[p] = sum(last) / len(last) * 1024.0 * scale
+        return out, scale, max(cp)
+
+    f, fs, fcp = per_pass(fetch)
+    w, ws, wcp = per_pass(write)
+    cmd = (f"python bench.py --config {args.config} --prec {args.prec} --steps {args.steps} --warmup {args.warmup} "
+           f"--no-cpu --no-solve --no-other --calib-copy-mib {args.calib_copy_mib}")
+    res = {"source_hash": kernel_source_hash(), "config": args.config, "prec": args.prec,
+           "commands": [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- {cmd}",
+                        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- {cmd}"],
+           "copy_bytes": copy_bytes, "copy_fetch_kib": fcp, "copy_write_kib": wcp,
+           "scale_fetch": fs, "scale_write": ws,
+           "passes": {p: f[p] + w[p] for p in f},
+           "fetch_bytes": f, "write_bytes": w}
+    path = os.path.join(ROOT, "profiles", f"traffic_{args.config}_{args.prec}.json")
+    with open(path, "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(json.dumps(res, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,7 +159,17 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="heuristic x-pass configuration instead of the autotuner")
+    ap.add_argument("--no-other", action="store_true", help="skip the product in the other precision")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device (HBM-counter calibration under rocprofv3 --pmc)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="(no GPU) turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this command with "
+                         "--calib-copy-mib into profiles/traffic_<config>_<prec>.json, then exit")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is design-only", file=sys.stderr)
@@ -108,9 +182,17 @@ def main():
     from paper_2004_02609_amd import voxcap
 
     dev = torch.device("cuda:0")
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib << 18
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     scene = scenes.by_name(args.config)
     t0 = time.perf_counter()
-    P = voxcap.Problem.from_scene(scene).setup()
+    P = voxcap.Problem.from_scene(scene).setup(autotune=not args.no_tune)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     B, N = P.m, P.N
@@ -141,10 +223,12 @@ def main():
     ms, (pms, pcnt, pbytes) = run(args.prec, args.steps, args.warmup, True)
     value = args.steps * B / (ms / 1e3)
     other = "fp64" if args.prec == "fp32" else "fp32"
-    ms_o, _ = run(other, max(10, args.steps // 2), 3, False)
-    value_o = max(10, args.steps // 2) * B / (ms_o / 1e3)
-    print(f"# {args.prec} product {ms / args.steps * 1e3:.1f} us/step, {other} "
-          f"{ms_o / max(10, args.steps // 2) * 1e3:.1f} us/step", file=sys.stderr, flush=True)
+    value_o = None
+    if not args.no_other:
+        ms_o, _ = run(other, max(10, args.steps // 2), 3, False)
+        value_o = max(10, args.steps // 2) * B / (ms_o / 1e3)
+        print(f"# {args.prec} product {ms / args.steps * 1e3:.1f} us/step, {other} "
+              f"{ms_o / max(10, args.steps // 2) * 1e3:.1f} us/step", file=sys.stderr, flush=True)
 
     dom = int(np.argmax(pms))
     avg_ms = pms[dom] / max(1, pcnt[dom])
@@ -187,10 +271,11 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "cpu_baseline": cpu,
-        "other_precision": {"prec": other, "value": value_o, "unit": "RHS-MVPs/s"},
+        "other_precision": {"prec": other, "value": value_o, "unit": "RHS-MVPs/s"} if value_o else None,
         "passes": passes,
         "solve": solve,
         "setup_s": t_setup,
+        "xpass_tuning": P.tuning_report().strip().splitlines(),
     }
     print(json.dumps(line), flush=True)
 

@@ -94,6 +94,11 @@ typedef struct {
   double tucker_tol;
   int32_t precisions;
   int32_t max_rhs;     /* largest nrhs later passed to vc_apply (0 = m)              */
+  int32_t autotune;    /* 1: the first product of each (precision, direction, nrhs)
+                          times every launch configuration of the x pass (radix plan x
+                          column tile) and keeps the fastest; 0: a fixed heuristic.
+                          Tuning synchronizes the stream once and is skipped while the
+                          stream is being captured into a graph.                    */
 } vc_setup_opts;
 
 /* Solve options.  GMRES(restart) with the block-diagonal-diagonal preconditioner
@@ -167,6 +172,26 @@ vc_status vc_capacitance_grad_eps(vc_problem *p, const vc_solve_opts *opts,
  * most recent vc_apply (compulsory reads + writes of the pruned pass, counting the
  * kernel spectra once per launch); it then clears the accumulators. */
 vc_status vc_profile_enable(vc_problem *p, int enable);
+
+/* Text report of the x-pass launch configurations in use, one line per
+ * (precision, direction, nrhs): radices, columns per workgroup, threads, and whether
+ * the autotuner timed it (with the time of the chosen and of the default
+ * configuration).  Writes at most len bytes including the terminating zero. */
+vc_status vc_tuning_report(vc_problem *p, char *buf, int32_t len);
+
+/* Launch configurations of the x pass available for a precision and direction, as
+ * rows of 8 int32: {nst, r_0, ..., r_5, cols} (radices r_0 >= ... >= r_{nst-1}, unused
+ * ones 0; cols = columns per workgroup).  Writes at most max_rows rows to out and the
+ * number available to *n_rows.  Requires vc_setup. */
+vc_status vc_xpass_candidates(vc_problem *p, vc_precision prec, int transpose, int32_t *out,
+                              int32_t max_rows, int32_t *n_rows);
+
+/* Pins the x-pass configuration (a row as returned above) for products with this
+ * precision, direction and nrhs; it replaces what the heuristic or the autotuner chose
+ * and is kept until the next vc_setup.  VC_ERR_ARG if the row is not a valid
+ * configuration for this problem. */
+vc_status vc_xpass_set(vc_problem *p, vc_precision prec, int transpose, int32_t nrhs,
+                       const int32_t cfg[8]);
 vc_status vc_pass_times(vc_problem *p, double ms[5], int32_t launches[5], double bytes[5]);
 
 const char *vc_status_string(vc_status s);

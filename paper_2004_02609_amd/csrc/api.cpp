@@ -406,6 +406,8 @@ vc_status vc_setup(vc_problem* p, const vc_setup_opts* opts, void* stream) {
   s = build_spectra(p, (prec & 1) != 0, (prec & 2) != 0, st);
   if (s != VC_OK) return mark(p, s);
   p->max_rhs = o.max_rhs > 0 ? o.max_rhs : p->m;
+  p->autotune = o.autotune != 0;
+  p->sand_choice.clear();
   const bool diel = p->n_diel > 0;
   p->ncomp_F = diel ? 6 : 3;
   p->ncomp_O = diel ? 6 : 3;
@@ -563,6 +565,74 @@ vc_status vc_pass_times(vc_problem* p, double ms[5], int32_t launches[5], double
     for (hipEvent_t e : ev) p->ev_free.push_back(e);
   }
   p->ev_pending.clear();
+  return VC_OK;
+}
+
+vc_status vc_xpass_candidates(vc_problem* p, vc_precision prec, int transpose, int32_t* out, int32_t max_rows,
+                              int32_t* n_rows) {
+  VC_CHECK_PROBLEM(p);
+  if (!p->setup_done) { set_error("vc_setup first"); return VC_ERR_STATE; }
+  if (!n_rows || (max_rows > 0 && !out)) { set_error("null argument"); return VC_ERR_ARG; }
+  if (prec != VC_FP64 && prec != VC_FP32) { set_error("prec must be VC_FP64 or VC_FP32"); return VC_ERR_ARG; }
+  const int elem = prec == VC_FP32 ? 4 : 8;
+  const int nin = (transpose && p->n_diel > 0) ? 6 : 3;
+  const std::vector<vc::SandCfg> cand = vc::sandwich_candidates(p->M[0], elem, nin, p->n1[0], vc::kLdsBudget);
+  *n_rows = (int32_t)cand.size();
+  for (int32_t r = 0; r < (int32_t)cand.size() && r < max_rows; ++r) {
+    int32_t* row = out + 8 * r;
+    for (int k = 0; k < 8; ++k) row[k] = 0;
+    row[0] = cand[r].nst;
+    for (int s2 = 0; s2 < cand[r].nst; ++s2) row[1 + s2] = (int32_t)((cand[r].radpack >> (5 * s2)) & 31u);
+    row[7] = 1 << cand[r].lgc;
+  }
+  return VC_OK;
+}
+
+vc_status vc_xpass_set(vc_problem* p, vc_precision prec, int transpose, int32_t nrhs, const int32_t cfg[8]) {
+  VC_CHECK_PROBLEM(p);
+  if (!p->setup_done) { set_error("vc_setup first"); return VC_ERR_STATE; }
+  if (!cfg || nrhs <= 0 || nrhs > p->max_rhs) { set_error("bad cfg or nrhs"); return VC_ERR_ARG; }
+  if (prec != VC_FP64 && prec != VC_FP32) { set_error("prec must be VC_FP64 or VC_FP32"); return VC_ERR_ARG; }
+  const int elem = prec == VC_FP32 ? 4 : 8;
+  const int nin = (transpose && p->n_diel > 0) ? 6 : 3;
+  const std::vector<vc::SandCfg> cand = vc::sandwich_candidates(p->M[0], elem, nin, p->n1[0], vc::kLdsBudget);
+  for (const vc::SandCfg& g : cand) {
+    bool same = cfg[0] == g.nst && cfg[7] == (1 << g.lgc);
+    for (int s2 = 0; s2 < 6 && same; ++s2)
+      same = cfg[1 + s2] == (s2 < g.nst ? (int32_t)((g.radpack >> (5 * s2)) & 31u) : 0);
+    if (!same) continue;
+    const int t = (transpose && p->n_diel > 0) ? 1 : 0;   // without dielectric rows A is symmetric
+    const int key = (nrhs << 2) | (t << 1) | (elem == 8 ? 1 : 0);
+    p->sand_choice[key] = vc_problem::SandChoice{g.nst, g.tl, g.lgc, g.nthr, g.radpack, false, 0.0, 0.0};
+    return VC_OK;
+  }
+  set_error("not an x-pass configuration of this problem (see vc_xpass_candidates)");
+  return VC_ERR_ARG;
+}
+
+vc_status vc_tuning_report(vc_problem* p, char* buf, int32_t len) {
+  VC_CHECK_PROBLEM(p);
+  if (!buf || len <= 0) { set_error("null or empty buffer"); return VC_ERR_ARG; }
+  std::string out;
+  char line[256];
+  for (const auto& kv : p->sand_choice) {
+    const auto& c = kv.second;
+    std::string rad;
+    for (int s = 0; s < c.nst; ++s) {
+      if (s) rad += "x";
+      rad += std::to_string((int)((c.radpack >> (5 * s)) & 31u));
+    }
+    std::snprintf(line, sizeof line, "x-pass %s %s nrhs=%d radices=%s cols=%d threads=%d %s", (kv.first & 1) ? "fp64" : "fp32",
+                  (kv.first & 2) ? "transpose" : "forward", kv.first >> 2, rad.c_str(), 1 << c.lgc, c.nthr,
+                  c.tuned ? "tuned" : "default");
+    out += line;
+    if (c.tuned) {
+      std::snprintf(line, sizeof line, " best_ms=%.4f default_ms=%.4f", c.ms_best, c.ms_default);
+      out += line;
+    }
+    out += "\n";
+  }
+  std::snprintf(buf, (size_t)len, "%s", out.c_str());
   return VC_OK;
 }
 

@@ -182,13 +182,54 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
     for (int o = 0; o < 3; ++o) { cout.comp[o] = o; cout.axis[o] = o; cout.min_[o] = 0; cout.mout[o] = 3; }
   }
   {
-    SandCfg cfg;
-    if (!sandwich_default(Mx, (int)sizeof(T), xa.nin, n1x, budget, &cfg)) {
-      set_error("x transform length %d too long for the sandwich kernel", Mx);
-      return VC_ERR_ARG;
+    const int key = (nrhs << 2) | (transpose << 1) | (sizeof(T) == 8 ? 1 : 0);
+    auto it = P->sand_choice.find(key);
+    if (it == P->sand_choice.end()) {
+      SandCfg cfg;
+      if (!sandwich_default(Mx, (int)sizeof(T), xa.nin, n1x, budget, &cfg)) {
+        set_error("x transform length %d too long for the sandwich kernel", Mx);
+        return VC_ERR_ARG;
+      }
+      vc_problem::SandChoice ch{cfg.nst, cfg.tl, cfg.lgc, cfg.nthr, cfg.radpack, false, 0.0, 0.0};
+      hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+      VC_HIP(hipStreamIsCapturing(st, &cap));
+      if (P->autotune && cap == hipStreamCaptureStatusNone) {
+        // time every candidate on the live work arrays (the chosen one runs again below)
+        const std::vector<SandCfg> cand = sandwich_candidates(Mx, (int)sizeof(T), xa.nin, n1x, budget);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        VC_HIP(hipEventCreate(&e0));
+        VC_HIP(hipEventCreate(&e1));
+        double best = 1e30, dflt = 0.0;
+        for (const SandCfg& g : cand) {
+          SandArgs t = xa;
+          t.nst = g.nst; t.radpack = g.radpack; t.tl = g.tl; t.lgc = g.lgc;
+          VC_HIP(launch_sandwich<T>(F, O, tb.R.p, t, tb.ax[0].tw.p, tb.ax[0].ph.p, tb.ax[1].ph.p, tb.ax[2].ph.p,
+                                    pflag, g.nthr, st));
+          VC_HIP(hipEventRecord(e0, st));
+          for (int rep = 0; rep < 3; ++rep)
+            VC_HIP(launch_sandwich<T>(F, O, tb.R.p, t, tb.ax[0].tw.p, tb.ax[0].ph.p, tb.ax[1].ph.p, tb.ax[2].ph.p,
+                                      pflag, g.nthr, st));
+          VC_HIP(hipEventRecord(e1, st));
+          VC_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          VC_HIP(hipEventElapsedTime(&ms, e0, e1));
+          const double per = ms / 3.0;
+          if (g.radpack == cfg.radpack && g.lgc == cfg.lgc) dflt = per;
+          if (per < best) {
+            best = per;
+            ch = vc_problem::SandChoice{g.nst, g.tl, g.lgc, g.nthr, g.radpack, true, 0.0, 0.0};
+          }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        ch.ms_best = best;
+        ch.ms_default = dflt;
+      }
+      it = P->sand_choice.emplace(key, ch).first;
     }
-    xa.nst = cfg.nst; xa.radpack = cfg.radpack; xa.tl = cfg.tl; xa.lgc = cfg.lgc;
-    nthr = cfg.nthr;
+    const vc_problem::SandChoice& ch = it->second;
+    xa.nst = ch.nst; xa.radpack = ch.radpack; xa.tl = ch.tl; xa.lgc = ch.lgc;
+    nthr = ch.nthr;
   }
   VC_HIP(launch_sandwich<T>(F, O, tb.R.p, xa, tb.ax[0].tw.p, tb.ax[0].ph.p, tb.ax[1].ph.p, tb.ax[2].ph.p, pflag, nthr,
                             st));

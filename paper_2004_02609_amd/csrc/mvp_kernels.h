@@ -61,7 +61,7 @@ inline size_t sandwich_lds_bytes(int L, int ncol, int elem, int n1x) {
 // (smallest) radix <= rs_max, at most max_tl threads per column; nst = -1 when none
 AxisPlan make_sandwich_plan(int L, int rmax, int rmid, int rs_max, int max_tl);
 constexpr int kSandMaxStages = 6;
-constexpr int sandwich_rmid(int elem) { return elem == 4 ? 16 : 10; }
+constexpr int sandwich_rmid(int elem) { return elem == 4 ? 10 : 10; }
 
 template <typename T>
 hipError_t launch_zfwd(const double* x, int64_t N, int nrhs, int mode, const int32_t* items, int nitems,
@@ -86,8 +86,8 @@ hipError_t launch_sandwich_v(const void* Fin, void* Fout, const void* R, const S
                              const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
                              size_t lds, int rs, hipStream_t st);
 // largest last-stage radix compiled for each sandwich variant (registers: NIN x RS held values)
-constexpr int sandwich_rs_max(int elem, int nin) { return elem == 4 ? (nin == 3 ? 6 : 9) : (nin == 3 ? 5 : 4); }
-constexpr int sandwich_rmax(int elem) { return elem == 4 ? 16 : 10; }
+constexpr int sandwich_rs_max(int elem, int nin) { return elem == 4 ? (nin == 3 ? 6 : 7) : (nin == 3 ? 5 : 3); }
+constexpr int sandwich_rmax(int elem) { return elem == 4 ? 10 : 10; }
 template <typename T>
 hipError_t launch_zinv(const void* O, double* y, const double* x, int64_t N, int nrhs, int mode, const int32_t* items,
                        int nitems, const int32_t* line_ptr, const int32_t* pk, const int8_t* pkind,

@@ -258,6 +258,10 @@ hipError_t launch_sandwich(const void* Fin, void* Fout, const void* R, const San
   if (prod != a.Mx || (long)a.tl * rs != a.Mx || ((long)a.tl << a.lgc) > nthr) return hipErrorInvalidValue;
   if (a.nst == 1 && a.tl != 1) return hipErrorInvalidValue;
   if (rs > sandwich_rs_max((int)sizeof(T), a.nin)) return hipErrorInvalidValue;
+  // 32-bit byte offsets inside one (component, rhs) slab and one stored pair
+  if ((uint64_t)a.n1x * a.My * a.H * 2 * sizeof(T) >= ((uint64_t)1 << 32) ||
+      (uint64_t)a.pair_stride * sizeof(T) >= ((uint64_t)1 << 32))
+    return hipErrorInvalidValue;
   const size_t lds = sandwich_lds_bytes(a.Mx, 1 << a.lgc, (int)sizeof(T), a.n1x);
   if (!a.adjoint && a.nin == 3 && a.nout == 6)
     return launch_sandwich_v<T, 3, 6>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st);

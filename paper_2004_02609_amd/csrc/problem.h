@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -109,6 +110,15 @@ struct vc_problem {
   vc::DevMem s_V, s_w, s_z, s_r, s_b, s_x, s_h, s_partial, s_norm, s_active, s_tmp, s_y2;
   int s_restart = 0, s_nrhs = 0;
   int mvp_count = 0;
+  // x-pass launch configuration per (precision, direction, nrhs) key
+  bool autotune = false;
+  struct SandChoice {
+    int nst, tl, lgc, nthr;
+    uint32_t radpack;
+    bool tuned;
+    double ms_best, ms_default;
+  };
+  std::map<int, SandChoice> sand_choice;
   // per-pass timing (measurement)
   bool prof = false;
   std::vector<hipEvent_t> ev_free;

@@ -19,16 +19,18 @@
 //
 // Each transform makes one round trip through LDS (plus one per middle stage), and the
 // first and last butterflies touch HBM directly.  With S = 1 (L = RS) no LDS is used.
+//
+// Instruction economy (the pass is bound by vector-instruction issue): every LDS and
+// HBM address is a per-thread byte base computed once plus a workgroup-uniform stride
+// (one add per element); the rows a thread's first / last butterfly touches are
+// validated once into bit masks; the spectra offsets and fold signs of the thread's
+// frequencies are computed once, so each multiply term is a load, a sign flip and two
+// FMAs.
 #pragma once
 #include "fft_core.hpp"
 #include "mvp_kernels.h"
 
 namespace vc {
-
-// Largest radix compiled into the LDS stages of the sandwich, per precision.
-template <typename T> struct SandTune {
-  static constexpr int rmax = sandwich_rmax((int)sizeof(T));
-};
 
 // Workgroups are dispatched to the 8 XCDs round-robin by linear id; this maps linear id
 // -> work index so that each XCD gets one contiguous range of work.
@@ -38,9 +40,8 @@ __device__ __forceinline__ int xcd_remap(int lin, int n) {
   return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
-// Loads / stores at a uniform base plus a 32-bit per-lane byte offset (the launcher
-// checks every array the sandwich touches is below 4 GiB), so the addresses take one
-// VGPR each instead of a 64-bit pair.
+// Loads / stores at a base plus a 32-bit byte offset (the launcher checks every array
+// slab the sandwich indexes is below 4 GiB), one VGPR per address.
 template <typename V>
 __device__ __forceinline__ V ldo(const V* __restrict__ base, uint32_t byte_off) {
   return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + byte_off);
@@ -49,22 +50,13 @@ template <typename V>
 __device__ __forceinline__ void sto(V* __restrict__ base, uint32_t byte_off, V v) {
   *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
-
-// Stored real spectrum of pair q at (kx, ky, kz), ky already folded to kyp <= My/2
-// (yflip set when it was), layout [q][kxp < Hx][kyp < Hy][kz < H]: the folds use the
-// parity of the pair's spectrum under k_a -> M_a - k_a (bit a of its 3-bit field).
 template <typename T>
-__device__ __forceinline__ T rget(const T* __restrict__ R, const SandArgs& a, int q, int kx, int kyp, int kz,
-                                  int yflip) {
-  int kxp = kx;
-  const unsigned odd = (unsigned)(a.oddmask >> (3 * q)) & 7u;
-  bool neg = yflip && ((odd >> 1) & 1u);
-  if (kx > a.Mx / 2) {
-    kxp = a.Mx - kx;
-    if (odd & 1u) neg = !neg;
-  }
-  const T v = ldo(R + (int64_t)q * a.pair_stride, (uint32_t)(((kxp * a.Hy + kyp) * a.H + kz) * (int)sizeof(T)));
-  return neg ? -v : v;
+__device__ __forceinline__ C2<T> lds_ld(const char* __restrict__ lds, uint32_t off) {
+  return *reinterpret_cast<const C2<T>*>(lds + off);
+}
+template <typename T>
+__device__ __forceinline__ void lds_st(char* __restrict__ lds, uint32_t off, C2<T> v) {
+  *reinterpret_cast<C2<T>*>(lds + off) = v;
 }
 
 // component-wise select (a select of whole structs by a runtime flag can be lowered to
@@ -74,80 +66,119 @@ __device__ __forceinline__ C2<T> csel(bool f, C2<T> a, C2<T> b) {
   return C2<T>{f ? a.x : b.x, f ? a.y : b.y};
 }
 
-// v[q] *= w^(q ts), w = exp(-+2 pi i / L) from the table (conjugated for sg = +1)
+// flip the sign of v when bit 31 of s is set (s is 0 or 0x80000000)
+__device__ __forceinline__ float flip(float v, uint32_t s) { return __uint_as_float(__float_as_uint(v) ^ s); }
+__device__ __forceinline__ double flip(double v, uint32_t s) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v) ^ ((uint64_t)s << 32);
+  return __longlong_as_double((long long)u);
+}
+
+// v[q] *= w^(q ts), w = exp(-+2 pi i / L) from the LDS table; tsb = ts * sizeof(C2)
 template <typename T, int R>
-__device__ __forceinline__ void tw_mul(C2<T>* v, const C2<T>* __restrict__ tw, int ts, T sg) {
+__device__ __forceinline__ void tw_mul(C2<T>* v, const char* __restrict__ twb, uint32_t tsb, T sg) {
+  uint32_t o = 0;
 #pragma unroll
   for (int q = 1; q < R; ++q) {
-    C2<T> w = tw[q * ts];
+    o += tsb;
+    C2<T> w = lds_ld<T>(twb, o);
     w.y *= -sg;
     v[q] = cmul(v[q], w);
   }
 }
 
-// forward stage 0 (p = 1): butterfly i of column c straight from HBM (rows >= nrows or
-// without the flag bits are zero), outputs y[i R + q] to LDS
+// first-stage inputs of butterfly i: rows i + q L/R of one component from HBM into
+// registers; bit q of vmask says row i + q L/R is stored (else zero)
 template <typename T, int R>
-__device__ __forceinline__ void sw_first(const C2<T>* __restrict__ src, uint32_t off0, uint32_t rowb,
-                                         const uint8_t* __restrict__ pfl, int msk, int nrows, int L, int i,
-                                         bool colok, C2<T>* __restrict__ buf, int ncolp, int c) {
-  asm volatile("" : "+v"(i), "+v"(c));   // keep this stage's address arithmetic here (no hoisting)
-  const int LR = L / R;
-  if (i >= LR) return;
-  C2<T> v[R];
+__device__ __forceinline__ void sw_load(C2<T>* __restrict__ pre, const C2<T>* __restrict__ src, uint32_t gbase,
+                                        uint32_t gstride, uint32_t vmask, bool act) {
+  if (!act) return;
+  uint32_t o = gbase;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    const int r = i + q * LR;
-    v[q] = C2<T>{T(0), T(0)};
-    if (colok && r < nrows && (pfl[r] & msk)) v[q] = ldo(src, off0 + (uint32_t)r * rowb);
+    pre[q] = C2<T>{T(0), T(0)};
+    if (vmask & (1u << q)) pre[q] = ldo(src, o);
+    o += gstride;
   }
-  Dft<T, R>::run(v, T(-1));
-#pragma unroll
-  for (int q = 0; q < R; ++q) buf[(i * R + q) * ncolp + c] = v[Dft<T, R>::pos(q)];
 }
 
-// a middle Stockham stage in place in LDS: all reads, barrier, all writes, barrier
+// forward stage 0 (p = 1) on the staged inputs, outputs y[i R + q] to LDS; the loads
+// of the next component (if any) go into the staging registers first, so they are in
+// flight during this component's transform
 template <typename T, int R>
-__device__ __forceinline__ void sw_mid(C2<T>* __restrict__ buf, const C2<T>* __restrict__ tw, int L, int p,
-                                       float invp, int i, int c, int ncolp, T sg) {
-  asm volatile("" : "+v"(i), "+v"(c));   // keep this stage's address arithmetic here (no hoisting)
+__device__ __forceinline__ void sw_first(C2<T>* __restrict__ pre, bool next, const C2<T>* __restrict__ nsrc,
+                                         uint32_t gbase, uint32_t gstride, uint32_t nmask, bool act,
+                                         char* __restrict__ lds, uint32_t wbase, uint32_t ncolpE) {
+  if (!act) return;
+  C2<T> v[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) v[q] = pre[q];
+  if (next) sw_load<T, R>(pre, nsrc, gbase, gstride, nmask, true);
+  Dft<T, R>::run(v, T(-1));
+  uint32_t o = wbase;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    lds_st<T>(lds, o, v[Dft<T, R>::pos(q)]);
+    o += ncolpE;
+  }
+}
+
+// a middle Stockham stage in place in LDS (reads, barrier, writes, barrier); rbase is
+// the thread's row-i byte offset (i * ncolpE + c * E)
+template <typename T, int R>
+__device__ __forceinline__ void sw_mid(char* __restrict__ lds, const char* __restrict__ twb, int L, int p, float invp,
+                                       int i, uint32_t rbase, uint32_t cE, uint32_t ncolpE, T sg) {
+  asm volatile("" : "+v"(i), "+v"(rbase));   // keep this stage's address arithmetic here (no hoisting)
   const int LR = L / R;
   const bool act = i < LR;
   C2<T> v[R];
-  int j = 0;
+  uint32_t wb = 0;
   if (act) {
+    const uint32_t rstride = (uint32_t)LR * ncolpE;
+    uint32_t o = rbase;
 #pragma unroll
-    for (int q = 0; q < R; ++q) v[q] = buf[(i + q * LR) * ncolp + c];
+    for (int q = 0; q < R; ++q) {
+      v[q] = lds_ld<T>(lds, o);
+      o += rstride;
+    }
     const int ip = fdiv(i, invp), k = i - ip * p;
-    tw_mul<T, R>(v, tw, k * (LR / p), sg);
+    tw_mul<T, R>(v, twb, (uint32_t)(k * (LR / p)) * (uint32_t)sizeof(C2<T>), sg);
     Dft<T, R>::run(v, sg);
-    j = ip * p * R + k;
+    wb = (uint32_t)(ip * p * R + k) * ncolpE + cE;
   }
   __syncthreads();
   if (act) {
+    const uint32_t wstride = (uint32_t)p * ncolpE;
 #pragma unroll
-    for (int q = 0; q < R; ++q) buf[(j + q * p) * ncolp + c] = v[Dft<T, R>::pos(q)];
+    for (int q = 0; q < R; ++q) {
+      lds_st<T>(lds, wb, v[Dft<T, R>::pos(q)]);
+      wb += wstride;
+    }
   }
   __syncthreads();
 }
 
 // inverse last stage (radix R = f0, p = L/R): LDS -> butterfly -> HBM rows i + q L/R
 template <typename T, int R>
-__device__ __forceinline__ void sw_last_inv(const C2<T>* __restrict__ buf, const C2<T>* __restrict__ tw, int L, int i,
-                                            int c, int ncolp, C2<T>* __restrict__ dst, uint32_t off0, uint32_t rowb,
-                                            const uint8_t* __restrict__ pfl, int msk, int nrows, bool colok) {
-  asm volatile("" : "+v"(i), "+v"(c));   // keep this stage's address arithmetic here (no hoisting)
-  const int LR = L / R;
-  if (i >= LR) return;
+__device__ __forceinline__ void sw_last_inv(const char* __restrict__ lds, const char* __restrict__ twb, int L, int i,
+                                            uint32_t rbase, uint32_t ncolpE, C2<T>* __restrict__ dst, uint32_t gbase,
+                                            uint32_t gstride, uint32_t vmask, bool act) {
+  asm volatile("" : "+v"(i), "+v"(rbase));
+  if (!act) return;
+  const uint32_t rstride = (uint32_t)(L / R) * ncolpE;
   C2<T> v[R];
-#pragma unroll
-  for (int q = 0; q < R; ++q) v[q] = buf[(i + q * LR) * ncolp + c];
-  tw_mul<T, R>(v, tw, i, T(1));
-  Dft<T, R>::run(v, T(1));
+  uint32_t o = rbase;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    const int r = i + q * LR;
-    if (colok && r < nrows && (pfl[r] & msk)) sto(dst, off0 + (uint32_t)r * rowb, v[Dft<T, R>::pos(q)]);
+    v[q] = lds_ld<T>(lds, o);
+    o += rstride;
+  }
+  tw_mul<T, R>(v, twb, (uint32_t)i * (uint32_t)sizeof(C2<T>), T(1));
+  Dft<T, R>::run(v, T(1));
+  o = gbase;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    if (vmask & (1u << q)) sto(dst, o, v[Dft<T, R>::pos(q)]);
+    o += gstride;
   }
 }
 
@@ -162,12 +193,25 @@ __device__ __forceinline__ void sw_last_inv(const C2<T>* __restrict__ buf, const
     VC_SW_CASE(25, CALL, HI) VC_SW_CASE(27, CALL, HI)                                                     \
     default: break;                                                                                       \
   }
-#define VC_SW_CASE(RR, CALL, HI)                   \
-  case RR:                                         \
+#define VC_SW_CASE(RR, CALL, HI)                     \
+  case RR:                                           \
     if constexpr (RR >= RS && RR <= HI) { CALL(RR) } \
     break;
 
 __device__ __forceinline__ int srad(const SandArgs& a, int s) { return (int)((a.radpack >> (5 * s)) & 31u); }
+
+// pair index of the stored spectrum multiplying input b into output o
+//   forward (NIN = 3): o < 3 -> P(o,b); o >= 3 -> E(o-3,b)
+//   transposed (NIN = 6): b < 3 -> P(b,o); b >= 3 -> E(b-3,o)
+template <int NIN>
+__device__ __forceinline__ int sw_pair(int o, int b) {
+  if (NIN == 3) {
+    const int al = o < 3 ? o : o - 3;
+    return o < 3 ? (al == b ? al : 2 + al + b) : 6 + 3 * al + b;
+  }
+  const int al = b < 3 ? b : b - 3;
+  return b < 3 ? (al == o ? al : 2 + al + o) : 6 + 3 * al + o;
+}
 
 template <typename T, int NIN, int NOUT, int RS>
 __global__ void __launch_bounds__(512, (sizeof(T) == 8 || NIN == 6) ? 2 : 3)
@@ -175,67 +219,105 @@ k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __
             const C2<T>* __restrict__ twg, const C2<T>* __restrict__ phx, const C2<T>* __restrict__ phy,
             const C2<T>* __restrict__ phz, const uint8_t* __restrict__ pflag) {
   constexpr int RMAX = sandwich_rmax((int)sizeof(T)), RMID = sandwich_rmid((int)sizeof(T));
+  constexpr uint32_t E = sizeof(C2<T>);
   extern __shared__ char smem_raw[];
   const int L = a.Mx, tl = a.tl, S = a.nst;
-  const int lgc = a.lgc, ncol = 1 << lgc, ncolp = ncol + 1;
-  C2<T>* tw = reinterpret_cast<C2<T>*>(smem_raw);
-  C2<T>* buf = tw + L;
-  uint8_t* sflag = reinterpret_cast<uint8_t*>(buf + L * ncolp);   // plane flags of the 3 axes
+  const int lgc = a.lgc, ncol = 1 << lgc;
+  const uint32_t ncolpE = (uint32_t)(ncol + 1) * E;
+  char* twb = smem_raw;                                    // L twiddles
+  char* lds = smem_raw + (size_t)L * E;                    // [L][ncol + 1] tile
+  uint8_t* sflag = reinterpret_cast<uint8_t*>(lds + (size_t)L * ncolpE);   // plane flags of the 3 axes
   const int tid = threadIdx.x;
-  const int c_ = tid & (ncol - 1), i_ = tid >> lgc;
-  const bool valid = i_ < tl;
+  const int c = tid & (ncol - 1), i = tid >> lgc;
+  const bool valid = i < tl;
   // right-hand sides fastest: the workgroups that read one tile's spectra run together
   // on one XCD, so those spectra come from HBM once per tile rather than once per RHS
   const int ntiles = gridDim.x;
   const int work = xcd_remap(blockIdx.y * ntiles + blockIdx.x, ntiles * gridDim.y);
   const int tile = work / a.nrhs, rhs = work - tile * a.nrhs;
   const int ncols = a.My * a.H;                 // flattened (ky, kz) columns
-  const int col = (tile << lgc) + c_;
+  const int col = (tile << lgc) + c;
   const bool colok = col < ncols;
   const int colc = colok ? col : ncols - 1;
   const int ky = fdiv(colc, 1.0f / (float)a.H), kz = colc - ky * a.H;
   const int yflip = ky > a.My / 2;
   const int kyp = yflip ? a.My - ky : ky;
-  const uint32_t rowb = (uint32_t)ncols * (uint32_t)sizeof(C2<T>);   // bytes between x rows
-  const uint32_t off0 = (uint32_t)colc * (uint32_t)sizeof(C2<T>);
+  const uint32_t rowb = (uint32_t)ncols * E;   // bytes between x rows
   const int r0 = srad(a, 0);
-  for (int t = tid; t < L; t += blockDim.x) tw[t] = twg[t];
+  const int LR0 = L / r0;
+  const bool act0 = i < LR0;                   // owns a butterfly of the first / last stage
+  for (int t = tid; t < L; t += blockDim.x) reinterpret_cast<C2<T>*>(twb)[t] = twg[t];
   for (int t = tid; t < 3 * a.n1x; t += blockDim.x) sflag[t] = pflag[t];
   __syncthreads();
   const C2<T> phy_t = phy[ky], phz_t = phz[kz];
 
+  // per-thread geometry: LDS bases, HBM bases and strides of the first / last stage
+  const uint32_t cE = (uint32_t)c * E;
+  const uint32_t rbase = (uint32_t)i * ncolpE + cE;                // row i of the tile
+  const uint32_t gbase = (uint32_t)colc * E + (uint32_t)i * rowb;    // HBM row i of the column
+  const uint32_t gstride = (uint32_t)LR0 * rowb;                   // HBM rows i + q L/f0
+  // rows i + q L/f0 (q < f0) that are stored, per axis: bits 0..15 planes with conductor
+  // panels, bits 16..31 planes with dielectric panels
+  uint32_t rm0 = 0u, rm1 = 0u, rm2 = 0u;
+  if (act0 && colok) {
+    for (int qq = 0; qq < r0; ++qq) {
+      const int r = i + qq * LR0;
+      if (r >= a.n1x) break;
+      const uint32_t f0 = sflag[r], f1 = sflag[a.n1x + r], f2 = sflag[2 * a.n1x + r];
+      rm0 |= ((f0 & 1u) << qq) | (((f0 >> 1) & 1u) << (16 + qq));
+      rm1 |= ((f1 & 1u) << qq) | (((f1 >> 1) & 1u) << (16 + qq));
+      rm2 |= ((f2 & 1u) << qq) | (((f2 >> 1) & 1u) << (16 + qq));
+    }
+  }
+  auto vm = [&](int ax, int msk) -> uint32_t {
+    const uint32_t m = ax == 0 ? rm0 : (ax == 1 ? rm1 : rm2);
+    return ((msk & 1) ? (m & 0xffffu) : 0u) | ((msk & 2) ? (m >> 16) : 0u);
+  };
+
   C2<T> q[NIN][RS];
+  C2<T> pre[RMAX];   // staged first-stage inputs of the component about to be transformed
+  if (S > 1) {
+#define VC_CALL(RR) sw_load<T, RR>(pre, Fin + rhs * a.rhs_stride, gbase, gstride, vm(0, NIN == 3 ? 3 : 1), act0);
+    VC_SW_SWITCH(r0, VC_CALL, RMAX)
+#undef VC_CALL
+  }
 #pragma unroll 1
   for (int b = 0; b < NIN; ++b) {
-    // opaque per-iteration copies: without them the compiler hoists the address
-    // arithmetic of every radix case out of the loop and keeps it all live
-    int i = i_, c = c_;
-    asm volatile("" : "+v"(i), "+v"(c));
     const int fax = b % 3;
     const int fmsk = NIN == 3 ? 3 : (b < 3 ? 1 : 2);
     const C2<T>* src = Fin + b * a.comp_stride + rhs * a.rhs_stride;
-    const uint8_t* pfl = sflag + fax * a.n1x;
     C2<T> v[RS];
     if (S == 1) {
       if (valid) {
+        const uint32_t msk = vm(fax, fmsk);
+        uint32_t o = gbase;
 #pragma unroll
         for (int m = 0; m < RS; ++m) {
           v[m] = C2<T>{T(0), T(0)};
-          if (colok && m < a.n1x && (pfl[m] & fmsk)) v[m] = ldo(src, off0 + (uint32_t)m * rowb);
+          if (msk & (1u << m)) v[m] = ldo(src, o);
+          o += rowb;
         }
         Dft<T, RS>::run(v, T(-1));
       }
     } else {
-      if (b > 0) __syncthreads();   // readers of the previous component are done with buf
-#define VC_CALL(RR) sw_first<T, RR>(src, off0, rowb, pfl, fmsk, a.n1x, L, i, colok, buf, ncolp, c);
-      VC_SW_SWITCH(r0, VC_CALL, RMAX)
+      if (b > 0) __syncthreads();   // readers of the previous component are done with the tile
+      const int bn = b + 1;
+      const bool next = bn < NIN;
+      const C2<T>* nsrc = src + a.comp_stride;
+      const uint32_t nmask = vm(bn % 3, NIN == 3 ? 3 : (bn < 3 ? 1 : 2));
+      {
+        uint32_t wbase = (uint32_t)i * (uint32_t)r0 * ncolpE + cE;
+        asm volatile("" : "+v"(wbase));
+#define VC_CALL(RR) sw_first<T, RR>(pre, next, nsrc, gbase, gstride, nmask, act0, lds, wbase, ncolpE);
+        VC_SW_SWITCH(r0, VC_CALL, RMAX)
 #undef VC_CALL
+      }
       __syncthreads();
       int p = r0;
       for (int s = 1; s < S - 1; ++s) {
         const int rs = srad(a, s);
         const float invp = 1.0f / (float)p;
-#define VC_CALL(RR) sw_mid<T, RR>(buf, tw, L, p, invp, i, c, ncolp, T(-1));
+#define VC_CALL(RR) sw_mid<T, RR>(lds, twb, L, p, invp, i, rbase, cE, ncolpE, T(-1));
         VC_SW_SWITCH(rs, VC_CALL, RMID)
 #undef VC_CALL
         p *= rs;
@@ -243,9 +325,14 @@ k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __
       if (valid) {
         // last forward stage (radix RS, p = tl): butterfly i reads rows i + q tl,
         // twiddle exponent q i, outputs X[i + q tl]
+        const uint32_t st = (uint32_t)tl * ncolpE;
+        uint32_t o = rbase;
 #pragma unroll
-        for (int m = 0; m < RS; ++m) v[m] = buf[(i + m * tl) * ncolp + c];
-        tw_mul<T, RS>(v, tw, i, T(-1));
+        for (int m = 0; m < RS; ++m) {
+          v[m] = lds_ld<T>(lds, o);
+          o += st;
+        }
+        tw_mul<T, RS>(v, twb, (uint32_t)i * E, T(-1));
         Dft<T, RS>::run(v, T(-1));
       }
     }
@@ -253,37 +340,62 @@ k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __
     // pos(m) holds X[i + m tl]
     if (valid) {
       const C2<T> phyz = csel(fax == 1, phy_t, phz_t);
+      C2<T> w[RS];
 #pragma unroll
-      for (int m = 0; m < RS; ++m) {
-        const C2<T> ph = fax == 0 ? phx[i + m * tl] : phyz;
-        const C2<T> w = cmul(v[Dft<T, RS>::pos(m)], ph);
+      for (int m = 0; m < RS; ++m) w[m] = cmul(v[Dft<T, RS>::pos(m)], fax == 0 ? phx[i + m * tl] : phyz);
+      // per-element selects keep q in registers (a switch of stores is merged into one
+      // dynamically indexed store, which moves q to scratch memory)
 #pragma unroll
-        for (int bb = 0; bb < NIN; ++bb)
-          if (bb == b) q[bb][m] = w;
-      }
+      for (int bb = 0; bb < NIN; ++bb)
+#pragma unroll
+        for (int m = 0; m < RS; ++m)
+          if (bb == b) q[bb][m] = w[m];
     }
   }
 
+  // spectra offsets and fold signs of the thread's frequencies kx = i + m tl
+  uint32_t roff[RS], xs[RS];
+  const uint32_t ys = yflip ? 0x80000000u : 0u;
+#pragma unroll
+  for (int m = 0; m < RS; ++m) {
+    const int kx = i + m * tl;
+    const bool xf = kx > a.Mx / 2;
+    const int kxp = xf ? a.Mx - kx : kx;
+    roff[m] = valid ? (uint32_t)((kxp * a.Hy + kyp) * a.H + kz) * (uint32_t)sizeof(T) : 0u;
+    xs[m] = xf ? 0x80000000u : 0u;
+  }
+  // spectra of the block multiply, loaded one output component ahead
+  constexpr int NQ = NIN == 3 ? 3 : 6;
+  T rv[NQ][RS];
+  auto load_spectra = [&](int o) {
+#pragma unroll
+    for (int b = 0; b < NQ; ++b) {
+      const int qi = sw_pair<NIN>(o, b);
+      const unsigned odd = (unsigned)(a.oddmask >> (3 * qi)) & 7u;
+      const T* base = R + (int64_t)qi * a.pair_stride;
+#pragma unroll
+      for (int m = 0; m < RS; ++m) {
+        const uint32_t sg = ((odd & 1u) ? xs[m] : 0u) ^ ((odd & 2u) ? ys : 0u);
+        rv[b][m] = flip(ldo(base, roff[m]), sg);
+      }
+    }
+  };
+  if (valid) load_spectra(0);
 #pragma unroll 1
   for (int o = 0; o < NOUT; ++o) {
-    int i = i_, c = c_;
-    asm volatile("" : "+v"(i), "+v"(c));
     const int oax = NIN == 3 ? (o < 3 ? o : o - 3) : o;
     C2<T> z[RS];
     if (valid) {
       const C2<T> phyz = csel(oax == 1, phy_t, phz_t);
 #pragma unroll
       for (int m = 0; m < RS; ++m) {
-        const int kx = i + m * tl;
         C2<T> acc = {T(0), T(0)};
         if (NIN == 3) {
           // o < 3: C_alpha = sum_b P(alpha,b) Q'_b ; o >= 3: D_alpha = i sum_b E(alpha,b) Q'_b
 #pragma unroll
           for (int b = 0; b < 3; ++b) {
-            const int qi = o < 3 ? (oax == b ? oax : 2 + oax + b) : 6 + 3 * oax + b;
-            const T rv = rget(R, a, qi, kx, kyp, kz, yflip);
-            acc.x += rv * q[b][m].x;
-            acc.y += rv * q[b][m].y;
+            acc.x += rv[b][m] * q[b][m].x;
+            acc.y += rv[b][m] * q[b][m].y;
           }
           if (o >= 3) acc = C2<T>{-acc.y, acc.x};
         } else {
@@ -291,51 +403,55 @@ k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __
           C2<T> accE = {T(0), T(0)};
 #pragma unroll
           for (int al = 0; al < 3; ++al) {
-            const int qp = al == oax ? al : 2 + al + oax;
-            const T rp = rget(R, a, qp, kx, kyp, kz, yflip);
-            acc.x += rp * q[al][m].x;
-            acc.y += rp * q[al][m].y;
-            const T re = rget(R, a, 6 + 3 * al + oax, kx, kyp, kz, yflip);
-            accE.x += re * q[(NIN > 3 ? 3 : 0) + al][m].x;
-            accE.y += re * q[(NIN > 3 ? 3 : 0) + al][m].y;
+            acc.x += rv[al][m] * q[al][m].x;
+            acc.y += rv[al][m] * q[al][m].y;
+            accE.x += rv[3 + al][m] * q[(NIN > 3 ? 3 : 0) + al][m].x;
+            accE.y += rv[3 + al][m] * q[(NIN > 3 ? 3 : 0) + al][m].y;
           }
           acc.x += accE.y;   // -i * accE
           acc.y -= accE.x;
         }
         // output phase: conj of the half-voxel shift of the output component
-        const C2<T> ph = oax == 0 ? phx[kx] : phyz;
-        z[m] = cmul(acc, cconj(ph));
+        z[m] = cmul(acc, cconj(oax == 0 ? phx[i + m * tl] : phyz));
       }
+      if (o + 1 < NOUT) load_spectra(o + 1);
     }
     const int msk = NIN == 3 ? (o < 3 ? 1 : 2) : 3;
     C2<T>* dst = Fout + o * a.comp_stride + rhs * a.rhs_stride;
-    const uint8_t* pfl = sflag + oax * a.n1x;
+    const uint32_t omask = vm(oax, msk);
     if (S == 1) {
       if (valid) {
         Dft<T, RS>::run(z, T(1));
+        uint32_t og = gbase;
 #pragma unroll
-        for (int m = 0; m < RS; ++m)
-          if (colok && m < a.n1x && (pfl[m] & msk)) sto(dst, off0 + (uint32_t)m * rowb, z[Dft<T, RS>::pos(m)]);
+        for (int m = 0; m < RS; ++m) {
+          if (omask & (1u << m)) sto(dst, og, z[Dft<T, RS>::pos(m)]);
+          og += rowb;
+        }
       }
     } else {
-      __syncthreads();   // the previous readers of buf are done
+      __syncthreads();   // the previous readers of the tile are done
       if (valid) {
         // first inverse stage (radix RS, p = 1) on the held values X[i + q tl]
         Dft<T, RS>::run(z, T(1));
+        uint32_t ow = (uint32_t)i * (uint32_t)RS * ncolpE + cE;
 #pragma unroll
-        for (int m = 0; m < RS; ++m) buf[(i * RS + m) * ncolp + c] = z[Dft<T, RS>::pos(m)];
+        for (int m = 0; m < RS; ++m) {
+          lds_st<T>(lds, ow, z[Dft<T, RS>::pos(m)]);
+          ow += ncolpE;
+        }
       }
       __syncthreads();
       int p = RS;
       for (int s = S - 2; s >= 1; --s) {
         const int rs = srad(a, s);
         const float invp = 1.0f / (float)p;
-#define VC_CALL(RR) sw_mid<T, RR>(buf, tw, L, p, invp, i, c, ncolp, T(1));
+#define VC_CALL(RR) sw_mid<T, RR>(lds, twb, L, p, invp, i, rbase, cE, ncolpE, T(1));
         VC_SW_SWITCH(rs, VC_CALL, RMID)
 #undef VC_CALL
         p *= rs;
       }
-#define VC_CALL(RR) sw_last_inv<T, RR>(buf, tw, L, i, c, ncolp, dst, off0, rowb, pfl, msk, a.n1x, colok);
+#define VC_CALL(RR) sw_last_inv<T, RR>(lds, twb, L, i, rbase, ncolpE, dst, gbase, gstride, omask, act0);
       VC_SW_SWITCH(r0, VC_CALL, RMAX)
 #undef VC_CALL
     }

@@ -48,7 +48,7 @@ PANEL_DTYPE = np.dtype({"names": ["i", "j", "k", "dir", "kind", "pad", "cond", "
 
 class vc_setup_opts(C.Structure):
     _fields_ = [("fft_size", C.c_int32 * 3), ("nv", C.c_int32 * 3), ("tucker_tol", C.c_double),
-                ("precisions", C.c_int32), ("max_rhs", C.c_int32)]
+                ("precisions", C.c_int32), ("max_rhs", C.c_int32), ("autotune", C.c_int32)]
 
 
 class vc_solve_opts(C.Structure):
@@ -78,6 +78,10 @@ _sig = {
                                           C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(vc_stats)]),
     "vc_profile_enable": (C.c_int, [_P, C.c_int]),
     "vc_pass_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "vc_tuning_report": (C.c_int, [_P, C.c_char_p, C.c_int32]),
+    "vc_xpass_candidates": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int32), C.c_int32,
+                                      C.POINTER(C.c_int32)]),
+    "vc_xpass_set": (C.c_int, [_P, C.c_int, C.c_int, C.c_int32, C.POINTER(C.c_int32)]),
     "vc_status_string": (C.c_char_p, [C.c_int]),
     "vc_last_error": (C.c_char_p, []),
 }
@@ -149,7 +153,7 @@ def vc_fft_size(h):
     return tuple(m)
 
 
-def vc_setup(h, fft_size=None, nv=None, tucker_tol=0.0, precisions=0, max_rhs=0, stream=None):
+def vc_setup(h, fft_size=None, nv=None, tucker_tol=0.0, precisions=0, max_rhs=0, autotune=False, stream=None):
     o = vc_setup_opts()
     if fft_size is not None:
         o.fft_size[:] = [int(v) for v in fft_size]
@@ -158,6 +162,7 @@ def vc_setup(h, fft_size=None, nv=None, tucker_tol=0.0, precisions=0, max_rhs=0,
     o.tucker_tol = float(tucker_tol)
     o.precisions = int(precisions)
     o.max_rhs = int(max_rhs)
+    o.autotune = int(bool(autotune))
     _check(_lib.vc_setup(h, C.byref(o), _stream(stream)), "vc_setup")
 
 
@@ -176,6 +181,28 @@ def vc_profile_enable(h, enable=True):
 
 
 PASS_NAMES = ("zfwd_scatter", "y_forward", "x_sandwich_multiply", "y_inverse", "zinv_gather")
+
+
+def vc_tuning_report(h):
+    buf = C.create_string_buffer(8192)
+    _check(_lib.vc_tuning_report(h, buf, len(buf)), "vc_tuning_report")
+    return buf.value.decode()
+
+
+def vc_xpass_candidates(h, prec="fp64", transpose=False):
+    n = C.c_int32(0)
+    _check(_lib.vc_xpass_candidates(h, _PREC[prec], int(bool(transpose)), None, 0, C.byref(n)),
+           "vc_xpass_candidates")
+    out = (C.c_int32 * (8 * max(1, n.value)))()
+    _check(_lib.vc_xpass_candidates(h, _PREC[prec], int(bool(transpose)), out, n.value, C.byref(n)),
+           "vc_xpass_candidates")
+    rows = np.frombuffer(out, dtype=np.int32).reshape(-1, 8)[: n.value]
+    return [tuple(int(v) for v in r) for r in rows]
+
+
+def vc_xpass_set(h, cfg, prec="fp64", transpose=False, nrhs=1):
+    arr = (C.c_int32 * 8)(*[int(v) for v in cfg])
+    _check(_lib.vc_xpass_set(h, _PREC[prec], int(bool(transpose)), int(nrhs), arr), "vc_xpass_set")
 
 
 def vc_pass_times(h):
@@ -275,6 +302,17 @@ class Problem:
 
     def profile(self, enable=True):
         vc_profile_enable(self._h, enable)
+
+    def xpass_candidates(self, prec="fp64", transpose=False):
+        """Rows (nst, r0..r5, cols) of the x-pass configurations this problem can use."""
+        return vc_xpass_candidates(self._h, prec, transpose)
+
+    def xpass_set(self, cfg, prec="fp64", transpose=False, nrhs=1):
+        vc_xpass_set(self._h, cfg, prec, transpose, nrhs)
+
+    def tuning_report(self):
+        """Launch configurations of the x pass in use (and what the autotuner measured)."""
+        return vc_tuning_report(self._h)
 
     def pass_times(self):
         """(ms summed, launches, algorithmic bytes of one launch) per pass of the product."""

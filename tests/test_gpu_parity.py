@@ -117,3 +117,57 @@ def test_unit_cube_16(dev):
     C_ref = oracle.solve_capacitance(s)
     assert abs(C[0, 0] / C_ref[0, 0] - 1) < 1e-10
     assert abs(C[0, 0] / (4 * np.pi * oracle.EPS0) / 0.66068 - 1) < 0.01
+
+
+# x lengths 6 (one-stage plan), 90 (three stages) and 54 (two stages), with dielectric
+# rows so the transposed product takes the six-input variant
+XPASS_SCENES = [
+    ("x6", lambda: scenes.random_small(21, shape=(2, 6, 5), n_cond=1, n_diel=1)),
+    ("x90", lambda: scenes.random_small(23, shape=(44, 5, 4), n_cond=2, n_diel=1)),
+    ("x54", lambda: scenes.random_small(29, shape=(25, 4, 6), n_cond=2, n_diel=2)),
+]
+
+
+@pytest.mark.parametrize("name,make", XPASS_SCENES)
+def test_every_xpass_configuration_matches_dense(dev, name, make):
+    """Each launch configuration the autotuner may pick (radix plan x column tile) gives
+    the dense product of eq. (4), forward and transposed, in both precisions."""
+    s = make()
+    P = _problem(s, max_rhs=2)
+    A, po, perm = oracle_matrix_library_order(s, P.panels())
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((2, P.N))
+    xt = torch.tensor(x, device=dev)
+    nplans = set()
+    for prec, tol in (("fp64", 1e-11), ("fp32", 2e-5)):
+        for transpose in (False, True):
+            ref = ((A.T if transpose else A) @ x.T).T
+            cands = P.xpass_candidates(prec, transpose)
+            assert cands, (name, prec, transpose)
+            for cfg in cands:
+                nplans.add(cfg[0])
+                P.xpass_set(cfg, prec, transpose, nrhs=2)
+                y = P.apply(xt, transpose=transpose, prec=prec).cpu().numpy()
+                err = np.abs(y - ref).max() / np.abs(ref).max()
+                print(name, prec, "T" if transpose else "F", cfg, f"{err:.2e}", flush=True)
+                assert err < tol, (name, prec, transpose, cfg, err)
+    print(name, "stage counts covered", sorted(nplans), flush=True)
+
+
+def test_autotuned_product_matches_dense(dev):
+    s = scenes.random_small(29, shape=(25, 4, 6), n_cond=2, n_diel=2)
+    P = _problem(s, max_rhs=2, autotune=True)
+    A, po, perm = oracle_matrix_library_order(s, P.panels())
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((2, P.N))
+    xt = torch.tensor(x, device=dev)
+    for prec, tol in (("fp64", 1e-11), ("fp32", 2e-5)):
+        for transpose in (False, True):
+            ref = ((A.T if transpose else A) @ x.T).T
+            for rep in range(2):   # first call tunes, second reuses the choice
+                y = P.apply(xt, transpose=transpose, prec=prec).cpu().numpy()
+                err = np.abs(y - ref).max() / np.abs(ref).max()
+                assert err < tol, (prec, transpose, rep, err)
+    rep = P.tuning_report()
+    print(rep, flush=True)
+    assert rep.count("tuned") == 4, rep
