@@ -171,6 +171,17 @@ vc_status vc_capacitance_grad_eps(vc_problem *p, const vc_solve_opts *opts,
  * milliseconds, the number of launches, and the algorithmic bytes of ONE launch of the
  * most recent vc_apply (compulsory reads + writes of the pruned pass, counting the
  * kernel spectra once per launch); it then clears the accumulators. */
+/* The reduction of eq. (8) as a map of given charges: C_dev[i*nrhs + j] =
+ * 4 pi eps0 dv sum over the panels k of conductor i of eps_adj(k) rho[j*N + k].
+ * rho_dev: N x nrhs device doubles, column-major; C_dev: m x nrhs device doubles. */
+vc_status vc_charges_to_capacitance(vc_problem *p, const double *rho_dev, int32_t nrhs, double *C_dev,
+                                    void *hip_stream);
+
+/* Its adjoint (dC/d(charges) applied to a cotangent): grho_dev[j*N + k] =
+ * 4 pi eps0 dv eps_adj(k) gC_dev[cond(k)*nrhs + j] on conductor panels, 0 on dielectric. */
+vc_status vc_charges_to_capacitance_adjoint(vc_problem *p, const double *gC_dev, int32_t nrhs,
+                                            double *grho_dev, void *hip_stream);
+
 vc_status vc_profile_enable(vc_problem *p, int enable);
 
 /* Text report of the x-pass launch configurations in use, one line per

@@ -496,10 +496,12 @@ vc_status vc_capacitance_grad_eps(vc_problem* p, const vc_solve_opts* opts, cons
   const int m = p->m;
   const int64_t N = npanels(p);
   std::vector<double> C((size_t)m * m);
-  std::vector<double> rho;
-  vc_status s = capacitance_impl(p, opts, C.data(), nullptr, stats, &rho);
+  vc_status s = capacitance_impl(p, opts, C.data(), nullptr, stats, nullptr);
   if (s != VC_OK) return s;
   if (C_out) std::memcpy(C_out, C.data(), C.size() * sizeof(double));
+  DevMem rho;
+  VC_HIP(rho.alloc((size_t)m * N * sizeof(double)));
+  VC_HIP(hipMemcpy(rho.p, p->s_x.p, (size_t)m * N * sizeof(double), hipMemcpyDeviceToDevice));
   // adjoint solves A^T lambda_i = w_i, w_i = eps_adj on the panels of conductor i
   vc_solve_opts o = fill_defaults(opts);
   std::vector<double> W((size_t)m * N, 0.0);
@@ -508,15 +510,16 @@ vc_status vc_capacitance_grad_eps(vc_problem* p, const vc_solve_opts* opts, cons
   VC_HIP(hipMemcpy(p->s_b.p, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice));
   s = solve(p, o, 1, p->s_b.as<double>(), p->s_x.as<double>(), m, nullptr, nullptr);
   if (s != VC_OK) return mark(p, s);
-  std::vector<double> lam((size_t)m * N);
-  VC_HIP(hipMemcpy(lam.data(), p->s_x.p, lam.size() * sizeof(double), hipMemcpyDeviceToHost));
-  // dC_ij/deps_b = scale * [ sum_{k in i, adj in b} rho_kj - sum_{k diel} lam_ki dI_k/deps_b rho_kj ]
-  const double scale = 4.0 * M_PI * kEps0 * p->dv;
-  std::fill(dC, dC + (size_t)nblocks * m * m, 0.0);
+  // per-block entries of the derivative (index bookkeeping on the host, sums on the GPU):
+  //   conductor panel k: d w_{cond k} / d eps(non-conductor side block) = 1 (eq. 8)
+  //   dielectric panel k: d I_kk / d eps_lo = -4 pi eps_hi / (eps_lo - eps_hi)^2,
+  //                       d I_kk / d eps_hi = +4 pi eps_lo / (eps_lo - eps_hi)^2 (eq. 7)
   auto vox = [&](int i, int j, int k) -> int32_t {
     if (i < 0 || j < 0 || k < 0 || i >= p->nx || j >= p->ny || k >= p->nz) return -1;
     return block_of_voxel[((int64_t)i * p->ny + j) * p->nz + k];
   };
+  std::vector<std::vector<int32_t>> ek(nblocks), ec(nblocks);
+  std::vector<std::vector<double>> ef(nblocks);
   for (int64_t k = 0; k < N; ++k) {
     const vc_panel& pn = p->panels[k];
     int lo[3] = {pn.i, pn.j, pn.k};
@@ -526,21 +529,63 @@ vc_status vc_capacitance_grad_eps(vc_problem* p, const vc_solve_opts* opts, cons
     if (pn.kind == 0) {
       const int32_t b = pn.eps_lo == 0.0 ? bhi : blo;   // non-conductor side
       if (b < 0 || b >= nblocks) continue;
-      for (int j = 0; j < m; ++j) dC[((size_t)b * m + pn.cond) * m + j] += scale * rho[(size_t)j * N + k];
+      ek[b].push_back((int32_t)k); ec[b].push_back(pn.cond); ef[b].push_back(1.0);
     } else {
       const double el = pn.eps_lo, eh = pn.eps_hi, dd = (el - eh) * (el - eh);
-      const double dlo = -4.0 * M_PI * eh / dd, dhi = 4.0 * M_PI * el / dd;
+      const double d[2] = {-4.0 * M_PI * eh / dd, 4.0 * M_PI * el / dd};
       for (int side = 0; side < 2; ++side) {
         const int32_t b = side == 0 ? blo : bhi;
         if (b < 0 || b >= nblocks) continue;
-        const double dI = side == 0 ? dlo : dhi;
-        for (int i = 0; i < m; ++i) {
-          const double li = lam[(size_t)i * N + k] * dI * scale;
-          for (int j = 0; j < m; ++j) dC[((size_t)b * m + i) * m + j] -= li * rho[(size_t)j * N + k];
-        }
+        ek[b].push_back((int32_t)k); ec[b].push_back(-1); ef[b].push_back(d[side]);
       }
     }
   }
+  std::vector<int32_t> bptr(nblocks + 1, 0), fk, fc;
+  std::vector<double> ff;
+  for (int b = 0; b < nblocks; ++b) {
+    fk.insert(fk.end(), ek[b].begin(), ek[b].end());
+    fc.insert(fc.end(), ec[b].begin(), ec[b].end());
+    ff.insert(ff.end(), ef[b].begin(), ef[b].end());
+    bptr[b + 1] = (int32_t)fk.size();
+  }
+  DevMem d_bptr, d_k, d_c, d_f, d_dC;
+  VC_HIP(d_bptr.alloc(bptr.size() * sizeof(int32_t)));
+  VC_HIP(d_k.alloc(std::max<size_t>(1, fk.size()) * sizeof(int32_t)));
+  VC_HIP(d_c.alloc(std::max<size_t>(1, fc.size()) * sizeof(int32_t)));
+  VC_HIP(d_f.alloc(std::max<size_t>(1, ff.size()) * sizeof(double)));
+  VC_HIP(d_dC.alloc((size_t)nblocks * m * m * sizeof(double)));
+  VC_HIP(hipMemcpy(d_bptr.p, bptr.data(), bptr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (!fk.empty()) {
+    VC_HIP(hipMemcpy(d_k.p, fk.data(), fk.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    VC_HIP(hipMemcpy(d_c.p, fc.data(), fc.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    VC_HIP(hipMemcpy(d_f.p, ff.data(), ff.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  VC_HIP(launch_grad_eps(d_bptr.as<int32_t>(), d_k.as<int32_t>(), d_c.as<int32_t>(), d_f.as<double>(),
+                         rho.as<double>(), p->s_x.as<double>(), N, m, nblocks, 4.0 * M_PI * kEps0 * p->dv,
+                         d_dC.as<double>(), nullptr));
+  VC_HIP(hipMemcpy(dC, d_dC.p, (size_t)nblocks * m * m * sizeof(double), hipMemcpyDeviceToHost));
+  return VC_OK;
+}
+
+vc_status vc_charges_to_capacitance(vc_problem* p, const double* rho_dev, int32_t nrhs, double* C_dev, void* stream) {
+  VC_CHECK_PROBLEM(p);
+  if (!p->setup_done) { set_error("vc_setup first"); return VC_ERR_STATE; }
+  if (!rho_dev || !C_dev || nrhs <= 0) { set_error("bad arguments"); return VC_ERR_ARG; }
+  VC_HIP(hipSetDevice(p->device));
+  VC_HIP(launch_cap_reduce_n(rho_dev, npanels(p), p->m, nrhs, p->d_cond_panels.as<int32_t>(),
+                             p->d_cond_ptr.as<int32_t>(), p->d_weight.as<double>(), 4.0 * M_PI * kEps0 * p->dv, C_dev,
+                             (hipStream_t)stream));
+  return VC_OK;
+}
+
+vc_status vc_charges_to_capacitance_adjoint(vc_problem* p, const double* gC_dev, int32_t nrhs, double* grho_dev,
+                                            void* stream) {
+  VC_CHECK_PROBLEM(p);
+  if (!p->setup_done) { set_error("vc_setup first"); return VC_ERR_STATE; }
+  if (!gC_dev || !grho_dev || nrhs <= 0) { set_error("bad arguments"); return VC_ERR_ARG; }
+  VC_HIP(hipSetDevice(p->device));
+  VC_HIP(launch_cap_reduce_adj(gC_dev, npanels(p), nrhs, p->d_pcond.as<int32_t>(), p->d_weight.as<double>(),
+                               4.0 * M_PI * kEps0 * p->dv, grho_dev, (hipStream_t)stream));
   return VC_OK;
 }
 

@@ -137,4 +137,13 @@ hipError_t launch_cap_reduce(const double* rho, int64_t N, int m, const int32_t*
                              const int32_t* cond_ptr, const double* weight, double scale, double* C,
                              hipStream_t st);
 
+hipError_t launch_cap_reduce_n(const double* rho, int64_t N, int m, int nrhs, const int32_t* cond_panels,
+                               const int32_t* cond_ptr, const double* weight, double scale, double* C,
+                               hipStream_t st);
+hipError_t launch_cap_reduce_adj(const double* gC, int64_t N, int nrhs, const int32_t* pcond, const double* weight,
+                                 double scale, double* grho, hipStream_t st);
+hipError_t launch_grad_eps(const int32_t* bptr, const int32_t* ek, const int32_t* econd, const double* ecoef,
+                           const double* rho, const double* lam, int64_t N, int m, int nblocks, double scale,
+                           double* dC, hipStream_t st);
+
 }  // namespace vc

@@ -101,6 +101,7 @@ struct vc_problem {
   double extract_resid = 0.0;
   // device mirrors
   vc::DevMem d_line_ptr, d_items, d_lflag, d_pflag, d_pk, d_pkind, d_diag, d_cond_ptr, d_cond_panels, d_weight, d_gl;
+  vc::DevMem d_pcond;               // conductor id per panel (-1 on dielectric panels)
   vc::PrecTables t64, t32;
   vc::DevMem work_F, work_O;        // spectral work arrays (sized for FP64, reused by FP32)
   int64_t rhs_stride = 0, comp_stride = 0;

@@ -160,6 +160,11 @@ vc_status build_spectra(vc_problem* P, int want64, int want32, hipStream_t st) {
   if ((s = upload(P->d_cond_ptr, P->cond_ptr)) != VC_OK) return s;
   if ((s = upload(P->d_cond_panels, P->cond_panels)) != VC_OK) return s;
   if ((s = upload(P->d_weight, P->weight)) != VC_OK) return s;
+  {
+    std::vector<int32_t> pc(P->panels.size());
+    for (size_t k = 0; k < pc.size(); ++k) pc[k] = P->panels[k].kind == 0 ? P->panels[k].cond : -1;
+    if ((s = upload(P->d_pcond, pc)) != VC_OK) return s;
+  }
   std::vector<double> gl;
   gauss_legendre_table(gl);
   if ((s = upload(P->d_gl, gl)) != VC_OK) return s;

@@ -225,4 +225,81 @@ hipError_t launch_cap_reduce(const double* rho, int64_t N, int m, const int32_t*
   return hipGetLastError();
 }
 
+// C = scale * W^T rho for nrhs columns (eq. 8): C[i, j] over the panels of conductor i
+__global__ void __launch_bounds__(kRedThreads)
+k_cap_reduce_n(const double* __restrict__ rho, int64_t N, int nrhs, const int32_t* __restrict__ cond_panels,
+               const int32_t* __restrict__ cond_ptr, const double* __restrict__ weight, double scale,
+               double* __restrict__ C) {
+  __shared__ double red[kRedThreads];
+  const int i = blockIdx.x, j = blockIdx.y;
+  double acc = 0.0;
+  for (int t = cond_ptr[i] + threadIdx.x; t < cond_ptr[i + 1]; t += blockDim.x) {
+    const int k = cond_panels[t];
+    acc += weight[k] * rho[(int64_t)j * N + k];
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) C[(int64_t)i * nrhs + j] = scale * acc;
+}
+
+hipError_t launch_cap_reduce_n(const double* rho, int64_t N, int m, int nrhs, const int32_t* cond_panels,
+                               const int32_t* cond_ptr, const double* weight, double scale, double* C,
+                               hipStream_t st) {
+  if (m <= 0 || nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cap_reduce_n, dim3(m, nrhs), dim3(kRedThreads), 0, st, rho, N, nrhs, cond_panels, cond_ptr,
+                     weight, scale, C);
+  return hipGetLastError();
+}
+
+// adjoint of the reduction: g_rho[k, j] = scale * w_k * g_C[cond_k, j] (0 on dielectric panels)
+__global__ void k_cap_reduce_adj(const double* __restrict__ gC, int64_t N, int nrhs, const int32_t* __restrict__ pcond,
+                                 const double* __restrict__ weight, double scale, double* __restrict__ grho) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (k >= N) return;
+  const int ci = pcond[k];
+  grho[(int64_t)j * N + k] = ci >= 0 ? scale * weight[k] * gC[(int64_t)ci * nrhs + j] : 0.0;
+}
+
+hipError_t launch_cap_reduce_adj(const double* gC, int64_t N, int nrhs, const int32_t* pcond, const double* weight,
+                                 double scale, double* grho, hipStream_t st) {
+  if (N <= 0 || nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cap_reduce_adj, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, gC, N, nrhs, pcond,
+                     weight, scale, grho);
+  return hipGetLastError();
+}
+
+// dC[b, i, j] = scale * sum over the entries e of block b of
+//   cond_e >= 0 (free-charge weight term):  [i == cond_e] rho[k_e, j]
+//   cond_e <  0 (jump term, eq. 7):         -coef_e lam[k_e, i] rho[k_e, j]
+// one workgroup per (b, i, j); deterministic reduction order
+__global__ void __launch_bounds__(kRedThreads)
+k_grad_eps(const int32_t* __restrict__ bptr, const int32_t* __restrict__ ek, const int32_t* __restrict__ econd,
+           const double* __restrict__ ecoef, const double* __restrict__ rho, const double* __restrict__ lam,
+           int64_t N, int m, double scale, double* __restrict__ dC) {
+  __shared__ double red[kRedThreads];
+  const int b = blockIdx.x, i = blockIdx.y, j = blockIdx.z;
+  double acc = 0.0;
+  for (int t = bptr[b] + threadIdx.x; t < bptr[b + 1]; t += blockDim.x) {
+    const int64_t k = ek[t];
+    const int ce = econd[t];
+    const double r = rho[(int64_t)j * N + k];
+    if (ce >= 0) {
+      if (ce == i) acc += r;
+    } else {
+      acc -= ecoef[t] * lam[(int64_t)i * N + k] * r;
+    }
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) dC[((int64_t)b * m + i) * m + j] = scale * acc;
+}
+
+hipError_t launch_grad_eps(const int32_t* bptr, const int32_t* ek, const int32_t* econd, const double* ecoef,
+                           const double* rho, const double* lam, int64_t N, int m, int nblocks, double scale,
+                           double* dC, hipStream_t st) {
+  if (nblocks <= 0 || m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_grad_eps, dim3(nblocks, m, m), dim3(kRedThreads), 0, st, bptr, ek, econd, ecoef, rho, lam, N,
+                     m, scale, dC);
+  return hipGetLastError();
+}
+
 }  // namespace vc

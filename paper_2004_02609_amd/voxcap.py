@@ -79,6 +79,8 @@ _sig = {
     "vc_profile_enable": (C.c_int, [_P, C.c_int]),
     "vc_pass_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "vc_tuning_report": (C.c_int, [_P, C.c_char_p, C.c_int32]),
+    "vc_charges_to_capacitance": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
+    "vc_charges_to_capacitance_adjoint": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
     "vc_xpass_candidates": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int32), C.c_int32,
                                       C.POINTER(C.c_int32)]),
     "vc_xpass_set": (C.c_int, [_P, C.c_int, C.c_int, C.c_int32, C.POINTER(C.c_int32)]),
@@ -181,6 +183,16 @@ def vc_profile_enable(h, enable=True):
 
 
 PASS_NAMES = ("zfwd_scatter", "y_forward", "x_sandwich_multiply", "y_inverse", "zinv_gather")
+
+
+def vc_charges_to_capacitance(h, rho, C_out, nrhs, stream=None):
+    _check(_lib.vc_charges_to_capacitance(h, _ptr(rho), int(nrhs), _ptr(C_out), _stream(stream)),
+           "vc_charges_to_capacitance")
+
+
+def vc_charges_to_capacitance_adjoint(h, gC, grho, nrhs, stream=None):
+    _check(_lib.vc_charges_to_capacitance_adjoint(h, _ptr(gC), int(nrhs), _ptr(grho), _stream(stream)),
+           "vc_charges_to_capacitance_adjoint")
 
 
 def vc_tuning_report(h):
