@@ -256,6 +256,11 @@ def main():
             solve[mode] = {"time_s": t, "iters": st["iters"], "ir_steps": st["ir_steps"],
                            "max_rel_err_vs_fp64_1e-12": err, "products": st["mvp_count"]}
         solve["speedup_mixed_vs_fp64"] = solve["fp64"]["time_s"] / solve["mixed"]["time_s"]
+        # the same FP64 solve with the restart cycle's kernels issued one by one
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.capacitance(prec="fp64", rtol=1e-9, graph=False)
+        solve["fp64_no_graph_time_s"] = time.perf_counter() - t0
 
     cpu = None
     if not args.no_cpu:

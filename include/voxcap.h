@@ -113,6 +113,9 @@ typedef struct {
   double inner_rtol;
   int32_t ir_max;
   int32_t use_precond;   /* 1 = block-diagonal-diagonal (default), 0 = none, 2 = diagonal only */
+  int32_t graph;         /* 0: each restart cycle runs on the device without host round trips
+                            and, after the first, is replayed as one captured hipGraph
+                            (default); 1: the same kernels issued one by one             */
 } vc_solve_opts;
 
 typedef struct {

@@ -111,7 +111,8 @@ bool sandwich_default(int L, int elem, int nin, int n1x, size_t budget, SandCfg*
 }
 
 template <typename T>
-static vc_status run_apply(vc_problem* P, int transpose, const double* x, double* y, int nrhs, hipStream_t st) {
+static vc_status run_apply(vc_problem* P, int transpose, const double* x, double* y, int nrhs, hipStream_t st,
+                           const int* skip) {
   PrecTables& tb = (sizeof(T) == 8) ? P->t64 : P->t32;
   const int n1x = P->n1[0], n1y = P->n1[1];
   const int Mx = P->M[0], My = P->M[1];
@@ -133,18 +134,21 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
   const uint8_t* pflag = P->d_pflag.as<uint8_t>();
   int ncol, nthr;
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  if (P->prof) {
+  hipStreamCaptureStatus capst = hipStreamCaptureStatusNone;
+  VC_HIP(hipStreamIsCapturing(st, &capst));
+  const bool prof = P->prof && capst == hipStreamCaptureStatusNone;   // no timing events inside a graph
+  if (prof) {
     for (int i = 0; i < 6; ++i)
       if (!(ev[i] = take_event(P))) { set_error("hipEventCreate failed"); return VC_ERR_HIP; }
     VC_HIP(hipEventRecord(ev[0], st));
     pass_byte_model(P, transpose, (int)sizeof(T), nrhs, P->pass_bytes);
   }
 #define VC_MARK(i) \
-  if (P->prof) VC_HIP(hipEventRecord(ev[i], st))
+  if (prof) VC_HIP(hipEventRecord(ev[i], st))
   // 1. scatter + z transform
   if (!pick_tile(P->M[2], eb, Tune<T>::emax, nitems, &ncol, &nthr, budget, transpose ? nrhs : (nrhs + 1) / 2)) return VC_ERR_ARG;
   VC_HIP(launch_zfwd<T>(x, N, nrhs, transpose ? 1 : 0, items, nitems, lptr, pk, pkind, F, cs, rs, n1x, n1y, My, H,
-                        tb.ax[2].plan, tb.ax[2].tw.p, ncol, nthr, st));
+                        tb.ax[2].plan, tb.ax[2].tw.p, ncol, nthr, skip, st));
   VC_MARK(1);
   // 2. y transform of the input components
   CompSet cin{};
@@ -158,6 +162,7 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
   StridedArgs sa{};
   sa.comp_stride = cs; sa.rhs_stride = rs; sa.plane_stride = (int64_t)My * H; sa.row_stride = H;
   sa.ncols = H; sa.nrhs = nrhs; sa.n1x = n1x; sa.n1y = n1y;
+  sa.skip = skip;
   if (!pick_tile(My, eb, Tune<T>::emax, H, &ncol, &nthr, budget, (int64_t)n1x * cin.n * nrhs)) return VC_ERR_ARG;
   sa.ncol = ncol; sa.nin = n1y; sa.nout = My; sa.inverse = 0;
   VC_HIP(launch_strided<T>(F, sa, cin, n1x, tb.ax[1].plan, tb.ax[1].tw.p, lflag, pflag, nthr, st));
@@ -169,6 +174,7 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
   xa.oddmask = 0;
   for (int q = 0; q < 15; ++q) xa.oddmask |= (uint64_t)pair_odd_bits(q) << (3 * q);
   xa.adjoint = transpose;
+  xa.skip = skip;
   CompSet cout{};
   if (!transpose) {
     xa.nin = 3;
@@ -242,36 +248,37 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
   // 5. inverse z transform + gather + jump term
   if (!pick_tile(P->M[2], eb, Tune<T>::emax, nitems, &ncol, &nthr, budget, transpose ? (nrhs + 1) / 2 : nrhs)) return VC_ERR_ARG;
   VC_HIP(launch_zinv<T>(O, y, x, N, nrhs, transpose ? 1 : 0, items, nitems, lptr, pk, pkind, P->d_diag.as<double>(),
-                        lflag, cs, rs, n1x, n1y, My, H, tb.ax[2].plan, tb.ax[2].tw.p, ncol, nthr, st));
+                        lflag, cs, rs, n1x, n1y, My, H, tb.ax[2].plan, tb.ax[2].tw.p, ncol, nthr, skip, st));
   VC_MARK(5);
 #undef VC_MARK
-  if (P->prof) P->ev_pending.push_back(std::vector<hipEvent_t>(ev, ev + 6));
+  if (prof) P->ev_pending.push_back(std::vector<hipEvent_t>(ev, ev + 6));
   P->mvp_count++;
   return VC_OK;
 }
 
 vc_status apply_op(vc_problem* P, int transpose, vc_precision prec, const double* x, double* y, int nrhs,
-                   hipStream_t st) {
+                   hipStream_t st, const int* skip) {
   if (prec == VC_FP32) {
     if (!P->have32) { set_error("FP32 spectra were not built at setup"); return VC_ERR_STATE; }
-    return run_apply<float>(P, transpose, x, y, nrhs, st);
+    return run_apply<float>(P, transpose, x, y, nrhs, st, skip);
   }
   if (!P->have64) { set_error("FP64 spectra were not built at setup"); return VC_ERR_STATE; }
-  return run_apply<double>(P, transpose, x, y, nrhs, st);
+  return run_apply<double>(P, transpose, x, y, nrhs, st, skip);
 }
 
-vc_status apply_precond(vc_problem* P, int transpose, const double* x, double* y, int nrhs, hipStream_t st) {
+vc_status apply_precond(vc_problem* P, int transpose, const double* x, double* y, int nrhs, hipStream_t st,
+                        const int* skip) {
   (void)transpose;   // the blocks of eq. (5) are symmetric and the diagonal is its own transpose
   const int64_t N = npanels(P);
   Precond& pc = P->pc;
   if (pc.mode == 2) {
-    VC_HIP(launch_diag_scale(x, y, pc.dinv_diag.as<double>(), N, nrhs, st));
+    VC_HIP(launch_diag_scale(x, y, pc.dinv_diag.as<double>(), N, nrhs, skip, st));
     return VC_OK;
   }
-  VC_HIP(launch_diag_scale(x, y, pc.dinv.as<double>(), N, nrhs, st));
+  VC_HIP(launch_diag_scale(x, y, pc.dinv.as<double>(), N, nrhs, skip, st));
   VC_HIP(launch_block_apply(x, y, N, nrhs, pc.box_ptr.as<int32_t>(), pc.box_panels.as<int32_t>(),
                             pc.box_block.as<int32_t>(), pc.block_off.as<int64_t>(), pc.block_n.as<int32_t>(),
-                            pc.blocks.as<double>(), pc.nbox, st));
+                            pc.blocks.as<double>(), pc.nbox, skip, st));
   return VC_OK;
 }
 

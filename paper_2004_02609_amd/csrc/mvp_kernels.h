@@ -36,6 +36,7 @@ struct StridedArgs {
   int inverse;
   int n1x, n1y;   // flag array extents (planes x rows)
   int lgc;        // log2(ncol), set by the launcher
+  const int* skip;   // optional device flag: when set, the launch does nothing
 };
 
 struct SandArgs {
@@ -51,6 +52,7 @@ struct SandArgs {
   uint32_t radpack;
   // bits 3q..3q+2: stored spectrum of pair q is odd under k_a -> M_a - k_a (bit a)
   uint64_t oddmask;
+  const int* skip;   // optional device flag: when set, the launch does nothing
 };
 // dynamic LDS of the sandwich: twiddle table + one [L][ncol+1] tile + 3 n1x plane flags
 inline size_t sandwich_lds_bytes(int L, int ncol, int elem, int n1x) {
@@ -67,7 +69,7 @@ template <typename T>
 hipError_t launch_zfwd(const double* x, int64_t N, int nrhs, int mode, const int32_t* items, int nitems,
                        const int32_t* line_ptr, const int32_t* pk, const int8_t* pkind, void* F, int64_t comp_stride,
                        int64_t rhs_stride, int n1x, int n1y, int My, int H, const AxisPlan& pl, const void* tw, int ncol,
-                       int nthr, hipStream_t st);
+                       int nthr, const int* skip, hipStream_t st);
 template <typename T>
 hipError_t launch_strided(void* data, const StridedArgs& a, const CompSet& cs, int nplanes, const AxisPlan& pl,
                           const void* tw, const uint8_t* lflag, const uint8_t* pflag, int nthr, hipStream_t st);
@@ -93,7 +95,7 @@ hipError_t launch_zinv(const void* O, double* y, const double* x, int64_t N, int
                        int nitems, const int32_t* line_ptr, const int32_t* pk, const int8_t* pkind,
                        const double* diag, const uint8_t* lflag, int64_t comp_stride, int64_t rhs_stride, int n1x,
                        int n1y, int My, int H, const AxisPlan& pl, const void* tw, int ncol, int nthr,
-                       hipStream_t st);
+                       const int* skip, hipStream_t st);
 
 // setup kernels (setup_kernels.hip)
 struct FillArgs {
@@ -124,15 +126,33 @@ int64_t gemv_t_partial_size(int64_t N, int kmax, int nrhs);
 hipError_t launch_gemv_n_sub(const double* V, int64_t ldv, int64_t N, int k, const double* h, int64_t ldh,
                              double* w, int64_t ldw, int nrhs, const int* active, int accumulate_into_h2,
                              hipStream_t st);
-hipError_t launch_colnorm(const double* w, int64_t ldw, int64_t N, int nrhs, double* out, hipStream_t st);
+hipError_t launch_colnorm(const double* w, int64_t ldw, int64_t N, int nrhs, double* out, double* partial,
+                          hipStream_t st);
+int64_t colnorm_partial_size(int64_t N, int nrhs);
 hipError_t launch_scale_cols(double* w, int64_t ldw, int64_t N, int nrhs, const double* s, int mode,
                              hipStream_t st);
 hipError_t launch_axpy_cols(double* y, const double* x, int64_t N, int nrhs, const double* a, int sub,
                             hipStream_t st);
-hipError_t launch_diag_scale(const double* x, double* y, const double* dinv, int64_t N, int nrhs, hipStream_t st);
+hipError_t launch_diag_scale(const double* x, double* y, const double* dinv, int64_t N, int nrhs, const int* skip,
+                             hipStream_t st);
 hipError_t launch_block_apply(const double* x, double* y, int64_t N, int nrhs, const int32_t* box_ptr,
                               const int32_t* box_panels, const int32_t* box_block, const int64_t* block_off,
-                              const int32_t* block_n, const double* blocks, int nbox, hipStream_t st);
+                              const int32_t* block_n, const double* blocks, int nbox, const int* skip,
+                              hipStream_t st);
+// device-side GMRES cycle (one thread per right-hand side, nrhs <= 64)
+hipError_t launch_cycle_start(int nrhs, int m, const double* rn, const double* bn, const double* rtol, int* act_cycle,
+                              int* act_step, double* g, double* scal, int* kd, int* skip, double* rre_out,
+                              hipStream_t st);
+hipError_t launch_arnoldi(int j, int nrhs, int m, const double* h1, const double* h2, int ldh, const double* hn,
+                          double* H, double* cs, double* sn, double* g, const double* bn, const double* rtol,
+                          int* act_step, int* kd, int* iters, double* scal, int* skip, int* bad, hipStream_t st);
+hipError_t launch_backsolve(int nrhs, int m, const double* H, const double* g, const int* kd, const int* act_cycle,
+                            double* y, int ldy, hipStream_t st);
+hipError_t launch_scale_copy(double* dst, const double* src, int64_t N, int nrhs, const double* s, const int* skip,
+                             hipStream_t st);
+hipError_t launch_zero(double* p, int64_t n, hipStream_t st);
+hipError_t launch_add_active(double* x, const double* z, int64_t N, int nrhs, const int* act, const int* skip,
+                             hipStream_t st);
 hipError_t launch_cap_reduce(const double* rho, int64_t N, int m, const int32_t* cond_panels,
                              const int32_t* cond_ptr, const double* weight, double scale, double* C,
                              hipStream_t st);

@@ -27,7 +27,8 @@ __global__ void __launch_bounds__(1024)
 k_zfwd(const double* __restrict__ x, int64_t N, int nrhs, int mode, const int32_t* __restrict__ items, int nitems,
        const int32_t* __restrict__ line_ptr, const int32_t* __restrict__ pk, const int8_t* __restrict__ pkind,
        C2<T>* __restrict__ F, int64_t comp_stride, int64_t rhs_stride, int n1x, int n1y, int My, int H, AxisPlan pl,
-       const C2<T>* __restrict__ twg, int lgc) {
+       const C2<T>* __restrict__ twg, int lgc, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   extern __shared__ char smem_raw[];
   const int L = pl.L;
   const int ncol = 1 << lgc, ncolp = ncol + 1;
@@ -92,6 +93,7 @@ template <typename T, int EMAX>
 __global__ void __launch_bounds__(1024)
 k_strided(C2<T>* __restrict__ data, StridedArgs a, CompSet cs, AxisPlan pl, const C2<T>* __restrict__ twg,
           const uint8_t* __restrict__ lflag, const uint8_t* __restrict__ pflag) {
+  if (a.skip && *a.skip) return;
   extern __shared__ char smem_raw[];
   const int L = pl.L;
   const int lgc = a.lgc, ncol = 1 << lgc, ncolp = ncol + 1, cmask = ncol - 1;
@@ -138,7 +140,8 @@ k_zinv(const C2<T>* __restrict__ O, double* __restrict__ y, const double* __rest
        int mode, const int32_t* __restrict__ items, int nitems, const int32_t* __restrict__ line_ptr,
        const int32_t* __restrict__ pk, const int8_t* __restrict__ pkind, const double* __restrict__ diag,
        const uint8_t* __restrict__ lflag, int64_t comp_stride, int64_t rhs_stride, int n1x, int n1y, int My, int H,
-       AxisPlan pl, const C2<T>* __restrict__ twg, int lgc) {
+       AxisPlan pl, const C2<T>* __restrict__ twg, int lgc, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   extern __shared__ char smem_raw[];
   const int L = pl.L;
   const int ncol = 1 << lgc, ncolp = ncol + 1;
@@ -216,12 +219,12 @@ template <typename T>
 hipError_t launch_zfwd(const double* x, int64_t N, int nrhs, int mode, const int32_t* items, int nitems,
                        const int32_t* line_ptr, const int32_t* pk, const int8_t* pkind, void* F, int64_t comp_stride,
                        int64_t rhs_stride, int n1x, int n1y, int My, int H, const AxisPlan& pl, const void* tw, int ncol,
-                       int nthr, hipStream_t st) {
+                       int nthr, const int* skip, hipStream_t st) {
   if (nitems == 0) return hipSuccess;
   dim3 grid((nitems + ncol - 1) / ncol, mode == 0 ? (nrhs + 1) / 2 : nrhs);
   hipLaunchKernelGGL((k_zfwd<T, Tune<T>::emax>), grid, dim3(nthr), lds_bytes<T>(pl.L, ncol), st, x, N, nrhs, mode, items,
                      nitems, line_ptr, pk, pkind, (C2<T>*)F, comp_stride, rhs_stride, n1x, n1y, My, H, pl,
-                     (const C2<T>*)tw, ilog2(ncol));
+                     (const C2<T>*)tw, ilog2(ncol), skip);
   return hipGetLastError();
 }
 
@@ -277,19 +280,19 @@ hipError_t launch_zinv(const void* O, double* y, const double* x, int64_t N, int
                        int nitems, const int32_t* line_ptr, const int32_t* pk, const int8_t* pkind,
                        const double* diag, const uint8_t* lflag, int64_t comp_stride, int64_t rhs_stride, int n1x,
                        int n1y, int My, int H, const AxisPlan& pl, const void* tw, int ncol, int nthr,
-                       hipStream_t st) {
+                       const int* skip, hipStream_t st) {
   if (nitems == 0) return hipSuccess;
   dim3 grid((nitems + ncol - 1) / ncol, mode == 0 ? nrhs : (nrhs + 1) / 2);
   hipLaunchKernelGGL((k_zinv<T, Tune<T>::emax>), grid, dim3(nthr), lds_bytes<T>(pl.L, ncol), st, (const C2<T>*)O, y, x, N,
                      nrhs, mode, items, nitems, line_ptr, pk, pkind, diag, lflag, comp_stride, rhs_stride, n1x, n1y,
-                     My, H, pl, (const C2<T>*)tw, ilog2(ncol));
+                     My, H, pl, (const C2<T>*)tw, ilog2(ncol), skip);
   return hipGetLastError();
 }
 
 #define VC_INST(T)                                                                                                \
   template hipError_t launch_zfwd<T>(const double*, int64_t, int, int, const int32_t*, int, const int32_t*,        \
                                      const int32_t*, const int8_t*, void*, int64_t, int64_t, int, int, int, int,   \
-                                     const AxisPlan&, const void*, int, int, hipStream_t);                         \
+                                     const AxisPlan&, const void*, int, int, const int*, hipStream_t);             \
   template hipError_t launch_strided<T>(void*, const StridedArgs&, const CompSet&, int, const AxisPlan&,          \
                                         const void*, const uint8_t*, const uint8_t*, int, hipStream_t);            \
   template hipError_t launch_sandwich<T>(const void*, void*, const void*, const SandArgs&, const void*, const void*, \
@@ -297,7 +300,7 @@ hipError_t launch_zinv(const void* O, double* y, const double* x, int64_t N, int
   template hipError_t launch_zinv<T>(const void*, double*, const double*, int64_t, int, int, const int32_t*, int, \
                                      const int32_t*, const int32_t*, const int8_t*, const double*, const uint8_t*, \
                                      int64_t, int64_t, int, int, int, int, const AxisPlan&, const void*, int, int, \
-                                     hipStream_t);
+                                     const int*, hipStream_t);
 VC_INST(float)
 VC_INST(double)
 

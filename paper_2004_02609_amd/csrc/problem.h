@@ -108,8 +108,47 @@ struct vc_problem {
   int ncomp_F = 0, ncomp_O = 0;
   vc::Precond pc;
   // solver workspace
-  vc::DevMem s_V, s_w, s_z, s_r, s_b, s_x, s_h, s_partial, s_norm, s_active, s_tmp, s_y2;
+  vc::DevMem s_V, s_w, s_z, s_r, s_b, s_x, s_h, s_partial, s_norm, s_active, s_tmp, s_y2, s_rr, s_dd;
+  vc::DevMem s_cyc, s_cyci;         // device-side GMRES cycle state (doubles, ints)
   int s_restart = 0, s_nrhs = 0;
+  // restart cycles captured as graphs, keyed by what their kernel arguments bake in
+  bool use_graphs = true;
+  struct GraphKey {
+    int mvp, transpose, precond, nrhs, restart;
+    const double* b;
+    double* x;
+    bool operator==(const GraphKey& o) const {
+      return mvp == o.mvp && transpose == o.transpose && precond == o.precond && nrhs == o.nrhs &&
+             restart == o.restart && b == o.b && x == o.x;
+    }
+  };
+  struct GraphEntry {
+    GraphKey key;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  hipGraphExec_t find_graph(const GraphKey& k) const {
+    for (const auto& e : graphs)
+      if (e.key == k) return e.exec;
+    return nullptr;
+  }
+  void add_graph(const GraphKey& k, hipGraph_t g, hipGraphExec_t e) {
+    if (graphs.size() >= 8) {   // bounded cache: drop the oldest
+      (void)hipGraphExecDestroy(graphs.front().exec);
+      (void)hipGraphDestroy(graphs.front().graph);
+      graphs.erase(graphs.begin());
+    }
+    graphs.push_back(GraphEntry{k, g, e});
+  }
+  void drop_graphs() {
+    for (auto& e : graphs) {
+      (void)hipGraphExecDestroy(e.exec);
+      (void)hipGraphDestroy(e.graph);
+    }
+    graphs.clear();
+  }
+  hipStream_t solve_stream = nullptr;   // blocking stream of the solves (graphs cannot use the null stream)
   int mvp_count = 0;
   // x-pass launch configuration per (precision, direction, nrhs) key
   bool autotune = false;
@@ -126,6 +165,8 @@ struct vc_problem {
   std::vector<std::vector<hipEvent_t>> ev_pending;
   double pass_bytes[5] = {0, 0, 0, 0, 0};
   ~vc_problem() {
+    drop_graphs();
+    if (solve_stream) (void)hipStreamDestroy(solve_stream);
     for (auto& v : ev_pending)
       for (hipEvent_t e : v) (void)hipEventDestroy(e);
     for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
@@ -139,8 +180,9 @@ vc_status choose_sizes(vc_problem* p, const int32_t* fft_size);
 vc_status build_spectra(vc_problem* p, int want64, int want32, hipStream_t st);
 vc_status build_precond(vc_problem* p, hipStream_t st);
 vc_status apply_op(vc_problem* p, int transpose, vc_precision prec, const double* x, double* y, int nrhs,
-                   hipStream_t st);
-vc_status apply_precond(vc_problem* p, int transpose, const double* x, double* y, int nrhs, hipStream_t st);
+                   hipStream_t st, const int* skip = nullptr);
+vc_status apply_precond(vc_problem* p, int transpose, const double* x, double* y, int nrhs, hipStream_t st,
+                        const int* skip = nullptr);
 AxisPlan make_plan(int L, int max_radix);
 bool pick_tile(int L, int elem_bytes, int emax, int ncols_total, int* ncol, int* nthr, size_t budget,
                int64_t other_blocks, int max_thr = 1024);

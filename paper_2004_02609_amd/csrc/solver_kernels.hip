@@ -10,7 +10,6 @@
 namespace vc {
 
 constexpr int kRedThreads = 256;
-constexpr int kChunk = 8192;   // rows per partial-sum block
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
   red[threadIdx.x] = v;
@@ -24,27 +23,55 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return r;
 }
 
-// partial[(chunk*nrhs + r)*k + i] = sum_{n in chunk} V_i[r][n] * w[r][n]
+// Inner products for Gram-Schmidt.  Work is split over (row chunk, block of 8 basis
+// vectors, right-hand side): each thread keeps 8 running sums over its rows (w read once
+// per block), the wave sums them with shuffles and the waves through LDS, in a fixed
+// order.  partial[(chunk*nrhs + r)*k + i] = sum_{n in chunk} V_i[r][n] * w[r][n].
+constexpr int kDotChunk = 2048;   // rows per partial sum
+constexpr int kDotBlk = 8;        // basis vectors per workgroup
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 __global__ void __launch_bounds__(kRedThreads)
 k_dot_partial(const double* __restrict__ V, int64_t ldv, int64_t N, int k, const double* __restrict__ w,
               int64_t ldw, int nrhs, double* __restrict__ partial, const int* __restrict__ active) {
-  __shared__ double red[kRedThreads];
-  const int chunk = blockIdx.x, r = blockIdx.y;
-  const int64_t n0 = (int64_t)chunk * kChunk;
-  const int64_t n1 = n0 + kChunk < N ? n0 + kChunk : N;
-  double* out = partial + ((int64_t)chunk * nrhs + r) * k;
+  __shared__ double red[kDotBlk][kRedThreads / 64];
+  const int chunk = blockIdx.x, kb = blockIdx.y, r = blockIdx.z;
+  const int i0 = kb * kDotBlk;
+  const int nb = k - i0 < kDotBlk ? k - i0 : kDotBlk;
+  double* out = partial + ((int64_t)chunk * nrhs + r) * k + i0;
   if (active && !active[r]) {
-    if (threadIdx.x == 0)
-      for (int i = 0; i < k; ++i) out[i] = 0.0;
+    if ((int)threadIdx.x < nb) out[threadIdx.x] = 0.0;
     return;
   }
+  const int64_t n0 = (int64_t)chunk * kDotChunk;
+  const int64_t n1 = n0 + kDotChunk < N ? n0 + kDotChunk : N;
   const double* wr = w + (int64_t)r * ldw;
-  for (int i = 0; i < k; ++i) {
-    const double* vi = V + (int64_t)i * ldv + (int64_t)r * N;
-    double acc = 0.0;
-    for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) acc += vi[n] * wr[n];
-    acc = block_sum(acc, red);
-    if (threadIdx.x == 0) out[i] = acc;
+  const double* v0 = V + (int64_t)i0 * ldv + (int64_t)r * N;
+  double acc[kDotBlk];
+#pragma unroll
+  for (int q = 0; q < kDotBlk; ++q) acc[q] = 0.0;
+  for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
+    const double wn = wr[n];
+#pragma unroll
+    for (int q = 0; q < kDotBlk; ++q)
+      if (q < nb) acc[q] += v0[(int64_t)q * ldv + n] * wn;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kDotBlk; ++q) {
+    const double t = wave_sum(acc[q]);
+    if (lane == 0) red[q][wv] = t;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nb) {
+    double t = 0.0;
+    for (int u = 0; u < (int)(blockDim.x >> 6); ++u) t += red[threadIdx.x][u];
+    out[threadIdx.x] = t;
   }
 }
 
@@ -62,15 +89,16 @@ __global__ void k_dot_final(const double* __restrict__ partial, int nchunk, int 
 hipError_t launch_gemv_t(const double* V, int64_t ldv, int64_t N, int k, const double* w, int64_t ldw, int nrhs,
                          double* h, int64_t ldh, const int* active, double* partial, hipStream_t st) {
   if (k <= 0) return hipSuccess;
-  const int nchunk = (int)((N + kChunk - 1) / kChunk);
-  hipLaunchKernelGGL(k_dot_partial, dim3(nchunk, nrhs), dim3(kRedThreads), 0, st, V, ldv, N, k, w, ldw, nrhs,
+  const int nchunk = (int)((N + kDotChunk - 1) / kDotChunk);
+  const int nkb = (k + kDotBlk - 1) / kDotBlk;
+  hipLaunchKernelGGL(k_dot_partial, dim3(nchunk, nkb, nrhs), dim3(kRedThreads), 0, st, V, ldv, N, k, w, ldw, nrhs,
                      partial, active);
   hipLaunchKernelGGL(k_dot_final, dim3((k * nrhs + 127) / 128), dim3(128), 0, st, partial, nchunk, nrhs, k, h, ldh);
   return hipGetLastError();
 }
 
 int64_t gemv_t_partial_size(int64_t N, int kmax, int nrhs) {
-  return ((N + kChunk - 1) / kChunk) * (int64_t)nrhs * kmax;
+  return ((N + kDotChunk - 1) / kDotChunk) * (int64_t)nrhs * kmax;
 }
 
 // w[r] -= sum_{i<k} V_i[r] h[r*ldh + i]
@@ -92,21 +120,45 @@ hipError_t launch_gemv_n_sub(const double* V, int64_t ldv, int64_t N, int k, con
   return hipGetLastError();
 }
 
+// column 2-norms: per-chunk partial sums of squares (wave shuffles, fixed order), then
+// one thread per column adds the chunks and takes the root
 __global__ void __launch_bounds__(kRedThreads)
-k_colnorm(const double* __restrict__ w, int64_t ldw, int64_t N, double* __restrict__ out) {
-  __shared__ double red[kRedThreads];
-  const int r = blockIdx.x;
+k_sumsq_partial(const double* __restrict__ w, int64_t ldw, int64_t N, int nrhs, double* __restrict__ partial) {
+  __shared__ double red[kRedThreads / 64];
+  const int chunk = blockIdx.x, r = blockIdx.y;
+  const int64_t n0 = (int64_t)chunk * kDotChunk;
+  const int64_t n1 = n0 + kDotChunk < N ? n0 + kDotChunk : N;
   const double* wr = w + (int64_t)r * ldw;
   double acc = 0.0;
-  for (int64_t n = threadIdx.x; n < N; n += blockDim.x) acc += wr[n] * wr[n];
-  acc = block_sum(acc, red);
-  if (threadIdx.x == 0) out[r] = sqrt(acc);
+  for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) acc += wr[n] * wr[n];
+  const double t = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double u = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) u += red[q];
+    partial[(int64_t)chunk * nrhs + r] = u;
+  }
 }
 
-hipError_t launch_colnorm(const double* w, int64_t ldw, int64_t N, int nrhs, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_colnorm, dim3(nrhs), dim3(kRedThreads), 0, st, w, ldw, N, out);
+__global__ void k_sumsq_final(const double* __restrict__ partial, int nchunk, int nrhs, double* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += partial[(int64_t)c * nrhs + r];
+  out[r] = sqrt(s);
+}
+
+// norms of nrhs columns; partial: caller workspace of colnorm_partial_size(N, nrhs)
+hipError_t launch_colnorm(const double* w, int64_t ldw, int64_t N, int nrhs, double* out, double* partial,
+                          hipStream_t st) {
+  const int nchunk = (int)((N + kDotChunk - 1) / kDotChunk);
+  hipLaunchKernelGGL(k_sumsq_partial, dim3(nchunk, nrhs), dim3(kRedThreads), 0, st, w, ldw, N, nrhs, partial);
+  hipLaunchKernelGGL(k_sumsq_final, dim3((nrhs + 63) / 64), dim3(64), 0, st, partial, nchunk, nrhs, out);
   return hipGetLastError();
 }
+
+int64_t colnorm_partial_size(int64_t N, int nrhs) { return ((N + kDotChunk - 1) / kDotChunk) * (int64_t)nrhs; }
 
 // mode 0: w[r] *= s[r]; mode 1: w[r] /= s[r] (w[r] = 0 when s[r] == 0)
 __global__ void k_scale_cols(double* __restrict__ w, int64_t ldw, int64_t N, const double* __restrict__ s, int mode) {
@@ -145,15 +197,17 @@ hipError_t launch_axpy_cols(double* y, const double* x, int64_t N, int nrhs, con
 
 // Dielectric rows of eq. (14): y = x / I_kk; conductor rows are overwritten by the block apply.
 __global__ void k_diag_scale(const double* __restrict__ x, double* __restrict__ y, const double* __restrict__ dinv,
-                             int64_t N) {
+                             int64_t N, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int r = blockIdx.y;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
   y[(int64_t)r * N + n] = dinv[n] * x[(int64_t)r * N + n];
 }
 
-hipError_t launch_diag_scale(const double* x, double* y, const double* dinv, int64_t N, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(k_diag_scale, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, x, y, dinv, N);
+hipError_t launch_diag_scale(const double* x, double* y, const double* dinv, int64_t N, int nrhs, const int* skip,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_diag_scale, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, x, y, dinv, N, skip);
   return hipGetLastError();
 }
 
@@ -165,7 +219,8 @@ __global__ void __launch_bounds__(kBoxThreads)
 k_block_apply(const double* __restrict__ x, double* __restrict__ y, int64_t N, int nrhs,
               const int32_t* __restrict__ box_ptr, const int32_t* __restrict__ box_panels,
               const int32_t* __restrict__ box_block, const int64_t* __restrict__ block_off,
-              const int32_t* __restrict__ block_n, const double* __restrict__ blocks) {
+              const int32_t* __restrict__ block_n, const double* __restrict__ blocks, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double xs[kBoxLds];
   const int box = blockIdx.x;
   const int p0 = box_ptr[box];
@@ -195,10 +250,11 @@ k_block_apply(const double* __restrict__ x, double* __restrict__ y, int64_t N, i
 
 hipError_t launch_block_apply(const double* x, double* y, int64_t N, int nrhs, const int32_t* box_ptr,
                               const int32_t* box_panels, const int32_t* box_block, const int64_t* block_off,
-                              const int32_t* block_n, const double* blocks, int nbox, hipStream_t st) {
+                              const int32_t* block_n, const double* blocks, int nbox, const int* skip,
+                              hipStream_t st) {
   if (nbox == 0) return hipSuccess;
   hipLaunchKernelGGL(k_block_apply, dim3(nbox), dim3(kBoxThreads), 0, st, x, y, N, nrhs, box_ptr, box_panels,
-                     box_block, block_off, block_n, blocks);
+                     box_block, block_off, block_n, blocks, skip);
   return hipGetLastError();
 }
 
@@ -222,6 +278,196 @@ hipError_t launch_cap_reduce(const double* rho, int64_t N, int m, const int32_t*
                              const double* weight, double scale, double* C, hipStream_t st) {
   hipLaunchKernelGGL(k_cap_reduce, dim3(m, m), dim3(kRedThreads), 0, st, rho, N, m, cond_panels, cond_ptr, weight,
                      scale, C);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ device-side GMRES cycle
+// The restart cycle runs without host round trips (so it can be captured as a graph):
+// per-column Hessenberg columns, Givens rotations, convergence masks and the final
+// triangular solve live on the device.  One workgroup, one thread per column.
+// Per-column state layout: H[c][(m+1) x m] row-major, cs/sn[c][m], g[c][m+1].
+
+__device__ __forceinline__ int any_over_block(int v, int* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] |= red[threadIdx.x + s];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// start of a cycle from the residual norms rn: relative residual, active masks,
+// g = (|r|, 0, ...), scal = |r| for V_0 = r / |r| (0 = zero column), skip flags
+__global__ void k_cycle_start(int nrhs, int m, const double* __restrict__ rn, const double* __restrict__ bn,
+                              const double* __restrict__ rtolp, int* __restrict__ act_cycle, int* __restrict__ act_step,
+                              double* __restrict__ g, double* __restrict__ scal, int* __restrict__ kd,
+                              int* __restrict__ skip, double* __restrict__ rre_out) {
+  __shared__ int red[64];
+  const int c = threadIdx.x;
+  const double rtol = *rtolp;
+  int a = 0;
+  if (c < nrhs) {
+    const double b = bn[c], r = rn[c];
+    const double rre = b > 0.0 ? r / b : 0.0;
+    rre_out[c] = rre;
+    a = (b > 0.0 && !(rre <= rtol)) ? 1 : 0;   // NaN stays active; the host reports it
+    act_cycle[c] = a;
+    act_step[c] = a;
+    kd[c] = 0;
+    for (int i = 0; i <= m; ++i) g[(int64_t)c * (m + 1) + i] = 0.0;
+    g[(int64_t)c * (m + 1)] = r;
+    scal[c] = a ? r : 0.0;
+  }
+  const int any = any_over_block(a, red);
+  if (threadIdx.x == 0) {
+    skip[0] = any ? 0 : 1;   // cycle-level: nothing to do this cycle
+    skip[1] = any ? 0 : 1;   // step-level: no column still iterating
+  }
+}
+
+hipError_t launch_cycle_start(int nrhs, int m, const double* rn, const double* bn, const double* rtol, int* act_cycle,
+                              int* act_step, double* g, double* scal, int* kd, int* skip, double* rre_out,
+                              hipStream_t st) {
+  if (nrhs > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(64), 0, st, nrhs, m, rn, bn, rtol, act_cycle, act_step, g, scal,
+                     kd, skip, rre_out);
+  return hipGetLastError();
+}
+
+// Arnoldi step j: H(:, j) = h1 + h2 (classical Gram-Schmidt, twice), H(j+1, j) = |w|,
+// previous rotations applied, new rotation from (H(j,j), H(j+1,j)), g rotated; a column
+// freezes when its residual estimate |g(j+1)| / |b| <= rtol / 2, on breakdown, or at
+// the end of the cycle.  scal = |w| for V_{j+1} = w / |w| (0 once frozen).
+__global__ void k_arnoldi(int j, int nrhs, int m, const double* __restrict__ h1, const double* __restrict__ h2,
+                          int ldh, const double* __restrict__ hn, double* __restrict__ H, double* __restrict__ cs,
+                          double* __restrict__ sn, double* __restrict__ g, const double* __restrict__ bn,
+                          const double* __restrict__ rtolp, int* __restrict__ act_step, int* __restrict__ kd, int* __restrict__ iters,
+                          double* __restrict__ scal, int* __restrict__ skip, int* __restrict__ bad) {
+  __shared__ int red[64];
+  const int c = threadIdx.x;
+  const double rtol = *rtolp;
+  int still = 0;
+  if (c < nrhs) {
+    if (act_step[c]) {
+      double* Hc = H + (int64_t)c * (m + 1) * m;
+      double* csc = cs + (int64_t)c * m;
+      double* snc = sn + (int64_t)c * m;
+      double* gc = g + (int64_t)c * (m + 1);
+      for (int i = 0; i <= j; ++i) Hc[i * m + j] = h1[(int64_t)c * ldh + i] + h2[(int64_t)c * ldh + i];
+      const double hnc = hn[c];
+      Hc[(j + 1) * m + j] = hnc;
+      for (int i = 0; i < j; ++i) {
+        const double a = Hc[i * m + j], b = Hc[(i + 1) * m + j];
+        Hc[i * m + j] = csc[i] * a + snc[i] * b;
+        Hc[(i + 1) * m + j] = -snc[i] * a + csc[i] * b;
+      }
+      const double a = Hc[j * m + j], b = Hc[(j + 1) * m + j];
+      const double rr = hypot(a, b);
+      const double cc = rr > 0.0 ? a / rr : 1.0, ss = rr > 0.0 ? b / rr : 0.0;
+      csc[j] = cc;
+      snc[j] = ss;
+      Hc[j * m + j] = rr;
+      Hc[(j + 1) * m + j] = 0.0;
+      gc[j + 1] = -ss * gc[j];
+      gc[j] = cc * gc[j];
+      const double est = fabs(gc[j + 1]) / bn[c];
+      if (!isfinite(est)) bad[0] = 1;
+      const bool breakdown = hnc <= 1e-300 || hnc <= 1e-14 * fabs(rr);
+      kd[c] = j + 1;
+      iters[c] += 1;
+      still = (est > 0.5 * rtol && !breakdown && j + 1 < m && isfinite(est)) ? 1 : 0;
+      act_step[c] = still;
+      scal[c] = still ? hnc : 0.0;
+    } else {
+      scal[c] = 0.0;
+    }
+  }
+  const int any = any_over_block(still, red);
+  if (threadIdx.x == 0) skip[1] = any ? 0 : 1;
+}
+
+hipError_t launch_arnoldi(int j, int nrhs, int m, const double* h1, const double* h2, int ldh, const double* hn,
+                          double* H, double* cs, double* sn, double* g, const double* bn, const double* rtol,
+                          int* act_step, int* kd, int* iters, double* scal, int* skip, int* bad, hipStream_t st) {
+  if (nrhs > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), 0, st, j, nrhs, m, h1, h2, ldh, hn, H, cs, sn, g, bn, rtol,
+                     act_step, kd, iters, scal, skip, bad);
+  return hipGetLastError();
+}
+
+// y = -(R^{-1} g) over the kd[c] steps of the cycle (the rotated Hessenberg R is upper
+// triangular), zero beyond and for columns inactive this cycle; the sign matches the
+// subtracting gemv that forms V y.
+__global__ void k_backsolve(int nrhs, int m, const double* __restrict__ H, const double* __restrict__ g,
+                            const int* __restrict__ kd, const int* __restrict__ act_cycle, double* __restrict__ y,
+                            int ldy) {
+  const int c = threadIdx.x;
+  if (c >= nrhs) return;
+  double* yc = y + (int64_t)c * ldy;
+  for (int i = 0; i < ldy; ++i) yc[i] = 0.0;
+  if (!act_cycle[c]) return;
+  const double* Hc = H + (int64_t)c * (m + 1) * m;
+  const double* gc = g + (int64_t)c * (m + 1);
+  const int k = kd[c];
+  for (int i = k - 1; i >= 0; --i) {
+    double t = gc[i];
+    for (int l = i + 1; l < k; ++l) t -= Hc[i * m + l] * yc[l];
+    yc[i] = Hc[i * m + i] != 0.0 ? t / Hc[i * m + i] : 0.0;
+  }
+  for (int i = 0; i < k; ++i) yc[i] = -yc[i];
+}
+
+hipError_t launch_backsolve(int nrhs, int m, const double* H, const double* g, const int* kd, const int* act_cycle,
+                            double* y, int ldy, hipStream_t st) {
+  if (nrhs > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, st, nrhs, m, H, g, kd, act_cycle, y, ldy);
+  return hipGetLastError();
+}
+
+// dst[r] = src[r] / s[r] (0 when s[r] == 0); skipped when *skip
+__global__ void k_scale_copy(double* __restrict__ dst, const double* __restrict__ src, int64_t N,
+                             const double* __restrict__ s, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int r = blockIdx.y;
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const double f = s[r];
+  dst[(int64_t)r * N + n] = f != 0.0 ? src[(int64_t)r * N + n] / f : 0.0;
+}
+
+hipError_t launch_scale_copy(double* dst, const double* src, int64_t N, int nrhs, const double* s, const int* skip,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_copy, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, dst, src, N, s, skip);
+  return hipGetLastError();
+}
+
+// fill with zeros (a kernel, so a captured graph holds no memset node)
+__global__ void k_zero(double* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+hipError_t launch_zero(double* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+// x[r] += z[r] for the columns active this cycle; skipped when *skip
+__global__ void k_add_active(double* __restrict__ x, const double* __restrict__ z, int64_t N,
+                             const int* __restrict__ act, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int r = blockIdx.y;
+  if (!act[r]) return;
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  x[(int64_t)r * N + n] += z[(int64_t)r * N + n];
+}
+
+hipError_t launch_add_active(double* x, const double* z, int64_t N, int nrhs, const int* act, const int* skip,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_add_active, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, x, z, N, act, skip);
   return hipGetLastError();
 }
 

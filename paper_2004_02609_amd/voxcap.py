@@ -53,7 +53,8 @@ class vc_setup_opts(C.Structure):
 
 class vc_solve_opts(C.Structure):
     _fields_ = [("prec", C.c_int), ("rtol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
-                ("inner_rtol", C.c_double), ("ir_max", C.c_int32), ("use_precond", C.c_int32)]
+                ("inner_rtol", C.c_double), ("ir_max", C.c_int32), ("use_precond", C.c_int32),
+                ("graph", C.c_int32)]
 
 
 class vc_stats(C.Structure):
@@ -225,7 +226,7 @@ def vc_pass_times(h):
     return list(ms), list(n), list(b)
 
 
-def _solve_opts(prec="fp64", rtol=0.0, restart=0, max_iter=0, inner_rtol=0.0, ir_max=0, use_precond=1):
+def _solve_opts(prec="fp64", rtol=0.0, restart=0, max_iter=0, inner_rtol=0.0, ir_max=0, use_precond=1, graph=True):
     o = vc_solve_opts()
     o.prec = _PREC[prec]
     o.rtol = rtol
@@ -234,6 +235,7 @@ def _solve_opts(prec="fp64", rtol=0.0, restart=0, max_iter=0, inner_rtol=0.0, ir
     o.inner_rtol = inner_rtol
     o.ir_max = ir_max
     o.use_precond = use_precond
+    o.graph = 0 if graph else 1
     return o
 
 

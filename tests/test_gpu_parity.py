@@ -171,3 +171,23 @@ def test_autotuned_product_matches_dense(dev):
     rep = P.tuning_report()
     print(rep, flush=True)
     assert rep.count("tuned") == 4, rep
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_graph_replayed_cycles_match_eager(dev, prec):
+    """Restart cycles replayed from one captured graph (GMRES(5): many replays, host
+    reads and eager work between them) give bitwise the eager result, which matches
+    the oracle."""
+    s = scenes.random_small(9, shape=(11, 7, 13), n_cond=3, n_diel=2)
+    P = _problem(s)
+    Cg, stg = P.capacitance(prec=prec, rtol=1e-11, restart=5, graph=True)
+    Ce, ste = P.capacitance(prec=prec, rtol=1e-11, restart=5, graph=False)
+    print(prec, "iters graph", stg["iters"], "eager", ste["iters"], flush=True)
+    assert stg["iters"] == ste["iters"]
+    assert np.array_equal(Cg, Ce)
+    C_ref = oracle.solve_capacitance(s)
+    err = np.abs(Cg - C_ref).max() / np.abs(C_ref).max()
+    assert err < 1e-9, err
+    # a second graph solve reuses the cached graph and reproduces the first
+    Cg2, _ = P.capacitance(prec=prec, rtol=1e-11, restart=5, graph=True)
+    assert np.array_equal(Cg, Cg2)
