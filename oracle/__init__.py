@@ -18,7 +18,7 @@ What it computes is the plain definition of the paper's method (Sec. II.A):
 
 Dimensionless units: voxel edge 1 and 4*pi*eps0 = 1 (scaling of App. C).
 """
-from . import panels, integrals, dense  # noqa: F401
+from . import panels, integrals, dense, tucker  # noqa: F401
 from .panels import panelize, GeometryError  # noqa: F401
 from .dense import (assemble, rhs, solve_capacitance, mvp, capacitance_gradient,  # noqa: F401
                     capacitance_from_rho, free_charge_weights, EPS0)
