@@ -185,6 +185,14 @@ vc_status vc_charges_to_capacitance(vc_problem *p, const double *rho_dev, int32_
 vc_status vc_charges_to_capacitance_adjoint(vc_problem *p, const double *gC_dev, int32_t nrhs,
                                             double *grho_dev, void *hip_stream);
 
+/* Tucker form of the stored spectra (vc_setup with tucker_tol > 0; eq. 13, Sec. II.C):
+ * number of stored pairs, their multilinear ranks (rows of 3 in ranks[0..44], pair order
+ * P xx yy zz xy xz yz then E xx xy xz yx yy yz zx zy zz), numbers kept compressed
+ * (r1 r2 r3 + sum D_i r_i) and uncompressed (D1 D2 D3 per pair), and the summed time and
+ * count of the rebuilds recorded while profiling was enabled.  Zeros without Tucker. */
+vc_status vc_tucker_info(vc_problem *p, int32_t *npairs, int32_t ranks[45], double *stored_numbers,
+                         double *full_numbers, double *rebuild_ms, int32_t *rebuilds);
+
 vc_status vc_profile_enable(vc_problem *p, int enable);
 
 /* Text report of the x-pass launch configurations in use, one line per

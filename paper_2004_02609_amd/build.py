@@ -11,7 +11,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvoxcap.so")
 SOURCES = ["sandwich_f32_36.hip", "sandwich_f32_33.hip", "sandwich_f32_63.hip", "sandwich_f64_36.hip",
            "sandwich_f64_33.hip", "sandwich_f64_63.hip", "mvp_kernels.hip", "setup_kernels.hip",
-           "solver_kernels.hip", "geometry.cpp", "setup.cpp", "apply.cpp", "api.cpp"]
+           "solver_kernels.hip", "tucker_kernels.hip", "geometry.cpp", "setup.cpp", "apply.cpp", "tucker.cpp",
+           "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -37,7 +38,8 @@ def build(verbose=False):
                 print(out)
             objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs + [
+        "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)

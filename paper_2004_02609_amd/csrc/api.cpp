@@ -426,7 +426,6 @@ vc_status vc_setup(vc_problem* p, const vc_setup_opts* opts, void* stream) {
   vc_setup_opts o{};
   if (opts) o = *opts;
   if (o.tucker_tol < 0) { set_error("tucker_tol must be >= 0"); return VC_ERR_ARG; }
-  if (o.tucker_tol > 0) { set_error("Tucker compression is not available in this build"); return VC_ERR_ARG; }
   const double t0 = now_s();
   VC_HIP(hipSetDevice(p->device));
   p->drop_graphs();   // they hold pointers to tables and work arrays set up again below
@@ -435,7 +434,9 @@ vc_status vc_setup(vc_problem* p, const vc_setup_opts* opts, void* stream) {
   if (s != VC_OK) return s;
   for (int a = 0; a < 3; ++a) p->nv[a] = o.nv[a] > 0 ? o.nv[a] : 8;
   const int prec = o.precisions ? o.precisions : 3;
-  s = build_spectra(p, (prec & 1) != 0, (prec & 2) != 0, st);
+  p->tk.clear();
+  p->tucker_tol = 0.0;
+  s = build_spectra(p, (prec & 1) != 0, (prec & 2) != 0, o.tucker_tol, st);
   if (s != VC_OK) return mark(p, s);
   p->max_rhs = o.max_rhs > 0 ? o.max_rhs : p->m;
   p->autotune = o.autotune != 0;
@@ -514,6 +515,9 @@ static vc_status capacitance_impl(vc_problem* p, const vc_solve_opts* opts, doub
     stats->t_setup_s = p->t_setup;
     stats->t_solve_s = now_s() - t0;
     stats->spectra_bytes = p->spectra_bytes;
+    int rmax = 0;
+    for (const auto& t : p->tk) rmax = std::max(rmax, std::max(t.r[0], std::max(t.r[1], t.r[2])));
+    stats->tucker_rank_max = rmax;
   }
   return s;
 }
@@ -619,6 +623,40 @@ vc_status vc_charges_to_capacitance_adjoint(vc_problem* p, const double* gC_dev,
   VC_HIP(hipSetDevice(p->device));
   VC_HIP(launch_cap_reduce_adj(gC_dev, npanels(p), nrhs, p->d_pcond.as<int32_t>(), p->d_weight.as<double>(),
                                4.0 * M_PI * kEps0 * p->dv, grho_dev, (hipStream_t)stream));
+  return VC_OK;
+}
+
+vc_status vc_tucker_info(vc_problem* p, int32_t* npairs, int32_t ranks[45], double* stored_numbers,
+                         double* full_numbers, double* rebuild_ms, int32_t* rebuilds) {
+  VC_CHECK_PROBLEM(p);
+  if (!npairs || !ranks || !stored_numbers || !full_numbers || !rebuild_ms || !rebuilds) {
+    set_error("null argument");
+    return VC_ERR_ARG;
+  }
+  for (auto& e : p->tk_pending) {
+    VC_HIP(hipEventSynchronize(e.second));
+    float t = 0.f;
+    VC_HIP(hipEventElapsedTime(&t, e.first, e.second));
+    p->tk_ms += t;
+    p->tk_count += 1;
+    p->ev_free.push_back(e.first);
+    p->ev_free.push_back(e.second);
+  }
+  p->tk_pending.clear();
+  *npairs = (int32_t)p->tk.size();
+  for (int i = 0; i < 45; ++i) ranks[i] = 0;
+  double st = 0.0, full = 0.0;
+  const double D[3] = {(double)p->Hx, (double)p->Hy, (double)p->H};
+  for (size_t q = 0; q < p->tk.size() && q < 15; ++q) {
+    const auto& t = p->tk[q];
+    for (int m = 0; m < 3; ++m) ranks[3 * q + m] = t.r[m];
+    st += (double)t.r[0] * t.r[1] * t.r[2] + D[0] * t.r[0] + D[1] * t.r[1] + D[2] * t.r[2];
+    full += D[0] * D[1] * D[2];
+  }
+  *stored_numbers = st;
+  *full_numbers = full;
+  *rebuild_ms = p->tk_ms;
+  *rebuilds = p->tk_count;
   return VC_OK;
 }
 

@@ -137,6 +137,20 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
   hipStreamCaptureStatus capst = hipStreamCaptureStatusNone;
   VC_HIP(hipStreamIsCapturing(st, &capst));
   const bool prof = P->prof && capst == hipStreamCaptureStatusNone;   // no timing events inside a graph
+  // Tucker form: rebuild the stored pairs before the x pass reads them
+  if (!P->tk.empty()) {
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (prof) {
+      if (!(t0 = take_event(P)) || !(t1 = take_event(P))) { set_error("hipEventCreate failed"); return VC_ERR_HIP; }
+      VC_HIP(hipEventRecord(t0, st));
+    }
+    vc_status ts = tucker_rebuild<T>(P, (T*)tb.R.p, (int64_t)P->Hy * H * P->Hx, st);
+    if (ts != VC_OK) return ts;
+    if (prof) {
+      VC_HIP(hipEventRecord(t1, st));
+      P->tk_pending.emplace_back(t0, t1);
+    }
+  }
   if (prof) {
     for (int i = 0; i < 6; ++i)
       if (!(ev[i] = take_event(P))) { set_error("hipEventCreate failed"); return VC_ERR_HIP; }

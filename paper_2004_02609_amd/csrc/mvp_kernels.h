@@ -157,6 +157,16 @@ hipError_t launch_cap_reduce(const double* rho, int64_t N, int m, const int32_t*
                              const int32_t* cond_ptr, const double* weight, double scale, double* C,
                              hipStream_t st);
 
+// Tucker rebuild GEMMs (tucker_kernels.hip): C[z] = A[z] B[z] with element strides
+struct GemmArgs {
+  int M, N, K, batch;
+  int64_t sam, sak, sbk, sbn, scm, scn;   // A[m][k], B[k][n], C[m][n]
+  int64_t bsa, bsb, bsc;                  // batch strides
+};
+template <typename T>
+hipError_t launch_mfma_gemm(const T* A, const T* B, T* C, const GemmArgs& g, hipStream_t st);
+hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t st);
+
 hipError_t launch_cap_reduce_n(const double* rho, int64_t N, int m, int nrhs, const int32_t* cond_panels,
                                const int32_t* cond_ptr, const double* weight, double scale, double* C,
                                hipStream_t st);

@@ -24,6 +24,17 @@ struct DevMem {
   DevMem() = default;
   DevMem(const DevMem&) = delete;
   DevMem& operator=(const DevMem&) = delete;
+  DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevMem& operator=(DevMem&& o) noexcept {
+    if (this != &o) {
+      reset();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
   ~DevMem() { reset(); }
   void reset() {
     if (p) (void)hipFree(p);
@@ -51,6 +62,13 @@ struct AxisTables {
 struct PrecTables {
   AxisTables ax[3];
   DevMem R;    // [15][Hx][Hy][H] real spectra, kz contiguous (pairs not stored left unset)
+};
+
+// Tucker form of one stored spectrum pair (eq. 13): core r0 x r1 x r2 and factors
+// D_m x r_m (row-major), FP64 and FP32 copies.
+struct TuckerPair {
+  int r[3] = {0, 0, 0};
+  DevMem S64, U64[3], S32, U32[3];
 };
 
 struct Precond {
@@ -99,6 +117,13 @@ struct vc_problem {
   double t_setup = 0.0;
   double spectra_bytes = 0.0;
   double extract_resid = 0.0;
+  // Tucker compression of the stored spectra (tucker_tol > 0): rebuilt before each product
+  double tucker_tol = 0.0;
+  std::vector<vc::TuckerPair> tk;
+  vc::DevMem tk_T1, tk_T2;          // rebuild scratch
+  double tk_ms = 0.0;
+  int tk_count = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tk_pending;
   // device mirrors
   vc::DevMem d_line_ptr, d_items, d_lflag, d_pflag, d_pk, d_pkind, d_diag, d_cond_ptr, d_cond_panels, d_weight, d_gl;
   vc::DevMem d_pcond;               // conductor id per panel (-1 on dielectric panels)
@@ -169,6 +194,10 @@ struct vc_problem {
     if (solve_stream) (void)hipStreamDestroy(solve_stream);
     for (auto& v : ev_pending)
       for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    for (auto& e : tk_pending) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
     for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
   }
 };
@@ -177,8 +206,12 @@ namespace vc {
 inline int64_t npanels(const vc_problem* p) { return (int64_t)p->panels.size(); }
 vc_status panelize(vc_problem* p);
 vc_status choose_sizes(vc_problem* p, const int32_t* fft_size);
-vc_status build_spectra(vc_problem* p, int want64, int want32, hipStream_t st);
+vc_status build_spectra(vc_problem* p, int want64, int want32, double tucker_tol, hipStream_t st);
 vc_status build_precond(vc_problem* p, hipStream_t st);
+vc_status tucker_begin(vc_problem* p, double tol);
+vc_status tucker_compress_pair(vc_problem* p, const double* X, hipStream_t st);
+vc_status tucker_end(vc_problem* p);
+template <typename T> vc_status tucker_rebuild(vc_problem* p, T* R, int64_t pair_stride, hipStream_t st);
 vc_status apply_op(vc_problem* p, int transpose, vc_precision prec, const double* x, double* y, int nrhs,
                    hipStream_t st, const int* skip = nullptr);
 vc_status apply_precond(vc_problem* p, int transpose, const double* x, double* y, int nrhs, hipStream_t st,

@@ -145,7 +145,7 @@ static vc_status upload(DevMem& d, const std::vector<T>& h) {
   return VC_OK;
 }
 
-vc_status build_spectra(vc_problem* P, int want64, int want32, hipStream_t st) {
+vc_status build_spectra(vc_problem* P, int want64, int want32, double tucker_tol, hipStream_t st) {
   const int Mx = P->M[0], My = P->M[1], Mz = P->M[2];
   const int H = P->H, Hx = P->Hx, Hy = P->Hy;
   // index maps
@@ -180,7 +180,12 @@ vc_status build_spectra(vc_problem* P, int want64, int want32, hipStream_t st) {
   P->spectra_bytes = 0;
   if (want64) { VC_HIP(P->t64.R.alloc((size_t)15 * per_pair * sizeof(double))); P->spectra_bytes += (double)npairs * per_pair * 8; }
   if (want32) { VC_HIP(P->t32.R.alloc((size_t)15 * per_pair * sizeof(float))); P->spectra_bytes += (double)npairs * per_pair * 4; }
-  DevMem circ, spec, resid;
+  const bool tucker = tucker_tol > 0.0;
+  DevMem circ, spec, resid, one;   // one: a pair's FP64 spectrum when compressing
+  if (tucker) {
+    VC_HIP(one.alloc((size_t)per_pair * sizeof(double)));
+    if ((s = tucker_begin(P, tucker_tol)) != VC_OK) return s;
+  }
   VC_HIP(circ.alloc((size_t)Mx * My * Mz * sizeof(double)));
   VC_HIP(spec.alloc((size_t)Mx * My * H * 2 * sizeof(double)));
   VC_HIP(resid.alloc(sizeof(double)));
@@ -219,9 +224,22 @@ vc_status build_spectra(vc_problem* P, int want64, int want32, hipStream_t st) {
     ea.Mx = Mx; ea.My = My; ea.Mz = Mz; ea.H = H; ea.Hx = Hx; ea.Hy = Hy;
     ea.kind = want == 1 ? 2 : (a == b ? 0 : 1);
     ea.alpha = a; ea.beta = b;
-    ea.pair_off = (int64_t)q * per_pair;
-    VC_HIP(launch_extract(spec.p, want64 ? P->t64.R.as<double>() : nullptr, want32 ? P->t32.R.as<float>() : nullptr, ea,
-                          resid.as<double>(), st));
+    if (tucker) {
+      ea.pair_off = 0;
+      VC_HIP(launch_extract(spec.p, one.as<double>(), nullptr, ea, resid.as<double>(), st));
+      if ((s = tucker_compress_pair(P, one.as<double>(), st)) != VC_OK) return s;
+    } else {
+      ea.pair_off = (int64_t)q * per_pair;
+      VC_HIP(launch_extract(spec.p, want64 ? P->t64.R.as<double>() : nullptr, want32 ? P->t32.R.as<float>() : nullptr,
+                            ea, resid.as<double>(), st));
+    }
+  }
+  if (tucker) {
+    if ((s = tucker_end(P)) != VC_OK) return s;
+    // the spectra buffers now only hold rebuilds: start them as NaN so a product that
+    // skipped the rebuild could not pass for a correct one
+    if (want64) VC_HIP(hipMemsetAsync(P->t64.R.p, 0xff, (size_t)15 * per_pair * sizeof(double), st));
+    if (want32) VC_HIP(hipMemsetAsync(P->t32.R.p, 0xff, (size_t)15 * per_pair * sizeof(float), st));
   }
   double r = 0.0;
   VC_HIP(hipMemcpyAsync(&r, resid.p, sizeof(double), hipMemcpyDeviceToHost, st));

@@ -1,0 +1,206 @@
+// Tucker compression of the stored kernel spectra at setup and their rebuild before
+// each product (eq. 13, Sec. II.C).
+//
+// Compression (FP64, once): the sequentially truncated HOSVD.  For modes kx, ky, kz in
+// turn the Gram matrix of the current tensor's unfolding is formed (rocBLAS GEMM), its
+// eigenvectors found (rocSOLVER syevd), the smallest rank whose discarded eigenvalues
+// sum to at most tol^2 ||X||^2 / 3 kept, and the tensor projected onto them; what is
+// left is the core.  The three budgets add up to ||X - X_hat|| <= tol ||X||.
+//
+// Rebuild (every product, FP32 or FP64): three strided batched GEMMs on the matrix
+// cores (tucker_kernels.hip) write each stored pair back into the spectra buffer the
+// x pass reads.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "mvp_kernels.h"
+#include "problem.h"
+
+namespace vc {
+
+#define VC_RB(expr)                                                          \
+  do {                                                                       \
+    const rocblas_status _s = (expr);                                        \
+    if (_s != rocblas_status_success) {                                      \
+      set_error("%s failed (rocblas status %d)", #expr, (int)_s);            \
+      return VC_ERR_HIP;                                                     \
+    }                                                                        \
+  } while (0)
+
+// Leading eigenvectors of the symmetric n x n Gram matrix G (device, column-major;
+// overwritten): the smallest r whose discarded eigenvalues sum to at most budget.
+// U: n x r row-major on the device.
+static vc_status leading_subspace(rocblas_handle h, double* G, int n, double budget, DevMem& U, int* r_out,
+                                  hipStream_t st) {
+  DevMem ev, work, info;
+  VC_HIP(ev.alloc((size_t)n * sizeof(double)));
+  VC_HIP(work.alloc((size_t)n * sizeof(double)));
+  VC_HIP(info.alloc(sizeof(rocblas_int)));
+  VC_RB(rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, G, n, ev.as<double>(), work.as<double>(),
+                         info.as<rocblas_int>()));
+  std::vector<double> e(n), g((size_t)n * n);
+  rocblas_int inf = 0;
+  VC_HIP(hipMemcpyAsync(e.data(), ev.p, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st));
+  VC_HIP(hipMemcpyAsync(&inf, info.p, sizeof(rocblas_int), hipMemcpyDeviceToHost, st));
+  VC_HIP(hipMemcpyAsync(g.data(), G, (size_t)n * n * sizeof(double), hipMemcpyDeviceToHost, st));
+  VC_HIP(hipStreamSynchronize(st));
+  if (inf != 0) { set_error("symmetric eigensolver did not converge (info %d)", (int)inf); return VC_ERR_NUMERIC; }
+  // eigenvalues ascending: discard the d smallest with sum <= budget (negative round-off clamped)
+  int d = 0;
+  double acc = 0.0;
+  while (d < n - 1) {
+    acc += std::max(e[d], 0.0);
+    if (acc > budget) break;
+    ++d;
+  }
+  const int r = n - d;
+  std::vector<double> u((size_t)n * r);
+  for (int a = 0; a < r; ++a)
+    for (int i = 0; i < n; ++i) u[(size_t)i * r + a] = g[(size_t)(n - 1 - a) * n + i];
+  VC_HIP(U.alloc(u.size() * sizeof(double)));
+  VC_HIP(hipMemcpyAsync(U.p, u.data(), u.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  VC_HIP(hipStreamSynchronize(st));
+  *r_out = r;
+  return VC_OK;
+}
+
+// Compress one tensor X (device, D1 x D2 x D3 row-major: [kx][ky][kz]).
+static vc_status compress_one(rocblas_handle h, const double* X, int D1, int D2, int D3, double tol, TuckerPair& tp,
+                              hipStream_t st) {
+  const int64_t K1 = (int64_t)D2 * D3;
+  const double one = 1.0, zero = 0.0;
+  // ||X||^2 and mode 1: G1 = X X^T
+  DevMem G1;
+  VC_HIP(G1.alloc((size_t)D1 * D1 * sizeof(double)));
+  VC_RB(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, D1, D1, (rocblas_int)K1, &one, X,
+                      (rocblas_int)K1, X, (rocblas_int)K1, &zero, G1.as<double>(), D1));
+  std::vector<double> g1((size_t)D1 * D1);
+  VC_HIP(hipMemcpyAsync(g1.data(), G1.p, g1.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  VC_HIP(hipStreamSynchronize(st));
+  double nrm2 = 0.0;
+  for (int i = 0; i < D1; ++i) nrm2 += g1[(size_t)i * D1 + i];
+  const double budget = tol * tol * nrm2 / 3.0;
+  vc_status s = leading_subspace(h, G1.as<double>(), D1, budget, tp.U64[0], &tp.r[0], st);
+  if (s != VC_OK) return s;
+  const int r1 = tp.r[0];
+  // X1 (r1 x D2 D3) = U1^T X
+  DevMem X1;
+  VC_HIP(X1.alloc((size_t)r1 * K1 * sizeof(double)));
+  VC_RB(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)K1, r1, D1, &one, X,
+                      (rocblas_int)K1, tp.U64[0].as<double>(), r1, &zero, X1.as<double>(), (rocblas_int)K1));
+  // mode 2: G2 = sum_a X1[a] X1[a]^T (X1[a] is D2 x D3)
+  DevMem G2;
+  VC_HIP(G2.alloc((size_t)D2 * D2 * sizeof(double)));
+  for (int a = 0; a < r1; ++a) {
+    const double beta = a == 0 ? 0.0 : 1.0;
+    const double* Xa = X1.as<double>() + (size_t)a * K1;
+    VC_RB(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, D2, D2, D3, &one, Xa, D3, Xa, D3,
+                        &beta, G2.as<double>(), D2));
+  }
+  s = leading_subspace(h, G2.as<double>(), D2, budget, tp.U64[1], &tp.r[1], st);
+  if (s != VC_OK) return s;
+  const int r2 = tp.r[1];
+  // X2[a] (r2 x D3) = U2^T X1[a]
+  DevMem X2;
+  VC_HIP(X2.alloc((size_t)r1 * r2 * D3 * sizeof(double)));
+  VC_RB(rocblas_dgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_transpose, D3, r2, D2, &one,
+                                      X1.as<double>(), D3, K1, tp.U64[1].as<double>(), r2, 0, &zero, X2.as<double>(),
+                                      D3, (rocblas_stride)r2 * D3, r1));
+  // mode 3: Y = X2 as (r1 r2 x D3); G3 = Y^T Y
+  DevMem G3;
+  VC_HIP(G3.alloc((size_t)D3 * D3 * sizeof(double)));
+  VC_RB(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, D3, D3, r1 * r2, &one, X2.as<double>(),
+                      D3, X2.as<double>(), D3, &zero, G3.as<double>(), D3));
+  s = leading_subspace(h, G3.as<double>(), D3, budget, tp.U64[2], &tp.r[2], st);
+  if (s != VC_OK) return s;
+  const int r3 = tp.r[2];
+  // core S (r1 r2 x r3) = Y U3
+  VC_HIP(tp.S64.alloc((size_t)r1 * r2 * r3 * sizeof(double)));
+  VC_RB(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, r3, r1 * r2, D3, &one,
+                      tp.U64[2].as<double>(), r3, X2.as<double>(), D3, &zero, tp.S64.as<double>(), r3));
+  VC_HIP(hipStreamSynchronize(st));
+  return VC_OK;
+}
+
+vc_status tucker_begin(vc_problem* P, double tol) {
+  P->tucker_tol = tol;
+  P->tk.clear();
+  P->tk_ms = 0.0;
+  P->tk_count = 0;
+  return VC_OK;
+}
+
+vc_status tucker_compress_pair(vc_problem* P, const double* X, hipStream_t st) {
+  rocblas_handle h = nullptr;
+  if (rocblas_create_handle(&h) != rocblas_status_success) { set_error("rocblas_create_handle failed"); return VC_ERR_HIP; }
+  rocblas_set_stream(h, st);
+  P->tk.emplace_back();
+  TuckerPair& tp = P->tk.back();
+  vc_status s = compress_one(h, X, P->Hx, P->Hy, P->H, P->tucker_tol, tp, st);
+  rocblas_destroy_handle(h);
+  if (s != VC_OK) return s;
+  // FP32 copies of the core and factors
+  const int64_t ns = (int64_t)tp.r[0] * tp.r[1] * tp.r[2];
+  VC_HIP(tp.S32.alloc((size_t)ns * sizeof(float)));
+  VC_HIP(launch_to_f32(tp.S64.as<double>(), tp.S32.as<float>(), ns, st));
+  const int D[3] = {P->Hx, P->Hy, P->H};
+  for (int m = 0; m < 3; ++m) {
+    const int64_t nu = (int64_t)D[m] * tp.r[m];
+    VC_HIP(tp.U32[m].alloc((size_t)nu * sizeof(float)));
+    VC_HIP(launch_to_f32(tp.U64[m].as<double>(), tp.U32[m].as<float>(), nu, st));
+  }
+  return VC_OK;
+}
+
+// scratch of the rebuild (sized for FP64, reused by FP32)
+vc_status tucker_end(vc_problem* P) {
+  int64_t t1 = 1, t2 = 1;
+  for (const TuckerPair& tp : P->tk) {
+    t1 = std::max(t1, (int64_t)tp.r[0] * tp.r[1] * P->H);
+    t2 = std::max(t2, (int64_t)tp.r[0] * P->Hy * P->H);
+  }
+  VC_HIP(P->tk_T1.alloc((size_t)t1 * sizeof(double)));
+  VC_HIP(P->tk_T2.alloc((size_t)t2 * sizeof(double)));
+  return VC_OK;
+}
+
+template <typename T>
+vc_status tucker_rebuild(vc_problem* P, T* R, int64_t pair_stride, hipStream_t st) {
+  const int D1 = P->Hx, D2 = P->Hy, D3 = P->H;
+  T* T1 = P->tk_T1.as<T>();
+  T* T2 = P->tk_T2.as<T>();
+  for (size_t q = 0; q < P->tk.size(); ++q) {
+    const TuckerPair& tp = P->tk[q];
+    const int r1 = tp.r[0], r2 = tp.r[1], r3 = tp.r[2];
+    const T* S = sizeof(T) == 8 ? (const T*)tp.S64.p : (const T*)tp.S32.p;
+    const T* U1 = sizeof(T) == 8 ? (const T*)tp.U64[0].p : (const T*)tp.U32[0].p;
+    const T* U2 = sizeof(T) == 8 ? (const T*)tp.U64[1].p : (const T*)tp.U32[1].p;
+    const T* U3 = sizeof(T) == 8 ? (const T*)tp.U64[2].p : (const T*)tp.U32[2].p;
+    GemmArgs g{};
+    // T1 (r1 r2 x D3) = S (r1 r2 x r3) U3^T
+    g.M = r1 * r2; g.N = D3; g.K = r3; g.batch = 1;
+    g.sam = r3; g.sak = 1; g.sbk = 1; g.sbn = r3; g.scm = D3; g.scn = 1;
+    VC_HIP(launch_mfma_gemm<T>(S, U3, T1, g, st));
+    // T2[a] (D2 x D3) = U2 (D2 x r2) T1[a] (r2 x D3)
+    g = GemmArgs{};
+    g.M = D2; g.N = D3; g.K = r2; g.batch = r1;
+    g.sam = r2; g.sak = 1; g.sbk = D3; g.sbn = 1; g.scm = D3; g.scn = 1;
+    g.bsa = 0; g.bsb = (int64_t)r2 * D3; g.bsc = (int64_t)D2 * D3;
+    VC_HIP(launch_mfma_gemm<T>(U2, T1, T2, g, st));
+    // X (D1 x D2 D3) = U1 (D1 x r1) T2 (r1 x D2 D3)
+    g = GemmArgs{};
+    g.M = D1; g.N = D2 * D3; g.K = r1; g.batch = 1;
+    g.sam = r1; g.sak = 1; g.sbk = (int64_t)D2 * D3; g.sbn = 1; g.scm = (int64_t)D2 * D3; g.scn = 1;
+    VC_HIP(launch_mfma_gemm<T>(U1, T2, R + (int64_t)q * pair_stride, g, st));
+  }
+  return VC_OK;
+}
+
+template vc_status tucker_rebuild<float>(vc_problem*, float*, int64_t, hipStream_t);
+template vc_status tucker_rebuild<double>(vc_problem*, double*, int64_t, hipStream_t);
+
+}  // namespace vc

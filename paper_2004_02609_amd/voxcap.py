@@ -80,6 +80,8 @@ _sig = {
     "vc_profile_enable": (C.c_int, [_P, C.c_int]),
     "vc_pass_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "vc_tuning_report": (C.c_int, [_P, C.c_char_p, C.c_int32]),
+    "vc_tucker_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "vc_charges_to_capacitance": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
     "vc_charges_to_capacitance_adjoint": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
     "vc_xpass_candidates": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int32), C.c_int32,
@@ -194,6 +196,19 @@ def vc_charges_to_capacitance(h, rho, C_out, nrhs, stream=None):
 def vc_charges_to_capacitance_adjoint(h, gC, grho, nrhs, stream=None):
     _check(_lib.vc_charges_to_capacitance_adjoint(h, _ptr(gC), int(nrhs), _ptr(grho), _stream(stream)),
            "vc_charges_to_capacitance_adjoint")
+
+
+def vc_tucker_info(h):
+    n = C.c_int32(0)
+    ranks = (C.c_int32 * 45)()
+    st, full, ms = C.c_double(0), C.c_double(0), C.c_double(0)
+    cnt = C.c_int32(0)
+    _check(_lib.vc_tucker_info(h, C.byref(n), ranks, C.byref(st), C.byref(full), C.byref(ms), C.byref(cnt)),
+           "vc_tucker_info")
+    r = [tuple(ranks[3 * q:3 * q + 3]) for q in range(n.value)]
+    return {"npairs": n.value, "ranks": r, "stored_numbers": st.value, "full_numbers": full.value,
+            "compression_ratio": (full.value / st.value) if st.value > 0 else None,
+            "rebuild_ms": ms.value, "rebuilds": cnt.value}
 
 
 def vc_tuning_report(h):
@@ -323,6 +338,10 @@ class Problem:
 
     def xpass_set(self, cfg, prec="fp64", transpose=False, nrhs=1):
         vc_xpass_set(self._h, cfg, prec, transpose, nrhs)
+
+    def tucker_info(self):
+        """Ranks, compression ratio and rebuild timing of the Tucker-compressed spectra."""
+        return vc_tucker_info(self._h)
 
     def tuning_report(self):
         """Launch configurations of the x pass in use (and what the autotuner measured)."""
