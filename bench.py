@@ -150,6 +150,87 @@ def write_traffic(args):
     print(json.dumps(res, indent=1))
 
 
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+
+
+def tucker_run(args, scene, x, stream, B, ms_product_full):
+    """The same product with the spectra Tucker-compressed (eq. 13) and rebuilt on the
+    matrix cores before each product: compression ratio, rebuild time, the paper's
+    computational overhead CO = rebuild time / one product, and the rebuild's MFMA
+    rate (dense GEMM flops of the three mode products) and output bandwidth."""
+    import torch
+
+    from paper_2004_02609_amd import voxcap
+    Pt = voxcap.Problem.from_scene(scene).setup(tucker_tol=args.tucker_tol, autotune=not args.no_tune,
+                                                precisions=2 if args.prec == "fp32" else 1)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        Pt.apply(x, y, prec=args.prec, stream=stream)
+    torch.cuda.synchronize()
+    Pt.tucker_info()                       # drop what was recorded before
+    base = Pt.tucker_info()
+    steps = max(5, args.steps // 4)
+    Pt.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        Pt.apply(x, y, prec=args.prec, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    Pt.profile(False)
+    ms = e0.elapsed_time(e1) / steps
+    info = Pt.tucker_info()
+    n_rb = info["rebuilds"] - base["rebuilds"]
+    rb_ms = (info["rebuild_ms"] - base["rebuild_ms"]) / max(1, n_rb)
+    D = (Pt.fft_size()[0] // 2 + 1, Pt.fft_size()[1] // 2 + 1, Pt.fft_size()[2] // 2 + 1)
+    flops = 0.0
+    out_bytes = 0.0
+    elem = 4 if args.prec == "fp32" else 8
+    for r1, r2, r3 in info["ranks"]:
+        flops += 2.0 * (r1 * r2 * r3 * D[2] + r1 * r2 * D[1] * D[2] + r1 * D[0] * D[1] * D[2])
+        out_bytes += elem * (D[0] * D[1] * D[2] + 2 * r1 * D[1] * D[2])   # X written, T2 written and read
+    tf = flops / (rb_ms / 1e3) / 1e12
+    return {"tol": args.tucker_tol, "ranks": info["ranks"], "compression_ratio": info["compression_ratio"],
+            "product_ms_with_rebuild": ms, "rebuild_ms": rb_ms,
+            "computational_overhead": rb_ms / ms_product_full,
+            "rhs_products_per_s": B / (ms / 1e3),
+            "rebuild_mfma": {"flops": flops, "achieved_tflops": tf, "peak_tflops": MFMA_PEAK_TFLOPS[args.prec],
+                             "frac": tf / MFMA_PEAK_TFLOPS[args.prec]},
+            "rebuild_hbm": {"bytes": out_bytes, "achieved_gbs": out_bytes / (rb_ms / 1e3) / 1e9,
+                            "peak_gbs": HBM_PEAK_GBS}}
+
+
+def batch_run(args):
+    """Uneven batch: `args.batch` independent random scenes (grid edges U{16..64}, 1-4
+    conductors, half with a dielectric box) solved in mixed precision together (one
+    graph launch per round) and one after another; rtol 1e-9."""
+    import numpy as np
+    import torch
+
+    import scenes
+    from paper_2004_02609_amd import voxcap
+    ss = scenes.uneven_batch(args.batch)
+    t0 = time.perf_counter()
+    probs = [voxcap.Problem.from_scene(s).setup() for s in ss]
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    voxcap.capacitance_batch(probs, prec="mixed", rtol=1e-9)          # captures every cycle graph
+    for P in probs:
+        P.capacitance(prec="mixed", rtol=1e-9)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Cb, stb = voxcap.capacitance_batch(probs, prec="mixed", rtol=1e-9)
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Cs = [P.capacitance(prec="mixed", rtol=1e-9)[0] for P in probs]
+    t_seq = time.perf_counter() - t0
+    diff = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(Cb, Cs))
+    return {"scenes": len(ss), "panels_total": int(sum(P.N for P in probs)),
+            "conductors_total": int(sum(P.m for P in probs)), "setup_s": t_setup,
+            "batched_solve_s": t_batch, "sequential_solve_s": t_seq, "speedup": t_seq / t_batch,
+            "scenes_per_s_batched": len(ss) / t_batch, "max_rel_diff_batch_vs_single": diff}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +242,10 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="heuristic x-pass configuration instead of the autotuner")
     ap.add_argument("--no-other", action="store_true", help="skip the product in the other precision")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="also solve this many uneven random scenes (edges 16-64) together and one by one")
+    ap.add_argument("--tucker-tol", type=float, default=1e-8,
+                    help="also run the product with Tucker-compressed spectra at this tolerance (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (HBM-counter calibration under rocprofv3 --pmc)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -262,6 +347,14 @@ def main():
         P.capacitance(prec="fp64", rtol=1e-9, graph=False)
         solve["fp64_no_graph_time_s"] = time.perf_counter() - t0
 
+    tucker = None
+    if args.tucker_tol > 0:
+        tucker = tucker_run(args, scene, x, stream, B, ms / args.steps)
+
+    batch = None
+    if args.batch > 0:
+        batch = batch_run(args)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(scene, B)
@@ -281,6 +374,8 @@ def main():
         "solve": solve,
         "setup_s": t_setup,
         "xpass_tuning": P.tuning_report().strip().splitlines(),
+        "tucker": tucker,
+        "batch": batch,
     }
     print(json.dumps(line), flush=True)
 

@@ -159,6 +159,15 @@ vc_status vc_apply_precond(vc_problem *p, int transpose, const double *x_dev, do
 vc_status vc_capacitance(vc_problem *p, const vc_solve_opts *opts, double *C, double *rho_dev,
                          vc_stats *stats);
 
+/* Capacitance matrices of n independent problems of any sizes (each after vc_setup, all
+ * on one device), solved together: every round replays, in ONE graph launch, the next
+ * restart cycle of every unfinished problem (independent branches the GPU overlaps);
+ * mixed precision runs its FP64 refinement steps between rounds.  C_out[k]: m_k x m_k
+ * host doubles (row-major); stats: optional array of n.  Returns the first failing
+ * status; every problem's outputs are still written. */
+vc_status vc_capacitance_batch(vc_problem *const *problems, int32_t n, const vc_solve_opts *opts,
+                               double *const *C_out, vc_stats *stats);
+
 /* dC/d(eps_r of block b) for every block (nblocks x m x m, row-major, farads per unit
  * relative permittivity) by one adjoint solve per conductor (A^T lambda_i = w_i).
  * block_of_voxel: nx*ny*nz host ids in [-1, nblocks).  C_out: optional m x m. */

@@ -144,7 +144,7 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
       if (!(t0 = take_event(P)) || !(t1 = take_event(P))) { set_error("hipEventCreate failed"); return VC_ERR_HIP; }
       VC_HIP(hipEventRecord(t0, st));
     }
-    vc_status ts = tucker_rebuild<T>(P, (T*)tb.R.p, (int64_t)P->Hy * H * P->Hx, st);
+    vc_status ts = tucker_rebuild<T>(P, (T*)tb.R.p, (int64_t)P->Hy * H * P->Hx, st, skip);
     if (ts != VC_OK) return ts;
     if (prof) {
       VC_HIP(hipEventRecord(t1, st));

@@ -125,14 +125,14 @@ hipError_t launch_gemv_t(const double* V, int64_t ldv, int64_t N, int k, const d
 int64_t gemv_t_partial_size(int64_t N, int kmax, int nrhs);
 hipError_t launch_gemv_n_sub(const double* V, int64_t ldv, int64_t N, int k, const double* h, int64_t ldh,
                              double* w, int64_t ldw, int nrhs, const int* active, int accumulate_into_h2,
-                             hipStream_t st);
+                             hipStream_t st, const int* kcol = nullptr);
 hipError_t launch_colnorm(const double* w, int64_t ldw, int64_t N, int nrhs, double* out, double* partial,
-                          hipStream_t st);
+                          hipStream_t st, const int* skip = nullptr);
 int64_t colnorm_partial_size(int64_t N, int nrhs);
 hipError_t launch_scale_cols(double* w, int64_t ldw, int64_t N, int nrhs, const double* s, int mode,
                              hipStream_t st);
 hipError_t launch_axpy_cols(double* y, const double* x, int64_t N, int nrhs, const double* a, int sub,
-                            hipStream_t st);
+                            hipStream_t st, const int* skip = nullptr);
 hipError_t launch_diag_scale(const double* x, double* y, const double* dinv, int64_t N, int nrhs, const int* skip,
                              hipStream_t st);
 hipError_t launch_block_apply(const double* x, double* y, int64_t N, int nrhs, const int32_t* box_ptr,
@@ -162,6 +162,7 @@ struct GemmArgs {
   int M, N, K, batch;
   int64_t sam, sak, sbk, sbn, scm, scn;   // A[m][k], B[k][n], C[m][n]
   int64_t bsa, bsb, bsc;                  // batch strides
+  const int* skip;                        // optional device flag: when set, the launch does nothing
 };
 template <typename T>
 hipError_t launch_mfma_gemm(const T* A, const T* B, T* C, const GemmArgs& g, hipStream_t st);

@@ -211,7 +211,8 @@ vc_status build_precond(vc_problem* p, hipStream_t st);
 vc_status tucker_begin(vc_problem* p, double tol);
 vc_status tucker_compress_pair(vc_problem* p, const double* X, hipStream_t st);
 vc_status tucker_end(vc_problem* p);
-template <typename T> vc_status tucker_rebuild(vc_problem* p, T* R, int64_t pair_stride, hipStream_t st);
+template <typename T>
+vc_status tucker_rebuild(vc_problem* p, T* R, int64_t pair_stride, hipStream_t st, const int* skip = nullptr);
 vc_status apply_op(vc_problem* p, int transpose, vc_precision prec, const double* x, double* y, int nrhs,
                    hipStream_t st, const int* skip = nullptr);
 vc_status apply_precond(vc_problem* p, int transpose, const double* x, double* y, int nrhs, hipStream_t st,

@@ -1,0 +1,337 @@
+// GMRES driver of the solve: restarted, several right-hand sides in lock-step,
+// right-preconditioned with eq. (14) (Sec. II.D); every step of a restart cycle runs on
+// the device (capturable as a graph); FP32-product GMRES inside FP64 refinement.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mvp_kernels.h"
+#include "problem.h"
+#include "solver.h"
+
+namespace vc {
+
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------------------------ GMRES
+
+vc_status ensure_workspace(vc_problem* P, int nrhs, int restart) {
+  if (P->s_nrhs >= nrhs && P->s_restart >= restart) return VC_OK;
+  const int64_t N = npanels(P);
+  const int r = std::max(restart, P->s_restart), k = std::max(nrhs, P->s_nrhs);
+  if (k > 64) { set_error("at most 64 right-hand sides per solve"); return VC_ERR_ARG; }
+  P->drop_graphs();   // captured graphs hold pointers into the old workspace
+  VC_HIP(P->s_V.alloc((size_t)(r + 1) * k * N * sizeof(double)));
+  VC_HIP(P->s_w.alloc((size_t)k * N * sizeof(double)));
+  VC_HIP(P->s_z.alloc((size_t)k * N * sizeof(double)));
+  VC_HIP(P->s_r.alloc((size_t)k * N * sizeof(double)));
+  VC_HIP(P->s_b.alloc((size_t)k * N * sizeof(double)));
+  VC_HIP(P->s_x.alloc((size_t)k * N * sizeof(double)));
+  VC_HIP(P->s_tmp.alloc((size_t)k * N * sizeof(double)));
+  VC_HIP(P->s_rr.alloc((size_t)k * N * sizeof(double)));
+  VC_HIP(P->s_dd.alloc((size_t)k * N * sizeof(double)));
+  VC_HIP(P->s_h.alloc((size_t)2 * (r + 2) * k * sizeof(double)));
+  VC_HIP(P->s_y2.alloc((size_t)(r + 2) * k * sizeof(double)));
+  VC_HIP(P->s_partial.alloc((size_t)std::max(gemv_t_partial_size(N, r + 2, k), colnorm_partial_size(N, k)) *
+                            sizeof(double)));
+  VC_HIP(P->s_norm.alloc((size_t)4 * k * sizeof(double)));
+  VC_HIP(P->s_active.alloc((size_t)k * sizeof(int)));
+  // device-side cycle state: H, cs, sn, g, bn, rn, rre, scal (doubles); kd, iters,
+  // act_cycle, act_step (ints) + skip[2], bad
+  const size_t nd = (size_t)k * ((size_t)(r + 1) * r + 2 * r + (r + 1) + 4) + 1;
+  VC_HIP(P->s_cyc.alloc(nd * sizeof(double)));
+  VC_HIP(P->s_cyci.alloc(((size_t)4 * k + 5) * sizeof(int)));
+  P->s_nrhs = k;
+  P->s_restart = r;
+  return VC_OK;
+}
+
+Cyc cycle_views(vc_problem* P, int nrhs, int m) {
+  Cyc c{};
+  double* d = P->s_cyc.as<double>();
+  c.H = d; d += (size_t)nrhs * (m + 1) * m;
+  c.cs = d; d += (size_t)nrhs * m;
+  c.sn = d; d += (size_t)nrhs * m;
+  c.g = d; d += (size_t)nrhs * (m + 1);
+  c.bn = d; d += nrhs;
+  c.rn = d; d += nrhs;
+  c.rre = d; d += nrhs;
+  c.scal = d; d += nrhs;
+  c.rtol = d;
+  int* q = P->s_cyci.as<int>();
+  c.kd = q; q += nrhs;
+  c.iters = q; q += nrhs;
+  c.act_cycle = q; q += nrhs;
+  c.act_step = q; q += nrhs;
+  c.skip = q; q += 3;   // [0] cycle-level, [1] step-level, [2] problem disabled (batch)
+  c.bad = q;
+  return c;
+}
+
+// z = R v (if preconditioned), w = A z; skipped entirely when *skip
+vc_status op_with_precond(vc_problem* P, const SolveSpec& sp, const double* v, double* z, double* w, int nrhs,
+                          hipStream_t st, const int* skip) {
+  const double* src = v;
+  if (sp.precond) {
+    P->pc.mode = sp.precond;
+    vc_status s = apply_precond(P, sp.transpose, v, z, nrhs, st, skip);
+    if (s != VC_OK) return s;
+    src = z;
+  }
+  return apply_op(P, sp.transpose, sp.mvp, src, w, nrhs, st, skip);
+}
+
+// r = b - A x
+vc_status residual(vc_problem* P, const SolveSpec& sp, const double* b, const double* x, double* r, int nrhs,
+                   hipStream_t st, const int* skip) {
+  const int64_t N = npanels(P);
+  vc_status s = apply_op(P, sp.transpose, sp.mvp, x, r, nrhs, st, skip);
+  if (s != VC_OK) return s;
+  VC_HIP(launch_axpy_cols(r, b, N, nrhs, nullptr, 1, st, skip));
+  return VC_OK;
+}
+
+vc_status col_norms(vc_problem* P, const double* w, int64_t N, int nrhs, double* d_out, std::vector<double>& h,
+                           hipStream_t st) {
+  VC_HIP(launch_colnorm(w, N, N, nrhs, d_out, P->s_partial.as<double>(), st));
+  h.resize(nrhs);
+  VC_HIP(hipMemcpyAsync(h.data(), d_out, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+  VC_HIP(hipStreamSynchronize(st));
+  return VC_OK;
+}
+
+// One GMRES(m) restart cycle, every step on the device (so it can be captured):
+// residual and its norms, cycle start (masks, g, skip flags), m Arnoldi steps with
+// classical Gram-Schmidt applied twice and the Givens update, then x += R V y for the
+// columns that were active at the start.  Columns freeze once converged; when all
+// have, the remaining steps' products are skipped by the device flag.
+vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs,
+                             hipStream_t st) {
+  const int64_t N = npanels(P);
+  const int m = sp.restart;
+  const Cyc c = cycle_views(P, nrhs, m);
+  double* V = P->s_V.as<double>();
+  double* w = P->s_w.as<double>();
+  double* z = P->s_z.as<double>();
+  double* r = P->s_r.as<double>();
+  double* hd = P->s_h.as<double>();
+  double* y2 = P->s_y2.as<double>();
+  double* nrm = P->s_norm.as<double>();
+  const int64_t ldv = (int64_t)nrhs * N;
+  const int ldh = m + 2;
+  vc_status s = residual(P, sp, b, x, r, nrhs, st, c.skip + 2);
+  if (s != VC_OK) return s;
+  VC_HIP(launch_colnorm(r, N, N, nrhs, c.rn, P->s_partial.as<double>(), st, c.skip + 2));
+  VC_HIP(launch_cycle_start(nrhs, m, c.rn, c.bn, c.rtol, c.act_cycle, c.act_step, c.g, c.scal, c.kd, c.skip, c.rre,
+                            st));
+  VC_HIP(launch_scale_copy(V, r, N, nrhs, c.scal, c.skip, st));   // V_0 = r / |r|
+  for (int j = 0; j < m; ++j) {
+    s = op_with_precond(P, sp, V + j * ldv, z, w, nrhs, st, c.skip + 1);
+    if (s != VC_OK) return s;
+    VC_HIP(launch_gemv_t(V, ldv, N, j + 1, w, N, nrhs, hd, ldh, c.act_step, P->s_partial.as<double>(), st));
+    VC_HIP(launch_gemv_n_sub(V, ldv, N, j + 1, hd, ldh, w, N, nrhs, c.act_step, 0, st));
+    VC_HIP(launch_gemv_t(V, ldv, N, j + 1, w, N, nrhs, hd + (size_t)ldh * nrhs, ldh, c.act_step,
+                         P->s_partial.as<double>(), st));
+    VC_HIP(launch_gemv_n_sub(V, ldv, N, j + 1, hd + (size_t)ldh * nrhs, ldh, w, N, nrhs, c.act_step, 0, st));
+    VC_HIP(launch_colnorm(w, N, N, nrhs, nrm, P->s_partial.as<double>(), st));
+    VC_HIP(launch_arnoldi(j, nrhs, m, hd, hd + (size_t)ldh * nrhs, ldh, nrm, c.H, c.cs, c.sn, c.g, c.bn, c.rtol,
+                          c.act_step, c.kd, c.iters, c.scal, c.skip, c.bad, st));
+    if (j + 1 < m) VC_HIP(launch_scale_copy(V + (j + 1) * ldv, w, N, nrhs, c.scal, c.skip + 1, st));
+  }
+  // x += R V y, y = R_H^{-1} g over each column's steps
+  VC_HIP(launch_backsolve(nrhs, m, c.H, c.g, c.kd, c.act_cycle, y2, ldh, st));
+  VC_HIP(launch_zero(w, (int64_t)nrhs * N, st));
+  VC_HIP(launch_gemv_n_sub(V, ldv, N, m, y2, ldh, w, N, nrhs, c.act_cycle, 0, st, c.kd));   // w = V y
+  const double* upd = w;
+  if (sp.precond) {
+    P->pc.mode = sp.precond;
+    s = apply_precond(P, sp.transpose, w, z, nrhs, st, c.skip);
+    if (s != VC_OK) return s;
+    upd = z;
+  }
+  VC_HIP(launch_add_active(x, upd, N, nrhs, c.act_cycle, c.skip, st));
+  return VC_OK;
+}
+
+// The captured restart cycle for this solve shape (captured and instantiated on first
+// use).  An eager product first settles the launch configurations (and runs the
+// autotuner) outside the capture.
+vc_status cycle_graph(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs, hipStream_t st,
+                      hipGraph_t* g_out, hipGraphExec_t* e_out) {
+  vc_problem::GraphKey key{(int)sp.mvp, sp.transpose, sp.precond, nrhs, sp.restart, b, x};
+  for (const auto& e : P->graphs)
+    if (e.key == key) {
+      *g_out = e.graph;
+      *e_out = e.exec;
+      return VC_OK;
+    }
+  vc_status s = apply_op(P, sp.transpose, sp.mvp, b, P->s_tmp.as<double>(), nrhs, st);
+  if (s != VC_OK) return s;
+  VC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  vc_status sc = issue_cycle(P, sp, b, x, nrhs, st);
+  hipGraph_t gr = nullptr;
+  const hipError_t ee = hipStreamEndCapture(st, &gr);
+  if (sc != VC_OK) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return sc;
+  }
+  if (ee != hipSuccess) { set_error("graph capture failed: %s", hipGetErrorString(ee)); return VC_ERR_HIP; }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(gr);
+    set_error("graph instantiation failed: %s", hipGetErrorString(ei));
+    return VC_ERR_HIP;
+  }
+  P->add_graph(key, gr, ex);
+  *g_out = gr;
+  *e_out = ex;
+  return VC_OK;
+}
+
+// Solve A x = b (x holds the initial guess).  iters/rre: per column outputs.  With
+// graphs on, every cycle replays one graph captured at the first solve of this shape
+// (rtol is read from device memory, so solves to any tolerance share it); an eager
+// product before the capture settles the autotuned launch configuration.
+vc_status gmres(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs,
+                       std::vector<int>& iters, std::vector<double>& rre, hipStream_t st) {
+  const int64_t N = npanels(P);
+  const int m = sp.restart;
+  vc_status s = ensure_workspace(P, nrhs, m);
+  if (s != VC_OK) return s;
+  const Cyc c = cycle_views(P, nrhs, m);
+  VC_HIP(hipMemcpyAsync(c.rtol, &sp.rtol, sizeof(double), hipMemcpyHostToDevice, st));
+  VC_HIP(launch_colnorm(b, N, N, nrhs, c.bn, P->s_partial.as<double>(), st));
+  VC_HIP(hipMemsetAsync(c.iters, 0, (size_t)nrhs * sizeof(int), st));
+  VC_HIP(hipMemsetAsync(c.bad, 0, sizeof(int), st));
+  VC_HIP(hipMemsetAsync(c.skip + 2, 0, sizeof(int), st));
+  std::vector<int> it(nrhs), skip(2);
+  rre.assign(nrhs, 0.0);
+  int bad = 0;
+  for (int cycle = 0;; ++cycle) {
+    if (P->use_graphs) {
+      hipGraph_t gr = nullptr;
+      hipGraphExec_t ex = nullptr;
+      s = cycle_graph(P, sp, b, x, nrhs, st, &gr, &ex);
+      if (s != VC_OK) return s;
+      VC_HIP(hipGraphLaunch(ex, st));
+    } else {
+      s = issue_cycle(P, sp, b, x, nrhs, st);
+      if (s != VC_OK) return s;
+    }
+    VC_HIP(hipMemcpyAsync(rre.data(), c.rre, (size_t)nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    VC_HIP(hipMemcpyAsync(it.data(), c.iters, (size_t)nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+    VC_HIP(hipMemcpyAsync(skip.data(), c.skip, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    VC_HIP(hipMemcpyAsync(&bad, c.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    VC_HIP(hipStreamSynchronize(st));
+    iters = it;
+    for (int k = 0; k < nrhs; ++k)
+      if (!std::isfinite(rre[k])) { set_error("non-finite residual in column %d", k); return VC_ERR_NUMERIC; }
+    if (bad) { set_error("non-finite Arnoldi coefficient"); return VC_ERR_NUMERIC; }
+    if (skip[0]) return VC_OK;   // every column met rtol at the start of this cycle
+    const int total = *std::max_element(it.begin(), it.end());
+    if (total >= sp.max_iter) {
+      // this cycle already advanced x: report the residual it starts from
+      set_error("GMRES did not reach rtol %.3g in %d iterations (worst rre %.3g at the last restart)", sp.rtol,
+                total, *std::max_element(rre.begin(), rre.end()));
+      return VC_ERR_NOT_CONVERGED;
+    }
+  }
+}
+
+// the (blocking, default-priority) stream the solves run on: graphs cannot be captured
+// on the null stream, and a blocking stream stays ordered with null-stream copies
+hipStream_t get_solve_stream(vc_problem* P) {
+  if (!P->solve_stream && hipStreamCreate(&P->solve_stream) != hipSuccess) P->solve_stream = nullptr;
+  return P->solve_stream;
+}
+
+// FP64 solve, or FP32-product GMRES inside FP64 refinement (VC_MIXED).
+vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const double* b, double* x, int nrhs,
+                       vc_stats* stats, hipStream_t st) {
+  const int64_t N = npanels(P);
+  SolveSpec sp{};
+  sp.transpose = transpose;
+  sp.precond = o.use_precond;
+  sp.restart = o.restart;
+  sp.max_iter = o.max_iter;
+  std::vector<int> it;
+  std::vector<double> rre;
+  P->use_graphs = o.graph == 0;
+  if (!st) st = get_solve_stream(P);
+  if (!st) { set_error("could not create the solve stream"); return VC_ERR_HIP; }
+  VC_HIP(hipMemsetAsync(x, 0, (size_t)nrhs * N * sizeof(double), st));
+  int ir_steps = 0;
+  vc_status s;
+  if (o.prec != VC_MIXED) {
+    sp.mvp = o.prec == VC_FP32 ? VC_FP32 : VC_FP64;
+    sp.rtol = o.rtol;
+    s = gmres(P, sp, b, x, nrhs, it, rre, st);
+  } else {
+    // outer FP64 refinement: r = b - A x (FP64 product), inner FP32 GMRES on A d = r, x += d
+    s = ensure_workspace(P, nrhs, o.restart);
+    if (s != VC_OK) return s;
+    double* rrp = P->s_rr.as<double>();   // stable buffers: the inner solves reuse their graph
+    double* ddp = P->s_dd.as<double>();
+    std::vector<int> tot(nrhs, 0);
+    SolveSpec s64 = sp;
+    s64.mvp = VC_FP64;
+    std::vector<double> bn, rn;
+    s = col_norms(P, b, N, nrhs, P->s_norm.as<double>(), bn, st);
+    if (s != VC_OK) return s;
+    VC_HIP(hipMemcpyAsync(rrp, b, (size_t)nrhs * N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    s = VC_ERR_NOT_CONVERGED;
+    rre.assign(nrhs, 1.0);
+    for (ir_steps = 0; ir_steps < o.ir_max; ++ir_steps) {
+      SolveSpec s32 = sp;
+      s32.mvp = VC_FP32;
+      s32.rtol = o.inner_rtol;
+      VC_HIP(hipMemsetAsync(ddp, 0, (size_t)nrhs * N * sizeof(double), st));
+      vc_status si = gmres(P, s32, rrp, ddp, nrhs, it, rre, st);
+      if (si != VC_OK && si != VC_ERR_NOT_CONVERGED) return si;
+      for (int c = 0; c < nrhs; ++c) tot[c] += it[c];
+      std::vector<double> ones(nrhs, 1.0);
+      VC_HIP(hipMemcpyAsync(P->s_norm.as<double>() + nrhs, ones.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+      VC_HIP(launch_axpy_cols(x, ddp, N, nrhs, P->s_norm.as<double>() + nrhs, 0, st));
+      vc_status sr = residual(P, s64, b, x, rrp, nrhs, st);
+      if (sr != VC_OK) return sr;
+      sr = col_norms(P, rrp, N, nrhs, P->s_norm.as<double>(), rn, st);
+      if (sr != VC_OK) return sr;
+      bool ok = true;
+      for (int c = 0; c < nrhs; ++c) {
+        rre[c] = bn[c] > 0 ? rn[c] / bn[c] : 0.0;
+        if (rre[c] > o.rtol) ok = false;
+      }
+      if (ok) { s = VC_OK; ++ir_steps; break; }
+    }
+    it = tot;
+    if (s != VC_OK) set_error("refinement did not reach rtol %.3g in %d steps", o.rtol, o.ir_max);
+  }
+  if (stats) {
+    for (int c = 0; c < nrhs && c < 64; ++c) {
+      stats->iters[c] = c < (int)it.size() ? it[c] : 0;
+      stats->final_rre[c] = c < (int)rre.size() ? rre[c] : 0.0;
+    }
+    stats->ir_steps = ir_steps;
+  }
+  return s;
+}
+
+vc_solve_opts fill_defaults(const vc_solve_opts* in) {
+  vc_solve_opts o{};
+  if (in) o = *in;
+  if (o.rtol <= 0) o.rtol = 1e-12;
+  if (o.restart <= 0) o.restart = 35;
+  if (o.max_iter <= 0) o.max_iter = 2000;
+  if (o.inner_rtol <= 0) o.inner_rtol = 1e-5;
+  if (o.ir_max <= 0) o.ir_max = 20;
+  if (!in) o.use_precond = 1;
+  return o;
+}
+
+}  // namespace vc

@@ -1,0 +1,49 @@
+// Internal interface of the GMRES driver (solver.cpp) shared by the C ABI (api.cpp)
+// and the multi-scene batch driver (batch.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "problem.h"
+
+namespace vc {
+
+constexpr double kEps0 = 8.8541878128e-12;   // F/m (CODATA 2018)
+
+struct SolveSpec {
+  vc_precision mvp;     // VC_FP64 or VC_FP32 product
+  int transpose;
+  int precond;          // 0 none, 1 block-diagonal-diagonal, 2 diagonal
+  double rtol;
+  int restart, max_iter;
+};
+
+// views of the cycle state for one (nrhs, restart) solve
+struct Cyc {
+  double *H, *cs, *sn, *g, *bn, *rn, *rre, *scal, *rtol;
+  int *kd, *iters, *act_cycle, *act_step, *skip, *bad;
+};
+
+double now_s();
+vc_status ensure_workspace(vc_problem* P, int nrhs, int restart);
+Cyc cycle_views(vc_problem* P, int nrhs, int m);
+vc_status op_with_precond(vc_problem* P, const SolveSpec& sp, const double* v, double* z, double* w, int nrhs,
+                          hipStream_t st, const int* skip = nullptr);
+vc_status residual(vc_problem* P, const SolveSpec& sp, const double* b, const double* x, double* r, int nrhs,
+                   hipStream_t st, const int* skip = nullptr);
+vc_status col_norms(vc_problem* P, const double* w, int64_t N, int nrhs, double* d_out, std::vector<double>& h,
+                    hipStream_t st);
+vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs, hipStream_t st);
+vc_status cycle_graph(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs, hipStream_t st,
+                      hipGraph_t* g_out, hipGraphExec_t* e_out);
+vc_status gmres(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs, std::vector<int>& iters,
+                std::vector<double>& rre, hipStream_t st);
+hipStream_t get_solve_stream(vc_problem* P);
+vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const double* b, double* x, int nrhs,
+                vc_stats* stats, hipStream_t st);
+vc_solve_opts fill_defaults(const vc_solve_opts* in);
+vc_status batch_capacitance(vc_problem* const* problems, int n, const vc_solve_opts* opts, double* const* C_out,
+                            vc_stats* stats);
+
+}  // namespace vc

@@ -101,29 +101,34 @@ int64_t gemv_t_partial_size(int64_t N, int kmax, int nrhs) {
   return ((N + kDotChunk - 1) / kDotChunk) * (int64_t)nrhs * kmax;
 }
 
-// w[r] -= sum_{i<k} V_i[r] h[r*ldh + i]
+// w[r] -= sum_{i<k_r} V_i[r] h[r*ldh + i], k_r = kcol[r] when given (basis vectors past
+// a column's own count are never read: they may hold stale memory), else k
 __global__ void k_gemv_n_sub(const double* __restrict__ V, int64_t ldv, int64_t N, int k, const double* __restrict__ h,
-                             int64_t ldh, double* __restrict__ w, int64_t ldw, const int* __restrict__ active) {
+                             int64_t ldh, double* __restrict__ w, int64_t ldw, const int* __restrict__ active,
+                             const int* __restrict__ kcol) {
   const int r = blockIdx.y;
   if (active && !active[r]) return;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
+  const int kr = kcol ? min(kcol[r], k) : k;
   double acc = 0.0;
-  for (int i = 0; i < k; ++i) acc += V[(int64_t)i * ldv + (int64_t)r * N + n] * h[(int64_t)r * ldh + i];
+  for (int i = 0; i < kr; ++i) acc += V[(int64_t)i * ldv + (int64_t)r * N + n] * h[(int64_t)r * ldh + i];
   w[(int64_t)r * ldw + n] -= acc;
 }
 
 hipError_t launch_gemv_n_sub(const double* V, int64_t ldv, int64_t N, int k, const double* h, int64_t ldh, double* w,
-                             int64_t ldw, int nrhs, const int* active, int, hipStream_t st) {
+                             int64_t ldw, int nrhs, const int* active, int, hipStream_t st, const int* kcol) {
   hipLaunchKernelGGL(k_gemv_n_sub, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, V, ldv, N, k, h, ldh,
-                     w, ldw, active);
+                     w, ldw, active, kcol);
   return hipGetLastError();
 }
 
 // column 2-norms: per-chunk partial sums of squares (wave shuffles, fixed order), then
 // one thread per column adds the chunks and takes the root
 __global__ void __launch_bounds__(kRedThreads)
-k_sumsq_partial(const double* __restrict__ w, int64_t ldw, int64_t N, int nrhs, double* __restrict__ partial) {
+k_sumsq_partial(const double* __restrict__ w, int64_t ldw, int64_t N, int nrhs, double* __restrict__ partial,
+                const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double red[kRedThreads / 64];
   const int chunk = blockIdx.x, r = blockIdx.y;
   const int64_t n0 = (int64_t)chunk * kDotChunk;
@@ -141,7 +146,9 @@ k_sumsq_partial(const double* __restrict__ w, int64_t ldw, int64_t N, int nrhs, 
   }
 }
 
-__global__ void k_sumsq_final(const double* __restrict__ partial, int nchunk, int nrhs, double* __restrict__ out) {
+__global__ void k_sumsq_final(const double* __restrict__ partial, int nchunk, int nrhs, double* __restrict__ out,
+                              const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrhs) return;
   double s = 0.0;
@@ -151,10 +158,10 @@ __global__ void k_sumsq_final(const double* __restrict__ partial, int nchunk, in
 
 // norms of nrhs columns; partial: caller workspace of colnorm_partial_size(N, nrhs)
 hipError_t launch_colnorm(const double* w, int64_t ldw, int64_t N, int nrhs, double* out, double* partial,
-                          hipStream_t st) {
+                          hipStream_t st, const int* skip) {
   const int nchunk = (int)((N + kDotChunk - 1) / kDotChunk);
-  hipLaunchKernelGGL(k_sumsq_partial, dim3(nchunk, nrhs), dim3(kRedThreads), 0, st, w, ldw, N, nrhs, partial);
-  hipLaunchKernelGGL(k_sumsq_final, dim3((nrhs + 63) / 64), dim3(64), 0, st, partial, nchunk, nrhs, out);
+  hipLaunchKernelGGL(k_sumsq_partial, dim3(nchunk, nrhs), dim3(kRedThreads), 0, st, w, ldw, N, nrhs, partial, skip);
+  hipLaunchKernelGGL(k_sumsq_final, dim3((nrhs + 63) / 64), dim3(64), 0, st, partial, nchunk, nrhs, out, skip);
   return hipGetLastError();
 }
 
@@ -180,7 +187,8 @@ hipError_t launch_scale_cols(double* w, int64_t ldw, int64_t N, int nrhs, const 
 
 // y[r] += a[r] x[r] (sub = 0) or y[r] = x[r] - y[r] (sub = 1, a unused)
 __global__ void k_axpy_cols(double* __restrict__ y, const double* __restrict__ x, int64_t N,
-                            const double* __restrict__ a, int sub) {
+                            const double* __restrict__ a, int sub, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int r = blockIdx.y;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
@@ -190,8 +198,8 @@ __global__ void k_axpy_cols(double* __restrict__ y, const double* __restrict__ x
 }
 
 hipError_t launch_axpy_cols(double* y, const double* x, int64_t N, int nrhs, const double* a, int sub,
-                            hipStream_t st) {
-  hipLaunchKernelGGL(k_axpy_cols, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, y, x, N, a, sub);
+                            hipStream_t st, const int* skip) {
+  hipLaunchKernelGGL(k_axpy_cols, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, y, x, N, a, sub, skip);
   return hipGetLastError();
 }
 
@@ -303,6 +311,7 @@ __global__ void k_cycle_start(int nrhs, int m, const double* __restrict__ rn, co
                               const double* __restrict__ rtolp, int* __restrict__ act_cycle, int* __restrict__ act_step,
                               double* __restrict__ g, double* __restrict__ scal, int* __restrict__ kd,
                               int* __restrict__ skip, double* __restrict__ rre_out) {
+  if (skip[2]) return;   // problem disabled for this round (batched form): state left as is
   __shared__ int red[64];
   const int c = threadIdx.x;
   const double rtol = *rtolp;

@@ -169,7 +169,7 @@ vc_status tucker_end(vc_problem* P) {
 }
 
 template <typename T>
-vc_status tucker_rebuild(vc_problem* P, T* R, int64_t pair_stride, hipStream_t st) {
+vc_status tucker_rebuild(vc_problem* P, T* R, int64_t pair_stride, hipStream_t st, const int* skip) {
   const int D1 = P->Hx, D2 = P->Hy, D3 = P->H;
   T* T1 = P->tk_T1.as<T>();
   T* T2 = P->tk_T2.as<T>();
@@ -184,23 +184,26 @@ vc_status tucker_rebuild(vc_problem* P, T* R, int64_t pair_stride, hipStream_t s
     // T1 (r1 r2 x D3) = S (r1 r2 x r3) U3^T
     g.M = r1 * r2; g.N = D3; g.K = r3; g.batch = 1;
     g.sam = r3; g.sak = 1; g.sbk = 1; g.sbn = r3; g.scm = D3; g.scn = 1;
+    g.skip = skip;
     VC_HIP(launch_mfma_gemm<T>(S, U3, T1, g, st));
     // T2[a] (D2 x D3) = U2 (D2 x r2) T1[a] (r2 x D3)
     g = GemmArgs{};
     g.M = D2; g.N = D3; g.K = r2; g.batch = r1;
     g.sam = r2; g.sak = 1; g.sbk = D3; g.sbn = 1; g.scm = D3; g.scn = 1;
     g.bsa = 0; g.bsb = (int64_t)r2 * D3; g.bsc = (int64_t)D2 * D3;
+    g.skip = skip;
     VC_HIP(launch_mfma_gemm<T>(U2, T1, T2, g, st));
     // X (D1 x D2 D3) = U1 (D1 x r1) T2 (r1 x D2 D3)
     g = GemmArgs{};
     g.M = D1; g.N = D2 * D3; g.K = r1; g.batch = 1;
     g.sam = r1; g.sak = 1; g.sbk = (int64_t)D2 * D3; g.sbn = 1; g.scm = (int64_t)D2 * D3; g.scn = 1;
+    g.skip = skip;
     VC_HIP(launch_mfma_gemm<T>(U1, T2, R + (int64_t)q * pair_stride, g, st));
   }
   return VC_OK;
 }
 
-template vc_status tucker_rebuild<float>(vc_problem*, float*, int64_t, hipStream_t);
-template vc_status tucker_rebuild<double>(vc_problem*, double*, int64_t, hipStream_t);
+template vc_status tucker_rebuild<float>(vc_problem*, float*, int64_t, hipStream_t, const int*);
+template vc_status tucker_rebuild<double>(vc_problem*, double*, int64_t, hipStream_t, const int*);
 
 }  // namespace vc

@@ -38,6 +38,7 @@ template <> struct Mfma<double> {
 template <typename T>
 __global__ void __launch_bounds__(256) k_mfma_gemm(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
                                                    GemmArgs g) {
+  if (g.skip && *g.skip) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int m0 = blockIdx.y * 32 + (wave >> 1) * 16;
   const int n0 = blockIdx.x * 32 + (wave & 1) * 16;

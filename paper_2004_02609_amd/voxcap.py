@@ -80,6 +80,8 @@ _sig = {
     "vc_profile_enable": (C.c_int, [_P, C.c_int]),
     "vc_pass_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "vc_tuning_report": (C.c_int, [_P, C.c_char_p, C.c_int32]),
+    "vc_capacitance_batch": (C.c_int, [C.POINTER(_P), C.c_int32, C.POINTER(vc_solve_opts), C.POINTER(C.c_void_p),
+                                       C.POINTER(vc_stats)]),
     "vc_tucker_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                  C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "vc_charges_to_capacitance": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
@@ -211,6 +213,20 @@ def vc_tucker_info(h):
             "rebuild_ms": ms.value, "rebuilds": cnt.value}
 
 
+def vc_capacitance_batch(handles, ms, allow_not_converged=False, **solve):
+    """C matrices (list of m_k x m_k arrays) and stats of several set-up problems solved
+    together (one graph launch per round over all unfinished problems)."""
+    o = _solve_opts(**solve)
+    n = len(handles)
+    hs = (_P * n)(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    Cs = [np.zeros((m, m)) for m in ms]
+    outs = (C.c_void_p * n)(*[c.ctypes.data for c in Cs])
+    st = (vc_stats * n)()
+    status = _check(_lib.vc_capacitance_batch(hs, n, C.byref(o), outs, st), "vc_capacitance_batch",
+                    allow=(VC_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+    return Cs, [stats_dict(st[k], ms[k]) for k in range(n)], status
+
+
 def vc_tuning_report(h):
     buf = C.create_string_buffer(8192)
     _check(_lib.vc_tuning_report(h, buf, len(buf)), "vc_tuning_report")
@@ -281,6 +297,13 @@ def stats_dict(st, nrhs):
     return {"iters": list(st.iters[:nrhs]), "final_rre": list(st.final_rre[:nrhs]), "ir_steps": st.ir_steps,
             "mvp_count": st.mvp_count, "t_setup_s": st.t_setup_s, "t_solve_s": st.t_solve_s,
             "spectra_bytes": st.spectra_bytes}
+
+
+def capacitance_batch(problems, **solve):
+    """Solve several set-up Problems together (uneven sizes welcome); returns
+    ([C_k], [stats_k])."""
+    Cs, sts, _ = vc_capacitance_batch([p._h for p in problems], [p.m for p in problems], **solve)
+    return Cs, sts
 
 
 class Problem:
