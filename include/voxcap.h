@@ -159,12 +159,38 @@ vc_status vc_apply_precond(vc_problem *p, int transpose, const double *x_dev, do
 vc_status vc_capacitance(vc_problem *p, const vc_solve_opts *opts, double *C, double *rho_dev,
                          vc_stats *stats);
 
-/* Capacitance matrices of n independent problems of any sizes (each after vc_setup, all
- * on one device), solved together: every round replays, in ONE graph launch, the next
- * restart cycle of every unfinished problem (independent branches the GPU overlaps);
- * mixed precision runs its FP64 refinement steps between rounds.  C_out[k]: m_k x m_k
- * host doubles (row-major); stats: optional array of n.  Returns the first failing
- * status; every problem's outputs are still written. */
+/* ---- Packed sets: many independent problems of different sizes solved as one
+ * (eq. (8) per member; the product of eq. (11) and preconditioner of eq. (14) of every
+ * member in the same launches).  The members' conductor right-hand sides become the
+ * columns of one block whose rows are the largest member's panel count (zero past each
+ * member's own panels); one GMRES runs over all columns, each column stopping at its
+ * own tolerance, and every restart cycle of the whole set is one graph launch in which
+ * each pass of the product is ONE kernel launch over all members (the x pass: one per
+ * distinct compiled radix).
+ * vc_pack_create: problems[0..n) after vc_setup (uncompressed spectra, max_rhs >= m,
+ * one device, at most 256 conductors in total).  The set keeps pointers into the
+ * members' device tables and work arrays: the members must outlive it and must not be
+ * set up again or solved concurrently with it.  Errors: VC_ERR_ARG / VC_ERR_STATE with
+ * vc_last_error; *out stays NULL. */
+typedef struct vc_pack vc_pack;
+vc_status vc_pack_create(vc_problem *const *problems, int32_t n, vc_pack **out);
+vc_status vc_pack_destroy(vc_pack *pk);
+/* out[0] members, out[1] columns, out[2] rows, out[3] / out[4] kernel launches per
+ * FP64 / FP32 product, out[5] launches per preconditioner application. */
+vc_status vc_pack_info(const vc_pack *pk, int32_t out[6]);
+/* The product of every member at once: x_dev / y_dev hold out[1] columns of out[2]
+ * rows (column-major device doubles); member k's columns (one per conductor, members in
+ * order) carry its panel vector in their first N_k rows.  Rows past N_k of y are left
+ * as they are.  Same per-member arithmetic as vc_apply (transpose 0); stream as in
+ * vc_apply. */
+vc_status vc_pack_apply(vc_pack *pk, vc_precision prec, const double *x_dev, double *y_dev, void *hip_stream);
+/* Capacitance matrices of every member: C_out[k] m_k x m_k host doubles (row-major),
+ * stats: optional array of n (iterations and final relative residual per column; solve
+ * time and product count are the whole set's).  The first call for a given (precision,
+ * restart) captures the cycle graphs; later calls replay them. */
+vc_status vc_pack_capacitance(vc_pack *pk, const vc_solve_opts *opts, double *const *C_out, vc_stats *stats);
+
+/* One-shot form: vc_pack_create + vc_pack_capacitance + vc_pack_destroy. */
 vc_status vc_capacitance_batch(vc_problem *const *problems, int32_t n, const vc_solve_opts *opts,
                                double *const *C_out, vc_stats *stats);
 

@@ -209,12 +209,50 @@ static vc_status capacitance_impl(vc_problem* p, const vc_solve_opts* opts, doub
   return s;
 }
 
+vc_status vc_pack_create(vc_problem* const* problems, int32_t n, vc_pack** out) {
+  if (!out) { set_error("null output"); return VC_ERR_ARG; }
+  *out = nullptr;
+  vc_problem* q = nullptr;
+  const vc_status s = pack_create(problems, n, &q);
+  if (s != VC_OK) return s;
+  *out = reinterpret_cast<vc_pack*>(q);
+  return VC_OK;
+}
+
+vc_status vc_pack_destroy(vc_pack* pk) {
+  delete reinterpret_cast<vc_problem*>(pk);
+  return VC_OK;
+}
+
+vc_status vc_pack_info(const vc_pack* pk, int32_t out[6]) {
+  if (!pk || !out) { set_error("null argument"); return VC_ERR_ARG; }
+  pack_info(reinterpret_cast<const vc_problem*>(pk), out);
+  return VC_OK;
+}
+
+vc_status vc_pack_apply(vc_pack* pk, vc_precision prec, const double* x, double* y, void* stream) {
+  vc_problem* q = reinterpret_cast<vc_problem*>(pk);
+  VC_CHECK_PROBLEM(q);
+  if (!q->pack) { set_error("not a packed set"); return VC_ERR_ARG; }
+  if (!x || !y) { set_error("null x/y"); return VC_ERR_ARG; }
+  VC_HIP(hipSetDevice(q->device));
+  return mark(q, apply_op(q, 0, prec, x, y, q->m, (hipStream_t)stream));
+}
+
+vc_status vc_pack_capacitance(vc_pack* pk, const vc_solve_opts* opts, double* const* C_out, vc_stats* stats) {
+  vc_problem* q = reinterpret_cast<vc_problem*>(pk);
+  VC_CHECK_PROBLEM(q);
+  if (!q->pack) { set_error("not a packed set"); return VC_ERR_ARG; }
+  return mark(q, pack_capacitance(q, opts, C_out, stats));
+}
+
 vc_status vc_capacitance_batch(vc_problem* const* problems, int32_t n, const vc_solve_opts* opts, double* const* C_out,
                                vc_stats* stats) {
-  const vc_status s = batch_capacitance(problems, n, opts, C_out, stats);
-  if (s == VC_ERR_HIP)
-    for (int k = 0; k < n; ++k)
-      if (problems && problems[k]) problems[k]->hip_failed = true;
+  vc_pack* pk = nullptr;
+  vc_status s = vc_pack_create(problems, n, &pk);
+  if (s != VC_OK) return s;
+  s = vc_pack_capacitance(pk, opts, C_out, stats);
+  vc_pack_destroy(pk);
   return s;
 }
 

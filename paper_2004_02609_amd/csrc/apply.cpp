@@ -112,7 +112,7 @@ bool sandwich_default(int L, int elem, int nin, int n1x, size_t budget, SandCfg*
 
 template <typename T>
 static vc_status run_apply(vc_problem* P, int transpose, const double* x, double* y, int nrhs, hipStream_t st,
-                           const int* skip) {
+                           const int* skip, const int* act) {
   PrecTables& tb = (sizeof(T) == 8) ? P->t64 : P->t32;
   const int n1x = P->n1[0], n1y = P->n1[1];
   const int Mx = P->M[0], My = P->M[1];
@@ -162,7 +162,7 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
   // 1. scatter + z transform
   if (!pick_tile(P->M[2], eb, Tune<T>::emax, nitems, &ncol, &nthr, budget, transpose ? nrhs : (nrhs + 1) / 2)) return VC_ERR_ARG;
   VC_HIP(launch_zfwd<T>(x, N, nrhs, transpose ? 1 : 0, items, nitems, lptr, pk, pkind, F, cs, rs, n1x, n1y, My, H,
-                        tb.ax[2].plan, tb.ax[2].tw.p, ncol, nthr, skip, st));
+                        tb.ax[2].plan, tb.ax[2].tw.p, ncol, nthr, skip, st, act));
   VC_MARK(1);
   // 2. y transform of the input components
   CompSet cin{};
@@ -177,6 +177,7 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
   sa.comp_stride = cs; sa.rhs_stride = rs; sa.plane_stride = (int64_t)My * H; sa.row_stride = H;
   sa.ncols = H; sa.nrhs = nrhs; sa.n1x = n1x; sa.n1y = n1y;
   sa.skip = skip;
+  sa.act = act;
   if (!pick_tile(My, eb, Tune<T>::emax, H, &ncol, &nthr, budget, (int64_t)n1x * cin.n * nrhs)) return VC_ERR_ARG;
   sa.ncol = ncol; sa.nin = n1y; sa.nout = My; sa.inverse = 0;
   VC_HIP(launch_strided<T>(F, sa, cin, n1x, tb.ax[1].plan, tb.ax[1].tw.p, lflag, pflag, nthr, st));
@@ -189,6 +190,7 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
   for (int q = 0; q < 15; ++q) xa.oddmask |= (uint64_t)pair_odd_bits(q) << (3 * q);
   xa.adjoint = transpose;
   xa.skip = skip;
+  xa.act = act;
   CompSet cout{};
   if (!transpose) {
     xa.nin = 3;
@@ -222,6 +224,7 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
         double best = 1e30, dflt = 0.0;
         for (const SandCfg& g : cand) {
           SandArgs t = xa;
+          t.act = nullptr;   // time every right-hand side
           t.nst = g.nst; t.radpack = g.radpack; t.tl = g.tl; t.lgc = g.lgc;
           VC_HIP(launch_sandwich<T>(F, O, tb.R.p, t, tb.ax[0].tw.p, tb.ax[0].ph.p, tb.ax[1].ph.p, tb.ax[2].ph.p,
                                     pflag, g.nthr, st));
@@ -262,7 +265,7 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
   // 5. inverse z transform + gather + jump term
   if (!pick_tile(P->M[2], eb, Tune<T>::emax, nitems, &ncol, &nthr, budget, transpose ? (nrhs + 1) / 2 : nrhs)) return VC_ERR_ARG;
   VC_HIP(launch_zinv<T>(O, y, x, N, nrhs, transpose ? 1 : 0, items, nitems, lptr, pk, pkind, P->d_diag.as<double>(),
-                        lflag, cs, rs, n1x, n1y, My, H, tb.ax[2].plan, tb.ax[2].tw.p, ncol, nthr, skip, st));
+                        lflag, cs, rs, n1x, n1y, My, H, tb.ax[2].plan, tb.ax[2].tw.p, ncol, nthr, skip, st, act));
   VC_MARK(5);
 #undef VC_MARK
   if (prof) P->ev_pending.push_back(std::vector<hipEvent_t>(ev, ev + 6));
@@ -271,18 +274,20 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
 }
 
 vc_status apply_op(vc_problem* P, int transpose, vc_precision prec, const double* x, double* y, int nrhs,
-                   hipStream_t st, const int* skip) {
+                   hipStream_t st, const int* skip, const int* act) {
+  if (P->pack) return pack_apply(P, transpose, prec, x, y, nrhs, st, skip, act);
   if (prec == VC_FP32) {
     if (!P->have32) { set_error("FP32 spectra were not built at setup"); return VC_ERR_STATE; }
-    return run_apply<float>(P, transpose, x, y, nrhs, st, skip);
+    return run_apply<float>(P, transpose, x, y, nrhs, st, skip, act);
   }
   if (!P->have64) { set_error("FP64 spectra were not built at setup"); return VC_ERR_STATE; }
-  return run_apply<double>(P, transpose, x, y, nrhs, st, skip);
+  return run_apply<double>(P, transpose, x, y, nrhs, st, skip, act);
 }
 
 vc_status apply_precond(vc_problem* P, int transpose, const double* x, double* y, int nrhs, hipStream_t st,
                         const int* skip) {
   (void)transpose;   // the blocks of eq. (5) are symmetric and the diagonal is its own transpose
+  if (P->pack) return pack_precond(P, x, y, nrhs, st, skip);
   const int64_t N = npanels(P);
   Precond& pc = P->pc;
   if (pc.mode == 2) {

@@ -224,6 +224,19 @@ template <typename T> struct Dft<T, 21> : DftAB<T, 3, 7> {};
 template <typename T> struct Dft<T, 25> : DftAB<T, 5, 5> {};
 template <typename T> struct Dft<T, 27> : DftAB<T, 3, 9> {};
 
+// The scene a workgroup of a multi-scene launch works on: the last entry whose first
+// linear workgroup blk0 is <= lin (blk0 increases along the table).
+template <typename S>
+__device__ __forceinline__ int find_scene(const S* __restrict__ tab, int n, int lin) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab[mid].blk0 <= lin) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Exact t / d for 0 <= t < 2^22 and d >= 1 given inv = 1.0f / d: (t + 1/2) / d is at
 // least 1/(2d) away from an integer, and the float product errs by < t * 2^-23 / d.
 __device__ __forceinline__ int fdiv(int t, float inv) { return (int)(((float)t + 0.5f) * inv); }

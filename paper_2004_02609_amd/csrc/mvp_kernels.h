@@ -37,6 +37,7 @@ struct StridedArgs {
   int n1x, n1y;   // flag array extents (planes x rows)
   int lgc;        // log2(ncol), set by the launcher
   const int* skip;   // optional device flag: when set, the launch does nothing
+  const int* act;    // optional per right-hand side activity: workgroups of inactive ones return
 };
 
 struct SandArgs {
@@ -53,6 +54,7 @@ struct SandArgs {
   // bits 3q..3q+2: stored spectrum of pair q is odd under k_a -> M_a - k_a (bit a)
   uint64_t oddmask;
   const int* skip;   // optional device flag: when set, the launch does nothing
+  const int* act;    // optional per right-hand side activity: workgroups of inactive ones return
 };
 // dynamic LDS of the sandwich: twiddle table + one [L][ncol+1] tile + 3 n1x plane flags
 inline size_t sandwich_lds_bytes(int L, int ncol, int elem, int n1x) {
@@ -69,7 +71,7 @@ template <typename T>
 hipError_t launch_zfwd(const double* x, int64_t N, int nrhs, int mode, const int32_t* items, int nitems,
                        const int32_t* line_ptr, const int32_t* pk, const int8_t* pkind, void* F, int64_t comp_stride,
                        int64_t rhs_stride, int n1x, int n1y, int My, int H, const AxisPlan& pl, const void* tw, int ncol,
-                       int nthr, const int* skip, hipStream_t st);
+                       int nthr, const int* skip, hipStream_t st, const int* act = nullptr);
 template <typename T>
 hipError_t launch_strided(void* data, const StridedArgs& a, const CompSet& cs, int nplanes, const AxisPlan& pl,
                           const void* tw, const uint8_t* lflag, const uint8_t* pflag, int nthr, hipStream_t st);
@@ -95,7 +97,67 @@ hipError_t launch_zinv(const void* O, double* y, const double* x, int64_t N, int
                        int nitems, const int32_t* line_ptr, const int32_t* pk, const int8_t* pkind,
                        const double* diag, const uint8_t* lflag, int64_t comp_stride, int64_t rhs_stride, int n1x,
                        int n1y, int My, int H, const AxisPlan& pl, const void* tw, int ncol, int nthr,
-                       const int* skip, hipStream_t st);
+                       const int* skip, hipStream_t st, const int* act = nullptr);
+
+// ---- one launch per pass over several independent problems ("scenes") of different
+// sizes: a device table holds every scene's arguments and its first linear workgroup
+// (blk0, increasing); a workgroup finds its scene by binary search on blk0.
+// z pass of one scene (forward scatter + R2C, or C2R + gather); the panel vectors of
+// scene s are columns c0 .. c0+nrhs-1 of the call's x / y (column stride ldx).
+struct ZScene {
+  const int32_t* items;
+  const int32_t* line_ptr;
+  const int32_t* pk;
+  const int8_t* pkind;
+  const double* diag;
+  const uint8_t* lflag;
+  void* F;            // spectral work array (written by the forward pass, read by the inverse)
+  const void* tw;
+  AxisPlan pl;
+  int64_t comp_stride, rhs_stride;
+  int nitems, nrhs, n1x, n1y, My, H, lgc;
+  int c0;             // first column of the scene
+  int gx;             // workgroups along the line items (the rest index right-hand sides)
+  int blk0;
+};
+struct StridedScene {
+  StridedArgs a;      // a.act is unused: the call's activity array (offset by c0) applies
+  CompSet cs;
+  AxisPlan pl;
+  void* data;
+  const void* tw;
+  const uint8_t* lflag;
+  const uint8_t* pflag;
+  int c0, gx, gy, blk0;
+};
+struct SandScene {
+  SandArgs a;         // a.skip / a.act unused: the call's flags apply
+  const void* Fin;
+  void* Fout;
+  const void* R;
+  const void* tw;
+  const void* phx;
+  const void* phy;
+  const void* phz;
+  const uint8_t* pflag;
+  int c0, ntiles, blk0;
+};
+template <typename T>
+hipError_t launch_zfwd_multi(const ZScene* tab, int nscene, int nblocks, const double* x, int64_t ldx,
+                             const int* skip, const int* act, int nthr, size_t lds, hipStream_t st);
+template <typename T>
+hipError_t launch_zinv_multi(const ZScene* tab, int nscene, int nblocks, const double* x, double* y, int64_t ldx,
+                             const int* skip, const int* act, int nthr, size_t lds, hipStream_t st);
+template <typename T>
+hipError_t launch_strided_multi(const StridedScene* tab, int nscene, int nblocks, const int* skip, const int* act,
+                                int nthr, size_t lds, hipStream_t st);
+template <typename T, int NIN, int NOUT>
+hipError_t launch_sandwich_multi_v(const SandScene* tab, int nscene, int nblocks, const int* skip, const int* act,
+                                   int nthr, size_t lds, int rs, hipStream_t st);
+// LDS bytes of the z / strided kernels for transform length L and ncol lines
+size_t zs_lds_bytes(int elem, int L, int ncol);
+// host-side check of one sandwich configuration (what the kernel assumes); false = invalid
+template <typename T> bool sandwich_args_ok(const SandArgs& a, int nthr);
 
 // setup kernels (setup_kernels.hip)
 struct FillArgs {
@@ -134,12 +196,12 @@ hipError_t launch_scale_cols(double* w, int64_t ldw, int64_t N, int nrhs, const 
 hipError_t launch_axpy_cols(double* y, const double* x, int64_t N, int nrhs, const double* a, int sub,
                             hipStream_t st, const int* skip = nullptr);
 hipError_t launch_diag_scale(const double* x, double* y, const double* dinv, int64_t N, int nrhs, const int* skip,
-                             hipStream_t st);
+                             hipStream_t st, int64_t dinv_ld = 0);
 hipError_t launch_block_apply(const double* x, double* y, int64_t N, int nrhs, const int32_t* box_ptr,
                               const int32_t* box_panels, const int32_t* box_block, const int64_t* block_off,
                               const int32_t* block_n, const double* blocks, int nbox, const int* skip,
-                              hipStream_t st);
-// device-side GMRES cycle (one thread per right-hand side, nrhs <= 64)
+                              hipStream_t st, const int32_t* box_c0 = nullptr, const int32_t* box_nc = nullptr);
+// device-side GMRES cycle (one thread per right-hand side, nrhs <= 256)
 hipError_t launch_cycle_start(int nrhs, int m, const double* rn, const double* bn, const double* rtol, int* act_cycle,
                               int* act_step, double* g, double* scal, int* kd, int* skip, double* rre_out,
                               hipStream_t st);

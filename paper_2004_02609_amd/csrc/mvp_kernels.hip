@@ -22,16 +22,27 @@ template <typename T> __device__ __forceinline__ C2<T> ld(const C2<T>* p) { retu
 
 // ------------------------------------------------------------------------------ z forward
 // Tiles hold 2^lgc lines; divisions by non-powers of two use fdiv (exact in range).
-template <typename T, int EMAX>
-__global__ void __launch_bounds__(1024)
-k_zfwd(const double* __restrict__ x, int64_t N, int nrhs, int mode, const int32_t* __restrict__ items, int nitems,
-       const int32_t* __restrict__ line_ptr, const int32_t* __restrict__ pk, const int8_t* __restrict__ pkind,
-       C2<T>* __restrict__ F, int64_t comp_stride, int64_t rhs_stride, int n1x, int n1y, int My, int H, AxisPlan pl,
-       const C2<T>* __restrict__ twg, int lgc, const int* __restrict__ skip) {
-  if (skip && *skip) return;
+// Workgroup (bx, by): lines bx*ncol .. of the item list, right-hand side(s) by (two per
+// complex transform in mode 0).  x: the scene's first column, column stride ldx.
+template <typename T>
+__device__ __forceinline__ void zfwd_body(const ZScene& a, int mode, const double* __restrict__ x, int64_t ldx,
+                                          const int* __restrict__ act, int bx, int by) {
+  const int nrhs = a.nrhs;
+  const int ra = (mode == 0) ? 2 * by : by;
+  const int rb = (mode == 0) ? ra + 1 : -1;
+  if (act && !act[ra] && !(rb >= 0 && rb < nrhs && act[rb])) return;   // uniform per workgroup
   extern __shared__ char smem_raw[];
+  const AxisPlan& pl = a.pl;
   const int L = pl.L;
-  const int ncol = 1 << lgc, ncolp = ncol + 1;
+  const int lgc = a.lgc, ncol = 1 << lgc, ncolp = ncol + 1;
+  const int nitems = a.nitems, n1x = a.n1x, n1y = a.n1y, My = a.My, H = a.H;
+  const int64_t comp_stride = a.comp_stride, rhs_stride = a.rhs_stride;
+  const int32_t* __restrict__ items = a.items;
+  const int32_t* __restrict__ line_ptr = a.line_ptr;
+  const int32_t* __restrict__ pk = a.pk;
+  const int8_t* __restrict__ pkind = a.pkind;
+  C2<T>* __restrict__ F = static_cast<C2<T>*>(a.F);
+  const C2<T>* __restrict__ twg = static_cast<const C2<T>*>(a.tw);
   C2<T>* tw = reinterpret_cast<C2<T>*>(smem_raw);
   C2<T>* buf = tw + L;
   C2<T>* buf2 = buf + L * ncolp;
@@ -39,9 +50,7 @@ k_zfwd(const double* __restrict__ x, int64_t N, int nrhs, int mode, const int32_
   for (int t = tid; t < L; t += nthr) tw[t] = twg[t];
   for (int e = tid; e < L * ncolp; e += nthr) buf[e] = C2<T>{T(0), T(0)};
   __syncthreads();
-  const int ra = (mode == 0) ? 2 * blockIdx.y : blockIdx.y;
-  const int rb = (mode == 0) ? ra + 1 : -1;
-  const int item0 = blockIdx.x * ncol;
+  const int item0 = bx * ncol;
   for (int c = 0; c < ncol; ++c) {
     const int it = item0 + c;
     if (it >= nitems) break;
@@ -51,10 +60,10 @@ k_zfwd(const double* __restrict__ x, int64_t N, int nrhs, int mode, const int32_
       const int k = pk[p];
       double re, im;
       if (mode == 0) {
-        re = x[(int64_t)ra * N + p];
-        im = (rb < nrhs) ? x[(int64_t)rb * N + p] : 0.0;
+        re = x[(int64_t)ra * ldx + p];
+        im = (rb < nrhs) ? x[(int64_t)rb * ldx + p] : 0.0;
       } else {
-        const double v = x[(int64_t)ra * N + p];
+        const double v = x[(int64_t)ra * ldx + p];
         re = pkind[p] == 0 ? v : 0.0;
         im = pkind[p] == 0 ? 0.0 : v;
       }
@@ -88,71 +97,131 @@ k_zfwd(const double* __restrict__ x, int64_t N, int nrhs, int mode, const int32_
   }
 }
 
-// ------------------------------------------------------------------------------ strided C2C
-template <typename T, int EMAX>
+template <typename T>
 __global__ void __launch_bounds__(1024)
-k_strided(C2<T>* __restrict__ data, StridedArgs a, CompSet cs, AxisPlan pl, const C2<T>* __restrict__ twg,
-          const uint8_t* __restrict__ lflag, const uint8_t* __restrict__ pflag) {
-  if (a.skip && *a.skip) return;
+k_zfwd(ZScene a, int mode, const double* __restrict__ x, int64_t ldx, const int* __restrict__ skip,
+       const int* __restrict__ act) {
+  if (skip && *skip) return;
+  zfwd_body<T>(a, mode, x, ldx, act, blockIdx.x, blockIdx.y);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_zfwd_multi(const ZScene* __restrict__ tab, int nscene, const double* __restrict__ x, int64_t ldx,
+             const int* __restrict__ skip, const int* __restrict__ act) {
+  if (skip && *skip) return;
+  const int lin = blockIdx.x;
+  const ZScene& a = tab[find_scene(tab, nscene, lin)];
+  const int local = lin - a.blk0;
+  const int by = local / a.gx, bx = local - by * a.gx;
+  zfwd_body<T>(a, 0, x + (int64_t)a.c0 * ldx, ldx, act ? act + a.c0 : nullptr, bx, by);
+}
+
+// ------------------------------------------------------------------------------ strided C2C
+// Workgroup (bx, plane, bz = component * nrhs + rhs).
+template <typename T>
+__device__ __forceinline__ void strided_body(C2<T>* __restrict__ data, const StridedArgs& a, const CompSet& cs,
+                                             const AxisPlan& pl, const C2<T>* __restrict__ twg,
+                                             const uint8_t* __restrict__ lflag, const uint8_t* __restrict__ pflag,
+                                             const int* __restrict__ act, int bx, int plane, int bz) {
+  const int nrhs = a.nrhs;
+  const int cz = bz / nrhs, rhs = bz - cz * nrhs;
+  if (act && !act[rhs]) return;   // uniform per workgroup
+  const int comp = cs.comp[cz], axis = cs.axis[cz];
+  const int min_ = cs.min_[cz], mout = cs.mout[cz];
+  const int need = a.inverse ? mout : min_;
+  const int n1x = a.n1x, n1y = a.n1y;
+  if (pflag && need && !(pflag[axis * n1x + plane] & need)) return;  // uniform per block
   extern __shared__ char smem_raw[];
   const int L = pl.L;
   const int lgc = a.lgc, ncol = 1 << lgc, ncolp = ncol + 1, cmask = ncol - 1;
+  const int nin = a.nin, nout = a.nout, ncols = a.ncols, inverse = a.inverse;
+  const int64_t row_stride = a.row_stride;
   C2<T>* tw = reinterpret_cast<C2<T>*>(smem_raw);
   C2<T>* buf = tw + L;
   C2<T>* buf2 = buf + L * ncolp;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int plane = blockIdx.y;
-  const int cz = blockIdx.z / a.nrhs, rhs = blockIdx.z - cz * a.nrhs;
-  const int comp = cs.comp[cz], axis = cs.axis[cz];
-  const int min_ = cs.min_[cz], mout = cs.mout[cz];
-  const int need = a.inverse ? mout : min_;
-  if (pflag && need && !(pflag[axis * a.n1x + plane] & need)) return;  // uniform per block
   C2<T>* base = data + comp * a.comp_stride + rhs * a.rhs_stride + plane * a.plane_stride;
-  const int col0 = blockIdx.x * ncol;
+  const int col0 = bx * ncol;
   for (int t = tid; t < L; t += nthr) tw[t] = twg[t];
-  const uint8_t* lf = lflag ? lflag + ((int64_t)axis * a.n1x + plane) * a.n1y : nullptr;
+  const uint8_t* lf = lflag ? lflag + ((int64_t)axis * n1x + plane) * n1y : nullptr;
   for (int e = tid; e < (L << lgc); e += nthr) {
     const int r = e >> lgc, c = e & cmask;
     C2<T> v = {T(0), T(0)};
     const int col = col0 + c;
-    if (r < a.nin && col < a.ncols) {
+    if (r < nin && col < ncols) {
       bool ok = true;
       if (lf && min_) ok = (lf[r] & min_) != 0;
-      if (ok) v = base[(int64_t)r * a.row_stride + col];
+      if (ok) v = base[(int64_t)r * row_stride + col];
     }
     buf[r * ncolp + c] = v;
   }
   __syncthreads();
-  const C2<T>* res = lds_fft<T, Tune<T>::maxr>(buf, buf2, tw, pl, lgc, ncolp, a.inverse != 0);
-  for (int e = tid; e < (a.nout << lgc); e += nthr) {
+  const C2<T>* res = lds_fft<T, Tune<T>::maxr>(buf, buf2, tw, pl, lgc, ncolp, inverse != 0);
+  for (int e = tid; e < (nout << lgc); e += nthr) {
     const int r = e >> lgc, c = e & cmask;
     const int col = col0 + c;
-    if (col >= a.ncols) continue;
+    if (col >= ncols) continue;
     if (lf && mout && !(lf[r] & mout)) continue;
-    base[(int64_t)r * a.row_stride + col] = res[r * ncolp + c];
+    base[(int64_t)r * row_stride + col] = res[r * ncolp + c];
   }
 }
 
-// ------------------------------------------------------------------------------ z inverse + gather
-template <typename T, int EMAX>
+template <typename T>
 __global__ void __launch_bounds__(1024)
-k_zinv(const C2<T>* __restrict__ O, double* __restrict__ y, const double* __restrict__ x, int64_t N, int nrhs,
-       int mode, const int32_t* __restrict__ items, int nitems, const int32_t* __restrict__ line_ptr,
-       const int32_t* __restrict__ pk, const int8_t* __restrict__ pkind, const double* __restrict__ diag,
-       const uint8_t* __restrict__ lflag, int64_t comp_stride, int64_t rhs_stride, int n1x, int n1y, int My, int H,
-       AxisPlan pl, const C2<T>* __restrict__ twg, int lgc, const int* __restrict__ skip) {
+k_strided(C2<T>* __restrict__ data, StridedArgs a, CompSet cs, AxisPlan pl, const C2<T>* __restrict__ twg,
+          const uint8_t* __restrict__ lflag, const uint8_t* __restrict__ pflag) {
+  if (a.skip && *a.skip) return;
+  strided_body<T>(data, a, cs, pl, twg, lflag, pflag, a.act, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_strided_multi(const StridedScene* __restrict__ tab, int nscene, const int* __restrict__ skip,
+                const int* __restrict__ act) {
   if (skip && *skip) return;
+  const int lin = blockIdx.x;
+  const StridedScene& sc = tab[find_scene(tab, nscene, lin)];
+  const int local = lin - sc.blk0;
+  const int gxy = sc.gx * sc.gy;
+  const int bz = local / gxy, rem = local - bz * gxy;
+  const int by = rem / sc.gx, bx = rem - by * sc.gx;
+  strided_body<T>(static_cast<C2<T>*>(sc.data), sc.a, sc.cs, sc.pl, static_cast<const C2<T>*>(sc.tw), sc.lflag,
+                  sc.pflag, act ? act + sc.c0 : nullptr, bx, by, bz);
+}
+
+// ------------------------------------------------------------------------------ z inverse + gather
+// Workgroup (bx, by): lines bx*ncol .. of the item list, right-hand side(s) by.  x is
+// the product's input (jump term of eq. (7)), y its output, both from the scene's
+// first column with column stride ldx.
+template <typename T>
+__device__ __forceinline__ void zinv_body(const ZScene& a, int mode, const double* __restrict__ x,
+                                          double* __restrict__ y, int64_t ldx, const int* __restrict__ act, int bx,
+                                          int by) {
+  const int nrhs = a.nrhs;
+  const int ra = (mode == 0) ? by : 2 * by;
+  const int rb = (mode == 0) ? -1 : ra + 1;
+  if (act && !act[ra] && !(rb >= 0 && rb < nrhs && act[rb])) return;   // uniform per workgroup
   extern __shared__ char smem_raw[];
+  const AxisPlan& pl = a.pl;
   const int L = pl.L;
-  const int ncol = 1 << lgc, ncolp = ncol + 1;
+  const int lgc = a.lgc, ncol = 1 << lgc, ncolp = ncol + 1;
+  const int nitems = a.nitems, n1x = a.n1x, n1y = a.n1y, My = a.My, H = a.H;
+  const int64_t comp_stride = a.comp_stride, rhs_stride = a.rhs_stride;
+  const int32_t* __restrict__ items = a.items;
+  const int32_t* __restrict__ line_ptr = a.line_ptr;
+  const int32_t* __restrict__ pk = a.pk;
+  const int8_t* __restrict__ pkind = a.pkind;
+  const double* __restrict__ diag = a.diag;
+  const uint8_t* __restrict__ lflag = a.lflag;
+  const C2<T>* __restrict__ O = static_cast<const C2<T>*>(a.F);
+  const C2<T>* __restrict__ twg = static_cast<const C2<T>*>(a.tw);
   C2<T>* tw = reinterpret_cast<C2<T>*>(smem_raw);
   C2<T>* buf = tw + L;
   C2<T>* buf2 = buf + L * ncolp;
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int t = tid; t < L; t += nthr) tw[t] = twg[t];
-  const int ra = (mode == 0) ? blockIdx.y : 2 * blockIdx.y;
-  const int rb = (mode == 0) ? -1 : ra + 1;
-  const int item0 = blockIdx.x * ncol;
+  const int item0 = bx * ncol;
   const int plane = n1x * n1y;
   const float invH = 1.0f / (float)H, invPl = 1.0f / (float)plane, invN1y = 1.0f / (float)n1y;
   for (int e = tid; e < H * ncol; e += nthr) {
@@ -189,18 +258,39 @@ k_zinv(const C2<T>* __restrict__ O, double* __restrict__ y, const double* __rest
       const C2<T> Z = res[pk[p] * ncolp + c];
       const double dg = diag[p];
       if (mode == 0) {
-        const int64_t o = (int64_t)ra * N + p;
+        const int64_t o = (int64_t)ra * ldx + p;
         y[o] = pkind[p] == 0 ? double(Z.x) : double(Z.y) + dg * x[o];
       } else {
-        const int64_t oa = (int64_t)ra * N + p;
+        const int64_t oa = (int64_t)ra * ldx + p;
         y[oa] = double(Z.x) + dg * x[oa];
         if (rb < nrhs) {
-          const int64_t ob = (int64_t)rb * N + p;
+          const int64_t ob = (int64_t)rb * ldx + p;
           y[ob] = double(Z.y) + dg * x[ob];
         }
       }
     }
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_zinv(ZScene a, int mode, const double* __restrict__ x, double* __restrict__ y, int64_t ldx,
+       const int* __restrict__ skip, const int* __restrict__ act) {
+  if (skip && *skip) return;
+  zinv_body<T>(a, mode, x, y, ldx, act, blockIdx.x, blockIdx.y);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_zinv_multi(const ZScene* __restrict__ tab, int nscene, const double* __restrict__ x, double* __restrict__ y,
+             int64_t ldx, const int* __restrict__ skip, const int* __restrict__ act) {
+  if (skip && *skip) return;
+  const int lin = blockIdx.x;
+  const ZScene& a = tab[find_scene(tab, nscene, lin)];
+  const int local = lin - a.blk0;
+  const int by = local / a.gx, bx = local - by * a.gx;
+  const int64_t o = (int64_t)a.c0 * ldx;
+  zinv_body<T>(a, 0, x + o, y + o, ldx, act ? act + a.c0 : nullptr, bx, by);
 }
 
 static inline int ilog2(int n) {
@@ -215,16 +305,22 @@ static size_t lds_bytes(int L, int ncol) {
   return sizeof(C2<T>) * ((size_t)L + 2 * (size_t)L * (ncol + 1));   // twiddles + ping-pong tiles
 }
 
+size_t zs_lds_bytes(int elem, int L, int ncol) {
+  return (size_t)2 * elem * ((size_t)L + 2 * (size_t)L * (ncol + 1));
+}
+
 template <typename T>
 hipError_t launch_zfwd(const double* x, int64_t N, int nrhs, int mode, const int32_t* items, int nitems,
                        const int32_t* line_ptr, const int32_t* pk, const int8_t* pkind, void* F, int64_t comp_stride,
                        int64_t rhs_stride, int n1x, int n1y, int My, int H, const AxisPlan& pl, const void* tw, int ncol,
-                       int nthr, const int* skip, hipStream_t st) {
+                       int nthr, const int* skip, hipStream_t st, const int* act) {
   if (nitems == 0) return hipSuccess;
+  ZScene a{};
+  a.items = items; a.line_ptr = line_ptr; a.pk = pk; a.pkind = pkind; a.F = F; a.tw = tw; a.pl = pl;
+  a.comp_stride = comp_stride; a.rhs_stride = rhs_stride;
+  a.nitems = nitems; a.nrhs = nrhs; a.n1x = n1x; a.n1y = n1y; a.My = My; a.H = H; a.lgc = ilog2(ncol);
   dim3 grid((nitems + ncol - 1) / ncol, mode == 0 ? (nrhs + 1) / 2 : nrhs);
-  hipLaunchKernelGGL((k_zfwd<T, Tune<T>::emax>), grid, dim3(nthr), lds_bytes<T>(pl.L, ncol), st, x, N, nrhs, mode, items,
-                     nitems, line_ptr, pk, pkind, (C2<T>*)F, comp_stride, rhs_stride, n1x, n1y, My, H, pl,
-                     (const C2<T>*)tw, ilog2(ncol), skip);
+  hipLaunchKernelGGL((k_zfwd<T>), grid, dim3(nthr), lds_bytes<T>(pl.L, ncol), st, a, mode, x, N, skip, act);
   return hipGetLastError();
 }
 
@@ -235,36 +331,43 @@ hipError_t launch_strided(void* data, const StridedArgs& a, const CompSet& cs, i
   StridedArgs b = a;
   b.lgc = ilog2(a.ncol);
   if ((1 << b.lgc) != a.ncol) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_strided<T, Tune<T>::emax>), grid, dim3(nthr), lds_bytes<T>(pl.L, a.ncol), st, (C2<T>*)data, b, cs,
+  hipLaunchKernelGGL((k_strided<T>), grid, dim3(nthr), lds_bytes<T>(pl.L, a.ncol), st, (C2<T>*)data, b, cs,
                      pl, (const C2<T>*)tw, lflag, pflag);
   return hipGetLastError();
+}
+
+template <typename T>
+bool sandwich_args_ok(const SandArgs& a, int nthr) {
+  // the kernel assumes every one of these
+  if (a.nst < 1 || a.nst > kSandMaxStages || a.lgc < 0 || a.lgc > 5 || nthr < 64 || nthr > 512 || (nthr & 63))
+    return false;
+  long prod = 1;
+  int prev = 1 << 30;
+  for (int s = 0; s < a.nst; ++s) {
+    const int r = (int)((a.radpack >> (5 * s)) & 31u);
+    if (r < 2 || r > prev) return false;
+    if (s == 0 && r > sandwich_rmax((int)sizeof(T))) return false;
+    if (s > 0 && s < a.nst - 1 && r > sandwich_rmid((int)sizeof(T))) return false;
+    prev = r;
+    prod *= r;
+  }
+  const int rs = (int)((a.radpack >> (5 * (a.nst - 1))) & 31u);
+  if (prod != a.Mx || (long)a.tl * rs != a.Mx || ((long)a.tl << a.lgc) > nthr) return false;
+  if (a.nst == 1 && a.tl != 1) return false;
+  if (rs > sandwich_rs_max((int)sizeof(T), a.nin)) return false;
+  // 32-bit byte offsets inside one (component, rhs) slab and one stored pair
+  if ((uint64_t)a.n1x * a.My * a.H * 2 * sizeof(T) >= ((uint64_t)1 << 32) ||
+      (uint64_t)a.pair_stride * sizeof(T) >= ((uint64_t)1 << 32))
+    return false;
+  return true;
 }
 
 template <typename T>
 hipError_t launch_sandwich(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
                            const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
                            hipStream_t st) {
-  // the kernel assumes every one of these
-  if (a.nst < 1 || a.nst > kSandMaxStages || a.lgc < 0 || a.lgc > 5 || nthr < 64 || nthr > 512 || (nthr & 63))
-    return hipErrorInvalidValue;
-  long prod = 1;
-  int prev = 1 << 30;
-  for (int s = 0; s < a.nst; ++s) {
-    const int r = (int)((a.radpack >> (5 * s)) & 31u);
-    if (r < 2 || r > prev) return hipErrorInvalidValue;
-    if (s == 0 && r > sandwich_rmax((int)sizeof(T))) return hipErrorInvalidValue;
-    if (s > 0 && s < a.nst - 1 && r > sandwich_rmid((int)sizeof(T))) return hipErrorInvalidValue;
-    prev = r;
-    prod *= r;
-  }
+  if (!sandwich_args_ok<T>(a, nthr)) return hipErrorInvalidValue;
   const int rs = (int)((a.radpack >> (5 * (a.nst - 1))) & 31u);
-  if (prod != a.Mx || (long)a.tl * rs != a.Mx || ((long)a.tl << a.lgc) > nthr) return hipErrorInvalidValue;
-  if (a.nst == 1 && a.tl != 1) return hipErrorInvalidValue;
-  if (rs > sandwich_rs_max((int)sizeof(T), a.nin)) return hipErrorInvalidValue;
-  // 32-bit byte offsets inside one (component, rhs) slab and one stored pair
-  if ((uint64_t)a.n1x * a.My * a.H * 2 * sizeof(T) >= ((uint64_t)1 << 32) ||
-      (uint64_t)a.pair_stride * sizeof(T) >= ((uint64_t)1 << 32))
-    return hipErrorInvalidValue;
   const size_t lds = sandwich_lds_bytes(a.Mx, 1 << a.lgc, (int)sizeof(T), a.n1x);
   if (!a.adjoint && a.nin == 3 && a.nout == 6)
     return launch_sandwich_v<T, 3, 6>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st);
@@ -280,19 +383,45 @@ hipError_t launch_zinv(const void* O, double* y, const double* x, int64_t N, int
                        int nitems, const int32_t* line_ptr, const int32_t* pk, const int8_t* pkind,
                        const double* diag, const uint8_t* lflag, int64_t comp_stride, int64_t rhs_stride, int n1x,
                        int n1y, int My, int H, const AxisPlan& pl, const void* tw, int ncol, int nthr,
-                       const int* skip, hipStream_t st) {
+                       const int* skip, hipStream_t st, const int* act) {
   if (nitems == 0) return hipSuccess;
+  ZScene a{};
+  a.items = items; a.line_ptr = line_ptr; a.pk = pk; a.pkind = pkind; a.diag = diag; a.lflag = lflag;
+  a.F = const_cast<void*>(O); a.tw = tw; a.pl = pl;
+  a.comp_stride = comp_stride; a.rhs_stride = rhs_stride;
+  a.nitems = nitems; a.nrhs = nrhs; a.n1x = n1x; a.n1y = n1y; a.My = My; a.H = H; a.lgc = ilog2(ncol);
   dim3 grid((nitems + ncol - 1) / ncol, mode == 0 ? nrhs : (nrhs + 1) / 2);
-  hipLaunchKernelGGL((k_zinv<T, Tune<T>::emax>), grid, dim3(nthr), lds_bytes<T>(pl.L, ncol), st, (const C2<T>*)O, y, x, N,
-                     nrhs, mode, items, nitems, line_ptr, pk, pkind, diag, lflag, comp_stride, rhs_stride, n1x, n1y,
-                     My, H, pl, (const C2<T>*)tw, ilog2(ncol), skip);
+  hipLaunchKernelGGL((k_zinv<T>), grid, dim3(nthr), lds_bytes<T>(pl.L, ncol), st, a, mode, x, y, N, skip, act);
+  return hipGetLastError();
+}
+
+// multi-scene launches: the table (device memory) was checked and laid out by the host
+template <typename T>
+hipError_t launch_zfwd_multi(const ZScene* tab, int nscene, int nblocks, const double* x, int64_t ldx,
+                             const int* skip, const int* act, int nthr, size_t lds, hipStream_t st) {
+  if (nscene <= 0 || nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_zfwd_multi<T>), dim3(nblocks), dim3(nthr), lds, st, tab, nscene, x, ldx, skip, act);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_zinv_multi(const ZScene* tab, int nscene, int nblocks, const double* x, double* y, int64_t ldx,
+                             const int* skip, const int* act, int nthr, size_t lds, hipStream_t st) {
+  if (nscene <= 0 || nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_zinv_multi<T>), dim3(nblocks), dim3(nthr), lds, st, tab, nscene, x, y, ldx, skip, act);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_strided_multi(const StridedScene* tab, int nscene, int nblocks, const int* skip, const int* act,
+                                int nthr, size_t lds, hipStream_t st) {
+  if (nscene <= 0 || nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_strided_multi<T>), dim3(nblocks), dim3(nthr), lds, st, tab, nscene, skip, act);
   return hipGetLastError();
 }
 
 #define VC_INST(T)                                                                                                \
   template hipError_t launch_zfwd<T>(const double*, int64_t, int, int, const int32_t*, int, const int32_t*,        \
                                      const int32_t*, const int8_t*, void*, int64_t, int64_t, int, int, int, int,   \
-                                     const AxisPlan&, const void*, int, int, const int*, hipStream_t);             \
+                                     const AxisPlan&, const void*, int, int, const int*, hipStream_t, const int*); \
   template hipError_t launch_strided<T>(void*, const StridedArgs&, const CompSet&, int, const AxisPlan&,          \
                                         const void*, const uint8_t*, const uint8_t*, int, hipStream_t);            \
   template hipError_t launch_sandwich<T>(const void*, void*, const void*, const SandArgs&, const void*, const void*, \
@@ -300,7 +429,14 @@ hipError_t launch_zinv(const void* O, double* y, const double* x, int64_t N, int
   template hipError_t launch_zinv<T>(const void*, double*, const double*, int64_t, int, int, const int32_t*, int, \
                                      const int32_t*, const int32_t*, const int8_t*, const double*, const uint8_t*, \
                                      int64_t, int64_t, int, int, int, int, const AxisPlan&, const void*, int, int, \
-                                     const int*, hipStream_t);
+                                     const int*, hipStream_t, const int*);                                         \
+  template hipError_t launch_zfwd_multi<T>(const ZScene*, int, int, const double*, int64_t, const int*,           \
+                                           const int*, int, size_t, hipStream_t);                                 \
+  template hipError_t launch_zinv_multi<T>(const ZScene*, int, int, const double*, double*, int64_t, const int*,  \
+                                           const int*, int, size_t, hipStream_t);                                 \
+  template hipError_t launch_strided_multi<T>(const StridedScene*, int, int, const int*, const int*, int, size_t, \
+                                              hipStream_t);                                                       \
+  template bool sandwich_args_ok<T>(const SandArgs&, int);
 VC_INST(float)
 VC_INST(double)
 

@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -82,6 +83,8 @@ struct Precond {
   std::vector<int64_t> h_block_off;
   std::vector<double> h_blocks;
 };
+
+struct PackData;   // several problems solved as one (pack.cpp)
 
 }  // namespace vc
 
@@ -189,6 +192,10 @@ struct vc_problem {
   std::vector<hipEvent_t> ev_free;
   std::vector<std::vector<hipEvent_t>> ev_pending;
   double pass_bytes[5] = {0, 0, 0, 0, 0};
+  // set on the combined problem of a packed set: its rows are the largest member's
+  // panel count and its products / preconditioner run over every member at once
+  std::shared_ptr<vc::PackData> pack;
+  int64_t pack_rows = 0;
   ~vc_problem() {
     drop_graphs();
     if (solve_stream) (void)hipStreamDestroy(solve_stream);
@@ -203,7 +210,7 @@ struct vc_problem {
 };
 
 namespace vc {
-inline int64_t npanels(const vc_problem* p) { return (int64_t)p->panels.size(); }
+inline int64_t npanels(const vc_problem* p) { return p->pack ? p->pack_rows : (int64_t)p->panels.size(); }
 vc_status panelize(vc_problem* p);
 vc_status choose_sizes(vc_problem* p, const int32_t* fft_size);
 vc_status build_spectra(vc_problem* p, int want64, int want32, double tucker_tol, hipStream_t st);
@@ -214,7 +221,11 @@ vc_status tucker_end(vc_problem* p);
 template <typename T>
 vc_status tucker_rebuild(vc_problem* p, T* R, int64_t pair_stride, hipStream_t st, const int* skip = nullptr);
 vc_status apply_op(vc_problem* p, int transpose, vc_precision prec, const double* x, double* y, int nrhs,
-                   hipStream_t st, const int* skip = nullptr);
+                   hipStream_t st, const int* skip = nullptr, const int* act = nullptr);
+// the same over a packed set (pack.cpp)
+vc_status pack_apply(vc_problem* q, int transpose, vc_precision prec, const double* x, double* y, int nrhs,
+                     hipStream_t st, const int* skip, const int* act);
+vc_status pack_precond(vc_problem* q, const double* x, double* y, int nrhs, hipStream_t st, const int* skip);
 vc_status apply_precond(vc_problem* p, int transpose, const double* x, double* y, int nrhs, hipStream_t st,
                         const int* skip = nullptr);
 AxisPlan make_plan(int L, int max_radix);

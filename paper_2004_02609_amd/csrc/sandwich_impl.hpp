@@ -213,12 +213,13 @@ __device__ __forceinline__ int sw_pair(int o, int b) {
   return b < 3 ? (al == o ? al : 2 + al + o) : 6 + 3 * al + o;
 }
 
+// one (column tile, right-hand side) of the pass
 template <typename T, int NIN, int NOUT, int RS>
-__global__ void __launch_bounds__(512, (sizeof(T) == 8 || NIN == 6) ? 2 : 3)
-k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __restrict__ R, SandArgs a,
-            const C2<T>* __restrict__ twg, const C2<T>* __restrict__ phx, const C2<T>* __restrict__ phy,
-            const C2<T>* __restrict__ phz, const uint8_t* __restrict__ pflag) {
-  if (a.skip && *a.skip) return;
+__device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout,
+                                              const T* __restrict__ R, const SandArgs& a,
+                                              const C2<T>* __restrict__ twg, const C2<T>* __restrict__ phx,
+                                              const C2<T>* __restrict__ phy, const C2<T>* __restrict__ phz,
+                                              const uint8_t* __restrict__ pflag, int tile, int rhs) {
   constexpr int RMAX = sandwich_rmax((int)sizeof(T)), RMID = sandwich_rmid((int)sizeof(T));
   constexpr uint32_t E = sizeof(C2<T>);
   extern __shared__ char smem_raw[];
@@ -231,11 +232,6 @@ k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __
   const int tid = threadIdx.x;
   const int c = tid & (ncol - 1), i = tid >> lgc;
   const bool valid = i < tl;
-  // right-hand sides fastest: the workgroups that read one tile's spectra run together
-  // on one XCD, so those spectra come from HBM once per tile rather than once per RHS
-  const int ntiles = gridDim.x;
-  const int work = xcd_remap(blockIdx.y * ntiles + blockIdx.x, ntiles * gridDim.y);
-  const int tile = work / a.nrhs, rhs = work - tile * a.nrhs;
   const int ncols = a.My * a.H;                 // flattened (ky, kz) columns
   const int col = (tile << lgc) + c;
   const bool colok = col < ncols;
@@ -461,6 +457,38 @@ k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __
 #undef VC_SW_CASE
 #undef VC_SW_SWITCH
 
+// Right-hand sides fastest: the workgroups that read one tile's spectra run together on
+// one XCD, so those spectra come from HBM once per tile rather than once per RHS.
+template <typename T, int NIN, int NOUT, int RS>
+__global__ void __launch_bounds__(512, (sizeof(T) == 8 || NIN == 6) ? 2 : 3)
+k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __restrict__ R, SandArgs a,
+            const C2<T>* __restrict__ twg, const C2<T>* __restrict__ phx, const C2<T>* __restrict__ phy,
+            const C2<T>* __restrict__ phz, const uint8_t* __restrict__ pflag) {
+  if (a.skip && *a.skip) return;
+  const int ntiles = gridDim.x;
+  const int work = xcd_remap(blockIdx.y * ntiles + blockIdx.x, ntiles * gridDim.y);
+  const int tile = work / a.nrhs, rhs = work - tile * a.nrhs;
+  if (a.act && !a.act[rhs]) return;
+  sandwich_body<T, NIN, NOUT, RS>(Fin, Fout, R, a, twg, phx, phy, phz, pflag, tile, rhs);
+}
+
+// several scenes in one launch: linear workgroup -> (scene, tile, rhs), XCD-contiguous
+template <typename T, int NIN, int NOUT, int RS>
+__global__ void __launch_bounds__(512, (sizeof(T) == 8 || NIN == 6) ? 2 : 3)
+k_xsandwich_multi(const SandScene* __restrict__ tab, int nscene, const int* __restrict__ skip,
+                  const int* __restrict__ act) {
+  if (skip && *skip) return;
+  const int lin = xcd_remap(blockIdx.x, gridDim.x);
+  const SandScene& sc = tab[find_scene(tab, nscene, lin)];
+  const int work = lin - sc.blk0;
+  const int tile = work / sc.a.nrhs, rhs = work - tile * sc.a.nrhs;
+  if (act && !act[sc.c0 + rhs]) return;
+  sandwich_body<T, NIN, NOUT, RS>(static_cast<const C2<T>*>(sc.Fin), static_cast<C2<T>*>(sc.Fout),
+                                  static_cast<const T*>(sc.R), sc.a, static_cast<const C2<T>*>(sc.tw),
+                                  static_cast<const C2<T>*>(sc.phx), static_cast<const C2<T>*>(sc.phy),
+                                  static_cast<const C2<T>*>(sc.phz), sc.pflag, tile, rhs);
+}
+
 // Compiled last-stage radices per kernel variant (register budget: the thread holds
 // NIN x RS transformed inputs).
 template <typename T, int NIN> struct SandRS {
@@ -478,6 +506,26 @@ hipError_t launch_sandwich_v(const void* Fin, void* Fout, const void* R, const S
       hipLaunchKernelGGL((k_xsandwich<T, NIN, NOUT, RR>), grid, dim3(nthr), lds, st, (const C2<T>*)Fin,          \
                          (C2<T>*)Fout, (const T*)R, a, (const C2<T>*)tw, (const C2<T>*)phx, (const C2<T>*)phy,    \
                          (const C2<T>*)phz, pflag);                                                               \
+      return hipGetLastError();                                                                                   \
+    }                                                                                                             \
+    break;
+  switch (rs) {
+    VC_RS(2) VC_RS(3) VC_RS(4) VC_RS(5) VC_RS(6) VC_RS(7) VC_RS(8) VC_RS(9) VC_RS(10)
+    default: break;
+  }
+#undef VC_RS
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int NIN, int NOUT>
+hipError_t launch_sandwich_multi_v(const SandScene* tab, int nscene, int nblocks, const int* skip, const int* act,
+                                   int nthr, size_t lds, int rs, hipStream_t st) {
+  if (nscene <= 0 || nblocks <= 0) return hipSuccess;
+#define VC_RS(RR)                                                                                                 \
+  case RR:                                                                                                        \
+    if constexpr (RR <= SandRS<T, NIN>::max) {                                                                    \
+      hipLaunchKernelGGL((k_xsandwich_multi<T, NIN, NOUT, RR>), dim3(nblocks), dim3(nthr), lds, st, tab, nscene, \
+                         skip, act);                                                                              \
       return hipGetLastError();                                                                                   \
     }                                                                                                             \
     break;

@@ -24,7 +24,7 @@ vc_status ensure_workspace(vc_problem* P, int nrhs, int restart) {
   if (P->s_nrhs >= nrhs && P->s_restart >= restart) return VC_OK;
   const int64_t N = npanels(P);
   const int r = std::max(restart, P->s_restart), k = std::max(nrhs, P->s_nrhs);
-  if (k > 64) { set_error("at most 64 right-hand sides per solve"); return VC_ERR_ARG; }
+  if (k > 256) { set_error("at most 256 right-hand sides per solve"); return VC_ERR_ARG; }
   P->drop_graphs();   // captured graphs hold pointers into the old workspace
   VC_HIP(P->s_V.alloc((size_t)(r + 1) * k * N * sizeof(double)));
   VC_HIP(P->s_w.alloc((size_t)k * N * sizeof(double)));
@@ -46,6 +46,10 @@ vc_status ensure_workspace(vc_problem* P, int nrhs, int restart) {
   const size_t nd = (size_t)k * ((size_t)(r + 1) * r + 2 * r + (r + 1) + 4) + 1;
   VC_HIP(P->s_cyc.alloc(nd * sizeof(double)));
   VC_HIP(P->s_cyci.alloc(((size_t)4 * k + 5) * sizeof(int)));
+  // vectors start at zero: rows a product never writes (the padding rows of a packed
+  // set) then stay zero through every update
+  for (DevMem* d : {&P->s_V, &P->s_w, &P->s_z, &P->s_r, &P->s_b, &P->s_x, &P->s_tmp, &P->s_rr, &P->s_dd})
+    VC_HIP(hipMemset(d->p, 0, d->bytes));
   P->s_nrhs = k;
   P->s_restart = r;
   return VC_OK;
@@ -68,14 +72,15 @@ Cyc cycle_views(vc_problem* P, int nrhs, int m) {
   c.iters = q; q += nrhs;
   c.act_cycle = q; q += nrhs;
   c.act_step = q; q += nrhs;
-  c.skip = q; q += 3;   // [0] cycle-level, [1] step-level, [2] problem disabled (batch)
+  c.skip = q; q += 3;   // [0] cycle-level, [1] step-level, [2] whole solve disabled (cleared per solve)
   c.bad = q;
   return c;
 }
 
 // z = R v (if preconditioned), w = A z; skipped entirely when *skip
+// (act: optional per-column activity; the product skips inactive columns)
 vc_status op_with_precond(vc_problem* P, const SolveSpec& sp, const double* v, double* z, double* w, int nrhs,
-                          hipStream_t st, const int* skip) {
+                          hipStream_t st, const int* skip, const int* act) {
   const double* src = v;
   if (sp.precond) {
     P->pc.mode = sp.precond;
@@ -83,7 +88,7 @@ vc_status op_with_precond(vc_problem* P, const SolveSpec& sp, const double* v, d
     if (s != VC_OK) return s;
     src = z;
   }
-  return apply_op(P, sp.transpose, sp.mvp, src, w, nrhs, st, skip);
+  return apply_op(P, sp.transpose, sp.mvp, src, w, nrhs, st, skip, act);
 }
 
 // r = b - A x
@@ -131,7 +136,7 @@ vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, doubl
                             st));
   VC_HIP(launch_scale_copy(V, r, N, nrhs, c.scal, c.skip, st));   // V_0 = r / |r|
   for (int j = 0; j < m; ++j) {
-    s = op_with_precond(P, sp, V + j * ldv, z, w, nrhs, st, c.skip + 1);
+    s = op_with_precond(P, sp, V + j * ldv, z, w, nrhs, st, c.skip + 1, c.act_step);
     if (s != VC_OK) return s;
     VC_HIP(launch_gemv_t(V, ldv, N, j + 1, w, N, nrhs, hd, ldh, c.act_step, P->s_partial.as<double>(), st));
     VC_HIP(launch_gemv_n_sub(V, ldv, N, j + 1, hd, ldh, w, N, nrhs, c.act_step, 0, st));
@@ -253,7 +258,7 @@ hipStream_t get_solve_stream(vc_problem* P) {
 
 // FP64 solve, or FP32-product GMRES inside FP64 refinement (VC_MIXED).
 vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const double* b, double* x, int nrhs,
-                       vc_stats* stats, hipStream_t st) {
+                       vc_stats* stats, hipStream_t st, std::vector<int>* it_out, std::vector<double>* rre_out) {
   const int64_t N = npanels(P);
   SolveSpec sp{};
   sp.transpose = transpose;
@@ -281,7 +286,7 @@ vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const doub
     std::vector<int> tot(nrhs, 0);
     SolveSpec s64 = sp;
     s64.mvp = VC_FP64;
-    std::vector<double> bn, rn;
+    std::vector<double> bn, rn, keep(nrhs), ones(nrhs, 1.0);
     s = col_norms(P, b, N, nrhs, P->s_norm.as<double>(), bn, st);
     if (s != VC_OK) return s;
     VC_HIP(hipMemcpyAsync(rrp, b, (size_t)nrhs * N * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -295,7 +300,6 @@ vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const doub
       vc_status si = gmres(P, s32, rrp, ddp, nrhs, it, rre, st);
       if (si != VC_OK && si != VC_ERR_NOT_CONVERGED) return si;
       for (int c = 0; c < nrhs; ++c) tot[c] += it[c];
-      std::vector<double> ones(nrhs, 1.0);
       VC_HIP(hipMemcpyAsync(P->s_norm.as<double>() + nrhs, ones.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
       VC_HIP(launch_axpy_cols(x, ddp, N, nrhs, P->s_norm.as<double>() + nrhs, 0, st));
       vc_status sr = residual(P, s64, b, x, rrp, nrhs, st);
@@ -305,13 +309,20 @@ vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const doub
       bool ok = true;
       for (int c = 0; c < nrhs; ++c) {
         rre[c] = bn[c] > 0 ? rn[c] / bn[c] : 0.0;
+        keep[c] = rre[c] > o.rtol ? 1.0 : 0.0;
         if (rre[c] > o.rtol) ok = false;
       }
       if (ok) { s = VC_OK; ++ir_steps; break; }
+      // columns already within rtol get a zero residual: the next inner solve leaves them
+      VC_HIP(hipMemcpyAsync(P->s_norm.as<double>() + 2 * nrhs, keep.data(), nrhs * sizeof(double),
+                            hipMemcpyHostToDevice, st));
+      VC_HIP(launch_scale_cols(rrp, N, N, nrhs, P->s_norm.as<double>() + 2 * nrhs, 0, st));
     }
     it = tot;
     if (s != VC_OK) set_error("refinement did not reach rtol %.3g in %d steps", o.rtol, o.ir_max);
   }
+  if (it_out) *it_out = it;
+  if (rre_out) *rre_out = rre;
   if (stats) {
     for (int c = 0; c < nrhs && c < 64; ++c) {
       stats->iters[c] = c < (int)it.size() ? it[c] : 0;

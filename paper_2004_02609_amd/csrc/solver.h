@@ -1,5 +1,5 @@
 // Internal interface of the GMRES driver (solver.cpp) shared by the C ABI (api.cpp)
-// and the multi-scene batch driver (batch.cpp).
+// and the packed multi-problem solve (pack.cpp).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -29,7 +29,7 @@ double now_s();
 vc_status ensure_workspace(vc_problem* P, int nrhs, int restart);
 Cyc cycle_views(vc_problem* P, int nrhs, int m);
 vc_status op_with_precond(vc_problem* P, const SolveSpec& sp, const double* v, double* z, double* w, int nrhs,
-                          hipStream_t st, const int* skip = nullptr);
+                          hipStream_t st, const int* skip = nullptr, const int* act = nullptr);
 vc_status residual(vc_problem* P, const SolveSpec& sp, const double* b, const double* x, double* r, int nrhs,
                    hipStream_t st, const int* skip = nullptr);
 vc_status col_norms(vc_problem* P, const double* w, int64_t N, int nrhs, double* d_out, std::vector<double>& h,
@@ -41,9 +41,12 @@ vc_status gmres(vc_problem* P, const SolveSpec& sp, const double* b, double* x, 
                 std::vector<double>& rre, hipStream_t st);
 hipStream_t get_solve_stream(vc_problem* P);
 vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const double* b, double* x, int nrhs,
-                vc_stats* stats, hipStream_t st);
+                vc_stats* stats, hipStream_t st, std::vector<int>* it_out = nullptr,
+                std::vector<double>* rre_out = nullptr);
 vc_solve_opts fill_defaults(const vc_solve_opts* in);
-vc_status batch_capacitance(vc_problem* const* problems, int n, const vc_solve_opts* opts, double* const* C_out,
-                            vc_stats* stats);
+// packed sets (pack.cpp): members must outlive the combined problem
+vc_status pack_create(vc_problem* const* problems, int n, vc_problem** out);
+vc_status pack_capacitance(vc_problem* q, const vc_solve_opts* opts, double* const* C_out, vc_stats* stats);
+void pack_info(const vc_problem* q, int32_t out[6]);
 
 }  // namespace vc

@@ -204,18 +204,20 @@ hipError_t launch_axpy_cols(double* y, const double* x, int64_t N, int nrhs, con
 }
 
 // Dielectric rows of eq. (14): y = x / I_kk; conductor rows are overwritten by the block apply.
+// (dinv_ld: column stride of dinv, 0 when one diagonal serves every column)
 __global__ void k_diag_scale(const double* __restrict__ x, double* __restrict__ y, const double* __restrict__ dinv,
-                             int64_t N, const int* __restrict__ skip) {
+                             int64_t dinv_ld, int64_t N, const int* __restrict__ skip) {
   if (skip && *skip) return;
   const int r = blockIdx.y;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
-  y[(int64_t)r * N + n] = dinv[n] * x[(int64_t)r * N + n];
+  y[(int64_t)r * N + n] = dinv[(int64_t)r * dinv_ld + n] * x[(int64_t)r * N + n];
 }
 
 hipError_t launch_diag_scale(const double* x, double* y, const double* dinv, int64_t N, int nrhs, const int* skip,
-                             hipStream_t st) {
-  hipLaunchKernelGGL(k_diag_scale, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, x, y, dinv, N, skip);
+                             hipStream_t st, int64_t dinv_ld) {
+  hipLaunchKernelGGL(k_diag_scale, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, x, y, dinv, dinv_ld, N,
+                     skip);
   return hipGetLastError();
 }
 
@@ -227,10 +229,17 @@ __global__ void __launch_bounds__(kBoxThreads)
 k_block_apply(const double* __restrict__ x, double* __restrict__ y, int64_t N, int nrhs,
               const int32_t* __restrict__ box_ptr, const int32_t* __restrict__ box_panels,
               const int32_t* __restrict__ box_block, const int64_t* __restrict__ block_off,
-              const int32_t* __restrict__ block_n, const double* __restrict__ blocks, const int* __restrict__ skip) {
+              const int32_t* __restrict__ block_n, const double* __restrict__ blocks, const int* __restrict__ skip,
+              const int32_t* __restrict__ box_c0, const int32_t* __restrict__ box_nc) {
   if (skip && *skip) return;
   __shared__ double xs[kBoxLds];
   const int box = blockIdx.x;
+  if (box_c0) {   // the box belongs to one problem of a packed set: its own columns only
+    const int64_t o = (int64_t)box_c0[box] * N;
+    x += o;
+    y += o;
+    nrhs = box_nc[box];
+  }
   const int p0 = box_ptr[box];
   const int nb = box_ptr[box + 1] - p0;
   const int blk = box_block[box];
@@ -259,10 +268,10 @@ k_block_apply(const double* __restrict__ x, double* __restrict__ y, int64_t N, i
 hipError_t launch_block_apply(const double* x, double* y, int64_t N, int nrhs, const int32_t* box_ptr,
                               const int32_t* box_panels, const int32_t* box_block, const int64_t* block_off,
                               const int32_t* block_n, const double* blocks, int nbox, const int* skip,
-                              hipStream_t st) {
+                              hipStream_t st, const int32_t* box_c0, const int32_t* box_nc) {
   if (nbox == 0) return hipSuccess;
   hipLaunchKernelGGL(k_block_apply, dim3(nbox), dim3(kBoxThreads), 0, st, x, y, N, nrhs, box_ptr, box_panels,
-                     box_block, block_off, block_n, blocks, skip);
+                     box_block, block_off, block_n, blocks, skip, box_c0, box_nc);
   return hipGetLastError();
 }
 
@@ -292,8 +301,13 @@ hipError_t launch_cap_reduce(const double* rho, int64_t N, int m, const int32_t*
 // ------------------------------------------------------------------ device-side GMRES cycle
 // The restart cycle runs without host round trips (so it can be captured as a graph):
 // per-column Hessenberg columns, Givens rotations, convergence masks and the final
-// triangular solve live on the device.  One workgroup, one thread per column.
+// triangular solve live on the device.  One workgroup, one thread per column (up to
+// kCycleMax columns).
 // Per-column state layout: H[c][(m+1) x m] row-major, cs/sn[c][m], g[c][m+1].
+
+constexpr int kCycleMax = 256;
+// a power of two (the block reductions halve the width) of at least one wave
+static inline unsigned cycle_threads(int nrhs) { return nrhs <= 64 ? 64u : (nrhs <= 128 ? 128u : 256u); }
 
 __device__ __forceinline__ int any_over_block(int v, int* red) {
   red[threadIdx.x] = v;
@@ -312,7 +326,7 @@ __global__ void k_cycle_start(int nrhs, int m, const double* __restrict__ rn, co
                               double* __restrict__ g, double* __restrict__ scal, int* __restrict__ kd,
                               int* __restrict__ skip, double* __restrict__ rre_out) {
   if (skip[2]) return;   // problem disabled for this round (batched form): state left as is
-  __shared__ int red[64];
+  __shared__ int red[kCycleMax];
   const int c = threadIdx.x;
   const double rtol = *rtolp;
   int a = 0;
@@ -338,8 +352,8 @@ __global__ void k_cycle_start(int nrhs, int m, const double* __restrict__ rn, co
 hipError_t launch_cycle_start(int nrhs, int m, const double* rn, const double* bn, const double* rtol, int* act_cycle,
                               int* act_step, double* g, double* scal, int* kd, int* skip, double* rre_out,
                               hipStream_t st) {
-  if (nrhs > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(64), 0, st, nrhs, m, rn, bn, rtol, act_cycle, act_step, g, scal,
+  if (nrhs > kCycleMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(cycle_threads(nrhs)), 0, st, nrhs, m, rn, bn, rtol, act_cycle, act_step, g, scal,
                      kd, skip, rre_out);
   return hipGetLastError();
 }
@@ -353,7 +367,7 @@ __global__ void k_arnoldi(int j, int nrhs, int m, const double* __restrict__ h1,
                           double* __restrict__ sn, double* __restrict__ g, const double* __restrict__ bn,
                           const double* __restrict__ rtolp, int* __restrict__ act_step, int* __restrict__ kd, int* __restrict__ iters,
                           double* __restrict__ scal, int* __restrict__ skip, int* __restrict__ bad) {
-  __shared__ int red[64];
+  __shared__ int red[kCycleMax];
   const int c = threadIdx.x;
   const double rtol = *rtolp;
   int still = 0;
@@ -399,8 +413,8 @@ __global__ void k_arnoldi(int j, int nrhs, int m, const double* __restrict__ h1,
 hipError_t launch_arnoldi(int j, int nrhs, int m, const double* h1, const double* h2, int ldh, const double* hn,
                           double* H, double* cs, double* sn, double* g, const double* bn, const double* rtol,
                           int* act_step, int* kd, int* iters, double* scal, int* skip, int* bad, hipStream_t st) {
-  if (nrhs > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), 0, st, j, nrhs, m, h1, h2, ldh, hn, H, cs, sn, g, bn, rtol,
+  if (nrhs > kCycleMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(cycle_threads(nrhs)), 0, st, j, nrhs, m, h1, h2, ldh, hn, H, cs, sn, g, bn, rtol,
                      act_step, kd, iters, scal, skip, bad);
   return hipGetLastError();
 }
@@ -429,8 +443,8 @@ __global__ void k_backsolve(int nrhs, int m, const double* __restrict__ H, const
 
 hipError_t launch_backsolve(int nrhs, int m, const double* H, const double* g, const int* kd, const int* act_cycle,
                             double* y, int ldy, hipStream_t st) {
-  if (nrhs > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, st, nrhs, m, H, g, kd, act_cycle, y, ldy);
+  if (nrhs > kCycleMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(cycle_threads(nrhs)), 0, st, nrhs, m, H, g, kd, act_cycle, y, ldy);
   return hipGetLastError();
 }
 

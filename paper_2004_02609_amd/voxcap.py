@@ -82,6 +82,11 @@ _sig = {
     "vc_tuning_report": (C.c_int, [_P, C.c_char_p, C.c_int32]),
     "vc_capacitance_batch": (C.c_int, [C.POINTER(_P), C.c_int32, C.POINTER(vc_solve_opts), C.POINTER(C.c_void_p),
                                        C.POINTER(vc_stats)]),
+    "vc_pack_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.POINTER(_P)]),
+    "vc_pack_destroy": (C.c_int, [_P]),
+    "vc_pack_info": (C.c_int, [_P, C.POINTER(C.c_int32)]),
+    "vc_pack_capacitance": (C.c_int, [_P, C.POINTER(vc_solve_opts), C.POINTER(C.c_void_p), C.POINTER(vc_stats)]),
+    "vc_pack_apply": (C.c_int, [_P, C.c_int, C.c_void_p, C.c_void_p, _P]),
     "vc_tucker_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                  C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "vc_charges_to_capacitance": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
@@ -213,12 +218,50 @@ def vc_tucker_info(h):
             "rebuild_ms": ms.value, "rebuilds": cnt.value}
 
 
+def _handles(handles):
+    n = len(handles)
+    return (_P * n)(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+
+
+def vc_pack_create(handles):
+    out = _P()
+    _check(_lib.vc_pack_create(_handles(handles), len(handles), C.byref(out)), "vc_pack_create")
+    return out
+
+
+def vc_pack_destroy(h):
+    _check(_lib.vc_pack_destroy(h), "vc_pack_destroy")
+
+
+def vc_pack_info(h):
+    out = (C.c_int32 * 6)()
+    _check(_lib.vc_pack_info(h, out), "vc_pack_info")
+    keys = ("members", "columns", "rows", "launches_fp64", "launches_fp32", "launches_precond")
+    return dict(zip(keys, (int(v) for v in out)))
+
+
+def vc_pack_apply(h, x, y, prec="fp64", stream=None):
+    """y = A x for every member at once; x, y: (columns, rows) float64 CUDA tensors."""
+    _check(_lib.vc_pack_apply(h, _PREC[prec], _ptr(x), _ptr(y), _stream(stream)), "vc_pack_apply")
+
+
+def vc_pack_capacitance(h, ms, allow_not_converged=False, **solve):
+    o = _solve_opts(**solve)
+    n = len(ms)
+    Cs = [np.zeros((m, m)) for m in ms]
+    outs = (C.c_void_p * n)(*[c.ctypes.data for c in Cs])
+    st = (vc_stats * n)()
+    status = _check(_lib.vc_pack_capacitance(h, C.byref(o), outs, st), "vc_pack_capacitance",
+                    allow=(VC_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+    return Cs, [stats_dict(st[k], ms[k]) for k in range(n)], status
+
+
 def vc_capacitance_batch(handles, ms, allow_not_converged=False, **solve):
     """C matrices (list of m_k x m_k arrays) and stats of several set-up problems solved
-    together (one graph launch per round over all unfinished problems)."""
+    as one packed set (create, solve, free)."""
     o = _solve_opts(**solve)
     n = len(handles)
-    hs = (_P * n)(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    hs = _handles(handles)
     Cs = [np.zeros((m, m)) for m in ms]
     outs = (C.c_void_p * n)(*[c.ctypes.data for c in Cs])
     st = (vc_stats * n)()
@@ -304,6 +347,47 @@ def capacitance_batch(problems, **solve):
     ([C_k], [stats_k])."""
     Cs, sts, _ = vc_capacitance_batch([p._h for p in problems], [p.m for p in problems], **solve)
     return Cs, sts
+
+
+class Pack:
+    """Owning wrapper of a vc_pack: set-up Problems of any sizes solved as one (their
+    products and preconditioner in shared launches).  Keeps the members alive; they
+    must not be set up again while the pack exists."""
+
+    def __init__(self, problems):
+        self.members = list(problems)
+        self._h = vc_pack_create([p._h for p in self.members])
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            vc_pack_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        return vc_pack_info(self._h)
+
+    def apply(self, x, prec="fp64"):
+        """Product of every member: x (columns, rows) float64 CUDA tensor -> y (same shape;
+        rows past a member's panel count come back zero)."""
+        import torch
+        inf = self.info()
+        if tuple(x.shape) != (inf["columns"], inf["rows"]) or x.dtype != torch.float64 or not x.is_cuda:
+            raise ValueError(f"x must be a ({inf['columns']}, {inf['rows']}) float64 CUDA tensor")
+        x = x.contiguous()
+        y = torch.zeros_like(x)
+        vc_pack_apply(self._h, x, y, prec=prec, stream=torch.cuda.current_stream())
+        return y
+
+    def capacitance(self, **solve):
+        """([C_k], [stats_k]) for every member."""
+        Cs, sts, _ = vc_pack_capacitance(self._h, [p.m for p in self.members], **solve)
+        return Cs, sts
 
 
 class Problem:
