@@ -251,6 +251,16 @@ vc_status vc_xpass_set(vc_problem *p, vc_precision prec, int transpose, int32_t 
                        const int32_t cfg[8]);
 vc_status vc_pass_times(vc_problem *p, double ms[5], int32_t launches[5], double bytes[5]);
 
+/* Tuning cache file (text, one line per choice).  vc_tuning_save merges this problem's
+ * timed x-pass choices into `path` (replacing entries of the same shape, precision,
+ * direction, nrhs and GPU architecture; written to path.tmp, then renamed) and reports
+ * how many it wrote.  vc_tuning_load adopts every entry of `path` that matches this
+ * problem's shape and architecture and is one of its own candidates (as if pinned by
+ * vc_xpass_set, so those products skip the timing); a missing file loads nothing.
+ * Both require vc_setup; a later vc_setup forgets what was loaded. */
+vc_status vc_tuning_save(vc_problem *p, const char *path, int32_t *n_saved);
+vc_status vc_tuning_load(vc_problem *p, const char *path, int32_t *n_loaded);
+
 const char *vc_status_string(vc_status s);
 const char *vc_last_error(void);
 

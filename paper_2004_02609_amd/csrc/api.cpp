@@ -474,7 +474,7 @@ vc_status vc_tuning_report(vc_problem* p, char* buf, int32_t len) {
     }
     std::snprintf(line, sizeof line, "x-pass %s %s nrhs=%d radices=%s cols=%d threads=%d %s", (kv.first & 1) ? "fp64" : "fp32",
                   (kv.first & 2) ? "transpose" : "forward", kv.first >> 2, rad.c_str(), 1 << c.lgc, c.nthr,
-                  c.tuned ? "tuned" : "default");
+                  c.from_file ? "cached" : (c.tuned ? "tuned" : "default"));
     out += line;
     if (c.tuned) {
       std::snprintf(line, sizeof line, " best_ms=%.4f default_ms=%.4f", c.ms_best, c.ms_default);

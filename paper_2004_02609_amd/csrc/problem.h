@@ -185,6 +185,7 @@ struct vc_problem {
     uint32_t radpack;
     bool tuned;
     double ms_best, ms_default;
+    bool from_file = false;   // read from a tuning cache (vc_tuning_load)
   };
   std::map<int, SandChoice> sand_choice;
   // per-pass timing (measurement)

@@ -94,6 +94,8 @@ _sig = {
     "vc_xpass_candidates": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int32), C.c_int32,
                                       C.POINTER(C.c_int32)]),
     "vc_xpass_set": (C.c_int, [_P, C.c_int, C.c_int, C.c_int32, C.POINTER(C.c_int32)]),
+    "vc_tuning_save": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int32)]),
+    "vc_tuning_load": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int32)]),
     "vc_status_string": (C.c_char_p, [C.c_int]),
     "vc_last_error": (C.c_char_p, []),
 }
@@ -276,6 +278,18 @@ def vc_tuning_report(h):
     return buf.value.decode()
 
 
+def vc_tuning_save(h, path):
+    n = C.c_int32(0)
+    _check(_lib.vc_tuning_save(h, os.fsencode(path), C.byref(n)), "vc_tuning_save")
+    return n.value
+
+
+def vc_tuning_load(h, path):
+    n = C.c_int32(0)
+    _check(_lib.vc_tuning_load(h, os.fsencode(path), C.byref(n)), "vc_tuning_load")
+    return n.value
+
+
 def vc_xpass_candidates(h, prec="fp64", transpose=False):
     n = C.c_int32(0)
     _check(_lib.vc_xpass_candidates(h, _PREC[prec], int(bool(transpose)), None, 0, C.byref(n)),
@@ -453,6 +467,14 @@ class Problem:
     def tuning_report(self):
         """Launch configurations of the x pass in use (and what the autotuner measured)."""
         return vc_tuning_report(self._h)
+
+    def save_tuning(self, path):
+        """Merge the timed x-pass choices into the cache file `path`; returns how many."""
+        return vc_tuning_save(self._h, path)
+
+    def load_tuning(self, path):
+        """Adopt the cached x-pass choices of `path` that fit this problem; returns how many."""
+        return vc_tuning_load(self._h, path)
 
     def pass_times(self):
         """(ms summed, launches, algorithmic bytes of one launch) per pass of the product."""

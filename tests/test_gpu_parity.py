@@ -171,6 +171,28 @@ def test_autotuned_product_matches_dense(dev):
     rep = P.tuning_report()
     print(rep, flush=True)
     assert rep.count("tuned") == 4, rep
+    # the tuning cache file: a second problem of the same shape adopts the four choices
+    # without timing and computes the same products
+    import os
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "xpass.txt")
+        assert P.save_tuning(path) == 4
+        assert P.save_tuning(path) == 4                      # merge replaces, never duplicates
+        assert len(open(path).read().splitlines()) == 4
+        Q = _problem(s, max_rhs=2, autotune=True)
+        assert Q.load_tuning(path) == 4
+        other = _problem(scenes.random_small(21, shape=(2, 6, 5), n_cond=1, n_diel=1), max_rhs=2)
+        assert other.load_tuning(path) == 0                  # another shape takes nothing
+        assert Q.load_tuning(os.path.join(d, "missing.txt")) == 0
+    for prec in ("fp64", "fp32"):
+        for transpose in (False, True):
+            yq = Q.apply(xt, transpose=transpose, prec=prec).cpu().numpy()
+            yp = P.apply(xt, transpose=transpose, prec=prec).cpu().numpy()
+            assert np.array_equal(yq, yp), (prec, transpose)
+    rq = Q.tuning_report()
+    print(rq, flush=True)
+    assert rq.count("cached") == 4 and rq.count("tuned") == 0, rq
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
