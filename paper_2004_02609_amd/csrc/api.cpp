@@ -115,6 +115,7 @@ vc_status vc_setup(vc_problem* p, const vc_setup_opts* opts, void* stream) {
   if (o.tucker_tol < 0) { set_error("tucker_tol must be >= 0"); return VC_ERR_ARG; }
   const double t0 = now_s();
   VC_HIP(hipSetDevice(p->device));
+  note_device_lds(p->device);
   p->drop_graphs();   // they hold pointers to tables and work arrays set up again below
   hipStream_t st = (hipStream_t)stream;
   vc_status s = choose_sizes(p, (o.fft_size[0] || o.fft_size[1] || o.fft_size[2]) ? o.fft_size : nullptr);

@@ -15,8 +15,12 @@ template <typename T> struct Tune {
   // largest FFT radix compiled into the z and strided kernels (register budget)
   static constexpr int maxr = sizeof(T) == 4 ? 21 : 12;
 };
-// Dynamic LDS per workgroup kept within the default 64 KiB launch limit.
+// Dynamic LDS per workgroup: tiles are chosen within 64 KiB (several workgroups per
+// CU); a transform too long for that falls back to the device's per-workgroup maximum
+// (160 KiB on gfx950), queried at setup.
 constexpr size_t kLdsBudget = 64 * 1024;
+size_t lds_ext_budget();
+void note_device_lds(int device);
 
 // Up to six field components handled by one strided launch (blockIdx.z = comp*nrhs+rhs).
 struct CompSet {
@@ -229,6 +233,7 @@ struct GemmArgs {
 template <typename T>
 hipError_t launch_mfma_gemm(const T* A, const T* B, T* C, const GemmArgs& g, hipStream_t st);
 hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t st);
+hipError_t launch_swap01(const double* in, double* out, int A, int B, int C, hipStream_t st);
 
 hipError_t launch_cap_reduce_n(const double* rho, int64_t N, int m, int nrhs, const int32_t* cond_panels,
                                const int32_t* cond_ptr, const double* weight, double scale, double* C,

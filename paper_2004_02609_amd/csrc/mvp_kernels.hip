@@ -305,6 +305,15 @@ static size_t lds_bytes(int L, int ncol) {
   return sizeof(C2<T>) * ((size_t)L + 2 * (size_t)L * (ncol + 1));   // twiddles + ping-pong tiles
 }
 
+// launches above the default 64 KiB of dynamic LDS declare it first
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t lds) {
+  if (lds <= kLdsBudget) return hipSuccess;
+  if (lds > lds_ext_budget()) return hipErrorInvalidValue;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
+}
+
 size_t zs_lds_bytes(int elem, int L, int ncol) {
   return (size_t)2 * elem * ((size_t)L + 2 * (size_t)L * (ncol + 1));
 }
@@ -320,6 +329,8 @@ hipError_t launch_zfwd(const double* x, int64_t N, int nrhs, int mode, const int
   a.comp_stride = comp_stride; a.rhs_stride = rhs_stride;
   a.nitems = nitems; a.nrhs = nrhs; a.n1x = n1x; a.n1y = n1y; a.My = My; a.H = H; a.lgc = ilog2(ncol);
   dim3 grid((nitems + ncol - 1) / ncol, mode == 0 ? (nrhs + 1) / 2 : nrhs);
+  const hipError_t e = allow_lds(k_zfwd<T>, lds_bytes<T>(pl.L, ncol));
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_zfwd<T>), grid, dim3(nthr), lds_bytes<T>(pl.L, ncol), st, a, mode, x, N, skip, act);
   return hipGetLastError();
 }
@@ -331,6 +342,8 @@ hipError_t launch_strided(void* data, const StridedArgs& a, const CompSet& cs, i
   StridedArgs b = a;
   b.lgc = ilog2(a.ncol);
   if ((1 << b.lgc) != a.ncol) return hipErrorInvalidValue;
+  const hipError_t e = allow_lds(k_strided<T>, lds_bytes<T>(pl.L, a.ncol));
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_strided<T>), grid, dim3(nthr), lds_bytes<T>(pl.L, a.ncol), st, (C2<T>*)data, b, cs,
                      pl, (const C2<T>*)tw, lflag, pflag);
   return hipGetLastError();
@@ -391,6 +404,8 @@ hipError_t launch_zinv(const void* O, double* y, const double* x, int64_t N, int
   a.comp_stride = comp_stride; a.rhs_stride = rhs_stride;
   a.nitems = nitems; a.nrhs = nrhs; a.n1x = n1x; a.n1y = n1y; a.My = My; a.H = H; a.lgc = ilog2(ncol);
   dim3 grid((nitems + ncol - 1) / ncol, mode == 0 ? nrhs : (nrhs + 1) / 2);
+  const hipError_t e = allow_lds(k_zinv<T>, lds_bytes<T>(pl.L, ncol));
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_zinv<T>), grid, dim3(nthr), lds_bytes<T>(pl.L, ncol), st, a, mode, x, y, N, skip, act);
   return hipGetLastError();
 }
@@ -400,6 +415,8 @@ template <typename T>
 hipError_t launch_zfwd_multi(const ZScene* tab, int nscene, int nblocks, const double* x, int64_t ldx,
                              const int* skip, const int* act, int nthr, size_t lds, hipStream_t st) {
   if (nscene <= 0 || nblocks <= 0) return hipSuccess;
+  const hipError_t e = allow_lds(k_zfwd_multi<T>, lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_zfwd_multi<T>), dim3(nblocks), dim3(nthr), lds, st, tab, nscene, x, ldx, skip, act);
   return hipGetLastError();
 }
@@ -407,6 +424,8 @@ template <typename T>
 hipError_t launch_zinv_multi(const ZScene* tab, int nscene, int nblocks, const double* x, double* y, int64_t ldx,
                              const int* skip, const int* act, int nthr, size_t lds, hipStream_t st) {
   if (nscene <= 0 || nblocks <= 0) return hipSuccess;
+  const hipError_t e = allow_lds(k_zinv_multi<T>, lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_zinv_multi<T>), dim3(nblocks), dim3(nthr), lds, st, tab, nscene, x, y, ldx, skip, act);
   return hipGetLastError();
 }
@@ -414,6 +433,8 @@ template <typename T>
 hipError_t launch_strided_multi(const StridedScene* tab, int nscene, int nblocks, const int* skip, const int* act,
                                 int nthr, size_t lds, hipStream_t st) {
   if (nscene <= 0 || nblocks <= 0) return hipSuccess;
+  const hipError_t e = allow_lds(k_strided_multi<T>, lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_strided_multi<T>), dim3(nblocks), dim3(nthr), lds, st, tab, nscene, skip, act);
   return hipGetLastError();
 }

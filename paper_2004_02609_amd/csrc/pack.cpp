@@ -214,7 +214,7 @@ static vc_status build_tables(PackData& D, PackPrec& pp) {
   pp.yi.nblk = byi;
   pp.zi.nblk = bzi;
   for (PackPass* q : {&pp.zf, &pp.yf, &pp.yi, &pp.zi})
-    if (q->lds > kLdsBudget || q->nthr > 1024) { set_error("packed pass exceeds the launch limits"); return VC_ERR_ARG; }
+    if (q->lds > lds_ext_budget() || q->nthr > 1024) { set_error("packed pass exceeds the launch limits"); return VC_ERR_ARG; }
   vc_status s;
   if ((s = upload_tab(pp.zf, zf)) != VC_OK || (s = upload_tab(pp.yf, yf)) != VC_OK ||
       (s = upload_tab(pp.yi, yi)) != VC_OK || (s = upload_tab(pp.zi, zi)) != VC_OK)

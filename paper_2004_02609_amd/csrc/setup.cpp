@@ -114,8 +114,22 @@ static hipError_t upload_axis(AxisTables& t, int L, int axis) {
 // Among feasible tiles, prefer little padding waste (tiles past the last column) and
 // enough workgroups (other_blocks = product of the other grid dimensions) to fill the
 // chip several times over; then the widest tile.
+static size_t g_lds_ext = kLdsBudget;
+
+size_t lds_ext_budget() { return g_lds_ext; }
+
+void note_device_lds(int device) {
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
+      (size_t)v > kLdsBudget)
+    g_lds_ext = (size_t)v;
+}
+
 bool pick_tile(int L, int elem_bytes, int emax, int ncols_total, int* ncol, int* nthr, size_t budget,
                int64_t other_blocks, int max_thr) {
+  // nothing fits the preferred budget: use the device's per-workgroup maximum
+  const size_t one = (size_t)elem_bytes * ((size_t)L + 2 * (size_t)L * 2);
+  if (one > budget && budget < g_lds_ext) budget = g_lds_ext;
   int best = 0;
   double best_score = -1e30;
   for (int c : {32, 16, 8, 4, 2, 1}) {

@@ -225,6 +225,12 @@ hipError_t launch_zr2c_dense(const double* in, void* out, int nlines, int H, con
                              int ncol, int nthr, hipStream_t st) {
   const int npairs = (nlines + 1) / 2;
   const size_t lds = sizeof(C2<double>) * ((size_t)pl.L + 2 * (size_t)pl.L * (ncol + 1));
+  if (lds > kLdsBudget) {   // a transform too long for the default budget declares its LDS
+    if (lds > lds_ext_budget()) return hipErrorInvalidValue;
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_zr2c_dense),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_zr2c_dense, dim3((npairs + ncol - 1) / ncol), dim3(nthr), lds, st, in, (C2<double>*)out,
                      nlines, H, pl, (const C2<double>*)tw, ncol);
   return hipGetLastError();

@@ -2,10 +2,11 @@
 // each product (eq. 13, Sec. II.C).
 //
 // Compression (FP64, once): the sequentially truncated HOSVD.  For modes kx, ky, kz in
-// turn the Gram matrix of the current tensor's unfolding is formed (rocBLAS GEMM), its
-// eigenvectors found (rocSOLVER syevd), the smallest rank whose discarded eigenvalues
-// sum to at most tol^2 ||X||^2 / 3 kept, and the tensor projected onto them; what is
-// left is the core.  The three budgets add up to ||X - X_hat|| <= tol ||X||.
+// turn the current tensor's unfolding goes through an SVD (rocSOLVER gesvd), the
+// smallest rank whose discarded squared singular values sum to at most
+// tol^2 ||X||^2 / 3 is kept, and the tensor is projected onto those singular vectors
+// (rocBLAS GEMM); what is left is the core.  The three budgets add up to
+// ||X - X_hat|| <= tol ||X||.
 //
 // Rebuild (every product, FP32 or FP64): three strided batched GEMMs on the matrix
 // cores (tucker_kernels.hip) write each stored pair back into the spectra buffer the
@@ -31,36 +32,41 @@ namespace vc {
     }                                                                        \
   } while (0)
 
-// Leading eigenvectors of the symmetric n x n Gram matrix G (device, column-major;
-// overwritten): the smallest r whose discarded eigenvalues sum to at most budget.
-// U: n x r row-major on the device.
-static vc_status leading_subspace(rocblas_handle h, double* G, int n, double budget, DevMem& U, int* r_out,
+// Leading right singular vectors of A (m x n column-major, lda = m; destroyed): the
+// smallest r whose discarded squared singular values sum to at most budget (directions
+// beyond min(m, n) carry none).  Singular vectors straight from the SVD of the
+// unfolding (not from the eigenvectors of its Gram matrix, whose squared condition
+// number limits the small components the spectra need to ~1e-8 of the largest).
+// U: n x r row-major on the device (U[i][a] = component i of vector a).
+static vc_status leading_subspace(rocblas_handle h, double* A, int m, int n, double budget, DevMem& U, int* r_out,
                                   hipStream_t st) {
-  DevMem ev, work, info;
-  VC_HIP(ev.alloc((size_t)n * sizeof(double)));
-  VC_HIP(work.alloc((size_t)n * sizeof(double)));
+  const int k = std::min(m, n);
+  DevMem sv, vt, e, info;
+  VC_HIP(sv.alloc((size_t)k * sizeof(double)));
+  VC_HIP(vt.alloc((size_t)n * n * sizeof(double)));
+  VC_HIP(e.alloc((size_t)std::max(k - 1, 1) * sizeof(double)));
   VC_HIP(info.alloc(sizeof(rocblas_int)));
-  VC_RB(rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, G, n, ev.as<double>(), work.as<double>(),
-                         info.as<rocblas_int>()));
-  std::vector<double> e(n), g((size_t)n * n);
+  VC_RB(rocsolver_dgesvd(h, rocblas_svect_none, rocblas_svect_all, m, n, A, m, sv.as<double>(), nullptr, 1,
+                         vt.as<double>(), n, e.as<double>(), rocblas_outofplace, info.as<rocblas_int>()));
+  std::vector<double> s(k), v((size_t)n * n);
   rocblas_int inf = 0;
-  VC_HIP(hipMemcpyAsync(e.data(), ev.p, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st));
+  VC_HIP(hipMemcpyAsync(s.data(), sv.p, (size_t)k * sizeof(double), hipMemcpyDeviceToHost, st));
+  VC_HIP(hipMemcpyAsync(v.data(), vt.p, v.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   VC_HIP(hipMemcpyAsync(&inf, info.p, sizeof(rocblas_int), hipMemcpyDeviceToHost, st));
-  VC_HIP(hipMemcpyAsync(g.data(), G, (size_t)n * n * sizeof(double), hipMemcpyDeviceToHost, st));
   VC_HIP(hipStreamSynchronize(st));
-  if (inf != 0) { set_error("symmetric eigensolver did not converge (info %d)", (int)inf); return VC_ERR_NUMERIC; }
-  // eigenvalues ascending: discard the d smallest with sum <= budget (negative round-off clamped)
-  int d = 0;
+  if (inf != 0) { set_error("SVD did not converge (info %d)", (int)inf); return VC_ERR_NUMERIC; }
+  // singular values descending: drop from the smallest while the dropped energy fits
+  int r = k;
   double acc = 0.0;
-  while (d < n - 1) {
-    acc += std::max(e[d], 0.0);
+  while (r > 1) {
+    acc += s[r - 1] * s[r - 1];
     if (acc > budget) break;
-    ++d;
+    --r;
   }
-  const int r = n - d;
+  // row a of V^T (element (a, i) at a + i n) is right singular vector a
   std::vector<double> u((size_t)n * r);
   for (int a = 0; a < r; ++a)
-    for (int i = 0; i < n; ++i) u[(size_t)i * r + a] = g[(size_t)(n - 1 - a) * n + i];
+    for (int i = 0; i < n; ++i) u[(size_t)i * r + a] = v[(size_t)a + (size_t)i * n];
   VC_HIP(U.alloc(u.size() * sizeof(double)));
   VC_HIP(hipMemcpyAsync(U.p, u.data(), u.size() * sizeof(double), hipMemcpyHostToDevice, st));
   VC_HIP(hipStreamSynchronize(st));
@@ -68,23 +74,21 @@ static vc_status leading_subspace(rocblas_handle h, double* G, int n, double bud
   return VC_OK;
 }
 
-// Compress one tensor X (device, D1 x D2 x D3 row-major: [kx][ky][kz]).
+// Compress one tensor X (device, D1 x D2 x D3 row-major: [kx][ky][kz]).  The mode-i
+// unfolding's transpose is handed to the SVD as a column-major matrix: X itself for
+// mode 1, a copy with the first two indices swapped for modes 2 and 3.
 static vc_status compress_one(rocblas_handle h, const double* X, int D1, int D2, int D3, double tol, TuckerPair& tp,
                               hipStream_t st) {
   const int64_t K1 = (int64_t)D2 * D3;
   const double one = 1.0, zero = 0.0;
-  // ||X||^2 and mode 1: G1 = X X^T
-  DevMem G1;
-  VC_HIP(G1.alloc((size_t)D1 * D1 * sizeof(double)));
-  VC_RB(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, D1, D1, (rocblas_int)K1, &one, X,
-                      (rocblas_int)K1, X, (rocblas_int)K1, &zero, G1.as<double>(), D1));
-  std::vector<double> g1((size_t)D1 * D1);
-  VC_HIP(hipMemcpyAsync(g1.data(), G1.p, g1.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-  VC_HIP(hipStreamSynchronize(st));
   double nrm2 = 0.0;
-  for (int i = 0; i < D1; ++i) nrm2 += g1[(size_t)i * D1 + i];
+  VC_RB(rocblas_ddot(h, (rocblas_int)(D1 * K1), X, 1, X, 1, &nrm2));   // host result: synchronizes
   const double budget = tol * tol * nrm2 / 3.0;
-  vc_status s = leading_subspace(h, G1.as<double>(), D1, budget, tp.U64[0], &tp.r[0], st);
+  // mode 1: A = X (D2 D3 x D1 column-major)
+  DevMem A;
+  VC_HIP(A.alloc((size_t)D1 * K1 * sizeof(double)));
+  VC_HIP(hipMemcpyAsync(A.p, X, (size_t)D1 * K1 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  vc_status s = leading_subspace(h, A.as<double>(), (int)K1, D1, budget, tp.U64[0], &tp.r[0], st);
   if (s != VC_OK) return s;
   const int r1 = tp.r[0];
   // X1 (r1 x D2 D3) = U1^T X
@@ -92,16 +96,9 @@ static vc_status compress_one(rocblas_handle h, const double* X, int D1, int D2,
   VC_HIP(X1.alloc((size_t)r1 * K1 * sizeof(double)));
   VC_RB(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)K1, r1, D1, &one, X,
                       (rocblas_int)K1, tp.U64[0].as<double>(), r1, &zero, X1.as<double>(), (rocblas_int)K1));
-  // mode 2: G2 = sum_a X1[a] X1[a]^T (X1[a] is D2 x D3)
-  DevMem G2;
-  VC_HIP(G2.alloc((size_t)D2 * D2 * sizeof(double)));
-  for (int a = 0; a < r1; ++a) {
-    const double beta = a == 0 ? 0.0 : 1.0;
-    const double* Xa = X1.as<double>() + (size_t)a * K1;
-    VC_RB(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, D2, D2, D3, &one, Xa, D3, Xa, D3,
-                        &beta, G2.as<double>(), D2));
-  }
-  s = leading_subspace(h, G2.as<double>(), D2, budget, tp.U64[1], &tp.r[1], st);
+  // mode 2: A[ky][a][kz] (r1 D3 x D2 column-major)
+  VC_HIP(launch_swap01(X1.as<double>(), A.as<double>(), r1, D2, D3, st));
+  s = leading_subspace(h, A.as<double>(), r1 * D3, D2, budget, tp.U64[1], &tp.r[1], st);
   if (s != VC_OK) return s;
   const int r2 = tp.r[1];
   // X2[a] (r2 x D3) = U2^T X1[a]
@@ -110,15 +107,12 @@ static vc_status compress_one(rocblas_handle h, const double* X, int D1, int D2,
   VC_RB(rocblas_dgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_transpose, D3, r2, D2, &one,
                                       X1.as<double>(), D3, K1, tp.U64[1].as<double>(), r2, 0, &zero, X2.as<double>(),
                                       D3, (rocblas_stride)r2 * D3, r1));
-  // mode 3: Y = X2 as (r1 r2 x D3); G3 = Y^T Y
-  DevMem G3;
-  VC_HIP(G3.alloc((size_t)D3 * D3 * sizeof(double)));
-  VC_RB(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, D3, D3, r1 * r2, &one, X2.as<double>(),
-                      D3, X2.as<double>(), D3, &zero, G3.as<double>(), D3));
-  s = leading_subspace(h, G3.as<double>(), D3, budget, tp.U64[2], &tp.r[2], st);
+  // mode 3: A[kz][(a, b)] (r1 r2 x D3 column-major)
+  VC_HIP(launch_swap01(X2.as<double>(), A.as<double>(), r1 * r2, D3, 1, st));
+  s = leading_subspace(h, A.as<double>(), r1 * r2, D3, budget, tp.U64[2], &tp.r[2], st);
   if (s != VC_OK) return s;
   const int r3 = tp.r[2];
-  // core S (r1 r2 x r3) = Y U3
+  // core S (r1 r2 x r3) = Y U3 with Y = X2 as (r1 r2 x D3)
   VC_HIP(tp.S64.alloc((size_t)r1 * r2 * r3 * sizeof(double)));
   VC_RB(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, r3, r1 * r2, D3, &one,
                       tp.U64[2].as<double>(), r3, X2.as<double>(), D3, &zero, tp.S64.as<double>(), r3));

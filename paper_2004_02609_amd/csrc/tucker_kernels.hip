@@ -81,6 +81,23 @@ __global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out,
   if (i < n) out[i] = (float)in[i];
 }
 
+// out[b][a][c] = in[a][b][c] (the unfoldings the compression hands to the SVD)
+__global__ void k_swap01(const double* __restrict__ in, double* __restrict__ out, int A, int B, int C) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)A * B * C;
+  if (i >= n) return;
+  const int64_t c = i % C, ab = i / C;
+  const int64_t b = ab % B, a = ab / B;
+  out[(b * A + a) * C + c] = in[i];
+}
+
+hipError_t launch_swap01(const double* in, double* out, int A, int B, int C, hipStream_t st) {
+  const int64_t n = (int64_t)A * B * C;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_swap01, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, A, B, C);
+  return hipGetLastError();
+}
+
 hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, n);
