@@ -434,7 +434,7 @@ vc_status vc_xpass_candidates(vc_problem* p, vc_precision prec, int transpose, i
     for (int k = 0; k < 8; ++k) row[k] = 0;
     row[0] = cand[r].nst;
     for (int s2 = 0; s2 < cand[r].nst; ++s2) row[1 + s2] = (int32_t)((cand[r].radpack >> (5 * s2)) & 31u);
-    row[7] = 1 << cand[r].lgc;
+    row[7] = cand[r].ncol;
   }
   return VC_OK;
 }
@@ -448,13 +448,13 @@ vc_status vc_xpass_set(vc_problem* p, vc_precision prec, int transpose, int32_t 
   const int nin = (transpose && p->n_diel > 0) ? 6 : 3;
   const std::vector<vc::SandCfg> cand = vc::sandwich_candidates(p->M[0], elem, nin, p->n1[0], vc::kLdsBudget);
   for (const vc::SandCfg& g : cand) {
-    bool same = cfg[0] == g.nst && cfg[7] == (1 << g.lgc);
+    bool same = cfg[0] == g.nst && cfg[7] == g.ncol;
     for (int s2 = 0; s2 < 6 && same; ++s2)
       same = cfg[1 + s2] == (s2 < g.nst ? (int32_t)((g.radpack >> (5 * s2)) & 31u) : 0);
     if (!same) continue;
     const int t = (transpose && p->n_diel > 0) ? 1 : 0;   // without dielectric rows A is symmetric
     const int key = (nrhs << 2) | (t << 1) | (elem == 8 ? 1 : 0);
-    p->sand_choice[key] = vc_problem::SandChoice{g.nst, g.tl, g.lgc, g.nthr, g.radpack, false, 0.0, 0.0};
+    p->sand_choice[key] = vc_problem::SandChoice{g.nst, g.tl, g.ncol, g.nthr, g.radpack, false, 0.0, 0.0};
     return VC_OK;
   }
   set_error("not an x-pass configuration of this problem (see vc_xpass_candidates)");
@@ -474,7 +474,7 @@ vc_status vc_tuning_report(vc_problem* p, char* buf, int32_t len) {
       rad += std::to_string((int)((c.radpack >> (5 * s)) & 31u));
     }
     std::snprintf(line, sizeof line, "x-pass %s %s nrhs=%d radices=%s cols=%d threads=%d %s", (kv.first & 1) ? "fp64" : "fp32",
-                  (kv.first & 2) ? "transpose" : "forward", kv.first >> 2, rad.c_str(), 1 << c.lgc, c.nthr,
+                  (kv.first & 2) ? "transpose" : "forward", kv.first >> 2, rad.c_str(), c.ncol, c.nthr,
                   c.from_file ? "cached" : (c.tuned ? "tuned" : "default"));
     out += line;
     if (c.tuned) {

@@ -69,23 +69,26 @@ static void pass_byte_model(vc_problem* P, int transpose, int elem, int nrhs, do
 }
 
 // Sandwich launch configurations for one x length: for every register radix RS the
-// plan with the fewest stages, and every power-of-two column tile that fits 512 threads
-// and the LDS budget.
+// plan with the fewest stages, and every column tile (1..32 columns) within 512 threads
+// and the LDS budget that is a power of two or keeps at least 3/4 of the workgroup's
+// lanes busy (tl x ncol of the rounded-up thread count).
 std::vector<SandCfg> sandwich_candidates(int L, int elem, int nin, int n1x, size_t budget) {
   std::vector<SandCfg> out;
   for (int rs = sandwich_rs_max(elem, nin); rs >= 2; --rs) {
     const AxisPlan sp = make_sandwich_plan(L, sandwich_rmax(elem), sandwich_rmid(elem), rs, 512);
     if (sp.nst < 1 || sp.rad[sp.nst - 1] != rs) continue;
-    for (int lgc = 0; lgc <= 5; ++lgc) {
-      const int c = 1 << lgc;
-      const int tl = L / rs;
+    const int tl = L / rs;
+    for (int c = 1; c <= 32; ++c) {
       if ((int64_t)c * tl > 512 || sandwich_lds_bytes(L, c, elem, n1x) > budget) break;
+      const int nthr = (c * tl + 63) / 64 * 64;
+      const bool pow2 = (c & (c - 1)) == 0;
+      if (!pow2 && 4 * c * tl < 3 * nthr) continue;
       SandCfg g{};
       g.nst = sp.nst;
       for (int s2 = 0; s2 < sp.nst; ++s2) g.radpack |= (uint32_t)sp.rad[s2] << (5 * s2);
       g.tl = tl;
-      g.lgc = lgc;
-      g.nthr = (c * tl + 63) / 64 * 64;
+      g.ncol = c;
+      g.nthr = nthr;
       out.push_back(g);
     }
   }
@@ -93,19 +96,24 @@ std::vector<SandCfg> sandwich_candidates(int L, int elem, int nin, int n1x, size
 }
 
 // Default without timing: fewest stages, then the largest register radix, then the
-// widest tile of at most 256 threads (several workgroups per CU), else the narrowest.
+// widest power-of-two tile of at most 256 threads (several workgroups per CU), else
+// the narrowest.  (Tiles of other widths are left to the autotuner: they fill waves
+// better but their gains and losses depend on the shape.)
 bool sandwich_default(int L, int elem, int nin, int n1x, size_t budget, SandCfg* cfg) {
   const std::vector<SandCfg> cand = sandwich_candidates(L, elem, nin, n1x, budget);
-  if (cand.empty()) return false;
   int best = -1;
   double bscore = -1e30;
   for (size_t k = 0; k < cand.size(); ++k) {
     const SandCfg& g = cand[k];
+    if (g.ncol & (g.ncol - 1)) continue;
     const int rs = (int)((g.radpack >> (5 * (g.nst - 1))) & 31u);
-    const double fit = g.nthr <= 256 ? 10.0 * g.lgc : -10.0 * g.lgc;
+    int lg = 0;
+    while ((1 << (lg + 1)) <= g.ncol) ++lg;
+    const double fit = g.nthr <= 256 ? 10.0 * lg : -10.0 * lg;
     const double score = -1e6 * g.nst + 1e3 * rs + fit;
     if (score > bscore) { bscore = score; best = (int)k; }
   }
+  if (best < 0) return false;
   *cfg = cand[best];
   return true;
 }
@@ -212,7 +220,7 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
         set_error("x transform length %d too long for the sandwich kernel", Mx);
         return VC_ERR_ARG;
       }
-      vc_problem::SandChoice ch{cfg.nst, cfg.tl, cfg.lgc, cfg.nthr, cfg.radpack, false, 0.0, 0.0};
+      vc_problem::SandChoice ch{cfg.nst, cfg.tl, cfg.ncol, cfg.nthr, cfg.radpack, false, 0.0, 0.0};
       hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
       VC_HIP(hipStreamIsCapturing(st, &cap));
       if (P->autotune && cap == hipStreamCaptureStatusNone) {
@@ -225,7 +233,7 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
         for (const SandCfg& g : cand) {
           SandArgs t = xa;
           t.act = nullptr;   // time every right-hand side
-          t.nst = g.nst; t.radpack = g.radpack; t.tl = g.tl; t.lgc = g.lgc;
+          t.nst = g.nst; t.radpack = g.radpack; t.tl = g.tl; t.ncol = g.ncol;
           VC_HIP(launch_sandwich<T>(F, O, tb.R.p, t, tb.ax[0].tw.p, tb.ax[0].ph.p, tb.ax[1].ph.p, tb.ax[2].ph.p,
                                     pflag, g.nthr, st));
           VC_HIP(hipEventRecord(e0, st));
@@ -237,10 +245,10 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
           float ms = 0.f;
           VC_HIP(hipEventElapsedTime(&ms, e0, e1));
           const double per = ms / 3.0;
-          if (g.radpack == cfg.radpack && g.lgc == cfg.lgc) dflt = per;
+          if (g.radpack == cfg.radpack && g.ncol == cfg.ncol) dflt = per;
           if (per < best) {
             best = per;
-            ch = vc_problem::SandChoice{g.nst, g.tl, g.lgc, g.nthr, g.radpack, true, 0.0, 0.0};
+            ch = vc_problem::SandChoice{g.nst, g.tl, g.ncol, g.nthr, g.radpack, true, 0.0, 0.0};
           }
         }
         (void)hipEventDestroy(e0);
@@ -251,7 +259,7 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
       it = P->sand_choice.emplace(key, ch).first;
     }
     const vc_problem::SandChoice& ch = it->second;
-    xa.nst = ch.nst; xa.radpack = ch.radpack; xa.tl = ch.tl; xa.lgc = ch.lgc;
+    xa.nst = ch.nst; xa.radpack = ch.radpack; xa.tl = ch.tl; xa.ncol = ch.ncol;
     nthr = ch.nthr;
   }
   VC_HIP(launch_sandwich<T>(F, O, tb.R.p, xa, tb.ax[0].tw.p, tb.ax[0].ph.p, tb.ax[1].ph.p, tb.ax[2].ph.p, pflag, nthr,

@@ -47,7 +47,7 @@ struct StridedArgs {
 struct SandArgs {
   int64_t comp_stride, rhs_stride, pair_stride;
   int nrhs, n1x, Mx, My, H, Hx, Hy;
-  int lgc;        // log2(columns per workgroup)
+  int ncol;       // (ky, kz) columns per workgroup, 1..32
   int adjoint;
   int nin, nout;
   // x transform: radices r_0 >= ... >= r_{nst-1} (product Mx), r_s in bits 5s..5s+4
@@ -85,7 +85,7 @@ hipError_t launch_sandwich(const void* Fin, void* Fout, const void* R, const San
                            hipStream_t st);
 // a sandwich launch configuration (plan, tile, threads)
 struct SandCfg {
-  int nst, tl, lgc, nthr;
+  int nst, tl, ncol, nthr;
   uint32_t radpack;
 };
 // one sandwich variant (NIN input / NOUT output components), last-stage radix rs

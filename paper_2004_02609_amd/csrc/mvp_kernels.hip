@@ -352,7 +352,7 @@ hipError_t launch_strided(void* data, const StridedArgs& a, const CompSet& cs, i
 template <typename T>
 bool sandwich_args_ok(const SandArgs& a, int nthr) {
   // the kernel assumes every one of these
-  if (a.nst < 1 || a.nst > kSandMaxStages || a.lgc < 0 || a.lgc > 5 || nthr < 64 || nthr > 512 || (nthr & 63))
+  if (a.nst < 1 || a.nst > kSandMaxStages || a.ncol < 1 || a.ncol > 32 || nthr < 64 || nthr > 512 || (nthr & 63))
     return false;
   long prod = 1;
   int prev = 1 << 30;
@@ -365,7 +365,7 @@ bool sandwich_args_ok(const SandArgs& a, int nthr) {
     prod *= r;
   }
   const int rs = (int)((a.radpack >> (5 * (a.nst - 1))) & 31u);
-  if (prod != a.Mx || (long)a.tl * rs != a.Mx || ((long)a.tl << a.lgc) > nthr) return false;
+  if (prod != a.Mx || (long)a.tl * rs != a.Mx || (long)a.tl * a.ncol > nthr) return false;
   if (a.nst == 1 && a.tl != 1) return false;
   if (rs > sandwich_rs_max((int)sizeof(T), a.nin)) return false;
   // 32-bit byte offsets inside one (component, rhs) slab and one stored pair
@@ -381,7 +381,7 @@ hipError_t launch_sandwich(const void* Fin, void* Fout, const void* R, const San
                            hipStream_t st) {
   if (!sandwich_args_ok<T>(a, nthr)) return hipErrorInvalidValue;
   const int rs = (int)((a.radpack >> (5 * (a.nst - 1))) & 31u);
-  const size_t lds = sandwich_lds_bytes(a.Mx, 1 << a.lgc, (int)sizeof(T), a.n1x);
+  const size_t lds = sandwich_lds_bytes(a.Mx, a.ncol, (int)sizeof(T), a.n1x);
   if (!a.adjoint && a.nin == 3 && a.nout == 6)
     return launch_sandwich_v<T, 3, 6>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st);
   if (!a.adjoint && a.nin == 3 && a.nout == 3)

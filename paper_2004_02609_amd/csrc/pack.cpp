@@ -162,7 +162,7 @@ static vc_status build_tables(PackData& D, PackPrec& pp) {
         set_error("x transform length %d too long for the sandwich kernel", Mx);
         return VC_ERR_ARG;
       }
-      xa.nst = cfg.nst; xa.radpack = cfg.radpack; xa.tl = cfg.tl; xa.lgc = cfg.lgc;
+      xa.nst = cfg.nst; xa.radpack = cfg.radpack; xa.tl = cfg.tl; xa.ncol = cfg.ncol;
       sc.Fin = P->work_F.p;
       sc.Fout = P->work_O.p;
       sc.R = tb.R.p;
@@ -172,14 +172,14 @@ static vc_status build_tables(PackData& D, PackPrec& pp) {
       sc.phz = tb.ax[2].ph.p;
       sc.pflag = P->d_pflag.as<uint8_t>();
       sc.c0 = c0;
-      sc.ntiles = (My * H + (1 << cfg.lgc) - 1) >> cfg.lgc;
+      sc.ntiles = (My * H + cfg.ncol - 1) / cfg.ncol;
       const int rs = (int)((cfg.radpack >> (5 * (cfg.nst - 1))) & 31u);
       const std::pair<int, int> key(xa.nout, rs);
       sg[key].push_back(sc);
       PackPass& g = sgp[key];
       g.rs = rs;
       g.nout = xa.nout;
-      grow(g, cfg.nthr, sandwich_lds_bytes(Mx, 1 << cfg.lgc, (int)sizeof(T), n1x));
+      grow(g, cfg.nthr, sandwich_lds_bytes(Mx, cfg.ncol, (int)sizeof(T), n1x));
     }
     // 4. inverse y transform of the outputs
     {

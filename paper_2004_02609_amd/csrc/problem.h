@@ -181,7 +181,7 @@ struct vc_problem {
   // x-pass launch configuration per (precision, direction, nrhs) key
   bool autotune = false;
   struct SandChoice {
-    int nst, tl, lgc, nthr;
+    int nst, tl, ncol, nthr;
     uint32_t radpack;
     bool tuned;
     double ms_best, ms_default;

@@ -224,16 +224,16 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
   constexpr uint32_t E = sizeof(C2<T>);
   extern __shared__ char smem_raw[];
   const int L = a.Mx, tl = a.tl, S = a.nst;
-  const int lgc = a.lgc, ncol = 1 << lgc;
+  const int ncol = a.ncol;
   const uint32_t ncolpE = (uint32_t)(ncol + 1) * E;
   char* twb = smem_raw;                                    // L twiddles
   char* lds = smem_raw + (size_t)L * E;                    // [L][ncol + 1] tile
   uint8_t* sflag = reinterpret_cast<uint8_t*>(lds + (size_t)L * ncolpE);   // plane flags of the 3 axes
   const int tid = threadIdx.x;
-  const int c = tid & (ncol - 1), i = tid >> lgc;
+  const int i = fdiv(tid, 1.0f / (float)ncol), c = tid - i * ncol;   // column fastest
   const bool valid = i < tl;
   const int ncols = a.My * a.H;                 // flattened (ky, kz) columns
-  const int col = (tile << lgc) + c;
+  const int col = tile * ncol + c;
   const bool colok = col < ncols;
   const int colc = colok ? col : ncols - 1;
   const int ky = fdiv(colc, 1.0f / (float)a.H), kz = colc - ky * a.H;
@@ -499,7 +499,7 @@ template <typename T, int NIN, int NOUT>
 hipError_t launch_sandwich_v(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
                              const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
                              size_t lds, int rs, hipStream_t st) {
-  dim3 grid((a.My * a.H + (1 << a.lgc) - 1) >> a.lgc, a.nrhs);
+  dim3 grid((a.My * a.H + a.ncol - 1) / a.ncol, a.nrhs);
 #define VC_RS(RR)                                                                                                 \
   case RR:                                                                                                        \
     if constexpr (RR <= SandRS<T, NIN>::max) {                                                                    \
