@@ -212,6 +212,16 @@ hipError_t launch_cycle_start(int nrhs, int m, const double* rn, const double* b
 hipError_t launch_arnoldi(int j, int nrhs, int m, const double* h1, const double* h2, int ldh, const double* hn,
                           double* H, double* cs, double* sn, double* g, const double* bn, const double* rtol,
                           int* act_step, int* kd, int* iters, double* scal, int* skip, int* bad, hipStream_t st);
+// One Arnoldi step after the product w = A z: CGS twice, |w| and the Givens update in
+// three launches (k = j + 1 basis vectors, nrhs <= 256).  cnt: cgs_counter_size(kmax,
+// nrhs) zeroed unsigned counters (each launch leaves them zero); partial: as for
+// launch_gemv_t; nrm_out: |w| per active column.
+hipError_t launch_cgs_step(const double* V, int64_t ldv, int64_t N, int k, double* w, int nrhs, double* h1,
+                           double* h2, int ldh, double* partial, unsigned* cnt, int j, int m, double* H, double* cs,
+                           double* sn, double* g, const double* bn, const double* rtol, int* act_step, int* kd,
+                           int* iters, double* scal, int* skip, int* bad, double* nrm_out, hipStream_t st);
+int64_t cgs_counter_size_a(int kmax, int nrhs);
+int64_t cgs_counter_size(int kmax, int nrhs);
 hipError_t launch_backsolve(int nrhs, int m, const double* H, const double* g, const int* kd, const int* act_cycle,
                             double* y, int ldy, hipStream_t st);
 hipError_t launch_scale_copy(double* dst, const double* src, int64_t N, int nrhs, const double* s, const int* skip,

@@ -138,16 +138,18 @@ struct vc_problem {
   // solver workspace
   vc::DevMem s_V, s_w, s_z, s_r, s_b, s_x, s_h, s_partial, s_norm, s_active, s_tmp, s_y2, s_rr, s_dd;
   vc::DevMem s_cyc, s_cyci;         // device-side GMRES cycle state (doubles, ints)
+  vc::DevMem s_cnt;                 // completion counters of the fused Gram-Schmidt step (rest at 0)
   int s_restart = 0, s_nrhs = 0;
   // restart cycles captured as graphs, keyed by what their kernel arguments bake in
   bool use_graphs = true;
   struct GraphKey {
     int mvp, transpose, precond, nrhs, restart;
+    int part;   // 0: cycle start, 1: the cycle's Arnoldi steps and update
     const double* b;
     double* x;
     bool operator==(const GraphKey& o) const {
       return mvp == o.mvp && transpose == o.transpose && precond == o.precond && nrhs == o.nrhs &&
-             restart == o.restart && b == o.b && x == o.x;
+             restart == o.restart && part == o.part && b == o.b && x == o.x;
     }
   };
   struct GraphEntry {
@@ -162,7 +164,7 @@ struct vc_problem {
     return nullptr;
   }
   void add_graph(const GraphKey& k, hipGraph_t g, hipGraphExec_t e) {
-    if (graphs.size() >= 8) {   // bounded cache: drop the oldest
+    if (graphs.size() >= 16) {   // bounded cache: drop the oldest
       (void)hipGraphExecDestroy(graphs.front().exec);
       (void)hipGraphDestroy(graphs.front().graph);
       graphs.erase(graphs.begin());

@@ -73,18 +73,29 @@ __device__ __forceinline__ double flip(double v, uint32_t s) {
   return __longlong_as_double((long long)u);
 }
 
-// v[q] *= w^(q ts), w = exp(-+2 pi i / L) from the LDS table; tsb = ts * sizeof(C2)
+// v[q] *= w^(q ts), w = exp(-+2 pi i / L) from the LDS table; tsb = ts * sizeof(C2).
+// All R-1 table reads are issued before the first multiply, so they are in flight
+// together instead of one LDS round trip per factor.
 template <typename T, int R>
 __device__ __forceinline__ void tw_mul(C2<T>* v, const char* __restrict__ twb, uint32_t tsb, T sg) {
+  C2<T> w[R];
   uint32_t o = 0;
 #pragma unroll
   for (int q = 1; q < R; ++q) {
     o += tsb;
-    C2<T> w = lds_ld<T>(twb, o);
-    w.y *= -sg;
-    v[q] = cmul(v[q], w);
+    w[q] = lds_ld<T>(twb, o);
+  }
+#pragma unroll
+  for (int q = 1; q < R; ++q) {
+    w[q].y *= -sg;
+    v[q] = cmul(v[q], w[q]);
   }
 }
+
+// 1/p for the butterfly split i = ip p + k of a middle stage (p <= 512, i < 512): the
+// hardware reciprocal (1 ulp) keeps fdiv exact there, (i + 1/2)/p being at least
+// 1/(2p) >= 1/1024 from an integer while the product errs by < 512 * 2^-22 / p
+__device__ __forceinline__ float stage_inv(int p) { return __builtin_amdgcn_rcpf((float)p); }
 
 // first-stage inputs of butterfly i: rows i + q L/R of one component from HBM into
 // registers; bit q of vmask says row i + q L/R is stored (else zero)
@@ -313,7 +324,7 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
       int p = r0;
       for (int s = 1; s < S - 1; ++s) {
         const int rs = srad(a, s);
-        const float invp = 1.0f / (float)p;
+        const float invp = stage_inv(p);
 #define VC_CALL(RR) sw_mid<T, RR>(lds, twb, L, p, invp, i, rbase, cE, ncolpE, T(-1));
         VC_SW_SWITCH(rs, VC_CALL, RMID)
 #undef VC_CALL
@@ -442,7 +453,7 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
       int p = RS;
       for (int s = S - 2; s >= 1; --s) {
         const int rs = srad(a, s);
-        const float invp = 1.0f / (float)p;
+        const float invp = stage_inv(p);
 #define VC_CALL(RR) sw_mid<T, RR>(lds, twb, L, p, invp, i, rbase, cE, ncolpE, T(1));
         VC_SW_SWITCH(rs, VC_CALL, RMID)
 #undef VC_CALL

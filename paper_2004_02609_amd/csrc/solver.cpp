@@ -46,6 +46,8 @@ vc_status ensure_workspace(vc_problem* P, int nrhs, int restart) {
   const size_t nd = (size_t)k * ((size_t)(r + 1) * r + 2 * r + (r + 1) + 4) + 1;
   VC_HIP(P->s_cyc.alloc(nd * sizeof(double)));
   VC_HIP(P->s_cyci.alloc(((size_t)4 * k + 5) * sizeof(int)));
+  VC_HIP(P->s_cnt.alloc((size_t)cgs_counter_size(r + 1, k) * sizeof(unsigned)));
+  VC_HIP(hipMemset(P->s_cnt.p, 0, P->s_cnt.bytes));
   // vectors start at zero: rows a product never writes (the padding rows of a packed
   // set) then stay zero through every update
   for (DevMem* d : {&P->s_V, &P->s_w, &P->s_z, &P->s_r, &P->s_b, &P->s_x, &P->s_tmp, &P->s_rr, &P->s_dd})
@@ -110,13 +112,16 @@ vc_status col_norms(vc_problem* P, const double* w, int64_t N, int nrhs, double*
   return VC_OK;
 }
 
-// One GMRES(m) restart cycle, every step on the device (so it can be captured):
-// residual and its norms, cycle start (masks, g, skip flags), m Arnoldi steps with
-// classical Gram-Schmidt applied twice and the Givens update, then x += R V y for the
-// columns that were active at the start.  Columns freeze once converged; when all
-// have, the remaining steps' products are skipped by the device flag.
-vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs,
-                             hipStream_t st) {
+// One GMRES(m) restart cycle, every step on the device (so it can be captured), in two
+// parts so that the last cycle of a solve (which only finds every column converged)
+// costs one residual:
+//   part 0: residual and its norms, cycle start (masks, g, skip flags), V_0 = r / |r|;
+//   part 1: m Arnoldi steps with classical Gram-Schmidt applied twice and the Givens
+//           update, then x += R V y for the columns that were active at the start.
+// Columns freeze once converged; when all have, the remaining steps' products are
+// skipped by the device flag.
+vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs, hipStream_t st,
+                      int part) {
   const int64_t N = npanels(P);
   const int m = sp.restart;
   const Cyc c = cycle_views(P, nrhs, m);
@@ -129,23 +134,23 @@ vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, doubl
   double* nrm = P->s_norm.as<double>();
   const int64_t ldv = (int64_t)nrhs * N;
   const int ldh = m + 2;
-  vc_status s = residual(P, sp, b, x, r, nrhs, st, c.skip + 2);
-  if (s != VC_OK) return s;
-  VC_HIP(launch_colnorm(r, N, N, nrhs, c.rn, P->s_partial.as<double>(), st, c.skip + 2));
-  VC_HIP(launch_cycle_start(nrhs, m, c.rn, c.bn, c.rtol, c.act_cycle, c.act_step, c.g, c.scal, c.kd, c.skip, c.rre,
-                            st));
-  VC_HIP(launch_scale_copy(V, r, N, nrhs, c.scal, c.skip, st));   // V_0 = r / |r|
+  vc_status s;
+  if (part == 0) {
+    s = residual(P, sp, b, x, r, nrhs, st, c.skip + 2);
+    if (s != VC_OK) return s;
+    VC_HIP(launch_colnorm(r, N, N, nrhs, c.rn, P->s_partial.as<double>(), st, c.skip + 2));
+    VC_HIP(launch_cycle_start(nrhs, m, c.rn, c.bn, c.rtol, c.act_cycle, c.act_step, c.g, c.scal, c.kd, c.skip, c.rre,
+                              st));
+    VC_HIP(launch_scale_copy(V, r, N, nrhs, c.scal, c.skip, st));   // V_0 = r / |r|
+    return VC_OK;
+  }
   for (int j = 0; j < m; ++j) {
     s = op_with_precond(P, sp, V + j * ldv, z, w, nrhs, st, c.skip + 1, c.act_step);
     if (s != VC_OK) return s;
-    VC_HIP(launch_gemv_t(V, ldv, N, j + 1, w, N, nrhs, hd, ldh, c.act_step, P->s_partial.as<double>(), st));
-    VC_HIP(launch_gemv_n_sub(V, ldv, N, j + 1, hd, ldh, w, N, nrhs, c.act_step, 0, st));
-    VC_HIP(launch_gemv_t(V, ldv, N, j + 1, w, N, nrhs, hd + (size_t)ldh * nrhs, ldh, c.act_step,
-                         P->s_partial.as<double>(), st));
-    VC_HIP(launch_gemv_n_sub(V, ldv, N, j + 1, hd + (size_t)ldh * nrhs, ldh, w, N, nrhs, c.act_step, 0, st));
-    VC_HIP(launch_colnorm(w, N, N, nrhs, nrm, P->s_partial.as<double>(), st));
-    VC_HIP(launch_arnoldi(j, nrhs, m, hd, hd + (size_t)ldh * nrhs, ldh, nrm, c.H, c.cs, c.sn, c.g, c.bn, c.rtol,
-                          c.act_step, c.kd, c.iters, c.scal, c.skip, c.bad, st));
+    // classical Gram-Schmidt twice, |w| and the Givens update (three launches)
+    VC_HIP(launch_cgs_step(V, ldv, N, j + 1, w, nrhs, hd, hd + (size_t)ldh * nrhs, ldh, P->s_partial.as<double>(),
+                           P->s_cnt.as<unsigned>(), j, m, c.H, c.cs, c.sn, c.g, c.bn, c.rtol, c.act_step, c.kd,
+                           c.iters, c.scal, c.skip, c.bad, nrm, st));
     if (j + 1 < m) VC_HIP(launch_scale_copy(V + (j + 1) * ldv, w, N, nrhs, c.scal, c.skip + 1, st));
   }
   // x += R V y, y = R_H^{-1} g over each column's steps
@@ -163,12 +168,12 @@ vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, doubl
   return VC_OK;
 }
 
-// The captured restart cycle for this solve shape (captured and instantiated on first
-// use).  An eager product first settles the launch configurations (and runs the
-// autotuner) outside the capture.
+// The captured part of a restart cycle for this solve shape (captured and
+// instantiated on first use).  An eager product first settles the launch
+// configurations (and runs the autotuner) outside the capture.
 vc_status cycle_graph(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs, hipStream_t st,
-                      hipGraph_t* g_out, hipGraphExec_t* e_out) {
-  vc_problem::GraphKey key{(int)sp.mvp, sp.transpose, sp.precond, nrhs, sp.restart, b, x};
+                      int part, hipGraph_t* g_out, hipGraphExec_t* e_out) {
+  vc_problem::GraphKey key{(int)sp.mvp, sp.transpose, sp.precond, nrhs, sp.restart, part, b, x};
   for (const auto& e : P->graphs)
     if (e.key == key) {
       *g_out = e.graph;
@@ -178,7 +183,7 @@ vc_status cycle_graph(vc_problem* P, const SolveSpec& sp, const double* b, doubl
   vc_status s = apply_op(P, sp.transpose, sp.mvp, b, P->s_tmp.as<double>(), nrhs, st);
   if (s != VC_OK) return s;
   VC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  vc_status sc = issue_cycle(P, sp, b, x, nrhs, st);
+  vc_status sc = issue_cycle(P, sp, b, x, nrhs, st, part);
   hipGraph_t gr = nullptr;
   const hipError_t ee = hipStreamEndCapture(st, &gr);
   if (sc != VC_OK) {
@@ -196,6 +201,17 @@ vc_status cycle_graph(vc_problem* P, const SolveSpec& sp, const double* b, doubl
   P->add_graph(key, gr, ex);
   *g_out = gr;
   *e_out = ex;
+  return VC_OK;
+}
+
+static vc_status run_part(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs, hipStream_t st,
+                          int part) {
+  if (!P->use_graphs) return issue_cycle(P, sp, b, x, nrhs, st, part);
+  hipGraph_t gr = nullptr;
+  hipGraphExec_t ex = nullptr;
+  vc_status s = cycle_graph(P, sp, b, x, nrhs, st, part, &gr, &ex);
+  if (s != VC_OK) return s;
+  VC_HIP(hipGraphLaunch(ex, st));
   return VC_OK;
 }
 
@@ -218,15 +234,15 @@ vc_status gmres(vc_problem* P, const SolveSpec& sp, const double* b, double* x, 
   std::vector<int> it(nrhs), skip(2);
   rre.assign(nrhs, 0.0);
   int bad = 0;
+  // start of the first cycle; each later round runs the previous cycle's steps and
+  // the next cycle's start before one host read-back
+  s = run_part(P, sp, b, x, nrhs, st, 0);
+  if (s != VC_OK) return s;
   for (int cycle = 0;; ++cycle) {
-    if (P->use_graphs) {
-      hipGraph_t gr = nullptr;
-      hipGraphExec_t ex = nullptr;
-      s = cycle_graph(P, sp, b, x, nrhs, st, &gr, &ex);
+    if (cycle > 0) {
+      s = run_part(P, sp, b, x, nrhs, st, 1);
       if (s != VC_OK) return s;
-      VC_HIP(hipGraphLaunch(ex, st));
-    } else {
-      s = issue_cycle(P, sp, b, x, nrhs, st);
+      s = run_part(P, sp, b, x, nrhs, st, 0);
       if (s != VC_OK) return s;
     }
     VC_HIP(hipMemcpyAsync(rre.data(), c.rre, (size_t)nrhs * sizeof(double), hipMemcpyDeviceToHost, st));

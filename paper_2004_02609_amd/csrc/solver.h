@@ -34,9 +34,10 @@ vc_status residual(vc_problem* P, const SolveSpec& sp, const double* b, const do
                    hipStream_t st, const int* skip = nullptr);
 vc_status col_norms(vc_problem* P, const double* w, int64_t N, int nrhs, double* d_out, std::vector<double>& h,
                     hipStream_t st);
-vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs, hipStream_t st);
+vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs, hipStream_t st,
+                      int part);
 vc_status cycle_graph(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs, hipStream_t st,
-                      hipGraph_t* g_out, hipGraphExec_t* e_out);
+                      int part, hipGraph_t* g_out, hipGraphExec_t* e_out);
 vc_status gmres(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs, std::vector<int>& iters,
                 std::vector<double>& rre, hipStream_t st);
 hipStream_t get_solve_stream(vc_problem* P);

@@ -362,14 +362,13 @@ hipError_t launch_cycle_start(int nrhs, int m, const double* rn, const double* b
 // previous rotations applied, new rotation from (H(j,j), H(j+1,j)), g rotated; a column
 // freezes when its residual estimate |g(j+1)| / |b| <= rtol / 2, on breakdown, or at
 // the end of the cycle.  scal = |w| for V_{j+1} = w / |w| (0 once frozen).
-__global__ void k_arnoldi(int j, int nrhs, int m, const double* __restrict__ h1, const double* __restrict__ h2,
-                          int ldh, const double* __restrict__ hn, double* __restrict__ H, double* __restrict__ cs,
-                          double* __restrict__ sn, double* __restrict__ g, const double* __restrict__ bn,
-                          const double* __restrict__ rtolp, int* __restrict__ act_step, int* __restrict__ kd, int* __restrict__ iters,
-                          double* __restrict__ scal, int* __restrict__ skip, int* __restrict__ bad) {
-  __shared__ int red[kCycleMax];
-  const int c = threadIdx.x;
-  const double rtol = *rtolp;
+__device__ __forceinline__ void arnoldi_step(int c, int j, int nrhs, int m, const double* __restrict__ h1,
+                                             const double* __restrict__ h2, int ldh, double hnc,
+                                             double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
+                                             double* __restrict__ g, const double* __restrict__ bn, double rtol,
+                                             int* __restrict__ act_step, int* __restrict__ kd, int* __restrict__ iters,
+                                             double* __restrict__ scal, int* __restrict__ skip, int* __restrict__ bad,
+                                             int* red) {
   int still = 0;
   if (c < nrhs) {
     if (act_step[c]) {
@@ -378,7 +377,6 @@ __global__ void k_arnoldi(int j, int nrhs, int m, const double* __restrict__ h1,
       double* snc = sn + (int64_t)c * m;
       double* gc = g + (int64_t)c * (m + 1);
       for (int i = 0; i <= j; ++i) Hc[i * m + j] = h1[(int64_t)c * ldh + i] + h2[(int64_t)c * ldh + i];
-      const double hnc = hn[c];
       Hc[(j + 1) * m + j] = hnc;
       for (int i = 0; i < j; ++i) {
         const double a = Hc[i * m + j], b = Hc[(i + 1) * m + j];
@@ -408,6 +406,17 @@ __global__ void k_arnoldi(int j, int nrhs, int m, const double* __restrict__ h1,
   }
   const int any = any_over_block(still, red);
   if (threadIdx.x == 0) skip[1] = any ? 0 : 1;
+}
+
+__global__ void k_arnoldi(int j, int nrhs, int m, const double* __restrict__ h1, const double* __restrict__ h2,
+                          int ldh, const double* __restrict__ hn, double* __restrict__ H, double* __restrict__ cs,
+                          double* __restrict__ sn, double* __restrict__ g, const double* __restrict__ bn,
+                          const double* __restrict__ rtolp, int* __restrict__ act_step, int* __restrict__ kd, int* __restrict__ iters,
+                          double* __restrict__ scal, int* __restrict__ skip, int* __restrict__ bad) {
+  __shared__ int red[kCycleMax];
+  const int c = threadIdx.x;
+  arnoldi_step(c, j, nrhs, m, h1, h2, ldh, c < nrhs ? hn[c] : 0.0, H, cs, sn, g, bn, *rtolp, act_step, kd, iters,
+               scal, skip, bad, red);
 }
 
 hipError_t launch_arnoldi(int j, int nrhs, int m, const double* h1, const double* h2, int ldh, const double* hn,
@@ -570,5 +579,196 @@ hipError_t launch_grad_eps(const int32_t* bptr, const int32_t* ek, const int32_t
                      m, scale, dC);
   return hipGetLastError();
 }
+
+
+// ------------------------------------------------------------------ fused Gram-Schmidt step
+// One Arnoldi step's classical Gram-Schmidt (applied twice) and norm in three launches:
+//   A  h1 = V^T w                          (partials, the last block of each
+//                                           (vector block, column) adds the chunks)
+//   B  w -= V h1; h2 = V^T w               (the last block of each column adds the chunks)
+//   C  w -= V h2; |w|; Arnoldi/Givens step  (the last block of the launch does the step)
+// "Last block" = the block whose increment of a device counter completes the count;
+// it resets the counter for the next launch.  Partials are indexed by block and added
+// in a fixed order, so results stay bitwise reproducible.
+
+// true in every thread of the block that completes the count (after a device fence)
+__device__ __forceinline__ bool last_block(unsigned* cnt, unsigned total, int* flag) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) *flag = atomicAdd(cnt, 1u) == total - 1u ? 1 : 0;
+  __syncthreads();
+  const bool last = *flag != 0;
+  if (last) {
+    __threadfence();
+    if (threadIdx.x == 0) *cnt = 0u;
+  }
+  return last;
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+k_cgs_dot(const double* __restrict__ V, int64_t ldv, int64_t N, int k, const double* __restrict__ w, int nrhs,
+          double* __restrict__ h, int64_t ldh, double* __restrict__ partial, const int* __restrict__ active,
+          unsigned* __restrict__ cnt) {
+  __shared__ double red[kDotBlk][kRedThreads / 64];
+  __shared__ int flag;
+  const int chunk = blockIdx.x, kb = blockIdx.y, r = blockIdx.z, nchunk = gridDim.x;
+  if (active && !active[r]) return;   // every block of this column returns: its count stays 0
+  const int i0 = kb * kDotBlk;
+  const int nb = k - i0 < kDotBlk ? k - i0 : kDotBlk;
+  const int64_t n0 = (int64_t)chunk * kDotChunk;
+  const int64_t n1 = n0 + kDotChunk < N ? n0 + kDotChunk : N;
+  const double* wr = w + (int64_t)r * N;
+  const double* v0 = V + (int64_t)i0 * ldv + (int64_t)r * N;
+  double acc[kDotBlk];
+#pragma unroll
+  for (int q = 0; q < kDotBlk; ++q) acc[q] = 0.0;
+  for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
+    const double wn = wr[n];
+#pragma unroll
+    for (int q = 0; q < kDotBlk; ++q)
+      if (q < nb) acc[q] += v0[(int64_t)q * ldv + n] * wn;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kDotBlk; ++q) {
+    const double t = wave_sum(acc[q]);
+    if (lane == 0) red[q][wv] = t;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nb) {
+    double t = 0.0;
+    for (int u = 0; u < (int)(blockDim.x >> 6); ++u) t += red[threadIdx.x][u];
+    partial[((int64_t)chunk * nrhs + r) * k + i0 + threadIdx.x] = t;
+  }
+  if (last_block(cnt + (int64_t)kb * nrhs + r, (unsigned)nchunk, &flag) && (int)threadIdx.x < nb) {
+    double t = 0.0;
+    for (int c = 0; c < nchunk; ++c) t += partial[((int64_t)c * nrhs + r) * k + i0 + threadIdx.x];
+    h[(int64_t)r * ldh + i0 + threadIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+k_cgs_update_dot(const double* __restrict__ V, int64_t ldv, int64_t N, int k, const double* __restrict__ h1,
+                 int64_t ldh, double* __restrict__ w, int nrhs, double* __restrict__ h2, double* __restrict__ partial,
+                 const int* __restrict__ active, unsigned* __restrict__ cnt) {
+  __shared__ double red[kDotBlk][kRedThreads / 64];
+  __shared__ int flag;
+  const int chunk = blockIdx.x, r = blockIdx.y, nchunk = gridDim.x;
+  if (active && !active[r]) return;
+  const int64_t n0 = (int64_t)chunk * kDotChunk;
+  const int64_t n1 = n0 + kDotChunk < N ? n0 + kDotChunk : N;
+  double* wr = w + (int64_t)r * N;
+  const double* vr = V + (int64_t)r * N;
+  const double* hr = h1 + (int64_t)r * ldh;
+  // w -= V h1 on this chunk (each thread keeps to its own rows in both phases)
+  for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
+    double acc = 0.0;
+    for (int i = 0; i < k; ++i) acc += vr[(int64_t)i * ldv + n] * hr[i];
+    wr[n] -= acc;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i0 = 0; i0 < k; i0 += kDotBlk) {
+    const int nb = k - i0 < kDotBlk ? k - i0 : kDotBlk;
+    double acc[kDotBlk];
+#pragma unroll
+    for (int q = 0; q < kDotBlk; ++q) acc[q] = 0.0;
+    for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
+      const double wn = wr[n];
+#pragma unroll
+      for (int q = 0; q < kDotBlk; ++q)
+        if (q < nb) acc[q] += vr[(int64_t)(i0 + q) * ldv + n] * wn;
+    }
+#pragma unroll
+    for (int q = 0; q < kDotBlk; ++q) {
+      const double t = wave_sum(acc[q]);
+      if (lane == 0) red[q][wv] = t;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nb) {
+      double t = 0.0;
+      for (int u = 0; u < (int)(blockDim.x >> 6); ++u) t += red[threadIdx.x][u];
+      partial[((int64_t)chunk * nrhs + r) * k + i0 + threadIdx.x] = t;
+    }
+    __syncthreads();
+  }
+  if (last_block(cnt + r, (unsigned)nchunk, &flag))
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+      double t = 0.0;
+      for (int c = 0; c < nchunk; ++c) t += partial[((int64_t)c * nrhs + r) * k + i];
+      h2[(int64_t)r * ldh + i] = t;
+    }
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+k_cgs_update_norm_step(const double* __restrict__ V, int64_t ldv, int64_t N, int k, const double* __restrict__ h1,
+                       const double* __restrict__ h2, int64_t ldh, double* __restrict__ w, int nrhs,
+                       double* __restrict__ partial, unsigned* __restrict__ cnt, int j, int m, double* __restrict__ H,
+                       double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
+                       const double* __restrict__ bn, const double* __restrict__ rtolp, int* __restrict__ act_step,
+                       int* __restrict__ kd, int* __restrict__ iters, double* __restrict__ scal,
+                       int* __restrict__ skip, int* __restrict__ bad, double* __restrict__ nrm_out) {
+  __shared__ double red[kRedThreads / 64];
+  __shared__ int ired[kRedThreads];
+  __shared__ int flag;
+  const int chunk = blockIdx.x, r = blockIdx.y, nchunk = gridDim.x;
+  if (act_step[r]) {
+    const int64_t n0 = (int64_t)chunk * kDotChunk;
+    const int64_t n1 = n0 + kDotChunk < N ? n0 + kDotChunk : N;
+    double* wr = w + (int64_t)r * N;
+    const double* vr = V + (int64_t)r * N;
+    const double* hr = h2 + (int64_t)r * ldh;
+    double sq = 0.0;
+    for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
+      double acc = 0.0;
+      for (int i = 0; i < k; ++i) acc += vr[(int64_t)i * ldv + n] * hr[i];
+      const double wn = wr[n] - acc;
+      wr[n] = wn;
+      sq += wn * wn;
+    }
+    const double t = wave_sum(sq);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double u = 0.0;
+      for (int q = 0; q < (int)(blockDim.x >> 6); ++q) u += red[q];
+      partial[(int64_t)chunk * nrhs + r] = u;
+    }
+  }
+  // every block counts (the step below also handles the inactive columns)
+  if (!last_block(cnt, (unsigned)(nchunk * nrhs), &flag)) return;
+  const int c = threadIdx.x;
+  double hnc = 0.0;
+  if (c < nrhs && act_step[c]) {
+    double s2 = 0.0;
+    for (int q = 0; q < nchunk; ++q) s2 += partial[(int64_t)q * nrhs + c];
+    hnc = sqrt(s2);
+    nrm_out[c] = hnc;
+  }
+  arnoldi_step(c, j, nrhs, m, h1, h2, (int)ldh, hnc, H, cs, sn, g, bn, *rtolp, act_step, kd, iters, scal, skip, bad,
+               ired);
+}
+
+hipError_t launch_cgs_step(const double* V, int64_t ldv, int64_t N, int k, double* w, int nrhs, double* h1,
+                           double* h2, int ldh, double* partial, unsigned* cnt, int j, int m, double* H, double* cs,
+                           double* sn, double* g, const double* bn, const double* rtol, int* act_step, int* kd,
+                           int* iters, double* scal, int* skip, int* bad, double* nrm_out, hipStream_t st) {
+  if (nrhs > kRedThreads || k <= 0) return hipErrorInvalidValue;
+  const int nchunk = (int)((N + kDotChunk - 1) / kDotChunk);
+  const int nkb = (k + kDotBlk - 1) / kDotBlk;
+  unsigned* cA = cnt;                                  // [nkb][nrhs]
+  unsigned* cB = cnt + cgs_counter_size_a(k, nrhs);    // [nrhs]
+  unsigned* cC = cB + nrhs;                            // [1]
+  hipLaunchKernelGGL(k_cgs_dot, dim3(nchunk, nkb, nrhs), dim3(kRedThreads), 0, st, V, ldv, N, k, w, nrhs, h1,
+                     (int64_t)ldh, partial, act_step, cA);
+  hipLaunchKernelGGL(k_cgs_update_dot, dim3(nchunk, nrhs), dim3(kRedThreads), 0, st, V, ldv, N, k, h1, (int64_t)ldh,
+                     w, nrhs, h2, partial, act_step, cB);
+  hipLaunchKernelGGL(k_cgs_update_norm_step, dim3(nchunk, nrhs), dim3(kRedThreads), 0, st, V, ldv, N, k, h1, h2,
+                     (int64_t)ldh, w, nrhs, partial, cC, j, m, H, cs, sn, g, bn, rtol, act_step, kd, iters, scal,
+                     skip, bad, nrm_out);
+  return hipGetLastError();
+}
+
+int64_t cgs_counter_size_a(int kmax, int nrhs) { return (int64_t)((kmax + kDotBlk - 1) / kDotBlk) * nrhs; }
+int64_t cgs_counter_size(int kmax, int nrhs) { return cgs_counter_size_a(kmax, nrhs) + nrhs + 1; }
 
 }  // namespace vc
