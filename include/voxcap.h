@@ -103,9 +103,11 @@ typedef struct {
 
 /* Solve options.  GMRES(restart) with the block-diagonal-diagonal preconditioner
  * (Sec. II.D) applied on the right; stops when ||b - A x|| <= rtol ||b|| per column.
- * VC_MIXED runs FP32 inner GMRES (inner_rtol) inside FP64 refinement (ir_max outer
- * steps).  0 picks defaults (rtol 1e-12, restart 35, max_iter 2000, inner_rtol 1e-5,
- * ir_max 20). */
+ * VC_MIXED runs FP32 inner GMRES inside FP64 refinement (ir_max outer steps): each
+ * inner solve stops at max(inner_rtol, rtol / (2 x the largest outer relative residual
+ * still above rtol)), i.e. when the step has done what the outer tolerance needs or
+ * FP32 products can do (inner_rtol), and after at most 4 restart cycles.  0 picks
+ * defaults (rtol 1e-12, restart 35, max_iter 2000, inner_rtol 1e-6, ir_max 20). */
 typedef struct {
   vc_precision prec;
   double rtol;

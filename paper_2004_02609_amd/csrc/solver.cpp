@@ -308,10 +308,14 @@ vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const doub
     VC_HIP(hipMemcpyAsync(rrp, b, (size_t)nrhs * N * sizeof(double), hipMemcpyDeviceToDevice, st));
     s = VC_ERR_NOT_CONVERGED;
     rre.assign(nrhs, 1.0);
+    double worst = 1.0;   // largest relative residual of a column still above rtol
     for (ir_steps = 0; ir_steps < o.ir_max; ++ir_steps) {
       SolveSpec s32 = sp;
       s32.mvp = VC_FP32;
-      s32.rtol = o.inner_rtol;
+      // reduce the residual no further than this step needs (half of rtol / worst),
+      // and no further than FP32 products can (inner_rtol)
+      s32.rtol = std::max(o.inner_rtol, 0.5 * o.rtol / worst);
+      s32.max_iter = std::min(o.max_iter, 4 * o.restart);
       VC_HIP(hipMemsetAsync(ddp, 0, (size_t)nrhs * N * sizeof(double), st));
       vc_status si = gmres(P, s32, rrp, ddp, nrhs, it, rre, st);
       if (si != VC_OK && si != VC_ERR_NOT_CONVERGED) return si;
@@ -323,10 +327,12 @@ vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const doub
       sr = col_norms(P, rrp, N, nrhs, P->s_norm.as<double>(), rn, st);
       if (sr != VC_OK) return sr;
       bool ok = true;
+      worst = 0.0;
       for (int c = 0; c < nrhs; ++c) {
         rre[c] = bn[c] > 0 ? rn[c] / bn[c] : 0.0;
         keep[c] = rre[c] > o.rtol ? 1.0 : 0.0;
         if (rre[c] > o.rtol) ok = false;
+        worst = std::max(worst, rre[c]);
       }
       if (ok) { s = VC_OK; ++ir_steps; break; }
       // columns already within rtol get a zero residual: the next inner solve leaves them
@@ -355,7 +361,7 @@ vc_solve_opts fill_defaults(const vc_solve_opts* in) {
   if (o.rtol <= 0) o.rtol = 1e-12;
   if (o.restart <= 0) o.restart = 35;
   if (o.max_iter <= 0) o.max_iter = 2000;
-  if (o.inner_rtol <= 0) o.inner_rtol = 1e-5;
+  if (o.inner_rtol <= 0) o.inner_rtol = 1e-6;
   if (o.ir_max <= 0) o.ir_max = 20;
   if (!in) o.use_precond = 1;
   return o;
