@@ -129,6 +129,7 @@ vc_status vc_setup(vc_problem* p, const vc_setup_opts* opts, void* stream) {
   p->max_rhs = o.max_rhs > 0 ? o.max_rhs : p->m;
   p->autotune = o.autotune != 0;
   p->sand_choice.clear();
+  p->y_choice.clear();
   const bool diel = p->n_diel > 0;
   p->ncomp_F = diel ? 6 : 3;
   p->ncomp_O = diel ? 6 : 3;
@@ -479,6 +480,18 @@ vc_status vc_tuning_report(vc_problem* p, char* buf, int32_t len) {
     out += line;
     if (c.tuned) {
       std::snprintf(line, sizeof line, " best_ms=%.4f default_ms=%.4f", c.ms_best, c.ms_default);
+      out += line;
+    }
+    out += "\n";
+  }
+  for (const auto& kv : p->y_choice) {
+    const auto& c = kv.second;
+    std::snprintf(line, sizeof line, "y-pass %s %s%s nrhs=%d kernel=%s %s", (kv.first & 1) ? "fp64" : "fp32",
+                  (kv.first & 2) ? "inverse" : "forward", (kv.first & 4) ? " (transposed product)" : "",
+                  kv.first >> 3, c.impl ? "register-edge" : "lds-tiles", c.tuned ? "tuned" : "default");
+    out += line;
+    if (c.tuned) {
+      std::snprintf(line, sizeof line, " lds_ms=%.4f register_ms=%.4f", c.ms[0], c.ms[1]);
       out += line;
     }
     out += "\n";

@@ -95,6 +95,41 @@ std::vector<SandCfg> sandwich_candidates(int L, int elem, int nin, int n1x, size
   return out;
 }
 
+bool ypass_config(int L, int elem, size_t budget, YArgs* a, int* nthr) {
+  int best_nst = 1 << 30, best_rs = 0;
+  AxisPlan best{};
+  for (int rs = 10; rs >= 2; --rs) {
+    const AxisPlan sp = make_sandwich_plan(L, 10, 10, rs, 512);
+    if (sp.nst < 1 || sp.rad[sp.nst - 1] != rs) continue;
+    if (sp.nst < best_nst || (sp.nst == best_nst && rs > best_rs)) {
+      best_nst = sp.nst;
+      best_rs = rs;
+      best = sp;
+    }
+  }
+  if (best_rs == 0) return false;
+  const int tl = L / best_rs;
+  int bc = 0, bt = 0;
+  double bscore = -1.0;
+  for (int c = 1; c <= 32; ++c) {
+    const int t = (c * tl + 63) / 64 * 64;
+    if (t > 512) break;
+    const size_t lds = (size_t)2 * elem * ((size_t)L + (size_t)L * (c + 1));
+    if (lds > budget) break;
+    const double score = (double)(c * tl) / t + (t <= 256 ? 1.0 : 0.0) + 0.001 * c;
+    if (score > bscore) { bscore = score; bc = c; bt = t; }
+  }
+  if (bc == 0) return false;
+  a->L = L;
+  a->nst = best.nst;
+  a->tl = tl;
+  a->radpack = 0;
+  for (int s2 = 0; s2 < best.nst; ++s2) a->radpack |= (uint32_t)best.rad[s2] << (5 * s2);
+  a->ncol = bc;
+  *nthr = bt;
+  return true;
+}
+
 // Default without timing: fewest stages, then the largest register radix, then the
 // widest power-of-two tile of at most 256 threads (several workgroups per CU), else
 // the narrowest.  (Tiles of other widths are left to the autotuner: they fill waves
@@ -116,6 +151,67 @@ bool sandwich_default(int L, int elem, int nin, int n1x, size_t budget, SandCfg*
   if (best < 0) return false;
   *cfg = cand[best];
   return true;
+}
+
+// One y pass (forward or inverse) over the components cset of `data`.  Two kernels can
+// do it: LDS Stockham tiles (k_strided) or register-edge stages (k_ypass, fewer LDS
+// round trips but at most L/RS threads per column, so long transforms get narrow
+// tiles).  The choice is made once per key: timed on `scratch` (a work array whose
+// contents are not needed at this point of the product) when autotuning, else the
+// register-edge kernel whenever its tile covers at least 32 bytes of a row.
+template <typename T>
+static vc_status y_pass(vc_problem* P, PrecTables& tb, void* data, void* scratch, int inverse, const CompSet& cset,
+                        int nin, int nout, int nrhs, int transpose, const int* skip, const int* act, hipStream_t st) {
+  const int n1x = P->n1[0], n1y = P->n1[1], My = P->M[1], H = P->H;
+  const int eb = (int)sizeof(T) * 2;
+  const uint8_t* lflag = P->d_lflag.as<uint8_t>();
+  const uint8_t* pflag = P->d_pflag.as<uint8_t>();
+  StridedArgs sa{};
+  sa.comp_stride = P->comp_stride; sa.rhs_stride = P->rhs_stride; sa.plane_stride = (int64_t)My * H;
+  sa.row_stride = H; sa.ncols = H; sa.nrhs = nrhs; sa.n1x = n1x; sa.n1y = n1y;
+  sa.skip = skip; sa.act = act; sa.nin = nin; sa.nout = nout; sa.inverse = inverse;
+  int ncol = 0, nthr = 0;
+  if (!pick_tile(My, eb, Tune<T>::emax, H, &ncol, &nthr, kLdsBudget, (int64_t)n1x * cset.n * nrhs)) return VC_ERR_ARG;
+  sa.ncol = ncol;
+  YArgs ya{};
+  ya.comp_stride = P->comp_stride; ya.rhs_stride = P->rhs_stride; ya.plane_stride = (int64_t)My * H;
+  ya.row_stride = H; ya.ncols = H; ya.nrhs = nrhs; ya.n1x = n1x; ya.n1y = n1y;
+  ya.skip = skip; ya.act = act; ya.cs = cset; ya.nin = nin; ya.nout = nout; ya.inverse = inverse;
+  int ythr = 0;
+  const bool yok = ypass_config(My, (int)sizeof(T), kLdsBudget, &ya, &ythr);
+  auto launch = [&](int impl, void* d) -> hipError_t {
+    if (impl == 1) return launch_ypass<T>(d, ya, tb.ax[1].tw.p, lflag, pflag, n1x, ythr, st);
+    return launch_strided<T>(d, sa, cset, n1x, tb.ax[1].plan, tb.ax[1].tw.p, lflag, pflag, nthr, st);
+  };
+  const int key = (nrhs << 3) | (transpose << 2) | (inverse << 1) | (sizeof(T) == 8 ? 1 : 0);
+  auto it = P->y_choice.find(key);
+  if (it == P->y_choice.end()) {
+    vc_problem::YChoice ch{(yok && ya.ncol * eb >= 32) ? 1 : 0, false, {0.0, 0.0}};
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    VC_HIP(hipStreamIsCapturing(st, &cap));
+    if (P->autotune && yok && cap == hipStreamCaptureStatusNone) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      VC_HIP(hipEventCreate(&e0));
+      VC_HIP(hipEventCreate(&e1));
+      for (int impl = 0; impl < 2; ++impl) {
+        VC_HIP(launch(impl, scratch));
+        VC_HIP(hipEventRecord(e0, st));
+        for (int rep = 0; rep < 3; ++rep) VC_HIP(launch(impl, scratch));
+        VC_HIP(hipEventRecord(e1, st));
+        VC_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        VC_HIP(hipEventElapsedTime(&ms, e0, e1));
+        ch.ms[impl] = ms / 3.0;
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      ch.impl = ch.ms[1] < ch.ms[0] ? 1 : 0;
+      ch.tuned = true;
+    }
+    it = P->y_choice.emplace(key, ch).first;
+  }
+  VC_HIP(launch(it->second.impl, data));
+  return VC_OK;
 }
 
 template <typename T>
@@ -181,14 +277,10 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
     cin.n = 6;
     for (int c = 0; c < 6; ++c) { cin.comp[c] = c; cin.axis[c] = c % 3; cin.min_[c] = c < 3 ? 1 : 2; cin.mout[c] = 0; }
   }
-  StridedArgs sa{};
-  sa.comp_stride = cs; sa.rhs_stride = rs; sa.plane_stride = (int64_t)My * H; sa.row_stride = H;
-  sa.ncols = H; sa.nrhs = nrhs; sa.n1x = n1x; sa.n1y = n1y;
-  sa.skip = skip;
-  sa.act = act;
-  if (!pick_tile(My, eb, Tune<T>::emax, H, &ncol, &nthr, budget, (int64_t)n1x * cin.n * nrhs)) return VC_ERR_ARG;
-  sa.ncol = ncol; sa.nin = n1y; sa.nout = My; sa.inverse = 0;
-  VC_HIP(launch_strided<T>(F, sa, cin, n1x, tb.ax[1].plan, tb.ax[1].tw.p, lflag, pflag, nthr, st));
+  {
+    const vc_status ys = y_pass<T>(P, tb, F, O, 0, cin, n1y, My, nrhs, transpose, skip, act, st);
+    if (ys != VC_OK) return ys;
+  }
   VC_MARK(2);
   // 3. x sandwich
   SandArgs xa{};
@@ -266,9 +358,10 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
                             st));
   VC_MARK(3);
   // 4. inverse y transform of the outputs (only rows with panels that need them)
-  if (!pick_tile(My, eb, Tune<T>::emax, H, &ncol, &nthr, budget, (int64_t)n1x * cout.n * nrhs)) return VC_ERR_ARG;
-  sa.ncol = ncol; sa.nin = My; sa.nout = n1y; sa.inverse = 1;
-  VC_HIP(launch_strided<T>(O, sa, cout, n1x, tb.ax[1].plan, tb.ax[1].tw.p, lflag, pflag, nthr, st));
+  {
+    const vc_status ys = y_pass<T>(P, tb, O, F, 1, cout, My, n1y, nrhs, transpose, skip, act, st);
+    if (ys != VC_OK) return ys;
+  }
   VC_MARK(4);
   // 5. inverse z transform + gather + jump term
   if (!pick_tile(P->M[2], eb, Tune<T>::emax, nitems, &ncol, &nthr, budget, transpose ? (nrhs + 1) / 2 : nrhs)) return VC_ERR_ARG;

@@ -44,6 +44,27 @@ struct StridedArgs {
   const int* act;    // optional per right-hand side activity: workgroups of inactive ones return
 };
 
+// y pass with register-edge stages (ypass_impl.hpp): blockIdx = (kz tile, x plane,
+// component * nrhs + rhs)
+struct YArgs {
+  int64_t comp_stride, rhs_stride, plane_stride, row_stride;
+  int ncols;        // kz columns (H)
+  int ncol;         // columns per workgroup, 1..32
+  int nin, nout;    // rows loaded (rest zero) / rows stored, each also filtered by line flags
+  int nrhs, inverse, n1x, n1y;
+  int L, nst, tl;   // y length, stages (radices f0 >= ... >= RS in radpack), L / RS
+  uint32_t radpack;
+  CompSet cs;
+  const int* skip;  // optional device flag: when set, the launch does nothing
+  const int* act;   // optional per right-hand side activity
+};
+template <typename T>
+hipError_t launch_ypass(void* data, const YArgs& a, const void* tw, const uint8_t* lflag, const uint8_t* pflag,
+                        int nplanes, int nthr, hipStream_t st);
+// plan and tile of the y pass for length L (fewest stages, largest last radix, then the
+// tile with the most lanes busy within 256 threads); false when none fits
+bool ypass_config(int L, int elem, size_t budget, YArgs* a, int* nthr);
+
 struct SandArgs {
   int64_t comp_stride, rhs_stride, pair_stride;
   int nrhs, n1x, Mx, My, H, Hx, Hy;

@@ -190,6 +190,14 @@ struct vc_problem {
     bool from_file = false;   // read from a tuning cache (vc_tuning_load)
   };
   std::map<int, SandChoice> sand_choice;
+  // y-pass kernel per (precision, direction, transposed product, nrhs) key:
+  // 0 = LDS Stockham tiles (k_strided), 1 = register-edge stages (k_ypass)
+  struct YChoice {
+    int impl;
+    bool tuned;
+    double ms[2];
+  };
+  std::map<int, YChoice> y_choice;
   // per-pass timing (measurement)
   bool prof = false;
   std::vector<hipEvent_t> ev_free;

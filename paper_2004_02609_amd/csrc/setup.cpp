@@ -377,7 +377,12 @@ vc_status build_precond(vc_problem* P, hipStream_t st) {
       uniq.emplace(std::move(pat), blk);
       pc.h_block_n.push_back(nb);
       pc.h_block_off.push_back((int64_t)pc.h_blocks.size());
-      pc.h_blocks.insert(pc.h_blocks.end(), A.begin(), A.end());
+      // stored transposed (column i of the inverse contiguous): the apply kernel's lanes
+      // then read consecutive addresses
+      const size_t o = pc.h_blocks.size();
+      pc.h_blocks.resize(o + (size_t)nb * nb);
+      for (int r = 0; r < nb; ++r)
+        for (int c = 0; c < nb; ++c) pc.h_blocks[o + (size_t)c * nb + r] = A[(size_t)r * nb + c];
     } else {
       blk = it->second;
     }

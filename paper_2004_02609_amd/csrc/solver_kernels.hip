@@ -222,7 +222,8 @@ hipError_t launch_diag_scale(const double* x, double* y, const double* dinv, int
 }
 
 // Conductor rows of eq. (14): for each box, y_box = Binv x_box with the box's (shared,
-// de-duplicated) inverse block.  One workgroup per box; x_box staged in LDS.
+// de-duplicated) inverse block, stored transposed.  One workgroup per box; x_box staged
+// in LDS.
 constexpr int kBoxThreads = 256;
 constexpr int kBoxLds = 4096;   // doubles of x_box staged per pass
 __global__ void __launch_bounds__(kBoxThreads)
@@ -255,10 +256,11 @@ k_block_apply(const double* __restrict__ x, double* __restrict__ y, int64_t N, i
     __syncthreads();
     for (int e = threadIdx.x; e < rn * nb; e += blockDim.x) {
       const int r = e / nb, i = e - r * nb;
-      const double* Bi = B + (int64_t)i * nb;
       const double* xr = xs + r * nb;
       double acc = 0.0;
-      for (int j = 0; j < nb; ++j) acc += Bi[j] * xr[j];
+      // the block is stored transposed: B^T[j][i] = Binv[i][j], lanes (consecutive i)
+      // read consecutive addresses
+      for (int j = 0; j < nb; ++j) acc += B[(int64_t)j * nb + i] * xr[j];
       y[(int64_t)(r0 + r) * N + box_panels[p0 + i]] = acc;
     }
   }

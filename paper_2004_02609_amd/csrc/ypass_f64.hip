@@ -1,0 +1,7 @@
+// Instantiation of the y pass (double); kernel in ypass_impl.hpp.
+#include "ypass_impl.hpp"
+
+namespace vc {
+template hipError_t launch_ypass<double>(void*, const YArgs&, const void*, const uint8_t*, const uint8_t*, int, int,
+                                      hipStream_t);
+}  // namespace vc

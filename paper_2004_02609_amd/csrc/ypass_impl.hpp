@@ -1,0 +1,215 @@
+// y pass of the FFT product of eq. (11) (Sec. II.B): the C2C transform along y of
+// every stored x plane, forward (after the z pass) or inverse (before it), for one tile
+// of consecutive kz columns of one (component, right-hand side, x plane) per workgroup.
+//
+// Same register-edge Stockham structure as the x pass (sandwich_impl.hpp), without the
+// multiply: with radices f0 >= ... >= RS (RS compile-time), thread (i, c) owns
+// butterfly i < L/RS of column c, columns fastest across lanes;
+//   stage 0 (radix f0, p = 1):  HBM rows i + q L/f0 -> registers -> LDS
+//   middle stages:              LDS -> LDS in place
+//   last stage (radix RS):      LDS -> registers -> HBM rows i + m L/RS
+// so each column crosses LDS once plus once per middle stage, and the HBM reads and
+// writes of a row touch the tile's consecutive columns.  The inverse transform is the
+// same pipeline with conjugate twiddles.  Rows are pruned by per-line flags: only
+// stored input rows are read and only needed output rows are written.
+#pragma once
+#include "sandwich_impl.hpp"
+
+namespace vc {
+
+// first stage (p = 1) on staged inputs: DFT of sign sg, outputs y[i R + q] to LDS
+template <typename T, int R>
+__device__ __forceinline__ void yp_first(const C2<T>* __restrict__ pre, bool act, T sg, char* __restrict__ lds,
+                                         uint32_t wbase, uint32_t ncolpE) {
+  if (!act) return;
+  C2<T> v[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) v[q] = pre[q];
+  Dft<T, R>::run(v, sg);
+  uint32_t o = wbase;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    lds_st<T>(lds, o, v[Dft<T, R>::pos(q)]);
+    o += ncolpE;
+  }
+}
+
+#define VC_YP_SWITCH(RADIX, CALL, HI)                                                                     \
+  switch (RADIX) {                                                                                        \
+    VC_YP_CASE(2, CALL, HI) VC_YP_CASE(3, CALL, HI) VC_YP_CASE(4, CALL, HI) VC_YP_CASE(5, CALL, HI)       \
+    VC_YP_CASE(6, CALL, HI) VC_YP_CASE(7, CALL, HI) VC_YP_CASE(8, CALL, HI) VC_YP_CASE(9, CALL, HI)       \
+    VC_YP_CASE(10, CALL, HI)                                                                              \
+    default: break;                                                                                       \
+  }
+#define VC_YP_CASE(RR, CALL, HI)                     \
+  case RR:                                           \
+    if constexpr (RR >= RS && RR <= HI) { CALL(RR) } \
+    break;
+
+template <typename T, int RS>
+__global__ void __launch_bounds__(512)
+k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const uint8_t* __restrict__ lflag,
+        const uint8_t* __restrict__ pflag) {
+  if (a.skip && *a.skip) return;
+  constexpr int RMAX = 10;
+  constexpr uint32_t E = sizeof(C2<T>);
+  const int plane = blockIdx.y;
+  const int cz = blockIdx.z / a.nrhs, rhs = blockIdx.z - cz * a.nrhs;
+  if (a.act && !a.act[rhs]) return;   // uniform per workgroup
+  const int comp = a.cs.comp[cz], axis = a.cs.axis[cz];
+  const int min_ = a.cs.min_[cz], mout = a.cs.mout[cz];
+  const int need = a.inverse ? mout : min_;
+  if (pflag && need && !(pflag[axis * a.n1x + plane] & need)) return;   // uniform per workgroup
+  extern __shared__ char smem_raw[];
+  const int L = a.L, tl = a.tl, S = a.nst, ncol = a.ncol;
+  const T sg = a.inverse ? T(1) : T(-1);
+  const uint32_t ncolpE = (uint32_t)(ncol + 1) * E;
+  char* twb = smem_raw;                       // L twiddles
+  char* lds = smem_raw + (size_t)L * E;       // [L][ncol + 1] tile
+  const int tid = threadIdx.x;
+  const int i = fdiv(tid, 1.0f / (float)ncol), c = tid - i * ncol;   // column fastest
+  const bool valid = i < tl;
+  const int col = blockIdx.x * ncol + c;
+  const bool colok = col < a.ncols;
+  const int colc = colok ? col : a.ncols - 1;
+  C2<T>* base = data + comp * a.comp_stride + rhs * a.rhs_stride + plane * a.plane_stride;
+  const uint8_t* lf = lflag ? lflag + ((int64_t)axis * a.n1x + plane) * a.n1y : nullptr;
+  const uint32_t rowb = (uint32_t)a.row_stride * E;
+  const int r0 = (int)(a.radpack & 31u);
+  const int LR0 = L / r0;
+  const bool act0 = i < LR0;
+  for (int t = tid; t < L; t += blockDim.x) reinterpret_cast<C2<T>*>(twb)[t] = twg[t];
+  // input rows i + q L/f0 that are stored (bit q), output rows i + m tl that are needed
+  uint32_t inmask = 0u, outmask = 0u;
+  if (colok) {
+    if (act0)
+      for (int q = 0; q < r0; ++q) {
+        const int r = i + q * LR0;
+        if (r < a.nin && (!lf || !min_ || (lf[r] & min_))) inmask |= 1u << q;
+      }
+    if (valid)
+      for (int m = 0; m < RS; ++m) {
+        const int r = i + m * tl;
+        if (r < a.nout && (!lf || !mout || (lf[r] & mout))) outmask |= 1u << m;
+      }
+  }
+  const uint32_t cE = (uint32_t)c * E;
+  const uint32_t rbase = (uint32_t)i * ncolpE + cE;
+  const uint32_t gbase = (uint32_t)colc * E + (uint32_t)i * rowb;
+  if (S == 1) {
+    // one stage of radix RS = L (tl = 1): rows m straight in and out
+    __syncthreads();
+    if (valid) {
+      C2<T> v[RS];
+      uint32_t o = gbase;
+#pragma unroll
+      for (int m = 0; m < RS; ++m) {
+        v[m] = C2<T>{T(0), T(0)};
+        if (inmask & (1u << m)) v[m] = ldo(base, o);
+        o += rowb;
+      }
+      Dft<T, RS>::run(v, sg);
+      o = gbase;
+#pragma unroll
+      for (int m = 0; m < RS; ++m) {
+        if (outmask & (1u << m)) sto(base, o, v[Dft<T, RS>::pos(m)]);
+        o += rowb;
+      }
+    }
+    return;
+  }
+  C2<T> pre[RMAX];
+  {
+    const uint32_t gstride = (uint32_t)LR0 * rowb;
+#define VC_CALL(RR) sw_load<T, RR>(pre, base, gbase, gstride, inmask, act0);
+    VC_YP_SWITCH(r0, VC_CALL, RMAX)
+#undef VC_CALL
+  }
+  __syncthreads();   // twiddles in LDS
+  {
+    uint32_t wbase = (uint32_t)i * (uint32_t)r0 * ncolpE + cE;
+    asm volatile("" : "+v"(wbase));
+#define VC_CALL(RR) yp_first<T, RR>(pre, act0, sg, lds, wbase, ncolpE);
+    VC_YP_SWITCH(r0, VC_CALL, RMAX)
+#undef VC_CALL
+  }
+  __syncthreads();
+  int p = r0;
+  for (int s = 1; s < S - 1; ++s) {
+    const int rs = (int)((a.radpack >> (5 * s)) & 31u);
+    const float invp = stage_inv(p);
+#define VC_CALL(RR) sw_mid<T, RR>(lds, twb, L, p, invp, i, rbase, cE, ncolpE, sg);
+    VC_YP_SWITCH(rs, VC_CALL, RMAX)
+#undef VC_CALL
+    p *= rs;
+  }
+  if (valid) {
+    // last stage (radix RS, p = tl): rows i + m tl, twiddle exponent m i, outputs
+    // X[i + m tl] straight to HBM
+    C2<T> v[RS];
+    const uint32_t st = (uint32_t)tl * ncolpE;
+    uint32_t o = rbase;
+#pragma unroll
+    for (int m = 0; m < RS; ++m) {
+      v[m] = lds_ld<T>(lds, o);
+      o += st;
+    }
+    tw_mul<T, RS>(v, twb, (uint32_t)i * E, sg);
+    Dft<T, RS>::run(v, sg);
+    uint32_t og = gbase;
+    const uint32_t gs = (uint32_t)tl * rowb;
+#pragma unroll
+    for (int m = 0; m < RS; ++m) {
+      if (outmask & (1u << m)) sto(base, og, v[Dft<T, RS>::pos(m)]);
+      og += gs;
+    }
+  }
+}
+#undef VC_YP_CASE
+#undef VC_YP_SWITCH
+
+template <typename T>
+hipError_t launch_ypass(void* data, const YArgs& a, const void* tw, const uint8_t* lflag, const uint8_t* pflag,
+                        int nplanes, int nthr, hipStream_t st) {
+  if (a.nst < 1 || a.nst > kSandMaxStages || a.ncol < 1 || a.ncol > 32 || nthr < 64 || nthr > 512 || (nthr & 63) ||
+      a.cs.n < 1 || a.cs.n > 6)
+    return hipErrorInvalidValue;
+  long prod = 1;
+  int prev = 1 << 30;
+  for (int s = 0; s < a.nst; ++s) {
+    const int r = (int)((a.radpack >> (5 * s)) & 31u);
+    if (r < 2 || r > 10 || r > prev) return hipErrorInvalidValue;
+    prev = r;
+    prod *= r;
+  }
+  const int rs = prev;
+  if (prod != a.L || (long)a.tl * rs != a.L || (long)a.tl * a.ncol > nthr) return hipErrorInvalidValue;
+  if (a.nin > a.L || a.nout > a.L) return hipErrorInvalidValue;
+  // rows whose flags are read lie inside the per-plane flag array of n1y rows
+  if (lflag)
+    for (int q = 0; q < a.cs.n; ++q)
+      if ((a.cs.min_[q] && a.nin > a.n1y) || (a.cs.mout[q] && a.nout > a.n1y)) return hipErrorInvalidValue;
+  // 32-bit byte offsets inside one (component, rhs, plane) slab
+  if ((uint64_t)a.plane_stride * sizeof(C2<T>) >= ((uint64_t)1 << 32)) return hipErrorInvalidValue;
+  const size_t lds = (size_t)sizeof(C2<T>) * ((size_t)a.L + (size_t)a.L * (a.ncol + 1));
+  if (lds > lds_ext_budget()) return hipErrorInvalidValue;
+  dim3 grid((a.ncols + a.ncol - 1) / a.ncol, nplanes, a.cs.n * a.nrhs);
+#define VC_RS(RR)                                                                                             \
+  case RR:                                                                                                    \
+    if (lds > kLdsBudget) {                                                                                   \
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ypass<T, RR>),                 \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);          \
+      if (e != hipSuccess) return e;                                                                          \
+    }                                                                                                         \
+    hipLaunchKernelGGL((k_ypass<T, RR>), grid, dim3(nthr), lds, st, (C2<T>*)data, a, (const C2<T>*)tw, lflag,   \
+                       pflag);                                                                                \
+    return hipGetLastError();
+  switch (rs) {
+    VC_RS(2) VC_RS(3) VC_RS(4) VC_RS(5) VC_RS(6) VC_RS(7) VC_RS(8) VC_RS(9) VC_RS(10)
+    default: break;
+  }
+#undef VC_RS
+  return hipErrorInvalidValue;
+}
+
+}  // namespace vc
