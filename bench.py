@@ -129,8 +129,10 @@ def write_traffic(args):
     if copy_bytes <= 0:
         raise SystemExit("--write-traffic needs the --calib-copy-mib of the profiled runs")
     tname = "float" if args.prec == "fp32" else "double"
-    kern = {"zfwd_scatter": "k_zfwd<" + tname, "y": "k_strided<" + tname, "x_sandwich_multiply": "k_xsandwich<" + tname,
-            "zinv_gather": "k_zinv<" + tname}
+    # the y pass runs on one of two kernels (the autotuner's choice): the timed steps'
+    # y launches are the last 2 x steps of either, alternating forward / inverse
+    kern = {"zfwd_scatter": ("k_zfwd<" + tname,), "y": ("k_strided<" + tname, "k_ypass<" + tname),
+            "x_sandwich_multiply": ("k_xsandwich<" + tname,), "zinv_gather": ("k_zinv<" + tname,)}
 
     def per_pass(rows):
         cp = [v for _, n, v in rows if "copy" in n.lower()]
@@ -139,7 +141,7 @@ def write_traffic(args):
         scale = copy_bytes / (max(cp) * 1024.0)
         out = {}
         for p, key in kern.items():
-            vals = [v for _, n, v in rows if key in n.replace(" ", "")]
+            vals = [v for _, n, v in rows if any(k in n.replace(" ", "") for k in key)]
             if p == "y":
                 last = vals[-2 * args.steps:]
                 out["y_forward"] = sum(last[0::2]) / args.steps * 1024.0 * scale
@@ -262,8 +264,9 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="heuristic x-pass configuration instead of the autotuner")
     ap.add_argument("--no-other", action="store_true", help="skip the product in the other precision")
-    ap.add_argument("--batch", type=int, default=0,
-                    help="also solve this many uneven random scenes (edges 16-64) together and one by one")
+    ap.add_argument("--batch", type=int, default=32,
+                    help="also solve this many uneven random scenes (edges 16-64) as one packed set and one by one "
+                         "(0: skip)")
     ap.add_argument("--tucker-tol", type=float, default=1e-8,
                     help="also run the product with Tucker-compressed spectra at this tolerance (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,

@@ -11,6 +11,8 @@
 // Transposed product (used by the adjoint solve): the conductor-row and dielectric-row
 // values of x are scattered into six grids, multiplied by the conjugated spectra of the
 // transposed blocks, transformed back into three grids and gathered on every panel.
+#include <algorithm>
+
 #include "mvp_kernels.h"
 #include "problem.h"
 
@@ -95,7 +97,7 @@ std::vector<SandCfg> sandwich_candidates(int L, int elem, int nin, int n1x, size
   return out;
 }
 
-bool ypass_config(int L, int elem, size_t budget, YArgs* a, int* nthr) {
+bool ypass_config(int L, int elem, int ncols, size_t budget, YArgs* a, int* nthr) {
   int best_nst = 1 << 30, best_rs = 0;
   AxisPlan best{};
   for (int rs = 10; rs >= 2; --rs) {
@@ -111,12 +113,17 @@ bool ypass_config(int L, int elem, size_t budget, YArgs* a, int* nthr) {
   const int tl = L / best_rs;
   int bc = 0, bt = 0;
   double bscore = -1.0;
+  // busy lanes, then rows read in whole 128-byte lines (the pass is bound by HBM
+  // traffic, and narrow tiles fetch lines they use only part of)
   for (int c = 1; c <= 32; ++c) {
     const int t = (c * tl + 63) / 64 * 64;
-    if (t > 512) break;
+    if (t > 1024) break;
     const size_t lds = (size_t)2 * elem * ((size_t)L + (size_t)L * (c + 1));
     if (lds > budget) break;
-    const double score = (double)(c * tl) / t + (t <= 256 ? 1.0 : 0.0) + 0.001 * c;
+    const double busy = (double)(c * tl) / t;
+    const double fill = (double)ncols / ((double)((ncols + c - 1) / c) * c);   // last tile's idle columns
+    const double line = std::min(1.0, (double)(c * 2 * elem) / 128.0);
+    const double score = busy * fill + 2.0 * line + 0.001 * c;
     if (score > bscore) { bscore = score; bc = c; bt = t; }
   }
   if (bc == 0) return false;
@@ -178,7 +185,7 @@ static vc_status y_pass(vc_problem* P, PrecTables& tb, void* data, void* scratch
   ya.row_stride = H; ya.ncols = H; ya.nrhs = nrhs; ya.n1x = n1x; ya.n1y = n1y;
   ya.skip = skip; ya.act = act; ya.cs = cset; ya.nin = nin; ya.nout = nout; ya.inverse = inverse;
   int ythr = 0;
-  const bool yok = ypass_config(My, (int)sizeof(T), kLdsBudget, &ya, &ythr);
+  const bool yok = ypass_config(My, (int)sizeof(T), H, kLdsBudget, &ya, &ythr);
   auto launch = [&](int impl, void* d) -> hipError_t {
     if (impl == 1) return launch_ypass<T>(d, ya, tb.ax[1].tw.p, lflag, pflag, n1x, ythr, st);
     return launch_strided<T>(d, sa, cset, n1x, tb.ax[1].plan, tb.ax[1].tw.p, lflag, pflag, nthr, st);

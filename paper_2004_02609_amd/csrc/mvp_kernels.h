@@ -61,9 +61,10 @@ struct YArgs {
 template <typename T>
 hipError_t launch_ypass(void* data, const YArgs& a, const void* tw, const uint8_t* lflag, const uint8_t* pflag,
                         int nplanes, int nthr, hipStream_t st);
-// plan and tile of the y pass for length L (fewest stages, largest last radix, then the
-// tile with the most lanes busy within 256 threads); false when none fits
-bool ypass_config(int L, int elem, size_t budget, YArgs* a, int* nthr);
+// plan and tile of the y pass for length L over ncols kz columns (fewest stages, largest
+// last radix, then the tile that keeps lanes and columns busy and reads whole 128-byte
+// row lines); false when none fits
+bool ypass_config(int L, int elem, int ncols, size_t budget, YArgs* a, int* nthr);
 
 struct SandArgs {
   int64_t comp_stride, rhs_stride, pair_stride;

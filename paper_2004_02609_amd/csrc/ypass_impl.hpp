@@ -47,7 +47,7 @@ __device__ __forceinline__ void yp_first(const C2<T>* __restrict__ pre, bool act
     break;
 
 template <typename T, int RS>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(1024)
 k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const uint8_t* __restrict__ lflag,
         const uint8_t* __restrict__ pflag) {
   if (a.skip && *a.skip) return;
@@ -171,7 +171,7 @@ k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const 
 template <typename T>
 hipError_t launch_ypass(void* data, const YArgs& a, const void* tw, const uint8_t* lflag, const uint8_t* pflag,
                         int nplanes, int nthr, hipStream_t st) {
-  if (a.nst < 1 || a.nst > kSandMaxStages || a.ncol < 1 || a.ncol > 32 || nthr < 64 || nthr > 512 || (nthr & 63) ||
+  if (a.nst < 1 || a.nst > kSandMaxStages || a.ncol < 1 || a.ncol > 32 || nthr < 64 || nthr > 1024 || (nthr & 63) ||
       a.cs.n < 1 || a.cs.n > 6)
     return hipErrorInvalidValue;
   long prod = 1;
