@@ -264,6 +264,19 @@ struct GemmArgs {
 };
 template <typename T>
 hipError_t launch_mfma_gemm(const T* A, const T* B, T* C, const GemmArgs& g, hipStream_t st);
+// one GEMM of a multi-GEMM launch: C[z] = A[z] B[z] (element strides as GemmArgs)
+struct GemmDesc {
+  const void* A;
+  const void* B;
+  void* C;
+  int M, N, K, batch;
+  int64_t sam, sak, sbk, sbn, scm, scn;
+  int64_t bsa, bsb, bsc;
+  int gx, gy, blk0;   // set by gemm_table_layout
+};
+int gemm_table_layout(GemmDesc* d, int n);
+template <typename T>
+hipError_t launch_mfma_gemm_multi(const GemmDesc* tab, int ndesc, int nblocks, const int* skip, hipStream_t st);
 hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t st);
 hipError_t launch_swap01(const double* in, double* out, int A, int B, int C, hipStream_t st);
 

@@ -123,7 +123,13 @@ struct vc_problem {
   // Tucker compression of the stored spectra (tucker_tol > 0): rebuilt before each product
   double tucker_tol = 0.0;
   std::vector<vc::TuckerPair> tk;
-  vc::DevMem tk_T1, tk_T2;          // rebuild scratch
+  vc::DevMem tk_T1, tk_T2;          // rebuild scratch (one region per stored pair)
+  std::vector<int64_t> tk_o1, tk_o2;  // element offsets of each pair's regions
+  struct TkTables {                 // device tables of the three batched rebuild GEMMs
+    const void* R = nullptr;
+    vc::DevMem tab[3];
+    int n[3] = {0, 0, 0}, nblk[3] = {0, 0, 0};
+  } tk_tab[2];                      // [0] FP32, [1] FP64
   double tk_ms = 0.0;
   int tk_count = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> tk_pending;

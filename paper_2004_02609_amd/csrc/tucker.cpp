@@ -8,9 +8,10 @@
 // (rocBLAS GEMM); what is left is the core.  The three budgets add up to
 // ||X - X_hat|| <= tol ||X||.
 //
-// Rebuild (every product, FP32 or FP64): three strided batched GEMMs on the matrix
-// cores (tucker_kernels.hip) write each stored pair back into the spectra buffer the
-// x pass reads.
+// Rebuild (every product, FP32 or FP64): three GEMM steps on the matrix cores
+// (tucker_kernels.hip) write each stored pair back into the spectra buffer the x pass
+// reads; each step is one launch covering every stored pair (a device table of the
+// pairs' GEMMs), so a rebuild is three launches whatever the number of pairs.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -150,21 +151,88 @@ vc_status tucker_compress_pair(vc_problem* P, const double* X, hipStream_t st) {
   return VC_OK;
 }
 
-// scratch of the rebuild (sized for FP64, reused by FP32)
+// scratch of the rebuild: each pair its own T1 (r1 r2 x D3) and T2 (r1 x D2 x D3)
+// regions, so the three GEMM steps of every pair can run as three launches; sized in
+// FP64 elements, reused by FP32
 vc_status tucker_end(vc_problem* P) {
-  int64_t t1 = 1, t2 = 1;
+  int64_t t1 = 0, t2 = 0;
+  P->tk_o1.clear();
+  P->tk_o2.clear();
   for (const TuckerPair& tp : P->tk) {
-    t1 = std::max(t1, (int64_t)tp.r[0] * tp.r[1] * P->H);
-    t2 = std::max(t2, (int64_t)tp.r[0] * P->Hy * P->H);
+    P->tk_o1.push_back(t1);
+    P->tk_o2.push_back(t2);
+    t1 += (int64_t)tp.r[0] * tp.r[1] * P->H;
+    t2 += (int64_t)tp.r[0] * P->Hy * P->H;
   }
-  VC_HIP(P->tk_T1.alloc((size_t)t1 * sizeof(double)));
-  VC_HIP(P->tk_T2.alloc((size_t)t2 * sizeof(double)));
+  VC_HIP(P->tk_T1.alloc((size_t)std::max<int64_t>(t1, 1) * sizeof(double)));
+  VC_HIP(P->tk_T2.alloc((size_t)std::max<int64_t>(t2, 1) * sizeof(double)));
+  for (auto& tt : P->tk_tab) tt.R = nullptr;   // rebuilt on next use
+  return VC_OK;
+}
+
+// the three GEMM tables of one precision (built on first use for a given spectra buffer)
+template <typename T>
+static vc_status rebuild_tables(vc_problem* P, T* R, int64_t pair_stride) {
+  vc_problem::TkTables& tt = P->tk_tab[sizeof(T) == 8 ? 1 : 0];
+  if (tt.R == R) return VC_OK;
+  const int D1 = P->Hx, D2 = P->Hy, D3 = P->H;
+  T* T1 = P->tk_T1.as<T>();
+  T* T2 = P->tk_T2.as<T>();
+  std::vector<GemmDesc> g1, g2, g3;
+  for (size_t q = 0; q < P->tk.size(); ++q) {
+    const TuckerPair& tp = P->tk[q];
+    const int r1 = tp.r[0], r2 = tp.r[1], r3 = tp.r[2];
+    const void* S = sizeof(T) == 8 ? tp.S64.p : tp.S32.p;
+    const void* U1 = sizeof(T) == 8 ? tp.U64[0].p : tp.U32[0].p;
+    const void* U2 = sizeof(T) == 8 ? tp.U64[1].p : tp.U32[1].p;
+    const void* U3 = sizeof(T) == 8 ? tp.U64[2].p : tp.U32[2].p;
+    T* t1 = T1 + P->tk_o1[q];
+    T* t2 = T2 + P->tk_o2[q];
+    GemmDesc d{};
+    // T1 (r1 r2 x D3) = S (r1 r2 x r3) U3^T
+    d.A = S; d.B = U3; d.C = t1;
+    d.M = r1 * r2; d.N = D3; d.K = r3; d.batch = 1;
+    d.sam = r3; d.sak = 1; d.sbk = 1; d.sbn = r3; d.scm = D3; d.scn = 1;
+    g1.push_back(d);
+    // T2[a] (D2 x D3) = U2 (D2 x r2) T1[a] (r2 x D3)
+    d = GemmDesc{};
+    d.A = U2; d.B = t1; d.C = t2;
+    d.M = D2; d.N = D3; d.K = r2; d.batch = r1;
+    d.sam = r2; d.sak = 1; d.sbk = D3; d.sbn = 1; d.scm = D3; d.scn = 1;
+    d.bsa = 0; d.bsb = (int64_t)r2 * D3; d.bsc = (int64_t)D2 * D3;
+    g2.push_back(d);
+    // X (D1 x D2 D3) = U1 (D1 x r1) T2 (r1 x D2 D3)
+    d = GemmDesc{};
+    d.A = U1; d.B = t2; d.C = R + (int64_t)q * pair_stride;
+    d.M = D1; d.N = D2 * D3; d.K = r1; d.batch = 1;
+    d.sam = r1; d.sak = 1; d.sbk = (int64_t)D2 * D3; d.sbn = 1; d.scm = (int64_t)D2 * D3; d.scn = 1;
+    g3.push_back(d);
+  }
+  std::vector<GemmDesc>* all[3] = {&g1, &g2, &g3};
+  for (int i = 0; i < 3; ++i) {
+    std::vector<GemmDesc>& v = *all[i];
+    const int nb = gemm_table_layout(v.data(), (int)v.size());
+    if (nb < 0) { tt.R = nullptr; return VC_ERR_ARG; }
+    VC_HIP(tt.tab[i].alloc(std::max<size_t>(v.size(), 1) * sizeof(GemmDesc)));
+    if (!v.empty()) VC_HIP(hipMemcpy(tt.tab[i].p, v.data(), v.size() * sizeof(GemmDesc), hipMemcpyHostToDevice));
+    tt.n[i] = (int)v.size();
+    tt.nblk[i] = nb;
+  }
+  tt.R = R;
   return VC_OK;
 }
 
 template <typename T>
 vc_status tucker_rebuild(vc_problem* P, T* R, int64_t pair_stride, hipStream_t st, const int* skip) {
   const int D1 = P->Hx, D2 = P->Hy, D3 = P->H;
+  // three launches for all pairs when every rank fits the register strip
+  if (rebuild_tables<T>(P, R, pair_stride) == VC_OK) {
+    const vc_problem::TkTables& tt = P->tk_tab[sizeof(T) == 8 ? 1 : 0];
+    for (int i = 0; i < 3; ++i)
+      VC_HIP(launch_mfma_gemm_multi<T>(tt.tab[i].as<GemmDesc>(), tt.n[i], tt.nblk[i], skip, st));
+    return VC_OK;
+  }
+  // ranks above the strip: one pair after another with the general kernel
   T* T1 = P->tk_T1.as<T>();
   T* T2 = P->tk_T2.as<T>();
   for (size_t q = 0; q < P->tk.size(); ++q) {
@@ -174,25 +242,24 @@ vc_status tucker_rebuild(vc_problem* P, T* R, int64_t pair_stride, hipStream_t s
     const T* U1 = sizeof(T) == 8 ? (const T*)tp.U64[0].p : (const T*)tp.U32[0].p;
     const T* U2 = sizeof(T) == 8 ? (const T*)tp.U64[1].p : (const T*)tp.U32[1].p;
     const T* U3 = sizeof(T) == 8 ? (const T*)tp.U64[2].p : (const T*)tp.U32[2].p;
+    T* t1 = T1 + P->tk_o1[q];
+    T* t2 = T2 + P->tk_o2[q];
     GemmArgs g{};
-    // T1 (r1 r2 x D3) = S (r1 r2 x r3) U3^T
     g.M = r1 * r2; g.N = D3; g.K = r3; g.batch = 1;
     g.sam = r3; g.sak = 1; g.sbk = 1; g.sbn = r3; g.scm = D3; g.scn = 1;
     g.skip = skip;
-    VC_HIP(launch_mfma_gemm<T>(S, U3, T1, g, st));
-    // T2[a] (D2 x D3) = U2 (D2 x r2) T1[a] (r2 x D3)
+    VC_HIP(launch_mfma_gemm<T>(S, U3, t1, g, st));
     g = GemmArgs{};
     g.M = D2; g.N = D3; g.K = r2; g.batch = r1;
     g.sam = r2; g.sak = 1; g.sbk = D3; g.sbn = 1; g.scm = D3; g.scn = 1;
     g.bsa = 0; g.bsb = (int64_t)r2 * D3; g.bsc = (int64_t)D2 * D3;
     g.skip = skip;
-    VC_HIP(launch_mfma_gemm<T>(U2, T1, T2, g, st));
-    // X (D1 x D2 D3) = U1 (D1 x r1) T2 (r1 x D2 D3)
+    VC_HIP(launch_mfma_gemm<T>(U2, t1, t2, g, st));
     g = GemmArgs{};
     g.M = D1; g.N = D2 * D3; g.K = r1; g.batch = 1;
     g.sam = r1; g.sak = 1; g.sbk = (int64_t)D2 * D3; g.sbn = 1; g.scm = (int64_t)D2 * D3; g.scn = 1;
     g.skip = skip;
-    VC_HIP(launch_mfma_gemm<T>(U1, T2, R + (int64_t)q * pair_stride, g, st));
+    VC_HIP(launch_mfma_gemm<T>(U1, t2, R + (int64_t)q * pair_stride, g, st));
   }
   return VC_OK;
 }

@@ -75,6 +75,83 @@ hipError_t launch_mfma_gemm(const T* A, const T* B, T* C, const GemmArgs& g, hip
 template hipError_t launch_mfma_gemm<float>(const float*, const float*, float*, const GemmArgs&, hipStream_t);
 template hipError_t launch_mfma_gemm<double>(const double*, const double*, double*, const GemmArgs&, hipStream_t);
 
+// Many GEMMs in one launch (every stored pair of a rebuild step): a device table holds
+// each GEMM's operands, sizes, strides, batch and first workgroup; a workgroup finds
+// its GEMM by binary search.  A wave keeps its 16-row strip of A in registers (K <= 64,
+// the Tucker ranks) and sweeps kGemmStrip output tiles along N, so one workgroup writes
+// 32 x 32 * kGemmStrip elements.
+constexpr int kGemmStrip = 8;
+constexpr int kGemmKFrag = 16;   // K <= 4 * kGemmKFrag held in registers
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_mfma_gemm_multi(const GemmDesc* __restrict__ tab, int ndesc,
+                                                         const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int lin = blockIdx.x;
+  const GemmDesc& g = tab[find_scene(tab, ndesc, lin)];
+  const int local = lin - g.blk0;
+  const int per = g.gx * g.gy;
+  const int z = local / per, rem = local - z * per;
+  const int by = rem / g.gx, bx = rem - by * g.gx;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int M = g.M, N = g.N, K = g.K;
+  const T* Az = static_cast<const T*>(g.A) + (int64_t)z * g.bsa;
+  const T* Bz = static_cast<const T*>(g.B) + (int64_t)z * g.bsb;
+  T* Cz = static_cast<T*>(g.C) + (int64_t)z * g.bsc;
+  const int m0 = by * 32 + (wave >> 1) * 16;
+  const int am = m0 + li;
+  T afrag[kGemmKFrag];
+#pragma unroll
+  for (int f = 0; f < kGemmKFrag; ++f) {
+    const int k = 4 * f + lk;
+    afrag[f] = (f * 4 < K && am < M && k < K) ? Az[(int64_t)am * g.sam + (int64_t)k * g.sak] : T(0);
+  }
+  for (int t = 0; t < kGemmStrip; ++t) {
+    const int n0 = (bx * kGemmStrip + t) * 32 + (wave & 1) * 16;
+    if (n0 >= N) break;
+    const int bn = n0 + li;
+    typename Mfma<T>::acc_t acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int f = 0; f < kGemmKFrag; ++f) {
+      if (f * 4 >= K) break;
+      const int k = 4 * f + lk;
+      const T b = (bn < N && k < K) ? Bz[(int64_t)k * g.sbk + (int64_t)bn * g.sbn] : T(0);
+      acc = Mfma<T>::run(afrag[f], b, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = sizeof(T) == 8 ? m0 + lk + 4 * r : m0 + 4 * lk + r;
+      if (row < M && bn < N) Cz[(int64_t)row * g.scm + (int64_t)bn * g.scn] = acc[r];
+    }
+  }
+}
+
+// lays out the table's workgroups (gx, gy, blk0) and returns the total, or -1 when a
+// GEMM does not fit the kernel (K above the register strip)
+int gemm_table_layout(GemmDesc* d, int n) {
+  int64_t blk = 0;
+  for (int i = 0; i < n; ++i) {
+    if (d[i].K < 1 || d[i].K > 4 * kGemmKFrag || d[i].M < 1 || d[i].N < 1 || d[i].batch < 1) return -1;
+    d[i].gx = (d[i].N + 32 * kGemmStrip - 1) / (32 * kGemmStrip);
+    d[i].gy = (d[i].M + 31) / 32;
+    d[i].blk0 = (int)blk;
+    blk += (int64_t)d[i].gx * d[i].gy * d[i].batch;
+    if (blk > (int64_t)1 << 30) return -1;
+  }
+  return (int)blk;
+}
+
+template <typename T>
+hipError_t launch_mfma_gemm_multi(const GemmDesc* tab, int ndesc, int nblocks, const int* skip, hipStream_t st) {
+  if (ndesc <= 0 || nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mfma_gemm_multi<T>, dim3(nblocks), dim3(256), 0, st, tab, ndesc, skip);
+  return hipGetLastError();
+}
+
+template hipError_t launch_mfma_gemm_multi<float>(const GemmDesc*, int, int, const int*, hipStream_t);
+template hipError_t launch_mfma_gemm_multi<double>(const GemmDesc*, int, int, const int*, hipStream_t);
+
 // FP64 -> FP32 copy of the compressed factors
 __global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
