@@ -188,15 +188,20 @@ def tucker_run(args, scene, x, stream, B, ms_product_full):
     Pt.tucker_info()                       # drop what was recorded before
     base = Pt.tucker_info()
     steps = max(5, args.steps // 4)
-    Pt.profile(True)
+    # product rate without timing events, then the rebuild's own time with events
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(steps):
         Pt.apply(x, y, prec=args.prec, stream=stream)
     e1.record(stream)
     torch.cuda.synchronize()
-    Pt.profile(False)
     ms = e0.elapsed_time(e1) / steps
+    Pt.profile(1)
+    for _ in range(steps):
+        Pt.apply(x, y, prec=args.prec, stream=stream)
+    torch.cuda.synchronize()
+    Pt.profile(0)
+    Pt.pass_times()
     info = Pt.tucker_info()
     n_rb = info["rebuilds"] - base["rebuilds"]
     rb_ms = (info["rebuild_ms"] - base["rebuild_ms"]) / max(1, n_rb)
@@ -309,12 +314,14 @@ def main():
     x = torch.randn(B, N, dtype=torch.float64, device=dev, generator=g)
     y = torch.empty_like(x)
 
-    def run(prec, steps, warm, profile):
+    def run(prec, steps, warm, level):
+        # level 2: HIP events around the x pass only (the timed run); level 1: around
+        # every pass (the breakdown run); each event adds a few us between launches
         for _ in range(warm):
             P.apply(x, y, prec=prec, stream=stream)
         torch.cuda.synchronize()
         P.pass_times()                       # drop anything recorded before
-        P.profile(profile)
+        P.profile(level)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -323,24 +330,26 @@ def main():
             P.apply(x, y, prec=prec, stream=stream)
         e1.record(stream)
         torch.cuda.synchronize()
-        P.profile(False)
+        P.profile(0)
         ms = e0.elapsed_time(e1)
         return ms, P.pass_times()
 
     print(f"# {args.config}: N={N} m={B} fft={P.fft_size()} setup {t_setup:.2f}s", file=sys.stderr, flush=True)
-    ms, (pms, pcnt, pbytes) = run(args.prec, args.steps, args.warmup, True)
+    ms, (pms, pcnt, pbytes) = run(args.prec, args.steps, args.warmup, 2)
     value = args.steps * B / (ms / 1e3)
+    # per-pass breakdown: a separate, shorter run with events around every pass
+    _, (bms, bcnt, bbytes) = run(args.prec, max(10, min(args.steps, 50)), 2, 1)
     other = "fp64" if args.prec == "fp32" else "fp32"
     value_o = None
     if not args.no_other:
-        ms_o, _ = run(other, max(10, args.steps // 2), 3, False)
+        ms_o, _ = run(other, max(10, args.steps // 2), 3, 0)
         value_o = max(10, args.steps // 2) * B / (ms_o / 1e3)
         print(f"# {args.prec} product {ms / args.steps * 1e3:.1f} us/step, {other} "
               f"{ms_o / max(10, args.steps // 2) * 1e3:.1f} us/step", file=sys.stderr, flush=True)
 
-    dom = int(np.argmax(pms))
-    avg_ms = pms[dom] / max(1, pcnt[dom])
-    achieved = pbytes[dom] / (avg_ms / 1e3) / 1e9
+    dom = int(np.argmax(bms))
+    avg_ms = bms[dom] / max(1, bcnt[dom])
+    achieved = bbytes[dom] / (avg_ms / 1e3) / 1e9
     kname = voxcap.PASS_NAMES[dom]
     traffic = load_traffic(args.config, kname, args.prec)
     # the x pass does ~30 flops per algorithmic byte (nine transforms per column) and is
@@ -356,10 +365,10 @@ def main():
                 "traffic": x_traffic, "alg_flops": x_flops, "alg_bytes": pbytes[xi], "avg_us": x_ms * 1e3,
                 "hbm_achieved_GBs": pbytes[xi] / (x_ms / 1e3) / 1e9,
                 "hbm_frac": pbytes[xi] / (x_ms / 1e3) / 1e9 / HBM_PEAK_GBS}
-    passes = {voxcap.PASS_NAMES[i]: {"avg_us": pms[i] / max(1, pcnt[i]) * 1e3, "launches": pcnt[i],
-                                     "alg_bytes": pbytes[i],
-                                     "alg_GBs": pbytes[i] / (pms[i] / max(1, pcnt[i]) / 1e3) / 1e9
-                                     if pms[i] > 0 else None}
+    passes = {voxcap.PASS_NAMES[i]: {"avg_us": bms[i] / max(1, bcnt[i]) * 1e3, "launches": bcnt[i],
+                                     "alg_bytes": bbytes[i],
+                                     "alg_GBs": bbytes[i] / (bms[i] / max(1, bcnt[i]) / 1e3) / 1e9
+                                     if bms[i] > 0 else None}
               for i in range(5)}
 
     solve = None
@@ -405,8 +414,8 @@ def main():
         "roofline": roofline,
         "product_hbm": {"dominant_pass": kname, "achieved_GBs": achieved, "frac": achieved / HBM_PEAK_GBS,
                         "traffic": traffic,
-                        "all_passes_alg_bytes": float(sum(pbytes)),
-                        "all_passes_GBs": float(sum(pbytes)) / (ms / args.steps / 1e3) / 1e9},
+                        "all_passes_alg_bytes": float(sum(bbytes)),
+                        "all_passes_GBs": float(sum(bbytes)) / (ms / args.steps / 1e3) / 1e9},
         "cpu_baseline": cpu,
         "other_precision": {"prec": other, "value": value_o, "unit": "RHS-MVPs/s"} if value_o else None,
         "passes": passes,

@@ -114,7 +114,9 @@ typedef struct {
   int32_t restart, max_iter;
   double inner_rtol;
   int32_t ir_max;
-  int32_t use_precond;   /* 1 = block-diagonal-diagonal (default), 0 = none, 2 = diagonal only */
+  int32_t use_precond;   /* 1 = block-diagonal-diagonal (default), 0 = none, 2 = diagonal only,
+                            3 = conventional block-diagonal over all panels (built on first
+                            use; not for packed sets) */
   int32_t graph;         /* 0: each restart cycle runs on the device without host round trips
                             and, after the first, is replayed as one captured hipGraph
                             (default); 1: the same kernels issued one by one             */
@@ -154,6 +156,23 @@ vc_status vc_apply(vc_problem *p, int transpose, vc_precision prec, const double
  * (R^T when transpose = 1; the blocks are symmetric). */
 vc_status vc_apply_precond(vc_problem *p, int transpose, const double *x_dev, double *y_dev,
                            int32_t nrhs, void *hip_stream);
+
+/* y = R x (R^T x when transpose = 1) with one of the preconditioners compared in
+ * Sec. III.A.  kind: 1 = block-diagonal-diagonal of eq. (14); 2 = diagonal (the eq. (7)
+ * diagonal on dielectric rows, the eq. (5) self term on conductor rows); 3 = the
+ * conventional block-diagonal preconditioner: every panel (conductor and dielectric)
+ * joins one nv box and each box's block of the full eq. (4) matrix is inverted (LU, FP64,
+ * identical boxes sharing one inverse).  Kind 3 is built on first use (host work, then
+ * device upload; not allowed during stream capture).  x_dev, y_dev: nrhs x N row-major
+ * device arrays, distinct.  Errors: VC_ERR_STATE before setup, VC_ERR_ARG for a bad kind
+ * or a packed set, VC_ERR_NUMERIC for a singular block. */
+vc_status vc_apply_precond_kind(vc_problem *p, int32_t kind, int transpose, const double *x_dev,
+                                double *y_dev, int32_t nrhs, void *hip_stream);
+
+/* Storage of preconditioner kind 1 or 3 (kind 3 is built if needed): boxes, distinct
+ * inverse blocks, and bytes of the distinct inverses plus the per-panel index and
+ * diagonal arrays the apply reads.  Any output pointer may be null. */
+vc_status vc_precond_info(vc_problem *p, int32_t kind, int64_t *nbox, int64_t *nblock, int64_t *bytes);
 
 /* Capacitance matrix C (m x m, row-major, farads) by one solve per conductor, all m
  * right-hand sides advancing together.  rho_dev: optional N x m device output of the
@@ -203,10 +222,14 @@ vc_status vc_capacitance_grad_eps(vc_problem *p, const vc_solve_opts *opts,
                                   const int32_t *block_of_voxel, int32_t nblocks,
                                   double *dC, double *C_out, vc_stats *stats);
 
-/* Per-pass timing of the product (measurement only).  While enabled, vc_apply records
- * HIP events on its stream around each of its passes:
+/* Per-pass timing of the product (measurement only).  At level 1, vc_apply records HIP
+ * events on its stream around each of its passes (and the Tucker rebuild):
  *   0 scatter + z transform, 1 y transform, 2 x transform + block multiply + inverse x,
  *   3 inverse y transform, 4 inverse z transform + gather.
+ * At level 2 it brackets pass 2 only (two events per product instead of six: each
+ * event adds a few microseconds between the launches it separates); the other passes
+ * then report zero launches.  Level 0 records nothing.  No events are recorded while
+ * the stream is being captured.
  * vc_pass_times waits for the recorded events and returns, per pass, the summed
  * milliseconds, the number of launches, and the algorithmic bytes of ONE launch of the
  * most recent vc_apply (compulsory reads + writes of the pruned pass, counting the
@@ -230,6 +253,7 @@ vc_status vc_charges_to_capacitance_adjoint(vc_problem *p, const double *gC_dev,
 vc_status vc_tucker_info(vc_problem *p, int32_t *npairs, int32_t ranks[45], double *stored_numbers,
                          double *full_numbers, double *rebuild_ms, int32_t *rebuilds);
 
+/* enable: the profiling level 0, 1 or 2 above; VC_ERR_ARG otherwise. */
 vc_status vc_profile_enable(vc_problem *p, int enable);
 
 /* Text report of the x-pass launch configurations in use, one line per

@@ -165,6 +165,48 @@ vc_status vc_apply_precond(vc_problem* p, int transpose, const double* x, double
   return mark(p, apply_precond(p, transpose, x, y, nrhs, (hipStream_t)stream));
 }
 
+vc_status vc_apply_precond_kind(vc_problem* p, int32_t kind, int transpose, const double* x, double* y, int32_t nrhs,
+                                void* stream) {
+  VC_CHECK_PROBLEM(p);
+  if (!p->setup_done) { set_error("vc_apply_precond_kind before vc_setup"); return VC_ERR_STATE; }
+  if (!x || !y || x == y || nrhs <= 0) { set_error("bad arguments"); return VC_ERR_ARG; }
+  if (kind < 1 || kind > 3) { set_error("preconditioner kind must be 1, 2 or 3"); return VC_ERR_ARG; }
+  VC_HIP(hipSetDevice(p->device));
+  if (kind == 3) {
+    if (p->pack) { set_error("packed sets use the block-diagonal-diagonal or diagonal preconditioner"); return VC_ERR_ARG; }
+    const vc_status s = build_precond_full(p, (hipStream_t)stream);
+    if (s != VC_OK) return mark(p, s);
+  }
+  p->pc.mode = kind;
+  return mark(p, apply_precond(p, transpose, x, y, nrhs, (hipStream_t)stream));
+}
+
+vc_status vc_precond_info(vc_problem* p, int32_t kind, int64_t* nbox, int64_t* nblock, int64_t* bytes) {
+  VC_CHECK_PROBLEM(p);
+  if (!p->setup_done || p->pack) { set_error("vc_precond_info needs a set-up single problem"); return VC_ERR_STATE; }
+  if (kind != 1 && kind != 3) { set_error("preconditioner kind must be 1 or 3"); return VC_ERR_ARG; }
+  VC_HIP(hipSetDevice(p->device));
+  const int64_t N = npanels(p);
+  if (kind == 1) {
+    const Precond& pc = p->pc;
+    if (nbox) *nbox = pc.nbox;
+    if (nblock) *nblock = pc.nblock;
+    // distinct inverses, box panel lists and pointers, block table, dielectric diagonal
+    if (bytes)
+      *bytes = pc.block_doubles * 8 + (int64_t)pc.h_box_panels.size() * 4 + (int64_t)(pc.nbox + 1) * 4 +
+               (int64_t)pc.nbox * 4 + (int64_t)pc.nblock * 12 + N * 8;
+    return VC_OK;
+  }
+  const vc_status s = build_precond_full(p, nullptr);
+  if (s != VC_OK) return mark(p, s);
+  const FullBlocks& fb = p->pc.full;
+  if (nbox) *nbox = fb.nbox;
+  if (nblock) *nblock = fb.nblock;
+  if (bytes)
+    *bytes = fb.block_doubles * 8 + N * 4 + (int64_t)(fb.nbox + 1) * 4 + (int64_t)fb.nbox * 4 + (int64_t)fb.nblock * 12;
+  return VC_OK;
+}
+
 static vc_status capacitance_impl(vc_problem* p, const vc_solve_opts* opts, double* C, double* rho_dev, vc_stats* stats,
                                   std::vector<double>* rho_host) {
   VC_CHECK_PROBLEM(p);
@@ -398,7 +440,8 @@ vc_status vc_tucker_info(vc_problem* p, int32_t* npairs, int32_t ranks[45], doub
 
 vc_status vc_profile_enable(vc_problem* p, int enable) {
   VC_CHECK_PROBLEM(p);
-  p->prof = enable != 0;
+  if (enable < 0 || enable > 2) { set_error("profiling level must be 0, 1 or 2"); return VC_ERR_ARG; }
+  p->prof = enable;
   return VC_OK;
 }
 
@@ -407,14 +450,17 @@ vc_status vc_pass_times(vc_problem* p, double ms[5], int32_t launches[5], double
   if (!ms || !launches || !bytes) { set_error("null argument"); return VC_ERR_ARG; }
   for (int i = 0; i < 5; ++i) { ms[i] = 0.0; launches[i] = 0; bytes[i] = p->pass_bytes[i]; }
   for (auto& ev : p->ev_pending) {
-    VC_HIP(hipEventSynchronize(ev[5]));
+    for (int i = 5; i >= 0; --i)
+      if (ev[i]) { VC_HIP(hipEventSynchronize(ev[i])); break; }
     for (int i = 0; i < 5; ++i) {
+      if (!ev[i] || !ev[i + 1]) continue;   // pass not bracketed at this profiling level
       float t = 0.f;
       VC_HIP(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
       ms[i] += t;
       launches[i] += 1;
     }
-    for (hipEvent_t e : ev) p->ev_free.push_back(e);
+    for (hipEvent_t e : ev)
+      if (e) p->ev_free.push_back(e);
   }
   p->ev_pending.clear();
   return VC_OK;

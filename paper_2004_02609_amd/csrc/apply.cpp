@@ -247,29 +247,32 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   hipStreamCaptureStatus capst = hipStreamCaptureStatusNone;
   VC_HIP(hipStreamIsCapturing(st, &capst));
-  const bool prof = P->prof && capst == hipStreamCaptureStatusNone;   // no timing events inside a graph
+  // no timing events inside a graph; level 1 brackets every pass (and the Tucker
+  // rebuild), level 2 only the x pass
+  const int prof = capst == hipStreamCaptureStatusNone ? P->prof : 0;
   // Tucker form: rebuild the stored pairs before the x pass reads them
   if (!P->tk.empty()) {
     hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (prof) {
+    if (prof == 1) {
       if (!(t0 = take_event(P)) || !(t1 = take_event(P))) { set_error("hipEventCreate failed"); return VC_ERR_HIP; }
       VC_HIP(hipEventRecord(t0, st));
     }
     vc_status ts = tucker_rebuild<T>(P, (T*)tb.R.p, (int64_t)P->Hy * H * P->Hx, st, skip);
     if (ts != VC_OK) return ts;
-    if (prof) {
+    if (prof == 1) {
       VC_HIP(hipEventRecord(t1, st));
       P->tk_pending.emplace_back(t0, t1);
     }
   }
   if (prof) {
     for (int i = 0; i < 6; ++i)
-      if (!(ev[i] = take_event(P))) { set_error("hipEventCreate failed"); return VC_ERR_HIP; }
-    VC_HIP(hipEventRecord(ev[0], st));
+      if (prof == 1 || i == 2 || i == 3)
+        if (!(ev[i] = take_event(P))) { set_error("hipEventCreate failed"); return VC_ERR_HIP; }
+    if (ev[0]) VC_HIP(hipEventRecord(ev[0], st));
     pass_byte_model(P, transpose, (int)sizeof(T), nrhs, P->pass_bytes);
   }
 #define VC_MARK(i) \
-  if (prof) VC_HIP(hipEventRecord(ev[i], st))
+  if (ev[i]) VC_HIP(hipEventRecord(ev[i], st))
   // 1. scatter + z transform
   if (!pick_tile(P->M[2], eb, Tune<T>::emax, nitems, &ncol, &nthr, budget, transpose ? nrhs : (nrhs + 1) / 2)) return VC_ERR_ARG;
   VC_HIP(launch_zfwd<T>(x, N, nrhs, transpose ? 1 : 0, items, nitems, lptr, pk, pkind, F, cs, rs, n1x, n1y, My, H,
@@ -394,10 +397,20 @@ vc_status apply_op(vc_problem* P, int transpose, vc_precision prec, const double
 
 vc_status apply_precond(vc_problem* P, int transpose, const double* x, double* y, int nrhs, hipStream_t st,
                         const int* skip) {
-  (void)transpose;   // the blocks of eq. (5) are symmetric and the diagonal is its own transpose
+  // the blocks of eq. (5) are symmetric and the diagonal is its own transpose; only the
+  // full blocks of the comparison preconditioner (mode 3) are read transposed
   if (P->pack) return pack_precond(P, x, y, nrhs, st, skip);
   const int64_t N = npanels(P);
   Precond& pc = P->pc;
+  if (pc.mode == 3) {
+    // every panel lies in exactly one box, so the block apply writes every row
+    if (!pc.full.built) { set_error("block-diagonal preconditioner not built"); return VC_ERR_STATE; }
+    const FullBlocks& fb = pc.full;
+    VC_HIP(launch_block_apply(x, y, N, nrhs, fb.box_ptr.as<int32_t>(), fb.box_panels.as<int32_t>(),
+                              fb.box_block.as<int32_t>(), fb.block_off.as<int64_t>(), fb.block_n.as<int32_t>(),
+                              fb.blocks.as<double>(), fb.nbox, skip, st, nullptr, nullptr, transpose ? 1 : 0));
+    return VC_OK;
+  }
   if (pc.mode == 2) {
     VC_HIP(launch_diag_scale(x, y, pc.dinv_diag.as<double>(), N, nrhs, skip, st));
     return VC_OK;

@@ -226,7 +226,8 @@ hipError_t launch_diag_scale(const double* x, double* y, const double* dinv, int
 hipError_t launch_block_apply(const double* x, double* y, int64_t N, int nrhs, const int32_t* box_ptr,
                               const int32_t* box_panels, const int32_t* box_block, const int64_t* block_off,
                               const int32_t* block_n, const double* blocks, int nbox, const int* skip,
-                              hipStream_t st, const int32_t* box_c0 = nullptr, const int32_t* box_nc = nullptr);
+                              hipStream_t st, const int32_t* box_c0 = nullptr, const int32_t* box_nc = nullptr,
+                              int trans = 0);
 // device-side GMRES cycle (one thread per right-hand side, nrhs <= 256)
 hipError_t launch_cycle_start(int nrhs, int m, const double* rn, const double* bn, const double* rtol, int* act_cycle,
                               int* act_step, double* g, double* scal, int* kd, int* skip, double* rre_out,

@@ -273,6 +273,7 @@ vc_status pack_apply(vc_problem* Q, int transpose, vc_precision prec, const doub
 vc_status pack_precond(vc_problem* Q, const double* x, double* y, int nrhs, hipStream_t st, const int* skip) {
   PackData& D = *Q->pack;
   const int64_t N = Q->pack_rows;
+  if (Q->pc.mode == 3) { set_error("packed sets use the block-diagonal-diagonal or diagonal preconditioner"); return VC_ERR_ARG; }
   if (Q->pc.mode == 2) {
     VC_HIP(launch_diag_scale(x, y, D.dinv_diag.as<double>(), N, nrhs, skip, st, N));
     return VC_OK;

@@ -72,9 +72,22 @@ struct TuckerPair {
   DevMem S64, U64[3], S32, U32[3];
 };
 
+// The conventional block-diagonal preconditioner the paper compares against (Sec. III.A):
+// every panel (conductor and dielectric) belongs to one box, and each box's block of the
+// full eq. (4) matrix is inverted; dielectric rows make the blocks unsymmetric, so the
+// transposed apply reads them transposed.
+struct FullBlocks {
+  int built = 0;
+  int nbox = 0;
+  int nblock = 0;
+  int64_t block_doubles = 0;
+  DevMem box_ptr, box_panels, box_block, block_off, block_n, blocks;
+};
+
 struct Precond {
   int built = 0;
-  int mode = 1;   // 1 = block-diagonal-diagonal, 2 = diagonal only
+  int mode = 1;   // 1 = block-diagonal-diagonal, 2 = diagonal only, 3 = block-diagonal (all panels)
+  FullBlocks full;
   int nbox = 0;
   int nblock = 0;
   int64_t block_doubles = 0;
@@ -205,7 +218,7 @@ struct vc_problem {
   };
   std::map<int, YChoice> y_choice;
   // per-pass timing (measurement)
-  bool prof = false;
+  int prof = 0;   // 0 off, 1 every pass, 2 the x pass only
   std::vector<hipEvent_t> ev_free;
   std::vector<std::vector<hipEvent_t>> ev_pending;
   double pass_bytes[5] = {0, 0, 0, 0, 0};
@@ -217,7 +230,8 @@ struct vc_problem {
     drop_graphs();
     if (solve_stream) (void)hipStreamDestroy(solve_stream);
     for (auto& v : ev_pending)
-      for (hipEvent_t e : v) (void)hipEventDestroy(e);
+      for (hipEvent_t e : v)
+        if (e) (void)hipEventDestroy(e);
     for (auto& e : tk_pending) {
       (void)hipEventDestroy(e.first);
       (void)hipEventDestroy(e.second);
@@ -232,6 +246,7 @@ vc_status panelize(vc_problem* p);
 vc_status choose_sizes(vc_problem* p, const int32_t* fft_size);
 vc_status build_spectra(vc_problem* p, int want64, int want32, double tucker_tol, hipStream_t st);
 vc_status build_precond(vc_problem* p, hipStream_t st);
+vc_status build_precond_full(vc_problem* p, hipStream_t st);
 vc_status tucker_begin(vc_problem* p, double tol);
 vc_status tucker_compress_pair(vc_problem* p, const double* X, hipStream_t st);
 vc_status tucker_end(vc_problem* p);

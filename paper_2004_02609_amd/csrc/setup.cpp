@@ -15,8 +15,12 @@
 // box (those on a conductor voxel of that box) form one dense block of eq. (5) values,
 // which is Cholesky-factored and inverted in FP64.  Identical panel patterns share one
 // inverse.  Dielectric rows use the inverse of the eq. (7) diagonal.
+#include <atomic>
+#include <thread>
+#include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <vector>
 
@@ -299,34 +303,48 @@ static bool cholesky_inverse(std::vector<double>& A, int n) {
   return true;
 }
 
+// The eq. (5) (want 0) or eq. (6) (want 1) integral for every observer/source normal
+// pair and every index lag in [-nv, nv] per axis: tab[(3 a + b) nl + t], lag t in
+// x-major order over the (2 nv + 1)^3 box of lags.
+static vc_status lag_tables(vc_problem* P, int want, std::vector<double>& tab, int64_t* nl_out, hipStream_t st) {
+  const int nvx = P->nv[0], nvy = P->nv[1], nvz = P->nv[2];
+  const int ex = 2 * nvx + 1, ey = 2 * nvy + 1, ez = 2 * nvz + 1;
+  const int64_t nl = (int64_t)ex * ey * ez;
+  *nl_out = nl;
+  tab.assign(9 * nl, 0.0);
+  std::vector<double> d(3 * nl);
+  DevMem dd, dout;
+  VC_HIP(dd.alloc(d.size() * sizeof(double)));
+  VC_HIP(dout.alloc(nl * sizeof(double)));
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      int64_t t = 0;
+      for (int lx = -nvx; lx <= nvx; ++lx)
+        for (int ly = -nvy; ly <= nvy; ++ly)
+          for (int lz = -nvz; lz <= nvz; ++lz, ++t) {
+            double o[3] = {(double)lx, (double)ly, (double)lz};
+            if (a != b) { o[a] -= 0.5; o[b] += 0.5; }
+            d[3 * t] = o[0]; d[3 * t + 1] = o[1]; d[3 * t + 2] = o[2];
+          }
+      VC_HIP(hipMemcpy(dd.p, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice));
+      VC_HIP(launch_kernel_table(dd.as<double>(), (int)nl, a, b, want, dout.as<double>(), P->d_gl.as<double>(), st));
+      VC_HIP(hipMemcpyAsync(&tab[(size_t)(3 * a + b) * nl], dout.p, nl * sizeof(double), hipMemcpyDeviceToHost, st));
+      VC_HIP(hipStreamSynchronize(st));
+    }
+  return VC_OK;
+}
+
 vc_status build_precond(vc_problem* P, hipStream_t st) {
   Precond& pc = P->pc;
   const int nvx = P->nv[0], nvy = P->nv[1], nvz = P->nv[2];
   const int64_t N = npanels(P);
   // kernel table of eq. (5) for every lag inside a box: lag in [-nv, nv] per axis
-  const int ex = 2 * nvx + 1, ey = 2 * nvy + 1, ez = 2 * nvz + 1;
-  const int64_t nl = (int64_t)ex * ey * ez;
-  std::vector<double> tab(9 * nl);
+  const int ey = 2 * nvy + 1, ez = 2 * nvz + 1;
+  int64_t nl = 0;
+  std::vector<double> tab;
   {
-    std::vector<double> d(3 * nl);
-    DevMem dd, dout;
-    VC_HIP(dd.alloc(d.size() * sizeof(double)));
-    VC_HIP(dout.alloc(nl * sizeof(double)));
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) {
-        int64_t t = 0;
-        for (int lx = -nvx; lx <= nvx; ++lx)
-          for (int ly = -nvy; ly <= nvy; ++ly)
-            for (int lz = -nvz; lz <= nvz; ++lz, ++t) {
-              double o[3] = {(double)lx, (double)ly, (double)lz};
-              if (a != b) { o[a] -= 0.5; o[b] += 0.5; }
-              d[3 * t] = o[0]; d[3 * t + 1] = o[1]; d[3 * t + 2] = o[2];
-            }
-        VC_HIP(hipMemcpy(dd.p, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice));
-        VC_HIP(launch_kernel_table(dd.as<double>(), (int)nl, a, b, 0, dout.as<double>(), P->d_gl.as<double>(), st));
-        VC_HIP(hipMemcpyAsync(&tab[(size_t)(3 * a + b) * nl], dout.p, nl * sizeof(double), hipMemcpyDeviceToHost, st));
-        VC_HIP(hipStreamSynchronize(st));
-      }
+    const vc_status ts = lag_tables(P, 0, tab, &nl, st);
+    if (ts != VC_OK) return ts;
   }
   // group conductor panels by owning box
   const int nbx = (P->nx + nvx - 1) / nvx, nby = (P->ny + nvy - 1) / nvy, nbz = (P->nz + nvz - 1) / nvz;
@@ -409,6 +427,151 @@ vc_status build_precond(vc_problem* P, hipStream_t st) {
   if ((s = upload(pc.dinv, dinv)) != VC_OK) return s;
   if ((s = upload(pc.dinv_diag, dinv_diag)) != VC_OK) return s;
   pc.built = 1;
+  return VC_OK;
+}
+
+// A^{-1} of a general n x n matrix (row-major) by Gauss-Jordan elimination with partial
+// pivoting, in place; false if a pivot vanishes.
+static bool lu_inverse(std::vector<double>& A, int n) {
+  std::vector<double> Inv((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Inv[(size_t)i * n + i] = 1.0;
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    double best = std::fabs(A[(size_t)k * n + k]);
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A[(size_t)i * n + k]) > best) { best = std::fabs(A[(size_t)i * n + k]); piv = i; }
+    if (!(best > 0.0)) return false;
+    if (piv != k)
+      for (int j = 0; j < n; ++j) {
+        std::swap(A[(size_t)k * n + j], A[(size_t)piv * n + j]);
+        std::swap(Inv[(size_t)k * n + j], Inv[(size_t)piv * n + j]);
+      }
+    const double ip = 1.0 / A[(size_t)k * n + k];
+    for (int j = 0; j < n; ++j) { A[(size_t)k * n + j] *= ip; Inv[(size_t)k * n + j] *= ip; }
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const double f = A[(size_t)i * n + k];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        A[(size_t)i * n + j] -= f * A[(size_t)k * n + j];
+        Inv[(size_t)i * n + j] -= f * Inv[(size_t)k * n + j];
+      }
+    }
+  }
+  A.swap(Inv);
+  return true;
+}
+
+// The conventional block-diagonal preconditioner of the comparison in Sec. III.A: the
+// same nv voxel boxes, but every panel joins a box (a conductor panel the box of its
+// conductor voxel, a dielectric panel the box of the voxel on its -axis side, or +axis
+// side on the grid's low face), and each box's block is the full row of eq. (4)
+// restricted to the box: eq. (5) values on conductor rows, the eq. (7) diagonal plus
+// eq. (6) values on dielectric rows (+axis normal, as the product's rows).  The blocks
+// are unsymmetric; their inverses are stored transposed like the conductor blocks, and
+// identical (pattern, permittivity) boxes share one inverse.
+vc_status build_precond_full(vc_problem* P, hipStream_t st) {
+  FullBlocks& fb = P->pc.full;
+  if (fb.built) return VC_OK;
+  const int nvx = P->nv[0], nvy = P->nv[1], nvz = P->nv[2];
+  const int64_t N = npanels(P);
+  const int ey = 2 * nvy + 1, ez = 2 * nvz + 1;
+  int64_t nl = 0;
+  std::vector<double> tp, te;
+  vc_status s;
+  if ((s = lag_tables(P, 0, tp, &nl, st)) != VC_OK) return s;
+  if ((s = lag_tables(P, 1, te, &nl, st)) != VC_OK) return s;
+  const int nby = (P->ny + nvy - 1) / nvy, nbz = (P->nz + nvz - 1) / nvz;
+  std::map<int64_t, std::vector<int32_t>> boxes;
+  for (int64_t p = 0; p < N; ++p) {
+    const vc_panel& pn = P->panels[p];
+    int v[3] = {pn.i, pn.j, pn.k};
+    if (pn.kind == 0) {
+      if (pn.eps_lo == 0.0) v[pn.dir] -= 1;   // conductor on the -axis side
+    } else if (v[pn.dir] > 0) {
+      v[pn.dir] -= 1;
+    }
+    const int64_t key = ((int64_t)(v[0] / nvx) * nby + v[1] / nvy) * nbz + v[2] / nvz;
+    boxes[key].push_back((int32_t)p);
+  }
+  std::map<std::vector<int64_t>, int> uniq;
+  std::vector<int32_t> box_ptr(1, 0), box_panels, box_block, block_n;
+  std::vector<const std::vector<int32_t>*> block_src;   // panels of the box that defines each block
+  for (auto& kv : boxes) {
+    const int64_t key = kv.first;
+    const int bz = (int)(key % nbz), by = (int)((key / nbz) % nby), bx = (int)(key / ((int64_t)nbz * nby));
+    const int ox = bx * nvx, oy = by * nvy, oz = bz * nvz;
+    const auto& pl = kv.second;
+    const int nb = (int)pl.size();
+    if (nb > 4096) { set_error("preconditioner box holds %d panels (> 4096); use smaller nv", nb); return VC_ERR_ARG; }
+    std::vector<int64_t> pat;
+    pat.reserve(5 * nb);
+    for (int32_t p : pl) {
+      const vc_panel& pn = P->panels[p];
+      int64_t dbits = 0;
+      std::memcpy(&dbits, &P->diag[p], sizeof(double));
+      pat.push_back(pn.kind * 4 + pn.dir); pat.push_back(pn.i - ox); pat.push_back(pn.j - oy); pat.push_back(pn.k - oz);
+      pat.push_back(dbits);
+    }
+    auto it = uniq.find(pat);
+    int blk;
+    if (it == uniq.end()) {
+      blk = (int)block_n.size();
+      uniq.emplace(std::move(pat), blk);
+      block_n.push_back(nb);
+      block_src.push_back(&pl);
+    } else {
+      blk = it->second;
+    }
+    for (int32_t p : pl) box_panels.push_back(p);
+    box_ptr.push_back((int32_t)box_panels.size());
+    box_block.push_back(blk);
+  }
+  const int nblk = (int)block_n.size();
+  std::vector<int64_t> block_off(nblk);
+  int64_t total = 0;
+  for (int b = 0; b < nblk; ++b) { block_off[b] = total; total += (int64_t)block_n[b] * block_n[b]; }
+  std::vector<double> blocks((size_t)total);
+  // assemble and invert the distinct blocks on the host's cores
+  std::atomic<int> next{0}, bad{0};
+  auto work = [&]() {
+    std::vector<double> A;
+    for (int b = next++; b < nblk && !bad; b = next++) {
+      const std::vector<int32_t>& pl = *block_src[b];
+      const int nb = block_n[b];
+      A.assign((size_t)nb * nb, 0.0);
+      for (int r = 0; r < nb; ++r) {
+        const vc_panel& pr = P->panels[pl[r]];
+        const std::vector<double>& tab = pr.kind == 0 ? tp : te;
+        for (int c = 0; c < nb; ++c) {
+          const vc_panel& pcn = P->panels[pl[c]];
+          const int lx = pr.i - pcn.i, ly = pr.j - pcn.j, lz = pr.k - pcn.k;
+          const int64_t t = ((int64_t)(lx + nvx) * ey + (ly + nvy)) * ez + (lz + nvz);
+          A[(size_t)r * nb + c] = tab[(size_t)(3 * pr.dir + pcn.dir) * nl + t] + (r == c ? P->diag[pl[r]] : 0.0);
+        }
+      }
+      if (!lu_inverse(A, nb)) { bad = 1; return; }
+      double* o = blocks.data() + block_off[b];
+      for (int r = 0; r < nb; ++r)
+        for (int c = 0; c < nb; ++c) o[(size_t)c * nb + r] = A[(size_t)r * nb + c];
+    }
+  };
+  const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (int t = 1; t < std::min(nth, nblk); ++t) pool.emplace_back(work);
+  work();
+  for (auto& t : pool) t.join();
+  if (bad) { set_error("block-diagonal preconditioner: singular block"); return VC_ERR_NUMERIC; }
+  fb.nbox = (int)box_block.size();
+  fb.nblock = (int)block_n.size();
+  fb.block_doubles = (int64_t)blocks.size();
+  if ((s = upload(fb.box_ptr, box_ptr)) != VC_OK) return s;
+  if ((s = upload(fb.box_panels, box_panels)) != VC_OK) return s;
+  if ((s = upload(fb.box_block, box_block)) != VC_OK) return s;
+  if ((s = upload(fb.block_off, block_off)) != VC_OK) return s;
+  if ((s = upload(fb.block_n, block_n)) != VC_OK) return s;
+  if ((s = upload(fb.blocks, blocks)) != VC_OK) return s;
+  fb.built = 1;
   return VC_OK;
 }
 

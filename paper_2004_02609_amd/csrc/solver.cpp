@@ -286,6 +286,13 @@ vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const doub
   P->use_graphs = o.graph == 0;
   if (!st) st = get_solve_stream(P);
   if (!st) { set_error("could not create the solve stream"); return VC_ERR_HIP; }
+  if (o.use_precond < 0 || o.use_precond > 3) { set_error("use_precond must be 0, 1, 2 or 3"); return VC_ERR_ARG; }
+  if (o.use_precond == 3) {
+    if (P->pack) { set_error("packed sets use the block-diagonal-diagonal or diagonal preconditioner"); return VC_ERR_ARG; }
+    // built on first use, before any restart cycle is captured
+    const vc_status bs = build_precond_full(P, st);
+    if (bs != VC_OK) return bs;
+  }
   VC_HIP(hipMemsetAsync(x, 0, (size_t)nrhs * N * sizeof(double), st));
   int ir_steps = 0;
   vc_status s;

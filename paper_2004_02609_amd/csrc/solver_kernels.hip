@@ -231,7 +231,7 @@ k_block_apply(const double* __restrict__ x, double* __restrict__ y, int64_t N, i
               const int32_t* __restrict__ box_ptr, const int32_t* __restrict__ box_panels,
               const int32_t* __restrict__ box_block, const int64_t* __restrict__ block_off,
               const int32_t* __restrict__ block_n, const double* __restrict__ blocks, const int* __restrict__ skip,
-              const int32_t* __restrict__ box_c0, const int32_t* __restrict__ box_nc) {
+              const int32_t* __restrict__ box_c0, const int32_t* __restrict__ box_nc, int trans) {
   if (skip && *skip) return;
   __shared__ double xs[kBoxLds];
   const int box = blockIdx.x;
@@ -259,8 +259,11 @@ k_block_apply(const double* __restrict__ x, double* __restrict__ y, int64_t N, i
       const double* xr = xs + r * nb;
       double acc = 0.0;
       // the block is stored transposed: B^T[j][i] = Binv[i][j], lanes (consecutive i)
-      // read consecutive addresses
-      for (int j = 0; j < nb; ++j) acc += B[(int64_t)j * nb + i] * xr[j];
+      // read consecutive addresses; the transposed apply reads row i of B^T
+      if (!trans)
+        for (int j = 0; j < nb; ++j) acc += B[(int64_t)j * nb + i] * xr[j];
+      else
+        for (int j = 0; j < nb; ++j) acc += B[(int64_t)i * nb + j] * xr[j];
       y[(int64_t)(r0 + r) * N + box_panels[p0 + i]] = acc;
     }
   }
@@ -270,10 +273,10 @@ k_block_apply(const double* __restrict__ x, double* __restrict__ y, int64_t N, i
 hipError_t launch_block_apply(const double* x, double* y, int64_t N, int nrhs, const int32_t* box_ptr,
                               const int32_t* box_panels, const int32_t* box_block, const int64_t* block_off,
                               const int32_t* block_n, const double* blocks, int nbox, const int* skip,
-                              hipStream_t st, const int32_t* box_c0, const int32_t* box_nc) {
+                              hipStream_t st, const int32_t* box_c0, const int32_t* box_nc, int trans) {
   if (nbox == 0) return hipSuccess;
   hipLaunchKernelGGL(k_block_apply, dim3(nbox), dim3(kBoxThreads), 0, st, x, y, N, nrhs, box_ptr, box_panels,
-                     box_block, block_off, block_n, blocks, skip, box_c0, box_nc);
+                     box_block, block_off, block_n, blocks, skip, box_c0, box_nc, trans);
   return hipGetLastError();
 }
 

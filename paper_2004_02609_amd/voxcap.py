@@ -73,6 +73,8 @@ _sig = {
     "vc_setup": (C.c_int, [_P, C.POINTER(vc_setup_opts), _P]),
     "vc_apply": (C.c_int, [_P, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int32, _P]),
     "vc_apply_precond": (C.c_int, [_P, C.c_int, C.c_void_p, C.c_void_p, C.c_int32, _P]),
+    "vc_apply_precond_kind": (C.c_int, [_P, C.c_int32, C.c_int, C.c_void_p, C.c_void_p, C.c_int32, _P]),
+    "vc_precond_info": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "vc_capacitance": (C.c_int, [_P, C.POINTER(vc_solve_opts), C.POINTER(C.c_double), C.c_void_p,
                                  C.POINTER(vc_stats)]),
     "vc_capacitance_grad_eps": (C.c_int, [_P, C.POINTER(vc_solve_opts), C.POINTER(C.c_int32), C.c_int32,
@@ -190,8 +192,21 @@ def vc_apply_precond(h, x, y, nrhs, transpose=False, stream=None):
            "vc_apply_precond")
 
 
+def vc_apply_precond_kind(h, kind, x, y, nrhs, transpose=False, stream=None):
+    _check(_lib.vc_apply_precond_kind(h, int(kind), int(bool(transpose)), _ptr(x), _ptr(y), int(nrhs),
+                                      _stream(stream)), "vc_apply_precond_kind")
+
+
+def vc_precond_info(h, kind):
+    nbox, nblock, nbytes = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+    _check(_lib.vc_precond_info(h, int(kind), C.byref(nbox), C.byref(nblock), C.byref(nbytes)), "vc_precond_info")
+    return {"boxes": nbox.value, "distinct_blocks": nblock.value, "bytes": nbytes.value}
+
+
 def vc_profile_enable(h, enable=True):
-    _check(_lib.vc_profile_enable(h, int(bool(enable))), "vc_profile_enable")
+    """enable: False / 0 off, True / 1 events around every pass, 2 around the x pass only."""
+    level = int(enable) if not isinstance(enable, bool) else int(enable)
+    _check(_lib.vc_profile_enable(h, level), "vc_profile_enable")
 
 
 PASS_NAMES = ("zfwd_scatter", "y_forward", "x_sandwich_multiply", "y_inverse", "zinv_gather")
@@ -449,6 +464,20 @@ class Problem:
             y = torch.empty_like(x)
         vc_apply_precond(self._h, x, y, x.shape[0], transpose, stream)
         return y
+
+    def apply_precond_kind(self, kind, x, y=None, transpose=False, stream=None):
+        """y = R x for preconditioner kind 1 (eq. 14), 2 (diagonal) or 3 (block-diagonal
+        over all panels, the comparison of Sec. III.A)."""
+        import torch
+        x = x.contiguous()
+        if y is None:
+            y = torch.empty_like(x)
+        vc_apply_precond_kind(self._h, kind, x, y, x.shape[0], transpose, stream)
+        return y
+
+    def precond_info(self, kind=1):
+        """Boxes, distinct inverse blocks and stored bytes of preconditioner kind 1 or 3."""
+        return vc_precond_info(self._h, kind)
 
     def profile(self, enable=True):
         vc_profile_enable(self._h, enable)

@@ -86,6 +86,53 @@ def test_precond_blocks_invert_dense_blocks(dev):
     assert err < 1e-10, err
 
 
+def test_comparison_preconditioners_match_dense(dev):
+    """Kinds 2 and 3 of the preconditioner comparison (Sec. III.A) against the dense
+    oracle matrix: the diagonal preconditioner is 1 / diag(A); the conventional
+    block-diagonal one solves the full eq. (4) block of every box of 4 voxels, where a
+    conductor panel joins the box of its conductor voxel and a dielectric panel the box
+    of the voxel on its -axis side (its own voxel on the grid's low face).  The blocks
+    are unsymmetric, so the transposed apply is checked against A_box^T as well."""
+    s = scenes.random_small(9, shape=(11, 7, 13), n_cond=3, n_diel=2)
+    P = _problem(s, nv=4)
+    A, po, perm = oracle_matrix_library_order(s, P.panels())
+    pan = P.panels()
+    N = P.N
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((2, N))
+    xt = torch.tensor(x, device=dev)
+    y2 = P.apply_precond_kind(2, xt).cpu().numpy()
+    ref2 = x / np.diag(A)[None, :]
+    e2 = np.abs(y2 - ref2).max() / np.abs(ref2).max()
+    print("diagonal preconditioner rel err", e2, flush=True)
+    assert e2 < 1e-12, e2
+    cond = pan["kind"] == 0
+    vox = np.stack([pan["i"], pan["j"], pan["k"]], 1).astype(int)
+    rows = np.arange(N)
+    shift = np.where(cond, (pan["eps_lo"] == 0.0).astype(int), (vox[rows, pan["dir"]] > 0).astype(int))
+    vox[rows, pan["dir"]] -= shift
+    box = vox // 4
+    groups = {}
+    for p in range(N):
+        groups.setdefault(tuple(box[p]), []).append(p)
+    assert sum(len(g) for g in groups.values()) == N
+    assert any(cond[g].any() and (~cond[g]).any() for g in map(np.array, groups.values())), \
+        "no box mixes conductor and dielectric panels"
+    for transpose in (False, True):
+        y3 = P.apply_precond_kind(3, xt, transpose=transpose).cpu().numpy()
+        ref3 = np.zeros_like(x)
+        for g in groups.values():
+            idx = np.array(g)
+            B = A[np.ix_(idx, idx)]
+            ref3[:, idx] = np.linalg.solve(B.T if transpose else B, x[:, idx].T).T
+        e3 = np.abs(y3 - ref3).max() / np.abs(ref3).max()
+        print("block-diagonal preconditioner", "transposed" if transpose else "forward", "rel err", e3, flush=True)
+        assert e3 < 1e-10, (transpose, e3)
+    info1, info3 = P.precond_info(1), P.precond_info(3)
+    print("storage kind 1", info1, "kind 3", info3, flush=True)
+    assert info3["boxes"] == len(groups)
+
+
 @pytest.mark.parametrize("name,make", SCENES)
 def test_capacitance_fp64(dev, name, make):
     s = make()
