@@ -92,6 +92,28 @@ inline size_t sandwich_lds_bytes(int L, int ncol, int elem, int n1x) {
 AxisPlan make_sandwich_plan(int L, int rmax, int rmid, int rs_max, int max_tl);
 constexpr int kSandMaxStages = 6;
 constexpr int sandwich_rmid(int elem) { return elem == 4 ? 10 : 10; }
+// x-transform plans compiled with their radices, stage count and length as constants
+// (entry 0: the generic kernel, which reads them from SandArgs).  A launch whose runtime
+// plan equals an entry uses that entry's kernel; every other plan runs the generic one.
+struct SandFixedPlan {
+  int L, nst, r[4];
+};
+constexpr SandFixedPlan kSandFixed[] = {
+    {0, 0, {0, 0, 0, 0}},
+    {36, 3, {4, 3, 3, 0}},
+    {140, 3, {7, 5, 4, 0}},
+    {270, 3, {9, 6, 5, 0}},
+    {540, 3, {10, 9, 6, 0}},
+    {540, 4, {10, 6, 3, 3}},
+    {1050, 4, {7, 6, 5, 5}},
+};
+constexpr int kSandNumFixed = (int)(sizeof(kSandFixed) / sizeof(kSandFixed[0]));
+constexpr uint32_t sand_fixed_pack(int id) {
+  uint32_t p = 0;
+  for (int s = 0; s < kSandFixed[id].nst; ++s) p |= (uint32_t)kSandFixed[id].r[s] << (5 * s);
+  return p;
+}
+constexpr int sand_fixed_last(int id) { return kSandFixed[id].nst > 0 ? kSandFixed[id].r[kSandFixed[id].nst - 1] : 0; }
 
 template <typename T>
 hipError_t launch_zfwd(const double* x, int64_t N, int nrhs, int mode, const int32_t* items, int nitems,

@@ -224,8 +224,9 @@ __device__ __forceinline__ int sw_pair(int o, int b) {
   return b < 3 ? (al == o ? al : 2 + al + o) : 6 + 3 * al + o;
 }
 
-// one (column tile, right-hand side) of the pass
-template <typename T, int NIN, int NOUT, int RS>
+// one (column tile, right-hand side) of the pass; PID > 0 takes the plan from
+// kSandFixed[PID] as compile-time constants (the launcher checks that it is a.radpack's)
+template <typename T, int NIN, int NOUT, int RS, int PID = 0>
 __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout,
                                               const T* __restrict__ R, const SandArgs& a,
                                               const C2<T>* __restrict__ twg, const C2<T>* __restrict__ phx,
@@ -234,7 +235,10 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
   constexpr int RMAX = sandwich_rmax((int)sizeof(T)), RMID = sandwich_rmid((int)sizeof(T));
   constexpr uint32_t E = sizeof(C2<T>);
   extern __shared__ char smem_raw[];
-  const int L = a.Mx, tl = a.tl, S = a.nst;
+  constexpr bool FX = PID > 0;
+  constexpr SandFixedPlan PD = kSandFixed[PID];
+  const int L = FX ? PD.L : a.Mx, tl = FX ? PD.L / RS : a.tl, S = FX ? PD.nst : a.nst;
+  auto rad = [&](int s) -> int { return FX ? PD.r[s] : srad(a, s); };
   const int ncol = a.ncol;
   const uint32_t ncolpE = (uint32_t)(ncol + 1) * E;
   char* twb = smem_raw;                                    // L twiddles
@@ -251,7 +255,7 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
   const int yflip = ky > a.My / 2;
   const int kyp = yflip ? a.My - ky : ky;
   const uint32_t rowb = (uint32_t)ncols * E;   // bytes between x rows
-  const int r0 = srad(a, 0);
+  const int r0 = rad(0);
   const int LR0 = L / r0;
   const bool act0 = i < LR0;                   // owns a butterfly of the first / last stage
   for (int t = tid; t < L; t += blockDim.x) reinterpret_cast<C2<T>*>(twb)[t] = twg[t];
@@ -322,8 +326,9 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
       }
       __syncthreads();
       int p = r0;
-      for (int s = 1; s < S - 1; ++s) {
-        const int rs = srad(a, s);
+#pragma unroll
+      for (int s = 1; s < (FX ? PD.nst : S) - 1; ++s) {
+        const int rs = rad(s);
         const float invp = stage_inv(p);
 #define VC_CALL(RR) sw_mid<T, RR>(lds, twb, L, p, invp, i, rbase, cE, ncolpE, T(-1));
         VC_SW_SWITCH(rs, VC_CALL, RMID)
@@ -451,8 +456,9 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
       }
       __syncthreads();
       int p = RS;
-      for (int s = S - 2; s >= 1; --s) {
-        const int rs = srad(a, s);
+#pragma unroll
+      for (int s = (FX ? PD.nst : S) - 2; s >= 1; --s) {
+        const int rs = rad(s);
         const float invp = stage_inv(p);
 #define VC_CALL(RR) sw_mid<T, RR>(lds, twb, L, p, invp, i, rbase, cE, ncolpE, T(1));
         VC_SW_SWITCH(rs, VC_CALL, RMID)
@@ -470,17 +476,21 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
 
 // Right-hand sides fastest: the workgroups that read one tile's spectra run together on
 // one XCD, so those spectra come from HBM once per tile rather than once per RHS.
-template <typename T, int NIN, int NOUT, int RS>
+template <typename T, int NIN, int NOUT, int RS, int PID = 0>
 __global__ void __launch_bounds__(512, (sizeof(T) == 8 || NIN == 6) ? 2 : 3)
 k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __restrict__ R, SandArgs a,
             const C2<T>* __restrict__ twg, const C2<T>* __restrict__ phx, const C2<T>* __restrict__ phy,
             const C2<T>* __restrict__ phz, const uint8_t* __restrict__ pflag) {
   if (a.skip && *a.skip) return;
+  // a fixed-plan kernel never runs a plan other than its own (uniform check)
+  if (PID > 0 && (a.Mx != kSandFixed[PID].L || a.nst != kSandFixed[PID].nst || a.radpack != sand_fixed_pack(PID) ||
+                  a.tl * RS != a.Mx))
+    return;
   const int ntiles = gridDim.x;
   const int work = xcd_remap(blockIdx.y * ntiles + blockIdx.x, ntiles * gridDim.y);
   const int tile = work / a.nrhs, rhs = work - tile * a.nrhs;
   if (a.act && !a.act[rhs]) return;
-  sandwich_body<T, NIN, NOUT, RS>(Fin, Fout, R, a, twg, phx, phy, phz, pflag, tile, rhs);
+  sandwich_body<T, NIN, NOUT, RS, PID>(Fin, Fout, R, a, twg, phx, phy, phz, pflag, tile, rhs);
 }
 
 // several scenes in one launch: linear workgroup -> (scene, tile, rhs), XCD-contiguous
@@ -506,18 +516,40 @@ template <typename T, int NIN> struct SandRS {
   static constexpr int max = sandwich_rs_max((int)sizeof(T), NIN);
 };
 
+// launch with last-stage radix RR: the fixed-plan kernel of the first table entry that
+// equals the runtime plan, else the generic one
+template <typename T, int NIN, int NOUT, int RR, int ID>
+hipError_t launch_sandwich_rs(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
+                              const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
+                              size_t lds, hipStream_t st) {
+  dim3 grid((a.My * a.H + a.ncol - 1) / a.ncol, a.nrhs);
+  if constexpr (ID < kSandNumFixed) {
+    if constexpr (sand_fixed_last(ID) == RR) {
+      if (a.Mx == kSandFixed[ID].L && a.nst == kSandFixed[ID].nst && a.radpack == sand_fixed_pack(ID) &&
+          a.tl * RR == a.Mx) {
+        hipLaunchKernelGGL((k_xsandwich<T, NIN, NOUT, RR, ID>), grid, dim3(nthr), lds, st, (const C2<T>*)Fin,
+                           (C2<T>*)Fout, (const T*)R, a, (const C2<T>*)tw, (const C2<T>*)phx, (const C2<T>*)phy,
+                           (const C2<T>*)phz, pflag);
+        return hipGetLastError();
+      }
+    }
+    return launch_sandwich_rs<T, NIN, NOUT, RR, ID + 1>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, st);
+  } else {
+    hipLaunchKernelGGL((k_xsandwich<T, NIN, NOUT, RR, 0>), grid, dim3(nthr), lds, st, (const C2<T>*)Fin,
+                       (C2<T>*)Fout, (const T*)R, a, (const C2<T>*)tw, (const C2<T>*)phx, (const C2<T>*)phy,
+                       (const C2<T>*)phz, pflag);
+    return hipGetLastError();
+  }
+}
+
 template <typename T, int NIN, int NOUT>
 hipError_t launch_sandwich_v(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
                              const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
                              size_t lds, int rs, hipStream_t st) {
-  dim3 grid((a.My * a.H + a.ncol - 1) / a.ncol, a.nrhs);
 #define VC_RS(RR)                                                                                                 \
   case RR:                                                                                                        \
     if constexpr (RR <= SandRS<T, NIN>::max) {                                                                    \
-      hipLaunchKernelGGL((k_xsandwich<T, NIN, NOUT, RR>), grid, dim3(nthr), lds, st, (const C2<T>*)Fin,          \
-                         (C2<T>*)Fout, (const T*)R, a, (const C2<T>*)tw, (const C2<T>*)phx, (const C2<T>*)phy,    \
-                         (const C2<T>*)phz, pflag);                                                               \
-      return hipGetLastError();                                                                                   \
+      return launch_sandwich_rs<T, NIN, NOUT, RR, 1>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, st);  \
     }                                                                                                             \
     break;
   switch (rs) {

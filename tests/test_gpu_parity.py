@@ -167,11 +167,18 @@ def test_unit_cube_16(dev):
 
 
 # x lengths 6 (one-stage plan), 90 (three stages) and 54 (two stages), with dielectric
-# rows so the transposed product takes the six-input variant
+# rows so the transposed product takes the six-input variant; and the lengths with
+# compiled plans (36, 140, 270, 540, 1050: the fixed-plan kernels run whenever the
+# configuration's plan is theirs, the generic kernel otherwise)
 XPASS_SCENES = [
     ("x6", lambda: scenes.random_small(21, shape=(2, 6, 5), n_cond=1, n_diel=1)),
     ("x90", lambda: scenes.random_small(23, shape=(44, 5, 4), n_cond=2, n_diel=1)),
     ("x54", lambda: scenes.random_small(29, shape=(25, 4, 6), n_cond=2, n_diel=2)),
+    ("x36", lambda: scenes.random_small(31, shape=(16, 5, 3), n_cond=2, n_diel=1)),
+    ("x140", lambda: scenes.random_small(31, shape=(64, 5, 3), n_cond=2, n_diel=1)),
+    ("x270", lambda: scenes.random_small(31, shape=(128, 5, 3), n_cond=2, n_diel=1)),
+    ("x540", lambda: scenes.random_small(31, shape=(256, 5, 3), n_cond=2, n_diel=1)),
+    ("x1050", lambda: scenes.random_small(31, shape=(512, 5, 3), n_cond=2, n_diel=1)),
 ]
 
 
