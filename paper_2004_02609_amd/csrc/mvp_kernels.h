@@ -92,9 +92,10 @@ inline size_t sandwich_lds_bytes(int L, int ncol, int elem, int n1x) {
 AxisPlan make_sandwich_plan(int L, int rmax, int rmid, int rs_max, int max_tl);
 constexpr int kSandMaxStages = 6;
 constexpr int sandwich_rmid(int elem) { return elem == 4 ? 10 : 10; }
-// x-transform plans compiled with their radices, stage count and length as constants
-// (entry 0: the generic kernel, which reads them from SandArgs).  A launch whose runtime
-// plan equals an entry uses that entry's kernel; every other plan runs the generic one.
+// Register-edge transform plans (x pass and y pass) compiled with their radices, stage
+// count and length as constants (entry 0: the generic kernels, which read them from
+// their arguments).  A launch whose runtime plan equals an entry uses that entry's
+// kernel; every other plan runs the generic one.
 struct SandFixedPlan {
   int L, nst, r[4];
 };
@@ -106,6 +107,7 @@ constexpr SandFixedPlan kSandFixed[] = {
     {540, 3, {10, 9, 6, 0}},
     {540, 4, {10, 6, 3, 3}},
     {1050, 4, {7, 6, 5, 5}},
+    {36, 2, {6, 6, 0, 0}},
 };
 constexpr int kSandNumFixed = (int)(sizeof(kSandFixed) / sizeof(kSandFixed[0]));
 constexpr uint32_t sand_fixed_pack(int id) {

@@ -46,11 +46,16 @@ __device__ __forceinline__ void yp_first(const C2<T>* __restrict__ pre, bool act
     if constexpr (RR >= RS && RR <= HI) { CALL(RR) } \
     break;
 
-template <typename T, int RS>
+// PID > 0: the plan of kSandFixed[PID] as compile-time constants; the kernel returns at
+// once if the runtime plan is not that one
+template <typename T, int RS, int PID = 0>
 __global__ void __launch_bounds__(1024)
 k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const uint8_t* __restrict__ lflag,
         const uint8_t* __restrict__ pflag) {
   if (a.skip && *a.skip) return;
+  constexpr bool FX = PID > 0;
+  constexpr SandFixedPlan PD = kSandFixed[PID];
+  if (FX && (a.L != PD.L || a.nst != PD.nst || a.radpack != sand_fixed_pack(PID) || a.tl * RS != a.L)) return;
   constexpr int RMAX = 10;
   constexpr uint32_t E = sizeof(C2<T>);
   const int plane = blockIdx.y;
@@ -61,7 +66,8 @@ k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const 
   const int need = a.inverse ? mout : min_;
   if (pflag && need && !(pflag[axis * a.n1x + plane] & need)) return;   // uniform per workgroup
   extern __shared__ char smem_raw[];
-  const int L = a.L, tl = a.tl, S = a.nst, ncol = a.ncol;
+  const int L = FX ? PD.L : a.L, tl = FX ? PD.L / RS : a.tl, S = FX ? PD.nst : a.nst, ncol = a.ncol;
+  auto rad = [&](int s) -> int { return FX ? PD.r[s] : (int)((a.radpack >> (5 * s)) & 31u); };
   const T sg = a.inverse ? T(1) : T(-1);
   const uint32_t ncolpE = (uint32_t)(ncol + 1) * E;
   char* twb = smem_raw;                       // L twiddles
@@ -75,7 +81,7 @@ k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const 
   C2<T>* base = data + comp * a.comp_stride + rhs * a.rhs_stride + plane * a.plane_stride;
   const uint8_t* lf = lflag ? lflag + ((int64_t)axis * a.n1x + plane) * a.n1y : nullptr;
   const uint32_t rowb = (uint32_t)a.row_stride * E;
-  const int r0 = (int)(a.radpack & 31u);
+  const int r0 = rad(0);
   const int LR0 = L / r0;
   const bool act0 = i < LR0;
   for (int t = tid; t < L; t += blockDim.x) reinterpret_cast<C2<T>*>(twb)[t] = twg[t];
@@ -135,8 +141,9 @@ k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const 
   }
   __syncthreads();
   int p = r0;
-  for (int s = 1; s < S - 1; ++s) {
-    const int rs = (int)((a.radpack >> (5 * s)) & 31u);
+#pragma unroll
+  for (int s = 1; s < (FX ? PD.nst : S) - 1; ++s) {
+    const int rs = rad(s);
     const float invp = stage_inv(p);
 #define VC_CALL(RR) sw_mid<T, RR>(lds, twb, L, p, invp, i, rbase, cE, ncolpE, sg);
     VC_YP_SWITCH(rs, VC_CALL, RMAX)
@@ -168,6 +175,38 @@ k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const 
 #undef VC_YP_CASE
 #undef VC_YP_SWITCH
 
+// launch with last-stage radix RR: the fixed-plan kernel of the first table entry that
+// equals the runtime plan, else the generic one
+template <typename T, int RR, int ID>
+hipError_t launch_ypass_rs(void* data, const YArgs& a, const void* tw, const uint8_t* lflag, const uint8_t* pflag,
+                           dim3 grid, int nthr, size_t lds, hipStream_t st) {
+  if constexpr (ID < kSandNumFixed) {
+    if constexpr (sand_fixed_last(ID) == RR) {
+      if (a.L == kSandFixed[ID].L && a.nst == kSandFixed[ID].nst && a.radpack == sand_fixed_pack(ID) &&
+          a.tl * RR == a.L) {
+        if (lds > kLdsBudget) {
+          const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ypass<T, RR, ID>),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+          if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL((k_ypass<T, RR, ID>), grid, dim3(nthr), lds, st, (C2<T>*)data, a, (const C2<T>*)tw,
+                           lflag, pflag);
+        return hipGetLastError();
+      }
+    }
+    return launch_ypass_rs<T, RR, ID + 1>(data, a, tw, lflag, pflag, grid, nthr, lds, st);
+  } else {
+    if (lds > kLdsBudget) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ypass<T, RR, 0>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_ypass<T, RR, 0>), grid, dim3(nthr), lds, st, (C2<T>*)data, a, (const C2<T>*)tw, lflag,
+                       pflag);
+    return hipGetLastError();
+  }
+}
+
 template <typename T>
 hipError_t launch_ypass(void* data, const YArgs& a, const void* tw, const uint8_t* lflag, const uint8_t* pflag,
                         int nplanes, int nthr, hipStream_t st) {
@@ -194,16 +233,9 @@ hipError_t launch_ypass(void* data, const YArgs& a, const void* tw, const uint8_
   const size_t lds = (size_t)sizeof(C2<T>) * ((size_t)a.L + (size_t)a.L * (a.ncol + 1));
   if (lds > lds_ext_budget()) return hipErrorInvalidValue;
   dim3 grid((a.ncols + a.ncol - 1) / a.ncol, nplanes, a.cs.n * a.nrhs);
-#define VC_RS(RR)                                                                                             \
-  case RR:                                                                                                    \
-    if (lds > kLdsBudget) {                                                                                   \
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ypass<T, RR>),                 \
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);          \
-      if (e != hipSuccess) return e;                                                                          \
-    }                                                                                                         \
-    hipLaunchKernelGGL((k_ypass<T, RR>), grid, dim3(nthr), lds, st, (C2<T>*)data, a, (const C2<T>*)tw, lflag,   \
-                       pflag);                                                                                \
-    return hipGetLastError();
+#define VC_RS(RR)                                                                                \
+  case RR:                                                                                       \
+    return launch_ypass_rs<T, RR, 1>(data, a, tw, lflag, pflag, grid, nthr, lds, st);
   switch (rs) {
     VC_RS(2) VC_RS(3) VC_RS(4) VC_RS(5) VC_RS(6) VC_RS(7) VC_RS(8) VC_RS(9) VC_RS(10)
     default: break;

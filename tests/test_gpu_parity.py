@@ -182,6 +182,41 @@ XPASS_SCENES = [
 ]
 
 
+# y lengths with compiled register-edge plans (36, 140, 270, 540, 1050)
+YPASS_SCENES = [
+    ("y36", lambda: scenes.random_small(37, shape=(5, 16, 7), n_cond=2, n_diel=1)),
+    ("y140", lambda: scenes.random_small(37, shape=(5, 64, 7), n_cond=2, n_diel=1)),
+    ("y270", lambda: scenes.random_small(37, shape=(5, 128, 7), n_cond=2, n_diel=1)),
+    ("y540", lambda: scenes.random_small(37, shape=(5, 256, 7), n_cond=2, n_diel=1)),
+    ("y1050", lambda: scenes.random_small(37, shape=(5, 512, 6), n_cond=2, n_diel=1)),
+]
+
+
+@pytest.mark.parametrize("name,make", YPASS_SCENES)
+def test_ypass_compiled_plans_match_dense(dev, name, make):
+    """The register-edge y pass on the lengths whose plans are compiled (the fixed-plan
+    kernels), forward and transposed, in both precisions, against the dense product."""
+    s = make()
+    P = _problem(s, max_rhs=2)
+    A, po, perm = oracle_matrix_library_order(s, P.panels())
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((2, P.N))
+    xt = torch.tensor(x, device=dev)
+    for prec, tol in (("fp64", 1e-11), ("fp32", 2e-5)):
+        for transpose in (False, True):
+            ref = ((A.T if transpose else A) @ x.T).T
+            y = P.apply(xt, transpose=transpose, prec=prec).cpu().numpy()
+            err = np.abs(y - ref).max() / np.abs(ref).max()
+            print(name, prec, "T" if transpose else "F", P.fft_size(), f"{err:.2e}", flush=True)
+            assert err < tol, (name, prec, transpose, err)
+    rep = [l for l in P.tuning_report().splitlines() if l.startswith("y-pass")]
+    print("\n".join(rep), flush=True)
+    # at length 1050 an FP64 register-edge tile of two columns exceeds 64 KiB of LDS, so
+    # the default there is the LDS-tile kernel (the autotuner may still pick one column)
+    need = [l for l in rep if name != "y1050" or "fp32" in l]
+    assert need and all("register-edge" in l for l in need), rep
+
+
 @pytest.mark.parametrize("name,make", XPASS_SCENES)
 def test_every_xpass_configuration_matches_dense(dev, name, make):
     """Each launch configuration the autotuner may pick (radix plan x column tile) gives
