@@ -368,9 +368,10 @@ bool sandwich_args_ok(const SandArgs& a, int nthr) {
   if (prod != a.Mx || (long)a.tl * rs != a.Mx || (long)a.tl * a.ncol > nthr) return false;
   if (a.nst == 1 && a.tl != 1) return false;
   if (rs > sandwich_rs_max((int)sizeof(T), a.nin)) return false;
-  // 32-bit byte offsets inside one (component, rhs) slab and one stored pair
-  if ((uint64_t)a.n1x * a.My * a.H * 2 * sizeof(T) >= ((uint64_t)1 << 32) ||
-      (uint64_t)a.pair_stride * sizeof(T) >= ((uint64_t)1 << 32))
+  // 32-bit byte offsets inside one (component, rhs) slab and one stored pair, each slab
+  // small enough for the out-of-range offset of the buffer views (0xFFFFFFF0)
+  if ((uint64_t)a.n1x * a.My * a.H * 2 * sizeof(T) > 0xFFFFFF00ull ||
+      (uint64_t)a.pair_stride * sizeof(T) > 0xFFFFFF00ull)
     return false;
   return true;
 }

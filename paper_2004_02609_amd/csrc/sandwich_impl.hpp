@@ -50,6 +50,42 @@ template <typename V>
 __device__ __forceinline__ void sto(V* __restrict__ base, uint32_t byte_off, V v) {
   *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
+// Raw buffer views (stride 0) of one array slab: an access at a byte offset at or past
+// the slab's size reads zero and a store there writes nothing (the memory unit's range
+// check).  Masked row accesses pass kOob instead of branching around the access, and
+// each address is a uniform resource plus one 32-bit offset.  Slabs are at most kOob
+// bytes (checked by the launchers).
+constexpr uint32_t kOob = 0xFFFFFFF0u;
+struct Buf {
+  __amdgpu_buffer_rsrc_t r;
+};
+__device__ __forceinline__ Buf make_buf(const void* p, uint32_t bytes) {
+  return Buf{__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000)};
+}
+typedef unsigned int vc_u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int vc_u32x4 __attribute__((ext_vector_type(4)));
+template <typename T> __device__ __forceinline__ C2<T> bld(Buf b, uint32_t off);
+template <> __device__ __forceinline__ C2<float> bld<float>(Buf b, uint32_t off) {
+  return __builtin_bit_cast(C2<float>, __builtin_amdgcn_raw_buffer_load_b64(b.r, off, 0, 0));
+}
+template <> __device__ __forceinline__ C2<double> bld<double>(Buf b, uint32_t off) {
+  return __builtin_bit_cast(C2<double>, __builtin_amdgcn_raw_buffer_load_b128(b.r, off, 0, 0));
+}
+template <typename T> __device__ __forceinline__ void bst(Buf b, uint32_t off, C2<T> v);
+template <> __device__ __forceinline__ void bst<float>(Buf b, uint32_t off, C2<float> v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(vc_u32x2, v), b.r, off, 0, 0);
+}
+template <> __device__ __forceinline__ void bst<double>(Buf b, uint32_t off, C2<double> v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(vc_u32x4, v), b.r, off, 0, 0);
+}
+template <typename T> __device__ __forceinline__ T bld1(Buf b, uint32_t off);
+template <> __device__ __forceinline__ float bld1<float>(Buf b, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, off, 0, 0));
+}
+template <> __device__ __forceinline__ double bld1<double>(Buf b, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, off, 0, 0));
+}
+
 template <typename T>
 __device__ __forceinline__ C2<T> lds_ld(const char* __restrict__ lds, uint32_t off) {
   return *reinterpret_cast<const C2<T>*>(lds + off);
@@ -98,16 +134,15 @@ __device__ __forceinline__ void tw_mul(C2<T>* v, const char* __restrict__ twb, u
 __device__ __forceinline__ float stage_inv(int p) { return __builtin_amdgcn_rcpf((float)p); }
 
 // first-stage inputs of butterfly i: rows i + q L/R of one component from HBM into
-// registers; bit q of vmask says row i + q L/R is stored (else zero)
+// registers; bit q of vmask says row i + q L/R is stored (else it reads as zero)
 template <typename T, int R>
-__device__ __forceinline__ void sw_load(C2<T>* __restrict__ pre, const C2<T>* __restrict__ src, uint32_t gbase,
-                                        uint32_t gstride, uint32_t vmask, bool act) {
+__device__ __forceinline__ void sw_load(C2<T>* __restrict__ pre, Buf src, uint32_t gbase, uint32_t gstride,
+                                        uint32_t vmask, bool act) {
   if (!act) return;
   uint32_t o = gbase;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    pre[q] = C2<T>{T(0), T(0)};
-    if (vmask & (1u << q)) pre[q] = ldo(src, o);
+    pre[q] = bld<T>(src, (vmask & (1u << q)) ? o : kOob);
     o += gstride;
   }
 }
@@ -116,7 +151,7 @@ __device__ __forceinline__ void sw_load(C2<T>* __restrict__ pre, const C2<T>* __
 // of the next component (if any) go into the staging registers first, so they are in
 // flight during this component's transform
 template <typename T, int R>
-__device__ __forceinline__ void sw_first(C2<T>* __restrict__ pre, bool next, const C2<T>* __restrict__ nsrc,
+__device__ __forceinline__ void sw_first(C2<T>* __restrict__ pre, bool next, Buf nsrc,
                                          uint32_t gbase, uint32_t gstride, uint32_t nmask, bool act,
                                          char* __restrict__ lds, uint32_t wbase, uint32_t ncolpE) {
   if (!act) return;
@@ -171,7 +206,7 @@ __device__ __forceinline__ void sw_mid(char* __restrict__ lds, const char* __res
 // inverse last stage (radix R = f0, p = L/R): LDS -> butterfly -> HBM rows i + q L/R
 template <typename T, int R>
 __device__ __forceinline__ void sw_last_inv(const char* __restrict__ lds, const char* __restrict__ twb, int L, int i,
-                                            uint32_t rbase, uint32_t ncolpE, C2<T>* __restrict__ dst, uint32_t gbase,
+                                            uint32_t rbase, uint32_t ncolpE, Buf dst, uint32_t gbase,
                                             uint32_t gstride, uint32_t vmask, bool act) {
   asm volatile("" : "+v"(i), "+v"(rbase));
   if (!act) return;
@@ -188,7 +223,7 @@ __device__ __forceinline__ void sw_last_inv(const char* __restrict__ lds, const 
   o = gbase;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    if (vmask & (1u << q)) sto(dst, o, v[Dft<T, R>::pos(q)]);
+    bst<T>(dst, (vmask & (1u << q)) ? o : kOob, v[Dft<T, R>::pos(q)]);
     o += gstride;
   }
 }
@@ -241,8 +276,12 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
   auto rad = [&](int s) -> int { return FX ? PD.r[s] : srad(a, s); };
   const int ncol = a.ncol;
   const uint32_t ncolpE = (uint32_t)(ncol + 1) * E;
+  // FP32 keeps the x half-voxel phases in LDS beside the twiddles; FP64 (whose tiles are
+  // twice as large, and whose registers are full) reads them from the cached table
+  constexpr bool PH_LDS = sizeof(T) == 4;
   char* twb = smem_raw;                                    // L twiddles
-  char* lds = smem_raw + (size_t)L * E;                    // [L][ncol + 1] tile
+  char* phb = smem_raw + (size_t)L * E;                    // L x phases (FP32)
+  char* lds = smem_raw + (size_t)(PH_LDS ? 2 : 1) * L * E; // [L][ncol + 1] tile
   uint8_t* sflag = reinterpret_cast<uint8_t*>(lds + (size_t)L * ncolpE);   // plane flags of the 3 axes
   const int tid = threadIdx.x;
   const int i = fdiv(tid, 1.0f / (float)ncol), c = tid - i * ncol;   // column fastest
@@ -255,13 +294,20 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
   const int yflip = ky > a.My / 2;
   const int kyp = yflip ? a.My - ky : ky;
   const uint32_t rowb = (uint32_t)ncols * E;   // bytes between x rows
+  const uint32_t slab = (uint32_t)a.n1x * rowb;  // bytes of one (component, rhs) slab
+  const uint32_t pairb = (uint32_t)a.pair_stride * (uint32_t)sizeof(T);
   const int r0 = rad(0);
   const int LR0 = L / r0;
   const bool act0 = i < LR0;                   // owns a butterfly of the first / last stage
-  for (int t = tid; t < L; t += blockDim.x) reinterpret_cast<C2<T>*>(twb)[t] = twg[t];
+  for (int t = tid; t < L; t += blockDim.x) {
+    reinterpret_cast<C2<T>*>(twb)[t] = twg[t];
+    if (PH_LDS) reinterpret_cast<C2<T>*>(phb)[t] = phx[t];
+  }
   for (int t = tid; t < 3 * a.n1x; t += blockDim.x) sflag[t] = pflag[t];
-  __syncthreads();
   const C2<T> phy_t = phy[ky], phz_t = phz[kz];
+  // half-voxel phase along x of the thread's frequency kx = i + m tl
+  auto phase_x = [&](int m) -> C2<T> { return PH_LDS ? lds_ld<T>(phb, (uint32_t)(i + m * tl) * E) : phx[i + m * tl]; };
+  __syncthreads();
 
   // per-thread geometry: LDS bases, HBM bases and strides of the first / last stage
   const uint32_t cE = (uint32_t)c * E;
@@ -289,7 +335,7 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
   C2<T> q[NIN][RS];
   C2<T> pre[RMAX];   // staged first-stage inputs of the component about to be transformed
   if (S > 1) {
-#define VC_CALL(RR) sw_load<T, RR>(pre, Fin + rhs * a.rhs_stride, gbase, gstride, vm(0, NIN == 3 ? 3 : 1), act0);
+#define VC_CALL(RR) sw_load<T, RR>(pre, make_buf(Fin + rhs * a.rhs_stride, slab), gbase, gstride, vm(0, NIN == 3 ? 3 : 1), act0);
     VC_SW_SWITCH(r0, VC_CALL, RMAX)
 #undef VC_CALL
   }
@@ -297,7 +343,7 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
   for (int b = 0; b < NIN; ++b) {
     const int fax = b % 3;
     const int fmsk = NIN == 3 ? 3 : (b < 3 ? 1 : 2);
-    const C2<T>* src = Fin + b * a.comp_stride + rhs * a.rhs_stride;
+    const Buf src = make_buf(Fin + b * a.comp_stride + rhs * a.rhs_stride, slab);
     C2<T> v[RS];
     if (S == 1) {
       if (valid) {
@@ -305,8 +351,7 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
         uint32_t o = gbase;
 #pragma unroll
         for (int m = 0; m < RS; ++m) {
-          v[m] = C2<T>{T(0), T(0)};
-          if (msk & (1u << m)) v[m] = ldo(src, o);
+          v[m] = bld<T>(src, (msk & (1u << m)) ? o : kOob);
           o += rowb;
         }
         Dft<T, RS>::run(v, T(-1));
@@ -315,7 +360,7 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
       if (b > 0) __syncthreads();   // readers of the previous component are done with the tile
       const int bn = b + 1;
       const bool next = bn < NIN;
-      const C2<T>* nsrc = src + a.comp_stride;
+      const Buf nsrc = make_buf(Fin + bn * a.comp_stride + rhs * a.rhs_stride, slab);
       const uint32_t nmask = vm(bn % 3, NIN == 3 ? 3 : (bn < 3 ? 1 : 2));
       {
         uint32_t wbase = (uint32_t)i * (uint32_t)r0 * ncolpE + cE;
@@ -355,7 +400,8 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
       const C2<T> phyz = csel(fax == 1, phy_t, phz_t);
       C2<T> w[RS];
 #pragma unroll
-      for (int m = 0; m < RS; ++m) w[m] = cmul(v[Dft<T, RS>::pos(m)], fax == 0 ? phx[i + m * tl] : phyz);
+      for (int m = 0; m < RS; ++m)
+        w[m] = cmul(v[Dft<T, RS>::pos(m)], fax == 0 ? phase_x(m) : phyz);
       // per-element selects keep q in registers (a switch of stores is merged into one
       // dynamically indexed store, which moves q to scratch memory)
 #pragma unroll
@@ -385,11 +431,11 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
     for (int b = 0; b < NQ; ++b) {
       const int qi = sw_pair<NIN>(o, b);
       const unsigned odd = (unsigned)(a.oddmask >> (3 * qi)) & 7u;
-      const T* base = R + (int64_t)qi * a.pair_stride;
+      const Buf base = make_buf(R + (int64_t)qi * a.pair_stride, pairb);
 #pragma unroll
       for (int m = 0; m < RS; ++m) {
         const uint32_t sg = ((odd & 1u) ? xs[m] : 0u) ^ ((odd & 2u) ? ys : 0u);
-        rv[b][m] = flip(ldo(base, roff[m]), sg);
+        rv[b][m] = flip(bld1<T>(base, roff[m]), sg);
       }
     }
   };
@@ -425,12 +471,12 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
           acc.y -= accE.x;
         }
         // output phase: conj of the half-voxel shift of the output component
-        z[m] = cmul(acc, cconj(oax == 0 ? phx[i + m * tl] : phyz));
+        z[m] = cmul(acc, cconj(oax == 0 ? phase_x(m) : phyz));
       }
       if (o + 1 < NOUT) load_spectra(o + 1);
     }
     const int msk = NIN == 3 ? (o < 3 ? 1 : 2) : 3;
-    C2<T>* dst = Fout + o * a.comp_stride + rhs * a.rhs_stride;
+    const Buf dst = make_buf(Fout + o * a.comp_stride + rhs * a.rhs_stride, slab);
     const uint32_t omask = vm(oax, msk);
     if (S == 1) {
       if (valid) {
@@ -438,7 +484,7 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
         uint32_t og = gbase;
 #pragma unroll
         for (int m = 0; m < RS; ++m) {
-          if (omask & (1u << m)) sto(dst, og, z[Dft<T, RS>::pos(m)]);
+          bst<T>(dst, (omask & (1u << m)) ? og : kOob, z[Dft<T, RS>::pos(m)]);
           og += rowb;
         }
       }

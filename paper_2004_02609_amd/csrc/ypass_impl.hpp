@@ -78,7 +78,9 @@ k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const 
   const int col = blockIdx.x * ncol + c;
   const bool colok = col < a.ncols;
   const int colc = colok ? col : a.ncols - 1;
-  C2<T>* base = data + comp * a.comp_stride + rhs * a.rhs_stride + plane * a.plane_stride;
+  // buffer view of this (component, rhs, plane) slab: masked rows read zero / write nothing
+  const Buf base = make_buf(data + comp * a.comp_stride + rhs * a.rhs_stride + plane * a.plane_stride,
+                            (uint32_t)a.plane_stride * E);
   const uint8_t* lf = lflag ? lflag + ((int64_t)axis * a.n1x + plane) * a.n1y : nullptr;
   const uint32_t rowb = (uint32_t)a.row_stride * E;
   const int r0 = rad(0);
@@ -110,15 +112,14 @@ k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const 
       uint32_t o = gbase;
 #pragma unroll
       for (int m = 0; m < RS; ++m) {
-        v[m] = C2<T>{T(0), T(0)};
-        if (inmask & (1u << m)) v[m] = ldo(base, o);
+        v[m] = bld<T>(base, (inmask & (1u << m)) ? o : kOob);
         o += rowb;
       }
       Dft<T, RS>::run(v, sg);
       o = gbase;
 #pragma unroll
       for (int m = 0; m < RS; ++m) {
-        if (outmask & (1u << m)) sto(base, o, v[Dft<T, RS>::pos(m)]);
+        bst<T>(base, (outmask & (1u << m)) ? o : kOob, v[Dft<T, RS>::pos(m)]);
         o += rowb;
       }
     }
@@ -167,7 +168,7 @@ k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const 
     const uint32_t gs = (uint32_t)tl * rowb;
 #pragma unroll
     for (int m = 0; m < RS; ++m) {
-      if (outmask & (1u << m)) sto(base, og, v[Dft<T, RS>::pos(m)]);
+      bst<T>(base, (outmask & (1u << m)) ? og : kOob, v[Dft<T, RS>::pos(m)]);
       og += gs;
     }
   }
@@ -228,8 +229,9 @@ hipError_t launch_ypass(void* data, const YArgs& a, const void* tw, const uint8_
   if (lflag)
     for (int q = 0; q < a.cs.n; ++q)
       if ((a.cs.min_[q] && a.nin > a.n1y) || (a.cs.mout[q] && a.nout > a.n1y)) return hipErrorInvalidValue;
-  // 32-bit byte offsets inside one (component, rhs, plane) slab
-  if ((uint64_t)a.plane_stride * sizeof(C2<T>) >= ((uint64_t)1 << 32)) return hipErrorInvalidValue;
+  // 32-bit byte offsets inside one (component, rhs, plane) slab, small enough for the
+  // out-of-range offset of the buffer views (0xFFFFFFF0)
+  if ((uint64_t)a.plane_stride * sizeof(C2<T>) > 0xFFFFFF00ull) return hipErrorInvalidValue;
   const size_t lds = (size_t)sizeof(C2<T>) * ((size_t)a.L + (size_t)a.L * (a.ncol + 1));
   if (lds > lds_ext_budget()) return hipErrorInvalidValue;
   dim3 grid((a.ncols + a.ncol - 1) / a.ncol, nplanes, a.cs.n * a.nrhs);
