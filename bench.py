@@ -314,19 +314,20 @@ def main():
     x = torch.randn(B, N, dtype=torch.float64, device=dev, generator=g)
     y = torch.empty_like(x)
 
-    def run(prec, steps, warm, level):
-        # level 2: HIP events around the x pass only (the timed run); level 1: around
-        # every pass (the breakdown run); each event adds a few us between launches
+    def run(prec, steps, warm, level, every=1):
+        # level 2: HIP events around the x pass only (the timed run, on every `every`-th
+        # step: each event adds a few us between the launches it separates); level 1:
+        # around every pass (the breakdown run)
         for _ in range(warm):
             P.apply(x, y, prec=prec, stream=stream)
         torch.cuda.synchronize()
         P.pass_times()                       # drop anything recorded before
-        P.profile(level)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(stream)
-        for _ in range(steps):
+        for k in range(steps):
+            P.profile(level if k % every == 0 else 0)
             P.apply(x, y, prec=prec, stream=stream)
         e1.record(stream)
         torch.cuda.synchronize()
@@ -335,7 +336,8 @@ def main():
         return ms, P.pass_times()
 
     print(f"# {args.config}: N={N} m={B} fft={P.fft_size()} setup {t_setup:.2f}s", file=sys.stderr, flush=True)
-    ms, (pms, pcnt, pbytes) = run(args.prec, args.steps, args.warmup, 2)
+    every = max(1, min(10, args.steps // 10))
+    ms, (pms, pcnt, pbytes) = run(args.prec, args.steps, args.warmup, 2, every)
     value = args.steps * B / (ms / 1e3)
     # per-pass breakdown: a separate, shorter run with events around every pass
     _, (bms, bcnt, bbytes) = run(args.prec, max(10, min(args.steps, 50)), 2, 1)
@@ -364,7 +366,8 @@ def main():
                 "peak": VEC_PEAK_TFLOPS[args.prec], "unit": "TFLOP/s", "frac": x_tflops / VEC_PEAK_TFLOPS[args.prec],
                 "traffic": x_traffic, "alg_flops": x_flops, "alg_bytes": pbytes[xi], "avg_us": x_ms * 1e3,
                 "hbm_achieved_GBs": pbytes[xi] / (x_ms / 1e3) / 1e9,
-                "hbm_frac": pbytes[xi] / (x_ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+                "hbm_frac": pbytes[xi] / (x_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                "timed_launches": pcnt[xi], "event_sampling": f"every {every}th of the {args.steps} timed steps"}
     passes = {voxcap.PASS_NAMES[i]: {"avg_us": bms[i] / max(1, bcnt[i]) * 1e3, "launches": bcnt[i],
                                      "alg_bytes": bbytes[i],
                                      "alg_GBs": bbytes[i] / (bms[i] / max(1, bcnt[i]) / 1e3) / 1e9

@@ -20,6 +20,29 @@ namespace vc {
 
 template <typename T> __device__ __forceinline__ C2<T> ld(const C2<T>* p) { return *p; }
 
+// Panels of one tile of z lines.  Items are the lines holding panels in line order and
+// line_ptr is the panels' CSR over all lines, so the panels of the tile's consecutive
+// items form one contiguous range; lp[c] is the first panel of tile column c and lp[nc]
+// one past the last.  Returns nc (columns of this tile, >= 1 whenever item0 < nitems).
+__device__ __forceinline__ int tile_panels(const int32_t* __restrict__ items, const int32_t* __restrict__ line_ptr,
+                                           int item0, int nitems, int ncol, int* lp) {
+  const int nc = min(ncol, nitems - item0);
+  const int tid = threadIdx.x;
+  if (nc > 0 && tid <= nc)
+    lp[tid] = tid < nc ? line_ptr[items[item0 + tid]] : line_ptr[items[item0 + nc - 1] + 1];
+  __syncthreads();
+  return nc;
+}
+// tile column of panel p: the last c < nc with lp[c] <= p (every line of the tile holds
+// a panel, so lp is strictly increasing); nc <= 32
+__device__ __forceinline__ int panel_col(const int* lp, int nc, int p) {
+  int c = 0;
+#pragma unroll
+  for (int st = 16; st > 0; st >>= 1)
+    if (c + st < nc && lp[c + st] <= p) c += st;
+  return c;
+}
+
 // ------------------------------------------------------------------------------ z forward
 // Tiles hold 2^lgc lines; divisions by non-powers of two use fdiv (exact in range).
 // Workgroup (bx, by): lines bx*ncol .. of the item list, right-hand side(s) by (two per
@@ -47,28 +70,25 @@ __device__ __forceinline__ void zfwd_body(const ZScene& a, int mode, const doubl
   C2<T>* buf = tw + L;
   C2<T>* buf2 = buf + L * ncolp;
   const int tid = threadIdx.x, nthr = blockDim.x;
+  __shared__ int lp[33];
   for (int t = tid; t < L; t += nthr) tw[t] = twg[t];
   for (int e = tid; e < L * ncolp; e += nthr) buf[e] = C2<T>{T(0), T(0)};
-  __syncthreads();
   const int item0 = bx * ncol;
-  for (int c = 0; c < ncol; ++c) {
-    const int it = item0 + c;
-    if (it >= nitems) break;
-    const int line = items[it];
-    const int p0 = line_ptr[line], p1 = line_ptr[line + 1];
-    for (int p = p0 + tid; p < p1; p += nthr) {
-      const int k = pk[p];
-      double re, im;
-      if (mode == 0) {
-        re = x[(int64_t)ra * ldx + p];
-        im = (rb < nrhs) ? x[(int64_t)rb * ldx + p] : 0.0;
-      } else {
-        const double v = x[(int64_t)ra * ldx + p];
-        re = pkind[p] == 0 ? v : 0.0;
-        im = pkind[p] == 0 ? 0.0 : v;
-      }
-      buf[k * ncolp + c] = C2<T>{T(re), T(im)};
+  const int nc = tile_panels(items, line_ptr, item0, nitems, ncol, lp);   // (synchronises)
+  // scatter: all threads over the tile's panels at once
+  for (int p = (nc > 0 ? lp[0] : 0) + tid; nc > 0 && p < lp[nc]; p += nthr) {
+    const int c = panel_col(lp, nc, p);
+    const int k = pk[p];
+    double re, im;
+    if (mode == 0) {
+      re = x[(int64_t)ra * ldx + p];
+      im = (rb < nrhs) ? x[(int64_t)rb * ldx + p] : 0.0;
+    } else {
+      const double v = x[(int64_t)ra * ldx + p];
+      re = pkind[p] == 0 ? v : 0.0;
+      im = pkind[p] == 0 ? 0.0 : v;
     }
+    buf[k * ncolp + c] = C2<T>{T(re), T(im)};
   }
   __syncthreads();
   const C2<T>* res = lds_fft<T, Tune<T>::maxr>(buf, buf2, tw, pl, lgc, ncolp, false);
@@ -220,8 +240,10 @@ __device__ __forceinline__ void zinv_body(const ZScene& a, int mode, const doubl
   C2<T>* buf = tw + L;
   C2<T>* buf2 = buf + L * ncolp;
   const int tid = threadIdx.x, nthr = blockDim.x;
+  __shared__ int lp[33];
   for (int t = tid; t < L; t += nthr) tw[t] = twg[t];
   const int item0 = bx * ncol;
+  const int nc = tile_panels(items, line_ptr, item0, nitems, ncol, lp);   // (synchronises)
   const int plane = n1x * n1y;
   const float invH = 1.0f / (float)H, invPl = 1.0f / (float)plane, invN1y = 1.0f / (float)n1y;
   for (int e = tid; e < H * ncol; e += nthr) {
@@ -249,24 +271,20 @@ __device__ __forceinline__ void zinv_body(const ZScene& a, int mode, const doubl
   }
   __syncthreads();
   const C2<T>* res = lds_fft<T, Tune<T>::maxr>(buf, buf2, tw, pl, lgc, ncolp, true);
-  for (int c = 0; c < ncol; ++c) {
-    const int it = item0 + c;
-    if (it >= nitems) break;
-    const int line = items[it];
-    const int p0 = line_ptr[line], p1 = line_ptr[line + 1];
-    for (int p = p0 + tid; p < p1; p += nthr) {
-      const C2<T> Z = res[pk[p] * ncolp + c];
-      const double dg = diag[p];
-      if (mode == 0) {
-        const int64_t o = (int64_t)ra * ldx + p;
-        y[o] = pkind[p] == 0 ? double(Z.x) : double(Z.y) + dg * x[o];
-      } else {
-        const int64_t oa = (int64_t)ra * ldx + p;
-        y[oa] = double(Z.x) + dg * x[oa];
-        if (rb < nrhs) {
-          const int64_t ob = (int64_t)rb * ldx + p;
-          y[ob] = double(Z.y) + dg * x[ob];
-        }
+  // gather: all threads over the tile's panels at once
+  for (int p = (nc > 0 ? lp[0] : 0) + tid; nc > 0 && p < lp[nc]; p += nthr) {
+    const int c = panel_col(lp, nc, p);
+    const C2<T> Z = res[pk[p] * ncolp + c];
+    const double dg = diag[p];
+    if (mode == 0) {
+      const int64_t o = (int64_t)ra * ldx + p;
+      y[o] = pkind[p] == 0 ? double(Z.x) : double(Z.y) + dg * x[o];
+    } else {
+      const int64_t oa = (int64_t)ra * ldx + p;
+      y[oa] = double(Z.x) + dg * x[oa];
+      if (rb < nrhs) {
+        const int64_t ob = (int64_t)rb * ldx + p;
+        y[ob] = double(Z.y) + dg * x[ob];
       }
     }
   }
@@ -324,6 +342,7 @@ hipError_t launch_zfwd(const double* x, int64_t N, int nrhs, int mode, const int
                        int64_t rhs_stride, int n1x, int n1y, int My, int H, const AxisPlan& pl, const void* tw, int ncol,
                        int nthr, const int* skip, hipStream_t st, const int* act) {
   if (nitems == 0) return hipSuccess;
+  if (ncol < 1 || ncol > 32 || (ncol & (ncol - 1)) || nthr < 64) return hipErrorInvalidValue;   // tile of <= 32 lines
   ZScene a{};
   a.items = items; a.line_ptr = line_ptr; a.pk = pk; a.pkind = pkind; a.F = F; a.tw = tw; a.pl = pl;
   a.comp_stride = comp_stride; a.rhs_stride = rhs_stride;
@@ -399,6 +418,7 @@ hipError_t launch_zinv(const void* O, double* y, const double* x, int64_t N, int
                        int n1y, int My, int H, const AxisPlan& pl, const void* tw, int ncol, int nthr,
                        const int* skip, hipStream_t st, const int* act) {
   if (nitems == 0) return hipSuccess;
+  if (ncol < 1 || ncol > 32 || (ncol & (ncol - 1)) || nthr < 64) return hipErrorInvalidValue;   // tile of <= 32 lines
   ZScene a{};
   a.items = items; a.line_ptr = line_ptr; a.pk = pk; a.pkind = pkind; a.diag = diag; a.lflag = lflag;
   a.F = const_cast<void*>(O); a.tw = tw; a.pl = pl;
