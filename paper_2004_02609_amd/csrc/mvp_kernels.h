@@ -269,6 +269,8 @@ hipError_t launch_cgs_step(const double* V, int64_t ldv, int64_t N, int k, doubl
                            double* sn, double* g, const double* bn, const double* rtol, int* act_step, int* kd,
                            int* iters, double* scal, int* skip, int* bad, double* nrm_out, hipStream_t st);
 int64_t cgs_counter_size_a(int kmax, int nrhs);
+// partials of the Gram-Schmidt launches (doubles), k <= kmax basis vectors
+int64_t cgs_partial_size(int64_t N, int kmax, int nrhs);
 int64_t cgs_counter_size(int kmax, int nrhs);
 hipError_t launch_backsolve(int nrhs, int m, const double* H, const double* g, const int* kd, const int* act_cycle,
                             double* y, int ldy, hipStream_t st);

@@ -37,7 +37,8 @@ vc_status ensure_workspace(vc_problem* P, int nrhs, int restart) {
   VC_HIP(P->s_dd.alloc((size_t)k * N * sizeof(double)));
   VC_HIP(P->s_h.alloc((size_t)2 * (r + 2) * k * sizeof(double)));
   VC_HIP(P->s_y2.alloc((size_t)(r + 2) * k * sizeof(double)));
-  VC_HIP(P->s_partial.alloc((size_t)std::max(gemv_t_partial_size(N, r + 2, k), colnorm_partial_size(N, k)) *
+  VC_HIP(P->s_partial.alloc((size_t)std::max({gemv_t_partial_size(N, r + 2, k), colnorm_partial_size(N, k),
+                                               cgs_partial_size(N, r + 1, k)}) *
                             sizeof(double)));
   VC_HIP(P->s_norm.alloc((size_t)4 * k * sizeof(double)));
   VC_HIP(P->s_active.alloc((size_t)k * sizeof(int)));

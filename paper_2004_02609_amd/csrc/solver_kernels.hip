@@ -223,9 +223,13 @@ hipError_t launch_diag_scale(const double* x, double* y, const double* dinv, int
 
 // Conductor rows of eq. (14): for each box, y_box = Binv x_box with the box's (shared,
 // de-duplicated) inverse block, stored transposed.  One workgroup per box; x_box staged
-// in LDS.
-constexpr int kBoxThreads = 256;
+// in LDS.  When the box has fewer panels than the workgroup has threads, G = threads / nb
+// groups of threads each sum every G-th column of the block for all staged right-hand
+// sides (each block entry loaded once per pass), and the groups' sums are added in a
+// fixed order through LDS.
+constexpr int kBoxThreads = 512;
 constexpr int kBoxLds = 4096;   // doubles of x_box staged per pass
+constexpr int kBoxRB = 4;       // right-hand sides per accumulation sweep
 __global__ void __launch_bounds__(kBoxThreads)
 k_block_apply(const double* __restrict__ x, double* __restrict__ y, int64_t N, int nrhs,
               const int32_t* __restrict__ box_ptr, const int32_t* __restrict__ box_panels,
@@ -234,6 +238,7 @@ k_block_apply(const double* __restrict__ x, double* __restrict__ y, int64_t N, i
               const int32_t* __restrict__ box_c0, const int32_t* __restrict__ box_nc, int trans) {
   if (skip && *skip) return;
   __shared__ double xs[kBoxLds];
+  __shared__ double red[kBoxRB * kBoxThreads];
   const int box = blockIdx.x;
   if (box_c0) {   // the box belongs to one problem of a packed set: its own columns only
     const int64_t o = (int64_t)box_c0[box] * N;
@@ -246,25 +251,58 @@ k_block_apply(const double* __restrict__ x, double* __restrict__ y, int64_t N, i
   const int blk = box_block[box];
   const double* B = blocks + block_off[blk];
   const int rpp = kBoxLds / nb;   // right-hand sides per pass (nb <= kBoxLds guaranteed by the host)
+  const int t = threadIdx.x;
+  const int G = nb < kBoxThreads ? kBoxThreads / nb : 1;
+  // the block is stored transposed: B^T[j][i] = Binv[i][j] (lanes, consecutive i, read
+  // consecutive addresses); the transposed apply reads B^T[i][j]
+  const int64_t sj = trans ? 1 : nb, si = trans ? nb : 1;
   for (int r0 = 0; r0 < nrhs; r0 += rpp) {
     const int rn = (nrhs - r0) < rpp ? (nrhs - r0) : rpp;
     __syncthreads();
-    for (int e = threadIdx.x; e < rn * nb; e += blockDim.x) {
+    for (int e = t; e < rn * nb; e += blockDim.x) {
       const int r = e / nb, j = e - r * nb;
       xs[e] = x[(int64_t)(r0 + r) * N + box_panels[p0 + j]];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < rn * nb; e += blockDim.x) {
-      const int r = e / nb, i = e - r * nb;
-      const double* xr = xs + r * nb;
-      double acc = 0.0;
-      // the block is stored transposed: B^T[j][i] = Binv[i][j], lanes (consecutive i)
-      // read consecutive addresses; the transposed apply reads row i of B^T
-      if (!trans)
-        for (int j = 0; j < nb; ++j) acc += B[(int64_t)j * nb + i] * xr[j];
-      else
-        for (int j = 0; j < nb; ++j) acc += B[(int64_t)i * nb + j] * xr[j];
-      y[(int64_t)(r0 + r) * N + box_panels[p0 + i]] = acc;
+    for (int rb = 0; rb < rn; rb += kBoxRB) {
+      const int rbn = rn - rb < kBoxRB ? rn - rb : kBoxRB;
+      for (int i0 = 0; i0 < nb; i0 += (G > 1 ? nb : kBoxThreads)) {
+        const int g = G > 1 ? t / nb : 0;
+        const int i = G > 1 ? t - g * nb : i0 + t;
+        const bool on = G > 1 ? g < G : i < nb;
+        double acc[kBoxRB];
+#pragma unroll
+        for (int q = 0; q < kBoxRB; ++q) acc[q] = 0.0;
+        if (on) {
+          const double* bi = B + (int64_t)i * si;
+          const double* xr = xs + rb * nb;
+#pragma unroll 4
+          for (int j = g; j < nb; j += G) {
+            const double bv = bi[(int64_t)j * sj];
+#pragma unroll
+            for (int q = 0; q < kBoxRB; ++q)
+              if (q < rbn) acc[q] += bv * xr[q * nb + j];
+          }
+        }
+        if (G == 1) {
+          if (on)
+#pragma unroll
+            for (int q = 0; q < kBoxRB; ++q)
+              if (q < rbn) y[(int64_t)(r0 + rb + q) * N + box_panels[p0 + i]] = acc[q];
+        } else {
+          if (on)
+#pragma unroll
+            for (int q = 0; q < kBoxRB; ++q) red[(q * G + g) * nb + i] = acc[q];
+          __syncthreads();
+          for (int e = t; e < rbn * nb; e += blockDim.x) {
+            const int q = e / nb, ii = e - q * nb;
+            double v = 0.0;
+            for (int gg = 0; gg < G; ++gg) v += red[(q * G + gg) * nb + ii];
+            y[(int64_t)(r0 + rb + q) * N + box_panels[p0 + ii]] = v;
+          }
+          __syncthreads();
+        }
+      }
     }
   }
   (void)block_n;
@@ -587,6 +625,46 @@ hipError_t launch_grad_eps(const int32_t* bptr, const int32_t* ek, const int32_t
 
 
 // ------------------------------------------------------------------ fused Gram-Schmidt step
+// Rows per partial sum of the three launches below: about 1024 workgroups per launch
+// over all columns, at least one row per thread (so a small system still spreads over
+// the chip instead of a few long per-thread loops).
+static int64_t cgs_chunk(int64_t N, int nrhs) {
+  int64_t c = (N * (int64_t)nrhs + 1023) / 1024;
+  c = (c + kRedThreads - 1) / kRedThreads * kRedThreads;
+  return c > kRedThreads ? c : kRedThreads;
+}
+int64_t cgs_partial_size(int64_t N, int kmax, int nrhs) {
+  return ((N + kRedThreads - 1) / kRedThreads) * (int64_t)nrhs * kmax;
+}
+// Sum over c < nchunk of part[c * stride + q * qstride] for q < nq (nq <= kDotBlk), by
+// every thread of the block in a fixed order (thread strides, then waves, then LDS
+// slots), so the result does not depend on timing.  Result valid in thread 0..nq-1 as
+// out[q] written by thread q.
+__device__ __forceinline__ void block_sum_chunks(const double* __restrict__ part, int nchunk, int64_t stride,
+                                                 int64_t qstride, int nq, double (*red)[kRedThreads / 64],
+                                                 double* __restrict__ out, int64_t out_stride) {
+  double acc[kDotBlk];
+#pragma unroll
+  for (int q = 0; q < kDotBlk; ++q) acc[q] = 0.0;
+  for (int c = threadIdx.x; c < nchunk; c += blockDim.x)
+#pragma unroll
+    for (int q = 0; q < kDotBlk; ++q)
+      if (q < nq) acc[q] += part[(int64_t)c * stride + q * qstride];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();   // red may still be read by a previous use
+#pragma unroll
+  for (int q = 0; q < kDotBlk; ++q) {
+    const double t = wave_sum(acc[q]);
+    if (lane == 0) red[q][wv] = t;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nq) {
+    double t = 0.0;
+    for (int u = 0; u < (int)(blockDim.x >> 6); ++u) t += red[threadIdx.x][u];
+    out[threadIdx.x * out_stride] = t;
+  }
+}
+
 // One Arnoldi step's classical Gram-Schmidt (applied twice) and norm in three launches:
 //   A  h1 = V^T w                          (partials, the last block of each
 //                                           (vector block, column) adds the chunks)
@@ -611,17 +689,17 @@ __device__ __forceinline__ bool last_block(unsigned* cnt, unsigned total, int* f
 }
 
 __global__ void __launch_bounds__(kRedThreads)
-k_cgs_dot(const double* __restrict__ V, int64_t ldv, int64_t N, int k, const double* __restrict__ w, int nrhs,
-          double* __restrict__ h, int64_t ldh, double* __restrict__ partial, const int* __restrict__ active,
-          unsigned* __restrict__ cnt) {
+k_cgs_dot(const double* __restrict__ V, int64_t ldv, int64_t N, int64_t chunk_rows, int k,
+          const double* __restrict__ w, int nrhs, double* __restrict__ h, int64_t ldh, double* __restrict__ partial,
+          const int* __restrict__ active, unsigned* __restrict__ cnt) {
   __shared__ double red[kDotBlk][kRedThreads / 64];
   __shared__ int flag;
   const int chunk = blockIdx.x, kb = blockIdx.y, r = blockIdx.z, nchunk = gridDim.x;
   if (active && !active[r]) return;   // every block of this column returns: its count stays 0
   const int i0 = kb * kDotBlk;
   const int nb = k - i0 < kDotBlk ? k - i0 : kDotBlk;
-  const int64_t n0 = (int64_t)chunk * kDotChunk;
-  const int64_t n1 = n0 + kDotChunk < N ? n0 + kDotChunk : N;
+  const int64_t n0 = (int64_t)chunk * chunk_rows;
+  const int64_t n1 = n0 + chunk_rows < N ? n0 + chunk_rows : N;
   const double* wr = w + (int64_t)r * N;
   const double* v0 = V + (int64_t)i0 * ldv + (int64_t)r * N;
   double acc[kDotBlk];
@@ -645,23 +723,22 @@ k_cgs_dot(const double* __restrict__ V, int64_t ldv, int64_t N, int k, const dou
     for (int u = 0; u < (int)(blockDim.x >> 6); ++u) t += red[threadIdx.x][u];
     partial[((int64_t)chunk * nrhs + r) * k + i0 + threadIdx.x] = t;
   }
-  if (last_block(cnt + (int64_t)kb * nrhs + r, (unsigned)nchunk, &flag) && (int)threadIdx.x < nb) {
-    double t = 0.0;
-    for (int c = 0; c < nchunk; ++c) t += partial[((int64_t)c * nrhs + r) * k + i0 + threadIdx.x];
-    h[(int64_t)r * ldh + i0 + threadIdx.x] = t;
-  }
+  if (last_block(cnt + (int64_t)kb * nrhs + r, (unsigned)nchunk, &flag))
+    block_sum_chunks(partial + (int64_t)r * k + i0, nchunk, (int64_t)nrhs * k, 1, nb, red, h + (int64_t)r * ldh + i0,
+                     1);
 }
 
 __global__ void __launch_bounds__(kRedThreads)
-k_cgs_update_dot(const double* __restrict__ V, int64_t ldv, int64_t N, int k, const double* __restrict__ h1,
-                 int64_t ldh, double* __restrict__ w, int nrhs, double* __restrict__ h2, double* __restrict__ partial,
-                 const int* __restrict__ active, unsigned* __restrict__ cnt) {
+k_cgs_update_dot(const double* __restrict__ V, int64_t ldv, int64_t N, int64_t chunk_rows, int k,
+                 const double* __restrict__ h1, int64_t ldh, double* __restrict__ w, int nrhs,
+                 double* __restrict__ h2, double* __restrict__ partial, const int* __restrict__ active,
+                 unsigned* __restrict__ cnt) {
   __shared__ double red[kDotBlk][kRedThreads / 64];
   __shared__ int flag;
   const int chunk = blockIdx.x, r = blockIdx.y, nchunk = gridDim.x;
   if (active && !active[r]) return;
-  const int64_t n0 = (int64_t)chunk * kDotChunk;
-  const int64_t n1 = n0 + kDotChunk < N ? n0 + kDotChunk : N;
+  const int64_t n0 = (int64_t)chunk * chunk_rows;
+  const int64_t n1 = n0 + chunk_rows < N ? n0 + chunk_rows : N;
   double* wr = w + (int64_t)r * N;
   const double* vr = V + (int64_t)r * N;
   const double* hr = h1 + (int64_t)r * ldh;
@@ -697,15 +774,14 @@ k_cgs_update_dot(const double* __restrict__ V, int64_t ldv, int64_t N, int k, co
     __syncthreads();
   }
   if (last_block(cnt + r, (unsigned)nchunk, &flag))
-    for (int i = threadIdx.x; i < k; i += blockDim.x) {
-      double t = 0.0;
-      for (int c = 0; c < nchunk; ++c) t += partial[((int64_t)c * nrhs + r) * k + i];
-      h2[(int64_t)r * ldh + i] = t;
-    }
+    for (int i0 = 0; i0 < k; i0 += kDotBlk)
+      block_sum_chunks(partial + (int64_t)r * k + i0, nchunk, (int64_t)nrhs * k, 1,
+                       k - i0 < kDotBlk ? k - i0 : kDotBlk, red, h2 + (int64_t)r * ldh + i0, 1);
 }
 
 __global__ void __launch_bounds__(kRedThreads)
-k_cgs_update_norm_step(const double* __restrict__ V, int64_t ldv, int64_t N, int k, const double* __restrict__ h1,
+k_cgs_update_norm_step(const double* __restrict__ V, int64_t ldv, int64_t N, int64_t chunk_rows, int k,
+                       const double* __restrict__ h1,
                        const double* __restrict__ h2, int64_t ldh, double* __restrict__ w, int nrhs,
                        double* __restrict__ partial, unsigned* __restrict__ cnt, int j, int m, double* __restrict__ H,
                        double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
@@ -717,8 +793,8 @@ k_cgs_update_norm_step(const double* __restrict__ V, int64_t ldv, int64_t N, int
   __shared__ int flag;
   const int chunk = blockIdx.x, r = blockIdx.y, nchunk = gridDim.x;
   if (act_step[r]) {
-    const int64_t n0 = (int64_t)chunk * kDotChunk;
-    const int64_t n1 = n0 + kDotChunk < N ? n0 + kDotChunk : N;
+    const int64_t n0 = (int64_t)chunk * chunk_rows;
+    const int64_t n1 = n0 + chunk_rows < N ? n0 + chunk_rows : N;
     double* wr = w + (int64_t)r * N;
     const double* vr = V + (int64_t)r * N;
     const double* hr = h2 + (int64_t)r * ldh;
@@ -758,16 +834,17 @@ hipError_t launch_cgs_step(const double* V, int64_t ldv, int64_t N, int k, doubl
                            double* sn, double* g, const double* bn, const double* rtol, int* act_step, int* kd,
                            int* iters, double* scal, int* skip, int* bad, double* nrm_out, hipStream_t st) {
   if (nrhs > kRedThreads || k <= 0) return hipErrorInvalidValue;
-  const int nchunk = (int)((N + kDotChunk - 1) / kDotChunk);
+  const int64_t rows = cgs_chunk(N, nrhs);
+  const int nchunk = (int)((N + rows - 1) / rows);
   const int nkb = (k + kDotBlk - 1) / kDotBlk;
   unsigned* cA = cnt;                                  // [nkb][nrhs]
   unsigned* cB = cnt + cgs_counter_size_a(k, nrhs);    // [nrhs]
   unsigned* cC = cB + nrhs;                            // [1]
-  hipLaunchKernelGGL(k_cgs_dot, dim3(nchunk, nkb, nrhs), dim3(kRedThreads), 0, st, V, ldv, N, k, w, nrhs, h1,
+  hipLaunchKernelGGL(k_cgs_dot, dim3(nchunk, nkb, nrhs), dim3(kRedThreads), 0, st, V, ldv, N, rows, k, w, nrhs, h1,
                      (int64_t)ldh, partial, act_step, cA);
-  hipLaunchKernelGGL(k_cgs_update_dot, dim3(nchunk, nrhs), dim3(kRedThreads), 0, st, V, ldv, N, k, h1, (int64_t)ldh,
-                     w, nrhs, h2, partial, act_step, cB);
-  hipLaunchKernelGGL(k_cgs_update_norm_step, dim3(nchunk, nrhs), dim3(kRedThreads), 0, st, V, ldv, N, k, h1, h2,
+  hipLaunchKernelGGL(k_cgs_update_dot, dim3(nchunk, nrhs), dim3(kRedThreads), 0, st, V, ldv, N, rows, k, h1,
+                     (int64_t)ldh, w, nrhs, h2, partial, act_step, cB);
+  hipLaunchKernelGGL(k_cgs_update_norm_step, dim3(nchunk, nrhs), dim3(kRedThreads), 0, st, V, ldv, N, rows, k, h1, h2,
                      (int64_t)ldh, w, nrhs, partial, cC, j, m, H, cs, sn, g, bn, rtol, act_step, kd, iters, scal,
                      skip, bad, nrm_out);
   return hipGetLastError();
