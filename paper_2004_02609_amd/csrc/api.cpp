@@ -532,9 +532,11 @@ vc_status vc_tuning_report(vc_problem* p, char* buf, int32_t len) {
   }
   for (const auto& kv : p->y_choice) {
     const auto& c = kv.second;
-    std::snprintf(line, sizeof line, "y-pass %s %s%s nrhs=%d kernel=%s %s", (kv.first & 1) ? "fp64" : "fp32",
+    std::snprintf(line, sizeof line, "y-pass %s %s%s nrhs=%d kernel=%s%s %s", (kv.first & 1) ? "fp64" : "fp32",
                   (kv.first & 2) ? "inverse" : "forward", (kv.first & 4) ? " (transposed product)" : "",
-                  kv.first >> 3, c.impl ? "register-edge" : "lds-tiles", c.tuned ? "tuned" : "default");
+                  kv.first >> 3, c.impl ? "register-edge" : "lds-tiles",
+                  (c.impl && c.ncol > 0) ? (" cols=" + std::to_string(c.ncol)).c_str() : "",
+                  c.tuned ? "tuned" : "default");
     out += line;
     if (c.tuned) {
       std::snprintf(line, sizeof line, " lds_ms=%.4f register_ms=%.4f", c.ms[0], c.ms[1]);

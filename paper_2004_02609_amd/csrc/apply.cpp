@@ -186,38 +186,68 @@ static vc_status y_pass(vc_problem* P, PrecTables& tb, void* data, void* scratch
   ya.skip = skip; ya.act = act; ya.cs = cset; ya.nin = nin; ya.nout = nout; ya.inverse = inverse;
   int ythr = 0;
   const bool yok = ypass_config(My, (int)sizeof(T), H, kLdsBudget, &ya, &ythr);
-  auto launch = [&](int impl, void* d) -> hipError_t {
-    if (impl == 1) return launch_ypass<T>(d, ya, tb.ax[1].tw.p, lflag, pflag, n1x, ythr, st);
+  const int ydef = ya.ncol;
+  // register-edge tile of c columns: threads c L/RS rounded up to waves (<= 1024), LDS
+  // twiddles + [L][c + 1] tile within the budget
+  auto ytile = [&](int c, int* thr) -> bool {
+    if (!yok || c < 1 || c > 32 || c > H) return false;
+    const int t = (c * ya.tl + 63) / 64 * 64;
+    if (t > 1024 || (size_t)eb * ((size_t)My + (size_t)My * (c + 1)) > kLdsBudget) return false;
+    *thr = t;
+    return true;
+  };
+  auto launch = [&](int impl, int c, void* d) -> hipError_t {
+    if (impl == 1) {
+      int t = ythr;
+      ya.ncol = c > 0 && ytile(c, &t) ? c : ydef;
+      if (ya.ncol == ydef) t = ythr;
+      return launch_ypass<T>(d, ya, tb.ax[1].tw.p, lflag, pflag, n1x, t, st);
+    }
     return launch_strided<T>(d, sa, cset, n1x, tb.ax[1].plan, tb.ax[1].tw.p, lflag, pflag, nthr, st);
   };
   const int key = (nrhs << 3) | (transpose << 2) | (inverse << 1) | (sizeof(T) == 8 ? 1 : 0);
   auto it = P->y_choice.find(key);
   if (it == P->y_choice.end()) {
-    vc_problem::YChoice ch{(yok && ya.ncol * eb >= 32) ? 1 : 0, false, {0.0, 0.0}};
+    vc_problem::YChoice ch{(yok && ydef * eb >= 32) ? 1 : 0, false, {0.0, 0.0}, 0};
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     VC_HIP(hipStreamIsCapturing(st, &cap));
     if (P->autotune && yok && cap == hipStreamCaptureStatusNone) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       VC_HIP(hipEventCreate(&e0));
       VC_HIP(hipEventCreate(&e1));
-      for (int impl = 0; impl < 2; ++impl) {
-        VC_HIP(launch(impl, scratch));
+      auto timeit = [&](int impl, int c, double* out) -> vc_status {
+        VC_HIP(launch(impl, c, scratch));
         VC_HIP(hipEventRecord(e0, st));
-        for (int rep = 0; rep < 3; ++rep) VC_HIP(launch(impl, scratch));
+        for (int rep = 0; rep < 3; ++rep) VC_HIP(launch(impl, c, scratch));
         VC_HIP(hipEventRecord(e1, st));
         VC_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
         VC_HIP(hipEventElapsedTime(&ms, e0, e1));
-        ch.ms[impl] = ms / 3.0;
+        *out = ms / 3.0;
+        return VC_OK;
+      };
+      vc_status ts = timeit(0, 0, &ch.ms[0]);
+      // the register-edge kernel at the heuristic's width and at power-of-two widths
+      double best = 1e30;
+      int bestc = 0;
+      for (int c : {0, 2, 4, 8, 16, 32}) {
+        int t = 0;
+        if (ts != VC_OK || (c > 0 && (c == ydef || !ytile(c, &t)))) continue;
+        double ms = 0.0;
+        ts = timeit(1, c, &ms);
+        if (ts == VC_OK && ms < best) { best = ms; bestc = c; }
       }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
+      if (ts != VC_OK) return ts;
+      ch.ms[1] = best;
+      ch.ncol = bestc;
       ch.impl = ch.ms[1] < ch.ms[0] ? 1 : 0;
       ch.tuned = true;
     }
     it = P->y_choice.emplace(key, ch).first;
   }
-  VC_HIP(launch(it->second.impl, data));
+  VC_HIP(launch(it->second.impl, it->second.ncol, data));
   return VC_OK;
 }
 

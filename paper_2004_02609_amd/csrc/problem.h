@@ -215,6 +215,7 @@ struct vc_problem {
     int impl;
     bool tuned;
     double ms[2];
+    int ncol;   // register-edge tile width (0: the heuristic's)
   };
   std::map<int, YChoice> y_choice;
   // per-pass timing (measurement)
