@@ -71,17 +71,21 @@ static void pass_byte_model(vc_problem* P, int transpose, int elem, int nrhs, do
 }
 
 // Sandwich launch configurations for one x length: for every register radix RS the
-// plan with the fewest stages, and every column tile (1..32 columns) within 512 threads
-// and the LDS budget that is a power of two or keeps at least 3/4 of the workgroup's
-// lanes busy (tl x ncol of the rounded-up thread count).
+// plan with the fewest stages, and every column tile (1..32 columns) within the kernel's
+// thread limit (512, or 1024 for the wide compiled plans) and the LDS budget that is a
+// power of two or keeps at least 3/4 of the workgroup's lanes busy (tl x ncol of the
+// rounded-up thread count).
 std::vector<SandCfg> sandwich_candidates(int L, int elem, int nin, int n1x, size_t budget) {
   std::vector<SandCfg> out;
   for (int rs = sandwich_rs_max(elem, nin); rs >= 2; --rs) {
     const AxisPlan sp = make_sandwich_plan(L, sandwich_rmax(elem), sandwich_rmid(elem), rs, 512);
     if (sp.nst < 1 || sp.rad[sp.nst - 1] != rs) continue;
     const int tl = L / rs;
+    uint32_t pack = 0;
+    for (int s2 = 0; s2 < sp.nst; ++s2) pack |= (uint32_t)sp.rad[s2] << (5 * s2);
+    const int maxt = sand_max_threads(L, sp.nst, pack, elem, nin);
     for (int c = 1; c <= 32; ++c) {
-      if ((int64_t)c * tl > 512 || sandwich_lds_bytes(L, c, elem, n1x) > budget) break;
+      if ((int64_t)c * tl > maxt || sandwich_lds_bytes(L, c, elem, n1x) > budget) break;
       const int nthr = (c * tl + 63) / 64 * 64;
       const bool pow2 = (c & (c - 1)) == 0;
       if (!pow2 && 4 * c * tl < 3 * nthr) continue;

@@ -97,18 +97,22 @@ constexpr int sandwich_rmid(int elem) { return elem == 4 ? 10 : 10; }
 // count and length as constants (entry 0: the generic kernels, which read them from
 // their arguments).  A launch whose runtime plan equals an entry uses that entry's
 // kernel; every other plan runs the generic one.
+// `wide`: the FP32 three-input x-pass kernel of the plan is compiled for workgroups of up
+// to 1024 threads (its registers fit 128 VGPRs), so long transforms, which need L/RS
+// threads per column, still get several columns per workgroup.
 struct SandFixedPlan {
   int L, nst, r[4];
+  bool wide;
 };
 constexpr SandFixedPlan kSandFixed[] = {
-    {0, 0, {0, 0, 0, 0}},
-    {36, 3, {4, 3, 3, 0}},
-    {140, 3, {7, 5, 4, 0}},
-    {270, 3, {9, 6, 5, 0}},
-    {540, 3, {10, 9, 6, 0}},
-    {540, 4, {10, 6, 3, 3}},
-    {1050, 4, {7, 6, 5, 5}},
-    {36, 2, {6, 6, 0, 0}},
+    {0, 0, {0, 0, 0, 0}, false},
+    {36, 3, {4, 3, 3, 0}, false},
+    {140, 3, {7, 5, 4, 0}, false},
+    {270, 3, {9, 6, 5, 0}, false},
+    {540, 3, {10, 9, 6, 0}, false},
+    {540, 4, {10, 6, 3, 3}, true},
+    {1050, 4, {7, 6, 5, 5}, true},
+    {36, 2, {6, 6, 0, 0}, false},
 };
 constexpr int kSandNumFixed = (int)(sizeof(kSandFixed) / sizeof(kSandFixed[0]));
 constexpr uint32_t sand_fixed_pack(int id) {
@@ -117,6 +121,19 @@ constexpr uint32_t sand_fixed_pack(int id) {
   return p;
 }
 constexpr int sand_fixed_last(int id) { return kSandFixed[id].nst > 0 ? kSandFixed[id].r[kSandFixed[id].nst - 1] : 0; }
+// table entry of a runtime plan (0: none)
+inline int sand_fixed_id(int L, int nst, uint32_t radpack) {
+  for (int id = 1; id < kSandNumFixed; ++id)
+    if (kSandFixed[id].L == L && kSandFixed[id].nst == nst && sand_fixed_pack(id) == radpack) return id;
+  return 0;
+}
+// most threads per workgroup of the x-pass kernel that runs a plan
+constexpr int sand_max_threads_fixed(int id, int elem, int nin) {
+  return (id > 0 && kSandFixed[id].wide && elem == 4 && nin == 3) ? 1024 : 512;
+}
+inline int sand_max_threads(int L, int nst, uint32_t radpack, int elem, int nin) {
+  return sand_max_threads_fixed(sand_fixed_id(L, nst, radpack), elem, nin);
+}
 
 template <typename T>
 hipError_t launch_zfwd(const double* x, int64_t N, int nrhs, int mode, const int32_t* items, int nitems,

@@ -371,7 +371,8 @@ hipError_t launch_strided(void* data, const StridedArgs& a, const CompSet& cs, i
 template <typename T>
 bool sandwich_args_ok(const SandArgs& a, int nthr) {
   // the kernel assumes every one of these
-  if (a.nst < 1 || a.nst > kSandMaxStages || a.ncol < 1 || a.ncol > 32 || nthr < 64 || nthr > 512 || (nthr & 63))
+  if (a.nst < 1 || a.nst > kSandMaxStages || a.ncol < 1 || a.ncol > 32 || nthr < 64 || (nthr & 63) ||
+      nthr > sand_max_threads(a.Mx, a.nst, a.radpack, (int)sizeof(T), a.nin))
     return false;
   long prod = 1;
   int prev = 1 << 30;

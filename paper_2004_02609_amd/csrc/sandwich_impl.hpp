@@ -523,7 +523,10 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
 // Right-hand sides fastest: the workgroups that read one tile's spectra run together on
 // one XCD, so those spectra come from HBM once per tile rather than once per RHS.
 template <typename T, int NIN, int NOUT, int RS, int PID = 0>
-__global__ void __launch_bounds__(512, (sizeof(T) == 8 || NIN == 6) ? 2 : 3)
+__global__ void __launch_bounds__(sand_max_threads_fixed(PID, (int)sizeof(T), NIN),
+                                  sand_max_threads_fixed(PID, (int)sizeof(T), NIN) == 1024
+                                      ? 4
+                                      : ((sizeof(T) == 8 || NIN == 6) ? 2 : 3))
 k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __restrict__ R, SandArgs a,
             const C2<T>* __restrict__ twg, const C2<T>* __restrict__ phx, const C2<T>* __restrict__ phy,
             const C2<T>* __restrict__ phz, const uint8_t* __restrict__ pflag) {
