@@ -86,13 +86,24 @@ template <> __device__ __forceinline__ double bld1<double>(Buf b, uint32_t off) 
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, off, 0, 0));
 }
 
+// LDS accesses of one complex value as one 8- (FP32) or 16-byte (FP64) access: every
+// offset here is a multiple of the element size, and the wide access takes a constant
+// offset in its immediate field.  (The LDS-tile FFT of the z passes keeps pairs of
+// 4-byte accesses, which conflict less in its access pattern.)
+template <typename T> struct LdsVec;
+template <> struct LdsVec<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct LdsVec<double> { typedef double type __attribute__((ext_vector_type(2))); };
 template <typename T>
 __device__ __forceinline__ C2<T> lds_ld(const char* __restrict__ lds, uint32_t off) {
-  return *reinterpret_cast<const C2<T>*>(lds + off);
+  const typename LdsVec<T>::type v = *reinterpret_cast<const typename LdsVec<T>::type*>(lds + off);
+  return C2<T>{v.x, v.y};
 }
 template <typename T>
 __device__ __forceinline__ void lds_st(char* __restrict__ lds, uint32_t off, C2<T> v) {
-  *reinterpret_cast<C2<T>*>(lds + off) = v;
+  typename LdsVec<T>::type w;
+  w.x = v.x;
+  w.y = v.y;
+  *reinterpret_cast<typename LdsVec<T>::type*>(lds + off) = w;
 }
 
 // component-wise select (a select of whole structs by a runtime flag can be lowered to
@@ -300,8 +311,8 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
   const int LR0 = L / r0;
   const bool act0 = i < LR0;                   // owns a butterfly of the first / last stage
   for (int t = tid; t < L; t += blockDim.x) {
-    reinterpret_cast<C2<T>*>(twb)[t] = twg[t];
-    if (PH_LDS) reinterpret_cast<C2<T>*>(phb)[t] = phx[t];
+    lds_st<T>(twb, (uint32_t)t * E, twg[t]);
+    if (PH_LDS) lds_st<T>(phb, (uint32_t)t * E, phx[t]);
   }
   for (int t = tid; t < 3 * a.n1x; t += blockDim.x) sflag[t] = pflag[t];
   const C2<T> phy_t = phy[ky], phz_t = phz[kz];

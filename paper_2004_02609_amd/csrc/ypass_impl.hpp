@@ -86,7 +86,7 @@ k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const 
   const int r0 = rad(0);
   const int LR0 = L / r0;
   const bool act0 = i < LR0;
-  for (int t = tid; t < L; t += blockDim.x) reinterpret_cast<C2<T>*>(twb)[t] = twg[t];
+  for (int t = tid; t < L; t += blockDim.x) lds_st<T>(twb, (uint32_t)t * E, twg[t]);
   // input rows i + q L/f0 that are stored (bit q), output rows i + m tl that are needed
   uint32_t inmask = 0u, outmask = 0u;
   if (colok) {
