@@ -82,10 +82,10 @@ struct SandArgs {
   const int* skip;   // optional device flag: when set, the launch does nothing
   const int* act;    // optional per right-hand side activity: workgroups of inactive ones return
 };
-// dynamic LDS of the sandwich: twiddle table (+ the x phases in FP32) + one [L][ncol+1]
+// dynamic LDS of the sandwich: twiddle table (+ the x phases in FP32) + one [L][ncol]
 // tile + 3 n1x plane flags
 inline size_t sandwich_lds_bytes(int L, int ncol, int elem, int n1x) {
-  return (size_t)2 * elem * ((size_t)(elem == 4 ? 2 : 1) * L + (size_t)L * (ncol + 1)) + (size_t)3 * n1x;
+  return (size_t)2 * elem * ((size_t)(elem == 4 ? 2 : 1) * L + (size_t)L * ncol) + (size_t)3 * n1x;
 }
 // x-transform plan of the sandwich for one precision / variant (see sandwich_impl.hpp):
 // fewest stages with the first radix <= rmax, middle radices <= rmid and the last

@@ -286,13 +286,13 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
   const int L = FX ? PD.L : a.Mx, tl = FX ? PD.L / RS : a.tl, S = FX ? PD.nst : a.nst;
   auto rad = [&](int s) -> int { return FX ? PD.r[s] : srad(a, s); };
   const int ncol = a.ncol;
-  const uint32_t ncolpE = (uint32_t)(ncol + 1) * E;
+  const uint32_t ncolpE = (uint32_t)ncol * E;   // unpadded rows: measured faster than a pitch of ncol + 1 or + 2
   // FP32 keeps the x half-voxel phases in LDS beside the twiddles; FP64 (whose tiles are
   // twice as large, and whose registers are full) reads them from the cached table
   constexpr bool PH_LDS = sizeof(T) == 4;
   char* twb = smem_raw;                                    // L twiddles
   char* phb = smem_raw + (size_t)L * E;                    // L x phases (FP32)
-  char* lds = smem_raw + (size_t)(PH_LDS ? 2 : 1) * L * E; // [L][ncol + 1] tile
+  char* lds = smem_raw + (size_t)(PH_LDS ? 2 : 1) * L * E; // [L][ncol] tile
   uint8_t* sflag = reinterpret_cast<uint8_t*>(lds + (size_t)L * ncolpE);   // plane flags of the 3 axes
   const int tid = threadIdx.x;
   const int i = fdiv(tid, 1.0f / (float)ncol), c = tid - i * ncol;   // column fastest
@@ -350,7 +350,7 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
     VC_SW_SWITCH(r0, VC_CALL, RMAX)
 #undef VC_CALL
   }
-#pragma unroll 1
+#pragma unroll
   for (int b = 0; b < NIN; ++b) {
     const int fax = b % 3;
     const int fmsk = NIN == 3 ? 3 : (b < 3 ? 1 : 2);
