@@ -23,13 +23,17 @@ template <typename T> __device__ __forceinline__ C2<T> ld(const C2<T>* p) { retu
 // Panels of one tile of z lines.  Items are the lines holding panels in line order and
 // line_ptr is the panels' CSR over all lines, so the panels of the tile's consecutive
 // items form one contiguous range; lp[c] is the first panel of tile column c and lp[nc]
-// one past the last.  Returns nc (columns of this tile, >= 1 whenever item0 < nitems).
+// one past the last, sl[c] the line of column c.  Returns nc (columns of this tile, >= 1
+// whenever item0 < nitems).
 __device__ __forceinline__ int tile_panels(const int32_t* __restrict__ items, const int32_t* __restrict__ line_ptr,
-                                           int item0, int nitems, int ncol, int* lp) {
+                                           int item0, int nitems, int ncol, int* lp, int* sl) {
   const int nc = min(ncol, nitems - item0);
   const int tid = threadIdx.x;
-  if (nc > 0 && tid <= nc)
-    lp[tid] = tid < nc ? line_ptr[items[item0 + tid]] : line_ptr[items[item0 + nc - 1] + 1];
+  if (nc > 0 && tid <= nc) {
+    const int line = items[item0 + (tid < nc ? tid : nc - 1)];
+    if (tid < nc) sl[tid] = line;
+    lp[tid] = line_ptr[tid < nc ? line : line + 1];
+  }
   __syncthreads();
   return nc;
 }
@@ -70,11 +74,11 @@ __device__ __forceinline__ void zfwd_body(const ZScene& a, int mode, const doubl
   C2<T>* buf = tw + L;
   C2<T>* buf2 = buf + L * ncolp;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  __shared__ int lp[33];
+  __shared__ int lp[33], sl[32];
   for (int t = tid; t < L; t += nthr) tw[t] = twg[t];
   for (int e = tid; e < L * ncolp; e += nthr) buf[e] = C2<T>{T(0), T(0)};
   const int item0 = bx * ncol;
-  const int nc = tile_panels(items, line_ptr, item0, nitems, ncol, lp);   // (synchronises)
+  const int nc = tile_panels(items, line_ptr, item0, nitems, ncol, lp, sl);   // (synchronises)
   // scatter: all threads over the tile's panels at once
   for (int p = (nc > 0 ? lp[0] : 0) + tid; nc > 0 && p < lp[nc]; p += nthr) {
     const int c = panel_col(lp, nc, p);
@@ -96,9 +100,8 @@ __device__ __forceinline__ void zfwd_body(const ZScene& a, int mode, const doubl
   const float invH = 1.0f / (float)H, invPl = 1.0f / (float)plane, invN1y = 1.0f / (float)n1y;
   for (int e = tid; e < H * ncol; e += nthr) {
     const int c = fdiv(e, invH), k = e - c * H;
-    const int it = item0 + c;
-    if (it >= nitems) continue;
-    const int line = items[it];
+    if (c >= nc) continue;
+    const int line = sl[c];
     const int axis = fdiv(line, invPl);
     const int rem = line - axis * plane;
     const int xi = fdiv(rem, invN1y), yi = rem - xi * n1y;
@@ -240,18 +243,17 @@ __device__ __forceinline__ void zinv_body(const ZScene& a, int mode, const doubl
   C2<T>* buf = tw + L;
   C2<T>* buf2 = buf + L * ncolp;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  __shared__ int lp[33];
+  __shared__ int lp[33], sl[32];
   for (int t = tid; t < L; t += nthr) tw[t] = twg[t];
   const int item0 = bx * ncol;
-  const int nc = tile_panels(items, line_ptr, item0, nitems, ncol, lp);   // (synchronises)
+  const int nc = tile_panels(items, line_ptr, item0, nitems, ncol, lp, sl);   // (synchronises)
   const int plane = n1x * n1y;
   const float invH = 1.0f / (float)H, invPl = 1.0f / (float)plane, invN1y = 1.0f / (float)n1y;
   for (int e = tid; e < H * ncol; e += nthr) {
     const int c = fdiv(e, invH), k = e - c * H;
-    const int it = item0 + c;
     C2<T> Cv = {T(0), T(0)}, Dv = {T(0), T(0)};
-    if (it < nitems) {
-      const int line = items[it];
+    if (c < nc) {
+      const int line = sl[c];
       const int axis = fdiv(line, invPl);
       const int rem = line - axis * plane;
       const int xi = fdiv(rem, invN1y), yi = rem - xi * n1y;
