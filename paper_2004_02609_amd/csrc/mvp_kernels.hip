@@ -244,8 +244,10 @@ __device__ __forceinline__ void zinv_body(const ZScene& a, int mode, const doubl
   C2<T>* buf2 = buf + L * ncolp;
   const int tid = threadIdx.x, nthr = blockDim.x;
   __shared__ int lp[33], sl[32];
+  __shared__ uint8_t sf[32];
   for (int t = tid; t < L; t += nthr) tw[t] = twg[t];
   const int item0 = bx * ncol;
+  if (tid < ncol && item0 + tid < nitems) sf[tid] = lflag[items[item0 + tid]];   // line flags of the tile
   const int nc = tile_panels(items, line_ptr, item0, nitems, ncol, lp, sl);   // (synchronises)
   const int plane = n1x * n1y;
   const float invH = 1.0f / (float)H, invPl = 1.0f / (float)plane, invN1y = 1.0f / (float)n1y;
@@ -259,7 +261,7 @@ __device__ __forceinline__ void zinv_body(const ZScene& a, int mode, const doubl
       const int xi = fdiv(rem, invN1y), yi = rem - xi * n1y;
       const int64_t off = ((int64_t)xi * My + yi) * H + k;
       if (mode == 0) {
-        const uint8_t f = lflag[line];
+        const uint8_t f = sf[c];
         if (f & 1) Cv = O[axis * comp_stride + ra * rhs_stride + off];
         if (f & 2) Dv = O[(3 + axis) * comp_stride + ra * rhs_stride + off];
       } else {
