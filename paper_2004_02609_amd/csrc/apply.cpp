@@ -325,8 +325,7 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
     const vc_status ys = y_pass<T>(P, tb, F, O, 0, cin, n1y, My, nrhs, transpose, skip, act, st);
     if (ys != VC_OK) return ys;
   }
-  VC_MARK(2);
-  // 3. x sandwich
+  // 3. x sandwich (its timing events, if any, are stamped by the launch itself)
   SandArgs xa{};
   xa.comp_stride = cs; xa.rhs_stride = rs; xa.pair_stride = (int64_t)P->Hy * H * P->Hx;
   xa.nrhs = nrhs; xa.n1x = n1x; xa.Mx = Mx; xa.My = My; xa.H = H; xa.Hx = P->Hx; xa.Hy = P->Hy;
@@ -399,8 +398,7 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
     nthr = ch.nthr;
   }
   VC_HIP(launch_sandwich<T>(F, O, tb.R.p, xa, tb.ax[0].tw.p, tb.ax[0].ph.p, tb.ax[1].ph.p, tb.ax[2].ph.p, pflag, nthr,
-                            st));
-  VC_MARK(3);
+                            st, ev[2], ev[3]));
   // 4. inverse y transform of the outputs (only rows with panels that need them)
   {
     const vc_status ys = y_pass<T>(P, tb, O, F, 1, cout, My, n1y, nrhs, transpose, skip, act, st);

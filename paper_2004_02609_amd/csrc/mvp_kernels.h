@@ -143,10 +143,12 @@ hipError_t launch_zfwd(const double* x, int64_t N, int nrhs, int mode, const int
 template <typename T>
 hipError_t launch_strided(void* data, const StridedArgs& a, const CompSet& cs, int nplanes, const AxisPlan& pl,
                           const void* tw, const uint8_t* lflag, const uint8_t* pflag, int nthr, hipStream_t st);
+// e0 / e1 (optional): events the launch itself stamps at the kernel's start and end
+// (no separate event packets around it)
 template <typename T>
 hipError_t launch_sandwich(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
                            const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
-                           hipStream_t st);
+                           hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // a sandwich launch configuration (plan, tile, threads)
 struct SandCfg {
   int nst, tl, ncol, nthr;
@@ -156,7 +158,7 @@ struct SandCfg {
 template <typename T, int NIN, int NOUT>
 hipError_t launch_sandwich_v(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
                              const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
-                             size_t lds, int rs, hipStream_t st);
+                             size_t lds, int rs, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
 // largest last-stage radix compiled for each sandwich variant (registers: NIN x RS held values)
 constexpr int sandwich_rs_max(int elem, int nin) { return elem == 4 ? (nin == 3 ? 6 : 7) : (nin == 3 ? 5 : 3); }
 constexpr int sandwich_rmax(int elem) { return elem == 4 ? 10 : 10; }

@@ -403,16 +403,16 @@ bool sandwich_args_ok(const SandArgs& a, int nthr) {
 template <typename T>
 hipError_t launch_sandwich(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
                            const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
-                           hipStream_t st) {
+                           hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (!sandwich_args_ok<T>(a, nthr)) return hipErrorInvalidValue;
   const int rs = (int)((a.radpack >> (5 * (a.nst - 1))) & 31u);
   const size_t lds = sandwich_lds_bytes(a.Mx, a.ncol, (int)sizeof(T), a.n1x);
   if (!a.adjoint && a.nin == 3 && a.nout == 6)
-    return launch_sandwich_v<T, 3, 6>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st);
+    return launch_sandwich_v<T, 3, 6>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
   if (!a.adjoint && a.nin == 3 && a.nout == 3)
-    return launch_sandwich_v<T, 3, 3>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st);
+    return launch_sandwich_v<T, 3, 3>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
   if (a.adjoint && a.nin == 6 && a.nout == 3)
-    return launch_sandwich_v<T, 6, 3>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st);
+    return launch_sandwich_v<T, 6, 3>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
   return hipErrorInvalidValue;
 }
 
@@ -472,7 +472,8 @@ hipError_t launch_strided_multi(const StridedScene* tab, int nscene, int nblocks
   template hipError_t launch_strided<T>(void*, const StridedArgs&, const CompSet&, int, const AxisPlan&,          \
                                         const void*, const uint8_t*, const uint8_t*, int, hipStream_t);            \
   template hipError_t launch_sandwich<T>(const void*, void*, const void*, const SandArgs&, const void*, const void*, \
-                                         const void*, const void*, const uint8_t*, int, hipStream_t);              \
+                                         const void*, const void*, const uint8_t*, int, hipStream_t, hipEvent_t,      \
+                                         hipEvent_t);              \
   template hipError_t launch_zinv<T>(const void*, double*, const double*, int64_t, int, int, const int32_t*, int, \
                                      const int32_t*, const int32_t*, const int8_t*, const double*, const uint8_t*, \
                                      int64_t, int64_t, int, int, int, int, const AxisPlan&, const void*, int, int, \

@@ -27,6 +27,8 @@
 // frequencies are computed once, so each multiply term is a load, a sign flip and two
 // FMAs.
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "fft_core.hpp"
 #include "mvp_kernels.h"
 
@@ -578,38 +580,44 @@ template <typename T, int NIN> struct SandRS {
 
 // launch with last-stage radix RR: the fixed-plan kernel of the first table entry that
 // equals the runtime plan, else the generic one
+// e0 / e1: optional events stamped by the launch itself (hipExtLaunchKernelGGL)
 template <typename T, int NIN, int NOUT, int RR, int ID>
 hipError_t launch_sandwich_rs(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
                               const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
-                              size_t lds, hipStream_t st) {
+                              size_t lds, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   dim3 grid((a.My * a.H + a.ncol - 1) / a.ncol, a.nrhs);
+  auto go = [&](auto kernel) -> hipError_t {
+    if (e0 || e1)
+      hipExtLaunchKernelGGL(kernel, grid, dim3(nthr), (std::uint32_t)lds, st, e0, e1, 0u, (const C2<T>*)Fin,
+                            (C2<T>*)Fout, (const T*)R, a, (const C2<T>*)tw, (const C2<T>*)phx, (const C2<T>*)phy,
+                            (const C2<T>*)phz, pflag);
+    else
+      hipLaunchKernelGGL(kernel, grid, dim3(nthr), lds, st, (const C2<T>*)Fin, (C2<T>*)Fout, (const T*)R, a,
+                         (const C2<T>*)tw, (const C2<T>*)phx, (const C2<T>*)phy, (const C2<T>*)phz, pflag);
+    return hipGetLastError();
+  };
   if constexpr (ID < kSandNumFixed) {
     if constexpr (sand_fixed_last(ID) == RR) {
       if (a.Mx == kSandFixed[ID].L && a.nst == kSandFixed[ID].nst && a.radpack == sand_fixed_pack(ID) &&
-          a.tl * RR == a.Mx) {
-        hipLaunchKernelGGL((k_xsandwich<T, NIN, NOUT, RR, ID>), grid, dim3(nthr), lds, st, (const C2<T>*)Fin,
-                           (C2<T>*)Fout, (const T*)R, a, (const C2<T>*)tw, (const C2<T>*)phx, (const C2<T>*)phy,
-                           (const C2<T>*)phz, pflag);
-        return hipGetLastError();
-      }
+          a.tl * RR == a.Mx)
+        return go(k_xsandwich<T, NIN, NOUT, RR, ID>);
     }
-    return launch_sandwich_rs<T, NIN, NOUT, RR, ID + 1>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, st);
+    return launch_sandwich_rs<T, NIN, NOUT, RR, ID + 1>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, st, e0,
+                                                        e1);
   } else {
-    hipLaunchKernelGGL((k_xsandwich<T, NIN, NOUT, RR, 0>), grid, dim3(nthr), lds, st, (const C2<T>*)Fin,
-                       (C2<T>*)Fout, (const T*)R, a, (const C2<T>*)tw, (const C2<T>*)phx, (const C2<T>*)phy,
-                       (const C2<T>*)phz, pflag);
-    return hipGetLastError();
+    return go(k_xsandwich<T, NIN, NOUT, RR, 0>);
   }
 }
 
 template <typename T, int NIN, int NOUT>
 hipError_t launch_sandwich_v(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
                              const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
-                             size_t lds, int rs, hipStream_t st) {
+                             size_t lds, int rs, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
 #define VC_RS(RR)                                                                                                 \
   case RR:                                                                                                        \
     if constexpr (RR <= SandRS<T, NIN>::max) {                                                                    \
-      return launch_sandwich_rs<T, NIN, NOUT, RR, 1>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, st);  \
+      return launch_sandwich_rs<T, NIN, NOUT, RR, 1>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, st, e0, \
+                                                     e1);                                                         \
     }                                                                                                             \
     break;
   switch (rs) {
