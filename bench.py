@@ -378,27 +378,44 @@ def main():
     if not args.no_solve:
         solve = {}
         Cref, st_ref = P.capacitance(prec="fp64", rtol=1e-12)
-        # both modes warm (their restart-cycle graphs captured by a first, untimed solve),
-        # then the median of three timed solves each
-        for mode in ("fp64", "mixed"):
-            P.capacitance(prec=mode, rtol=1e-9)
+        dmax = np.abs(np.diag(Cref)).max()
+        gate = np.abs(Cref) >= 1e-3 * dmax
+
+        def cerr(Cm):
+            return float((np.abs(Cm - Cref)[gate] / np.abs(Cref)[gate]).max())
+
+        def timed(mode, rtol):
+            """Median of three warm solves (the restart-cycle graphs are captured by a first,
+            untimed solve), with the entrywise error of the last against FP64 at 1e-12."""
+            P.capacitance(prec=mode, rtol=rtol)
             ts = []
             for _ in range(3):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                Cm, st = P.capacitance(prec=mode, rtol=1e-9)
+                Cm, st = P.capacitance(prec=mode, rtol=rtol)
                 ts.append(time.perf_counter() - t0)
-            t = float(np.median(ts))
-            d = np.abs(np.diag(Cref)).max()
-            gate = np.abs(Cref) >= 1e-3 * d
-            err = float((np.abs(Cm - Cref)[gate] / np.abs(Cref)[gate]).max())
-            solve[mode] = {"time_s": t, "times_s": ts, "iters": st["iters"], "ir_steps": st["ir_steps"],
-                           "max_rel_err_vs_fp64_1e-12": err, "products": st["mvp_count"]}
+            return {"time_s": float(np.median(ts)), "times_s": ts, "iters": st["iters"], "ir_steps": st["ir_steps"],
+                    "max_rel_err_vs_fp64_1e-12": cerr(Cm), "products": st["mvp_count"], "rtol": rtol}
+
+        # the metric's accuracy: the loosest GMRES tolerance at which both the FP64 and the
+        # mixed solve give every gated entry of C within 1e-6 of the FP64 reference
+        cal = 1e-10
+        for rt in (1e-5, 1e-6, 1e-7, 1e-8, 1e-9):
+            if all(cerr(P.capacitance(prec=mode, rtol=rt)[0]) <= 1e-6 for mode in ("fp64", "mixed")):
+                cal = rt
+                break
+        solve["rtol_for_1e-6"] = cal
+        for mode in ("fp64", "mixed"):
+            solve[mode] = timed(mode, cal)
         solve["speedup_mixed_vs_fp64"] = solve["fp64"]["time_s"] / solve["mixed"]["time_s"]
-        # the same FP64 solve with the restart cycle's kernels issued one by one
+        # the same pair at a fixed, tighter tolerance
+        solve["at_rtol_1e-9"] = {mode: timed(mode, 1e-9) for mode in ("fp64", "mixed")}
+        solve["at_rtol_1e-9"]["speedup_mixed_vs_fp64"] = (solve["at_rtol_1e-9"]["fp64"]["time_s"] /
+                                                          solve["at_rtol_1e-9"]["mixed"]["time_s"])
+        # the FP64 solve with the restart cycle's kernels issued one by one
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        P.capacitance(prec="fp64", rtol=1e-9, graph=False)
+        P.capacitance(prec="fp64", rtol=cal, graph=False)
         solve["fp64_no_graph_time_s"] = time.perf_counter() - t0
 
     tucker = None
