@@ -434,9 +434,14 @@ class Problem:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            vc_problem_destroy(h)
-            self._h = None
+        self._h = None
+        # at interpreter exit the module's globals may already be gone: the process
+        # releases the device memory then anyway
+        if h and callable(vc_problem_destroy):
+            try:
+                vc_problem_destroy(h)
+            except Exception:
+                pass
 
     def panels(self):
         return vc_panels(self._h)
