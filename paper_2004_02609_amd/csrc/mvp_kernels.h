@@ -61,6 +61,20 @@ struct YArgs {
 template <typename T>
 hipError_t launch_ypass(void* data, const YArgs& a, const void* tw, const uint8_t* lflag, const uint8_t* pflag,
                         int nplanes, int nthr, hipStream_t st);
+// the register-edge y pass of several scenes in one launch (members with last radix rs)
+struct YScene {
+  YArgs a;            // a.skip / a.act unused: the call's flags apply
+  void* data;
+  const void* tw;
+  const uint8_t* lflag;
+  const uint8_t* pflag;
+  int c0, gx, gy, blk0;   // first column; tiles, planes; first linear workgroup
+};
+template <typename T>
+bool ypass_args_ok(const YArgs& a, int nthr, bool flags, size_t* lds);
+template <typename T>
+hipError_t launch_ypass_multi(const YScene* tab, int nscene, int nblocks, int rs, int nthr, size_t lds,
+                              const int* skip, const int* act, hipStream_t st);
 // plan and tile of the y pass for length L over ncols kz columns (fewest stages, largest
 // last radix, then the tile that keeps lanes and columns busy and reads whole 128-byte
 // row lines); false when none fits

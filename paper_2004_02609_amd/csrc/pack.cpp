@@ -35,7 +35,8 @@ struct PackPass {   // one multi-member launch
 
 struct PackPrec {
   bool ok = false;
-  PackPass zf, yf, yi, zi;
+  PackPass zf, yf, yi, zi;   // yf / yi: members on the LDS-tile y kernel
+  std::vector<PackPass> yfr, yir;   // members on the register-edge y kernel, by last radix
   std::vector<PackPass> sand;
 };
 
@@ -79,6 +80,8 @@ static vc_status build_tables(PackData& D, PackPrec& pp) {
   std::vector<StridedScene> yf, yi;
   std::map<std::pair<int, int>, std::vector<SandScene>> sg;   // (outputs, register radix) -> members
   std::map<std::pair<int, int>, PackPass> sgp;
+  std::map<int, std::vector<YScene>> ygf, ygi;                 // register radix -> members (y forward / inverse)
+  std::map<int, PackPass> ypf, ypi;
   int bzf = 0, bzi = 0, byf = 0, byi = 0;
   for (size_t k = 0; k < D.mem.size(); ++k) {
     vc_problem* P = D.mem[k];
@@ -132,18 +135,48 @@ static vc_status build_tables(PackData& D, PackPrec& pp) {
     y.pflag = P->d_pflag.as<uint8_t>();
     y.c0 = c0;
     y.gy = n1x;
+    // the register-edge y kernel when its default tile covers at least 32 bytes of a row
+    // (the member's own default), else the LDS-tile kernel
+    auto yreg = [&](const CompSet& cs, int nin, int nout, int inverse, void* data,
+                    std::map<int, std::vector<YScene>>& grp, std::map<int, PackPass>& gp) -> bool {
+      YScene ys{};
+      YArgs& ya = ys.a;
+      ya.comp_stride = P->comp_stride; ya.rhs_stride = P->rhs_stride; ya.plane_stride = (int64_t)My * H;
+      ya.row_stride = H; ya.ncols = H; ya.nrhs = m; ya.n1x = n1x; ya.n1y = n1y;
+      ya.cs = cs; ya.nin = nin; ya.nout = nout; ya.inverse = inverse;
+      int ythr = 0;
+      size_t lds = 0;
+      if (!ypass_config(My, (int)sizeof(T), H, budget, &ya, &ythr) || ya.ncol * eb < 32 ||
+          !ypass_args_ok<T>(ya, ythr, true, &lds))
+        return false;
+      ys.data = data;
+      ys.tw = tb.ax[1].tw.p;
+      ys.lflag = P->d_lflag.as<uint8_t>();
+      ys.pflag = P->d_pflag.as<uint8_t>();
+      ys.c0 = c0;
+      ys.gx = (H + ya.ncol - 1) / ya.ncol;
+      ys.gy = n1x;
+      const int rs = (int)((ya.radpack >> (5 * (ya.nst - 1))) & 31u);
+      grp[rs].push_back(ys);
+      PackPass& g = gp[rs];
+      g.rs = rs;
+      grow(g, ythr, lds);
+      return true;
+    };
     {
       StridedScene f = y;
       f.cs.n = 3;
       for (int a = 0; a < 3; ++a) { f.cs.comp[a] = a; f.cs.axis[a] = a; f.cs.min_[a] = 3; f.cs.mout[a] = 0; }
-      if (!pick_tile(My, eb, Tune<T>::emax, H, &ncol, &nthr, budget, (int64_t)n1x * 3 * m)) return VC_ERR_ARG;
-      f.a.ncol = ncol; f.a.lgc = lg2(ncol); f.a.nin = n1y; f.a.nout = My; f.a.inverse = 0;
-      f.data = P->work_F.p;
-      f.gx = (H + ncol - 1) / ncol;
-      f.blk0 = byf;
-      byf += f.gx * f.gy * f.cs.n * m;
-      yf.push_back(f);
-      grow(pp.yf, nthr, zs_lds_bytes((int)sizeof(T), My, ncol));
+      if (!yreg(f.cs, n1y, My, 0, P->work_F.p, ygf, ypf)) {
+        if (!pick_tile(My, eb, Tune<T>::emax, H, &ncol, &nthr, budget, (int64_t)n1x * 3 * m)) return VC_ERR_ARG;
+        f.a.ncol = ncol; f.a.lgc = lg2(ncol); f.a.nin = n1y; f.a.nout = My; f.a.inverse = 0;
+        f.data = P->work_F.p;
+        f.gx = (H + ncol - 1) / ncol;
+        f.blk0 = byf;
+        byf += f.gx * f.gy * f.cs.n * m;
+        yf.push_back(f);
+        grow(pp.yf, nthr, zs_lds_bytes((int)sizeof(T), My, ncol));
+      }
     }
     // 3. x transform + block multiply + inverse x transform
     {
@@ -187,14 +220,16 @@ static vc_status build_tables(PackData& D, PackPrec& pp) {
       const int no = diel ? 6 : 3;
       f.cs.n = no;
       for (int o = 0; o < no; ++o) { f.cs.comp[o] = o; f.cs.axis[o] = o % 3; f.cs.min_[o] = 0; f.cs.mout[o] = o < 3 ? 1 : 2; }
-      if (!pick_tile(My, eb, Tune<T>::emax, H, &ncol, &nthr, budget, (int64_t)n1x * no * m)) return VC_ERR_ARG;
-      f.a.ncol = ncol; f.a.lgc = lg2(ncol); f.a.nin = My; f.a.nout = n1y; f.a.inverse = 1;
-      f.data = P->work_O.p;
-      f.gx = (H + ncol - 1) / ncol;
-      f.blk0 = byi;
-      byi += f.gx * f.gy * no * m;
-      yi.push_back(f);
-      grow(pp.yi, nthr, zs_lds_bytes((int)sizeof(T), My, ncol));
+      if (!yreg(f.cs, My, n1y, 1, P->work_O.p, ygi, ypi)) {
+        if (!pick_tile(My, eb, Tune<T>::emax, H, &ncol, &nthr, budget, (int64_t)n1x * no * m)) return VC_ERR_ARG;
+        f.a.ncol = ncol; f.a.lgc = lg2(ncol); f.a.nin = My; f.a.nout = n1y; f.a.inverse = 1;
+        f.data = P->work_O.p;
+        f.gx = (H + ncol - 1) / ncol;
+        f.blk0 = byi;
+        byi += f.gx * f.gy * no * m;
+        yi.push_back(f);
+        grow(pp.yi, nthr, zs_lds_bytes((int)sizeof(T), My, ncol));
+      }
     }
     // 5. inverse z transform + gather + jump term
     if (nitems > 0) {
@@ -219,6 +254,33 @@ static vc_status build_tables(PackData& D, PackPrec& pp) {
   if ((s = upload_tab(pp.zf, zf)) != VC_OK || (s = upload_tab(pp.yf, yf)) != VC_OK ||
       (s = upload_tab(pp.yi, yi)) != VC_OK || (s = upload_tab(pp.zi, zi)) != VC_OK)
     return s;
+  // register-edge y groups: workgroups laid out member after member
+  for (int dir = 0; dir < 2; ++dir) {
+    auto& grp = dir == 0 ? ygf : ygi;
+    auto& gp = dir == 0 ? ypf : ypi;
+    std::vector<PackPass>& out = dir == 0 ? pp.yfr : pp.yir;
+    out.clear();
+    for (auto& kv : grp) {
+      PackPass g = std::move(gp[kv.first]);
+      int blk = 0;
+      for (YScene& ys : kv.second) {
+        size_t lds = 0;
+        if (!ypass_args_ok<T>(ys.a, g.nthr, true, &lds)) {
+          set_error("packed y-pass configuration rejected");
+          return VC_ERR_ARG;
+        }
+        ys.blk0 = blk;
+        blk += ys.gx * ys.gy * ys.a.cs.n * ys.a.nrhs;
+      }
+      g.nblk = blk;
+      if (g.lds > lds_ext_budget() || g.nthr > 1024) {
+        set_error("packed pass exceeds the launch limits");
+        return VC_ERR_ARG;
+      }
+      if ((s = upload_tab(g, kv.second)) != VC_OK) return s;
+      out.push_back(std::move(g));
+    }
+  }
   pp.sand.clear();
   for (auto& kv : sg) {
     PackPass g = std::move(sgp[kv.first]);
@@ -242,6 +304,8 @@ static vc_status pack_apply_t(PackPrec& pp, int64_t N, const double* x, double* 
   VC_HIP(launch_zfwd_multi<T>(pp.zf.tab.as<ZScene>(), pp.zf.n, pp.zf.nblk, x, N, skip, act, pp.zf.nthr, pp.zf.lds, st));
   VC_HIP(launch_strided_multi<T>(pp.yf.tab.as<StridedScene>(), pp.yf.n, pp.yf.nblk, skip, act, pp.yf.nthr, pp.yf.lds,
                                  st));
+  for (PackPass& g : pp.yfr)
+    VC_HIP(launch_ypass_multi<T>(g.tab.as<YScene>(), g.n, g.nblk, g.rs, g.nthr, g.lds, skip, act, st));
   for (PackPass& g : pp.sand) {
     if (g.nout == 6)
       VC_HIP((launch_sandwich_multi_v<T, 3, 6>(g.tab.as<SandScene>(), g.n, g.nblk, skip, act, g.nthr, g.lds, g.rs, st)));
@@ -250,6 +314,8 @@ static vc_status pack_apply_t(PackPrec& pp, int64_t N, const double* x, double* 
   }
   VC_HIP(launch_strided_multi<T>(pp.yi.tab.as<StridedScene>(), pp.yi.n, pp.yi.nblk, skip, act, pp.yi.nthr, pp.yi.lds,
                                  st));
+  for (PackPass& g : pp.yir)
+    VC_HIP(launch_ypass_multi<T>(g.tab.as<YScene>(), g.n, g.nblk, g.rs, g.nthr, g.lds, skip, act, st));
   VC_HIP(launch_zinv_multi<T>(pp.zi.tab.as<ZScene>(), pp.zi.n, pp.zi.nblk, x, y, N, skip, act, pp.zi.nthr, pp.zi.lds,
                               st));
   return VC_OK;
@@ -437,13 +503,21 @@ vc_status pack_capacitance(vc_problem* Q, const vc_solve_opts* opts, double* con
   return s;
 }
 
+// kernel launches of one packed product: the z passes, the y passes (LDS-tile launch if
+// any member uses it, one register-edge launch per last radix) and the x-pass groups
+static int32_t pack_launches(const PackPrec& pp) {
+  if (!pp.ok) return 0;
+  return (pp.zf.n > 0) + (pp.zi.n > 0) + (pp.yf.n > 0) + (pp.yi.n > 0) + (int32_t)pp.yfr.size() +
+         (int32_t)pp.yir.size() + (int32_t)pp.sand.size();
+}
+
 void pack_info(const vc_problem* Q, int32_t out[6]) {
   const PackData& D = *Q->pack;
   out[0] = (int32_t)D.mem.size();
   out[1] = D.R;
   out[2] = (int32_t)Q->pack_rows;
-  out[3] = D.p64.ok ? 4 + (int32_t)D.p64.sand.size() : 0;
-  out[4] = D.p32.ok ? 4 + (int32_t)D.p32.sand.size() : 0;
+  out[3] = pack_launches(D.p64);
+  out[4] = pack_launches(D.p32);
   out[5] = 2;
 }
 

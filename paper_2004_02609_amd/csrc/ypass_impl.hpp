@@ -46,21 +46,19 @@ __device__ __forceinline__ void yp_first(const C2<T>* __restrict__ pre, bool act
     if constexpr (RR >= RS && RR <= HI) { CALL(RR) } \
     break;
 
-// PID > 0: the plan of kSandFixed[PID] as compile-time constants; the kernel returns at
-// once if the runtime plan is not that one
-template <typename T, int RS, int PID = 0>
-__global__ void __launch_bounds__(1024)
-k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const uint8_t* __restrict__ lflag,
-        const uint8_t* __restrict__ pflag) {
-  if (a.skip && *a.skip) return;
+// One (column tile, x plane, component x right-hand side) of the pass.  PID > 0: the plan
+// of kSandFixed[PID] as compile-time constants (the kernel checks it is a's).  act: the
+// right-hand sides' activity (null: all active).
+template <typename T, int RS, int PID>
+__device__ __forceinline__ void ypass_body(C2<T>* __restrict__ data, const YArgs& a, const C2<T>* __restrict__ twg,
+                                           const uint8_t* __restrict__ lflag, const uint8_t* __restrict__ pflag,
+                                           const int* __restrict__ act, int tile, int plane, int bz) {
   constexpr bool FX = PID > 0;
   constexpr SandFixedPlan PD = kSandFixed[PID];
-  if (FX && (a.L != PD.L || a.nst != PD.nst || a.radpack != sand_fixed_pack(PID) || a.tl * RS != a.L)) return;
   constexpr int RMAX = 10;
   constexpr uint32_t E = sizeof(C2<T>);
-  const int plane = blockIdx.y;
-  const int cz = blockIdx.z / a.nrhs, rhs = blockIdx.z - cz * a.nrhs;
-  if (a.act && !a.act[rhs]) return;   // uniform per workgroup
+  const int cz = bz / a.nrhs, rhs = bz - cz * a.nrhs;
+  if (act && !act[rhs]) return;   // uniform per workgroup
   const int comp = a.cs.comp[cz], axis = a.cs.axis[cz];
   const int min_ = a.cs.min_[cz], mout = a.cs.mout[cz];
   const int need = a.inverse ? mout : min_;
@@ -75,7 +73,7 @@ k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const 
   const int tid = threadIdx.x;
   const int i = fdiv(tid, 1.0f / (float)ncol), c = tid - i * ncol;   // column fastest
   const bool valid = i < tl;
-  const int col = blockIdx.x * ncol + c;
+  const int col = tile * ncol + c;
   const bool colok = col < a.ncols;
   const int colc = colok ? col : a.ncols - 1;
   // buffer view of this (component, rhs, plane) slab: masked rows read zero / write nothing
@@ -173,6 +171,33 @@ k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const 
     }
   }
 }
+
+template <typename T, int RS, int PID = 0>
+__global__ void __launch_bounds__(1024)
+k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const uint8_t* __restrict__ lflag,
+        const uint8_t* __restrict__ pflag) {
+  if (a.skip && *a.skip) return;
+  if (PID > 0 && (a.L != kSandFixed[PID].L || a.nst != kSandFixed[PID].nst || a.radpack != sand_fixed_pack(PID) ||
+                  a.tl * RS != a.L))
+    return;
+  ypass_body<T, RS, PID>(data, a, twg, lflag, pflag, a.act, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// several scenes in one launch (the members of a packed set with last radix RS):
+// linear workgroup -> (scene, component x rhs, plane, tile)
+template <typename T, int RS>
+__global__ void __launch_bounds__(1024)
+k_ypass_multi(const YScene* __restrict__ tab, int nscene, const int* __restrict__ skip, const int* __restrict__ act) {
+  if (skip && *skip) return;
+  const int lin = blockIdx.x;
+  const YScene& sc = tab[find_scene(tab, nscene, lin)];
+  const int local = lin - sc.blk0;
+  const int per = sc.gx * sc.gy;
+  const int bz = local / per, rem = local - bz * per;
+  const int plane = rem / sc.gx, tile = rem - plane * sc.gx;
+  ypass_body<T, RS, 0>(static_cast<C2<T>*>(sc.data), sc.a, static_cast<const C2<T>*>(sc.tw), sc.lflag, sc.pflag,
+                       act ? act + sc.c0 : nullptr, tile, plane, bz);
+}
 #undef VC_YP_CASE
 #undef VC_YP_SWITCH
 
@@ -208,32 +233,61 @@ hipError_t launch_ypass_rs(void* data, const YArgs& a, const void* tw, const uin
   }
 }
 
+// every assumption of the kernel on its arguments, the LDS bytes it needs in *lds
 template <typename T>
-hipError_t launch_ypass(void* data, const YArgs& a, const void* tw, const uint8_t* lflag, const uint8_t* pflag,
-                        int nplanes, int nthr, hipStream_t st) {
+bool ypass_args_ok(const YArgs& a, int nthr, bool flags, size_t* lds_out) {
   if (a.nst < 1 || a.nst > kSandMaxStages || a.ncol < 1 || a.ncol > 32 || nthr < 64 || nthr > 1024 || (nthr & 63) ||
-      a.cs.n < 1 || a.cs.n > 6)
-    return hipErrorInvalidValue;
+      a.cs.n < 1 || a.cs.n > 6 || a.nrhs < 1)
+    return false;
   long prod = 1;
   int prev = 1 << 30;
   for (int s = 0; s < a.nst; ++s) {
     const int r = (int)((a.radpack >> (5 * s)) & 31u);
-    if (r < 2 || r > 10 || r > prev) return hipErrorInvalidValue;
+    if (r < 2 || r > 10 || r > prev) return false;
     prev = r;
     prod *= r;
   }
-  const int rs = prev;
-  if (prod != a.L || (long)a.tl * rs != a.L || (long)a.tl * a.ncol > nthr) return hipErrorInvalidValue;
-  if (a.nin > a.L || a.nout > a.L) return hipErrorInvalidValue;
-  // rows whose flags are read lie inside the per-plane flag array of n1y rows
-  if (lflag)
+  if (prod != a.L || (long)a.tl * prev != a.L || (long)a.tl * a.ncol > nthr) return false;
+  if (a.nin > a.L || a.nout > a.L) return false;
+  if (flags)
     for (int q = 0; q < a.cs.n; ++q)
-      if ((a.cs.min_[q] && a.nin > a.n1y) || (a.cs.mout[q] && a.nout > a.n1y)) return hipErrorInvalidValue;
-  // 32-bit byte offsets inside one (component, rhs, plane) slab, small enough for the
-  // out-of-range offset of the buffer views (0xFFFFFFF0)
-  if ((uint64_t)a.plane_stride * sizeof(C2<T>) > 0xFFFFFF00ull) return hipErrorInvalidValue;
+      if ((a.cs.min_[q] && a.nin > a.n1y) || (a.cs.mout[q] && a.nout > a.n1y)) return false;
+  if ((uint64_t)a.plane_stride * sizeof(C2<T>) > 0xFFFFFF00ull) return false;
   const size_t lds = (size_t)sizeof(C2<T>) * ((size_t)a.L + (size_t)a.L * (a.ncol + 1));
-  if (lds > lds_ext_budget()) return hipErrorInvalidValue;
+  if (lds > lds_ext_budget()) return false;
+  *lds_out = lds;
+  return true;
+}
+
+template <typename T>
+hipError_t launch_ypass_multi(const YScene* tab, int nscene, int nblocks, int rs, int nthr, size_t lds,
+                              const int* skip, const int* act, hipStream_t st) {
+  if (nscene <= 0 || nblocks <= 0) return hipSuccess;
+  if (nthr < 64 || nthr > 1024 || (nthr & 63) || lds > lds_ext_budget()) return hipErrorInvalidValue;
+#define VC_RS(RR)                                                                                              \
+  case RR:                                                                                                     \
+    if (lds > kLdsBudget) {                                                                                    \
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ypass_multi<T, RR>),            \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
+      if (e != hipSuccess) return e;                                                                           \
+    }                                                                                                          \
+    hipLaunchKernelGGL((k_ypass_multi<T, RR>), dim3(nblocks), dim3(nthr), lds, st, tab, nscene, skip, act);     \
+    return hipGetLastError();
+  switch (rs) {
+    VC_RS(2) VC_RS(3) VC_RS(4) VC_RS(5) VC_RS(6) VC_RS(7) VC_RS(8) VC_RS(9) VC_RS(10)
+    default: break;
+  }
+#undef VC_RS
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_ypass(void* data, const YArgs& a, const void* tw, const uint8_t* lflag, const uint8_t* pflag,
+                        int nplanes, int nthr, hipStream_t st) {
+  // every assumption of the kernel (plan, tile, flag rows, 32-bit slab offsets, LDS)
+  size_t lds = 0;
+  if (!ypass_args_ok<T>(a, nthr, lflag != nullptr, &lds)) return hipErrorInvalidValue;
+  const int rs = (int)((a.radpack >> (5 * (a.nst - 1))) & 31u);
   dim3 grid((a.ncols + a.ncol - 1) / a.ncol, nplanes, a.cs.n * a.nrhs);
 #define VC_RS(RR)                                                                                \
   case RR:                                                                                       \
