@@ -666,8 +666,8 @@ __device__ __forceinline__ void block_sum_chunks(const double* __restrict__ part
 }
 
 // One Arnoldi step's classical Gram-Schmidt (applied twice) and norm in three launches:
-//   A  h1 = V^T w                          (partials, the last block of each
-//                                           (vector block, column) adds the chunks)
+//   A  h1 = V^T w                          (each block all k vectors on its row chunk;
+//                                           the last block of each column adds the chunks)
 //   B  w -= V h1; h2 = V^T w               (the last block of each column adds the chunks)
 //   C  w -= V h2; |w|; Arnoldi/Givens step  (the last block of the launch does the step)
 // "Last block" = the block whose increment of a device counter completes the count;
@@ -694,38 +694,42 @@ k_cgs_dot(const double* __restrict__ V, int64_t ldv, int64_t N, int64_t chunk_ro
           const int* __restrict__ active, unsigned* __restrict__ cnt) {
   __shared__ double red[kDotBlk][kRedThreads / 64];
   __shared__ int flag;
-  const int chunk = blockIdx.x, kb = blockIdx.y, r = blockIdx.z, nchunk = gridDim.x;
+  const int chunk = blockIdx.x, r = blockIdx.y, nchunk = gridDim.x;
   if (active && !active[r]) return;   // every block of this column returns: its count stays 0
-  const int i0 = kb * kDotBlk;
-  const int nb = k - i0 < kDotBlk ? k - i0 : kDotBlk;
   const int64_t n0 = (int64_t)chunk * chunk_rows;
   const int64_t n1 = n0 + chunk_rows < N ? n0 + chunk_rows : N;
   const double* wr = w + (int64_t)r * N;
-  const double* v0 = V + (int64_t)i0 * ldv + (int64_t)r * N;
-  double acc[kDotBlk];
-#pragma unroll
-  for (int q = 0; q < kDotBlk; ++q) acc[q] = 0.0;
-  for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
-    const double wn = wr[n];
-#pragma unroll
-    for (int q = 0; q < kDotBlk; ++q)
-      if (q < nb) acc[q] += v0[(int64_t)q * ldv + n] * wn;
-  }
+  const double* vr = V + (int64_t)r * N;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // all k basis vectors against this chunk of w, kDotBlk at a time (w re-read from L1/L2)
+  for (int i0 = 0; i0 < k; i0 += kDotBlk) {
+    const int nb = k - i0 < kDotBlk ? k - i0 : kDotBlk;
+    double acc[kDotBlk];
 #pragma unroll
-  for (int q = 0; q < kDotBlk; ++q) {
-    const double t = wave_sum(acc[q]);
-    if (lane == 0) red[q][wv] = t;
+    for (int q = 0; q < kDotBlk; ++q) acc[q] = 0.0;
+    for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
+      const double wn = wr[n];
+#pragma unroll
+      for (int q = 0; q < kDotBlk; ++q)
+        if (q < nb) acc[q] += vr[(int64_t)(i0 + q) * ldv + n] * wn;
+    }
+#pragma unroll
+    for (int q = 0; q < kDotBlk; ++q) {
+      const double t = wave_sum(acc[q]);
+      if (lane == 0) red[q][wv] = t;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nb) {
+      double t = 0.0;
+      for (int u = 0; u < (int)(blockDim.x >> 6); ++u) t += red[threadIdx.x][u];
+      partial[((int64_t)chunk * nrhs + r) * k + i0 + threadIdx.x] = t;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  if ((int)threadIdx.x < nb) {
-    double t = 0.0;
-    for (int u = 0; u < (int)(blockDim.x >> 6); ++u) t += red[threadIdx.x][u];
-    partial[((int64_t)chunk * nrhs + r) * k + i0 + threadIdx.x] = t;
-  }
-  if (last_block(cnt + (int64_t)kb * nrhs + r, (unsigned)nchunk, &flag))
-    block_sum_chunks(partial + (int64_t)r * k + i0, nchunk, (int64_t)nrhs * k, 1, nb, red, h + (int64_t)r * ldh + i0,
-                     1);
+  if (last_block(cnt + r, (unsigned)nchunk, &flag))
+    for (int i0 = 0; i0 < k; i0 += kDotBlk)
+      block_sum_chunks(partial + (int64_t)r * k + i0, nchunk, (int64_t)nrhs * k, 1,
+                       k - i0 < kDotBlk ? k - i0 : kDotBlk, red, h + (int64_t)r * ldh + i0, 1);
 }
 
 __global__ void __launch_bounds__(kRedThreads)
@@ -836,11 +840,10 @@ hipError_t launch_cgs_step(const double* V, int64_t ldv, int64_t N, int k, doubl
   if (nrhs > kRedThreads || k <= 0) return hipErrorInvalidValue;
   const int64_t rows = cgs_chunk(N, nrhs);
   const int nchunk = (int)((N + rows - 1) / rows);
-  const int nkb = (k + kDotBlk - 1) / kDotBlk;
-  unsigned* cA = cnt;                                  // [nkb][nrhs]
+  unsigned* cA = cnt;                                  // [nrhs]
   unsigned* cB = cnt + cgs_counter_size_a(k, nrhs);    // [nrhs]
   unsigned* cC = cB + nrhs;                            // [1]
-  hipLaunchKernelGGL(k_cgs_dot, dim3(nchunk, nkb, nrhs), dim3(kRedThreads), 0, st, V, ldv, N, rows, k, w, nrhs, h1,
+  hipLaunchKernelGGL(k_cgs_dot, dim3(nchunk, nrhs), dim3(kRedThreads), 0, st, V, ldv, N, rows, k, w, nrhs, h1,
                      (int64_t)ldh, partial, act_step, cA);
   hipLaunchKernelGGL(k_cgs_update_dot, dim3(nchunk, nrhs), dim3(kRedThreads), 0, st, V, ldv, N, rows, k, h1,
                      (int64_t)ldh, w, nrhs, h2, partial, act_step, cB);
