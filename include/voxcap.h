@@ -287,6 +287,55 @@ vc_status vc_pass_times(vc_problem *p, double ms[5], int32_t launches[5], double
 vc_status vc_tuning_save(vc_problem *p, const char *path, int32_t *n_saved);
 vc_status vc_tuning_load(vc_problem *p, const char *path, int32_t *n_loaded);
 
+/* ---- Toeplitz setup path (Sec. II.C, Tab. I) ----
+ * The block Toeplitz tensors of App. B are computed once over a largest grid of
+ * nmax[0] x nmax[1] x nmax[2] voxels, Tucker-compressed (eq. 13) and kept (in memory, or
+ * on disk through save / load); a problem's setup can then restore them cropped to its
+ * own grid and embed them in its circulants instead of evaluating the panel integrals.
+ *
+ * Pairs are numbered as in vc_tucker_info: 0..5 = eq. (5) xx yy zz xy xz yz, 6 + 3a + b
+ * = eq. (6) with observer normal a and source normal b.  Pair q is stored as its octant
+ * T_q[t0][t1][t2] = K_q(d) at the non-negative centre offsets d_a = t_a + h_a,
+ * t_a = 0..n_a, where h_a = 1/2 on the two normal axes of an orthogonal pair and 0
+ * otherwise (row-major, t2 fastest; (n0+1)(n1+1)(n2+1) doubles).  Eq. (5) is even in
+ * every offset component and eq. (6) odd in d_a and even in the rest, so the octant
+ * gives every lag of a grid of n voxels.  A grid of n <= nmax voxels uses the leading
+ * n_a + 1 rows of each Tucker factor, so its restored tensor carries no error beyond
+ * the compression's: ||T - T_restored||_F <= tol ||T over nmax||_F per pair.  Values
+ * are dimensionless (voxel edge 1), so one cache serves every voxel size. */
+typedef struct vc_toeplitz_cache vc_toeplitz_cache;
+
+/* Fills the 15 octants over nmax (1..4096 per axis) on `device` and compresses each with
+ * relative tolerance tol in (0, 1) (FP64, sequentially truncated HOSVD).  Synchronizes
+ * hip_stream.  *out is owned by the caller (vc_toeplitz_cache_destroy). */
+vc_status vc_toeplitz_cache_build(const int32_t nmax[3], double tol, int device, void *hip_stream,
+                                  vc_toeplitz_cache **out);
+vc_status vc_toeplitz_cache_destroy(vc_toeplitz_cache *c);
+/* Binary file: 8-byte tag, nmax, pair count, tol, then per pair its ranks, core and the
+ * three factors as host-order doubles.  load checks the tag, sizes and ranks
+ * (VC_ERR_ARG on any mismatch or a truncated file) and uploads to `device`. */
+vc_status vc_toeplitz_cache_save(const vc_toeplitz_cache *c, const char *path);
+vc_status vc_toeplitz_cache_load(const char *path, int device, vc_toeplitz_cache **out);
+/* Any output may be NULL.  ranks: 3 per pair; stored_numbers: sum of core and factor
+ * sizes; seconds: wall time of the build (fill and compression) or of the load. */
+vc_status vc_toeplitz_cache_info(const vc_toeplitz_cache *c, int32_t nmax[3], double *tol,
+                                 int32_t ranks[45], double *stored_numbers, double *seconds);
+/* out_dev: (n0+1)(n1+1)(n2+1) doubles on the cache's device, the restored octant of pair
+ * `pair` for a grid of n voxels (1 <= n_a <= nmax_a, else VC_ERR_ARG).  Synchronizes. */
+vc_status vc_toeplitz_cache_restore(const vc_toeplitz_cache *c, int32_t pair, const int32_t n[3],
+                                    double *out_dev, void *hip_stream);
+/* The same octant evaluated from the panel integrals (no cache), for comparison. */
+vc_status vc_toeplitz_octant(int32_t pair, const int32_t n[3], int device, double *out_dev,
+                             void *hip_stream);
+/* Later vc_setup calls on p take the Toeplitz tensors from c (NULL: the panel integrals,
+ * the default).  c must cover p's grid and live on p's device, and must stay alive until
+ * those vc_setup calls have returned.  The preconditioner blocks are evaluated from the
+ * panel integrals either way. */
+vc_status vc_setup_toeplitz_source(vc_problem *p, const vc_toeplitz_cache *c);
+/* Wall time of the last vc_setup, and the part of it spent producing the Toeplitz
+ * tensors in circulant form (the integrals, or restore + crop + embed). */
+vc_status vc_setup_time(const vc_problem *p, double *total_s, double *toeplitz_s);
+
 const char *vc_status_string(vc_status s);
 const char *vc_last_error(void);
 

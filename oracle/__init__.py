@@ -14,11 +14,13 @@ What it computes is the plain definition of the paper's method (Sec. II.A):
 * the dense system of eq. (4) with the jump term of eq. (7), solved by LU;
 * the capacitance matrix of eq. (8) with the free-charge scaling of Sec. II.A;
 * the adjoint derivative of C with respect to block permittivities;
-* the Tucker format of eq. (13) by its definition (tucker.py).
+* the Tucker format of eq. (13) by its definition (tucker.py);
+* the Toeplitz octants of App. B, compressed over a largest grid and restored for a
+  smaller one (toeplitz.py, Sec. II.C).
 
 Dimensionless units: voxel edge 1 and 4*pi*eps0 = 1 (scaling of App. C).
 """
-from . import panels, integrals, dense, tucker  # noqa: F401
+from . import panels, integrals, dense, tucker, toeplitz  # noqa: F401
 from .panels import panelize, GeometryError  # noqa: F401
 from .dense import (assemble, rhs, solve_capacitance, mvp, capacitance_gradient,  # noqa: F401
                     capacitance_from_rho, free_charge_weights, EPS0)

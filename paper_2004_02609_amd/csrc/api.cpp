@@ -146,6 +146,14 @@ vc_status vc_setup(vc_problem* p, const vc_setup_opts* opts, void* stream) {
   return VC_OK;
 }
 
+vc_status vc_setup_time(const vc_problem* p, double* total_s, double* toeplitz_s) {
+  if (!p) { set_error("null problem"); return VC_ERR_ARG; }
+  if (!p->setup_done) { set_error("vc_setup has not run"); return VC_ERR_STATE; }
+  if (total_s) *total_s = p->t_setup;
+  if (toeplitz_s) *toeplitz_s = p->t_toeplitz;
+  return VC_OK;
+}
+
 vc_status vc_apply(vc_problem* p, int transpose, vc_precision prec, const double* x, double* y, int32_t nrhs,
                    void* stream) {
   VC_CHECK_PROBLEM(p);

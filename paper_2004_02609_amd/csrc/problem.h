@@ -97,9 +97,23 @@ struct Precond {
   std::vector<double> h_blocks;
 };
 
+constexpr int kToeplitzPairs = 15;   // 6 pairs of eq. (5), 9 of eq. (6)
+
 struct PackData;   // several problems solved as one (pack.cpp)
 
 }  // namespace vc
+
+// Tucker-compressed Toeplitz octants of every pair over a largest grid (toeplitz.cpp):
+// device core and factors (FP64) plus their host copies for saving
+struct vc_toeplitz_cache {
+  int device = 0;
+  int nmax[3] = {0, 0, 0};
+  double tol = 0.0;
+  double build_s = 0.0;   // seconds taken by the build or the load
+  vc::TuckerPair pair[vc::kToeplitzPairs];
+  std::vector<double> hS[vc::kToeplitzPairs];
+  std::vector<double> hU[vc::kToeplitzPairs][3];
+};
 
 struct vc_problem {
   int device = 0;
@@ -124,6 +138,10 @@ struct vc_problem {
   std::vector<double> diag;         // eq. (7) term, +axis convention (0 on conductor panels)
   std::vector<int32_t> cond_ptr, cond_panels;   // conductor panels grouped by id
   std::vector<double> weight;       // eps_adj on conductor panels
+  // where setup takes the Toeplitz tensors from: nullptr = the panel integrals, else a
+  // cache restored and cropped to this grid (vc_setup_toeplitz_source)
+  const vc_toeplitz_cache* tz_cache = nullptr;
+  double t_toeplitz = 0.0;          // seconds of the last setup spent on the Toeplitz tensors
   // setup state
   bool setup_done = false;
   bool hip_failed = false;
@@ -248,6 +266,15 @@ vc_status choose_sizes(vc_problem* p, const int32_t* fft_size);
 vc_status build_spectra(vc_problem* p, int want64, int want32, double tucker_tol, hipStream_t st);
 vc_status build_precond(vc_problem* p, hipStream_t st);
 vc_status build_precond_full(vc_problem* p, hipStream_t st);
+// FP64 sequentially truncated HOSVD of a device tensor (D1 x D2 x D3 row-major) into
+// tp.S64 / tp.U64 (tucker.cpp)
+vc_status tucker_compress_tensor(const double* X, int D1, int D2, int D3, double tol, TuckerPair& tp,
+                                 hipStream_t st);
+void gauss_legendre_table(std::vector<double>& gl);
+// Toeplitz octants (toeplitz.cpp): n[a] voxels per axis -> (n0+1)(n1+1)(n2+1) doubles
+vc_status toeplitz_restore(const vc_toeplitz_cache* C, int q, const int n[3], double* out, hipStream_t st);
+vc_status toeplitz_octant(int q, const int n[3], double* out, const double* gl, hipStream_t st);
+void pair_axes(int q, int* a, int* b, int* want);
 vc_status tucker_begin(vc_problem* p, double tol);
 vc_status tucker_compress_pair(vc_problem* p, const double* X, hipStream_t st);
 vc_status tucker_end(vc_problem* p);

@@ -58,7 +58,7 @@ void pair_axes(int q, int* a, int* b, int* want) {
   *want = 1;
 }
 
-static void gauss_legendre_table(std::vector<double>& gl) {
+void gauss_legendre_table(std::vector<double>& gl) {
   gl.assign(11 * 24, 0.0);
   for (int n = 1; n <= 10; ++n) {
     for (int i = 0; i < n; ++i) {
@@ -206,6 +206,18 @@ vc_status build_spectra(vc_problem* P, int want64, int want32, double tucker_tol
   }
   VC_HIP(circ.alloc((size_t)Mx * My * Mz * sizeof(double)));
   VC_HIP(spec.alloc((size_t)Mx * My * H * 2 * sizeof(double)));
+  // Toeplitz source: the panel integrals on this grid, or a cache's octants cropped to it
+  const vc_toeplitz_cache* tzc = P->tz_cache;
+  const int ngrid[3] = {P->nx, P->ny, P->nz};
+  DevMem oct;
+  if (tzc) {
+    if (tzc->device != P->device || ngrid[0] > tzc->nmax[0] || ngrid[1] > tzc->nmax[1] || ngrid[2] > tzc->nmax[2]) {
+      set_error("the Toeplitz cache does not cover this grid on this device");
+      return VC_ERR_ARG;
+    }
+    VC_HIP(oct.alloc((size_t)(ngrid[0] + 1) * (ngrid[1] + 1) * (ngrid[2] + 1) * sizeof(double)));
+  }
+  P->t_toeplitz = 0.0;
   VC_HIP(resid.alloc(sizeof(double)));
   VC_HIP(hipMemsetAsync(resid.p, 0, sizeof(double), st));
   const int n[3] = {P->nx, P->ny, P->nz};
@@ -221,7 +233,19 @@ vc_status build_spectra(vc_problem* P, int want64, int want32, double tucker_tol
       fa.ns[ax] = n[ax] + (ax == b);
     }
     fa.scale = scale;
-    VC_HIP(launch_fill_circulant(circ.as<double>(), fa, P->d_gl.as<double>(), st));
+    VC_HIP(hipStreamSynchronize(st));
+    const auto tt0 = std::chrono::steady_clock::now();
+    if (tzc) {
+      if ((s = toeplitz_restore(tzc, q, ngrid, oct.as<double>(), st)) != VC_OK) return s;
+      OctArgs oa{};
+      oa.alpha = a; oa.beta = b; oa.want = want;
+      for (int ax = 0; ax < 3; ++ax) oa.D[ax] = ngrid[ax] + 1;
+      VC_HIP(launch_embed_octant(circ.as<double>(), oct.as<double>(), fa, oa, st));
+    } else {
+      VC_HIP(launch_fill_circulant(circ.as<double>(), fa, P->d_gl.as<double>(), st));
+    }
+    VC_HIP(hipStreamSynchronize(st));
+    P->t_toeplitz += std::chrono::duration<double>(std::chrono::steady_clock::now() - tt0).count();
     int ncol, nthr;
     if (!pick_tile(Mz, 16, Tune<double>::emax, (Mx * My + 1) / 2, &ncol, &nthr, kLdsBudget, 1)) return VC_ERR_ARG;
     VC_HIP(launch_zr2c_dense(circ.as<double>(), spec.p, Mx * My, H, P->t64.ax[2].plan, P->t64.ax[2].tw.p, ncol, nthr, st));

@@ -172,6 +172,72 @@ hipError_t launch_fill_circulant(double* C, const FillArgs& a, const double* gl,
   return hipGetLastError();
 }
 
+// Toeplitz octant of one pair (App. B): the kernel at the non-negative centre offsets
+// d_a = t_a + h_a, t_a = 0..D_a-1, with h_a = 1/2 on the two normal axes of an
+// orthogonal pair (their panel centres sit half a voxel apart there) and 0 elsewhere.
+// Every lag of a grid with n_a <= D_a - 1 voxels maps onto one of these offsets.
+__global__ void k_fill_octant(double* __restrict__ T, OctArgs a, const double* __restrict__ gl) {
+  const int64_t total = (int64_t)a.D[0] * a.D[1] * a.D[2];
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  double d[3];
+  d[2] = (double)(id % a.D[2]);
+  d[1] = (double)((id / a.D[2]) % a.D[1]);
+  d[0] = (double)(id / ((int64_t)a.D[2] * a.D[1]));
+  if (a.alpha != a.beta) {
+    d[a.alpha] += 0.5;
+    d[a.beta] += 0.5;
+  }
+  T[id] = panel_kernel(a.alpha, a.beta, d, a.want, gl);
+}
+
+hipError_t launch_fill_octant(double* T, const OctArgs& a, const double* gl, hipStream_t st) {
+  const int64_t total = (int64_t)a.D[0] * a.D[1] * a.D[2];
+  if (total == 0) return hipSuccess;
+  const int nt = 256;
+  hipLaunchKernelGGL(k_fill_octant, dim3((unsigned)((total + nt - 1) / nt)), dim3(nt), 0, st, T, a, gl);
+  return hipGetLastError();
+}
+
+// Circulant embedding of one pair read from its octant T (D0 x D1 x D2): the lags of
+// k_fill_circulant, each taken at |d| (the kernel of eq. 5 is even in every offset
+// component; its derivative of eq. 6 is odd in d_alpha and even in the other two).
+// Offsets beyond the octant (the host sizes it so that none occurs) are written as NaN.
+__global__ void k_embed_octant(double* __restrict__ C, const double* __restrict__ T, FillArgs a, OctArgs o) {
+  const int64_t total = (int64_t)a.Mx * a.My * a.Mz;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  const int j[3] = {(int)(id / ((int64_t)a.Mz * a.My)), (int)((id / a.Mz) % a.My), (int)(id % a.Mz)};
+  const int M[3] = {a.Mx, a.My, a.Mz};
+  int t[3];
+  bool neg_alpha = false;
+  for (int ax = 0; ax < 3; ++ax) {
+    int l;
+    if (j[ax] <= a.no[ax] - 1) l = j[ax];
+    else if (j[ax] >= M[ax] - (a.ns[ax] - 1)) l = j[ax] - M[ax];
+    else { C[id] = 0.0; return; }
+    // d = l - 1/2 on the observer normal, l + 1/2 on the source normal of an
+    // orthogonal pair, l elsewhere; t = |d| - h
+    int ta;
+    bool neg;
+    if (a.alpha != a.beta && ax == a.alpha) { neg = l <= 0; ta = neg ? -l : l - 1; }
+    else if (a.alpha != a.beta && ax == a.beta) { neg = l < 0; ta = neg ? -l - 1 : l; }
+    else { neg = l < 0; ta = neg ? -l : l; }
+    if (ax == a.alpha) neg_alpha = neg;
+    if (ta >= o.D[ax]) { C[id] = __builtin_nan(""); return; }
+    t[ax] = ta;
+  }
+  const double v = T[((int64_t)t[0] * o.D[1] + t[1]) * o.D[2] + t[2]];
+  C[id] = a.scale * ((a.want == 1 && neg_alpha) ? -v : v);
+}
+
+hipError_t launch_embed_octant(double* C, const double* T, const FillArgs& a, const OctArgs& o, hipStream_t st) {
+  const int64_t total = (int64_t)a.Mx * a.My * a.Mz;
+  const int nt = 256;
+  hipLaunchKernelGGL(k_embed_octant, dim3((unsigned)((total + nt - 1) / nt)), dim3(nt), 0, st, C, T, a, o);
+  return hipGetLastError();
+}
+
 __global__ void k_kernel_table(const double* __restrict__ dd, int n, int alpha, int beta, int want,
                                double* __restrict__ out, const double* __restrict__ gl) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -121,6 +121,16 @@ static vc_status compress_one(rocblas_handle h, const double* X, int D1, int D2,
   return VC_OK;
 }
 
+vc_status tucker_compress_tensor(const double* X, int D1, int D2, int D3, double tol, TuckerPair& tp,
+                                 hipStream_t st) {
+  rocblas_handle h = nullptr;
+  if (rocblas_create_handle(&h) != rocblas_status_success) { set_error("rocblas_create_handle failed"); return VC_ERR_HIP; }
+  rocblas_set_stream(h, st);
+  const vc_status s = compress_one(h, X, D1, D2, D3, tol, tp, st);
+  rocblas_destroy_handle(h);
+  return s;
+}
+
 vc_status tucker_begin(vc_problem* P, double tol) {
   P->tucker_tol = tol;
   P->tk.clear();

@@ -98,6 +98,16 @@ _sig = {
     "vc_xpass_set": (C.c_int, [_P, C.c_int, C.c_int, C.c_int32, C.POINTER(C.c_int32)]),
     "vc_tuning_save": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int32)]),
     "vc_tuning_load": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int32)]),
+    "vc_toeplitz_cache_build": (C.c_int, [C.POINTER(C.c_int32), C.c_double, C.c_int, _P, C.POINTER(_P)]),
+    "vc_toeplitz_cache_destroy": (C.c_int, [_P]),
+    "vc_toeplitz_cache_save": (C.c_int, [_P, C.c_char_p]),
+    "vc_toeplitz_cache_load": (C.c_int, [C.c_char_p, C.c_int, C.POINTER(_P)]),
+    "vc_toeplitz_cache_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "vc_toeplitz_cache_restore": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32), C.c_void_p, _P]),
+    "vc_toeplitz_octant": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.c_int, C.c_void_p, _P]),
+    "vc_setup_toeplitz_source": (C.c_int, [_P, _P]),
+    "vc_setup_time": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "vc_status_string": (C.c_char_p, [C.c_int]),
     "vc_last_error": (C.c_char_p, []),
 }
@@ -233,6 +243,123 @@ def vc_tucker_info(h):
     return {"npairs": n.value, "ranks": r, "stored_numbers": st.value, "full_numbers": full.value,
             "compression_ratio": (full.value / st.value) if st.value > 0 else None,
             "rebuild_ms": ms.value, "rebuilds": cnt.value}
+
+
+def _n3(n):
+    n = [int(v) for v in n]
+    if len(n) != 3:
+        raise ValueError("three sizes expected")
+    return (C.c_int32 * 3)(*n)
+
+
+def vc_toeplitz_cache_build(nmax, tol, device=0, stream=None):
+    out = _P()
+    _check(_lib.vc_toeplitz_cache_build(_n3(nmax), float(tol), int(device), _stream(stream), C.byref(out)),
+           "vc_toeplitz_cache_build")
+    return out
+
+
+def vc_toeplitz_cache_destroy(h):
+    _check(_lib.vc_toeplitz_cache_destroy(h), "vc_toeplitz_cache_destroy")
+
+
+def vc_toeplitz_cache_save(h, path):
+    _check(_lib.vc_toeplitz_cache_save(h, os.fsencode(path)), "vc_toeplitz_cache_save")
+
+
+def vc_toeplitz_cache_load(path, device=0):
+    out = _P()
+    _check(_lib.vc_toeplitz_cache_load(os.fsencode(path), int(device), C.byref(out)), "vc_toeplitz_cache_load")
+    return out
+
+
+def vc_toeplitz_cache_info(h):
+    nmax = (C.c_int32 * 3)()
+    tol, stored, secs = C.c_double(0), C.c_double(0), C.c_double(0)
+    ranks = (C.c_int32 * 45)()
+    _check(_lib.vc_toeplitz_cache_info(h, nmax, C.byref(tol), ranks, C.byref(stored), C.byref(secs)),
+           "vc_toeplitz_cache_info")
+    nm = tuple(nmax)
+    full = 15.0 * (nm[0] + 1) * (nm[1] + 1) * (nm[2] + 1)
+    return {"nmax": nm, "tol": tol.value, "ranks": [tuple(ranks[3 * q:3 * q + 3]) for q in range(15)],
+            "stored_numbers": stored.value, "full_numbers": full,
+            "compression_ratio": full / stored.value if stored.value > 0 else None, "seconds": secs.value}
+
+
+def vc_toeplitz_cache_restore(h, pair, n, out, stream=None):
+    _check(_lib.vc_toeplitz_cache_restore(h, int(pair), _n3(n), _ptr(out), _stream(stream)),
+           "vc_toeplitz_cache_restore")
+
+
+def vc_toeplitz_octant(pair, n, out, device=0, stream=None):
+    _check(_lib.vc_toeplitz_octant(int(pair), _n3(n), int(device), _ptr(out), _stream(stream)), "vc_toeplitz_octant")
+
+
+def vc_setup_toeplitz_source(h, cache):
+    _check(_lib.vc_setup_toeplitz_source(h, cache), "vc_setup_toeplitz_source")
+
+
+def vc_setup_time(h):
+    tot, tz = C.c_double(0), C.c_double(0)
+    _check(_lib.vc_setup_time(h, C.byref(tot), C.byref(tz)), "vc_setup_time")
+    return {"total_s": tot.value, "toeplitz_s": tz.value}
+
+
+def _octant_tensor(n, device):
+    import torch
+    n = [int(v) for v in n]
+    return torch.empty((n[0] + 1, n[1] + 1, n[2] + 1), dtype=torch.float64, device=f"cuda:{device}")
+
+
+def toeplitz_octant(pair, n, device=0):
+    """Octant of Toeplitz pair `pair` for a grid of n voxels, from the panel integrals:
+    a float64 CUDA tensor (n0+1, n1+1, n2+1)."""
+    import torch
+    out = _octant_tensor(n, device)
+    vc_toeplitz_octant(pair, n, out, device, torch.cuda.current_stream(device))
+    return out
+
+
+class ToeplitzCache:
+    """Owning wrapper of a vc_toeplitz_cache: the Tucker-compressed Toeplitz octants of
+    every pair over a largest grid."""
+
+    def __init__(self, handle, device):
+        self._h = handle
+        self.device = device
+
+    @classmethod
+    def build(cls, nmax, tol, device=0):
+        import torch
+        return cls(vc_toeplitz_cache_build(nmax, tol, device, torch.cuda.current_stream(device)), device)
+
+    @classmethod
+    def load(cls, path, device=0):
+        return cls(vc_toeplitz_cache_load(path, device), device)
+
+    def save(self, path):
+        vc_toeplitz_cache_save(self._h, path)
+
+    def info(self):
+        return vc_toeplitz_cache_info(self._h)
+
+    def restore(self, pair, n):
+        """Restored octant of pair `pair` cropped to a grid of n voxels (float64 CUDA)."""
+        import torch
+        out = _octant_tensor(n, self.device)
+        vc_toeplitz_cache_restore(self._h, pair, n, out, torch.cuda.current_stream(self.device))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            vc_toeplitz_cache_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _handles(handles):
@@ -452,6 +579,15 @@ class Problem:
     def setup(self, **kw):
         vc_setup(self._h, **kw)
         return self
+
+    def set_toeplitz_source(self, cache):
+        """Later setups take the Toeplitz tensors from `cache` (a ToeplitzCache), or from
+        the panel integrals when None."""
+        vc_setup_toeplitz_source(self._h, None if cache is None else cache._h)
+        self._toeplitz_cache = cache   # kept alive for the setups that use it
+
+    def setup_time(self):
+        return vc_setup_time(self._h)
 
     def apply(self, x, y=None, transpose=False, prec="fp64", stream=None):
         """y = A x for x a (nrhs, N) float64 cuda tensor."""
