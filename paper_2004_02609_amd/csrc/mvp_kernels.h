@@ -251,13 +251,6 @@ struct FillArgs {
   double scale;            // folded inverse-FFT normalisation 1/(Mx My Mz)
 };
 hipError_t launch_fill_circulant(double* C, const FillArgs& a, const double* gl_nodes, hipStream_t st);
-// Toeplitz octant of one pair: D[a] non-negative offsets per axis (k_fill_octant)
-struct OctArgs {
-  int alpha, beta, want;
-  int D[3];
-};
-hipError_t launch_fill_octant(double* T, const OctArgs& a, const double* gl_nodes, hipStream_t st);
-hipError_t launch_embed_octant(double* C, const double* T, const FillArgs& a, const OctArgs& o, hipStream_t st);
 hipError_t launch_zr2c_dense(const double* in, void* out, int nlines, int H, const AxisPlan& pl, const void* tw,
                              int ncol, int nthr, hipStream_t st);
 struct ExtractArgs {

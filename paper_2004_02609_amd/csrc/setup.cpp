@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "mvp_kernels.h"
+#include "octant_kernels.h"
 #include "problem.h"
 
 namespace vc {

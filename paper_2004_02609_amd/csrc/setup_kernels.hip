@@ -18,6 +18,7 @@
 
 #include "fft_core.hpp"
 #include "mvp_kernels.h"
+#include "octant_kernels.h"
 
 namespace vc {
 
