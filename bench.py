@@ -312,7 +312,32 @@ def batch_run(args):
     t_seq = time.perf_counter() - t0
     diff = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(Cb, Cs))
     inf = pk.info()
+    cached = None
+    if args.toeplitz_tol > 0:
+        # the same scenes set up from one Toeplitz cache over the batch's largest grid
+        nmax = tuple(max(int(s["cond_id"].shape[a]) for s in ss) for a in range(3))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cache = voxcap.ToeplitzCache.build(nmax, args.toeplitz_tol)
+        t_build = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        probs_c = []
+        for s in ss:
+            Pc = voxcap.Problem.from_scene(s)
+            Pc.set_toeplitz_source(cache)
+            probs_c.append(Pc.setup())
+        torch.cuda.synchronize()
+        t_setup_c = time.perf_counter() - t0
+        cache.close()
+        pk_c = voxcap.Pack(probs_c)
+        Cc, _ = pk_c.capacitance(prec="mixed", rtol=1e-9)
+        dc = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(Cc, Cb))
+        cached = {"nmax": list(nmax), "tol": args.toeplitz_tol, "cache_build_s": t_build, "setup_s": t_setup_c,
+                  "setup_speedup": t_setup / t_setup_c, "max_rel_diff_C_vs_direct": dc}
+        pk_c.close()
+        del probs_c
     return {"scenes": len(ss), "panels_total": int(sum(P.N for P in probs)), "pack": inf,
+            "setup_from_toeplitz_cache": cached,
             "ir_steps": int(stb[0]["ir_steps"]), "max_iters": int(max(max(t["iters"]) for t in stb)),
             "conductors_total": int(sum(P.m for P in probs)), "setup_s": t_setup,
             "batched_solve_s": t_batch, "sequential_solve_s": t_seq, "speedup": t_seq / t_batch,

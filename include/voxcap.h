@@ -329,8 +329,9 @@ vc_status vc_toeplitz_octant(int32_t pair, const int32_t n[3], int device, doubl
                              void *hip_stream);
 /* Later vc_setup calls on p take the Toeplitz tensors from c (NULL: the panel integrals,
  * the default).  c must cover p's grid and live on p's device, and must stay alive until
- * those vc_setup calls have returned.  The preconditioner blocks are evaluated from the
- * panel integrals either way. */
+ * those vc_setup calls have returned.  The eq. (14) preconditioner blocks that vc_setup
+ * builds are read from the cache too; the comparison preconditioner of use_precond 3,
+ * built at its first use, evaluates the panel integrals. */
 vc_status vc_setup_toeplitz_source(vc_problem *p, const vc_toeplitz_cache *c);
 /* Wall time of the last vc_setup, and the part of it spent producing the Toeplitz
  * tensors in circulant form (the integrals, or restore + crop + embed). */

@@ -328,15 +328,62 @@ static bool cholesky_inverse(std::vector<double>& A, int n) {
   return true;
 }
 
+// The same tables read from a Toeplitz cache: each pair's octant restored for
+// min(nv_a, n_a) offsets per axis (a panel lag along axis a never exceeds n_a; entries
+// of lags the grid cannot hold stay 0), then every lag's entry taken at |d| with the
+// sign of eq. (6) in d_alpha.  Eq. (5) with a > b reads the octant of (b, a): the
+// kernel is even, so both orders have the same values at the same |d|.
+static vc_status lag_tables_cached(vc_problem* P, const vc_toeplitz_cache* C, int want, std::vector<double>& tab,
+                                   int64_t nl, hipStream_t st) {
+  const int nv[3] = {P->nv[0], P->nv[1], P->nv[2]};
+  const int ng[3] = {P->nx, P->ny, P->nz};
+  int c[3];
+  for (int ax = 0; ax < 3; ++ax) c[ax] = std::min(nv[ax], ng[ax]);
+  const int64_t no = (int64_t)(c[0] + 1) * (c[1] + 1) * (c[2] + 1);
+  DevMem doct;
+  VC_HIP(doct.alloc(no * sizeof(double)));
+  std::vector<double> oct(no);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      const int q = want == 0 ? pair_index_P(std::min(a, b), std::max(a, b)) : pair_index_E(a, b);
+      vc_status s = toeplitz_restore(C, q, c, doct.as<double>(), st);   // synchronizes
+      if (s != VC_OK) return s;
+      VC_HIP(hipMemcpy(oct.data(), doct.p, no * sizeof(double), hipMemcpyDeviceToHost));
+      int64_t t = 0;
+      for (int lx = -nv[0]; lx <= nv[0]; ++lx)
+        for (int ly = -nv[1]; ly <= nv[1]; ++ly)
+          for (int lz = -nv[2]; lz <= nv[2]; ++lz, ++t) {
+            const int l[3] = {lx, ly, lz};
+            int o[3];
+            bool inside = true, neg_a = false;
+            for (int ax = 0; ax < 3; ++ax) {
+              // twice the offset, d = l - 1/2 on the observer normal and l + 1/2 on the
+              // source normal of an orthogonal pair; o = |d| - h
+              const int d2 = 2 * l[ax] + (a != b ? (ax == a ? -1 : (ax == b ? 1 : 0)) : 0);
+              o[ax] = (d2 < 0 ? -d2 : d2) / 2;
+              if (ax == a) neg_a = d2 < 0;
+              inside = inside && o[ax] <= c[ax];
+            }
+            if (!inside) continue;
+            const double v = oct[((int64_t)o[0] * (c[1] + 1) + o[1]) * (c[2] + 1) + o[2]];
+            tab[(size_t)(3 * a + b) * nl + t] = (want == 1 && neg_a) ? -v : v;
+          }
+    }
+  return VC_OK;
+}
+
 // The eq. (5) (want 0) or eq. (6) (want 1) integral for every observer/source normal
 // pair and every index lag in [-nv, nv] per axis: tab[(3 a + b) nl + t], lag t in
-// x-major order over the (2 nv + 1)^3 box of lags.
-static vc_status lag_tables(vc_problem* P, int want, std::vector<double>& tab, int64_t* nl_out, hipStream_t st) {
+// x-major order over the (2 nv + 1)^3 box of lags.  With a Toeplitz cache the values
+// come from its octants, else from the panel integrals.
+static vc_status lag_tables(vc_problem* P, int want, std::vector<double>& tab, int64_t* nl_out, hipStream_t st,
+                            const vc_toeplitz_cache* C = nullptr) {
   const int nvx = P->nv[0], nvy = P->nv[1], nvz = P->nv[2];
   const int ex = 2 * nvx + 1, ey = 2 * nvy + 1, ez = 2 * nvz + 1;
   const int64_t nl = (int64_t)ex * ey * ez;
   *nl_out = nl;
   tab.assign(9 * nl, 0.0);
+  if (C) return lag_tables_cached(P, C, want, tab, nl, st);
   std::vector<double> d(3 * nl);
   DevMem dd, dout;
   VC_HIP(dd.alloc(d.size() * sizeof(double)));
@@ -368,7 +415,8 @@ vc_status build_precond(vc_problem* P, hipStream_t st) {
   int64_t nl = 0;
   std::vector<double> tab;
   {
-    const vc_status ts = lag_tables(P, 0, tab, &nl, st);
+    // the cache is only known to be alive during vc_setup, which is where this runs
+    const vc_status ts = lag_tables(P, 0, tab, &nl, st, P->tz_cache);
     if (ts != VC_OK) return ts;
   }
   // group conductor panels by owning box

@@ -154,3 +154,43 @@ def test_capacitance_from_cache(dev, caches, name, make):
         err = np.abs(C - C_ref).max() / d
         print(name, "tol", tol, "C normwise rel err", err, flush=True)
         assert err < gate, (name, tol, err)
+
+
+def _precond_reference(A, pan, x, nv):
+    """Eq. (14) from the dense oracle matrix: every box of nv voxels solves the block of
+    the conductor panels of its conductor voxels, dielectric panels divide by their
+    diagonal entry."""
+    N = len(pan)
+    cond = pan["kind"] == 0
+    vox = np.stack([pan["i"], pan["j"], pan["k"]], 1).astype(int)
+    vox[np.arange(N), pan["dir"]] -= (pan["eps_lo"] == 0.0).astype(int)
+    box = vox // nv
+    ref = np.zeros_like(x)
+    ref[:, ~cond] = x[:, ~cond] / np.diag(A)[~cond]
+    keys = {}
+    for p in np.nonzero(cond)[0]:
+        keys.setdefault(tuple(box[p]), []).append(p)
+    for idx in keys.values():
+        idx = np.array(idx)
+        ref[:, idx] = np.linalg.solve(A[np.ix_(idx, idx)], x[:, idx].T).T
+    return ref
+
+
+def test_precond_from_cache_matches_dense(dev, caches):
+    """Setup from a cache reads the preconditioner's lag tables from its octants too.
+    The blocks are then within tol of the oracle's, so the apply agrees with the dense
+    block solves to about tol times the blocks' condition number."""
+    from paper_2004_02609_amd import voxcap
+    s = scenes.random_small(9, shape=(11, 7, 13), n_cond=3, n_diel=2)
+    rng = np.random.default_rng(4)
+    for tol, gate in ((1e-12, 1e-9), (1e-6, 1e-3)):
+        P = voxcap.Problem.from_scene(s)
+        P.set_toeplitz_source(caches[tol])
+        P.setup(nv=(4, 4, 4))
+        A, _, _ = oracle_matrix_library_order(s, P.panels())
+        x = rng.standard_normal((2, P.N))
+        y = P.apply_precond(torch.tensor(x, device=dev)).cpu().numpy()
+        ref = _precond_reference(A, P.panels(), x, 4)
+        err = float(np.abs(y - ref).max() / np.abs(ref).max())
+        print("precond from cache, tol", tol, "rel err vs dense blocks", err, flush=True)
+        assert err < gate, (tol, err)
