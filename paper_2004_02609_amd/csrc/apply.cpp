@@ -200,11 +200,12 @@ static vc_status y_pass(vc_problem* P, PrecTables& tb, void* data, void* scratch
     *thr = t;
     return true;
   };
-  auto launch = [&](int impl, int c, void* d) -> hipError_t {
+  auto launch = [&](int impl, int c, int g, void* d) -> hipError_t {
     if (impl == 1) {
       int t = ythr;
       ya.ncol = c > 0 && ytile(c, &t) ? c : ydef;
       if (ya.ncol == ydef) t = ythr;
+      ya.xg = g;
       return launch_ypass<T>(d, ya, tb.ax[1].tw.p, lflag, pflag, n1x, t, st);
     }
     return launch_strided<T>(d, sa, cset, n1x, tb.ax[1].plan, tb.ax[1].tw.p, lflag, pflag, nthr, st);
@@ -212,17 +213,17 @@ static vc_status y_pass(vc_problem* P, PrecTables& tb, void* data, void* scratch
   const int key = (nrhs << 3) | (transpose << 2) | (inverse << 1) | (sizeof(T) == 8 ? 1 : 0);
   auto it = P->y_choice.find(key);
   if (it == P->y_choice.end()) {
-    vc_problem::YChoice ch{(yok && ydef * eb >= 32) ? 1 : 0, false, {0.0, 0.0}, 0};
+    vc_problem::YChoice ch{(yok && ydef * eb >= 32) ? 1 : 0, false, {0.0, 0.0}, 0, 1};
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     VC_HIP(hipStreamIsCapturing(st, &cap));
     if (P->autotune && yok && cap == hipStreamCaptureStatusNone) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       VC_HIP(hipEventCreate(&e0));
       VC_HIP(hipEventCreate(&e1));
-      auto timeit = [&](int impl, int c, double* out) -> vc_status {
-        VC_HIP(launch(impl, c, scratch));
+      auto timeit = [&](int impl, int c, int g, double* out) -> vc_status {
+        VC_HIP(launch(impl, c, g, scratch));
         VC_HIP(hipEventRecord(e0, st));
-        for (int rep = 0; rep < 3; ++rep) VC_HIP(launch(impl, c, scratch));
+        for (int rep = 0; rep < 3; ++rep) VC_HIP(launch(impl, c, g, scratch));
         VC_HIP(hipEventRecord(e1, st));
         VC_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -230,28 +231,31 @@ static vc_status y_pass(vc_problem* P, PrecTables& tb, void* data, void* scratch
         *out = ms / 3.0;
         return VC_OK;
       };
-      vc_status ts = timeit(0, 0, &ch.ms[0]);
-      // the register-edge kernel at the heuristic's width and at power-of-two widths
+      vc_status ts = timeit(0, 0, 1, &ch.ms[0]);
+      // the register-edge kernel at the heuristic's width and at power-of-two widths,
+      // each with 1, 2 or 4 consecutive tiles per XCD
       double best = 1e30;
-      int bestc = 0;
-      for (int c : {0, 2, 4, 8, 16, 32}) {
-        int t = 0;
-        if (ts != VC_OK || (c > 0 && (c == ydef || !ytile(c, &t)))) continue;
-        double ms = 0.0;
-        ts = timeit(1, c, &ms);
-        if (ts == VC_OK && ms < best) { best = ms; bestc = c; }
-      }
+      int bestc = 0, bestg = 1;
+      for (int c : {0, 2, 4, 8, 16, 32})
+        for (int g : {1, 2, 4}) {
+          int t = 0;
+          if (ts != VC_OK || (c > 0 && (c == ydef || !ytile(c, &t)))) continue;
+          double ms = 0.0;
+          ts = timeit(1, c, g, &ms);
+          if (ts == VC_OK && ms < best) { best = ms; bestc = c; bestg = g; }
+        }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
       if (ts != VC_OK) return ts;
       ch.ms[1] = best;
       ch.ncol = bestc;
+      ch.xg = bestg;
       ch.impl = ch.ms[1] < ch.ms[0] ? 1 : 0;
       ch.tuned = true;
     }
     it = P->y_choice.emplace(key, ch).first;
   }
-  VC_HIP(launch(it->second.impl, it->second.ncol, data));
+  VC_HIP(launch(it->second.impl, it->second.ncol, it->second.xg, data));
   return VC_OK;
 }
 

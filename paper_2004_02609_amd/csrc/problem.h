@@ -234,6 +234,7 @@ struct vc_problem {
     bool tuned;
     double ms[2];
     int ncol;   // register-edge tile width (0: the heuristic's)
+    int xg;     // consecutive tiles per XCD (YArgs::xg)
   };
   std::map<int, YChoice> y_choice;
   // per-pass timing (measurement)

@@ -96,6 +96,7 @@ _sig = {
     "vc_xpass_candidates": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int32), C.c_int32,
                                       C.POINTER(C.c_int32)]),
     "vc_xpass_set": (C.c_int, [_P, C.c_int, C.c_int, C.c_int32, C.POINTER(C.c_int32)]),
+    "vc_ypass_set": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "vc_tuning_save": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int32)]),
     "vc_tuning_load": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int32)]),
     "vc_toeplitz_cache_build": (C.c_int, [C.POINTER(C.c_int32), C.c_double, C.c_int, _P, C.POINTER(_P)]),
@@ -448,6 +449,11 @@ def vc_xpass_set(h, cfg, prec="fp64", transpose=False, nrhs=1):
     _check(_lib.vc_xpass_set(h, _PREC[prec], int(bool(transpose)), int(nrhs), arr), "vc_xpass_set")
 
 
+def vc_ypass_set(h, kernel, cols=0, xcd_group=1, prec="fp64", transpose=False, inverse=False, nrhs=1):
+    _check(_lib.vc_ypass_set(h, _PREC[prec], int(bool(transpose)), int(bool(inverse)), int(nrhs), int(kernel),
+                             int(cols), int(xcd_group)), "vc_ypass_set")
+
+
 def vc_pass_times(h):
     ms = (C.c_double * 5)()
     n = (C.c_int32 * 5)()
@@ -629,6 +635,9 @@ class Problem:
 
     def xpass_set(self, cfg, prec="fp64", transpose=False, nrhs=1):
         vc_xpass_set(self._h, cfg, prec, transpose, nrhs)
+
+    def ypass_set(self, kernel, cols=0, xcd_group=1, prec="fp64", transpose=False, inverse=False, nrhs=1):
+        vc_ypass_set(self._h, kernel, cols, xcd_group, prec, transpose, inverse, nrhs)
 
     def tucker_info(self):
         """Ranks, compression ratio and rebuild timing of the Tucker-compressed spectra."""

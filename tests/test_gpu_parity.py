@@ -217,6 +217,34 @@ def test_ypass_compiled_plans_match_dense(dev, name, make):
     assert need and all("register-edge" in l for l in need), rep
 
 
+def test_ypass_xcd_groups_match_dense(dev):
+    """The register-edge y pass with 1, 2 or 4 consecutive column tiles per XCD (a
+    permutation of the workgroups over the tiles) and several tile widths, forward and
+    transposed, both precisions, against the dense product.  The grid (9 tiles per row
+    at 4 columns, 6 planes, 6 components, 2 right-hand sides = 648 workgroups) has both
+    the permuted prefix and an unpermuted tail for a group of 4."""
+    s = scenes.random_small(41, shape=(5, 20, 30), n_cond=2, n_diel=1)
+    P = _problem(s, max_rhs=2)
+    A, po, perm = oracle_matrix_library_order(s, P.panels())
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((2, P.N))
+    xt = torch.tensor(x, device=dev)
+    for prec, tol in (("fp64", 1e-11), ("fp32", 2e-5)):
+        for transpose in (False, True):
+            ref = ((A.T if transpose else A) @ x.T).T
+            for cols in (2, 4, 8):
+                for g in (1, 2, 4):
+                    for inverse in (False, True):
+                        P.ypass_set(1, cols, g, prec=prec, transpose=transpose, inverse=inverse, nrhs=2)
+                    y = P.apply(xt, transpose=transpose, prec=prec).cpu().numpy()
+                    err = np.abs(y - ref).max() / np.abs(ref).max()
+                    assert err < tol, (prec, transpose, cols, g, err)
+            print(prec, "T" if transpose else "F", P.fft_size(), "all widths and groups within", tol, flush=True)
+    from paper_2004_02609_amd import voxcap
+    with pytest.raises(voxcap.VoxcapError):
+        P.ypass_set(1, 4, 3, prec="fp32", nrhs=2)
+
+
 @pytest.mark.parametrize("name,make", XPASS_SCENES)
 def test_every_xpass_configuration_matches_dense(dev, name, make):
     """Each launch configuration the autotuner may pick (radix plan x column tile) gives
