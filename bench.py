@@ -160,7 +160,7 @@ def write_traffic(args):
     f, fs, fcp = per_pass(fetch)
     w, ws, wcp = per_pass(write)
     cmd = (f"python bench.py --config {args.config} --prec {args.prec} --steps {args.steps} --warmup {args.warmup} "
-           f"--no-cpu --no-solve --no-other --tucker-tol 0 --batch 0 --calib-copy-mib {args.calib_copy_mib}")
+           f"--no-cpu --no-solve --no-other --tucker-tol 0 --toeplitz-tol 0 --batch 0 --calib-copy-mib {args.calib_copy_mib}")
     res = {"source_hash": kernel_source_hash(), "config": args.config, "prec": args.prec,
            "commands": [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- {cmd}",
                         f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- {cmd}"],
