@@ -628,40 +628,61 @@ hipError_t launch_grad_eps(const int32_t* bptr, const int32_t* ek, const int32_t
 // Rows per partial sum of the three launches below: about 1024 workgroups per launch
 // over all columns, at least one row per thread (so a small system still spreads over
 // the chip instead of a few long per-thread loops).
+// A chunk of w is staged in LDS, so chunks hold at most kCgsMaxRows rows (more chunks
+// on larger systems).
+constexpr int kCgsMaxRows = 4096;
 static int64_t cgs_chunk(int64_t N, int nrhs) {
   int64_t c = (N * (int64_t)nrhs + 1023) / 1024;
   c = (c + kRedThreads - 1) / kRedThreads * kRedThreads;
+  c = c < kCgsMaxRows ? c : kCgsMaxRows;
   return c > kRedThreads ? c : kRedThreads;
 }
 int64_t cgs_partial_size(int64_t N, int kmax, int nrhs) {
   return ((N + kRedThreads - 1) / kRedThreads) * (int64_t)nrhs * kmax;
 }
-// Sum over c < nchunk of part[c * stride + q * qstride] for q < nq (nq <= kDotBlk), by
-// every thread of the block in a fixed order (thread strides, then waves, then LDS
-// slots), so the result does not depend on timing.  Result valid in thread 0..nq-1 as
-// out[q] written by thread q.
-__device__ __forceinline__ void block_sum_chunks(const double* __restrict__ part, int nchunk, int64_t stride,
-                                                 int64_t qstride, int nq, double (*red)[kRedThreads / 64],
-                                                 double* __restrict__ out, int64_t out_stride) {
-  double acc[kDotBlk];
+// out[i] = sum over the chunk's rows t < rows of V_i[n0 + t] wl[t] for i < k, with the
+// chunk of w in LDS (wl).  Wave v takes the basis vectors in groups of kCgsGroup:
+// [G v, G v + G), then G nw further on, and so on; each lane adds the rows lane,
+// lane + 64, ... in order, then one wave reduction per vector (no cross-wave step).
+constexpr int kCgsGroup = 4;
+__device__ __forceinline__ void chunk_dots(const double* __restrict__ vr, int64_t ldv, int64_t n0, int rows, int k,
+                                           const double* __restrict__ wl, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int i0 = wv * kCgsGroup; i0 < k; i0 += nw * kCgsGroup) {
+    double acc[kCgsGroup];
 #pragma unroll
-  for (int q = 0; q < kDotBlk; ++q) acc[q] = 0.0;
-  for (int c = threadIdx.x; c < nchunk; c += blockDim.x)
+    for (int q = 0; q < kCgsGroup; ++q) acc[q] = 0.0;
+    for (int t = lane; t < rows; t += 64) {
+      const double wt = wl[t];
 #pragma unroll
-    for (int q = 0; q < kDotBlk; ++q)
-      if (q < nq) acc[q] += part[(int64_t)c * stride + q * qstride];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __syncthreads();   // red may still be read by a previous use
+      for (int q = 0; q < kCgsGroup; ++q)
+        if (i0 + q < k) acc[q] += vr[(int64_t)(i0 + q) * ldv + n0 + t] * wt;
+    }
 #pragma unroll
-  for (int q = 0; q < kDotBlk; ++q) {
-    const double t = wave_sum(acc[q]);
-    if (lane == 0) red[q][wv] = t;
+    for (int q = 0; q < kCgsGroup; ++q) {
+      const double sum = wave_sum(acc[q]);
+      if (lane == 0 && i0 + q < k) out[i0 + q] = sum;
+    }
   }
-  __syncthreads();
-  if ((int)threadIdx.x < nq) {
-    double t = 0.0;
-    for (int u = 0; u < (int)(blockDim.x >> 6); ++u) t += red[threadIdx.x][u];
-    out[threadIdx.x * out_stride] = t;
+}
+
+// out[i * out_stride] = sum over c < nchunk of part[c * stride + i] for i < k: one thread
+// per vector, chunks added in order (loads issued ahead of the adds)
+__device__ __forceinline__ void sum_chunks_ordered(const double* __restrict__ part, int nchunk, int64_t stride, int k,
+                                                   double* __restrict__ out, int64_t out_stride) {
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    double sum = 0.0;
+    int c = 0;
+    for (; c + 4 <= nchunk; c += 4) {
+      const double a0 = part[(int64_t)c * stride + i], a1 = part[(int64_t)(c + 1) * stride + i];
+      const double a2 = part[(int64_t)(c + 2) * stride + i], a3 = part[(int64_t)(c + 3) * stride + i];
+      sum += a0;
+      sum += a1;
+      sum += a2;
+      sum += a3;
+    }
+    for (; c < nchunk; ++c) sum += part[(int64_t)c * stride + i];
+    out[i * out_stride] = sum;
   }
 }
 
@@ -692,44 +713,19 @@ __global__ void __launch_bounds__(kRedThreads)
 k_cgs_dot(const double* __restrict__ V, int64_t ldv, int64_t N, int64_t chunk_rows, int k,
           const double* __restrict__ w, int nrhs, double* __restrict__ h, int64_t ldh, double* __restrict__ partial,
           const int* __restrict__ active, unsigned* __restrict__ cnt) {
-  __shared__ double red[kDotBlk][kRedThreads / 64];
+  __shared__ double wl[kCgsMaxRows];
   __shared__ int flag;
   const int chunk = blockIdx.x, r = blockIdx.y, nchunk = gridDim.x;
   if (active && !active[r]) return;   // every block of this column returns: its count stays 0
   const int64_t n0 = (int64_t)chunk * chunk_rows;
-  const int64_t n1 = n0 + chunk_rows < N ? n0 + chunk_rows : N;
+  const int rows = (int)((n0 + chunk_rows < N ? n0 + chunk_rows : N) - n0);
   const double* wr = w + (int64_t)r * N;
-  const double* vr = V + (int64_t)r * N;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  // all k basis vectors against this chunk of w, kDotBlk at a time (w re-read from L1/L2)
-  for (int i0 = 0; i0 < k; i0 += kDotBlk) {
-    const int nb = k - i0 < kDotBlk ? k - i0 : kDotBlk;
-    double acc[kDotBlk];
-#pragma unroll
-    for (int q = 0; q < kDotBlk; ++q) acc[q] = 0.0;
-    for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
-      const double wn = wr[n];
-#pragma unroll
-      for (int q = 0; q < kDotBlk; ++q)
-        if (q < nb) acc[q] += vr[(int64_t)(i0 + q) * ldv + n] * wn;
-    }
-#pragma unroll
-    for (int q = 0; q < kDotBlk; ++q) {
-      const double t = wave_sum(acc[q]);
-      if (lane == 0) red[q][wv] = t;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < nb) {
-      double t = 0.0;
-      for (int u = 0; u < (int)(blockDim.x >> 6); ++u) t += red[threadIdx.x][u];
-      partial[((int64_t)chunk * nrhs + r) * k + i0 + threadIdx.x] = t;
-    }
-    __syncthreads();
-  }
+  for (int t = threadIdx.x; t < rows; t += blockDim.x) wl[t] = wr[n0 + t];
+  __syncthreads();
+  // all k basis vectors against this chunk of w
+  chunk_dots(V + (int64_t)r * N, ldv, n0, rows, k, wl, partial + ((int64_t)chunk * nrhs + r) * k);
   if (last_block(cnt + r, (unsigned)nchunk, &flag))
-    for (int i0 = 0; i0 < k; i0 += kDotBlk)
-      block_sum_chunks(partial + (int64_t)r * k + i0, nchunk, (int64_t)nrhs * k, 1,
-                       k - i0 < kDotBlk ? k - i0 : kDotBlk, red, h + (int64_t)r * ldh + i0, 1);
+    sum_chunks_ordered(partial + (int64_t)r * k, nchunk, (int64_t)nrhs * k, k, h + (int64_t)r * ldh, 1);
 }
 
 __global__ void __launch_bounds__(kRedThreads)
@@ -737,50 +733,28 @@ k_cgs_update_dot(const double* __restrict__ V, int64_t ldv, int64_t N, int64_t c
                  const double* __restrict__ h1, int64_t ldh, double* __restrict__ w, int nrhs,
                  double* __restrict__ h2, double* __restrict__ partial, const int* __restrict__ active,
                  unsigned* __restrict__ cnt) {
-  __shared__ double red[kDotBlk][kRedThreads / 64];
+  __shared__ double wl[kCgsMaxRows];
   __shared__ int flag;
   const int chunk = blockIdx.x, r = blockIdx.y, nchunk = gridDim.x;
   if (active && !active[r]) return;
   const int64_t n0 = (int64_t)chunk * chunk_rows;
-  const int64_t n1 = n0 + chunk_rows < N ? n0 + chunk_rows : N;
+  const int rows = (int)((n0 + chunk_rows < N ? n0 + chunk_rows : N) - n0);
   double* wr = w + (int64_t)r * N;
   const double* vr = V + (int64_t)r * N;
   const double* hr = h1 + (int64_t)r * ldh;
-  // w -= V h1 on this chunk (each thread keeps to its own rows in both phases)
-  for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
+  // w -= V h1 on this chunk, kept in LDS for the dots
+  for (int t = threadIdx.x; t < rows; t += blockDim.x) {
+    const int64_t n = n0 + t;
     double acc = 0.0;
     for (int i = 0; i < k; ++i) acc += vr[(int64_t)i * ldv + n] * hr[i];
-    wr[n] -= acc;
+    const double wn = wr[n] - acc;
+    wr[n] = wn;
+    wl[t] = wn;
   }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int i0 = 0; i0 < k; i0 += kDotBlk) {
-    const int nb = k - i0 < kDotBlk ? k - i0 : kDotBlk;
-    double acc[kDotBlk];
-#pragma unroll
-    for (int q = 0; q < kDotBlk; ++q) acc[q] = 0.0;
-    for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
-      const double wn = wr[n];
-#pragma unroll
-      for (int q = 0; q < kDotBlk; ++q)
-        if (q < nb) acc[q] += vr[(int64_t)(i0 + q) * ldv + n] * wn;
-    }
-#pragma unroll
-    for (int q = 0; q < kDotBlk; ++q) {
-      const double t = wave_sum(acc[q]);
-      if (lane == 0) red[q][wv] = t;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < nb) {
-      double t = 0.0;
-      for (int u = 0; u < (int)(blockDim.x >> 6); ++u) t += red[threadIdx.x][u];
-      partial[((int64_t)chunk * nrhs + r) * k + i0 + threadIdx.x] = t;
-    }
-    __syncthreads();
-  }
+  __syncthreads();
+  chunk_dots(vr, ldv, n0, rows, k, wl, partial + ((int64_t)chunk * nrhs + r) * k);
   if (last_block(cnt + r, (unsigned)nchunk, &flag))
-    for (int i0 = 0; i0 < k; i0 += kDotBlk)
-      block_sum_chunks(partial + (int64_t)r * k + i0, nchunk, (int64_t)nrhs * k, 1,
-                       k - i0 < kDotBlk ? k - i0 : kDotBlk, red, h2 + (int64_t)r * ldh + i0, 1);
+    sum_chunks_ordered(partial + (int64_t)r * k, nchunk, (int64_t)nrhs * k, k, h2 + (int64_t)r * ldh, 1);
 }
 
 __global__ void __launch_bounds__(kRedThreads)
