@@ -181,7 +181,7 @@ struct vc_problem {
   bool use_graphs = true;
   struct GraphKey {
     int mvp, transpose, precond, nrhs, restart;
-    int part;   // 0: cycle start, 1: the cycle's Arnoldi steps and update
+    int part;   // 0: cycle start, 1..nseg: segments of Arnoldi steps, nseg + 1: the update
     const double* b;
     double* x;
     bool operator==(const GraphKey& o) const {
@@ -201,7 +201,7 @@ struct vc_problem {
     return nullptr;
   }
   void add_graph(const GraphKey& k, hipGraph_t g, hipGraphExec_t e) {
-    if (graphs.size() >= 16) {   // bounded cache: drop the oldest
+    if (graphs.size() >= 32) {   // bounded cache (a solve shape holds a few segments): drop the oldest
       (void)hipGraphExecDestroy(graphs.front().exec);
       (void)hipGraphDestroy(graphs.front().graph);
       graphs.erase(graphs.begin());

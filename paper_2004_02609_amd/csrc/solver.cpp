@@ -13,6 +13,11 @@
 
 namespace vc {
 
+// Arnoldi steps per captured segment of a restart cycle: after each segment the host
+// reads whether any column still iterates (one small read-back per segment).
+constexpr int kCycleSeg = 8;
+static int cycle_segments(int m) { return (m + kCycleSeg - 1) / kCycleSeg; }
+
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -113,14 +118,17 @@ vc_status col_norms(vc_problem* P, const double* w, int64_t N, int nrhs, double*
   return VC_OK;
 }
 
-// One GMRES(m) restart cycle, every step on the device (so it can be captured), in two
-// parts so that the last cycle of a solve (which only finds every column converged)
-// costs one residual:
-//   part 0: residual and its norms, cycle start (masks, g, skip flags), V_0 = r / |r|;
-//   part 1: m Arnoldi steps with classical Gram-Schmidt applied twice and the Givens
-//           update, then x += R V y for the columns that were active at the start.
-// Columns freeze once converged; when all have, the remaining steps' products are
-// skipped by the device flag.
+// One GMRES(m) restart cycle, every step on the device (so it can be captured), in parts
+// so that the last cycle of a solve (which only finds every column converged) costs one
+// residual, and a cycle whose columns all converge early stops issuing steps:
+//   part 0:            residual and its norms, cycle start (masks, g, skip flags),
+//                      V_0 = r / |r|;
+//   parts 1..nseg:     Arnoldi steps [kCycleSeg (part - 1), kCycleSeg part) with
+//                      classical Gram-Schmidt applied twice and the Givens update;
+//   part nseg + 1:     x += R V y for the columns that were active at the start.
+// Columns freeze once converged; when all have, the remaining steps' kernels return at
+// once (device flag), and the host, which reads that flag after each segment, issues no
+// further segment.
 vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs, hipStream_t st,
                       int part) {
   const int64_t N = npanels(P);
@@ -145,14 +153,19 @@ vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, doubl
     VC_HIP(launch_scale_copy(V, r, N, nrhs, c.scal, c.skip, st));   // V_0 = r / |r|
     return VC_OK;
   }
-  for (int j = 0; j < m; ++j) {
-    s = op_with_precond(P, sp, V + j * ldv, z, w, nrhs, st, c.skip + 1, c.act_step);
-    if (s != VC_OK) return s;
-    // classical Gram-Schmidt twice, |w| and the Givens update (three launches)
-    VC_HIP(launch_cgs_step(V, ldv, N, j + 1, w, nrhs, hd, hd + (size_t)ldh * nrhs, ldh, P->s_partial.as<double>(),
-                           P->s_cnt.as<unsigned>(), j, m, c.H, c.cs, c.sn, c.g, c.bn, c.rtol, c.act_step, c.kd,
-                           c.iters, c.scal, c.skip, c.bad, nrm, st));
-    if (j + 1 < m) VC_HIP(launch_scale_copy(V + (j + 1) * ldv, w, N, nrhs, c.scal, c.skip + 1, st));
+  const int nseg = cycle_segments(m);
+  if (part <= nseg) {
+    const int j1 = std::min(m, part * kCycleSeg);
+    for (int j = (part - 1) * kCycleSeg; j < j1; ++j) {
+      s = op_with_precond(P, sp, V + j * ldv, z, w, nrhs, st, c.skip + 1, c.act_step);
+      if (s != VC_OK) return s;
+      // classical Gram-Schmidt twice, |w| and the Givens update (three launches)
+      VC_HIP(launch_cgs_step(V, ldv, N, j + 1, w, nrhs, hd, hd + (size_t)ldh * nrhs, ldh, P->s_partial.as<double>(),
+                             P->s_cnt.as<unsigned>(), j, m, c.H, c.cs, c.sn, c.g, c.bn, c.rtol, c.act_step, c.kd,
+                             c.iters, c.scal, c.skip, c.bad, nrm, st));
+      if (j + 1 < m) VC_HIP(launch_scale_copy(V + (j + 1) * ldv, w, N, nrhs, c.scal, c.skip + 1, st));
+    }
+    return VC_OK;
   }
   // x += R V y, y = R_H^{-1} g over each column's steps
   VC_HIP(launch_backsolve(nrhs, m, c.H, c.g, c.kd, c.act_cycle, y2, ldh, st));
@@ -239,9 +252,20 @@ vc_status gmres(vc_problem* P, const SolveSpec& sp, const double* b, double* x, 
   // the next cycle's start before one host read-back
   s = run_part(P, sp, b, x, nrhs, st, 0);
   if (s != VC_OK) return s;
+  const int nseg = cycle_segments(m);
   for (int cycle = 0;; ++cycle) {
     if (cycle > 0) {
-      s = run_part(P, sp, b, x, nrhs, st, 1);
+      // the steps segment by segment, until no column is still iterating
+      for (int seg = 1; seg <= nseg; ++seg) {
+        s = run_part(P, sp, b, x, nrhs, st, seg);
+        if (s != VC_OK) return s;
+        if (seg == nseg) break;
+        int step_done = 0;
+        VC_HIP(hipMemcpyAsync(&step_done, c.skip + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+        VC_HIP(hipStreamSynchronize(st));
+        if (step_done) break;
+      }
+      s = run_part(P, sp, b, x, nrhs, st, nseg + 1);
       if (s != VC_OK) return s;
       s = run_part(P, sp, b, x, nrhs, st, 0);
       if (s != VC_OK) return s;
