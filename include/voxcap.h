@@ -314,7 +314,8 @@ vc_status vc_tuning_load(vc_problem *p, const char *path, int32_t *n_loaded);
  * are dimensionless (voxel edge 1), so one cache serves every voxel size. */
 typedef struct vc_toeplitz_cache vc_toeplitz_cache;
 
-/* Fills the 15 octants over nmax (1..4096 per axis) on `device` and compresses each with
+/* Fills the 15 octants over nmax (1..4096 per axis, (nmax0+1)(nmax1+1)(nmax2+1) < 2^31) on
+ * `device` and compresses each with
  * relative tolerance tol in (0, 1) (FP64, sequentially truncated HOSVD).  Synchronizes
  * hip_stream.  *out is owned by the caller (vc_toeplitz_cache_destroy). */
 vc_status vc_toeplitz_cache_build(const int32_t nmax[3], double tol, int device, void *hip_stream,

@@ -138,6 +138,12 @@ extern "C" vc_status vc_toeplitz_cache_build(const int32_t nmax[3], double tol, 
   if (!(tol > 0.0) || tol >= 1.0) { set_error("tol must be in (0, 1)"); return VC_ERR_ARG; }
   for (int a = 0; a < 3; ++a)
     if (nmax[a] < 1 || nmax[a] > 4096) { set_error("nmax[%d] = %d outside 1..4096", a, nmax[a]); return VC_ERR_ARG; }
+  // the compression hands the octant's size to rocBLAS / rocSOLVER as 32-bit integers
+  const int64_t oct_elems = (int64_t)(nmax[0] + 1) * (nmax[1] + 1) * (nmax[2] + 1);
+  if (oct_elems >= ((int64_t)1 << 31)) {
+    set_error("octant of %d x %d x %d offsets exceeds 2^31 elements", nmax[0] + 1, nmax[1] + 1, nmax[2] + 1);
+    return VC_ERR_ARG;
+  }
   const double t0 = wall_s();
   VC_HIP(hipSetDevice(device));
   hipStream_t st = (hipStream_t)stream;

@@ -100,3 +100,11 @@ def test_cache_file_validation(tmp_path):
     assert e.value.status == voxcap.VC_ERR_ARG
     with pytest.raises(voxcap.VoxcapError):
         voxcap.vc_toeplitz_cache_load(os.path.join(str(tmp_path), "missing.vct"))
+    # sizes are checked before any device work
+    with pytest.raises(voxcap.VoxcapError) as e:
+        voxcap.vc_toeplitz_cache_build((1400, 1400, 1400), 1e-8)
+    assert e.value.status == voxcap.VC_ERR_ARG
+    with pytest.raises(voxcap.VoxcapError) as e:
+        voxcap.vc_toeplitz_cache_build((8, 8, 8), 0.0)
+    assert e.value.status == voxcap.VC_ERR_ARG
+
