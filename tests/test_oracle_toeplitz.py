@@ -8,6 +8,9 @@ Tab. I), and the library's validation of cache files (no GPU needed).
 * Lag ranges: the signed offsets of App. B are exactly the centre offsets between all
   panel pairs of a grid, found by brute force over the panels, and each maps inside
   the octant of that grid (t_a <= n_a).
+* Dense matrix: every entry of the oracle's eq. (4) matrix outside the jump diagonal is
+  the octant value of its pair, read at |centre offset| with the parity sign (and the
+  row's orientation sign on eq. 6 rows).
 * Crop: restoring with the leading factor rows equals restoring the whole tensor and
   cropping it (a property of the Tucker format), and the restored tensor of a smaller
   grid is within the compression bound tol * ||octant over nmax|| of its octant
@@ -82,6 +85,38 @@ def test_cropped_restore_within_compression_bound(q):
         if tol == 1e-4:
             # a real compression, so the bound is not met trivially
             assert sum(r for r in S.shape) < sum(big.shape)
+
+
+def test_dense_matrix_entries_are_octant_values():
+    """Every off-diagonal entry of the oracle's eq. (4) matrix, and the conductor rows'
+    diagonal, is the octant value of its pair at |centre offset| with the parity sign:
+    eq. (5) rows read the pair (min, max) of the two normal axes, eq. (6) rows the pair
+    (observer, source) times the row's orientation sign (Sec. II.B note 3)."""
+    import oracle
+    import scenes
+    s = scenes.random_small(5, shape=(5, 4, 6), n_cond=2, n_diel=1)
+    po = oracle.panelize(s["cond_id"], s["eps_r"], s["eps_b"])
+    A = oracle.assemble(po)
+    n = tuple(int(v) for v in s["cond_id"].shape)
+    T = [toeplitz.octant(q, n) for q in range(15)]
+    ax, ctr, kind = po["axis"], po["center"], po["kind"]
+    sign = np.where(kind == 1, po["sign"], 1).astype(float)
+    ref = np.zeros_like(A)
+    for a in range(3):
+        for b in range(3):
+            cols = np.nonzero(ax == b)[0]
+            for kd in (0, 1):
+                rows = np.nonzero((ax == a) & (kind == kd))[0]
+                if len(rows) == 0 or len(cols) == 0:
+                    continue
+                q = toeplitz.PAIRS.index((min(a, b), max(a, b), "P")) if kd == 0 else 6 + 3 * a + b
+                d = (ctr[rows][:, None, :] - ctr[cols][None, :, :]).reshape(-1, 3)
+                v = toeplitz.from_octant(q, T[q], d).reshape(len(rows), len(cols))
+                ref[np.ix_(rows, cols)] = sign[rows][:, None] * v
+    off = ~np.eye(len(A), dtype=bool) | (kind == 0)[:, None]
+    assert (kind == 1).any() and (kind == 0).any()
+    err = np.abs(A - ref)[off].max() / np.abs(A).max()
+    assert err < 1e-12, err
 
 
 def test_cache_file_validation(tmp_path):
