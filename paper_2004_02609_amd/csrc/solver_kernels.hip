@@ -226,7 +226,9 @@ hipError_t launch_diag_scale(const double* x, double* y, const double* dinv, int
 // in LDS.  When the box has fewer panels than the workgroup has threads, G = threads / nb
 // groups of threads each sum every G-th column of the block for all staged right-hand
 // sides (each block entry loaded once per pass), and the groups' sums are added in a
-// fixed order through LDS.
+// fixed order through LDS.  gridDim.y = S splits each box's rows into S slices, one per
+// workgroup, so a few large boxes still spread over the chip (every slice stages the
+// whole x_box; the columns of a row are summed by more groups).
 constexpr int kBoxThreads = 512;
 constexpr int kBoxLds = 4096;   // doubles of x_box staged per pass
 constexpr int kBoxRB = 4;       // right-hand sides per accumulation sweep
@@ -248,11 +250,16 @@ k_block_apply(const double* __restrict__ x, double* __restrict__ y, int64_t N, i
   }
   const int p0 = box_ptr[box];
   const int nb = box_ptr[box + 1] - p0;
+  // this workgroup's slice of the box's rows: [lo, lo + nr)
+  const int rsl = (nb + (int)gridDim.y - 1) / (int)gridDim.y;
+  const int lo = (int)blockIdx.y * rsl;
+  const int nr = nb - lo < rsl ? nb - lo : rsl;
+  if (nr <= 0) return;   // uniform over the workgroup, before any barrier
   const int blk = box_block[box];
   const double* B = blocks + block_off[blk];
   const int rpp = kBoxLds / nb;   // right-hand sides per pass (nb <= kBoxLds guaranteed by the host)
   const int t = threadIdx.x;
-  const int G = nb < kBoxThreads ? kBoxThreads / nb : 1;
+  const int G = nr < kBoxThreads ? kBoxThreads / nr : 1;
   // the block is stored transposed: B^T[j][i] = Binv[i][j] (lanes, consecutive i, read
   // consecutive addresses); the transposed apply reads B^T[i][j]
   const int64_t sj = trans ? 1 : nb, si = trans ? nb : 1;
@@ -266,10 +273,11 @@ k_block_apply(const double* __restrict__ x, double* __restrict__ y, int64_t N, i
     __syncthreads();
     for (int rb = 0; rb < rn; rb += kBoxRB) {
       const int rbn = rn - rb < kBoxRB ? rn - rb : kBoxRB;
-      for (int i0 = 0; i0 < nb; i0 += (G > 1 ? nb : kBoxThreads)) {
-        const int g = G > 1 ? t / nb : 0;
-        const int i = G > 1 ? t - g * nb : i0 + t;
-        const bool on = G > 1 ? g < G : i < nb;
+      for (int i0 = 0; i0 < nr; i0 += (G > 1 ? nr : kBoxThreads)) {
+        const int g = G > 1 ? t / nr : 0;
+        const int il = G > 1 ? t - g * nr : i0 + t;   // row within the slice
+        const int i = lo + il;
+        const bool on = G > 1 ? g < G : il < nr;
         double acc[kBoxRB];
 #pragma unroll
         for (int q = 0; q < kBoxRB; ++q) acc[q] = 0.0;
@@ -292,13 +300,13 @@ k_block_apply(const double* __restrict__ x, double* __restrict__ y, int64_t N, i
         } else {
           if (on)
 #pragma unroll
-            for (int q = 0; q < kBoxRB; ++q) red[(q * G + g) * nb + i] = acc[q];
+            for (int q = 0; q < kBoxRB; ++q) red[(q * G + g) * nr + il] = acc[q];
           __syncthreads();
-          for (int e = t; e < rbn * nb; e += blockDim.x) {
-            const int q = e / nb, ii = e - q * nb;
+          for (int e = t; e < rbn * nr; e += blockDim.x) {
+            const int q = e / nr, ii = e - q * nr;
             double v = 0.0;
-            for (int gg = 0; gg < G; ++gg) v += red[(q * G + gg) * nb + ii];
-            y[(int64_t)(r0 + rb + q) * N + box_panels[p0 + ii]] = v;
+            for (int gg = 0; gg < G; ++gg) v += red[(q * G + gg) * nr + ii];
+            y[(int64_t)(r0 + rb + q) * N + box_panels[p0 + lo + ii]] = v;
           }
           __syncthreads();
         }
@@ -313,7 +321,10 @@ hipError_t launch_block_apply(const double* x, double* y, int64_t N, int nrhs, c
                               const int32_t* block_n, const double* blocks, int nbox, const int* skip,
                               hipStream_t st, const int32_t* box_c0, const int32_t* box_nc, int trans) {
   if (nbox == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_block_apply, dim3(nbox), dim3(kBoxThreads), 0, st, x, y, N, nrhs, box_ptr, box_panels,
+  // row slices per box: enough workgroups for the chip when there are few boxes
+  int S = (512 + nbox - 1) / nbox;
+  if (S > 4) S = 4;
+  hipLaunchKernelGGL(k_block_apply, dim3(nbox, S), dim3(kBoxThreads), 0, st, x, y, N, nrhs, box_ptr, box_panels,
                      box_block, block_off, block_n, blocks, skip, box_c0, box_nc, trans);
   return hipGetLastError();
 }
