@@ -373,7 +373,7 @@ def main():
         write_traffic(args)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is design-only", file=sys.stderr)
         sys.exit(2)
 
