@@ -281,8 +281,9 @@ vc_status vc_pass_times(vc_problem *p, double ms[5], int32_t launches[5], double
  * transform direction (inverse = 0 after the z pass, 1 before it) and nrhs: kernel 0 =
  * LDS ping-pong tiles, 1 = register-edge stages with `cols` columns per workgroup
  * (0 = the heuristic's width; a width whose tile does not fit runs at that width) and
- * xcd_group = 1, 2 or 4 consecutive column tiles of a row per XCD.  Kept until the next
- * vc_setup.  VC_ERR_ARG on a value outside those ranges. */
+ * xcd_group = 1, 2 or 4 consecutive column tiles of a row per XCD, or -1 for all of a
+ * row's tiles.  Kept until the next vc_setup.  VC_ERR_ARG on a value outside those
+ * ranges. */
 vc_status vc_ypass_set(vc_problem *p, vc_precision prec, int transpose, int inverse, int32_t nrhs,
                        int32_t kernel, int32_t cols, int32_t xcd_group);
 

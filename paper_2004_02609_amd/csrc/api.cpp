@@ -524,7 +524,10 @@ vc_status vc_ypass_set(vc_problem* p, vc_precision prec, int transpose, int inve
   if (prec != VC_FP64 && prec != VC_FP32) { set_error("prec must be VC_FP64 or VC_FP32"); return VC_ERR_ARG; }
   if (kernel != 0 && kernel != 1) { set_error("kernel must be 0 (LDS tiles) or 1 (register edge)"); return VC_ERR_ARG; }
   if (cols < 0 || cols > 32 || (cols & (cols - 1))) { set_error("cols must be 0 or a power of two <= 32"); return VC_ERR_ARG; }
-  if (xcd_group != 1 && xcd_group != 2 && xcd_group != 4) { set_error("xcd_group must be 1, 2 or 4"); return VC_ERR_ARG; }
+  if (xcd_group != 1 && xcd_group != 2 && xcd_group != 4 && xcd_group != -1) {
+    set_error("xcd_group must be 1, 2, 4 or -1 (every tile of a row)");
+    return VC_ERR_ARG;
+  }
   const int t = (transpose && p->n_diel > 0) ? 1 : 0;   // without dielectric rows A is symmetric
   const int key = (nrhs << 3) | (t << 2) | ((inverse ? 1 : 0) << 1) | (prec == VC_FP64 ? 1 : 0);
   p->y_choice[key] = vc_problem::YChoice{kernel, false, {0.0, 0.0}, cols, xcd_group};
@@ -559,7 +562,9 @@ vc_status vc_tuning_report(vc_problem* p, char* buf, int32_t len) {
                   (kv.first & 2) ? "inverse" : "forward", (kv.first & 4) ? " (transposed product)" : "",
                   kv.first >> 3, c.impl ? "register-edge" : "lds-tiles",
                   ((c.impl && c.ncol > 0) ? " cols=" + std::to_string(c.ncol) : std::string()).append(
-                      (c.impl && c.xg > 1) ? " xcd_group=" + std::to_string(c.xg) : std::string()).c_str(),
+                      (c.impl && (c.xg > 1 || c.xg < 0)) ? (c.xg < 0 ? std::string(" xcd_group=row")
+                                                                    : " xcd_group=" + std::to_string(c.xg))
+                                                         : std::string()).c_str(),
                   c.tuned ? "tuned" : "default");
     out += line;
     if (c.tuned) {

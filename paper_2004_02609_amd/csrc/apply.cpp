@@ -233,11 +233,11 @@ static vc_status y_pass(vc_problem* P, PrecTables& tb, void* data, void* scratch
       };
       vc_status ts = timeit(0, 0, 1, &ch.ms[0]);
       // the register-edge kernel at the heuristic's width and at power-of-two widths,
-      // each with 1, 2 or 4 consecutive tiles per XCD
+      // each with 1, 2, 4 or all consecutive tiles of a row per XCD
       double best = 1e30;
       int bestc = 0, bestg = 1;
       for (int c : {0, 2, 4, 8, 16, 32})
-        for (int g : {1, 2, 4}) {
+        for (int g : {1, 2, 4, -1}) {
           int t = 0;
           if (ts != VC_OK || (c > 0 && (c == ydef || !ytile(c, &t)))) continue;
           double ms = 0.0;

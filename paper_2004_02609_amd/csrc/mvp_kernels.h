@@ -58,7 +58,8 @@ struct YArgs {
   const int* skip;  // optional device flag: when set, the launch does nothing
   const int* act;   // optional per right-hand side activity
   int xg;           // 2 or 4: that many consecutive tiles of a row (which share cache
-                    // lines) per XCD, issued together; 0 or 1: the launch order
+                    // lines) per XCD, issued together; -1: all tiles of a row; 0 or 1:
+                    // the launch order
 };
 template <typename T>
 hipError_t launch_ypass(void* data, const YArgs& a, const void* tw, const uint8_t* lflag, const uint8_t* pflag,

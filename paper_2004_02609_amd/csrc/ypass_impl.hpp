@@ -181,12 +181,12 @@ k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const 
                   a.tl * RS != a.L))
     return;
   int tile = blockIdx.x, plane = blockIdx.y, bz = blockIdx.z;
-  if (a.xg > 1) {
+  if (a.xg > 1 || (a.xg < 0 && gridDim.x > 1)) {
     // workgroups are issued to the 8 XCDs in turn by linear id w: hand the G consecutive
     // tiles of a row, whose rows share cache lines, to w, w + 8, ..., w + 8 (G - 1), which
     // sit on one XCD and start together (a bijection on the largest multiple of 8 G; the
-    // rest keep their order)
-    const uint32_t gx = gridDim.x, gy = gridDim.y, G = (uint32_t)a.xg, span = 8u * G;
+    // rest keep their order).  xg < 0: G = every tile of the row.
+    const uint32_t gx = gridDim.x, gy = gridDim.y, G = a.xg > 0 ? (uint32_t)a.xg : gx, span = 8u * G;
     const uint32_t W = gx * gy * gridDim.z;
     const uint32_t w = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
     uint32_t l = w;
@@ -256,7 +256,7 @@ hipError_t launch_ypass_rs(void* data, const YArgs& a, const void* tw, const uin
 template <typename T>
 bool ypass_args_ok(const YArgs& a, int nthr, bool flags, size_t* lds_out) {
   if (a.nst < 1 || a.nst > kSandMaxStages || a.ncol < 1 || a.ncol > 32 || nthr < 64 || nthr > 1024 || (nthr & 63) ||
-      a.cs.n < 1 || a.cs.n > 6 || a.nrhs < 1 || !(a.xg == 0 || a.xg == 1 || a.xg == 2 || a.xg == 4))
+      a.cs.n < 1 || a.cs.n > 6 || a.nrhs < 1 || !(a.xg >= -1 && a.xg <= 4 && a.xg != 3))
     return false;
   long prod = 1;
   int prev = 1 << 30;

@@ -218,7 +218,7 @@ def test_ypass_compiled_plans_match_dense(dev, name, make):
 
 
 def test_ypass_xcd_groups_match_dense(dev):
-    """The register-edge y pass with 1, 2 or 4 consecutive column tiles per XCD (a
+    """The register-edge y pass with 1, 2, 4 or all column tiles of a row per XCD (a
     permutation of the workgroups over the tiles) and several tile widths, forward and
     transposed, both precisions, against the dense product.  The grid (9 tiles per row
     at 4 columns, 6 planes, 6 components, 2 right-hand sides = 648 workgroups) has both
@@ -233,7 +233,7 @@ def test_ypass_xcd_groups_match_dense(dev):
         for transpose in (False, True):
             ref = ((A.T if transpose else A) @ x.T).T
             for cols in (2, 4, 8):
-                for g in (1, 2, 4):
+                for g in (1, 2, 4, -1):
                     for inverse in (False, True):
                         P.ypass_set(1, cols, g, prec=prec, transpose=transpose, inverse=inverse, nrhs=2)
                     y = P.apply(xt, transpose=transpose, prec=prec).cpu().numpy()
