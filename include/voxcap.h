@@ -153,7 +153,8 @@ vc_status vc_apply(vc_problem *p, int transpose, vc_precision prec, const double
                    double *y_dev, int32_t nrhs, void *hip_stream);
 
 /* y = R x with the block-diagonal-diagonal preconditioner R of eq. (14)
- * (R^T when transpose = 1; the blocks are symmetric). */
+ * (R^T when transpose = 1; the blocks are symmetric).  x_dev, y_dev: N x nrhs doubles as
+ * in vc_apply, distinct arrays; 1 <= nrhs <= max_rhs of vc_setup, else VC_ERR_ARG. */
 vc_status vc_apply_precond(vc_problem *p, int transpose, const double *x_dev, double *y_dev,
                            int32_t nrhs, void *hip_stream);
 
@@ -164,8 +165,8 @@ vc_status vc_apply_precond(vc_problem *p, int transpose, const double *x_dev, do
  * joins one nv box and each box's block of the full eq. (4) matrix is inverted (LU, FP64,
  * identical boxes sharing one inverse).  Kind 3 is built on first use (host work, then
  * device upload; not allowed during stream capture).  x_dev, y_dev: nrhs x N row-major
- * device arrays, distinct.  Errors: VC_ERR_STATE before setup, VC_ERR_ARG for a bad kind
- * or a packed set, VC_ERR_NUMERIC for a singular block. */
+ * device arrays, distinct, 1 <= nrhs <= max_rhs.  Errors: VC_ERR_STATE before setup, VC_ERR_ARG for a
+ * bad kind, nrhs or a packed set, VC_ERR_NUMERIC for a singular block. */
 vc_status vc_apply_precond_kind(vc_problem *p, int32_t kind, int transpose, const double *x_dev,
                                 double *y_dev, int32_t nrhs, void *hip_stream);
 
@@ -221,6 +222,22 @@ vc_status vc_capacitance_batch(vc_problem *const *problems, int32_t n, const vc_
 vc_status vc_capacitance_grad_eps(vc_problem *p, const vc_solve_opts *opts,
                                   const int32_t *block_of_voxel, int32_t nblocks,
                                   double *dC, double *C_out, vc_stats *stats);
+
+/* New relative permittivities for a set-up problem without a new setup (eq. 7, eq. 8):
+ * the operator depends on them only through the jump term of eq. (7) on dielectric
+ * panels, and C through the free-charge weights of eq. (8); the kernel spectra (and
+ * their Tucker form), the Toeplitz tensors and the eq. (14) conductor blocks do not, so
+ * only those per-panel arrays and the preconditioner's dielectric diagonal are
+ * rewritten (in place: graphs captured by earlier solves stay valid).
+ * eps_r: nx*ny*nz host doubles, C order, read where cond_id == -1 (> 0, finite);
+ * eps_background: the new background permittivity (> 0).  The panel list must not
+ * change: every dielectric face keeps different permittivities on its two sides and
+ * no new one appears, else VC_ERR_ARG and nothing is changed (VC_ERR_GEOMETRY for an
+ * invalid value).  Synchronizes hip_stream before and after the update.  The
+ * comparison preconditioner of use_precond 3, if built, is dropped and rebuilt at its
+ * next use.  A packed set created from p earlier keeps the old values: create packs
+ * after the update.  VC_ERR_STATE before vc_setup, VC_ERR_ARG on a packed set. */
+vc_status vc_update_eps(vc_problem *p, const double *eps_r, double eps_background, void *hip_stream);
 
 /* Per-pass timing of the product (measurement only).  At level 1, vc_apply records HIP
  * events on its stream around each of its passes (and the Tucker rebuild):

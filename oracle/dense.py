@@ -86,47 +86,27 @@ def assemble(p):
 
 
 def assemble_rows(p, rows):
-    """Rows `rows` (oracle order) of the matrix of eq. (4): the same integrals as
-    assemble(), for a bounded sample of the system."""
-    rows = np.asarray(rows)
+    """Rows `rows` (oracle order) of the matrix of eq. (4), with the same integrals and
+    row conventions as assemble(), for a bounded sample of a system too large to
+    assemble whole.  Every entry is integrated directly from its centre offset, one row
+    and source axis at a time (no offset table), so memory stays O(N)."""
+    rows = np.asarray(rows, dtype=np.int64)
     n = len(p["axis"])
     A = np.zeros((len(rows), n))
-    for a in range(3):
-        for kind in (0, 1):
-            sel = np.nonzero((p["axis"][rows] == a) & (p["kind"][rows] == kind))[0]
-            if len(sel) == 0:
-                continue
-            scale = None if kind == 0 else p["sign"][rows[sel]].astype(np.float64)
-            for b in range(3):
-                cols = np.nonzero(p["axis"] == b)[0]
-                sub = np.zeros((len(sel), len(cols)))
-                tmp = {"axis": p["axis"], "center": p["center"]}
-                # reuse the block filler on a private matrix indexed 0..len(sel)
-                Ablk = np.zeros((len(sel), n))
-                _block_rows(Ablk, tmp, rows[sel], cols, "P" if kind == 0 else "E", scale)
-                A[sel] += Ablk
-                del sub
+    cols_of = [np.nonzero(p["axis"] == b)[0] for b in range(3)]
     jump = _jump(p)
-    A[np.arange(len(rows)), rows] += jump[rows]
+    for t, k in enumerate(rows):
+        alpha = int(p["axis"][k])
+        diel = p["kind"][k] == 1
+        for b in range(3):
+            cols = cols_of[b]
+            if len(cols) == 0:
+                continue
+            d = p["center"][k][None, :] - p["center"][cols]
+            v = integrals.kernel(alpha, b, d, "E" if diel else "P")
+            A[t, cols] = float(p["sign"][k]) * v if diel else v
+        A[t, k] += jump[k]
     return A
-
-
-def _block_rows(A, p, rows, cols, want, row_scale):
-    """Like _block, but A has one row per entry of `rows` (in that order)."""
-    if len(rows) == 0 or len(cols) == 0:
-        return
-    alpha = int(p["axis"][rows[0]])
-    beta = int(p["axis"][cols[0]])
-    co = p["center"][rows]
-    cs = p["center"][cols]
-    d2 = np.rint(2.0 * (co[:, None, :] - cs[None, :, :])).astype(np.int64)
-    flat = d2.reshape(-1, 3)
-    uniq, inv = np.unique(flat, axis=0, return_inverse=True)
-    vals = integrals.kernel(alpha, beta, uniq / 2.0, want)
-    blk = vals[inv.ravel()].reshape(len(rows), len(cols))
-    if row_scale is not None:
-        blk = blk * row_scale[:, None]
-    A[:, cols] = blk
 
 
 def rhs(p):

@@ -19,18 +19,20 @@ from . import voxcap
 
 class _CapacitanceEps(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, eps_blocks, scene, block_of_voxel, device, setup_kw, solve_kw):
-        eps = np.array(scene["eps_r"], dtype=np.float64, copy=True)
+    def forward(ctx, eps_blocks, problem, base_eps, block_of_voxel, solve_kw):
+        eps = np.array(base_eps, dtype=np.float64, copy=True)
         e = eps_blocks.detach().to("cpu", torch.float64).numpy()
         nb = len(e)
         for b in range(nb):
             eps[block_of_voxel == b] = e[b]
-        P = voxcap.Problem(scene["cond_id"], eps, scene["dv"], scene["eps_b"], device).setup(**setup_kw)
+        # only the eq. (7) jump terms and eq. (8) weights depend on eps: the problem's
+        # setup (spectra, preconditioner blocks) is reused
+        problem.update_eps(eps)
         if ctx.needs_input_grad[0]:
-            dC, Cm, st = P.capacitance_grad_eps(block_of_voxel, nb, **solve_kw)
+            dC, Cm, st = problem.capacitance_grad_eps(block_of_voxel, nb, **solve_kw)
             ctx.save_for_backward(torch.from_numpy(dC))
         else:
-            Cm, st = P.capacitance(**solve_kw)
+            Cm, st = problem.capacitance(**solve_kw)
         ctx.stats = st
         return torch.from_numpy(np.ascontiguousarray(Cm)).to(eps_blocks.device)
 
@@ -39,20 +41,33 @@ class _CapacitanceEps(torch.autograd.Function):
         (dC,) = ctx.saved_tensors
         # vector-Jacobian product of the (nblocks, m, m) Jacobian with the m x m cotangent
         g = (dC * gC.detach().to("cpu", torch.float64).unsqueeze(0)).sum(dim=(1, 2))
-        return g.to(gC.device), None, None, None, None, None
+        return g.to(gC.device), None, None, None, None
 
 
-def capacitance_eps(scene, block_of_voxel, eps_blocks, device=0, setup=None, **solve):
+def capacitance_eps(scene, block_of_voxel, eps_blocks, device=0, setup=None, problem=None, **solve):
     """C (m x m, farads) of `scene` with the voxels of block b (block_of_voxel == b) set
     to relative permittivity eps_blocks[b]; differentiable in eps_blocks.
 
+    problem: a set-up voxcap.Problem of this scene's geometry to reuse (its
+    permittivities are overwritten; see problem_for); None sets one up (with the
+    keyword options `setup`) for this call alone.
     solve: keyword options of Problem.capacitance (prec, rtol, ...)."""
     blk = np.ascontiguousarray(block_of_voxel, dtype=np.int32)
     if blk.shape != np.shape(scene["cond_id"]):
         raise ValueError("block_of_voxel must have the grid's shape")
     if not torch.is_tensor(eps_blocks):
         eps_blocks = torch.as_tensor(eps_blocks, dtype=torch.float64)
-    return _CapacitanceEps.apply(eps_blocks, scene, blk, device, dict(setup or {}), dict(solve))
+    if problem is None:
+        problem = problem_for(scene, device=device, **dict(setup or {}))
+    elif problem.shape != blk.shape:
+        raise ValueError("problem and scene grids differ")
+    return _CapacitanceEps.apply(eps_blocks, problem, scene["eps_r"], blk, dict(solve))
+
+
+def problem_for(scene, device=0, **setup):
+    """A set-up Problem of `scene` for repeated capacitance_eps calls (one setup, then
+    only permittivity updates)."""
+    return voxcap.Problem.from_scene(scene, device).setup(**setup)
 
 
 class _ChargesToC(torch.autograd.Function):

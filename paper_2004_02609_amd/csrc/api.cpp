@@ -167,7 +167,10 @@ vc_status vc_apply(vc_problem* p, int transpose, vc_precision prec, const double
 vc_status vc_apply_precond(vc_problem* p, int transpose, const double* x, double* y, int32_t nrhs, void* stream) {
   VC_CHECK_PROBLEM(p);
   if (!p->setup_done) { set_error("vc_apply_precond before vc_setup"); return VC_ERR_STATE; }
-  if (!x || !y || nrhs <= 0) { set_error("bad arguments"); return VC_ERR_ARG; }
+  if (!x || !y || x == y || nrhs <= 0 || nrhs > p->max_rhs) {
+    set_error("bad x/y (null or the same array) or nrhs (1..%d)", p->max_rhs);
+    return VC_ERR_ARG;
+  }
   VC_HIP(hipSetDevice(p->device));
   p->pc.mode = 1;
   return mark(p, apply_precond(p, transpose, x, y, nrhs, (hipStream_t)stream));
@@ -177,7 +180,10 @@ vc_status vc_apply_precond_kind(vc_problem* p, int32_t kind, int transpose, cons
                                 void* stream) {
   VC_CHECK_PROBLEM(p);
   if (!p->setup_done) { set_error("vc_apply_precond_kind before vc_setup"); return VC_ERR_STATE; }
-  if (!x || !y || x == y || nrhs <= 0) { set_error("bad arguments"); return VC_ERR_ARG; }
+  if (!x || !y || x == y || nrhs <= 0 || nrhs > p->max_rhs) {
+    set_error("bad x/y (null or the same array) or nrhs (1..%d)", p->max_rhs);
+    return VC_ERR_ARG;
+  }
   if (kind < 1 || kind > 3) { set_error("preconditioner kind must be 1, 2 or 3"); return VC_ERR_ARG; }
   VC_HIP(hipSetDevice(p->device));
   if (kind == 3) {
@@ -387,6 +393,62 @@ vc_status vc_capacitance_grad_eps(vc_problem* p, const vc_solve_opts* opts, cons
                          rho.as<double>(), p->s_x.as<double>(), N, m, nblocks, 4.0 * M_PI * kEps0 * p->dv,
                          d_dC.as<double>(), nullptr));
   VC_HIP(hipMemcpy(dC, d_dC.p, (size_t)nblocks * m * m * sizeof(double), hipMemcpyDeviceToHost));
+  return VC_OK;
+}
+
+vc_status vc_update_eps(vc_problem* p, const double* eps_r, double eps_background, void* stream) {
+  VC_CHECK_PROBLEM(p);
+  if (!p->setup_done) { set_error("vc_update_eps before vc_setup"); return VC_ERR_STATE; }
+  if (p->pack) { set_error("vc_update_eps on a packed set"); return VC_ERR_ARG; }
+  if (!eps_r) { set_error("null eps_r"); return VC_ERR_ARG; }
+  // the panel list of the new permittivities (host only), compared with the current one
+  vc_problem q;
+  q.nx = p->nx; q.ny = p->ny; q.nz = p->nz;
+  q.dv = p->dv;
+  q.eps_b = eps_background;
+  q.cond_id = p->cond_id;
+  q.eps_r.assign(eps_r, eps_r + p->cond_id.size());
+  const vc_status s = panelize(&q);
+  if (s != VC_OK) return s;
+  bool same = q.panels.size() == p->panels.size();
+  for (size_t k = 0; same && k < q.panels.size(); ++k) {
+    const vc_panel &a = q.panels[k], &b = p->panels[k];
+    same = a.i == b.i && a.j == b.j && a.k == b.k && a.dir == b.dir && a.kind == b.kind && a.cond == b.cond;
+  }
+  if (!same) {
+    set_error("the new permittivities change the panel list (a dielectric face appears or vanishes): "
+              "create a new problem");
+    return VC_ERR_ARG;
+  }
+  VC_HIP(hipSetDevice(p->device));
+  hipStream_t st = (hipStream_t)stream;
+  // finish any work that still reads the current arrays, then rewrite them in place (the
+  // allocations stay, so captured graphs keep pointing at valid, updated data)
+  VC_HIP(hipStreamSynchronize(st));
+  const int64_t N = (int64_t)p->panels.size();
+  p->eps_r.swap(q.eps_r);
+  p->eps_b = eps_background;
+  p->panels.swap(q.panels);
+  p->diag.swap(q.diag);
+  p->weight.swap(q.weight);
+  std::vector<double> dinv(N, 0.0), dinv_diag(N, 0.0);
+  for (int64_t k = 0; k < N; ++k) {
+    if (p->panels[k].kind == 1) dinv[k] = dinv_diag[k] = 1.0 / p->diag[k];
+    else dinv_diag[k] = 1.0 / p->pc.pself;
+  }
+  const size_t nb = (size_t)N * sizeof(double);
+  VC_HIP(hipMemcpyAsync(p->d_diag.p, p->diag.data(), nb, hipMemcpyHostToDevice, st));
+  VC_HIP(hipMemcpyAsync(p->d_weight.p, p->weight.data(), nb, hipMemcpyHostToDevice, st));
+  VC_HIP(hipMemcpyAsync(p->pc.dinv.p, dinv.data(), nb, hipMemcpyHostToDevice, st));
+  VC_HIP(hipMemcpyAsync(p->pc.dinv_diag.p, dinv_diag.data(), nb, hipMemcpyHostToDevice, st));
+  VC_HIP(hipStreamSynchronize(st));
+  // the comparison preconditioner's blocks hold the eq. (7) diagonal: rebuilt at next use
+  // (graphs captured with it point at its blocks, so they go too)
+  if (p->pc.full.built) {
+    p->drop_graphs();
+    p->pc.full = FullBlocks();
+    if (p->pc.mode == 3) p->pc.mode = 1;
+  }
   return VC_OK;
 }
 

@@ -91,6 +91,7 @@ struct Precond {
   int nbox = 0;
   int nblock = 0;
   int64_t block_doubles = 0;
+  double pself = 0.0;   // eq. (5) self term of a panel (conductor rows of the diagonal preconditioner)
   DevMem box_ptr, box_panels, box_block, block_off, block_n, blocks, dinv, dinv_diag;
   std::vector<int32_t> h_box_ptr, h_box_panels, h_box_block, h_block_n;
   std::vector<int64_t> h_block_off;

@@ -486,6 +486,7 @@ vc_status build_precond(vc_problem* P, hipStream_t st) {
   pc.block_doubles = (int64_t)pc.h_blocks.size();
   std::vector<double> dinv(N, 0.0), dinv_diag(N, 0.0);
   const double pself = tab[(size_t)0 * nl + ((int64_t)nvx * ey + nvy) * ez + nvz];
+  pc.pself = pself;
   for (int64_t p = 0; p < N; ++p) {
     if (P->panels[p].kind == 1) dinv[p] = dinv_diag[p] = 1.0 / P->diag[p];
     else dinv_diag[p] = 1.0 / pself;

@@ -79,6 +79,7 @@ _sig = {
                                  C.POINTER(vc_stats)]),
     "vc_capacitance_grad_eps": (C.c_int, [_P, C.POINTER(vc_solve_opts), C.POINTER(C.c_int32), C.c_int32,
                                           C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(vc_stats)]),
+    "vc_update_eps": (C.c_int, [_P, C.POINTER(C.c_double), C.c_double, _P]),
     "vc_profile_enable": (C.c_int, [_P, C.c_int]),
     "vc_pass_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "vc_tuning_report": (C.c_int, [_P, C.c_char_p, C.c_int32]),
@@ -560,6 +561,8 @@ class Problem:
         self.n_cond, self.n_diel, self.m = vc_panel_counts(self._h)
         self.N = self.n_cond + self.n_diel
         self.device = device
+        self.shape = tuple(int(v) for v in np.shape(cond_id))
+        self.eps_background = float(eps_background)
 
     @classmethod
     def from_scene(cls, scene, device=0):
@@ -595,30 +598,43 @@ class Problem:
     def setup_time(self):
         return vc_setup_time(self._h)
 
-    def apply(self, x, y=None, transpose=False, prec="fp64", stream=None):
-        """y = A x for x a (nrhs, N) float64 cuda tensor."""
+    def _vectors(self, x, y):
+        """(x, y) checked for the C calls: (nrhs, N) contiguous float64 tensors on this
+        problem's device (y allocated when None, distinct from x).  The library reads
+        and writes nrhs * N doubles through the raw pointers, so anything else is
+        refused here."""
         import torch
+
+        def ok(t):
+            return (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_cuda and t.dim() == 2
+                    and t.shape[1] == self.N and t.shape[0] >= 1
+                    and (t.device.index if t.device.index is not None else torch.cuda.current_device()) == self.device)
+        if not ok(x):
+            raise ValueError(f"x must be a (nrhs, {self.N}) float64 tensor on cuda:{self.device}")
         x = x.contiguous()
         if y is None:
-            y = torch.empty_like(x)
+            return x, torch.empty_like(x)
+        if not ok(y) or tuple(y.shape) != tuple(x.shape) or not y.is_contiguous():
+            raise ValueError(f"y must be a contiguous float64 tensor of shape {tuple(x.shape)} on cuda:{self.device}")
+        if y.data_ptr() == x.data_ptr():
+            raise ValueError("y must not be x")
+        return x, y
+
+    def apply(self, x, y=None, transpose=False, prec="fp64", stream=None):
+        """y = A x for x a (nrhs, N) float64 cuda tensor."""
+        x, y = self._vectors(x, y)
         vc_apply(self._h, x, y, x.shape[0], transpose, prec, stream)
         return y
 
     def apply_precond(self, x, y=None, transpose=False, stream=None):
-        import torch
-        x = x.contiguous()
-        if y is None:
-            y = torch.empty_like(x)
+        x, y = self._vectors(x, y)
         vc_apply_precond(self._h, x, y, x.shape[0], transpose, stream)
         return y
 
     def apply_precond_kind(self, kind, x, y=None, transpose=False, stream=None):
         """y = R x for preconditioner kind 1 (eq. 14), 2 (diagonal) or 3 (block-diagonal
         over all panels, the comparison of Sec. III.A)."""
-        import torch
-        x = x.contiguous()
-        if y is None:
-            y = torch.empty_like(x)
+        x, y = self._vectors(x, y)
         vc_apply_precond_kind(self._h, kind, x, y, x.shape[0], transpose, stream)
         return y
 
@@ -662,6 +678,18 @@ class Problem:
     def capacitance(self, rho=None, **solve):
         Cm, st, _ = vc_capacitance(self._h, self.m, rho=rho, **solve)
         return Cm, stats_dict(st, self.m)
+
+    def update_eps(self, eps_r, eps_background=None, stream=None):
+        """New non-conductor permittivities (grid-shaped) without a new setup; the panel
+        list must stay the same (else VoxcapError with status VC_ERR_ARG)."""
+        e = np.ascontiguousarray(eps_r, dtype=np.float64)
+        if e.shape != self.shape:
+            raise ValueError(f"eps_r must have the grid's shape {self.shape}")
+        eb = self.eps_background if eps_background is None else float(eps_background)
+        _check(_lib.vc_update_eps(self._h, e.ctypes.data_as(C.POINTER(C.c_double)), eb, _stream(stream)),
+               "vc_update_eps")
+        self.eps_background = eb
+        return self
 
     def capacitance_grad_eps(self, block_of_voxel, nblocks, **solve):
         dC, Cm, st = vc_capacitance_grad_eps(self._h, self.m, block_of_voxel, nblocks, **solve)

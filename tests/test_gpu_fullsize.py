@@ -108,31 +108,40 @@ def test_meander_tucker_mixed_capacitance(dev):
 
 
 def test_grad256_eps_gradient_matches_central_differences(dev):
-    """The gradient workload at full size: dC/d(eps_r) over the 16 substrate blocks of
+    """The gradient workload at full size: dC/d(eps_r) over all 16 substrate blocks of
     the 256x256x64 scene (6 conductors) by the adjoint form (FP32 products inside FP64
-    refinement), against central differences with step 1e-4 of FP64 solves for the two
-    blocks with the largest derivative; gate 1e-5 relative."""
-    from paper_2004_02609_amd.autograd import capacitance_eps
+    refinement), against central differences with step 1e-4 of FP64 solves, entry by
+    entry: every (block, i, j) with |dC_ij/deps_b| >= 1e-3 of the largest within 1e-5
+    relative.  One problem serves every solve: the permittivities are rewritten in place
+    (eq. 7 jump terms and eq. 8 weights), with no second setup."""
+    from paper_2004_02609_amd.autograd import problem_for
     s = scenes.by_name("grad256")
-    blk = s["meta"]["block_of_voxel"]
+    blk = np.ascontiguousarray(s["meta"]["block_of_voxel"], dtype=np.int32)
     nb = int(s["meta"]["nblocks"])
-    eps0 = np.array([s["eps_r"][tuple(np.argwhere(blk == b)[0])] for b in range(nb)])
-    m = int(s["cond_id"].max()) + 1
-    G = torch.tensor(np.random.default_rng(9).standard_normal((m, m)))
-    e = torch.tensor(eps0, dtype=torch.float64, requires_grad=True)
-    C = capacitance_eps(s, blk, e, prec="mixed", rtol=1e-11)
-    (C * G).sum().backward()
-    g = e.grad.numpy()
-    pick = np.argsort(-np.abs(g))[:2]
+    base = s["eps_r"].copy()
+    eps0 = np.array([base[tuple(np.argwhere(blk == b)[0])] for b in range(nb)])
+    P = problem_for(s)
+    print("grad256 set up, N", P.N, "m", P.m, flush=True)
+    dC, C0, st = P.capacitance_grad_eps(blk, nb, prec="mixed", rtol=1e-12)
+    print("grad256 adjoint done, iters", st["iters"], "ir", st["ir_steps"], flush=True)
     h = 1e-4
-    for b in pick:
-        ep = torch.tensor(eps0)
-        ep[b] += h
-        em = torch.tensor(eps0)
-        em[b] -= h
-        cp = capacitance_eps(s, blk, ep, prec="fp64", rtol=1e-12).numpy()
-        cm = capacitance_eps(s, blk, em, prec="fp64", rtol=1e-12).numpy()
-        fd = ((cp - cm) / (2 * h) * G.numpy()).sum()
-        err = abs(g[b] - fd) / abs(fd)
-        print("grad256 block", b, "adjoint", g[b], "central differences", fd, "rel err", err, flush=True)
-        assert err < 1e-5, (b, g[b], fd)
+    fd = np.zeros_like(dC)
+    for b in range(nb):
+        for sgn in (1.0, -1.0):
+            e = base.copy()
+            e[blk == b] = eps0[b] + sgn * h
+            P.update_eps(e)
+            C, stf = P.capacitance(prec="fp64", rtol=1e-13)
+            fd[b] += sgn * C / (2 * h)
+        print("grad256 block", b, "fd done, iters", stf["iters"], flush=True)
+    P.update_eps(base)
+    C1, _ = P.capacitance(prec="fp64", rtol=1e-12)
+    gate = np.abs(fd) >= 1e-3 * np.abs(fd).max()
+    rel = np.abs(dC - fd)[gate] / np.abs(fd)[gate]
+    worst = np.unravel_index(np.argmax(np.where(gate, np.abs(dC - fd) / np.maximum(np.abs(fd), 1e-300), 0)), fd.shape)
+    print("grad256 gated entries", int(gate.sum()), "of", gate.size, "max rel err", rel.max(), "at", worst,
+          "adjoint", dC[worst], "fd", fd[worst], flush=True)
+    # the restored permittivities give back the first C
+    assert np.abs(C1 - C0).max() / np.abs(np.diag(C0)).max() < 1e-9
+    print("grad256 gated entries per block", [int(g.sum()) for g in gate], flush=True)
+    assert rel.max() < 1e-5, rel.max()

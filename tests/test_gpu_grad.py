@@ -101,3 +101,48 @@ def test_charges_to_capacitance_and_adjoint(dev):
     Cm, st = voxcap.vc_capacitance(P._h, m, rho=rho_dev, prec="fp64", rtol=1e-12)[:2]
     C2 = charges_to_capacitance(P, rho_dev).cpu().numpy()
     assert np.allclose(C2, Cm, rtol=1e-12, atol=1e-14 * np.abs(Cm).max())
+
+
+def test_update_eps_matches_fresh_setup(dev):
+    """New permittivities written into a set-up problem (eq. 7 jump terms, eq. 8 weights,
+    the preconditioner's dielectric diagonal) give the product, preconditioner and
+    capacitance of a problem set up from scratch with them, and the oracle's C; an
+    update that would change the panel list is refused and changes nothing."""
+    from paper_2004_02609_amd import voxcap
+    s, blk = _two_block_scene()
+    e2 = s["eps_r"].copy()
+    e2[blk == 0] = 4.5
+    e2[blk == 1] = 2.5
+    s2 = dict(s, eps_r=e2)
+    P = voxcap.Problem.from_scene(s).setup(max_rhs=2)
+    C1, _ = P.capacitance(prec="fp64", rtol=1e-13)          # captures graphs on the old values
+    P.apply_precond_kind(3, torch.zeros(1, P.N, dtype=torch.float64, device=dev))   # builds kind 3
+    P.update_eps(e2)
+    Q = voxcap.Problem.from_scene(s2).setup(max_rhs=2)
+    x = torch.tensor(np.random.default_rng(8).standard_normal((2, P.N)), device=dev)
+    for prec in ("fp64", "fp32"):
+        for tr in (False, True):
+            a, b = P.apply(x, prec=prec, transpose=tr), Q.apply(x, prec=prec, transpose=tr)
+            assert torch.equal(a, b), (prec, tr, float((a - b).abs().max()))
+    for kind in (1, 2, 3):
+        a, b = P.apply_precond_kind(kind, x), Q.apply_precond_kind(kind, x)
+        assert float((a - b).abs().max() / b.abs().max()) < 1e-14, kind
+    CP, _ = P.capacitance(prec="fp64", rtol=1e-13)
+    CQ, _ = Q.capacitance(prec="fp64", rtol=1e-13)
+    C_ref = oracle.solve_capacitance(s2)
+    d = np.abs(np.diag(C_ref)).max()
+    gate = np.abs(C_ref) >= 1e-3 * d
+    print("updated vs fresh", np.abs(CP - CQ).max() / d, "vs oracle",
+          (np.abs(CP - C_ref)[gate] / np.abs(C_ref)[gate]).max(), "old C moved", np.abs(CP - C1).max() / d, flush=True)
+    assert np.array_equal(CP, CQ)
+    assert (np.abs(CP - C_ref)[gate] / np.abs(C_ref)[gate]).max() < 1e-10
+    CM, _ = P.capacitance(prec="mixed", rtol=1e-10)
+    assert (np.abs(CM - C_ref)[gate] / np.abs(C_ref)[gate]).max() < 1e-6
+    # a block set to the background permittivity would remove dielectric panels
+    e3 = e2.copy()
+    e3[blk == 0] = s["eps_b"]
+    with pytest.raises(voxcap.VoxcapError) as ei:
+        P.update_eps(e3)
+    assert ei.value.status == voxcap.VC_ERR_ARG
+    CP2, _ = P.capacitance(prec="fp64", rtol=1e-13)
+    assert np.array_equal(CP2, CP)

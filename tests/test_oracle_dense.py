@@ -148,3 +148,46 @@ def test_dielectric_orientation_reading():
     assert np.allclose(np.diag(A2)[diel], I_plus[diel], rtol=1e-14)
     rho2 = np.linalg.solve(A2, oracle.rhs(p))
     assert np.allclose(rho2, st["rho"], rtol=1e-10, atol=1e-14)
+
+
+def _interface_scene():
+    """7x6x5 grid: a conductor on the grid's low x face, two overlapping dielectric boxes
+    (eps 3 and 6, so a dielectric-dielectric interface) that reach the grid's high y and
+    z faces, and a second conductor inside the eps-6 box."""
+    c = np.full((7, 6, 5), -1, np.int32)
+    e = np.ones((7, 6, 5))
+    e[2:7, 1:6, 1:5] = 3.0
+    e[4:7, 2:6, 2:5] = 6.0
+    c[0:2, 1:3, 1:3] = 0            # touches the low x face of the grid
+    c[5:6, 3:5, 3:4] = 1            # inside the eps-6 box
+    return {"cond_id": c, "eps_r": e, "eps_b": 1.0, "dv": 1e-6}
+
+
+@pytest.mark.parametrize("make", [_interface_scene,
+                                  lambda: scenes.random_small(5, n_cond=2, n_diel=2),
+                                  lambda: scenes.random_small(13, shape=(9, 14, 5), n_cond=2, n_diel=1)])
+def test_assemble_rows_equals_assemble(make):
+    """The sampled-row route (each entry integrated from its own offset) gives the rows
+    of the lag-table assembly of eq. (4): conductor rows, dielectric rows of both
+    orientation signs with their eq. (7) jump, grid-edge panels and a
+    dielectric-dielectric interface; rows asked in any order and repeated."""
+    s = make()
+    p = _panels(s)
+    A = dense.assemble(p)
+    n = len(p["axis"])
+    diel = p["kind"] == 1
+    rng = np.random.default_rng(4)
+    rows = rng.permutation(n)[: min(n, 40)]
+    # every kind of row the scenes hold: both signs, grid-edge faces, eps on both sides
+    edge = np.nonzero((p["idx"][np.arange(n), p["axis"]] == 0) |
+                      (p["idx"][np.arange(n), p["axis"]] == np.asarray(s["cond_id"].shape)[p["axis"]]))[0]
+    dd = np.nonzero(diel & (p["eps_lo"] != s["eps_b"]) & (p["eps_hi"] != s["eps_b"]))[0]
+    want = [np.nonzero(diel & (p["sign"] == 1))[0][:3], np.nonzero(diel & (p["sign"] == -1))[0][:3],
+            edge[:3], dd[:3], np.nonzero(~diel)[0][:3]]
+    rows = np.concatenate([rows] + want + [rows[:2]]).astype(np.int64)
+    if make is _interface_scene:
+        assert all(len(w) > 0 for w in want), [len(w) for w in want]
+    R = dense.assemble_rows(p, rows)
+    ref = A[rows]
+    err = np.abs(R - ref).max() / np.abs(A).max()
+    assert err <= 1e-15, err
