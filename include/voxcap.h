@@ -181,6 +181,26 @@ vc_status vc_precond_info(vc_problem *p, int32_t kind, int64_t *nbox, int64_t *n
 vc_status vc_capacitance(vc_problem *p, const vc_solve_opts *opts, double *C, double *rho_dev,
                          vc_stats *stats);
 
+/* vc_capacitance for callers that cannot allocate device memory (code next to graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same solve and
+ * kernels, with every device array of the solve (Krylov basis, vectors, Gram-Schmidt
+ * partials and completion counters, cycle state, the m x m result) taken from one
+ * static device array of VC_STATIC_SCRATCH_BYTES per GPU, held until the process ends.
+ * It calls no hipMalloc / hipFree; the problem must have been set up (vc_setup
+ * allocates its spectra, work arrays and preconditioner).  Restart cycles are issued
+ * kernel by kernel on hip_stream (NULL = the null stream; opts->graph is ignored: no
+ * graph is captured), and the call returns after C is on the host.  The first product
+ * of a (precision, direction, nrhs) key still runs the x-pass autotuner when the
+ * problem was set up with autotune = 1 (HIP events, no device memory).
+ * Errors: VC_ERR_ARG when the solve needs more than VC_STATIC_SCRATCH_BYTES (about
+ * 8 (N m (restart + 10)) bytes) or use_precond is 3 (its blocks are built on first
+ * use); otherwise as vc_capacitance.  Every call on one GPU shares that GPU's array
+ * and leaves its contents behind: calls that overlap on one GPU (several host threads,
+ * or streams that run concurrently) race and give wrong results. */
+#define VC_STATIC_SCRATCH_BYTES (64u << 20)
+vc_status vc_capacitance_static(vc_problem *p, const vc_solve_opts *opts, double *C, double *rho_dev,
+                                vc_stats *stats, void *hip_stream);
+
 /* ---- Packed sets: many independent problems of different sizes solved as one
  * (eq. (8) per member; the product of eq. (11) and preconditioner of eq. (14) of every
  * member in the same launches).  The members' conductor right-hand sides become the

@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "libvoxcap.so")
 SOURCES = ["sandwich_f32_36.hip", "sandwich_f32_33.hip", "sandwich_f32_63.hip", "sandwich_f64_36.hip",
            "sandwich_f64_33.hip", "sandwich_f64_63.hip", "mvp_kernels.hip", "ypass_f32.hip", "ypass_f64.hip", "setup_kernels.hip",
            "solver_kernels.hip", "tucker_kernels.hip", "geometry.cpp", "setup.cpp", "apply.cpp", "tucker.cpp", "solver.cpp", "pack.cpp", "tuning.cpp",
-           "toeplitz.cpp", "api.cpp"]
+           "toeplitz.cpp", "api.cpp", "noalloc.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

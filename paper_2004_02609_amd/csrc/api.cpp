@@ -221,40 +221,36 @@ vc_status vc_precond_info(vc_problem* p, int32_t kind, int64_t* nbox, int64_t* n
   return VC_OK;
 }
 
-static vc_status capacitance_impl(vc_problem* p, const vc_solve_opts* opts, double* C, double* rho_dev, vc_stats* stats,
-                                  std::vector<double>* rho_host) {
-  VC_CHECK_PROBLEM(p);
+}  // extern "C"
+
+vc_status vc::capacitance_check(vc_problem* p, const vc_solve_opts* opts, const double* C, vc_solve_opts* o) {
   if (!p->setup_done) { set_error("vc_capacitance before vc_setup"); return VC_ERR_STATE; }
   if (!C) { set_error("null C"); return VC_ERR_ARG; }
-  vc_solve_opts o = fill_defaults(opts);
-  if ((o.prec == VC_FP32 || o.prec == VC_MIXED) && !p->have32) { set_error("FP32 spectra not built"); return VC_ERR_STATE; }
+  *o = fill_defaults(opts);
+  if ((o->prec == VC_FP32 || o->prec == VC_MIXED) && !p->have32) { set_error("FP32 spectra not built"); return VC_ERR_STATE; }
   if (p->m > p->max_rhs) { set_error("setup max_rhs < number of conductors"); return VC_ERR_STATE; }
-  VC_HIP(hipSetDevice(p->device));
-  const double t0 = now_s();
-  hipStream_t st = get_solve_stream(p);
-  if (!st) { set_error("could not create the solve stream"); return VC_ERR_HIP; }
+  return VC_OK;
+}
+
+vc_status vc::capacitance_run(vc_problem* p, const vc_solve_opts& o, double* C, double* rho_dev, vc_stats* stats,
+                          hipStream_t st, std::vector<double>* rho_host, double t0) {
   const int64_t N = npanels(p);
   const int m = p->m;
   p->mvp_count = 0;
-  vc_status s = ensure_workspace(p, m, o.restart);
-  if (s != VC_OK) return mark(p, s);
-  std::vector<double> B((size_t)m * N, 0.0);
-  for (int64_t k = 0; k < N; ++k)
-    if (p->panels[k].kind == 0) B[(size_t)p->panels[k].cond * N + k] = 1.0;
-  VC_HIP(hipMemcpy(p->s_b.p, B.data(), B.size() * sizeof(double), hipMemcpyHostToDevice));
+  // unit potential on conductor j: b[j N + k] = 1 on the panels of conductor j (Sec. II.A)
+  VC_HIP(launch_unit_rhs(p->ws.b, p->d_pcond.as<int32_t>(), N, m, st));
   if (stats) std::memset(stats, 0, sizeof(vc_stats));
-  s = solve(p, o, 0, p->s_b.as<double>(), p->s_x.as<double>(), m, stats, st);
-  if (s != VC_OK && s != VC_ERR_NOT_CONVERGED) return mark(p, s);
-  DevMem dC;
-  VC_HIP(dC.alloc((size_t)m * m * sizeof(double)));
-  VC_HIP(launch_cap_reduce(p->s_x.as<double>(), N, m, p->d_cond_panels.as<int32_t>(), p->d_cond_ptr.as<int32_t>(),
-                           p->d_weight.as<double>(), 4.0 * M_PI * kEps0 * p->dv, dC.as<double>(), st));
-  VC_HIP(hipMemcpy(C, dC.p, (size_t)m * m * sizeof(double), hipMemcpyDeviceToHost));
-  if (rho_dev) VC_HIP(hipMemcpy(rho_dev, p->s_x.p, (size_t)m * N * sizeof(double), hipMemcpyDeviceToDevice));
+  vc_status s = solve(p, o, 0, p->ws.b, p->ws.x, m, stats, st);
+  if (s != VC_OK && s != VC_ERR_NOT_CONVERGED) return s;
+  VC_HIP(launch_cap_reduce(p->ws.x, N, m, p->d_cond_panels.as<int32_t>(), p->d_cond_ptr.as<int32_t>(),
+                           p->d_weight.as<double>(), 4.0 * M_PI * kEps0 * p->dv, p->ws.dC, st));
+  VC_HIP(hipMemcpyAsync(C, p->ws.dC, (size_t)m * m * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (rho_dev) VC_HIP(hipMemcpyAsync(rho_dev, p->ws.x, (size_t)m * N * sizeof(double), hipMemcpyDeviceToDevice, st));
   if (rho_host) {
     rho_host->resize((size_t)m * N);
-    VC_HIP(hipMemcpy(rho_host->data(), p->s_x.p, (size_t)m * N * sizeof(double), hipMemcpyDeviceToHost));
+    VC_HIP(hipMemcpyAsync(rho_host->data(), p->ws.x, (size_t)m * N * sizeof(double), hipMemcpyDeviceToHost, st));
   }
+  VC_HIP(hipStreamSynchronize(st));
   if (stats) {
     stats->mvp_count = p->mvp_count;
     stats->t_setup_s = p->t_setup;
@@ -265,6 +261,24 @@ static vc_status capacitance_impl(vc_problem* p, const vc_solve_opts* opts, doub
     stats->tucker_rank_max = rmax;
   }
   return s;
+}
+
+extern "C" {
+
+static vc_status capacitance_impl(vc_problem* p, const vc_solve_opts* opts, double* C, double* rho_dev, vc_stats* stats,
+                                  std::vector<double>* rho_host) {
+  VC_CHECK_PROBLEM(p);
+  vc_solve_opts o;
+  vc_status s = capacitance_check(p, opts, C, &o);
+  if (s != VC_OK) return s;
+  VC_HIP(hipSetDevice(p->device));
+  const double t0 = now_s();
+  hipStream_t st = get_solve_stream(p);
+  if (!st) { set_error("could not create the solve stream"); return VC_ERR_HIP; }
+  s = ensure_workspace(p, p->m, o.restart);
+  if (s != VC_OK) return mark(p, s);
+  s = capacitance_run(p, o, C, rho_dev, stats, st, rho_host, t0);
+  return s == VC_OK || s == VC_ERR_NOT_CONVERGED ? s : mark(p, s);
 }
 
 vc_status vc_pack_create(vc_problem* const* problems, int32_t n, vc_pack** out) {
@@ -330,14 +344,14 @@ vc_status vc_capacitance_grad_eps(vc_problem* p, const vc_solve_opts* opts, cons
   if (C_out) std::memcpy(C_out, C.data(), C.size() * sizeof(double));
   DevMem rho;
   VC_HIP(rho.alloc((size_t)m * N * sizeof(double)));
-  VC_HIP(hipMemcpy(rho.p, p->s_x.p, (size_t)m * N * sizeof(double), hipMemcpyDeviceToDevice));
+  VC_HIP(hipMemcpy(rho.p, p->ws.x, (size_t)m * N * sizeof(double), hipMemcpyDeviceToDevice));
   // adjoint solves A^T lambda_i = w_i, w_i = eps_adj on the panels of conductor i
   vc_solve_opts o = fill_defaults(opts);
   std::vector<double> W((size_t)m * N, 0.0);
   for (int64_t k = 0; k < N; ++k)
     if (p->panels[k].kind == 0) W[(size_t)p->panels[k].cond * N + k] = p->panels[k].eps_adj;
-  VC_HIP(hipMemcpy(p->s_b.p, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice));
-  s = solve(p, o, 1, p->s_b.as<double>(), p->s_x.as<double>(), m, nullptr, get_solve_stream(p));
+  VC_HIP(hipMemcpy(p->ws.b, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice));
+  s = solve(p, o, 1, p->ws.b, p->ws.x, m, nullptr, get_solve_stream(p));
   if (s != VC_OK) return mark(p, s);
   // per-block entries of the derivative (index bookkeeping on the host, sums on the GPU):
   //   conductor panel k: d w_{cond k} / d eps(non-conductor side block) = 1 (eq. 8)
@@ -390,7 +404,7 @@ vc_status vc_capacitance_grad_eps(vc_problem* p, const vc_solve_opts* opts, cons
     VC_HIP(hipMemcpy(d_f.p, ff.data(), ff.size() * sizeof(double), hipMemcpyHostToDevice));
   }
   VC_HIP(launch_grad_eps(d_bptr.as<int32_t>(), d_k.as<int32_t>(), d_c.as<int32_t>(), d_f.as<double>(),
-                         rho.as<double>(), p->s_x.as<double>(), N, m, nblocks, 4.0 * M_PI * kEps0 * p->dv,
+                         rho.as<double>(), p->ws.x, N, m, nblocks, 4.0 * M_PI * kEps0 * p->dv,
                          d_dC.as<double>(), nullptr));
   VC_HIP(hipMemcpy(dC, d_dC.p, (size_t)nblocks * m * m * sizeof(double), hipMemcpyDeviceToHost));
   return VC_OK;

@@ -313,6 +313,11 @@ hipError_t launch_backsolve(int nrhs, int m, const double* H, const double* g, c
 hipError_t launch_scale_copy(double* dst, const double* src, int64_t N, int nrhs, const double* s, const int* skip,
                              hipStream_t st);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t st);
+// b[j N + k] = 1 where pcond[k] == j, else 0 (k < N, j < m): the unit-potential
+// right-hand sides of the m conductors
+hipError_t launch_unit_rhs(double* b, const int32_t* pcond, int64_t N, int m, hipStream_t st);
+// p[0..n) = 0 (a kernel: no memset node when captured)
+hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t st);
 hipError_t launch_add_active(double* x, const double* z, int64_t N, int nrhs, const int* act, const int* skip,
                              hipStream_t st);
 hipError_t launch_cap_reduce(const double* rho, int64_t N, int m, const int32_t* cond_panels,

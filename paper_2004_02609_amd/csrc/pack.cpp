@@ -466,7 +466,7 @@ vc_status pack_capacitance(vc_problem* Q, const vc_solve_opts* opts, double* con
   std::vector<int> it;
   std::vector<double> rre;
   vc_stats all{};
-  s = solve(Q, o, 0, D.b.as<double>(), Q->s_x.as<double>(), R, &all, st, &it, &rre);
+  s = solve(Q, o, 0, D.b.as<double>(), Q->ws.x, R, &all, st, &it, &rre);
   if (s != VC_OK && s != VC_ERR_NOT_CONVERGED) return s;
   // eq. (8) per member, from its columns of the packed solution
   std::vector<int64_t> coff(D.mem.size() + 1, 0);
@@ -475,7 +475,7 @@ vc_status pack_capacitance(vc_problem* Q, const vc_solve_opts* opts, double* con
   VC_HIP(dC.alloc((size_t)coff.back() * sizeof(double)));
   for (size_t k = 0; k < D.mem.size(); ++k) {
     vc_problem* P = D.mem[k];
-    VC_HIP(launch_cap_reduce_n(Q->s_x.as<double>() + (size_t)D.c0[k] * N, N, P->m, P->m,
+    VC_HIP(launch_cap_reduce_n(Q->ws.x + (size_t)D.c0[k] * N, N, P->m, P->m,
                                P->d_cond_panels.as<int32_t>(), P->d_cond_ptr.as<int32_t>(), P->d_weight.as<double>(),
                                4.0 * M_PI * kEps0 * P->dv, dC.as<double>() + coff[k], st));
   }

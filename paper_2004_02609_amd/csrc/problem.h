@@ -102,6 +102,21 @@ constexpr int kToeplitzPairs = 15;   // 6 pairs of eq. (5), 9 of eq. (6)
 
 struct PackData;   // several problems solved as one (pack.cpp)
 
+// Device arrays of one GMRES solve (solver.cpp), all regions of one block: either the
+// problem's own allocation or the library's static scratch array (noalloc.cpp).
+struct SolveWs {
+  double *V = nullptr, *w = nullptr, *z = nullptr, *r = nullptr, *b = nullptr, *x = nullptr, *tmp = nullptr;
+  double *rr = nullptr, *dd = nullptr, *h = nullptr, *y2 = nullptr, *partial = nullptr, *norm = nullptr;
+  double *cyc = nullptr;       // device-side GMRES cycle state (doubles)
+  double *dC = nullptr;        // m x m capacitance of the last reduction
+  int *active = nullptr, *cyci = nullptr;
+  unsigned* cnt = nullptr;     // completion counters of the fused Gram-Schmidt step (rest at 0)
+  int nrhs = 0, restart = 0;   // the largest solve shape the regions hold
+};
+// byte size of the regions for nrhs columns of N rows and restart r, laid out from base
+// (256-byte aligned regions) into *ws when base is not null
+size_t solve_ws_layout(int64_t N, int nrhs, int r, char* base, SolveWs* ws);
+
 }  // namespace vc
 
 // Tucker-compressed Toeplitz octants of every pair over a largest grid (toeplitz.cpp):
@@ -173,11 +188,11 @@ struct vc_problem {
   int64_t rhs_stride = 0, comp_stride = 0;
   int ncomp_F = 0, ncomp_O = 0;
   vc::Precond pc;
-  // solver workspace
-  vc::DevMem s_V, s_w, s_z, s_r, s_b, s_x, s_h, s_partial, s_norm, s_active, s_tmp, s_y2, s_rr, s_dd;
-  vc::DevMem s_cyc, s_cyci;         // device-side GMRES cycle state (doubles, ints)
-  vc::DevMem s_cnt;                 // completion counters of the fused Gram-Schmidt step (rest at 0)
-  int s_restart = 0, s_nrhs = 0;
+  // solver workspace: the regions the solver uses (ws) and the problem's own block they
+  // point into, unless a call without allocation points them at the static scratch
+  vc::DevMem s_all;
+  vc::SolveWs ws, ws_own;
+  bool ws_static = false;           // set for the duration of vc_capacitance_static
   // restart cycles captured as graphs, keyed by what their kernel arguments bake in
   bool use_graphs = true;
   struct GraphKey {

@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "mvp_kernels.h"
@@ -25,47 +26,60 @@ double now_s() {
 
 // ------------------------------------------------------------------------------ GMRES
 
-vc_status ensure_workspace(vc_problem* P, int nrhs, int restart) {
-  if (P->s_nrhs >= nrhs && P->s_restart >= restart) return VC_OK;
-  const int64_t N = npanels(P);
-  const int r = std::max(restart, P->s_restart), k = std::max(nrhs, P->s_nrhs);
-  if (k > 256) { set_error("at most 256 right-hand sides per solve"); return VC_ERR_ARG; }
-  P->drop_graphs();   // captured graphs hold pointers into the old workspace
-  VC_HIP(P->s_V.alloc((size_t)(r + 1) * k * N * sizeof(double)));
-  VC_HIP(P->s_w.alloc((size_t)k * N * sizeof(double)));
-  VC_HIP(P->s_z.alloc((size_t)k * N * sizeof(double)));
-  VC_HIP(P->s_r.alloc((size_t)k * N * sizeof(double)));
-  VC_HIP(P->s_b.alloc((size_t)k * N * sizeof(double)));
-  VC_HIP(P->s_x.alloc((size_t)k * N * sizeof(double)));
-  VC_HIP(P->s_tmp.alloc((size_t)k * N * sizeof(double)));
-  VC_HIP(P->s_rr.alloc((size_t)k * N * sizeof(double)));
-  VC_HIP(P->s_dd.alloc((size_t)k * N * sizeof(double)));
-  VC_HIP(P->s_h.alloc((size_t)2 * (r + 2) * k * sizeof(double)));
-  VC_HIP(P->s_y2.alloc((size_t)(r + 2) * k * sizeof(double)));
-  VC_HIP(P->s_partial.alloc((size_t)std::max({gemv_t_partial_size(N, r + 2, k), colnorm_partial_size(N, k),
-                                               cgs_partial_size(N, r + 1, k)}) *
-                            sizeof(double)));
-  VC_HIP(P->s_norm.alloc((size_t)4 * k * sizeof(double)));
-  VC_HIP(P->s_active.alloc((size_t)k * sizeof(int)));
+size_t solve_ws_layout(int64_t N, int k, int r, char* base, SolveWs* ws) {
+  size_t off = 0;
+  // next region of n elements of type T (256-byte aligned)
+  auto take = [&](auto*& ptr, size_t n) {
+    using T = std::remove_reference_t<decltype(*ptr)>;
+    off = (off + 255) & ~(size_t)255;
+    ptr = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += std::max<size_t>(n, 1) * sizeof(T);
+  };
+  SolveWs w{};
+  const size_t kN = (size_t)k * (size_t)N;
+  take(w.V, (size_t)(r + 1) * kN);
+  for (double** v : {&w.w, &w.z, &w.r, &w.b, &w.x, &w.tmp, &w.rr, &w.dd}) take(*v, kN);
+  take(w.h, (size_t)2 * (r + 2) * k);
+  take(w.y2, (size_t)(r + 2) * k);
+  take(w.partial, (size_t)std::max({gemv_t_partial_size(N, r + 2, k), colnorm_partial_size(N, k),
+                                    cgs_partial_size(N, r + 1, k)}));
+  take(w.norm, (size_t)4 * k);
   // device-side cycle state: H, cs, sn, g, bn, rn, rre, scal (doubles); kd, iters,
   // act_cycle, act_step (ints) + skip[2], bad
-  const size_t nd = (size_t)k * ((size_t)(r + 1) * r + 2 * r + (r + 1) + 4) + 1;
-  VC_HIP(P->s_cyc.alloc(nd * sizeof(double)));
-  VC_HIP(P->s_cyci.alloc(((size_t)4 * k + 5) * sizeof(int)));
-  VC_HIP(P->s_cnt.alloc((size_t)cgs_counter_size(r + 1, k) * sizeof(unsigned)));
-  VC_HIP(hipMemset(P->s_cnt.p, 0, P->s_cnt.bytes));
-  // vectors start at zero: rows a product never writes (the padding rows of a packed
-  // set) then stay zero through every update
-  for (DevMem* d : {&P->s_V, &P->s_w, &P->s_z, &P->s_r, &P->s_b, &P->s_x, &P->s_tmp, &P->s_rr, &P->s_dd})
-    VC_HIP(hipMemset(d->p, 0, d->bytes));
-  P->s_nrhs = k;
-  P->s_restart = r;
+  take(w.cyc, (size_t)k * ((size_t)(r + 1) * r + 2 * r + (r + 1) + 4) + 1);
+  take(w.dC, (size_t)k * k);
+  take(w.active, (size_t)k);
+  take(w.cyci, (size_t)4 * k + 5);
+  take(w.cnt, (size_t)cgs_counter_size(r + 1, k));
+  w.nrhs = k;
+  w.restart = r;
+  if (ws) *ws = w;
+  return (off + 255) & ~(size_t)255;
+}
+
+vc_status ensure_workspace(vc_problem* P, int nrhs, int restart) {
+  if (P->ws.nrhs >= nrhs && P->ws.restart >= restart) return VC_OK;
+  if (P->ws_static) {
+    set_error("the static scratch holds a smaller solve than asked for");
+    return VC_ERR_STATE;
+  }
+  const int64_t N = npanels(P);
+  const int r = std::max(restart, P->ws.restart), k = std::max(nrhs, P->ws.nrhs);
+  if (k > 256) { set_error("at most 256 right-hand sides per solve"); return VC_ERR_ARG; }
+  P->drop_graphs();   // captured graphs hold pointers into the old workspace
+  const size_t bytes = solve_ws_layout(N, k, r, nullptr, nullptr);
+  VC_HIP(P->s_all.alloc(bytes));
+  solve_ws_layout(N, k, r, P->s_all.as<char>(), &P->ws_own);
+  // vectors start at zero (rows a product never writes, the padding rows of a packed
+  // set, then stay zero through every update), and so do the counters
+  VC_HIP(hipMemset(P->s_all.p, 0, bytes));
+  P->ws = P->ws_own;
   return VC_OK;
 }
 
 Cyc cycle_views(vc_problem* P, int nrhs, int m) {
   Cyc c{};
-  double* d = P->s_cyc.as<double>();
+  double* d = P->ws.cyc;
   c.H = d; d += (size_t)nrhs * (m + 1) * m;
   c.cs = d; d += (size_t)nrhs * m;
   c.sn = d; d += (size_t)nrhs * m;
@@ -75,7 +89,7 @@ Cyc cycle_views(vc_problem* P, int nrhs, int m) {
   c.rre = d; d += nrhs;
   c.scal = d; d += nrhs;
   c.rtol = d;
-  int* q = P->s_cyci.as<int>();
+  int* q = P->ws.cyci;
   c.kd = q; q += nrhs;
   c.iters = q; q += nrhs;
   c.act_cycle = q; q += nrhs;
@@ -111,7 +125,7 @@ vc_status residual(vc_problem* P, const SolveSpec& sp, const double* b, const do
 
 vc_status col_norms(vc_problem* P, const double* w, int64_t N, int nrhs, double* d_out, std::vector<double>& h,
                            hipStream_t st) {
-  VC_HIP(launch_colnorm(w, N, N, nrhs, d_out, P->s_partial.as<double>(), st));
+  VC_HIP(launch_colnorm(w, N, N, nrhs, d_out, P->ws.partial, st));
   h.resize(nrhs);
   VC_HIP(hipMemcpyAsync(h.data(), d_out, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
   VC_HIP(hipStreamSynchronize(st));
@@ -134,20 +148,20 @@ vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, doubl
   const int64_t N = npanels(P);
   const int m = sp.restart;
   const Cyc c = cycle_views(P, nrhs, m);
-  double* V = P->s_V.as<double>();
-  double* w = P->s_w.as<double>();
-  double* z = P->s_z.as<double>();
-  double* r = P->s_r.as<double>();
-  double* hd = P->s_h.as<double>();
-  double* y2 = P->s_y2.as<double>();
-  double* nrm = P->s_norm.as<double>();
+  double* V = P->ws.V;
+  double* w = P->ws.w;
+  double* z = P->ws.z;
+  double* r = P->ws.r;
+  double* hd = P->ws.h;
+  double* y2 = P->ws.y2;
+  double* nrm = P->ws.norm;
   const int64_t ldv = (int64_t)nrhs * N;
   const int ldh = m + 2;
   vc_status s;
   if (part == 0) {
     s = residual(P, sp, b, x, r, nrhs, st, c.skip + 2);
     if (s != VC_OK) return s;
-    VC_HIP(launch_colnorm(r, N, N, nrhs, c.rn, P->s_partial.as<double>(), st, c.skip + 2));
+    VC_HIP(launch_colnorm(r, N, N, nrhs, c.rn, P->ws.partial, st, c.skip + 2));
     VC_HIP(launch_cycle_start(nrhs, m, c.rn, c.bn, c.rtol, c.act_cycle, c.act_step, c.g, c.scal, c.kd, c.skip, c.rre,
                               st));
     VC_HIP(launch_scale_copy(V, r, N, nrhs, c.scal, c.skip, st));   // V_0 = r / |r|
@@ -160,8 +174,8 @@ vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, doubl
       s = op_with_precond(P, sp, V + j * ldv, z, w, nrhs, st, c.skip + 1, c.act_step);
       if (s != VC_OK) return s;
       // classical Gram-Schmidt twice, |w| and the Givens update (three launches)
-      VC_HIP(launch_cgs_step(V, ldv, N, j + 1, w, nrhs, hd, hd + (size_t)ldh * nrhs, ldh, P->s_partial.as<double>(),
-                             P->s_cnt.as<unsigned>(), j, m, c.H, c.cs, c.sn, c.g, c.bn, c.rtol, c.act_step, c.kd,
+      VC_HIP(launch_cgs_step(V, ldv, N, j + 1, w, nrhs, hd, hd + (size_t)ldh * nrhs, ldh, P->ws.partial,
+                             P->ws.cnt, j, m, c.H, c.cs, c.sn, c.g, c.bn, c.rtol, c.act_step, c.kd,
                              c.iters, c.scal, c.skip, c.bad, nrm, st));
       if (j + 1 < m) VC_HIP(launch_scale_copy(V + (j + 1) * ldv, w, N, nrhs, c.scal, c.skip + 1, st));
     }
@@ -194,7 +208,7 @@ vc_status cycle_graph(vc_problem* P, const SolveSpec& sp, const double* b, doubl
       *e_out = e.exec;
       return VC_OK;
     }
-  vc_status s = apply_op(P, sp.transpose, sp.mvp, b, P->s_tmp.as<double>(), nrhs, st);
+  vc_status s = apply_op(P, sp.transpose, sp.mvp, b, P->ws.tmp, nrhs, st);
   if (s != VC_OK) return s;
   VC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   vc_status sc = issue_cycle(P, sp, b, x, nrhs, st, part);
@@ -241,7 +255,7 @@ vc_status gmres(vc_problem* P, const SolveSpec& sp, const double* b, double* x, 
   if (s != VC_OK) return s;
   const Cyc c = cycle_views(P, nrhs, m);
   VC_HIP(hipMemcpyAsync(c.rtol, &sp.rtol, sizeof(double), hipMemcpyHostToDevice, st));
-  VC_HIP(launch_colnorm(b, N, N, nrhs, c.bn, P->s_partial.as<double>(), st));
+  VC_HIP(launch_colnorm(b, N, N, nrhs, c.bn, P->ws.partial, st));
   VC_HIP(hipMemsetAsync(c.iters, 0, (size_t)nrhs * sizeof(int), st));
   VC_HIP(hipMemsetAsync(c.bad, 0, sizeof(int), st));
   VC_HIP(hipMemsetAsync(c.skip + 2, 0, sizeof(int), st));
@@ -308,11 +322,16 @@ vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const doub
   sp.max_iter = o.max_iter;
   std::vector<int> it;
   std::vector<double> rre;
-  P->use_graphs = o.graph == 0;
-  if (!st) st = get_solve_stream(P);
-  if (!st) { set_error("could not create the solve stream"); return VC_ERR_HIP; }
+  // a call without allocation (static scratch) issues every cycle eagerly on the
+  // caller's stream: capturing and instantiating graphs, and creating a stream, allocate
+  P->use_graphs = o.graph == 0 && !P->ws_static;
+  if (!st && !P->ws_static) {
+    st = get_solve_stream(P);
+    if (!st) { set_error("could not create the solve stream"); return VC_ERR_HIP; }
+  }
   if (o.use_precond < 0 || o.use_precond > 3) { set_error("use_precond must be 0, 1, 2 or 3"); return VC_ERR_ARG; }
   if (o.use_precond == 3) {
+    if (P->ws_static) { set_error("use_precond 3 builds its blocks (allocates) on first use"); return VC_ERR_ARG; }
     if (P->pack) { set_error("packed sets use the block-diagonal-diagonal or diagonal preconditioner"); return VC_ERR_ARG; }
     // built on first use, before any restart cycle is captured
     const vc_status bs = build_precond_full(P, st);
@@ -329,13 +348,13 @@ vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const doub
     // outer FP64 refinement: r = b - A x (FP64 product), inner FP32 GMRES on A d = r, x += d
     s = ensure_workspace(P, nrhs, o.restart);
     if (s != VC_OK) return s;
-    double* rrp = P->s_rr.as<double>();   // stable buffers: the inner solves reuse their graph
-    double* ddp = P->s_dd.as<double>();
+    double* rrp = P->ws.rr;   // stable buffers: the inner solves reuse their graph
+    double* ddp = P->ws.dd;
     std::vector<int> tot(nrhs, 0);
     SolveSpec s64 = sp;
     s64.mvp = VC_FP64;
     std::vector<double> bn, rn, keep(nrhs), ones(nrhs, 1.0);
-    s = col_norms(P, b, N, nrhs, P->s_norm.as<double>(), bn, st);
+    s = col_norms(P, b, N, nrhs, P->ws.norm, bn, st);
     if (s != VC_OK) return s;
     VC_HIP(hipMemcpyAsync(rrp, b, (size_t)nrhs * N * sizeof(double), hipMemcpyDeviceToDevice, st));
     s = VC_ERR_NOT_CONVERGED;
@@ -352,11 +371,11 @@ vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const doub
       vc_status si = gmres(P, s32, rrp, ddp, nrhs, it, rre, st);
       if (si != VC_OK && si != VC_ERR_NOT_CONVERGED) return si;
       for (int c = 0; c < nrhs; ++c) tot[c] += it[c];
-      VC_HIP(hipMemcpyAsync(P->s_norm.as<double>() + nrhs, ones.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
-      VC_HIP(launch_axpy_cols(x, ddp, N, nrhs, P->s_norm.as<double>() + nrhs, 0, st));
+      VC_HIP(hipMemcpyAsync(P->ws.norm + nrhs, ones.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+      VC_HIP(launch_axpy_cols(x, ddp, N, nrhs, P->ws.norm + nrhs, 0, st));
       vc_status sr = residual(P, s64, b, x, rrp, nrhs, st);
       if (sr != VC_OK) return sr;
-      sr = col_norms(P, rrp, N, nrhs, P->s_norm.as<double>(), rn, st);
+      sr = col_norms(P, rrp, N, nrhs, P->ws.norm, rn, st);
       if (sr != VC_OK) return sr;
       bool ok = true;
       worst = 0.0;
@@ -368,9 +387,9 @@ vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const doub
       }
       if (ok) { s = VC_OK; ++ir_steps; break; }
       // columns already within rtol get a zero residual: the next inner solve leaves them
-      VC_HIP(hipMemcpyAsync(P->s_norm.as<double>() + 2 * nrhs, keep.data(), nrhs * sizeof(double),
+      VC_HIP(hipMemcpyAsync(P->ws.norm + 2 * nrhs, keep.data(), nrhs * sizeof(double),
                             hipMemcpyHostToDevice, st));
-      VC_HIP(launch_scale_cols(rrp, N, N, nrhs, P->s_norm.as<double>() + 2 * nrhs, 0, st));
+      VC_HIP(launch_scale_cols(rrp, N, N, nrhs, P->ws.norm + 2 * nrhs, 0, st));
     }
     it = tot;
     if (s != VC_OK) set_error("refinement did not reach rtol %.3g in %d steps", o.rtol, o.ir_max);

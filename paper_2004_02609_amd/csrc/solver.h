@@ -45,6 +45,12 @@ vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const doub
                 vc_stats* stats, hipStream_t st, std::vector<int>* it_out = nullptr,
                 std::vector<double>* rre_out = nullptr);
 vc_solve_opts fill_defaults(const vc_solve_opts* in);
+// vc_capacitance in two parts (api.cpp): argument checks and defaults; then, with the
+// workspace regions in place (P->ws) and st the stream, the solve, the reduction of
+// eq. (8) and the copies of C (and rho) out
+vc_status capacitance_check(vc_problem* p, const vc_solve_opts* opts, const double* C, vc_solve_opts* o);
+vc_status capacitance_run(vc_problem* p, const vc_solve_opts& o, double* C, double* rho_dev, vc_stats* stats,
+                          hipStream_t st, std::vector<double>* rho_host, double t0);
 // packed sets (pack.cpp): members must outlive the combined problem
 vc_status pack_create(vc_problem* const* problems, int n, vc_problem** out);
 vc_status pack_capacitance(vc_problem* q, const vc_solve_opts* opts, double* const* C_out, vc_stats* stats);

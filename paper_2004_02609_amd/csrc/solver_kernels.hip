@@ -540,6 +540,30 @@ hipError_t launch_zero(double* p, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
+__global__ void k_zero_u32(unsigned* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+// unit-potential right-hand sides: grid (ceil(N / 256), m)
+__global__ void k_unit_rhs(double* __restrict__ b, const int32_t* __restrict__ pcond, int64_t N) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (k < N) b[(int64_t)j * N + k] = pcond[k] == j ? 1.0 : 0.0;
+}
+
+hipError_t launch_unit_rhs(double* b, const int32_t* pcond, int64_t N, int m, hipStream_t st) {
+  if (N <= 0 || m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unit_rhs, dim3((unsigned)((N + 255) / 256), m), dim3(256), 0, st, b, pcond, N);
+  return hipGetLastError();
+}
+
 // x[r] += z[r] for the columns active this cycle; skipped when *skip
 __global__ void k_add_active(double* __restrict__ x, const double* __restrict__ z, int64_t N,
                              const int* __restrict__ act, const int* __restrict__ skip) {

@@ -77,6 +77,8 @@ _sig = {
     "vc_precond_info": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "vc_capacitance": (C.c_int, [_P, C.POINTER(vc_solve_opts), C.POINTER(C.c_double), C.c_void_p,
                                  C.POINTER(vc_stats)]),
+    "vc_capacitance_static": (C.c_int, [_P, C.POINTER(vc_solve_opts), C.POINTER(C.c_double), C.c_void_p,
+                                        C.POINTER(vc_stats), _P]),
     "vc_capacitance_grad_eps": (C.c_int, [_P, C.POINTER(vc_solve_opts), C.POINTER(C.c_int32), C.c_int32,
                                           C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(vc_stats)]),
     "vc_update_eps": (C.c_int, [_P, C.POINTER(C.c_double), C.c_double, _P]),
@@ -486,6 +488,15 @@ def vc_capacitance(h, m, rho=None, allow_not_converged=False, **solve):
     return Cm, st, status
 
 
+def vc_capacitance_static(h, m, rho=None, stream=None, **solve):
+    o = _solve_opts(**solve)
+    Cm = np.zeros((m, m))
+    st = vc_stats()
+    _check(_lib.vc_capacitance_static(h, C.byref(o), Cm.ctypes.data_as(C.POINTER(C.c_double)), _ptr(rho),
+                                      C.byref(st), _stream(stream)), "vc_capacitance_static")
+    return Cm, st
+
+
 def vc_capacitance_grad_eps(h, m, block_of_voxel, nblocks, **solve):
     o = _solve_opts(**solve)
     blk = np.ascontiguousarray(block_of_voxel, dtype=np.int32)
@@ -677,6 +688,16 @@ class Problem:
 
     def capacitance(self, rho=None, **solve):
         Cm, st, _ = vc_capacitance(self._h, self.m, rho=rho, **solve)
+        return Cm, stats_dict(st, self.m)
+
+    def capacitance_static(self, rho=None, stream=None, **solve):
+        """capacitance() with the solve's device arrays in the library's static scratch
+        (vc_capacitance_static: no device allocation, no graphs)."""
+        if rho is not None:
+            rho_c, _ = self._vectors(rho, None)
+            if rho_c.shape[0] != self.m or rho_c.data_ptr() != rho.data_ptr():
+                raise ValueError(f"rho must be a contiguous ({self.m}, {self.N}) float64 tensor on cuda:{self.device}")
+        Cm, st = vc_capacitance_static(self._h, self.m, rho=rho, stream=stream, **solve)
         return Cm, stats_dict(st, self.m)
 
     def update_eps(self, eps_r, eps_background=None, stream=None):
