@@ -3,12 +3,14 @@
 
 One step = one batched application of the operator of eq. (4) through the FFT product
 to all m right-hand sides of the workload (the unit of work of every GMRES iteration),
-in the precision the mixed solve uses for its inner iterations (FP32 FFT and block
-multiply; FP64 input, output and diagonal term).  value = RHS-products per second.
+in the form the workload's mixed solve uses for its inner iterations: FP32 FFT and
+block multiply (FP64 input, output and diagonal term), and for the meander lines
+(the default) the kernel spectra Tucker-compressed at 1e-8 and rebuilt on the matrix
+cores inside every step (eq. 13).  value = RHS-products per second.
 
-Also reported: the FP64 product rate, the C-matrix solve time in FP64 and in mixed
-precision at the same accuracy, a roofline entry for the dominant pass (algorithmic
-bytes from the library's byte model / live HIP-event durations), and the FP64 CPU
+Also reported: the uncompressed FP32 and the FP64-plain product rates, the C-matrix
+solve time in mixed precision (the step's form) and in FP64 plain at the same accuracy,
+a roofline entry for the dominant pass (live HIP-event durations), and the FP64 CPU
 oracle timed on a bounded sample of the same workload.
 """
 import argparse
@@ -74,22 +76,51 @@ def load_traffic(config, kernel, prec):
     return t.get("passes", {}).get(kernel)
 
 
-def cpu_baseline(scene, nrhs, budget_s=20.0):
-    """FP64 oracle: dense rows of eq. (4) assembled for a row sample, then the dense
-    product of that row block timed and scaled to a full N-row product."""
+def host_info():
+    """CPU model, the cores this process may run on and the BLAS thread pools."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = []
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [{"api": d.get("internal_api"), "threads": d.get("num_threads")} for d in threadpool_info()
+                if d.get("user_api") == "blas"]
+    except Exception:
+        pass
+    return {"cpu_model": model, "cores": len(os.sched_getaffinity(0)), "blas": blas}
+
+
+def cpu_baseline(scene, nrhs, budget_s=15.0, max_rows=512):
+    """FP64 oracle: dense rows of eq. (4) assembled for a random row sample (as many as
+    the budget allows, at least 4), then the dense product of that row block with all
+    right-hand sides timed and scaled to a full N-row product."""
     import numpy as np
 
     import oracle
     from oracle import dense
-    cores = len(os.sched_getaffinity(0))
     p = oracle.panelize(scene["cond_id"], scene["eps_r"], scene["eps_b"])
     N = len(p["axis"])
     rng = np.random.default_rng(0)
-    nrow = min(N, 512)
-    rows = np.sort(rng.choice(N, nrow, replace=False))
+    order = rng.permutation(N)[:min(N, max_rows)]
+    blocks = []
     t0 = time.perf_counter()
-    A = dense.assemble_rows(p, rows)
+    done = 0
+    while done < len(order):
+        step = min(8, len(order) - done)
+        rows = np.sort(order[done:done + step])
+        blocks.append((rows, dense.assemble_rows(p, rows)))
+        done += step
+        if time.perf_counter() - t0 > budget_s and done >= 4:
+            break
     t_asm = time.perf_counter() - t0
+    A = np.concatenate([b for _, b in blocks], axis=0)
+    nrow = A.shape[0]
     X = rng.standard_normal((N, nrhs))
     reps = 0
     t0 = time.perf_counter()
@@ -97,15 +128,66 @@ def cpu_baseline(scene, nrhs, budget_s=20.0):
         A @ X
         reps += 1
         el = time.perf_counter() - t0
-        if el > min(5.0, budget_s) or reps >= 2000:
+        if el > 5.0 or reps >= 2000:
             break
     t_block = el / reps
     t_full = t_block * N / nrow
-    return {"value": nrhs / t_full, "unit": "RHS-MVPs/s", "cores": cores, "kind": "oracle",
+    h = host_info()
+    return {"value": nrhs / t_full, "unit": "RHS-MVPs/s", "cores": h["cores"], "kind": "oracle",
             "sample": (f"{nrow} random rows of the dense eq.(4) matrix (N={N}) assembled by the oracle in "
                        f"{t_asm:.1f}s ({t_asm / nrow * N:.0f}s extrapolated to all rows, not counted), "
                        f"row-block product with {nrhs} RHS timed over {reps} reps and scaled by N/rows"),
-            "assembly_s_per_row": t_asm / nrow}
+            "assembly_s_per_row": t_asm / nrow, "cpu_model": h["cpu_model"], "blas": h["blas"]}
+
+
+# scenes of the oracle timing table: the two dense-solvable workloads at full size and
+# the three larger ones scaled down by the same seeded generators
+ORACLE_TABLE = [
+    ("cube16", lambda sc: sc.cube(16, 1.0)),
+    ("plates", lambda sc: sc.parallel_plates()),
+    ("random128/4 (32^3, 8 conductors, 6 dielectric boxes)",
+     lambda sc: sc.random_boxes(n=32, edge=(2, 6))),
+    ("meander/8 (64x64x16, 4 lanes, 2 runs)",
+     lambda sc: sc.meander(nx=64, ny=64, runs=2, run_pitch=24, x0=8, x1=48)),
+    ("grad256/5 (48x48x16, 6 conductors, 16 blocks)",
+     lambda sc: sc.gradient_scene(nx=48, ny=48, nz=16, sub=(2, 14))),
+]
+
+
+def oracle_table():
+    """The FP64 oracle's dense route on this host: assembly of eq. (4), LU factorisation
+    and one dense product with all right-hand sides, per scene (no GPU)."""
+    import numpy as np
+
+    import oracle
+    import scenes
+    from oracle import dense
+    out = {"host": host_info(), "rows": []}
+    for name, make in ORACLE_TABLE:
+        s = make(scenes)
+        p = oracle.panelize(s["cond_id"], s["eps_r"], s["eps_b"])
+        N = len(p["axis"])
+        t0 = time.perf_counter()
+        A = dense.assemble(p)
+        t_asm = time.perf_counter() - t0
+        B = dense.rhs(p)
+        t0 = time.perf_counter()
+        rho, lu = dense.solve(A, B)
+        t_lu = time.perf_counter() - t0
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            A @ B
+            reps += 1
+            if time.perf_counter() - t0 > 2.0:
+                break
+        t_mvp = (time.perf_counter() - t0) / reps
+        row = {"scene": name, "grid": list(s["cond_id"].shape), "N": N, "m": int(p["m"]),
+               "assembly_s": t_asm, "lu_solve_s": t_lu, "dense_mvp_s": t_mvp,
+               "rhs_mvps_per_s": p["m"] / t_mvp, "dense_gflops": 2.0 * N * N * p["m"] / t_mvp / 1e9}
+        out["rows"].append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+        del A, lu
+    print(json.dumps(out), flush=True)
 
 
 def _pmc_rows(d, counter):
@@ -177,55 +259,26 @@ def write_traffic(args):
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
 
 
-def tucker_run(args, scene, x, stream, B, ms_product_full):
-    """The same product with the spectra Tucker-compressed (eq. 13) and rebuilt on the
-    matrix cores before each product: compression ratio, rebuild time, the paper's
-    computational overhead CO = rebuild time / one product, and the rebuild's MFMA
-    rate (dense GEMM flops of the three mode products) and output bandwidth."""
-    import torch
-
-    from paper_2004_02609_amd import voxcap
-    Pt = voxcap.Problem.from_scene(scene).setup(tucker_tol=args.tucker_tol, autotune=not args.no_tune,
-                                                precisions=2 if args.prec == "fp32" else 1)
-    y = torch.empty_like(x)
-    for _ in range(3):
-        Pt.apply(x, y, prec=args.prec, stream=stream)
-    torch.cuda.synchronize()
-    Pt.tucker_info()                       # drop what was recorded before
-    base = Pt.tucker_info()
-    steps = max(5, args.steps // 4)
-    # product rate without timing events, then the rebuild's own time with events
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(steps):
-        Pt.apply(x, y, prec=args.prec, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    Pt.profile(1)
-    for _ in range(steps):
-        Pt.apply(x, y, prec=args.prec, stream=stream)
-    torch.cuda.synchronize()
-    Pt.profile(0)
-    Pt.pass_times()
-    info = Pt.tucker_info()
-    n_rb = info["rebuilds"] - base["rebuilds"]
-    rb_ms = (info["rebuild_ms"] - base["rebuild_ms"]) / max(1, n_rb)
-    D = (Pt.fft_size()[0] // 2 + 1, Pt.fft_size()[1] // 2 + 1, Pt.fft_size()[2] // 2 + 1)
+def tucker_summary(P, prec, ms_step, ms_step_plain, rb_ms):
+    """Tucker form of the step's spectra (eq. 13): ranks, compression ratio, the rebuild's
+    time from the profiled run, the paper's computational overhead CO = rebuild time /
+    one uncompressed product, and the rebuild's MFMA rate (dense GEMM flops of the three
+    mode products) and output bandwidth."""
+    info = P.tucker_info()
+    D = (P.fft_size()[0] // 2 + 1, P.fft_size()[1] // 2 + 1, P.fft_size()[2] // 2 + 1)
     flops = 0.0
     out_bytes = 0.0
-    elem = 4 if args.prec == "fp32" else 8
+    elem = 4 if prec == "fp32" else 8
     for r1, r2, r3 in info["ranks"]:
         flops += 2.0 * (r1 * r2 * r3 * D[2] + r1 * r2 * D[1] * D[2] + r1 * D[0] * D[1] * D[2])
         out_bytes += elem * (D[0] * D[1] * D[2] + 2 * r1 * D[1] * D[2])   # X written, T2 written and read
-    tf = flops / (rb_ms / 1e3) / 1e12
-    return {"tol": args.tucker_tol, "ranks": info["ranks"], "compression_ratio": info["compression_ratio"],
-            "product_ms_with_rebuild": ms, "rebuild_ms": rb_ms,
-            "computational_overhead": rb_ms / ms_product_full,
-            "rhs_products_per_s": B / (ms / 1e3),
-            "rebuild_mfma": {"flops": flops, "achieved_tflops": tf, "peak_tflops": MFMA_PEAK_TFLOPS[args.prec],
-                             "frac": tf / MFMA_PEAK_TFLOPS[args.prec]},
-            "rebuild_hbm": {"bytes": out_bytes, "achieved_gbs": out_bytes / (rb_ms / 1e3) / 1e9,
+    tf = flops / (rb_ms / 1e3) / 1e12 if rb_ms > 0 else None
+    return {"ranks": info["ranks"], "compression_ratio": info["compression_ratio"],
+            "step_ms_with_rebuild": ms_step, "rebuild_ms": rb_ms,
+            "computational_overhead": rb_ms / ms_step_plain if ms_step_plain else None,
+            "rebuild_mfma": {"flops": flops, "achieved_tflops": tf, "peak_tflops": MFMA_PEAK_TFLOPS[prec],
+                             "frac": tf / MFMA_PEAK_TFLOPS[prec] if tf else None},
+            "rebuild_hbm": {"bytes": out_bytes, "achieved_gbs": out_bytes / (rb_ms / 1e3) / 1e9 if rb_ms > 0 else None,
                             "peak_gbs": HBM_PEAK_GBS}}
 
 
@@ -344,22 +397,97 @@ def batch_run(args):
             "scenes_per_s_batched": len(ss) / t_batch, "max_rel_diff_batch_vs_single": diff}
 
 
+# Tucker tolerance of each workload's step (the meander lines are specified compressed)
+WORKLOAD_TUCKER = {"meander": 1e-8}
+
+
+def timed_products(P, x, y, prec, stream, steps, warm, level, every=1):
+    """Warm-up, then `steps` products bracketed by two events (level 2: HIP events around
+    the x pass on every `every`-th step; level 1: around every pass)."""
+    import torch
+    for _ in range(warm):
+        P.apply(x, y, prec=prec, stream=stream)
+    torch.cuda.synchronize()
+    P.pass_times()                       # drop anything recorded before
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for k in range(steps):
+        P.profile(level if k % every == 0 else 0)
+        P.apply(x, y, prec=prec, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    P.profile(0)
+    return e0.elapsed_time(e1), P.pass_times()
+
+
+def solve_times(Pm, P64, log):
+    """C-matrix solve times: mixed precision on the step's problem (Pm) and FP64 plain on
+    the uncompressed one (P64), both at the loosest GMRES tolerance at which every gated
+    entry of C is within 1e-6 of the FP64 solve at rtol 1e-12, and at rtol 1e-9."""
+    import numpy as np
+    import torch
+    Cref, _ = P64.capacitance(prec="fp64", rtol=1e-12)
+    gate = np.abs(Cref) >= 1e-3 * np.abs(np.diag(Cref)).max()
+
+    def cerr(Cm):
+        return float((np.abs(Cm - Cref)[gate] / np.abs(Cref)[gate]).max())
+
+    def timed(P, mode, rtol):
+        """Median of three warm solves (the restart-cycle graphs are captured by a first,
+        untimed solve), with the entrywise error of the last against FP64 at 1e-12."""
+        P.capacitance(prec=mode, rtol=rtol)
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Cm, st = P.capacitance(prec=mode, rtol=rtol)
+            ts.append(time.perf_counter() - t0)
+        return {"time_s": float(np.median(ts)), "times_s": ts, "iters": st["iters"], "ir_steps": st["ir_steps"],
+                "max_rel_err_vs_fp64_1e-12": cerr(Cm), "products": st["mvp_count"], "rtol": rtol,
+                "spectra_bytes": st["spectra_bytes"]}
+
+    runs = (("fp64", P64), ("mixed", Pm))
+    cal = 1e-10
+    for rt in (1e-5, 1e-6, 1e-7, 1e-8, 1e-9):
+        if all(cerr(P.capacitance(prec=mode, rtol=rt)[0]) <= 1e-6 for mode, P in runs):
+            cal = rt
+            break
+    out = {"rtol_for_1e-6": cal, "mixed_spectra": "tucker" if Pm is not P64 else "uncompressed"}
+    for mode, P in runs:
+        out[mode] = timed(P, mode, cal)
+        log(f"# solve {mode} at rtol {cal:g}: {out[mode]['time_s'] * 1e3:.1f} ms, "
+            f"err {out[mode]['max_rel_err_vs_fp64_1e-12']:.1e}")
+    out["speedup_mixed_vs_fp64"] = out["fp64"]["time_s"] / out["mixed"]["time_s"]
+    out["at_rtol_1e-9"] = {mode: timed(P, mode, 1e-9) for mode, P in runs}
+    out["at_rtol_1e-9"]["speedup_mixed_vs_fp64"] = (out["at_rtol_1e-9"]["fp64"]["time_s"] /
+                                                    out["at_rtol_1e-9"]["mixed"]["time_s"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P64.capacitance(prec="fp64", rtol=cal, graph=False)
+    out["fp64_no_graph_time_s"] = time.perf_counter() - t0
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default="plates", choices=sorted(WORKLOADS))
+    ap.add_argument("--config", default="meander", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="heuristic x-pass configuration instead of the autotuner")
-    ap.add_argument("--no-other", action="store_true", help="skip the product in the other precision")
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip the uncompressed and other-precision product rates")
     ap.add_argument("--batch", type=int, default=32,
                     help="also solve this many uneven random scenes (edges 16-64) as one packed set and one by one "
                          "(0: skip)")
-    ap.add_argument("--tucker-tol", type=float, default=1e-8,
-                    help="also run the product with Tucker-compressed spectra at this tolerance (0: skip)")
+    ap.add_argument("--tucker-tol", type=float, default=None,
+                    help="Tucker tolerance of the step's spectra (default: the workload's, 1e-8 for meander, "
+                         "else uncompressed; 0: uncompressed)")
     ap.add_argument("--toeplitz-tol", type=float, default=1e-8,
                     help="also build a Toeplitz cache over a larger grid at this tolerance and set the workload up "
                          "from it (0: skip)")
@@ -368,9 +496,14 @@ def main():
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="(no GPU) turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this command with "
                          "--calib-copy-mib into profiles/traffic_<config>_<prec>.json, then exit")
+    ap.add_argument("--oracle-table", action="store_true",
+                    help="(no GPU) time the FP64 oracle's assembly, LU and dense product on this host, then exit")
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(args)
+        return
+    if args.oracle_table:
+        oracle_table()
         return
     if args.gpus != 1:
         print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -383,6 +516,9 @@ def main():
     import scenes
     from paper_2004_02609_amd import voxcap
 
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     dev = torch.device("cuda:0")
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib << 18
@@ -392,9 +528,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    tucker_tol = WORKLOAD_TUCKER.get(args.config, 0.0) if args.tucker_tol is None else args.tucker_tol
     scene = scenes.by_name(args.config)
     t0 = time.perf_counter()
-    P = voxcap.Problem.from_scene(scene).setup(autotune=not args.no_tune)
+    P = voxcap.Problem.from_scene(scene).setup(autotune=not args.no_tune, tucker_tol=tucker_tol)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     B, N = P.m, P.N
@@ -402,51 +539,50 @@ def main():
     g = torch.Generator(device=dev).manual_seed(0)
     x = torch.randn(B, N, dtype=torch.float64, device=dev, generator=g)
     y = torch.empty_like(x)
+    log(f"# {args.config}: N={N} m={B} fft={P.fft_size()} tucker_tol={tucker_tol:g} setup {t_setup:.2f}s")
 
-    def run(prec, steps, warm, level, every=1):
-        # level 2: HIP events around the x pass only (the timed run, on every `every`-th
-        # step: each event adds a few us between the launches it separates); level 1:
-        # around every pass (the breakdown run)
-        for _ in range(warm):
-            P.apply(x, y, prec=prec, stream=stream)
-        torch.cuda.synchronize()
-        P.pass_times()                       # drop anything recorded before
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for k in range(steps):
-            P.profile(level if k % every == 0 else 0)
-            P.apply(x, y, prec=prec, stream=stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        P.profile(0)
-        ms = e0.elapsed_time(e1)
-        return ms, P.pass_times()
-
-    print(f"# {args.config}: N={N} m={B} fft={P.fft_size()} setup {t_setup:.2f}s", file=sys.stderr, flush=True)
+    # the step: timed with events around the x pass on every `every`-th step
     every = max(1, min(10, args.steps // 10))
-    ms, (pms, pcnt, pbytes) = run(args.prec, args.steps, args.warmup, 2, every)
+    ms, (pms, pcnt, pbytes) = timed_products(P, x, y, args.prec, stream, args.steps, args.warmup, 2, every)
     value = args.steps * B / (ms / 1e3)
-    # per-pass breakdown: a separate, shorter run with events around every pass
-    _, (bms, bcnt, bbytes) = run(args.prec, max(10, min(args.steps, 50)), 2, 1)
-    other = "fp64" if args.prec == "fp32" else "fp32"
-    value_o = None
-    if not args.no_other:
-        ms_o, _ = run(other, max(10, args.steps // 2), 3, 0)
-        value_o = max(10, args.steps // 2) * B / (ms_o / 1e3)
-        print(f"# {args.prec} product {ms / args.steps * 1e3:.1f} us/step, {other} "
-              f"{ms_o / max(10, args.steps // 2) * 1e3:.1f} us/step", file=sys.stderr, flush=True)
+    log(f"# step ({args.prec}{', Tucker rebuild' if tucker_tol > 0 else ''}): {ms / args.steps * 1e3:.1f} us")
+    # per-pass breakdown (and the Tucker rebuild's time): a separate, shorter run with
+    # events around every pass
+    nb = max(10, min(args.steps, 50))
+    tk0 = P.tucker_info() if tucker_tol > 0 else None
+    _, (bms, bcnt, bbytes) = timed_products(P, x, y, args.prec, stream, nb, 2, 1)
+    passes = {voxcap.PASS_NAMES[i]: {"avg_us": bms[i] / max(1, bcnt[i]) * 1e3, "launches": bcnt[i],
+                                     "alg_bytes": bbytes[i],
+                                     "alg_GBs": bbytes[i] / (bms[i] / max(1, bcnt[i]) / 1e3) / 1e9
+                                     if bms[i] > 0 else None}
+              for i in range(5)}
+    tucker = None
+    if tucker_tol > 0:
+        tk1 = P.tucker_info()
+        n_rb = tk1["rebuilds"] - tk0["rebuilds"]
+        tucker = {"tol": tucker_tol, "rebuild_ms": (tk1["rebuild_ms"] - tk0["rebuild_ms"]) / max(1, n_rb),
+                  "rebuilds_timed": n_rb}
 
-    dom = int(np.argmax(bms))
-    avg_ms = bms[dom] / max(1, bcnt[dom])
-    achieved = bbytes[dom] / (avg_ms / 1e3) / 1e9
-    kname = voxcap.PASS_NAMES[dom]
-    traffic = load_traffic(args.config, kname, args.prec)
+    # the uncompressed problem: FP32 rate without the rebuild, the FP64-plain rate and
+    # the FP64-plain solves
+    P64 = P
+    rates = {}
+    if tucker_tol > 0 and not (args.no_other and args.no_solve):
+        P64 = voxcap.Problem.from_scene(scene).setup(autotune=not args.no_tune)
+    if not args.no_other:
+        for prec in ("fp32", "fp64"):
+            if P64 is P and prec == args.prec:
+                rates[prec] = value
+                continue
+            n2 = max(10, args.steps // 2)
+            ms2, _ = timed_products(P64, x, y, prec, stream, n2, 3, 0)
+            rates[prec] = n2 * B / (ms2 / 1e3)
+            log(f"# uncompressed {prec} product: {ms2 / n2 * 1e3:.1f} us/step")
+
+    xi = voxcap.PASS_NAMES.index("x_sandwich_multiply")
     # the x pass does ~30 flops per algorithmic byte (nine transforms per column) and is
     # bound by vector-instruction issue, not HBM: report it against the vector peak
     nout = 6 if P.n_diel > 0 else 3
-    xi = voxcap.PASS_NAMES.index("x_sandwich_multiply")
     x_ms = pms[xi] / max(1, pcnt[xi])
     x_flops = xpass_flops(P.fft_size(), B, nout)
     x_tflops = x_flops / (x_ms / 1e3) / 1e12
@@ -457,59 +593,18 @@ def main():
                 "hbm_achieved_GBs": pbytes[xi] / (x_ms / 1e3) / 1e9,
                 "hbm_frac": pbytes[xi] / (x_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
                 "timed_launches": pcnt[xi], "event_sampling": f"every {every}th of the {args.steps} timed steps"}
-    passes = {voxcap.PASS_NAMES[i]: {"avg_us": bms[i] / max(1, bcnt[i]) * 1e3, "launches": bcnt[i],
-                                     "alg_bytes": bbytes[i],
-                                     "alg_GBs": bbytes[i] / (bms[i] / max(1, bcnt[i]) / 1e3) / 1e9
-                                     if bms[i] > 0 else None}
-              for i in range(5)}
+    dom = int(np.argmax(bms))
+    avg_ms = bms[dom] / max(1, bcnt[dom])
+    achieved = bbytes[dom] / (avg_ms / 1e3) / 1e9
+    kname = voxcap.PASS_NAMES[dom]
+
+    if tucker is not None:
+        ms_plain = B / rates[args.prec] * 1e3 if args.prec in rates else None
+        tucker.update(tucker_summary(P, args.prec, ms / args.steps, ms_plain, tucker["rebuild_ms"]))
 
     solve = None
     if not args.no_solve:
-        solve = {}
-        Cref, st_ref = P.capacitance(prec="fp64", rtol=1e-12)
-        dmax = np.abs(np.diag(Cref)).max()
-        gate = np.abs(Cref) >= 1e-3 * dmax
-
-        def cerr(Cm):
-            return float((np.abs(Cm - Cref)[gate] / np.abs(Cref)[gate]).max())
-
-        def timed(mode, rtol):
-            """Median of three warm solves (the restart-cycle graphs are captured by a first,
-            untimed solve), with the entrywise error of the last against FP64 at 1e-12."""
-            P.capacitance(prec=mode, rtol=rtol)
-            ts = []
-            for _ in range(3):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                Cm, st = P.capacitance(prec=mode, rtol=rtol)
-                ts.append(time.perf_counter() - t0)
-            return {"time_s": float(np.median(ts)), "times_s": ts, "iters": st["iters"], "ir_steps": st["ir_steps"],
-                    "max_rel_err_vs_fp64_1e-12": cerr(Cm), "products": st["mvp_count"], "rtol": rtol}
-
-        # the metric's accuracy: the loosest GMRES tolerance at which both the FP64 and the
-        # mixed solve give every gated entry of C within 1e-6 of the FP64 reference
-        cal = 1e-10
-        for rt in (1e-5, 1e-6, 1e-7, 1e-8, 1e-9):
-            if all(cerr(P.capacitance(prec=mode, rtol=rt)[0]) <= 1e-6 for mode in ("fp64", "mixed")):
-                cal = rt
-                break
-        solve["rtol_for_1e-6"] = cal
-        for mode in ("fp64", "mixed"):
-            solve[mode] = timed(mode, cal)
-        solve["speedup_mixed_vs_fp64"] = solve["fp64"]["time_s"] / solve["mixed"]["time_s"]
-        # the same pair at a fixed, tighter tolerance
-        solve["at_rtol_1e-9"] = {mode: timed(mode, 1e-9) for mode in ("fp64", "mixed")}
-        solve["at_rtol_1e-9"]["speedup_mixed_vs_fp64"] = (solve["at_rtol_1e-9"]["fp64"]["time_s"] /
-                                                          solve["at_rtol_1e-9"]["mixed"]["time_s"])
-        # the FP64 solve with the restart cycle's kernels issued one by one
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        P.capacitance(prec="fp64", rtol=cal, graph=False)
-        solve["fp64_no_graph_time_s"] = time.perf_counter() - t0
-
-    tucker = None
-    if args.tucker_tol > 0:
-        tucker = tucker_run(args, scene, x, stream, B, ms / args.steps)
+        solve = solve_times(P, P64, log)
 
     toeplitz = None
     if args.toeplitz_tol > 0:
@@ -523,20 +618,22 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(scene, B)
 
+    form = f"FP32 FFT product{' with Tucker-%g spectra rebuilt each step' % tucker_tol if tucker_tol > 0 else ''}"
     line = {
         "metric": "FFT-MVPs/s + C-matrix solve time @1e-6 rel err, mixed/batched vs FP64 plain",
         "value": value, "unit": "RHS-MVPs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.prec == "fp32" else "f64", "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "panels": N, "rhs": B,
-                   "fft_size": list(P.fft_size()), "product_precision": args.prec},
+                   "fft_size": list(P.fft_size()), "product_precision": args.prec, "tucker_tol": tucker_tol,
+                   "step": form if args.prec == "fp32" else form.replace("FP32", "FP64")},
         "roofline": roofline,
         "product_hbm": {"dominant_pass": kname, "achieved_GBs": achieved, "frac": achieved / HBM_PEAK_GBS,
-                        "traffic": traffic,
+                        "traffic": load_traffic(args.config, kname, args.prec),
                         "all_passes_alg_bytes": float(sum(bbytes)),
                         "all_passes_GBs": float(sum(bbytes)) / (ms / args.steps / 1e3) / 1e9},
         "cpu_baseline": cpu,
-        "other_precision": {"prec": other, "value": value_o, "unit": "RHS-MVPs/s"} if value_o else None,
+        "uncompressed_rates": {p: {"value": v, "unit": "RHS-MVPs/s"} for p, v in rates.items()},
         "passes": passes,
         "solve": solve,
         "setup_s": t_setup,
