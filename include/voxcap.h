@@ -384,6 +384,13 @@ vc_status vc_setup_toeplitz_source(vc_problem *p, const vc_toeplitz_cache *c);
 /* Wall time of the last vc_setup, and the part of it spent producing the Toeplitz
  * tensors in circulant form (the integrals, or restore + crop + embed). */
 vc_status vc_setup_time(const vc_problem *p, double *total_s, double *toeplitz_s);
+/* Device bytes the problem holds after vc_setup (Sec. II.C is about this memory):
+ * spectra_bytes: the kernel spectra as stored, uncompressed (6 or 15 real octants per
+ * kept precision) or in the Tucker form (cores and factors in FP64 and FP32, plus the
+ * strips T1 and T2 each product rebuilds; the spectra themselves are never stored);
+ * work_bytes: the product's spectral work arrays and the solver workspace allocated so
+ * far.  Any output pointer may be null. */
+vc_status vc_memory_info(const vc_problem *p, double *spectra_bytes, double *work_bytes);
 
 const char *vc_status_string(vc_status s);
 const char *vc_last_error(void);

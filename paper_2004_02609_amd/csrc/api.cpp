@@ -154,6 +154,14 @@ vc_status vc_setup_time(const vc_problem* p, double* total_s, double* toeplitz_s
   return VC_OK;
 }
 
+vc_status vc_memory_info(const vc_problem* p, double* spectra_bytes, double* work_bytes) {
+  if (!p) { set_error("null problem"); return VC_ERR_ARG; }
+  if (!p->setup_done) { set_error("vc_setup has not run"); return VC_ERR_STATE; }
+  if (spectra_bytes) *spectra_bytes = p->spectra_bytes;
+  if (work_bytes) *work_bytes = (double)(p->work_F.bytes + p->work_O.bytes + p->s_all.bytes);
+  return VC_OK;
+}
+
 vc_status vc_apply(vc_problem* p, int transpose, vc_precision prec, const double* x, double* y, int32_t nrhs,
                    void* stream) {
   VC_CHECK_PROBLEM(p);
@@ -558,7 +566,7 @@ vc_status vc_xpass_candidates(vc_problem* p, vc_precision prec, int transpose, i
   if (prec != VC_FP64 && prec != VC_FP32) { set_error("prec must be VC_FP64 or VC_FP32"); return VC_ERR_ARG; }
   const int elem = prec == VC_FP32 ? 4 : 8;
   const int nin = (transpose && p->n_diel > 0) ? 6 : 3;
-  const std::vector<vc::SandCfg> cand = vc::sandwich_candidates(p->M[0], elem, nin, p->n1[0], vc::kLdsBudget);
+  const std::vector<vc::SandCfg> cand = vc::sandwich_candidates(p->M[0], elem, nin, p->n1[0], vc::kLdsBudget, (int)p->tk.size(), p->Hx);
   *n_rows = (int32_t)cand.size();
   for (int32_t r = 0; r < (int32_t)cand.size() && r < max_rows; ++r) {
     int32_t* row = out + 8 * r;
@@ -577,7 +585,7 @@ vc_status vc_xpass_set(vc_problem* p, vc_precision prec, int transpose, int32_t 
   if (prec != VC_FP64 && prec != VC_FP32) { set_error("prec must be VC_FP64 or VC_FP32"); return VC_ERR_ARG; }
   const int elem = prec == VC_FP32 ? 4 : 8;
   const int nin = (transpose && p->n_diel > 0) ? 6 : 3;
-  const std::vector<vc::SandCfg> cand = vc::sandwich_candidates(p->M[0], elem, nin, p->n1[0], vc::kLdsBudget);
+  const std::vector<vc::SandCfg> cand = vc::sandwich_candidates(p->M[0], elem, nin, p->n1[0], vc::kLdsBudget, (int)p->tk.size(), p->Hx);
   for (const vc::SandCfg& g : cand) {
     bool same = cfg[0] == g.nst && cfg[7] == g.ncol;
     for (int s2 = 0; s2 < 6 && same; ++s2)

@@ -53,7 +53,13 @@ static void pass_byte_model(vc_problem* P, int transpose, int elem, int nrhs, do
   const double B = nrhs, row = (double)P->H * 2 * elem, plane = row * P->M[1];
   const double N = (double)npanels(P), Nd = (double)P->n_diel, it = (double)P->items.size();
   const double npairs = P->n_diel > 0 ? 15 : 6;
-  const double R = npairs * P->Hy * P->H * P->Hx * elem;
+  // the stored spectra, or in the Tucker form the factor U1 and the strip T2 the x pass
+  // builds them from
+  double R = npairs * P->Hy * P->H * P->Hx * elem;
+  if (!P->tk.empty()) {
+    R = 0.0;
+    for (const TuckerPair& tp : P->tk) R += (double)tp.r[0] * ((double)P->Hy * P->H + P->Hx) * elem;
+  }
   const double idx = N * 5 + it * 12;
   if (!transpose) {
     out[0] = N * B * 8 + idx + Lany * row * B;
@@ -75,8 +81,13 @@ static void pass_byte_model(vc_problem* P, int transpose, int elem, int nrhs, do
 // thread limit (512, or 1024 for the wide compiled plans) and the LDS budget that is a
 // power of two or keeps at least 3/4 of the workgroup's lanes busy (tl x ncol of the
 // rounded-up thread count).
-std::vector<SandCfg> sandwich_candidates(int L, int elem, int nin, int n1x, size_t budget) {
+std::vector<SandCfg> sandwich_candidates(int L, int elem, int nin, int n1x, size_t budget, int tk_npairs, int Hx) {
   std::vector<SandCfg> out;
+  // the fused form holds the tile's spectra in LDS: up to the device's whole LDS
+  auto lds_of = [&](int c) {
+    return tk_npairs > 0 ? sandwich_tk_lds_bytes(L, c, elem, n1x, tk_npairs, Hx) : sandwich_lds_bytes(L, c, elem, n1x);
+  };
+  if (tk_npairs > 0) budget = lds_ext_budget();
   for (int rs = sandwich_rs_max(elem, nin); rs >= 2; --rs) {
     const AxisPlan sp = make_sandwich_plan(L, sandwich_rmax(elem), sandwich_rmid(elem), rs, 512);
     if (sp.nst < 1 || sp.rad[sp.nst - 1] != rs) continue;
@@ -85,7 +96,7 @@ std::vector<SandCfg> sandwich_candidates(int L, int elem, int nin, int n1x, size
     for (int s2 = 0; s2 < sp.nst; ++s2) pack |= (uint32_t)sp.rad[s2] << (5 * s2);
     const int maxt = sand_max_threads(L, sp.nst, pack, elem, nin);
     for (int c = 1; c <= 32; ++c) {
-      if ((int64_t)c * tl > maxt || sandwich_lds_bytes(L, c, elem, n1x) > budget) break;
+      if ((int64_t)c * tl > maxt || lds_of(c) > budget) break;
       const int nthr = (c * tl + 63) / 64 * 64;
       const bool pow2 = (c & (c - 1)) == 0;
       if (!pow2 && 4 * c * tl < 3 * nthr) continue;
@@ -145,8 +156,8 @@ bool ypass_config(int L, int elem, int ncols, size_t budget, YArgs* a, int* nthr
 // widest power-of-two tile of at most 256 threads (several workgroups per CU), else
 // the narrowest.  (Tiles of other widths are left to the autotuner: they fill waves
 // better but their gains and losses depend on the shape.)
-bool sandwich_default(int L, int elem, int nin, int n1x, size_t budget, SandCfg* cfg) {
-  const std::vector<SandCfg> cand = sandwich_candidates(L, elem, nin, n1x, budget);
+bool sandwich_default(int L, int elem, int nin, int n1x, size_t budget, SandCfg* cfg, int tk_npairs, int Hx) {
+  const std::vector<SandCfg> cand = sandwich_candidates(L, elem, nin, n1x, budget, tk_npairs, Hx);
   int best = -1;
   double bscore = -1e30;
   for (size_t k = 0; k < cand.size(); ++k) {
@@ -295,7 +306,7 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
       if (!(t0 = take_event(P)) || !(t1 = take_event(P))) { set_error("hipEventCreate failed"); return VC_ERR_HIP; }
       VC_HIP(hipEventRecord(t0, st));
     }
-    vc_status ts = tucker_rebuild<T>(P, (T*)tb.R.p, (int64_t)P->Hy * H * P->Hx, st, skip);
+    vc_status ts = tucker_rebuild<T>(P, st, skip);
     if (ts != VC_OK) return ts;
     if (prof == 1) {
       VC_HIP(hipEventRecord(t1, st));
@@ -338,6 +349,10 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
   xa.adjoint = transpose;
   xa.skip = skip;
   xa.act = act;
+  // Tucker form: the x pass builds each tile's spectra from U1 and T2 (no stored R)
+  const int tk_np = (int)P->tk.size();
+  xa.tk = tk_np > 0 ? P->tk_dev[sizeof(T) == 8 ? 1 : 0].as<TkPairDev>() : nullptr;
+  xa.npairs = tk_np;
   CompSet cout{};
   if (!transpose) {
     xa.nin = 3;
@@ -355,7 +370,7 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
     auto it = P->sand_choice.find(key);
     if (it == P->sand_choice.end()) {
       SandCfg cfg;
-      if (!sandwich_default(Mx, (int)sizeof(T), xa.nin, n1x, budget, &cfg)) {
+      if (!sandwich_default(Mx, (int)sizeof(T), xa.nin, n1x, budget, &cfg, tk_np, P->Hx)) {
         set_error("x transform length %d too long for the sandwich kernel", Mx);
         return VC_ERR_ARG;
       }
@@ -364,7 +379,7 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
       VC_HIP(hipStreamIsCapturing(st, &cap));
       if (P->autotune && cap == hipStreamCaptureStatusNone) {
         // time every candidate on the live work arrays (the chosen one runs again below)
-        const std::vector<SandCfg> cand = sandwich_candidates(Mx, (int)sizeof(T), xa.nin, n1x, budget);
+        const std::vector<SandCfg> cand = sandwich_candidates(Mx, (int)sizeof(T), xa.nin, n1x, budget, tk_np, P->Hx);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         VC_HIP(hipEventCreate(&e0));
         VC_HIP(hipEventCreate(&e1));

@@ -83,6 +83,15 @@ hipError_t launch_ypass_multi(const YScene* tab, int nscene, int nblocks, int rs
 // row lines); false when none fits
 bool ypass_config(int L, int elem, int ncols, size_t budget, YArgs* a, int* nthr);
 
+// Tucker form of one stored pair for the fused x pass (eq. 13): the factor U1 (Hx x r1p,
+// row-major) and the strip T2 = S x2 U2 x3 U3 (Hy x H x r1p, r fastest), in the
+// product's precision; r1p = r1 rounded up to 4, zero past r1 in both
+struct TkPairDev {
+  const void* U1;
+  const void* T2;
+  int r1, r1p;
+};
+
 struct SandArgs {
   int64_t comp_stride, rhs_stride, pair_stride;
   int nrhs, n1x, Mx, My, H, Hx, Hy;
@@ -98,11 +107,20 @@ struct SandArgs {
   uint64_t oddmask;
   const int* skip;   // optional device flag: when set, the launch does nothing
   const int* act;    // optional per right-hand side activity: workgroups of inactive ones return
+  // Tucker-fused form (null: the stored spectra R): per stored pair its U1 and T2
+  // (device table of npairs entries); one workgroup per tile runs every right-hand side
+  const TkPairDev* tk;
+  int npairs;
 };
 // dynamic LDS of the sandwich: twiddle table (+ the x phases in FP32) + one [L][ncol]
 // tile + 3 n1x plane flags
 inline size_t sandwich_lds_bytes(int L, int ncol, int elem, int n1x) {
   return (size_t)2 * elem * ((size_t)(elem == 4 ? 2 : 1) * L + (size_t)L * ncol) + (size_t)3 * n1x;
+}
+// the fused form: the tile's spectra [npairs][Hx][ncol] (16-byte aligned) + one [L][ncol]
+// tile + 3 n1x plane flags (the twiddles and x phases stay in global memory)
+inline size_t sandwich_tk_lds_bytes(int L, int ncol, int elem, int n1x, int npairs, int Hx) {
+  return (((size_t)npairs * Hx * ncol * elem + 15) & ~(size_t)15) + (size_t)2 * elem * L * ncol + (size_t)3 * n1x;
 }
 // x-transform plan of the sandwich for one precision / variant (see sandwich_impl.hpp):
 // fewest stages with the first radix <= rmax, middle radices <= rmid and the last
@@ -171,8 +189,9 @@ struct SandCfg {
   int nst, tl, ncol, nthr;
   uint32_t radpack;
 };
-// one sandwich variant (NIN input / NOUT output components), last-stage radix rs
-template <typename T, int NIN, int NOUT>
+// one sandwich variant (NIN input / NOUT output components, TK: Tucker-fused), last-stage
+// radix rs
+template <typename T, int NIN, int NOUT, int TK>
 hipError_t launch_sandwich_v(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
                              const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
                              size_t lds, int rs, hipStream_t st, hipEvent_t e0, hipEvent_t e1);

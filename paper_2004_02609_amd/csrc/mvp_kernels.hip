@@ -395,7 +395,11 @@ bool sandwich_args_ok(const SandArgs& a, int nthr) {
   // 32-bit byte offsets inside one (component, rhs) slab and one stored pair, each slab
   // small enough for the out-of-range offset of the buffer views (0xFFFFFFF0)
   if ((uint64_t)a.n1x * a.My * a.H * 2 * sizeof(T) > 0xFFFFFF00ull ||
-      (uint64_t)a.pair_stride * sizeof(T) > 0xFFFFFF00ull)
+      (!a.tk && (uint64_t)a.pair_stride * sizeof(T) > 0xFFFFFF00ull))
+    return false;
+  // the fused form: its stored pairs, and the tile's spectra within the device's LDS
+  if (a.tk && (a.npairs < 1 || a.npairs > 15 ||
+               sandwich_tk_lds_bytes(a.Mx, a.ncol, (int)sizeof(T), a.n1x, a.npairs, a.Hx) > lds_ext_budget()))
     return false;
   return true;
 }
@@ -406,13 +410,23 @@ hipError_t launch_sandwich(const void* Fin, void* Fout, const void* R, const San
                            hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (!sandwich_args_ok<T>(a, nthr)) return hipErrorInvalidValue;
   const int rs = (int)((a.radpack >> (5 * (a.nst - 1))) & 31u);
+  if (a.tk) {
+    const size_t lds = sandwich_tk_lds_bytes(a.Mx, a.ncol, (int)sizeof(T), a.n1x, a.npairs, a.Hx);
+    if (!a.adjoint && a.nin == 3 && a.nout == 6)
+      return launch_sandwich_v<T, 3, 6, 1>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
+    if (!a.adjoint && a.nin == 3 && a.nout == 3)
+      return launch_sandwich_v<T, 3, 3, 1>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
+    if (a.adjoint && a.nin == 6 && a.nout == 3)
+      return launch_sandwich_v<T, 6, 3, 1>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
+    return hipErrorInvalidValue;
+  }
   const size_t lds = sandwich_lds_bytes(a.Mx, a.ncol, (int)sizeof(T), a.n1x);
   if (!a.adjoint && a.nin == 3 && a.nout == 6)
-    return launch_sandwich_v<T, 3, 6>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
+    return launch_sandwich_v<T, 3, 6, 0>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
   if (!a.adjoint && a.nin == 3 && a.nout == 3)
-    return launch_sandwich_v<T, 3, 3>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
+    return launch_sandwich_v<T, 3, 3, 0>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
   if (a.adjoint && a.nin == 6 && a.nout == 3)
-    return launch_sandwich_v<T, 6, 3>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
+    return launch_sandwich_v<T, 6, 3, 0>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
   return hipErrorInvalidValue;
 }
 

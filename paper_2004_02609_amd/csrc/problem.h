@@ -15,8 +15,11 @@ namespace vc {
 
 void set_error(const char* fmt, ...);
 struct SandCfg;
-std::vector<SandCfg> sandwich_candidates(int L, int elem, int nin, int n1x, size_t budget);
-bool sandwich_default(int L, int elem, int nin, int n1x, size_t budget, SandCfg* cfg);
+// tk_npairs > 0: the Tucker-fused x pass of that many stored pairs (its LDS holds the
+// tile's spectra, Hx rows each)
+std::vector<SandCfg> sandwich_candidates(int L, int elem, int nin, int n1x, size_t budget, int tk_npairs = 0,
+                                         int Hx = 0);
+bool sandwich_default(int L, int elem, int nin, int n1x, size_t budget, SandCfg* cfg, int tk_npairs = 0, int Hx = 0);
 
 // Owning device allocation.
 struct DevMem {
@@ -70,6 +73,10 @@ struct PrecTables {
 struct TuckerPair {
   int r[3] = {0, 0, 0};
   DevMem S64, U64[3], S32, U32[3];
+  // the fused x pass's copies of U1 with rows padded to r1p = r1 rounded up to 4 (zero
+  // filled), so a row is read as whole 16-byte vectors
+  int r1p = 0;
+  DevMem U1p64, U1p32;
 };
 
 // The conventional block-diagonal preconditioner the paper compares against (Sec. III.A):
@@ -167,16 +174,21 @@ struct vc_problem {
   double t_setup = 0.0;
   double spectra_bytes = 0.0;
   double extract_resid = 0.0;
-  // Tucker compression of the stored spectra (tucker_tol > 0): rebuilt before each product
+  // Tucker compression of the stored spectra (tucker_tol > 0): the strips T1, T2 are
+  // rebuilt before each product and the x pass builds each tile's spectra from them
   double tucker_tol = 0.0;
   std::vector<vc::TuckerPair> tk;
-  vc::DevMem tk_T1, tk_T2;          // rebuild scratch (one region per stored pair)
+  // rebuild scratch, one region per stored pair: T1 (shared by the precisions, rewritten
+  // whole by each rebuild) and T2 per precision ([0] FP32, [1] FP64: their zero padding
+  // past r1 must stay zero)
+  vc::DevMem tk_T1, tk_T2[2];
   std::vector<int64_t> tk_o1, tk_o2;  // element offsets of each pair's regions
-  struct TkTables {                 // device tables of the three batched rebuild GEMMs
-    const void* R = nullptr;
-    vc::DevMem tab[3];
-    int n[3] = {0, 0, 0}, nblk[3] = {0, 0, 0};
+  struct TkTables {                 // device tables of the two batched strip GEMMs (T1, T2)
+    bool built = false;
+    vc::DevMem tab[2];
+    int n[2] = {0, 0}, nblk[2] = {0, 0};
   } tk_tab[2];                      // [0] FP32, [1] FP64
+  vc::DevMem tk_dev[2];             // per stored pair {U1, T2, r1} of the fused x pass ([0] FP32, [1] FP64)
   double tk_ms = 0.0;
   int tk_count = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> tk_pending;
@@ -295,8 +307,9 @@ void pair_axes(int q, int* a, int* b, int* want);
 vc_status tucker_begin(vc_problem* p, double tol);
 vc_status tucker_compress_pair(vc_problem* p, const double* X, hipStream_t st);
 vc_status tucker_end(vc_problem* p);
+// T1 = S x3 U3 and T2 = T1 x2 U2 of every stored pair (the x pass applies U1)
 template <typename T>
-vc_status tucker_rebuild(vc_problem* p, T* R, int64_t pair_stride, hipStream_t st, const int* skip = nullptr);
+vc_status tucker_rebuild(vc_problem* p, hipStream_t st, const int* skip = nullptr);
 vc_status apply_op(vc_problem* p, int transpose, vc_precision prec, const double* x, double* y, int nrhs,
                    hipStream_t st, const int* skip = nullptr, const int* act = nullptr);
 // the same over a packed set (pack.cpp)

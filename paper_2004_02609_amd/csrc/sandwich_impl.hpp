@@ -122,17 +122,25 @@ __device__ __forceinline__ double flip(double v, uint32_t s) {
   return __longlong_as_double((long long)u);
 }
 
-// v[q] *= w^(q ts), w = exp(-+2 pi i / L) from the LDS table; tsb = ts * sizeof(C2).
+// one complex twiddle at byte offset off: from the LDS copy of the table, or (TWG) from
+// the table in global memory (the Tucker-fused pass, whose LDS holds the tile's spectra)
+template <typename T, bool TWG>
+__device__ __forceinline__ C2<T> tw_ld(const char* __restrict__ twb, uint32_t off) {
+  if constexpr (TWG) return ldo<C2<T>>(reinterpret_cast<const C2<T>*>(twb), off);
+  else return lds_ld<T>(twb, off);
+}
+
+// v[q] *= w^(q ts), w = exp(-+2 pi i / L) from the table; tsb = ts * sizeof(C2).
 // All R-1 table reads are issued before the first multiply, so they are in flight
-// together instead of one LDS round trip per factor.
-template <typename T, int R>
+// together instead of one round trip per factor.
+template <typename T, int R, bool TWG = false>
 __device__ __forceinline__ void tw_mul(C2<T>* v, const char* __restrict__ twb, uint32_t tsb, T sg) {
   C2<T> w[R];
   uint32_t o = 0;
 #pragma unroll
   for (int q = 1; q < R; ++q) {
     o += tsb;
-    w[q] = lds_ld<T>(twb, o);
+    w[q] = tw_ld<T, TWG>(twb, o);
   }
 #pragma unroll
   for (int q = 1; q < R; ++q) {
@@ -183,7 +191,7 @@ __device__ __forceinline__ void sw_first(C2<T>* __restrict__ pre, bool next, Buf
 
 // a middle Stockham stage in place in LDS (reads, barrier, writes, barrier); rbase is
 // the thread's row-i byte offset (i * ncolpE + c * E)
-template <typename T, int R>
+template <typename T, int R, bool TWG = false>
 __device__ __forceinline__ void sw_mid(char* __restrict__ lds, const char* __restrict__ twb, int L, int p, float invp,
                                        int i, uint32_t rbase, uint32_t cE, uint32_t ncolpE, T sg) {
   asm volatile("" : "+v"(i), "+v"(rbase));   // keep this stage's address arithmetic here (no hoisting)
@@ -200,7 +208,7 @@ __device__ __forceinline__ void sw_mid(char* __restrict__ lds, const char* __res
       o += rstride;
     }
     const int ip = fdiv(i, invp), k = i - ip * p;
-    tw_mul<T, R>(v, twb, (uint32_t)(k * (LR / p)) * (uint32_t)sizeof(C2<T>), sg);
+    tw_mul<T, R, TWG>(v, twb, (uint32_t)(k * (LR / p)) * (uint32_t)sizeof(C2<T>), sg);
     Dft<T, R>::run(v, sg);
     wb = (uint32_t)(ip * p * R + k) * ncolpE + cE;
   }
@@ -217,7 +225,7 @@ __device__ __forceinline__ void sw_mid(char* __restrict__ lds, const char* __res
 }
 
 // inverse last stage (radix R = f0, p = L/R): LDS -> butterfly -> HBM rows i + q L/R
-template <typename T, int R>
+template <typename T, int R, bool TWG = false>
 __device__ __forceinline__ void sw_last_inv(const char* __restrict__ lds, const char* __restrict__ twb, int L, int i,
                                             uint32_t rbase, uint32_t ncolpE, Buf dst, uint32_t gbase,
                                             uint32_t gstride, uint32_t vmask, bool act) {
@@ -231,7 +239,7 @@ __device__ __forceinline__ void sw_last_inv(const char* __restrict__ lds, const 
     v[q] = lds_ld<T>(lds, o);
     o += rstride;
   }
-  tw_mul<T, R>(v, twb, (uint32_t)i * (uint32_t)sizeof(C2<T>), T(1));
+  tw_mul<T, R, TWG>(v, twb, (uint32_t)i * (uint32_t)sizeof(C2<T>), T(1));
   Dft<T, R>::run(v, T(1));
   o = gbase;
 #pragma unroll
@@ -272,261 +280,419 @@ __device__ __forceinline__ int sw_pair(int o, int b) {
   return b < 3 ? (al == o ? al : 2 + al + o) : 6 + 3 * al + o;
 }
 
-// one (column tile, right-hand side) of the pass; PID > 0 takes the plan from
-// kSandFixed[PID] as compile-time constants (the launcher checks that it is a.radpack's)
-template <typename T, int NIN, int NOUT, int RS, int PID = 0>
+// The fused form's tile spectra (eq. 13, the x-mode product): for every stored pair q
+// and tile column cc, X[q][kx'][cc] = sum_r U1_q[kx'][r] T2_q[ky'][kz][r] into LDS
+// (xt: [npairs][Hx][ncol]).  Column cc of tile `tile` sits in row j of the fold-pair
+// order, whose folded ky' is (j + 1) / 2.  U1 rows and T2 columns are r1p long (r1
+// rounded up to 4, zero past r1), read as whole 16-byte vectors.  The caller
+// synchronizes before reading xt.
+//
+// FP32 on the matrix cores: V_MFMA_F32_4X4X1_16B (16 blocks of 4 x 4 x 1 per wave).
+// One wave takes one unit (pair, group of 64 kx' rows, group of 4 columns): lane l
+// feeds row 64g + l of U1 as A and column 4cg + (l & 3) of T2 as B, so block b = l / 4
+// forms rows 64g + 4b .. 64g + 4b + 3 of those four columns, accumulating over r (one
+// r per instruction).  Lane 4b + j then holds D_b[i][j] in accumulator element i.  The
+// next pass's operands (16 values of r per pass) are loaded while the current one runs.
+template <typename T>
+__device__ __forceinline__ void tk_tile_spectra(T* __restrict__ xt, const SandArgs& a, int tile, int ncol) {
+  const int ncols = a.My * a.H;
+  if constexpr (sizeof(T) == 4) {
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int ngr = (a.Hx + 63) >> 6, ncg = (ncol + 3) >> 2;
+    const int units = a.npairs * ngr * ncg;
+    // operands of unit u, r in [r0, r0 + 16): 4 vectors each (zero past r1p or outside)
+    auto load = [&](int u, int r0, f32x4* av, f32x4* bv, int* r1p_out) {
+      const int q = u / (ngr * ncg);
+      const int rem = u - q * ngr * ncg;
+      const int g = rem / ncg, cg = rem - g * ncg;
+      const TkPairDev tp = a.tk[q];
+      const int row = g * 64 + lane;
+      const bool aok = row < a.Hx;
+      const int colb = cg * 4 + (lane & 3);
+      const int colq = tile * ncol + colb;
+      const bool bok = colb < ncol && colq < ncols;
+      const int jq = bok ? colq / a.H : 0, kzq = bok ? colq - jq * a.H : 0;
+      const f32x4* __restrict__ u1 =
+          reinterpret_cast<const f32x4*>(static_cast<const float*>(tp.U1) + (int64_t)(aok ? row : 0) * tp.r1p);
+      const f32x4* __restrict__ t2 = reinterpret_cast<const f32x4*>(
+          static_cast<const float*>(tp.T2) + ((int64_t)((jq + 1) >> 1) * a.H + kzq) * tp.r1p);
+      const int nv = tp.r1p >> 2;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int v = (r0 >> 2) + k;
+        const bool in = v < nv;
+        const int vc = in ? v : nv - 1;   // clamped: every address stays inside the row
+        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+        av[k] = (in && aok) ? u1[vc] : z;
+        bv[k] = (in && bok) ? t2[vc] : z;
+      }
+      *r1p_out = tp.r1p;
+    };
+    // passes (unit, r0) of this wave: units wave, wave + nwave, ...; r0 = 0, 16, ... < r1p
+    f32x4 av[4], bv[4], acc = {0.f, 0.f, 0.f, 0.f};
+    int u = wave, r0 = 0, r1p = 4;
+    if (u < units) load(u, 0, av, bv, &r1p);
+    while (u < units) {
+      int un = u, rn = r0 + 16, r1pn = r1p;
+      if (rn >= r1p) { un = u + nwave; rn = 0; }
+      f32x4 an[4], bn[4];
+      if (un < units) load(un, rn, an, bn, &r1pn);
+      if (r0 == 0) acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_4x4x1f32(av[k][e], bv[k][e], acc, 0, 0, 0);
+      }
+      if (rn == 0) {   // this unit is complete
+        const int q = u / (ngr * ncg);
+        const int rem = u - q * ngr * ncg;
+        const int g = rem / ncg, cg = rem - g * ncg;
+        const int b = lane >> 2, col = cg * 4 + (lane & 3);
+        if (col < ncol) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int rw = g * 64 + 4 * b + i;
+            if (rw < a.Hx) xt[((int64_t)q * a.Hx + rw) * ncol + col] = acc[i];
+          }
+        }
+      }
+      u = un;
+      r0 = rn;
+      r1p = r1pn;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) { av[k] = an[k]; bv[k] = bn[k]; }
+    }
+  } else {
+    // FP64 (the refinement's residual products) on the vector units, 16-byte loads
+    typedef double f64x2 __attribute__((ext_vector_type(2)));
+    const int per = a.Hx * ncol;
+    for (int e = threadIdx.x; e < a.npairs * per; e += blockDim.x) {
+      const int qp = e / per;
+      const int rem = e - qp * per;
+      const int kxq = rem / ncol, cc = rem - kxq * ncol;
+      const int colq = tile * ncol + cc;
+      T acc = T(0);
+      if (colq < ncols) {
+        const int jq = colq / a.H, kzq = colq - jq * a.H;
+        const TkPairDev tp = a.tk[qp];
+        const f64x2* __restrict__ u = reinterpret_cast<const f64x2*>(static_cast<const T*>(tp.U1) + (int64_t)kxq * tp.r1p);
+        const f64x2* __restrict__ t2 = reinterpret_cast<const f64x2*>(
+            static_cast<const T*>(tp.T2) + ((int64_t)((jq + 1) >> 1) * a.H + kzq) * tp.r1p);
+        for (int v = 0; v < (tp.r1p >> 1); ++v) {
+          const f64x2 x = u[v], y = t2[v];
+          acc += x.x * y.x + x.y * y.y;
+        }
+      }
+      xt[e] = acc;
+    }
+  }
+}
+
+// one column tile of the pass for right-hand sides rhs0 .. rhs0 + nrhs_loop - 1; PID > 0
+// takes the plan from kSandFixed[PID] as compile-time constants (the launcher checks
+// that it is a.radpack's).
+// TK: the Tucker-fused form (eq. 13).  No stored spectra: the workgroup first builds its
+// tile's spectra X[pair][kx'][column] = sum_r U1[kx'][r] T2[r][ky'][kz] of every pair
+// into LDS (the x-mode product, from the factor U1 and the strip T2 = S x2 U2 x3 U3),
+// then runs every right-hand side against them; the twiddles and x phases are read from
+// their tables in global memory (the LDS holds the spectra instead).
+template <typename T, int NIN, int NOUT, int RS, int PID = 0, int TK = 0>
 __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout,
                                               const T* __restrict__ R, const SandArgs& a,
                                               const C2<T>* __restrict__ twg, const C2<T>* __restrict__ phx,
                                               const C2<T>* __restrict__ phy, const C2<T>* __restrict__ phz,
-                                              const uint8_t* __restrict__ pflag, int tile, int rhs) {
+                                              const uint8_t* __restrict__ pflag, int tile, int rhs0,
+                                              int nrhs_loop) {
   constexpr int RMAX = sandwich_rmax((int)sizeof(T)), RMID = sandwich_rmid((int)sizeof(T));
   constexpr uint32_t E = sizeof(C2<T>);
   extern __shared__ char smem_raw[];
   constexpr bool FX = PID > 0;
+  constexpr bool FU = TK != 0;
   constexpr SandFixedPlan PD = kSandFixed[PID];
   const int L = FX ? PD.L : a.Mx, tl = FX ? PD.L / RS : a.tl, S = FX ? PD.nst : a.nst;
   auto rad = [&](int s) -> int { return FX ? PD.r[s] : srad(a, s); };
-  const int ncol = a.ncol;
-  const uint32_t ncolpE = (uint32_t)ncol * E;   // unpadded rows: measured faster than a pitch of ncol + 1 or + 2
+  int ncol = a.ncol;
+  uint32_t ncolpE = (uint32_t)ncol * E;   // unpadded rows: measured faster than a pitch of ncol + 1 or + 2
   // FP32 keeps the x half-voxel phases in LDS beside the twiddles; FP64 (whose tiles are
   // twice as large, and whose registers are full) reads them from the cached table
-  constexpr bool PH_LDS = sizeof(T) == 4;
-  char* twb = smem_raw;                                    // L twiddles
+  constexpr bool PH_LDS = sizeof(T) == 4 && !FU;
+  // fused: [npairs][Hx][ncol] spectra of the tile (16-byte aligned), then the tile
+  const uint32_t pairXb = FU ? (uint32_t)(a.Hx * ncol) * (uint32_t)sizeof(T) : 0u;
+  const uint32_t xtb = FU ? ((uint32_t)a.npairs * pairXb + 15u) & ~15u : 0u;
+  const char* twb = FU ? reinterpret_cast<const char*>(twg) : smem_raw;   // L twiddles
   char* phb = smem_raw + (size_t)L * E;                    // L x phases (FP32)
-  char* lds = smem_raw + (size_t)(PH_LDS ? 2 : 1) * L * E; // [L][ncol] tile
+  char* lds = FU ? smem_raw + xtb : smem_raw + (size_t)(PH_LDS ? 2 : 1) * L * E; // [L][ncol] tile
   uint8_t* sflag = reinterpret_cast<uint8_t*>(lds + (size_t)L * ncolpE);   // plane flags of the 3 axes
   const int tid = threadIdx.x;
-  const int i = fdiv(tid, 1.0f / (float)ncol), c = tid - i * ncol;   // column fastest
-  const bool valid = i < tl;
   const int ncols = a.My * a.H;                 // flattened (ky, kz) columns
-  const int col = tile * ncol + c;
-  const bool colok = col < ncols;
-  const int colc = colok ? col : ncols - 1;
-  const int ky = fdiv(colc, 1.0f / (float)a.H), kz = colc - ky * a.H;
-  const int yflip = ky > a.My / 2;
-  const int kyp = yflip ? a.My - ky : ky;
   const uint32_t rowb = (uint32_t)ncols * E;   // bytes between x rows
   const uint32_t slab = (uint32_t)a.n1x * rowb;  // bytes of one (component, rhs) slab
   const uint32_t pairb = (uint32_t)a.pair_stride * (uint32_t)sizeof(T);
   const int r0 = rad(0);
   const int LR0 = L / r0;
-  const bool act0 = i < LR0;                   // owns a butterfly of the first / last stage
-  for (int t = tid; t < L; t += blockDim.x) {
-    lds_st<T>(twb, (uint32_t)t * E, twg[t]);
-    if (PH_LDS) lds_st<T>(phb, (uint32_t)t * E, phx[t]);
-  }
-  for (int t = tid; t < 3 * a.n1x; t += blockDim.x) sflag[t] = pflag[t];
-  const C2<T> phy_t = phy[ky], phz_t = phz[kz];
-  // half-voxel phase along x of the thread's frequency kx = i + m tl
-  auto phase_x = [&](int m) -> C2<T> { return PH_LDS ? lds_ld<T>(phb, (uint32_t)(i + m * tl) * E) : phx[i + m * tl]; };
-  __syncthreads();
-
-  // per-thread geometry: LDS bases, HBM bases and strides of the first / last stage
-  const uint32_t cE = (uint32_t)c * E;
-  const uint32_t rbase = (uint32_t)i * ncolpE + cE;                // row i of the tile
-  const uint32_t gbase = (uint32_t)colc * E + (uint32_t)i * rowb;    // HBM row i of the column
-  const uint32_t gstride = (uint32_t)LR0 * rowb;                   // HBM rows i + q L/f0
-  // rows i + q L/f0 (q < f0) that are stored, per axis: bits 0..15 planes with conductor
-  // panels, bits 16..31 planes with dielectric panels
-  uint32_t rm0 = 0u, rm1 = 0u, rm2 = 0u;
-  if (act0 && colok) {
-    for (int qq = 0; qq < r0; ++qq) {
-      const int r = i + qq * LR0;
-      if (r >= a.n1x) break;
-      const uint32_t f0 = sflag[r], f1 = sflag[a.n1x + r], f2 = sflag[2 * a.n1x + r];
-      rm0 |= ((f0 & 1u) << qq) | (((f0 >> 1) & 1u) << (16 + qq));
-      rm1 |= ((f1 & 1u) << qq) | (((f1 >> 1) & 1u) << (16 + qq));
-      rm2 |= ((f2 & 1u) << qq) | (((f2 >> 1) & 1u) << (16 + qq));
+  if (!FU) {
+    for (int t = tid; t < L; t += blockDim.x) {
+      lds_st<T>(smem_raw, (uint32_t)t * E, twg[t]);
+      if (PH_LDS) lds_st<T>(phb, (uint32_t)t * E, phx[t]);
     }
   }
-  auto vm = [&](int ax, int msk) -> uint32_t {
-    const uint32_t m = ax == 0 ? rm0 : (ax == 1 ? rm1 : rm2);
-    return ((msk & 1) ? (m & 0xffffu) : 0u) | ((msk & 2) ? (m >> 16) : 0u);
-  };
+  for (int t = tid; t < 3 * a.n1x; t += blockDim.x) sflag[t] = pflag[t];
+  if (FU) tk_tile_spectra<T>(reinterpret_cast<T*>(smem_raw), a, tile, ncol);
+  __syncthreads();
 
-  C2<T> q[NIN][RS];
-  C2<T> pre[RMAX];   // staged first-stage inputs of the component about to be transformed
-  if (S > 1) {
+  // right-hand sides of this workgroup (one, except in the fused form)
+  const int nloop = FU ? nrhs_loop : 1;
+#pragma unroll 1
+  for (int kr = 0; kr < nloop; ++kr) {
+    const int rhs = rhs0 + kr;
+    int tidv = tid;
+    if (FU) {
+      if (a.act && !a.act[rhs]) continue;   // uniform over the workgroup
+      __syncthreads();                      // the previous right-hand side is done with the tile
+      // the thread's geometry below is derived again for each right-hand side rather
+      // than held in registers across the loop (the transforms need those registers)
+      asm volatile("" : "+v"(tidv));
+    }
+    // the tile width too, so the per-stage strides derived from it are not all computed
+    // once before the loop and held in scalar registers across it
+    if (FU) asm volatile("" : "+s"(ncol), "+s"(ncolpE));
+    const int i = fdiv(tidv, 1.0f / (float)ncol), c = tidv - i * ncol;   // column fastest
+    const bool valid = i < tl;
+    const int col = tile * ncol + c;
+    const bool colok = col < ncols;
+    const int colc = colok ? col : ncols - 1;
+    // rows in fold-pair order 0, 1, My-1, 2, My-2, ...: rows ky and My - ky read the same
+    // stored octant row (each stored spectrum is even or odd under ky -> My - ky), so
+    // their tiles run next to each other on one XCD and that row comes from HBM once
+    const int jrow = fdiv(colc, 1.0f / (float)a.H), kz = colc - jrow * a.H;
+    const int jpair = (jrow + 1) >> 1;
+    const int ky = ((jrow & 1) || jrow == 0) ? jpair : a.My - jpair;
+    const int mcol = ky * a.H + kz;   // the column's position in the work array
+    const int yflip = ky > a.My / 2;
+    const int kyp = yflip ? a.My - ky : ky;
+    const bool act0 = i < LR0;                   // owns a butterfly of the first / last stage
+    const C2<T> phy_t = phy[ky], phz_t = phz[kz];
+    // half-voxel phase along x of the thread's frequency kx = i + m tl
+    auto phase_x = [&](int m) -> C2<T> { return PH_LDS ? lds_ld<T>(phb, (uint32_t)(i + m * tl) * E) : phx[i + m * tl]; };
+
+    // per-thread geometry: LDS bases, HBM bases and strides of the first / last stage
+    const uint32_t cE = (uint32_t)c * E;
+    const uint32_t rbase = (uint32_t)i * ncolpE + cE;                // row i of the tile
+    const uint32_t gbase = (uint32_t)mcol * E + (uint32_t)i * rowb;    // HBM row i of the column
+    const uint32_t gstride = (uint32_t)LR0 * rowb;                   // HBM rows i + q L/f0
+    // rows i + q L/f0 (q < f0) that are stored, per axis: bits 0..15 planes with conductor
+    // panels, bits 16..31 planes with dielectric panels
+    uint32_t rm0 = 0u, rm1 = 0u, rm2 = 0u;
+    if (act0 && colok) {
+      for (int qq = 0; qq < r0; ++qq) {
+        const int r = i + qq * LR0;
+        if (r >= a.n1x) break;
+        const uint32_t f0 = sflag[r], f1 = sflag[a.n1x + r], f2 = sflag[2 * a.n1x + r];
+        rm0 |= ((f0 & 1u) << qq) | (((f0 >> 1) & 1u) << (16 + qq));
+        rm1 |= ((f1 & 1u) << qq) | (((f1 >> 1) & 1u) << (16 + qq));
+        rm2 |= ((f2 & 1u) << qq) | (((f2 >> 1) & 1u) << (16 + qq));
+      }
+    }
+    auto vm = [&](int ax, int msk) -> uint32_t {
+      const uint32_t m = ax == 0 ? rm0 : (ax == 1 ? rm1 : rm2);
+      return ((msk & 1) ? (m & 0xffffu) : 0u) | ((msk & 2) ? (m >> 16) : 0u);
+    };
+
+    C2<T> q[NIN][RS];
+    C2<T> pre[RMAX];   // staged first-stage inputs of the component about to be transformed
+    if (S > 1) {
 #define VC_CALL(RR) sw_load<T, RR>(pre, make_buf(Fin + rhs * a.rhs_stride, slab), gbase, gstride, vm(0, NIN == 3 ? 3 : 1), act0);
-    VC_SW_SWITCH(r0, VC_CALL, RMAX)
+      VC_SW_SWITCH(r0, VC_CALL, RMAX)
 #undef VC_CALL
-  }
+    }
 #pragma unroll
-  for (int b = 0; b < NIN; ++b) {
-    const int fax = b % 3;
-    const int fmsk = NIN == 3 ? 3 : (b < 3 ? 1 : 2);
-    const Buf src = make_buf(Fin + b * a.comp_stride + rhs * a.rhs_stride, slab);
-    C2<T> v[RS];
-    if (S == 1) {
+    for (int b = 0; b < NIN; ++b) {
+      const int fax = b % 3;
+      const int fmsk = NIN == 3 ? 3 : (b < 3 ? 1 : 2);
+      const Buf src = make_buf(Fin + b * a.comp_stride + rhs * a.rhs_stride, slab);
+      C2<T> v[RS];
+      if (S == 1) {
+        if (valid) {
+          const uint32_t msk = vm(fax, fmsk);
+          uint32_t o = gbase;
+#pragma unroll
+          for (int m = 0; m < RS; ++m) {
+            v[m] = bld<T>(src, (msk & (1u << m)) ? o : kOob);
+            o += rowb;
+          }
+          Dft<T, RS>::run(v, T(-1));
+        }
+      } else {
+        if (b > 0) __syncthreads();   // readers of the previous component are done with the tile
+        const int bn = b + 1;
+        const bool next = bn < NIN;
+        const Buf nsrc = make_buf(Fin + bn * a.comp_stride + rhs * a.rhs_stride, slab);
+        const uint32_t nmask = vm(bn % 3, NIN == 3 ? 3 : (bn < 3 ? 1 : 2));
+        {
+          uint32_t wbase = (uint32_t)i * (uint32_t)r0 * ncolpE + cE;
+          asm volatile("" : "+v"(wbase));
+#define VC_CALL(RR) sw_first<T, RR>(pre, next, nsrc, gbase, gstride, nmask, act0, lds, wbase, ncolpE);
+          VC_SW_SWITCH(r0, VC_CALL, RMAX)
+#undef VC_CALL
+        }
+        __syncthreads();
+        int p = r0;
+#pragma unroll
+        for (int s = 1; s < (FX ? PD.nst : S) - 1; ++s) {
+          const int rs = rad(s);
+          const float invp = stage_inv(p);
+#define VC_CALL(RR) sw_mid<T, RR, FU>(lds, twb, L, p, invp, i, rbase, cE, ncolpE, T(-1));
+          VC_SW_SWITCH(rs, VC_CALL, RMID)
+#undef VC_CALL
+          p *= rs;
+        }
+        if (valid) {
+          // last forward stage (radix RS, p = tl): butterfly i reads rows i + q tl,
+          // twiddle exponent q i, outputs X[i + q tl]
+          const uint32_t st = (uint32_t)tl * ncolpE;
+          uint32_t o = rbase;
+#pragma unroll
+          for (int m = 0; m < RS; ++m) {
+            v[m] = lds_ld<T>(lds, o);
+            o += st;
+          }
+          tw_mul<T, RS, FU>(v, twb, (uint32_t)i * E, T(-1));
+          Dft<T, RS>::run(v, T(-1));
+        }
+      }
+      // half-voxel phase of the input component (shift to the common lattice); slot
+      // pos(m) holds X[i + m tl]
       if (valid) {
-        const uint32_t msk = vm(fax, fmsk);
-        uint32_t o = gbase;
+        const C2<T> phyz = csel(fax == 1, phy_t, phz_t);
+        C2<T> w[RS];
+#pragma unroll
+        for (int m = 0; m < RS; ++m)
+          w[m] = cmul(v[Dft<T, RS>::pos(m)], fax == 0 ? phase_x(m) : phyz);
+        // per-element selects keep q in registers (a switch of stores is merged into one
+        // dynamically indexed store, which moves q to scratch memory)
+#pragma unroll
+        for (int bb = 0; bb < NIN; ++bb)
+#pragma unroll
+          for (int m = 0; m < RS; ++m)
+            if (bb == b) q[bb][m] = w[m];
+      }
+    }
+
+    // spectra offsets and fold signs of the thread's frequencies kx = i + m tl
+    uint32_t roff[RS], xs[RS];
+    const uint32_t ys = yflip ? 0x80000000u : 0u;
+#pragma unroll
+    for (int m = 0; m < RS; ++m) {
+      const int kx = i + m * tl;
+      const bool xf = kx > a.Mx / 2;
+      const int kxp = xf ? a.Mx - kx : kx;
+      roff[m] = !valid ? 0u
+                : FU ? (uint32_t)(kxp * ncol + c) * (uint32_t)sizeof(T)
+                     : (uint32_t)((kxp * a.Hy + kyp) * a.H + kz) * (uint32_t)sizeof(T);
+      xs[m] = xf ? 0x80000000u : 0u;
+    }
+    // spectra of the block multiply, loaded one output component ahead
+    constexpr int NQ = NIN == 3 ? 3 : 6;
+    T rv[NQ][RS];
+    auto load_spectra = [&](int o) {
+#pragma unroll
+      for (int b = 0; b < NQ; ++b) {
+        const int qi = sw_pair<NIN>(o, b);
+        const unsigned odd = (unsigned)(a.oddmask >> (3 * qi)) & 7u;
+        if constexpr (FU) {
+          const char* xb = smem_raw + (uint32_t)qi * pairXb;
+#pragma unroll
+          for (int m = 0; m < RS; ++m) {
+            const uint32_t sg = ((odd & 1u) ? xs[m] : 0u) ^ ((odd & 2u) ? ys : 0u);
+            rv[b][m] = flip(*reinterpret_cast<const T*>(xb + roff[m]), sg);
+          }
+        } else {
+          const Buf base = make_buf(R + (int64_t)qi * a.pair_stride, pairb);
+#pragma unroll
+          for (int m = 0; m < RS; ++m) {
+            const uint32_t sg = ((odd & 1u) ? xs[m] : 0u) ^ ((odd & 2u) ? ys : 0u);
+            rv[b][m] = flip(bld1<T>(base, roff[m]), sg);
+          }
+        }
+      }
+    };
+    if (valid) load_spectra(0);
+#pragma unroll 1
+    for (int o = 0; o < NOUT; ++o) {
+      const int oax = NIN == 3 ? (o < 3 ? o : o - 3) : o;
+      C2<T> z[RS];
+      if (valid) {
+        const C2<T> phyz = csel(oax == 1, phy_t, phz_t);
 #pragma unroll
         for (int m = 0; m < RS; ++m) {
-          v[m] = bld<T>(src, (msk & (1u << m)) ? o : kOob);
-          o += rowb;
+          C2<T> acc = {T(0), T(0)};
+          if (NIN == 3) {
+            // o < 3: C_alpha = sum_b P(alpha,b) Q'_b ; o >= 3: D_alpha = i sum_b E(alpha,b) Q'_b
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              acc.x += rv[b][m] * q[b][m].x;
+              acc.y += rv[b][m] * q[b][m].y;
+            }
+            if (o >= 3) acc = C2<T>{-acc.y, acc.x};
+          } else {
+            // transposed product: out_b = sum_al P(al,b) X'C_al - i sum_al E(al,b) X'D_al
+            C2<T> accE = {T(0), T(0)};
+#pragma unroll
+            for (int al = 0; al < 3; ++al) {
+              acc.x += rv[al][m] * q[al][m].x;
+              acc.y += rv[al][m] * q[al][m].y;
+              accE.x += rv[3 + al][m] * q[(NIN > 3 ? 3 : 0) + al][m].x;
+              accE.y += rv[3 + al][m] * q[(NIN > 3 ? 3 : 0) + al][m].y;
+            }
+            acc.x += accE.y;   // -i * accE
+            acc.y -= accE.x;
+          }
+          // output phase: conj of the half-voxel shift of the output component
+          z[m] = cmul(acc, cconj(oax == 0 ? phase_x(m) : phyz));
         }
-        Dft<T, RS>::run(v, T(-1));
+        if (o + 1 < NOUT) load_spectra(o + 1);
       }
-    } else {
-      if (b > 0) __syncthreads();   // readers of the previous component are done with the tile
-      const int bn = b + 1;
-      const bool next = bn < NIN;
-      const Buf nsrc = make_buf(Fin + bn * a.comp_stride + rhs * a.rhs_stride, slab);
-      const uint32_t nmask = vm(bn % 3, NIN == 3 ? 3 : (bn < 3 ? 1 : 2));
-      {
-        uint32_t wbase = (uint32_t)i * (uint32_t)r0 * ncolpE + cE;
-        asm volatile("" : "+v"(wbase));
-#define VC_CALL(RR) sw_first<T, RR>(pre, next, nsrc, gbase, gstride, nmask, act0, lds, wbase, ncolpE);
+      const int msk = NIN == 3 ? (o < 3 ? 1 : 2) : 3;
+      const Buf dst = make_buf(Fout + o * a.comp_stride + rhs * a.rhs_stride, slab);
+      const uint32_t omask = vm(oax, msk);
+      if (S == 1) {
+        if (valid) {
+          Dft<T, RS>::run(z, T(1));
+          uint32_t og = gbase;
+#pragma unroll
+          for (int m = 0; m < RS; ++m) {
+            bst<T>(dst, (omask & (1u << m)) ? og : kOob, z[Dft<T, RS>::pos(m)]);
+            og += rowb;
+          }
+        }
+      } else {
+        __syncthreads();   // the previous readers of the tile are done
+        if (valid) {
+          // first inverse stage (radix RS, p = 1) on the held values X[i + q tl]
+          Dft<T, RS>::run(z, T(1));
+          uint32_t ow = (uint32_t)i * (uint32_t)RS * ncolpE + cE;
+#pragma unroll
+          for (int m = 0; m < RS; ++m) {
+            lds_st<T>(lds, ow, z[Dft<T, RS>::pos(m)]);
+            ow += ncolpE;
+          }
+        }
+        __syncthreads();
+        int p = RS;
+#pragma unroll
+        for (int s = (FX ? PD.nst : S) - 2; s >= 1; --s) {
+          const int rs = rad(s);
+          const float invp = stage_inv(p);
+#define VC_CALL(RR) sw_mid<T, RR, FU>(lds, twb, L, p, invp, i, rbase, cE, ncolpE, T(1));
+          VC_SW_SWITCH(rs, VC_CALL, RMID)
+#undef VC_CALL
+          p *= rs;
+        }
+#define VC_CALL(RR) sw_last_inv<T, RR, FU>(lds, twb, L, i, rbase, ncolpE, dst, gbase, gstride, omask, act0);
         VC_SW_SWITCH(r0, VC_CALL, RMAX)
 #undef VC_CALL
       }
-      __syncthreads();
-      int p = r0;
-#pragma unroll
-      for (int s = 1; s < (FX ? PD.nst : S) - 1; ++s) {
-        const int rs = rad(s);
-        const float invp = stage_inv(p);
-#define VC_CALL(RR) sw_mid<T, RR>(lds, twb, L, p, invp, i, rbase, cE, ncolpE, T(-1));
-        VC_SW_SWITCH(rs, VC_CALL, RMID)
-#undef VC_CALL
-        p *= rs;
-      }
-      if (valid) {
-        // last forward stage (radix RS, p = tl): butterfly i reads rows i + q tl,
-        // twiddle exponent q i, outputs X[i + q tl]
-        const uint32_t st = (uint32_t)tl * ncolpE;
-        uint32_t o = rbase;
-#pragma unroll
-        for (int m = 0; m < RS; ++m) {
-          v[m] = lds_ld<T>(lds, o);
-          o += st;
-        }
-        tw_mul<T, RS>(v, twb, (uint32_t)i * E, T(-1));
-        Dft<T, RS>::run(v, T(-1));
-      }
-    }
-    // half-voxel phase of the input component (shift to the common lattice); slot
-    // pos(m) holds X[i + m tl]
-    if (valid) {
-      const C2<T> phyz = csel(fax == 1, phy_t, phz_t);
-      C2<T> w[RS];
-#pragma unroll
-      for (int m = 0; m < RS; ++m)
-        w[m] = cmul(v[Dft<T, RS>::pos(m)], fax == 0 ? phase_x(m) : phyz);
-      // per-element selects keep q in registers (a switch of stores is merged into one
-      // dynamically indexed store, which moves q to scratch memory)
-#pragma unroll
-      for (int bb = 0; bb < NIN; ++bb)
-#pragma unroll
-        for (int m = 0; m < RS; ++m)
-          if (bb == b) q[bb][m] = w[m];
-    }
-  }
-
-  // spectra offsets and fold signs of the thread's frequencies kx = i + m tl
-  uint32_t roff[RS], xs[RS];
-  const uint32_t ys = yflip ? 0x80000000u : 0u;
-#pragma unroll
-  for (int m = 0; m < RS; ++m) {
-    const int kx = i + m * tl;
-    const bool xf = kx > a.Mx / 2;
-    const int kxp = xf ? a.Mx - kx : kx;
-    roff[m] = valid ? (uint32_t)((kxp * a.Hy + kyp) * a.H + kz) * (uint32_t)sizeof(T) : 0u;
-    xs[m] = xf ? 0x80000000u : 0u;
-  }
-  // spectra of the block multiply, loaded one output component ahead
-  constexpr int NQ = NIN == 3 ? 3 : 6;
-  T rv[NQ][RS];
-  auto load_spectra = [&](int o) {
-#pragma unroll
-    for (int b = 0; b < NQ; ++b) {
-      const int qi = sw_pair<NIN>(o, b);
-      const unsigned odd = (unsigned)(a.oddmask >> (3 * qi)) & 7u;
-      const Buf base = make_buf(R + (int64_t)qi * a.pair_stride, pairb);
-#pragma unroll
-      for (int m = 0; m < RS; ++m) {
-        const uint32_t sg = ((odd & 1u) ? xs[m] : 0u) ^ ((odd & 2u) ? ys : 0u);
-        rv[b][m] = flip(bld1<T>(base, roff[m]), sg);
-      }
-    }
-  };
-  if (valid) load_spectra(0);
-#pragma unroll 1
-  for (int o = 0; o < NOUT; ++o) {
-    const int oax = NIN == 3 ? (o < 3 ? o : o - 3) : o;
-    C2<T> z[RS];
-    if (valid) {
-      const C2<T> phyz = csel(oax == 1, phy_t, phz_t);
-#pragma unroll
-      for (int m = 0; m < RS; ++m) {
-        C2<T> acc = {T(0), T(0)};
-        if (NIN == 3) {
-          // o < 3: C_alpha = sum_b P(alpha,b) Q'_b ; o >= 3: D_alpha = i sum_b E(alpha,b) Q'_b
-#pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            acc.x += rv[b][m] * q[b][m].x;
-            acc.y += rv[b][m] * q[b][m].y;
-          }
-          if (o >= 3) acc = C2<T>{-acc.y, acc.x};
-        } else {
-          // transposed product: out_b = sum_al P(al,b) X'C_al - i sum_al E(al,b) X'D_al
-          C2<T> accE = {T(0), T(0)};
-#pragma unroll
-          for (int al = 0; al < 3; ++al) {
-            acc.x += rv[al][m] * q[al][m].x;
-            acc.y += rv[al][m] * q[al][m].y;
-            accE.x += rv[3 + al][m] * q[(NIN > 3 ? 3 : 0) + al][m].x;
-            accE.y += rv[3 + al][m] * q[(NIN > 3 ? 3 : 0) + al][m].y;
-          }
-          acc.x += accE.y;   // -i * accE
-          acc.y -= accE.x;
-        }
-        // output phase: conj of the half-voxel shift of the output component
-        z[m] = cmul(acc, cconj(oax == 0 ? phase_x(m) : phyz));
-      }
-      if (o + 1 < NOUT) load_spectra(o + 1);
-    }
-    const int msk = NIN == 3 ? (o < 3 ? 1 : 2) : 3;
-    const Buf dst = make_buf(Fout + o * a.comp_stride + rhs * a.rhs_stride, slab);
-    const uint32_t omask = vm(oax, msk);
-    if (S == 1) {
-      if (valid) {
-        Dft<T, RS>::run(z, T(1));
-        uint32_t og = gbase;
-#pragma unroll
-        for (int m = 0; m < RS; ++m) {
-          bst<T>(dst, (omask & (1u << m)) ? og : kOob, z[Dft<T, RS>::pos(m)]);
-          og += rowb;
-        }
-      }
-    } else {
-      __syncthreads();   // the previous readers of the tile are done
-      if (valid) {
-        // first inverse stage (radix RS, p = 1) on the held values X[i + q tl]
-        Dft<T, RS>::run(z, T(1));
-        uint32_t ow = (uint32_t)i * (uint32_t)RS * ncolpE + cE;
-#pragma unroll
-        for (int m = 0; m < RS; ++m) {
-          lds_st<T>(lds, ow, z[Dft<T, RS>::pos(m)]);
-          ow += ncolpE;
-        }
-      }
-      __syncthreads();
-      int p = RS;
-#pragma unroll
-      for (int s = (FX ? PD.nst : S) - 2; s >= 1; --s) {
-        const int rs = rad(s);
-        const float invp = stage_inv(p);
-#define VC_CALL(RR) sw_mid<T, RR>(lds, twb, L, p, invp, i, rbase, cE, ncolpE, T(1));
-        VC_SW_SWITCH(rs, VC_CALL, RMID)
-#undef VC_CALL
-        p *= rs;
-      }
-#define VC_CALL(RR) sw_last_inv<T, RR>(lds, twb, L, i, rbase, ncolpE, dst, gbase, gstride, omask, act0);
-      VC_SW_SWITCH(r0, VC_CALL, RMAX)
-#undef VC_CALL
     }
   }
 }
@@ -552,7 +718,27 @@ k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __
   const int work = xcd_remap(blockIdx.y * ntiles + blockIdx.x, ntiles * gridDim.y);
   const int tile = work / a.nrhs, rhs = work - tile * a.nrhs;
   if (a.act && !a.act[rhs]) return;
-  sandwich_body<T, NIN, NOUT, RS, PID>(Fin, Fout, R, a, twg, phx, phy, phz, pflag, tile, rhs);
+  sandwich_body<T, NIN, NOUT, RS, PID>(Fin, Fout, R, a, twg, phx, phy, phz, pflag, tile, rhs, 1);
+}
+
+// The Tucker-fused form: one workgroup per tile for all right-hand sides (the tile's
+// spectra are built once into LDS and shared by them: the factor U1 is read once per
+// tile, not once per right-hand side); tiles XCD-contiguous in the fold-pair column
+// order.
+template <typename T, int NIN, int NOUT, int RS, int PID = 0>
+__global__ void __launch_bounds__(sand_max_threads_fixed(PID, (int)sizeof(T), NIN),
+                                  sand_max_threads_fixed(PID, (int)sizeof(T), NIN) == 1024
+                                      ? 4
+                                      : ((sizeof(T) == 8 || NIN == 6) ? 2 : 3))
+k_xsandwich_tk(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __restrict__ R, SandArgs a,
+               const C2<T>* __restrict__ twg, const C2<T>* __restrict__ phx, const C2<T>* __restrict__ phy,
+               const C2<T>* __restrict__ phz, const uint8_t* __restrict__ pflag) {
+  if (a.skip && *a.skip) return;
+  if (PID > 0 && (a.Mx != kSandFixed[PID].L || a.nst != kSandFixed[PID].nst || a.radpack != sand_fixed_pack(PID) ||
+                  a.tl * RS != a.Mx))
+    return;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  sandwich_body<T, NIN, NOUT, RS, PID, 1>(Fin, Fout, R, a, twg, phx, phy, phz, pflag, tile, 0, a.nrhs);
 }
 
 // several scenes in one launch: linear workgroup -> (scene, tile, rhs), XCD-contiguous
@@ -569,7 +755,7 @@ k_xsandwich_multi(const SandScene* __restrict__ tab, int nscene, const int* __re
   sandwich_body<T, NIN, NOUT, RS>(static_cast<const C2<T>*>(sc.Fin), static_cast<C2<T>*>(sc.Fout),
                                   static_cast<const T*>(sc.R), sc.a, static_cast<const C2<T>*>(sc.tw),
                                   static_cast<const C2<T>*>(sc.phx), static_cast<const C2<T>*>(sc.phy),
-                                  static_cast<const C2<T>*>(sc.phz), sc.pflag, tile, rhs);
+                                  static_cast<const C2<T>*>(sc.phz), sc.pflag, tile, rhs, 1);
 }
 
 // Compiled last-stage radices per kernel variant (register budget: the thread holds
@@ -581,12 +767,19 @@ template <typename T, int NIN> struct SandRS {
 // launch with last-stage radix RR: the fixed-plan kernel of the first table entry that
 // equals the runtime plan, else the generic one
 // e0 / e1: optional events stamped by the launch itself (hipExtLaunchKernelGGL)
-template <typename T, int NIN, int NOUT, int RR, int ID>
+template <typename T, int NIN, int NOUT, int RR, int ID, int TK>
 hipError_t launch_sandwich_rs(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
                               const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
                               size_t lds, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-  dim3 grid((a.My * a.H + a.ncol - 1) / a.ncol, a.nrhs);
+  const int ntiles = (a.My * a.H + a.ncol - 1) / a.ncol;
+  dim3 grid = TK ? dim3(ntiles) : dim3(ntiles, a.nrhs);
   auto go = [&](auto kernel) -> hipError_t {
+    // above the default 64 KiB of dynamic LDS (the fused form's spectra), declare it
+    if (lds > kLdsBudget) {
+      const hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (ea != hipSuccess) return ea;
+    }
     if (e0 || e1)
       hipExtLaunchKernelGGL(kernel, grid, dim3(nthr), (std::uint32_t)lds, st, e0, e1, 0u, (const C2<T>*)Fin,
                             (C2<T>*)Fout, (const T*)R, a, (const C2<T>*)tw, (const C2<T>*)phx, (const C2<T>*)phy,
@@ -599,25 +792,28 @@ hipError_t launch_sandwich_rs(const void* Fin, void* Fout, const void* R, const 
   if constexpr (ID < kSandNumFixed) {
     if constexpr (sand_fixed_last(ID) == RR) {
       if (a.Mx == kSandFixed[ID].L && a.nst == kSandFixed[ID].nst && a.radpack == sand_fixed_pack(ID) &&
-          a.tl * RR == a.Mx)
-        return go(k_xsandwich<T, NIN, NOUT, RR, ID>);
+          a.tl * RR == a.Mx) {
+        if constexpr (TK) return go(k_xsandwich_tk<T, NIN, NOUT, RR, ID>);
+        else return go(k_xsandwich<T, NIN, NOUT, RR, ID>);
+      }
     }
-    return launch_sandwich_rs<T, NIN, NOUT, RR, ID + 1>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, st, e0,
-                                                        e1);
+    return launch_sandwich_rs<T, NIN, NOUT, RR, ID + 1, TK>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, st,
+                                                            e0, e1);
   } else {
-    return go(k_xsandwich<T, NIN, NOUT, RR, 0>);
+    if constexpr (TK) return go(k_xsandwich_tk<T, NIN, NOUT, RR, 0>);
+    else return go(k_xsandwich<T, NIN, NOUT, RR, 0>);
   }
 }
 
-template <typename T, int NIN, int NOUT>
+template <typename T, int NIN, int NOUT, int TK>
 hipError_t launch_sandwich_v(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
                              const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
                              size_t lds, int rs, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
 #define VC_RS(RR)                                                                                                 \
   case RR:                                                                                                        \
     if constexpr (RR <= SandRS<T, NIN>::max) {                                                                    \
-      return launch_sandwich_rs<T, NIN, NOUT, RR, 1>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, st, e0, \
-                                                     e1);                                                         \
+      return launch_sandwich_rs<T, NIN, NOUT, RR, 1, TK>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, st, \
+                                                         e0, e1);                                                 \
     }                                                                                                             \
     break;
   switch (rs) {

@@ -197,9 +197,15 @@ vc_status build_spectra(vc_problem* P, int want64, int want32, double tucker_tol
   P->have64 = want64;
   P->have32 = want32;
   P->spectra_bytes = 0;
-  if (want64) { VC_HIP(P->t64.R.alloc((size_t)15 * per_pair * sizeof(double))); P->spectra_bytes += (double)npairs * per_pair * 8; }
-  if (want32) { VC_HIP(P->t32.R.alloc((size_t)15 * per_pair * sizeof(float))); P->spectra_bytes += (double)npairs * per_pair * 4; }
   const bool tucker = tucker_tol > 0.0;
+  // the Tucker form keeps no spectra: each x-pass workgroup builds its tile's from the
+  // factors (eq. 13); uncompressed, every stored pair is kept
+  P->t64.R.reset();
+  P->t32.R.reset();
+  if (!tucker) {
+    if (want64) { VC_HIP(P->t64.R.alloc((size_t)15 * per_pair * sizeof(double))); P->spectra_bytes += (double)npairs * per_pair * 8; }
+    if (want32) { VC_HIP(P->t32.R.alloc((size_t)15 * per_pair * sizeof(float))); P->spectra_bytes += (double)npairs * per_pair * 4; }
+  }
   DevMem circ, spec, resid, one;   // one: a pair's FP64 spectrum when compressing
   if (tucker) {
     VC_HIP(one.alloc((size_t)per_pair * sizeof(double)));
@@ -279,10 +285,13 @@ vc_status build_spectra(vc_problem* P, int want64, int want32, double tucker_tol
   }
   if (tucker) {
     if ((s = tucker_end(P)) != VC_OK) return s;
-    // the spectra buffers now only hold rebuilds: start them as NaN so a product that
-    // skipped the rebuild could not pass for a correct one
-    if (want64) VC_HIP(hipMemsetAsync(P->t64.R.p, 0xff, (size_t)15 * per_pair * sizeof(double), st));
-    if (want32) VC_HIP(hipMemsetAsync(P->t32.R.p, 0xff, (size_t)15 * per_pair * sizeof(float), st));
+    // resident: every device buffer of the Tucker form (cores and factors in FP64 and
+    // FP32, the padded U1 copies) and the rebuild's T1 / T2 strips
+    for (const TuckerPair& tp : P->tk) {
+      P->spectra_bytes += (double)(tp.S64.bytes + tp.S32.bytes + tp.U1p64.bytes + tp.U1p32.bytes);
+      for (int m = 0; m < 3; ++m) P->spectra_bytes += (double)(tp.U64[m].bytes + tp.U32[m].bytes);
+    }
+    P->spectra_bytes += (double)(P->tk_T1.bytes + P->tk_T2[0].bytes + P->tk_T2[1].bytes);
   }
   double r = 0.0;
   VC_HIP(hipMemcpyAsync(&r, resid.p, sizeof(double), hipMemcpyDeviceToHost, st));

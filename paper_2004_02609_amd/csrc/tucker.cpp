@@ -153,17 +153,34 @@ vc_status tucker_compress_pair(vc_problem* P, const double* X, hipStream_t st) {
   VC_HIP(tp.S32.alloc((size_t)ns * sizeof(float)));
   VC_HIP(launch_to_f32(tp.S64.as<double>(), tp.S32.as<float>(), ns, st));
   const int D[3] = {P->Hx, P->Hy, P->H};
-  for (int m = 0; m < 3; ++m) {
+  for (int m = 1; m < 3; ++m) {
     const int64_t nu = (int64_t)D[m] * tp.r[m];
     VC_HIP(tp.U32[m].alloc((size_t)nu * sizeof(float)));
     VC_HIP(launch_to_f32(tp.U64[m].as<double>(), tp.U32[m].as<float>(), nu, st));
   }
+  // U1 with rows padded to a multiple of 4 (FP64 and FP32) for the fused x pass
+  const int r1 = tp.r[0];
+  tp.r1p = (r1 + 3) & ~3;
+  std::vector<double> u((size_t)D[0] * r1), u64((size_t)D[0] * tp.r1p, 0.0);
+  VC_HIP(hipMemcpyAsync(u.data(), tp.U64[0].p, u.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  VC_HIP(hipStreamSynchronize(st));
+  std::vector<float> u32(u64.size(), 0.0f);
+  for (int x = 0; x < D[0]; ++x)
+    for (int a = 0; a < r1; ++a) {
+      u64[(size_t)x * tp.r1p + a] = u[(size_t)x * r1 + a];
+      u32[(size_t)x * tp.r1p + a] = (float)u[(size_t)x * r1 + a];
+    }
+  VC_HIP(tp.U1p64.alloc(u64.size() * sizeof(double)));
+  VC_HIP(tp.U1p32.alloc(u32.size() * sizeof(float)));
+  VC_HIP(hipMemcpy(tp.U1p64.p, u64.data(), u64.size() * sizeof(double), hipMemcpyHostToDevice));
+  VC_HIP(hipMemcpy(tp.U1p32.p, u32.data(), u32.size() * sizeof(float), hipMemcpyHostToDevice));
   return VC_OK;
 }
 
-// scratch of the rebuild: each pair its own T1 (r1 r2 x D3) and T2 (r1 x D2 x D3)
-// regions, so the three GEMM steps of every pair can run as three launches; sized in
-// FP64 elements, reused by FP32
+// scratch of the rebuild: each pair its own T1 (r1 r2 x D3) and T2 (D2 x D3 x r1p)
+// regions, so the two GEMM steps of every pair can run as two launches; T1 sized in
+// FP64 elements and reused by FP32, T2 one per precision.  The fused x pass reads T2 and U1 through a per-pair device
+// table (one per precision).
 vc_status tucker_end(vc_problem* P) {
   int64_t t1 = 0, t2 = 0;
   P->tk_o1.clear();
@@ -172,28 +189,44 @@ vc_status tucker_end(vc_problem* P) {
     P->tk_o1.push_back(t1);
     P->tk_o2.push_back(t2);
     t1 += (int64_t)tp.r[0] * tp.r[1] * P->H;
-    t2 += (int64_t)tp.r[0] * P->Hy * P->H;
+    t2 += (int64_t)tp.r1p * P->Hy * P->H;
   }
   VC_HIP(P->tk_T1.alloc((size_t)std::max<int64_t>(t1, 1) * sizeof(double)));
-  VC_HIP(P->tk_T2.alloc((size_t)std::max<int64_t>(t2, 1) * sizeof(double)));
-  for (auto& tt : P->tk_tab) tt.R = nullptr;   // rebuilt on next use
+  VC_HIP(P->tk_T2[0].alloc((size_t)std::max<int64_t>(t2, 1) * sizeof(float)));
+  VC_HIP(P->tk_T2[1].alloc((size_t)std::max<int64_t>(t2, 1) * sizeof(double)));
+  // T2's padding entries (r1 <= r < r1p) are never written: they stay zero
+  for (auto& t : P->tk_T2) VC_HIP(hipMemset(t.p, 0, t.bytes));
+  for (auto& tt : P->tk_tab) tt.built = false;   // rebuilt on next use
+  for (int prec = 0; prec < 2; ++prec) {
+    const bool f64 = prec == 1;
+    std::vector<TkPairDev> v(P->tk.size());
+    for (size_t q = 0; q < P->tk.size(); ++q) {
+      const TuckerPair& tp = P->tk[q];
+      v[q].U1 = f64 ? tp.U1p64.p : tp.U1p32.p;
+      v[q].T2 = f64 ? (const void*)(P->tk_T2[1].as<double>() + P->tk_o2[q])
+                    : (const void*)(P->tk_T2[0].as<float>() + P->tk_o2[q]);
+      v[q].r1 = tp.r[0];
+      v[q].r1p = tp.r1p;
+    }
+    VC_HIP(P->tk_dev[prec].alloc(std::max<size_t>(v.size(), 1) * sizeof(TkPairDev)));
+    if (!v.empty()) VC_HIP(hipMemcpy(P->tk_dev[prec].p, v.data(), v.size() * sizeof(TkPairDev), hipMemcpyHostToDevice));
+  }
   return VC_OK;
 }
 
-// the three GEMM tables of one precision (built on first use for a given spectra buffer)
+// the two GEMM tables of one precision (built on first use)
 template <typename T>
-static vc_status rebuild_tables(vc_problem* P, T* R, int64_t pair_stride) {
+static vc_status rebuild_tables(vc_problem* P) {
   vc_problem::TkTables& tt = P->tk_tab[sizeof(T) == 8 ? 1 : 0];
-  if (tt.R == R) return VC_OK;
-  const int D1 = P->Hx, D2 = P->Hy, D3 = P->H;
+  if (tt.built) return VC_OK;
+  const int D2 = P->Hy, D3 = P->H;
   T* T1 = P->tk_T1.as<T>();
-  T* T2 = P->tk_T2.as<T>();
-  std::vector<GemmDesc> g1, g2, g3;
+  T* T2 = P->tk_T2[sizeof(T) == 8 ? 1 : 0].as<T>();
+  std::vector<GemmDesc> g1, g2;
   for (size_t q = 0; q < P->tk.size(); ++q) {
     const TuckerPair& tp = P->tk[q];
     const int r1 = tp.r[0], r2 = tp.r[1], r3 = tp.r[2];
     const void* S = sizeof(T) == 8 ? tp.S64.p : tp.S32.p;
-    const void* U1 = sizeof(T) == 8 ? tp.U64[0].p : tp.U32[0].p;
     const void* U2 = sizeof(T) == 8 ? tp.U64[1].p : tp.U32[1].p;
     const void* U3 = sizeof(T) == 8 ? tp.U64[2].p : tp.U32[2].p;
     T* t1 = T1 + P->tk_o1[q];
@@ -204,52 +237,46 @@ static vc_status rebuild_tables(vc_problem* P, T* R, int64_t pair_stride) {
     d.M = r1 * r2; d.N = D3; d.K = r3; d.batch = 1;
     d.sam = r3; d.sak = 1; d.sbk = 1; d.sbn = r3; d.scm = D3; d.scn = 1;
     g1.push_back(d);
-    // T2[a] (D2 x D3) = U2 (D2 x r2) T1[a] (r2 x D3)
+    // T2[.][.][a] (D2 x D3, element stride r1p) = U2 (D2 x r2) T1[a] (r2 x D3)
     d = GemmDesc{};
     d.A = U2; d.B = t1; d.C = t2;
     d.M = D2; d.N = D3; d.K = r2; d.batch = r1;
-    d.sam = r2; d.sak = 1; d.sbk = D3; d.sbn = 1; d.scm = D3; d.scn = 1;
-    d.bsa = 0; d.bsb = (int64_t)r2 * D3; d.bsc = (int64_t)D2 * D3;
+    d.sam = r2; d.sak = 1; d.sbk = D3; d.sbn = 1; d.scm = (int64_t)D3 * tp.r1p; d.scn = tp.r1p;
+    d.bsa = 0; d.bsb = (int64_t)r2 * D3; d.bsc = 1;
     g2.push_back(d);
-    // X (D1 x D2 D3) = U1 (D1 x r1) T2 (r1 x D2 D3)
-    d = GemmDesc{};
-    d.A = U1; d.B = t2; d.C = R + (int64_t)q * pair_stride;
-    d.M = D1; d.N = D2 * D3; d.K = r1; d.batch = 1;
-    d.sam = r1; d.sak = 1; d.sbk = (int64_t)D2 * D3; d.sbn = 1; d.scm = (int64_t)D2 * D3; d.scn = 1;
-    g3.push_back(d);
   }
-  std::vector<GemmDesc>* all[3] = {&g1, &g2, &g3};
-  for (int i = 0; i < 3; ++i) {
+  std::vector<GemmDesc>* all[2] = {&g1, &g2};
+  for (int i = 0; i < 2; ++i) {
     std::vector<GemmDesc>& v = *all[i];
     const int nb = gemm_table_layout(v.data(), (int)v.size());
-    if (nb < 0) { tt.R = nullptr; return VC_ERR_ARG; }
+    if (nb < 0) return VC_ERR_ARG;
     VC_HIP(tt.tab[i].alloc(std::max<size_t>(v.size(), 1) * sizeof(GemmDesc)));
     if (!v.empty()) VC_HIP(hipMemcpy(tt.tab[i].p, v.data(), v.size() * sizeof(GemmDesc), hipMemcpyHostToDevice));
     tt.n[i] = (int)v.size();
     tt.nblk[i] = nb;
   }
-  tt.R = R;
+  tt.built = true;
   return VC_OK;
 }
 
+// T1 and T2 of every stored pair (the x-mode product X = U1 T2 runs inside the x pass)
 template <typename T>
-vc_status tucker_rebuild(vc_problem* P, T* R, int64_t pair_stride, hipStream_t st, const int* skip) {
-  const int D1 = P->Hx, D2 = P->Hy, D3 = P->H;
-  // three launches for all pairs when every rank fits the register strip
-  if (rebuild_tables<T>(P, R, pair_stride) == VC_OK) {
+vc_status tucker_rebuild(vc_problem* P, hipStream_t st, const int* skip) {
+  const int D2 = P->Hy, D3 = P->H;
+  // two launches for all pairs when every rank fits the register strip
+  if (rebuild_tables<T>(P) == VC_OK) {
     const vc_problem::TkTables& tt = P->tk_tab[sizeof(T) == 8 ? 1 : 0];
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 2; ++i)
       VC_HIP(launch_mfma_gemm_multi<T>(tt.tab[i].as<GemmDesc>(), tt.n[i], tt.nblk[i], skip, st));
     return VC_OK;
   }
   // ranks above the strip: one pair after another with the general kernel
   T* T1 = P->tk_T1.as<T>();
-  T* T2 = P->tk_T2.as<T>();
+  T* T2 = P->tk_T2[sizeof(T) == 8 ? 1 : 0].as<T>();
   for (size_t q = 0; q < P->tk.size(); ++q) {
     const TuckerPair& tp = P->tk[q];
     const int r1 = tp.r[0], r2 = tp.r[1], r3 = tp.r[2];
     const T* S = sizeof(T) == 8 ? (const T*)tp.S64.p : (const T*)tp.S32.p;
-    const T* U1 = sizeof(T) == 8 ? (const T*)tp.U64[0].p : (const T*)tp.U32[0].p;
     const T* U2 = sizeof(T) == 8 ? (const T*)tp.U64[1].p : (const T*)tp.U32[1].p;
     const T* U3 = sizeof(T) == 8 ? (const T*)tp.U64[2].p : (const T*)tp.U32[2].p;
     T* t1 = T1 + P->tk_o1[q];
@@ -261,20 +288,15 @@ vc_status tucker_rebuild(vc_problem* P, T* R, int64_t pair_stride, hipStream_t s
     VC_HIP(launch_mfma_gemm<T>(S, U3, t1, g, st));
     g = GemmArgs{};
     g.M = D2; g.N = D3; g.K = r2; g.batch = r1;
-    g.sam = r2; g.sak = 1; g.sbk = D3; g.sbn = 1; g.scm = D3; g.scn = 1;
-    g.bsa = 0; g.bsb = (int64_t)r2 * D3; g.bsc = (int64_t)D2 * D3;
+    g.sam = r2; g.sak = 1; g.sbk = D3; g.sbn = 1; g.scm = (int64_t)D3 * tp.r1p; g.scn = tp.r1p;
+    g.bsa = 0; g.bsb = (int64_t)r2 * D3; g.bsc = 1;
     g.skip = skip;
     VC_HIP(launch_mfma_gemm<T>(U2, t1, t2, g, st));
-    g = GemmArgs{};
-    g.M = D1; g.N = D2 * D3; g.K = r1; g.batch = 1;
-    g.sam = r1; g.sak = 1; g.sbk = (int64_t)D2 * D3; g.sbn = 1; g.scm = (int64_t)D2 * D3; g.scn = 1;
-    g.skip = skip;
-    VC_HIP(launch_mfma_gemm<T>(U1, t2, R + (int64_t)q * pair_stride, g, st));
   }
   return VC_OK;
 }
 
-template vc_status tucker_rebuild<float>(vc_problem*, float*, int64_t, hipStream_t, const int*);
-template vc_status tucker_rebuild<double>(vc_problem*, double*, int64_t, hipStream_t, const int*);
+template vc_status tucker_rebuild<float>(vc_problem*, hipStream_t, const int*);
+template vc_status tucker_rebuild<double>(vc_problem*, hipStream_t, const int*);
 
 }  // namespace vc

@@ -142,7 +142,7 @@ vc_status vc_tuning_load(vc_problem* p, const char* path, int32_t* n_loaded) {
     const int key = (e.nrhs << 2) | (e.transpose << 1) | (e.elem == 8 ? 1 : 0);
     if (!shape_of(p, arch, key).same_key(e)) continue;
     // accept it only as one of this problem's own candidates
-    const std::vector<SandCfg> cand = sandwich_candidates(p->M[0], e.elem, e.nin, p->n1[0], kLdsBudget);
+    const std::vector<SandCfg> cand = sandwich_candidates(p->M[0], e.elem, e.nin, p->n1[0], kLdsBudget, (int)p->tk.size(), p->Hx);
     for (const SandCfg& g : cand) {
       bool same = e.nst == g.nst && e.cols == g.ncol;
       for (int s = 0; s < 6 && same; ++s)

@@ -112,6 +112,7 @@ _sig = {
     "vc_toeplitz_octant": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.c_int, C.c_void_p, _P]),
     "vc_setup_toeplitz_source": (C.c_int, [_P, _P]),
     "vc_setup_time": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "vc_memory_info": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "vc_status_string": (C.c_char_p, [C.c_int]),
     "vc_last_error": (C.c_char_p, []),
 }
@@ -307,6 +308,12 @@ def vc_setup_time(h):
     tot, tz = C.c_double(0), C.c_double(0)
     _check(_lib.vc_setup_time(h, C.byref(tot), C.byref(tz)), "vc_setup_time")
     return {"total_s": tot.value, "toeplitz_s": tz.value}
+
+
+def vc_memory_info(h):
+    sb, wb = C.c_double(0), C.c_double(0)
+    _check(_lib.vc_memory_info(h, C.byref(sb), C.byref(wb)), "vc_memory_info")
+    return {"spectra_bytes": sb.value, "work_bytes": wb.value}
 
 
 def _octant_tensor(n, device):
@@ -605,6 +612,13 @@ class Problem:
         the panel integrals when None."""
         vc_setup_toeplitz_source(self._h, None if cache is None else cache._h)
         self._toeplitz_cache = cache   # kept alive for the setups that use it
+
+    def spectra_bytes(self):
+        """Device bytes held by the kernel spectra (stored, or the Tucker form)."""
+        return vc_memory_info(self._h)["spectra_bytes"]
+
+    def memory_info(self):
+        return vc_memory_info(self._h)
 
     def setup_time(self):
         return vc_setup_time(self._h)

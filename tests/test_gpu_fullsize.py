@@ -85,6 +85,9 @@ def test_fullsize_product_sampled_rows(dev, name, ncond, ndiel):
         assert eq < 5e-5, (name, eq)
         assert eq64 < 5e-5, (name, eq64)
         assert info["compression_ratio"] > 1.0
+        # the spectra are never stored whole: the Tucker form holds a few percent of them
+        print(name, "spectra bytes uncompressed", P.spectra_bytes(), "Tucker", Q.spectra_bytes(), flush=True)
+        assert Q.spectra_bytes() < 0.1 * P.spectra_bytes()
 
 
 def test_meander_tucker_mixed_capacitance(dev):
