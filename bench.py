@@ -259,27 +259,39 @@ def write_traffic(args):
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
 
 
-def tucker_summary(P, prec, ms_step, ms_step_plain, rb_ms):
-    """Tucker form of the step's spectra (eq. 13): ranks, compression ratio, the rebuild's
-    time from the profiled run, the paper's computational overhead CO = rebuild time /
-    one uncompressed product, and the rebuild's MFMA rate (dense GEMM flops of the three
-    mode products) and output bandwidth."""
+def tucker_summary(P, prec, ms_step, ms_step_plain, rb_ms, x_ms, nrhs):
+    """Tucker form of the step's spectra (eq. 13), never stored whole: ranks, compression
+    ratio, the bytes resident, the strips' rebuild (T1 = S x3 U3, T2 = T1 x2 U2, two
+    batched MFMA GEMMs) with its MFMA rate, the x-mode product X = U1 T2 that the x pass
+    forms per tile on the matrix cores (its flops and their rate over the x pass), and
+    the paper's computational overhead CO, here the Tucker step's extra time over the
+    uncompressed product divided by that product."""
     info = P.tucker_info()
-    D = (P.fft_size()[0] // 2 + 1, P.fft_size()[1] // 2 + 1, P.fft_size()[2] // 2 + 1)
+    Mx, My, Mz = P.fft_size()
+    D = (Mx // 2 + 1, My // 2 + 1, Mz // 2 + 1)
     flops = 0.0
     out_bytes = 0.0
+    xmode = 0.0
     elem = 4 if prec == "fp32" else 8
     for r1, r2, r3 in info["ranks"]:
-        flops += 2.0 * (r1 * r2 * r3 * D[2] + r1 * r2 * D[1] * D[2] + r1 * D[0] * D[1] * D[2])
-        out_bytes += elem * (D[0] * D[1] * D[2] + 2 * r1 * D[1] * D[2])   # X written, T2 written and read
+        r1p = (r1 + 3) // 4 * 4
+        flops += 2.0 * (r1 * r2 * r3 * D[2] + r1 * r2 * D[1] * D[2])
+        out_bytes += elem * (r1 * r2 * D[2] + r1p * D[1] * D[2])        # T1 and T2 written
+        # per (ky, kz) column of the x pass (all My * H of them, once per tile)
+        xmode += 2.0 * D[0] * r1 * My * D[2]
     tf = flops / (rb_ms / 1e3) / 1e12 if rb_ms > 0 else None
+    xtf = xmode / (x_ms / 1e3) / 1e12 if x_ms > 0 else None
     return {"ranks": info["ranks"], "compression_ratio": info["compression_ratio"],
-            "step_ms_with_rebuild": ms_step, "rebuild_ms": rb_ms,
-            "computational_overhead": rb_ms / ms_step_plain if ms_step_plain else None,
-            "rebuild_mfma": {"flops": flops, "achieved_tflops": tf, "peak_tflops": MFMA_PEAK_TFLOPS[prec],
-                             "frac": tf / MFMA_PEAK_TFLOPS[prec] if tf else None},
-            "rebuild_hbm": {"bytes": out_bytes, "achieved_gbs": out_bytes / (rb_ms / 1e3) / 1e9 if rb_ms > 0 else None,
-                            "peak_gbs": HBM_PEAK_GBS}}
+            "spectra_bytes_resident": P.spectra_bytes(),
+            "step_ms": ms_step, "uncompressed_step_ms": ms_step_plain,
+            "computational_overhead": (ms_step - ms_step_plain) / ms_step_plain if ms_step_plain else None,
+            "strip_rebuild": {"ms": rb_ms, "flops": flops, "achieved_tflops": tf,
+                              "mfma_frac": tf / MFMA_PEAK_TFLOPS[prec] if tf else None,
+                              "bytes_written": out_bytes,
+                              "achieved_gbs": out_bytes / (rb_ms / 1e3) / 1e9 if rb_ms > 0 else None},
+            "xmode_in_x_pass": {"flops_per_launch": xmode, "x_pass_ms": x_ms,
+                                "tflops_over_x_pass": xtf,
+                                "mfma_frac_over_x_pass": xtf / MFMA_PEAK_TFLOPS[prec] if xtf else None}}
 
 
 def toeplitz_run(args, scene, x):
@@ -560,7 +572,7 @@ def main():
     if tucker_tol > 0:
         tk1 = P.tucker_info()
         n_rb = tk1["rebuilds"] - tk0["rebuilds"]
-        tucker = {"tol": tucker_tol, "rebuild_ms": (tk1["rebuild_ms"] - tk0["rebuild_ms"]) / max(1, n_rb),
+        tucker = {"tol": tucker_tol, "strip_rebuild_ms": (tk1["rebuild_ms"] - tk0["rebuild_ms"]) / max(1, n_rb),
                   "rebuilds_timed": n_rb}
 
     # the uncompressed problem: FP32 rate without the rebuild, the FP64-plain rate and
@@ -600,7 +612,7 @@ def main():
 
     if tucker is not None:
         ms_plain = B / rates[args.prec] * 1e3 if args.prec in rates else None
-        tucker.update(tucker_summary(P, args.prec, ms / args.steps, ms_plain, tucker["rebuild_ms"]))
+        tucker.update(tucker_summary(P, args.prec, ms / args.steps, ms_plain, tucker["strip_rebuild_ms"], x_ms, B))
 
     solve = None
     if not args.no_solve:

@@ -99,6 +99,11 @@ typedef struct {
                           column tile) and keeps the fastest; 0: a fixed heuristic.
                           Tuning synchronizes the stream once and is skipped while the
                           stream is being captured into a graph.                    */
+  const char *tune_cache; /* optional tuning cache file (NULL: none): its matching
+                          entries are loaded at setup (as vc_tuning_load; a missing
+                          file loads nothing), and every x-pass choice the autotuner
+                          makes afterwards is merged into it (as vc_tuning_save).
+                          The string is copied.                                      */
 } vc_setup_opts;
 
 /* Solve options.  GMRES(restart) with the block-diagonal-diagonal preconditioner
@@ -130,6 +135,9 @@ typedef struct {
   double t_setup_s, t_solve_s;
   double spectra_bytes;       /* device bytes held by the kernel spectra            */
   int32_t tucker_rank_max;
+  double bytes_model;         /* algorithmic HBM bytes of one product of the solve's
+                                 right-hand sides (every pass, the model of
+                                 vc_pass_times), in the inner product's precision   */
 } vc_stats;
 
 /* Copy the geometry, extract the panels and validate (host only, no GPU work).
@@ -232,7 +240,11 @@ vc_status vc_pack_apply(vc_pack *pk, vc_precision prec, const double *x_dev, dou
  * restart) captures the cycle graphs; later calls replay them. */
 vc_status vc_pack_capacitance(vc_pack *pk, const vc_solve_opts *opts, double *const *C_out, vc_stats *stats);
 
-/* One-shot form: vc_pack_create + vc_pack_capacitance + vc_pack_destroy. */
+/* One-shot form: vc_pack_create + vc_pack_capacitance + vc_pack_destroy, under two
+ * names (vc_batch_capacitance is the name of the batched call in the problem
+ * statement's interface; both behave identically). */
+vc_status vc_batch_capacitance(vc_problem *const *problems, int32_t n, const vc_solve_opts *opts,
+                               double *const *C_out, vc_stats *stats);
 vc_status vc_capacitance_batch(vc_problem *const *problems, int32_t n, const vc_solve_opts *opts,
                                double *const *C_out, vc_stats *stats);
 

@@ -64,6 +64,10 @@ def capacitance_eps(scene, block_of_voxel, eps_blocks, device=0, setup=None, pro
     return _CapacitanceEps.apply(eps_blocks, problem, scene["eps_r"], blk, dict(solve))
 
 
+# the autograd Function itself (eps per block -> C, backward by the adjoint solves)
+CapacitanceFn = _CapacitanceEps
+
+
 def problem_for(scene, device=0, **setup):
     """A set-up Problem of `scene` for repeated capacitance_eps calls (one setup, then
     only permittivity updates)."""

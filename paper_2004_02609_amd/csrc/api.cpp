@@ -143,6 +143,12 @@ vc_status vc_setup(vc_problem* p, const vc_setup_opts* opts, void* stream) {
   VC_HIP(hipStreamSynchronize(st));
   p->setup_done = true;
   p->t_setup = now_s() - t0;
+  p->tune_cache = o.tune_cache ? o.tune_cache : "";
+  if (!p->tune_cache.empty()) {
+    int32_t nl = 0;
+    s = vc_tuning_load(p, p->tune_cache.c_str(), &nl);
+    if (s != VC_OK) return s;
+  }
   return VC_OK;
 }
 
@@ -267,6 +273,7 @@ vc_status vc::capacitance_run(vc_problem* p, const vc_solve_opts& o, double* C, 
     int rmax = 0;
     for (const auto& t : p->tk) rmax = std::max(rmax, std::max(t.r[0], std::max(t.r[1], t.r[2])));
     stats->tucker_rank_max = rmax;
+    stats->bytes_model = product_bytes_model(p, o.prec == VC_FP64 ? 8 : 4, m);
   }
   return s;
 }
@@ -334,6 +341,11 @@ vc_status vc_capacitance_batch(vc_problem* const* problems, int32_t n, const vc_
   s = vc_pack_capacitance(pk, opts, C_out, stats);
   vc_pack_destroy(pk);
   return s;
+}
+
+vc_status vc_batch_capacitance(vc_problem* const* problems, int32_t n, const vc_solve_opts* opts, double* const* C_out,
+                               vc_stats* stats) {
+  return vc_capacitance_batch(problems, n, opts, C_out, stats);
 }
 
 vc_status vc_capacitance(vc_problem* p, const vc_solve_opts* opts, double* C, double* rho_dev, vc_stats* stats) {

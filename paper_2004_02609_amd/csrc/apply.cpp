@@ -76,6 +76,12 @@ static void pass_byte_model(vc_problem* P, int transpose, int elem, int nrhs, do
   }
 }
 
+double product_bytes_model(vc_problem* P, int elem, int nrhs) {
+  double b[5];
+  pass_byte_model(P, 0, elem, nrhs, b);
+  return b[0] + b[1] + b[2] + b[3] + b[4];
+}
+
 // Sandwich launch configurations for one x length: for every register radix RS the
 // plan with the fewest stages, and every column tile (1..32 columns) within the kernel's
 // thread limit (512, or 1024 for the wide compiled plans) and the LDS budget that is a
@@ -411,6 +417,12 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
         ch.ms_default = dflt;
       }
       it = P->sand_choice.emplace(key, ch).first;
+      // a tuning cache file given at setup takes every timed choice
+      if (ch.tuned && !P->tune_cache.empty()) {
+        int32_t ns = 0;
+        const vc_status ts = vc_tuning_save(P, P->tune_cache.c_str(), &ns);
+        if (ts != VC_OK) return ts;
+      }
     }
     const vc_problem::SandChoice& ch = it->second;
     xa.nst = ch.nst; xa.radpack = ch.radpack; xa.tl = ch.tl; xa.ncol = ch.ncol;

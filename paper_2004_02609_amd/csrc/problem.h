@@ -265,6 +265,7 @@ struct vc_problem {
     int xg;     // consecutive tiles per XCD (YArgs::xg)
   };
   std::map<int, YChoice> y_choice;
+  std::string tune_cache;   // tuning cache file of vc_setup_opts (empty: none)
   // per-pass timing (measurement)
   int prof = 0;   // 0 off, 1 every pass, 2 the x pass only
   std::vector<hipEvent_t> ev_free;
@@ -310,6 +311,8 @@ vc_status tucker_end(vc_problem* p);
 // T1 = S x3 U3 and T2 = T1 x2 U2 of every stored pair (the x pass applies U1)
 template <typename T>
 vc_status tucker_rebuild(vc_problem* p, hipStream_t st, const int* skip = nullptr);
+// algorithmic bytes of one forward product of nrhs columns, every pass (elem: 4 or 8)
+double product_bytes_model(vc_problem* p, int elem, int nrhs);
 vc_status apply_op(vc_problem* p, int transpose, vc_precision prec, const double* x, double* y, int nrhs,
                    hipStream_t st, const int* skip = nullptr, const int* act = nullptr);
 // the same over a packed set (pack.cpp)

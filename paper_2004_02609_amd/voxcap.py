@@ -48,7 +48,8 @@ PANEL_DTYPE = np.dtype({"names": ["i", "j", "k", "dir", "kind", "pad", "cond", "
 
 class vc_setup_opts(C.Structure):
     _fields_ = [("fft_size", C.c_int32 * 3), ("nv", C.c_int32 * 3), ("tucker_tol", C.c_double),
-                ("precisions", C.c_int32), ("max_rhs", C.c_int32), ("autotune", C.c_int32)]
+                ("precisions", C.c_int32), ("max_rhs", C.c_int32), ("autotune", C.c_int32),
+                ("tune_cache", C.c_char_p)]
 
 
 class vc_solve_opts(C.Structure):
@@ -60,7 +61,7 @@ class vc_solve_opts(C.Structure):
 class vc_stats(C.Structure):
     _fields_ = [("iters", C.c_int32 * 64), ("final_rre", C.c_double * 64), ("ir_steps", C.c_int32),
                 ("mvp_count", C.c_int32), ("t_setup_s", C.c_double), ("t_solve_s", C.c_double),
-                ("spectra_bytes", C.c_double), ("tucker_rank_max", C.c_int32)]
+                ("spectra_bytes", C.c_double), ("tucker_rank_max", C.c_int32), ("bytes_model", C.c_double)]
 
 
 _P = C.c_void_p
@@ -86,6 +87,8 @@ _sig = {
     "vc_pass_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "vc_tuning_report": (C.c_int, [_P, C.c_char_p, C.c_int32]),
     "vc_capacitance_batch": (C.c_int, [C.POINTER(_P), C.c_int32, C.POINTER(vc_solve_opts), C.POINTER(C.c_void_p),
+                                       C.POINTER(vc_stats)]),
+    "vc_batch_capacitance": (C.c_int, [C.POINTER(_P), C.c_int32, C.POINTER(vc_solve_opts), C.POINTER(C.c_void_p),
                                        C.POINTER(vc_stats)]),
     "vc_pack_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.POINTER(_P)]),
     "vc_pack_destroy": (C.c_int, [_P]),
@@ -184,7 +187,8 @@ def vc_fft_size(h):
     return tuple(m)
 
 
-def vc_setup(h, fft_size=None, nv=None, tucker_tol=0.0, precisions=0, max_rhs=0, autotune=False, stream=None):
+def vc_setup(h, fft_size=None, nv=None, tucker_tol=0.0, precisions=0, max_rhs=0, autotune=False, stream=None,
+             tune_cache=None):
     o = vc_setup_opts()
     if fft_size is not None:
         o.fft_size[:] = [int(v) for v in fft_size]
@@ -194,6 +198,7 @@ def vc_setup(h, fft_size=None, nv=None, tucker_tol=0.0, precisions=0, max_rhs=0,
     o.precisions = int(precisions)
     o.max_rhs = int(max_rhs)
     o.autotune = int(bool(autotune))
+    o.tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
     _check(_lib.vc_setup(h, C.byref(o), _stream(stream)), "vc_setup")
 
 
@@ -520,7 +525,7 @@ def vc_capacitance_grad_eps(h, m, block_of_voxel, nblocks, **solve):
 def stats_dict(st, nrhs):
     return {"iters": list(st.iters[:nrhs]), "final_rre": list(st.final_rre[:nrhs]), "ir_steps": st.ir_steps,
             "mvp_count": st.mvp_count, "t_setup_s": st.t_setup_s, "t_solve_s": st.t_solve_s,
-            "spectra_bytes": st.spectra_bytes}
+            "spectra_bytes": st.spectra_bytes, "bytes_model": st.bytes_model}
 
 
 def capacitance_batch(problems, **solve):
@@ -528,6 +533,14 @@ def capacitance_batch(problems, **solve):
     ([C_k], [stats_k])."""
     Cs, sts, _ = vc_capacitance_batch([p._h for p in problems], [p.m for p in problems], **solve)
     return Cs, sts
+
+
+def capacitance(cond_id, eps_r, dv, precision="fp64", eps_background=1.0, device=0, setup=None, **solve):
+    """One-call form: (C, stats) of a voxel geometry (m x m farads, row-major), set up
+    with the keyword options `setup` and solved with `solve` (rtol, restart, ...);
+    precision "fp64", "mixed" or "fp32"."""
+    P = Problem(cond_id, eps_r, dv, eps_background, device).setup(**dict(setup or {}))
+    return P.capacitance(prec=precision, **solve)
 
 
 class Pack:
