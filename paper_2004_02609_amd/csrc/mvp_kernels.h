@@ -42,6 +42,11 @@ struct StridedArgs {
   int lgc;        // log2(ncol), set by the launcher
   const int* skip;   // optional device flag: when set, the launch does nothing
   const int* act;    // optional per right-hand side activity: workgroups of inactive ones return
+  // optional half-voxel phase along the transformed axis (L complex; null: none): the
+  // components of normal axis phax take ph[k] on the forward outputs and conj(ph[k]) on
+  // the inverse inputs
+  const void* ph;
+  int phax;
 };
 
 // y pass with register-edge stages (ypass_impl.hpp): blockIdx = (kz tile, x plane,
@@ -60,6 +65,8 @@ struct YArgs {
   int xg;           // 2 or 4: that many consecutive tiles of a row (which share cache
                     // lines) per XCD, issued together; -1: all tiles of a row; 0 or 1:
                     // the launch order
+  const void* ph;   // optional half-voxel phase along y, as StridedArgs::ph
+  int phax;
 };
 template <typename T>
 hipError_t launch_ypass(void* data, const YArgs& a, const void* tw, const uint8_t* lflag, const uint8_t* pflag,
@@ -174,7 +181,7 @@ template <typename T>
 hipError_t launch_zfwd(const double* x, int64_t N, int nrhs, int mode, const int32_t* items, int nitems,
                        const int32_t* line_ptr, const int32_t* pk, const int8_t* pkind, void* F, int64_t comp_stride,
                        int64_t rhs_stride, int n1x, int n1y, int My, int H, const AxisPlan& pl, const void* tw, int ncol,
-                       int nthr, const int* skip, hipStream_t st, const int* act = nullptr);
+                       int nthr, const int* skip, hipStream_t st, const int* act = nullptr, const void* ph = nullptr);
 template <typename T>
 hipError_t launch_strided(void* data, const StridedArgs& a, const CompSet& cs, int nplanes, const AxisPlan& pl,
                           const void* tw, const uint8_t* lflag, const uint8_t* pflag, int nthr, hipStream_t st);
@@ -182,7 +189,7 @@ hipError_t launch_strided(void* data, const StridedArgs& a, const CompSet& cs, i
 // (no separate event packets around it)
 template <typename T>
 hipError_t launch_sandwich(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
-                           const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
+                           const void* phx, const uint8_t* pflag, int nthr,
                            hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // a sandwich launch configuration (plan, tile, threads)
 struct SandCfg {
@@ -193,7 +200,7 @@ struct SandCfg {
 // radix rs
 template <typename T, int NIN, int NOUT, int TK>
 hipError_t launch_sandwich_v(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
-                             const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
+                             const void* phx, const uint8_t* pflag, int nthr,
                              size_t lds, int rs, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
 // largest last-stage radix compiled for each sandwich variant (registers: NIN x RS held values)
 constexpr int sandwich_rs_max(int elem, int nin) { return elem == 4 ? (nin == 3 ? 6 : 7) : (nin == 3 ? 5 : 3); }
@@ -203,7 +210,7 @@ hipError_t launch_zinv(const void* O, double* y, const double* x, int64_t N, int
                        int nitems, const int32_t* line_ptr, const int32_t* pk, const int8_t* pkind,
                        const double* diag, const uint8_t* lflag, int64_t comp_stride, int64_t rhs_stride, int n1x,
                        int n1y, int My, int H, const AxisPlan& pl, const void* tw, int ncol, int nthr,
-                       const int* skip, hipStream_t st, const int* act = nullptr);
+                       const int* skip, hipStream_t st, const int* act = nullptr, const void* ph = nullptr);
 
 // ---- one launch per pass over several independent problems ("scenes") of different
 // sizes: a device table holds every scene's arguments and its first linear workgroup
@@ -219,6 +226,8 @@ struct ZScene {
   const uint8_t* lflag;
   void* F;            // spectral work array (written by the forward pass, read by the inverse)
   const void* tw;
+  const void* ph;     // half-voxel phase along z (null: none): z-normal components take ph[kz]
+                      // after the forward transform and conj(ph[kz]) before the inverse
   AxisPlan pl;
   int64_t comp_stride, rhs_stride;
   int nitems, nrhs, n1x, n1y, My, H, lgc;
@@ -243,8 +252,6 @@ struct SandScene {
   const void* R;
   const void* tw;
   const void* phx;
-  const void* phy;
-  const void* phz;
   const uint8_t* pflag;
   int c0, ntiles, blk0;
 };

@@ -70,6 +70,7 @@ __device__ __forceinline__ void zfwd_body(const ZScene& a, int mode, const doubl
   const int8_t* __restrict__ pkind = a.pkind;
   C2<T>* __restrict__ F = static_cast<C2<T>*>(a.F);
   const C2<T>* __restrict__ twg = static_cast<const C2<T>*>(a.tw);
+  const C2<T>* __restrict__ phz = static_cast<const C2<T>*>(a.ph);
   C2<T>* tw = reinterpret_cast<C2<T>*>(smem_raw);
   C2<T>* buf = tw + L;
   C2<T>* buf2 = buf + L * ncolp;
@@ -107,8 +108,14 @@ __device__ __forceinline__ void zfwd_body(const ZScene& a, int mode, const doubl
     const int xi = fdiv(rem, invN1y), yi = rem - xi * n1y;
     const C2<T> Z = res[k * ncolp + c];
     const C2<T> Zc = cconj(res[(k == 0 ? 0 : L - k) * ncolp + c]);
-    const C2<T> A = {T(0.5) * (Z.x + Zc.x), T(0.5) * (Z.y + Zc.y)};
-    const C2<T> B = {T(0.5) * (Z.y - Zc.y), T(-0.5) * (Z.x - Zc.x)};
+    C2<T> A = {T(0.5) * (Z.x + Zc.x), T(0.5) * (Z.y + Zc.y)};
+    C2<T> B = {T(0.5) * (Z.y - Zc.y), T(-0.5) * (Z.x - Zc.x)};
+    if (phz && axis == 2) {
+      // half-voxel shift of the z-normal component to the common lattice
+      const C2<T> w = phz[k];
+      A = cmul(A, w);
+      B = cmul(B, w);
+    }
     const int64_t off = ((int64_t)xi * My + yi) * H + k;
     if (mode == 0) {
       F[axis * comp_stride + ra * rhs_stride + off] = A;
@@ -168,6 +175,8 @@ __device__ __forceinline__ void strided_body(C2<T>* __restrict__ data, const Str
   const int col0 = bx * ncol;
   for (int t = tid; t < L; t += nthr) tw[t] = twg[t];
   const uint8_t* lf = lflag ? lflag + ((int64_t)axis * n1x + plane) * n1y : nullptr;
+  // half-voxel phase of this component along the transformed axis (null: none)
+  const C2<T>* __restrict__ ph = (a.ph && axis == a.phax) ? static_cast<const C2<T>*>(a.ph) : nullptr;
   for (int e = tid; e < (L << lgc); e += nthr) {
     const int r = e >> lgc, c = e & cmask;
     C2<T> v = {T(0), T(0)};
@@ -176,6 +185,7 @@ __device__ __forceinline__ void strided_body(C2<T>* __restrict__ data, const Str
       bool ok = true;
       if (lf && min_) ok = (lf[r] & min_) != 0;
       if (ok) v = base[(int64_t)r * row_stride + col];
+      if (ok && ph && inverse) v = cmul(v, cconj(ph[r]));
     }
     buf[r * ncolp + c] = v;
   }
@@ -186,7 +196,9 @@ __device__ __forceinline__ void strided_body(C2<T>* __restrict__ data, const Str
     const int col = col0 + c;
     if (col >= ncols) continue;
     if (lf && mout && !(lf[r] & mout)) continue;
-    base[(int64_t)r * row_stride + col] = res[r * ncolp + c];
+    C2<T> v = res[r * ncolp + c];
+    if (ph && !inverse) v = cmul(v, ph[r]);
+    base[(int64_t)r * row_stride + col] = v;
   }
 }
 
@@ -239,6 +251,7 @@ __device__ __forceinline__ void zinv_body(const ZScene& a, int mode, const doubl
   const uint8_t* __restrict__ lflag = a.lflag;
   const C2<T>* __restrict__ O = static_cast<const C2<T>*>(a.F);
   const C2<T>* __restrict__ twg = static_cast<const C2<T>*>(a.tw);
+  const C2<T>* __restrict__ phz = static_cast<const C2<T>*>(a.ph);
   C2<T>* tw = reinterpret_cast<C2<T>*>(smem_raw);
   C2<T>* buf = tw + L;
   C2<T>* buf2 = buf + L * ncolp;
@@ -267,6 +280,12 @@ __device__ __forceinline__ void zinv_body(const ZScene& a, int mode, const doubl
       } else {
         Cv = O[axis * comp_stride + ra * rhs_stride + off];
         if (rb < nrhs) Dv = O[axis * comp_stride + rb * rhs_stride + off];
+      }
+      if (phz && axis == 2) {
+        // back from the common lattice: the conjugate half-voxel shift
+        const C2<T> w = cconj(phz[k]);
+        Cv = cmul(Cv, w);
+        Dv = cmul(Dv, w);
       }
     }
     // Z = C + i D on the half spectrum, Hermitian completion for the other half
@@ -344,11 +363,11 @@ template <typename T>
 hipError_t launch_zfwd(const double* x, int64_t N, int nrhs, int mode, const int32_t* items, int nitems,
                        const int32_t* line_ptr, const int32_t* pk, const int8_t* pkind, void* F, int64_t comp_stride,
                        int64_t rhs_stride, int n1x, int n1y, int My, int H, const AxisPlan& pl, const void* tw, int ncol,
-                       int nthr, const int* skip, hipStream_t st, const int* act) {
+                       int nthr, const int* skip, hipStream_t st, const int* act, const void* ph) {
   if (nitems == 0) return hipSuccess;
   if (ncol < 1 || ncol > 32 || (ncol & (ncol - 1)) || nthr < 64) return hipErrorInvalidValue;   // tile of <= 32 lines
   ZScene a{};
-  a.items = items; a.line_ptr = line_ptr; a.pk = pk; a.pkind = pkind; a.F = F; a.tw = tw; a.pl = pl;
+  a.items = items; a.line_ptr = line_ptr; a.pk = pk; a.pkind = pkind; a.F = F; a.tw = tw; a.pl = pl; a.ph = ph;
   a.comp_stride = comp_stride; a.rhs_stride = rhs_stride;
   a.nitems = nitems; a.nrhs = nrhs; a.n1x = n1x; a.n1y = n1y; a.My = My; a.H = H; a.lgc = ilog2(ncol);
   dim3 grid((nitems + ncol - 1) / ncol, mode == 0 ? (nrhs + 1) / 2 : nrhs);
@@ -406,27 +425,27 @@ bool sandwich_args_ok(const SandArgs& a, int nthr) {
 
 template <typename T>
 hipError_t launch_sandwich(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
-                           const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
+                           const void* phx, const uint8_t* pflag, int nthr,
                            hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (!sandwich_args_ok<T>(a, nthr)) return hipErrorInvalidValue;
   const int rs = (int)((a.radpack >> (5 * (a.nst - 1))) & 31u);
   if (a.tk) {
     const size_t lds = sandwich_tk_lds_bytes(a.Mx, a.ncol, (int)sizeof(T), a.n1x, a.npairs, a.Hx);
     if (!a.adjoint && a.nin == 3 && a.nout == 6)
-      return launch_sandwich_v<T, 3, 6, 1>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
+      return launch_sandwich_v<T, 3, 6, 1>(Fin, Fout, R, a, tw, phx, pflag, nthr, lds, rs, st, e0, e1);
     if (!a.adjoint && a.nin == 3 && a.nout == 3)
-      return launch_sandwich_v<T, 3, 3, 1>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
+      return launch_sandwich_v<T, 3, 3, 1>(Fin, Fout, R, a, tw, phx, pflag, nthr, lds, rs, st, e0, e1);
     if (a.adjoint && a.nin == 6 && a.nout == 3)
-      return launch_sandwich_v<T, 6, 3, 1>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
+      return launch_sandwich_v<T, 6, 3, 1>(Fin, Fout, R, a, tw, phx, pflag, nthr, lds, rs, st, e0, e1);
     return hipErrorInvalidValue;
   }
   const size_t lds = sandwich_lds_bytes(a.Mx, a.ncol, (int)sizeof(T), a.n1x);
   if (!a.adjoint && a.nin == 3 && a.nout == 6)
-    return launch_sandwich_v<T, 3, 6, 0>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
+    return launch_sandwich_v<T, 3, 6, 0>(Fin, Fout, R, a, tw, phx, pflag, nthr, lds, rs, st, e0, e1);
   if (!a.adjoint && a.nin == 3 && a.nout == 3)
-    return launch_sandwich_v<T, 3, 3, 0>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
+    return launch_sandwich_v<T, 3, 3, 0>(Fin, Fout, R, a, tw, phx, pflag, nthr, lds, rs, st, e0, e1);
   if (a.adjoint && a.nin == 6 && a.nout == 3)
-    return launch_sandwich_v<T, 6, 3, 0>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, rs, st, e0, e1);
+    return launch_sandwich_v<T, 6, 3, 0>(Fin, Fout, R, a, tw, phx, pflag, nthr, lds, rs, st, e0, e1);
   return hipErrorInvalidValue;
 }
 
@@ -435,12 +454,12 @@ hipError_t launch_zinv(const void* O, double* y, const double* x, int64_t N, int
                        int nitems, const int32_t* line_ptr, const int32_t* pk, const int8_t* pkind,
                        const double* diag, const uint8_t* lflag, int64_t comp_stride, int64_t rhs_stride, int n1x,
                        int n1y, int My, int H, const AxisPlan& pl, const void* tw, int ncol, int nthr,
-                       const int* skip, hipStream_t st, const int* act) {
+                       const int* skip, hipStream_t st, const int* act, const void* ph) {
   if (nitems == 0) return hipSuccess;
   if (ncol < 1 || ncol > 32 || (ncol & (ncol - 1)) || nthr < 64) return hipErrorInvalidValue;   // tile of <= 32 lines
   ZScene a{};
   a.items = items; a.line_ptr = line_ptr; a.pk = pk; a.pkind = pkind; a.diag = diag; a.lflag = lflag;
-  a.F = const_cast<void*>(O); a.tw = tw; a.pl = pl;
+  a.F = const_cast<void*>(O); a.tw = tw; a.pl = pl; a.ph = ph;
   a.comp_stride = comp_stride; a.rhs_stride = rhs_stride;
   a.nitems = nitems; a.nrhs = nrhs; a.n1x = n1x; a.n1y = n1y; a.My = My; a.H = H; a.lgc = ilog2(ncol);
   dim3 grid((nitems + ncol - 1) / ncol, mode == 0 ? nrhs : (nrhs + 1) / 2);
@@ -482,16 +501,16 @@ hipError_t launch_strided_multi(const StridedScene* tab, int nscene, int nblocks
 #define VC_INST(T)                                                                                                \
   template hipError_t launch_zfwd<T>(const double*, int64_t, int, int, const int32_t*, int, const int32_t*,        \
                                      const int32_t*, const int8_t*, void*, int64_t, int64_t, int, int, int, int,   \
-                                     const AxisPlan&, const void*, int, int, const int*, hipStream_t, const int*); \
+                                     const AxisPlan&, const void*, int, int, const int*, hipStream_t, const int*,  \
+                                     const void*);                                                                \
   template hipError_t launch_strided<T>(void*, const StridedArgs&, const CompSet&, int, const AxisPlan&,          \
                                         const void*, const uint8_t*, const uint8_t*, int, hipStream_t);            \
   template hipError_t launch_sandwich<T>(const void*, void*, const void*, const SandArgs&, const void*, const void*, \
-                                         const void*, const void*, const uint8_t*, int, hipStream_t, hipEvent_t,      \
-                                         hipEvent_t);              \
+                                         const uint8_t*, int, hipStream_t, hipEvent_t, hipEvent_t);                 \
   template hipError_t launch_zinv<T>(const void*, double*, const double*, int64_t, int, int, const int32_t*, int, \
                                      const int32_t*, const int32_t*, const int8_t*, const double*, const uint8_t*, \
                                      int64_t, int64_t, int, int, int, int, const AxisPlan&, const void*, int, int, \
-                                     const int*, hipStream_t, const int*);                                         \
+                                     const int*, hipStream_t, const int*, const void*);                            \
   template hipError_t launch_zfwd_multi<T>(const ZScene*, int, int, const double*, int64_t, const int*,           \
                                            const int*, int, size_t, hipStream_t);                                 \
   template hipError_t launch_zinv_multi<T>(const ZScene*, int, int, const double*, double*, int64_t, const int*,  \

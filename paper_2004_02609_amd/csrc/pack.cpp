@@ -101,6 +101,7 @@ static vc_status build_tables(PackData& D, PackPrec& pp) {
     z.diag = P->d_diag.as<double>();
     z.lflag = P->d_lflag.as<uint8_t>();
     z.tw = tb.ax[2].tw.p;
+    z.ph = tb.ax[2].ph.p;   // the z-normal components' half-voxel shift
     z.pl = tb.ax[2].plan;
     z.comp_stride = P->comp_stride;
     z.rhs_stride = P->rhs_stride;
@@ -129,6 +130,8 @@ static vc_status build_tables(PackData& D, PackPrec& pp) {
     y.a.nrhs = m;
     y.a.n1x = n1x;
     y.a.n1y = n1y;
+    y.a.ph = tb.ax[1].ph.p;   // the y-normal components' half-voxel shift
+    y.a.phax = 1;
     y.pl = tb.ax[1].plan;
     y.tw = tb.ax[1].tw.p;
     y.lflag = P->d_lflag.as<uint8_t>();
@@ -144,6 +147,8 @@ static vc_status build_tables(PackData& D, PackPrec& pp) {
       ya.comp_stride = P->comp_stride; ya.rhs_stride = P->rhs_stride; ya.plane_stride = (int64_t)My * H;
       ya.row_stride = H; ya.ncols = H; ya.nrhs = m; ya.n1x = n1x; ya.n1y = n1y;
       ya.cs = cs; ya.nin = nin; ya.nout = nout; ya.inverse = inverse;
+      ya.ph = tb.ax[1].ph.p;
+      ya.phax = 1;
       int ythr = 0;
       size_t lds = 0;
       if (!ypass_config(My, (int)sizeof(T), H, budget, &ya, &ythr) || ya.ncol * eb < 32 ||
@@ -201,8 +206,6 @@ static vc_status build_tables(PackData& D, PackPrec& pp) {
       sc.R = tb.R.p;
       sc.tw = tb.ax[0].tw.p;
       sc.phx = tb.ax[0].ph.p;
-      sc.phy = tb.ax[1].ph.p;
-      sc.phz = tb.ax[2].ph.p;
       sc.pflag = P->d_pflag.as<uint8_t>();
       sc.c0 = c0;
       sc.ntiles = (My * H + cfg.ncol - 1) / cfg.ncol;

@@ -3,10 +3,10 @@
 
 namespace vc {
 template hipError_t launch_sandwich_v<double, 3, 3, 0>(const void*, void*, const void*, const SandArgs&, const void*,
-                                                const void*, const void*, const void*, const uint8_t*, int, size_t,
+                                                const void*, const uint8_t*, int, size_t,
                                                 int, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_sandwich_v<double, 3, 3, 1>(const void*, void*, const void*, const SandArgs&, const void*,
-                                                const void*, const void*, const void*, const uint8_t*, int, size_t,
+                                                const void*, const uint8_t*, int, size_t,
                                                 int, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_sandwich_multi_v<double, 3, 3>(const SandScene*, int, int, const int*, const int*, int,
                                                             size_t, int, hipStream_t);

@@ -401,7 +401,6 @@ template <typename T, int NIN, int NOUT, int RS, int PID = 0, int TK = 0>
 __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout,
                                               const T* __restrict__ R, const SandArgs& a,
                                               const C2<T>* __restrict__ twg, const C2<T>* __restrict__ phx,
-                                              const C2<T>* __restrict__ phy, const C2<T>* __restrict__ phz,
                                               const uint8_t* __restrict__ pflag, int tile, int rhs0,
                                               int nrhs_loop) {
   constexpr int RMAX = sandwich_rmax((int)sizeof(T)), RMID = sandwich_rmid((int)sizeof(T));
@@ -472,7 +471,6 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
     const int yflip = ky > a.My / 2;
     const int kyp = yflip ? a.My - ky : ky;
     const bool act0 = i < LR0;                   // owns a butterfly of the first / last stage
-    const C2<T> phy_t = phy[ky], phz_t = phz[kz];
     // half-voxel phase along x of the thread's frequency kx = i + m tl
     auto phase_x = [&](int m) -> C2<T> { return PH_LDS ? lds_ld<T>(phb, (uint32_t)(i + m * tl) * E) : phx[i + m * tl]; };
 
@@ -564,11 +562,10 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
       // half-voxel phase of the input component (shift to the common lattice); slot
       // pos(m) holds X[i + m tl]
       if (valid) {
-        const C2<T> phyz = csel(fax == 1, phy_t, phz_t);
         C2<T> w[RS];
 #pragma unroll
         for (int m = 0; m < RS; ++m)
-          w[m] = cmul(v[Dft<T, RS>::pos(m)], fax == 0 ? phase_x(m) : phyz);
+          w[m] = fax == 0 ? cmul(v[Dft<T, RS>::pos(m)], phase_x(m)) : v[Dft<T, RS>::pos(m)];
         // per-element selects keep q in registers (a switch of stores is merged into one
         // dynamically indexed store, which moves q to scratch memory)
 #pragma unroll
@@ -623,7 +620,6 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
       const int oax = NIN == 3 ? (o < 3 ? o : o - 3) : o;
       C2<T> z[RS];
       if (valid) {
-        const C2<T> phyz = csel(oax == 1, phy_t, phz_t);
 #pragma unroll
         for (int m = 0; m < RS; ++m) {
           C2<T> acc = {T(0), T(0)};
@@ -649,7 +645,7 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
             acc.y -= accE.x;
           }
           // output phase: conj of the half-voxel shift of the output component
-          z[m] = cmul(acc, cconj(oax == 0 ? phase_x(m) : phyz));
+          z[m] = oax == 0 ? cmul(acc, cconj(phase_x(m))) : acc;
         }
         if (o + 1 < NOUT) load_spectra(o + 1);
       }
@@ -707,8 +703,7 @@ __global__ void __launch_bounds__(sand_max_threads_fixed(PID, (int)sizeof(T), NI
                                       ? 4
                                       : ((sizeof(T) == 8 || NIN == 6) ? 2 : 3))
 k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __restrict__ R, SandArgs a,
-            const C2<T>* __restrict__ twg, const C2<T>* __restrict__ phx, const C2<T>* __restrict__ phy,
-            const C2<T>* __restrict__ phz, const uint8_t* __restrict__ pflag) {
+            const C2<T>* __restrict__ twg, const C2<T>* __restrict__ phx, const uint8_t* __restrict__ pflag) {
   if (a.skip && *a.skip) return;
   // a fixed-plan kernel never runs a plan other than its own (uniform check)
   if (PID > 0 && (a.Mx != kSandFixed[PID].L || a.nst != kSandFixed[PID].nst || a.radpack != sand_fixed_pack(PID) ||
@@ -718,7 +713,7 @@ k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __
   const int work = xcd_remap(blockIdx.y * ntiles + blockIdx.x, ntiles * gridDim.y);
   const int tile = work / a.nrhs, rhs = work - tile * a.nrhs;
   if (a.act && !a.act[rhs]) return;
-  sandwich_body<T, NIN, NOUT, RS, PID>(Fin, Fout, R, a, twg, phx, phy, phz, pflag, tile, rhs, 1);
+  sandwich_body<T, NIN, NOUT, RS, PID>(Fin, Fout, R, a, twg, phx, pflag, tile, rhs, 1);
 }
 
 // The Tucker-fused form: one workgroup per tile for all right-hand sides (the tile's
@@ -731,14 +726,13 @@ __global__ void __launch_bounds__(sand_max_threads_fixed(PID, (int)sizeof(T), NI
                                       ? 4
                                       : ((sizeof(T) == 8 || NIN == 6) ? 2 : 3))
 k_xsandwich_tk(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __restrict__ R, SandArgs a,
-               const C2<T>* __restrict__ twg, const C2<T>* __restrict__ phx, const C2<T>* __restrict__ phy,
-               const C2<T>* __restrict__ phz, const uint8_t* __restrict__ pflag) {
+               const C2<T>* __restrict__ twg, const C2<T>* __restrict__ phx, const uint8_t* __restrict__ pflag) {
   if (a.skip && *a.skip) return;
   if (PID > 0 && (a.Mx != kSandFixed[PID].L || a.nst != kSandFixed[PID].nst || a.radpack != sand_fixed_pack(PID) ||
                   a.tl * RS != a.Mx))
     return;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  sandwich_body<T, NIN, NOUT, RS, PID, 1>(Fin, Fout, R, a, twg, phx, phy, phz, pflag, tile, 0, a.nrhs);
+  sandwich_body<T, NIN, NOUT, RS, PID, 1>(Fin, Fout, R, a, twg, phx, pflag, tile, 0, a.nrhs);
 }
 
 // several scenes in one launch: linear workgroup -> (scene, tile, rhs), XCD-contiguous
@@ -754,8 +748,7 @@ k_xsandwich_multi(const SandScene* __restrict__ tab, int nscene, const int* __re
   if (act && !act[sc.c0 + rhs]) return;
   sandwich_body<T, NIN, NOUT, RS>(static_cast<const C2<T>*>(sc.Fin), static_cast<C2<T>*>(sc.Fout),
                                   static_cast<const T*>(sc.R), sc.a, static_cast<const C2<T>*>(sc.tw),
-                                  static_cast<const C2<T>*>(sc.phx), static_cast<const C2<T>*>(sc.phy),
-                                  static_cast<const C2<T>*>(sc.phz), sc.pflag, tile, rhs, 1);
+                                  static_cast<const C2<T>*>(sc.phx), sc.pflag, tile, rhs, 1);
 }
 
 // Compiled last-stage radices per kernel variant (register budget: the thread holds
@@ -769,7 +762,7 @@ template <typename T, int NIN> struct SandRS {
 // e0 / e1: optional events stamped by the launch itself (hipExtLaunchKernelGGL)
 template <typename T, int NIN, int NOUT, int RR, int ID, int TK>
 hipError_t launch_sandwich_rs(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
-                              const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
+                              const void* phx, const uint8_t* pflag, int nthr,
                               size_t lds, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   const int ntiles = (a.My * a.H + a.ncol - 1) / a.ncol;
   dim3 grid = TK ? dim3(ntiles) : dim3(ntiles, a.nrhs);
@@ -782,11 +775,10 @@ hipError_t launch_sandwich_rs(const void* Fin, void* Fout, const void* R, const 
     }
     if (e0 || e1)
       hipExtLaunchKernelGGL(kernel, grid, dim3(nthr), (std::uint32_t)lds, st, e0, e1, 0u, (const C2<T>*)Fin,
-                            (C2<T>*)Fout, (const T*)R, a, (const C2<T>*)tw, (const C2<T>*)phx, (const C2<T>*)phy,
-                            (const C2<T>*)phz, pflag);
+                            (C2<T>*)Fout, (const T*)R, a, (const C2<T>*)tw, (const C2<T>*)phx, pflag);
     else
       hipLaunchKernelGGL(kernel, grid, dim3(nthr), lds, st, (const C2<T>*)Fin, (C2<T>*)Fout, (const T*)R, a,
-                         (const C2<T>*)tw, (const C2<T>*)phx, (const C2<T>*)phy, (const C2<T>*)phz, pflag);
+                         (const C2<T>*)tw, (const C2<T>*)phx, pflag);
     return hipGetLastError();
   };
   if constexpr (ID < kSandNumFixed) {
@@ -797,7 +789,7 @@ hipError_t launch_sandwich_rs(const void* Fin, void* Fout, const void* R, const 
         else return go(k_xsandwich<T, NIN, NOUT, RR, ID>);
       }
     }
-    return launch_sandwich_rs<T, NIN, NOUT, RR, ID + 1, TK>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, st,
+    return launch_sandwich_rs<T, NIN, NOUT, RR, ID + 1, TK>(Fin, Fout, R, a, tw, phx, pflag, nthr, lds, st,
                                                             e0, e1);
   } else {
     if constexpr (TK) return go(k_xsandwich_tk<T, NIN, NOUT, RR, 0>);
@@ -807,12 +799,12 @@ hipError_t launch_sandwich_rs(const void* Fin, void* Fout, const void* R, const 
 
 template <typename T, int NIN, int NOUT, int TK>
 hipError_t launch_sandwich_v(const void* Fin, void* Fout, const void* R, const SandArgs& a, const void* tw,
-                             const void* phx, const void* phy, const void* phz, const uint8_t* pflag, int nthr,
+                             const void* phx, const uint8_t* pflag, int nthr,
                              size_t lds, int rs, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
 #define VC_RS(RR)                                                                                                 \
   case RR:                                                                                                        \
     if constexpr (RR <= SandRS<T, NIN>::max) {                                                                    \
-      return launch_sandwich_rs<T, NIN, NOUT, RR, 1, TK>(Fin, Fout, R, a, tw, phx, phy, phz, pflag, nthr, lds, st, \
+      return launch_sandwich_rs<T, NIN, NOUT, RR, 1, TK>(Fin, Fout, R, a, tw, phx, pflag, nthr, lds, st, \
                                                          e0, e1);                                                 \
     }                                                                                                             \
     break;

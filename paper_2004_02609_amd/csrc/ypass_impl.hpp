@@ -80,6 +80,9 @@ __device__ __forceinline__ void ypass_body(C2<T>* __restrict__ data, const YArgs
   const Buf base = make_buf(data + comp * a.comp_stride + rhs * a.rhs_stride + plane * a.plane_stride,
                             (uint32_t)a.plane_stride * E);
   const uint8_t* lf = lflag ? lflag + ((int64_t)axis * a.n1x + plane) * a.n1y : nullptr;
+  // half-voxel phase of this component along y (null: none): ph[ky] on the forward
+  // outputs, conj(ph[ky]) on the inverse inputs
+  const C2<T>* __restrict__ ph = (a.ph && axis == a.phax) ? static_cast<const C2<T>*>(a.ph) : nullptr;
   const uint32_t rowb = (uint32_t)a.row_stride * E;
   const int r0 = rad(0);
   const int LR0 = L / r0;
@@ -113,7 +116,15 @@ __device__ __forceinline__ void ypass_body(C2<T>* __restrict__ data, const YArgs
         v[m] = bld<T>(base, (inmask & (1u << m)) ? o : kOob);
         o += rowb;
       }
+      if (ph && a.inverse) {
+#pragma unroll
+        for (int m = 0; m < RS; ++m) v[m] = cmul(v[m], cconj(ph[m]));
+      }
       Dft<T, RS>::run(v, sg);
+      if (ph && !a.inverse) {
+#pragma unroll
+        for (int m = 0; m < RS; ++m) v[Dft<T, RS>::pos(m)] = cmul(v[Dft<T, RS>::pos(m)], ph[m]);
+      }
       o = gbase;
 #pragma unroll
       for (int m = 0; m < RS; ++m) {
@@ -131,6 +142,13 @@ __device__ __forceinline__ void ypass_body(C2<T>* __restrict__ data, const YArgs
 #undef VC_CALL
   }
   __syncthreads();   // twiddles in LDS
+  if (ph && a.inverse && act0) {
+    // inputs rows i + q L/f0
+#define VC_CALL(RR)                                                   \
+  _Pragma("unroll") for (int q = 0; q < RR; ++q) pre[q] = cmul(pre[q], cconj(ph[i + q * LR0]));
+    VC_YP_SWITCH(r0, VC_CALL, RMAX)
+#undef VC_CALL
+  }
   {
     uint32_t wbase = (uint32_t)i * (uint32_t)r0 * ncolpE + cE;
     asm volatile("" : "+v"(wbase));
@@ -162,6 +180,11 @@ __device__ __forceinline__ void ypass_body(C2<T>* __restrict__ data, const YArgs
     }
     tw_mul<T, RS>(v, twb, (uint32_t)i * E, sg);
     Dft<T, RS>::run(v, sg);
+    if (ph && !a.inverse) {
+      // outputs X[i + m tl]
+#pragma unroll
+      for (int m = 0; m < RS; ++m) v[Dft<T, RS>::pos(m)] = cmul(v[Dft<T, RS>::pos(m)], ph[i + m * tl]);
+    }
     uint32_t og = gbase;
     const uint32_t gs = (uint32_t)tl * rowb;
 #pragma unroll
