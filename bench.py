@@ -64,14 +64,17 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(config, kernel, prec):
-    """HBM bytes per launch from committed rocprofv3 --pmc summaries (null when absent or
-    taken on a different kernel source)."""
+def load_traffic(config, kernel, prec, tucker_tol=0.0):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries (null when absent,
+    taken on a different kernel source, or on the other form of the spectra: stored, or
+    Tucker-compressed and built in the x pass)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{config}_{prec}.json")
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
     if t.get("source_hash") != kernel_source_hash():
+        return None
+    if (float(t.get("tucker_tol", 0.0)) > 0) != (tucker_tol > 0):
         return None
     return t.get("passes", {}).get(kernel)
 
@@ -220,7 +223,8 @@ def write_traffic(args):
     # the y pass runs on one of two kernels (the autotuner's choice): the timed steps'
     # y launches are the last 2 x steps of either, alternating forward / inverse
     kern = {"zfwd_scatter": ("k_zfwd<" + tname,), "y": ("k_strided<" + tname, "k_ypass<" + tname),
-            "x_sandwich_multiply": ("k_xsandwich<" + tname,), "zinv_gather": ("k_zinv<" + tname,)}
+            "x_sandwich_multiply": ("k_xsandwich<" + tname, "k_xsandwich_tk<" + tname),
+            "zinv_gather": ("k_zinv<" + tname,)}
 
     def per_pass(rows):
         cp = [v for _, n, v in rows if "copy" in n.lower()]
@@ -241,9 +245,11 @@ def write_traffic(args):
 
     f, fs, fcp = per_pass(fetch)
     w, ws, wcp = per_pass(write)
+    tk = "" if args.tucker_tol is None else f" --tucker-tol {args.tucker_tol:g}"
     cmd = (f"python bench.py --config {args.config} --prec {args.prec} --steps {args.steps} --warmup {args.warmup} "
-           f"--no-cpu --no-solve --no-other --tucker-tol 0 --toeplitz-tol 0 --batch 0 --calib-copy-mib {args.calib_copy_mib}")
+           f"--no-cpu --no-solve --no-other{tk} --toeplitz-tol 0 --batch 0 --calib-copy-mib {args.calib_copy_mib}")
     res = {"source_hash": kernel_source_hash(), "config": args.config, "prec": args.prec,
+           "tucker_tol": WORKLOAD_TUCKER.get(args.config, 0.0) if args.tucker_tol is None else args.tucker_tol,
            "commands": [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- {cmd}",
                         f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- {cmd}"],
            "copy_bytes": copy_bytes, "copy_fetch_kib": fcp, "copy_write_kib": wcp,
@@ -598,7 +604,7 @@ def main():
     x_ms = pms[xi] / max(1, pcnt[xi])
     x_flops = xpass_flops(P.fft_size(), B, nout)
     x_tflops = x_flops / (x_ms / 1e3) / 1e12
-    x_traffic = load_traffic(args.config, "x_sandwich_multiply", args.prec)
+    x_traffic = load_traffic(args.config, "x_sandwich_multiply", args.prec, tucker_tol)
     roofline = {"bound": "alu", "kernel": "x_sandwich_multiply", "achieved": x_tflops,
                 "peak": VEC_PEAK_TFLOPS[args.prec], "unit": "TFLOP/s", "frac": x_tflops / VEC_PEAK_TFLOPS[args.prec],
                 "traffic": x_traffic, "alg_flops": x_flops, "alg_bytes": pbytes[xi], "avg_us": x_ms * 1e3,
@@ -641,7 +647,7 @@ def main():
                    "step": form if args.prec == "fp32" else form.replace("FP32", "FP64")},
         "roofline": roofline,
         "product_hbm": {"dominant_pass": kname, "achieved_GBs": achieved, "frac": achieved / HBM_PEAK_GBS,
-                        "traffic": load_traffic(args.config, kname, args.prec),
+                        "traffic": load_traffic(args.config, kname, args.prec, tucker_tol),
                         "all_passes_alg_bytes": float(sum(bbytes)),
                         "all_passes_GBs": float(sum(bbytes)) / (ms / args.steps / 1e3) / 1e9},
         "cpu_baseline": cpu,

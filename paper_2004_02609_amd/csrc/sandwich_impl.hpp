@@ -282,8 +282,8 @@ __device__ __forceinline__ int sw_pair(int o, int b) {
 
 // The fused form's tile spectra (eq. 13, the x-mode product): for every stored pair q
 // and tile column cc, X[q][kx'][cc] = sum_r U1_q[kx'][r] T2_q[ky'][kz][r] into LDS
-// (xt: [npairs][Hx][ncol]).  Column cc of tile `tile` sits in row j of the fold-pair
-// order, whose folded ky' is (j + 1) / 2.  U1 rows and T2 columns are r1p long (r1
+// (xt: [npairs][Hx][ncol]).  Column cc of tile `tile` is (ky, kz) of the flattened
+// column index, and ky' = min(ky, My - ky) its folded row.  U1 rows and T2 columns are r1p long (r1
 // rounded up to 4, zero past r1), read as whole 16-byte vectors.  The caller
 // synchronizes before reading xt.
 //
@@ -316,7 +316,7 @@ __device__ __forceinline__ void tk_tile_spectra(T* __restrict__ xt, const SandAr
       const f32x4* __restrict__ u1 =
           reinterpret_cast<const f32x4*>(static_cast<const float*>(tp.U1) + (int64_t)(aok ? row : 0) * tp.r1p);
       const f32x4* __restrict__ t2 = reinterpret_cast<const f32x4*>(
-          static_cast<const float*>(tp.T2) + ((int64_t)((jq + 1) >> 1) * a.H + kzq) * tp.r1p);
+          static_cast<const float*>(tp.T2) + ((int64_t)min(jq, a.My - jq) * a.H + kzq) * tp.r1p);
       const int nv = tp.r1p >> 2;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -378,7 +378,7 @@ __device__ __forceinline__ void tk_tile_spectra(T* __restrict__ xt, const SandAr
         const TkPairDev tp = a.tk[qp];
         const f64x2* __restrict__ u = reinterpret_cast<const f64x2*>(static_cast<const T*>(tp.U1) + (int64_t)kxq * tp.r1p);
         const f64x2* __restrict__ t2 = reinterpret_cast<const f64x2*>(
-            static_cast<const T*>(tp.T2) + ((int64_t)((jq + 1) >> 1) * a.H + kzq) * tp.r1p);
+            static_cast<const T*>(tp.T2) + ((int64_t)min(jq, a.My - jq) * a.H + kzq) * tp.r1p);
         for (int v = 0; v < (tp.r1p >> 1); ++v) {
           const f64x2 x = u[v], y = t2[v];
           acc += x.x * y.x + x.y * y.y;
@@ -461,13 +461,10 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
     const int col = tile * ncol + c;
     const bool colok = col < ncols;
     const int colc = colok ? col : ncols - 1;
-    // rows in fold-pair order 0, 1, My-1, 2, My-2, ...: rows ky and My - ky read the same
-    // stored octant row (each stored spectrum is even or odd under ky -> My - ky), so
-    // their tiles run next to each other on one XCD and that row comes from HBM once
-    const int jrow = fdiv(colc, 1.0f / (float)a.H), kz = colc - jrow * a.H;
-    const int jpair = (jrow + 1) >> 1;
-    const int ky = ((jrow & 1) || jrow == 0) ? jpair : a.My - jpair;
-    const int mcol = ky * a.H + kz;   // the column's position in the work array
+    // tiles of consecutive flattened columns: each tile's rows are 32-byte aligned
+    // chunks of the planes, and the tiles sharing a cache line run side by side
+    const int ky = fdiv(colc, 1.0f / (float)a.H), kz = colc - ky * a.H;
+    const int mcol = colc;   // the column's position in the work array
     const int yflip = ky > a.My / 2;
     const int kyp = yflip ? a.My - ky : ky;
     const bool act0 = i < LR0;                   // owns a butterfly of the first / last stage
@@ -718,7 +715,7 @@ k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __
 
 // The Tucker-fused form: one workgroup per tile for all right-hand sides (the tile's
 // spectra are built once into LDS and shared by them: the factor U1 is read once per
-// tile, not once per right-hand side); tiles XCD-contiguous in the fold-pair column
+// tile, not once per right-hand side); tiles XCD-contiguous in the column
 // order.
 template <typename T, int NIN, int NOUT, int RS, int PID = 0>
 __global__ void __launch_bounds__(sand_max_threads_fixed(PID, (int)sizeof(T), NIN),
