@@ -452,19 +452,24 @@ def solve_times(Pm, P64, log):
     def cerr(Cm):
         return float((np.abs(Cm - Cref)[gate] / np.abs(Cref)[gate]).max())
 
-    def timed(P, mode, rtol):
+    def timed(P, mode, rtol, form="auto"):
         """Median of three warm solves (the restart-cycle graphs are captured by a first,
         untimed solve), with the entrywise error of the last against FP64 at 1e-12."""
-        P.capacitance(prec=mode, rtol=rtol)
+        kw = {"mixed_form": form} if mode == "mixed" else {}
+        P.capacitance(prec=mode, rtol=rtol, **kw)
         ts = []
         for _ in range(3):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            Cm, st = P.capacitance(prec=mode, rtol=rtol)
+            Cm, st = P.capacitance(prec=mode, rtol=rtol, **kw)
             ts.append(time.perf_counter() - t0)
-        return {"time_s": float(np.median(ts)), "times_s": ts, "iters": st["iters"], "ir_steps": st["ir_steps"],
-                "max_rel_err_vs_fp64_1e-12": cerr(Cm), "products": st["mvp_count"], "rtol": rtol,
-                "spectra_bytes": st["spectra_bytes"]}
+        r = {"time_s": float(np.median(ts)), "times_s": ts, "iters": st["iters"], "ir_steps": st["ir_steps"],
+             "max_rel_err_vs_fp64_1e-12": cerr(Cm), "products": st["mvp_count"], "rtol": rtol,
+             "spectra_bytes": st["spectra_bytes"]}
+        if mode == "mixed":
+            r["mixed_form"] = st["mixed_form"]
+            r["steps_fp32"] = st["steps_fp32"]
+        return r
 
     runs = (("fp64", P64), ("mixed", Pm))
     cal = 1e-10
@@ -481,6 +486,15 @@ def solve_times(Pm, P64, log):
     out["at_rtol_1e-9"] = {mode: timed(P, mode, 1e-9) for mode, P in runs}
     out["at_rtol_1e-9"]["speedup_mixed_vs_fp64"] = (out["at_rtol_1e-9"]["fp64"]["time_s"] /
                                                     out["at_rtol_1e-9"]["mixed"]["time_s"])
+    # both mixed forms explicitly ("mixed" above is the automatic choice)
+    out["mixed_forms"] = {}
+    for form in ("refinement", "relaxed"):
+        for rt in (cal, 1e-9):
+            r = timed(Pm, "mixed", rt, form)
+            out["mixed_forms"][f"{form}_rtol_{rt:g}"] = {k: r[k] for k in (
+                "time_s", "iters", "ir_steps", "steps_fp32", "max_rel_err_vs_fp64_1e-12")}
+            log(f"# solve mixed/{form} at rtol {rt:g}: {r['time_s'] * 1e3:.2f} ms, iters {r['iters']}, "
+                f"fp32 steps {r['steps_fp32']}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     P64.capacitance(prec="fp64", rtol=cal, graph=False)

@@ -108,11 +108,18 @@ typedef struct {
 
 /* Solve options.  GMRES(restart) with the block-diagonal-diagonal preconditioner
  * (Sec. II.D) applied on the right; stops when ||b - A x|| <= rtol ||b|| per column.
- * VC_MIXED runs FP32 inner GMRES inside FP64 refinement (ir_max outer steps): each
- * inner solve stops at max(inner_rtol, rtol / (2 x the largest outer relative residual
- * still above rtol)), i.e. when the step has done what the outer tolerance needs or
- * FP32 products can do (inner_rtol), and after at most 4 restart cycles.  0 picks
- * defaults (rtol 1e-12, restart 35, max_iter 2000, inner_rtol 1e-6, ir_max 20). */
+ * VC_MIXED has two forms (mixed_form):
+ *   refinement: FP32 inner GMRES inside FP64 refinement (ir_max outer steps): each
+ *     inner solve stops at max(inner_rtol, rtol / (2 x the largest outer relative
+ *     residual still above rtol)), i.e. when the step has done what the outer tolerance
+ *     needs or FP32 products can do (inner_rtol), and after at most 4 restart cycles;
+ *   relaxed: one GMRES on the FP64 system whose restarts start from the FP64 residual,
+ *     and whose Arnoldi products are FP64 until every iterating column's residual
+ *     estimate is at most rtol / inner_rtol, FP32 after that (the product error a
+ *     step can afford grows as the residual shrinks); a cycle that starts in FP32 and
+ *     does not halve the true residual sends the rest of the solve back to FP64.
+ * 0 picks defaults (rtol 1e-12, restart 35, max_iter 2000, inner_rtol 1e-6, ir_max 20,
+ * mixed_form automatic). */
 typedef struct {
   vc_precision prec;
   double rtol;
@@ -125,7 +132,17 @@ typedef struct {
   int32_t graph;         /* 0: each restart cycle runs on the device without host round trips
                             and, after the first, is replayed as one captured hipGraph
                             (default); 1: the same kernels issued one by one             */
+  int32_t mixed_form;    /* VC_MIXED only: 0 automatic (relaxed when one FP64 product's
+                            algorithmic bytes, vc_stats.bytes_model at FP64, are at most
+                            VC_MIXED_RELAXED_MAX_BYTES: products that small are bound by
+                            latency and cache, so FP64 steps cost about as much as FP32
+                            ones, and refinement's restart would cost more; refinement
+                            otherwise), 1 refinement, 2 relaxed                          */
 } vc_solve_opts;
+
+#define VC_MIXED_REFINEMENT 1
+#define VC_MIXED_RELAXED 2
+#define VC_MIXED_RELAXED_MAX_BYTES (256.0 * 1024 * 1024)
 
 typedef struct {
   int32_t iters[64];          /* GMRES iterations per right-hand side (first 64)   */
@@ -138,6 +155,10 @@ typedef struct {
   double bytes_model;         /* algorithmic HBM bytes of one product of the solve's
                                  right-hand sides (every pass, the model of
                                  vc_pass_times), in the inner product's precision   */
+  int32_t mixed_form;         /* VC_MIXED: the form that ran (VC_MIXED_REFINEMENT or
+                                 VC_MIXED_RELAXED); 0 otherwise                      */
+  int32_t steps_fp32;         /* Arnoldi steps taken with FP32 products (the largest
+                                 over right-hand sides, summed over segments)       */
 } vc_stats;
 
 /* Copy the geometry, extract the panels and validate (host only, no GPU work).

@@ -319,6 +319,11 @@ hipError_t launch_block_apply(const double* x, double* y, int64_t N, int nrhs, c
 hipError_t launch_cycle_start(int nrhs, int m, const double* rn, const double* bn, const double* rtol, int* act_cycle,
                               int* act_step, double* g, double* scal, int* kd, int* skip, double* rre_out,
                               hipStream_t st);
+// what the host reads after a segment of the relaxed mixed form (2 + nrhs doubles):
+// the largest residual estimate of an iterating column, the step-level skip flag,
+// iteration counts
+hipError_t launch_relax_state(int nrhs, int m, const double* g, const int* kd, const int* act_step, const double* bn,
+                              const int* iters, const int* skip, double* out, hipStream_t st);
 hipError_t launch_arnoldi(int j, int nrhs, int m, const double* h1, const double* h2, int ldh, const double* hn,
                           double* H, double* cs, double* sn, double* g, const double* bn, const double* rtol,
                           int* act_step, int* kd, int* iters, double* scal, int* skip, int* bad, hipStream_t st);

@@ -450,6 +450,13 @@ vc_status pack_create(vc_problem* const* probs, int n, vc_problem** out) {
   return VC_OK;
 }
 
+double pack_product_bytes(vc_problem* Q, int elem) {
+  double b = 0.0;
+  if (Q && Q->pack)
+    for (vc_problem* P : Q->pack->mem) b += product_bytes_model(P, elem, P->m);
+  return b;
+}
+
 vc_status pack_capacitance(vc_problem* Q, const vc_solve_opts* opts, double* const* C_out, vc_stats* stats) {
   if (!Q || !Q->pack) { set_error("not a packed set"); return VC_ERR_ARG; }
   PackData& D = *Q->pack;
@@ -497,6 +504,8 @@ vc_status pack_capacitance(vc_problem* Q, const vc_solve_opts* opts, double* con
         sk.final_rre[j] = D.c0[k] + j < (int)rre.size() ? rre[D.c0[k] + j] : 0.0;
       }
       sk.ir_steps = all.ir_steps;
+      sk.mixed_form = all.mixed_form;
+      sk.steps_fp32 = all.steps_fp32;
       sk.mvp_count = Q->mvp_count;
       sk.t_setup_s = P->t_setup;
       sk.t_solve_s = t_solve;

@@ -116,6 +116,7 @@ struct SolveWs {
   double *rr = nullptr, *dd = nullptr, *h = nullptr, *y2 = nullptr, *partial = nullptr, *norm = nullptr;
   double *cyc = nullptr;       // device-side GMRES cycle state (doubles)
   double *dC = nullptr;        // m x m capacitance of the last reduction
+  double *rx = nullptr;        // 2 + nrhs doubles the relaxed mixed form reads per segment
   int *active = nullptr, *cyci = nullptr;
   unsigned* cnt = nullptr;     // completion counters of the fused Gram-Schmidt step (rest at 0)
   int nrhs = 0, restart = 0;   // the largest solve shape the regions hold
@@ -212,9 +213,10 @@ struct vc_problem {
     int part;   // 0: cycle start, 1..nseg: segments of Arnoldi steps, nseg + 1: the update
     const double* b;
     double* x;
+    int relax;  // segments of the relaxed mixed form end with the state read-back kernel
     bool operator==(const GraphKey& o) const {
       return mvp == o.mvp && transpose == o.transpose && precond == o.precond && nrhs == o.nrhs &&
-             restart == o.restart && part == o.part && b == o.b && x == o.x;
+             restart == o.restart && part == o.part && b == o.b && x == o.x && relax == o.relax;
     }
   };
   struct GraphEntry {
@@ -313,6 +315,8 @@ template <typename T>
 vc_status tucker_rebuild(vc_problem* p, hipStream_t st, const int* skip = nullptr);
 // algorithmic bytes of one forward product of nrhs columns, every pass (elem: 4 or 8)
 double product_bytes_model(vc_problem* p, int elem, int nrhs);
+// the same summed over the members of a packed set (one product of all their columns)
+double pack_product_bytes(vc_problem* q, int elem);
 vc_status apply_op(vc_problem* p, int transpose, vc_precision prec, const double* x, double* y, int nrhs,
                    hipStream_t st, const int* skip = nullptr, const int* act = nullptr);
 // the same over a packed set (pack.cpp)

@@ -48,6 +48,7 @@ size_t solve_ws_layout(int64_t N, int k, int r, char* base, SolveWs* ws) {
   // act_cycle, act_step (ints) + skip[2], bad
   take(w.cyc, (size_t)k * ((size_t)(r + 1) * r + 2 * r + (r + 1) + 4) + 1);
   take(w.dC, (size_t)k * k);
+  take(w.rx, (size_t)k + 2);
   take(w.active, (size_t)k);
   take(w.cyci, (size_t)4 * k + 5);
   take(w.cnt, (size_t)cgs_counter_size(r + 1, k));
@@ -179,6 +180,8 @@ vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, doubl
                              c.iters, c.scal, c.skip, c.bad, nrm, st));
       if (j + 1 < m) VC_HIP(launch_scale_copy(V + (j + 1) * ldv, w, N, nrhs, c.scal, c.skip + 1, st));
     }
+    if (sp.relax)
+      VC_HIP(launch_relax_state(nrhs, m, c.g, c.kd, c.act_step, c.bn, c.iters, c.skip, P->ws.rx, st));
     return VC_OK;
   }
   // x += R V y, y = R_H^{-1} g over each column's steps
@@ -201,7 +204,7 @@ vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, doubl
 // configurations (and runs the autotuner) outside the capture.
 vc_status cycle_graph(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs, hipStream_t st,
                       int part, hipGraph_t* g_out, hipGraphExec_t* e_out) {
-  vc_problem::GraphKey key{(int)sp.mvp, sp.transpose, sp.precond, nrhs, sp.restart, part, b, x};
+  vc_problem::GraphKey key{(int)sp.mvp, sp.transpose, sp.precond, nrhs, sp.restart, part, b, x, sp.relax};
   for (const auto& e : P->graphs)
     if (e.key == key) {
       *g_out = e.graph;
@@ -247,8 +250,15 @@ static vc_status run_part(vc_problem* P, const SolveSpec& sp, const double* b, d
 // graphs on, every cycle replays one graph captured at the first solve of this shape
 // (rtol is read from device memory, so solves to any tolerance share it); an eager
 // product before the capture settles the autotuned launch configuration.
+//
+// Relaxed mixed form (sp.relax): each segment's products are FP32 when the largest
+// residual estimate of an iterating column (read after the previous segment, or the
+// true residual at the cycle start) is at most sp.relax_thr, FP64 otherwise; the cycle
+// starts compute the true residual with FP64 products.  A cycle that starts in FP32
+// and does not halve the largest true residual sends the rest of the solve to FP64.
+// steps32: Arnoldi steps taken with FP32 products (largest over columns, per segment).
 vc_status gmres(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs,
-                       std::vector<int>& iters, std::vector<double>& rre, hipStream_t st) {
+                       std::vector<int>& iters, std::vector<double>& rre, hipStream_t st, int* steps32) {
   const int64_t N = npanels(P);
   const int m = sp.restart;
   vc_status s = ensure_workspace(P, nrhs, m);
@@ -262,6 +272,21 @@ vc_status gmres(vc_problem* P, const SolveSpec& sp, const double* b, double* x, 
   std::vector<int> it(nrhs), skip(2);
   rre.assign(nrhs, 0.0);
   int bad = 0;
+  const bool relax = sp.relax != 0;
+  std::vector<double> rx(relax ? nrhs + 2 : 0);
+  std::vector<int> it_seg(nrhs, 0);   // iteration counts before the current segment
+  double est = INFINITY;              // worst residual estimate of an iterating column
+  double start_prev = INFINITY;       // worst true residual at the previous cycle start
+  bool force64 = false, start32 = false, seg32 = false;
+  int n32 = 0;
+  // FP32 steps of the segment just run: the largest per-column count increase
+  auto count32 = [&](const int* now, bool was32) {
+    int d = 0;
+    for (int c = 0; c < nrhs; ++c) d = std::max(d, now[c] - it_seg[c]);
+    if (was32) n32 += d;
+    std::copy(now, now + nrhs, it_seg.begin());
+  };
+  std::vector<int> itv(nrhs);
   // start of the first cycle; each later round runs the previous cycle's steps and
   // the next cycle's start before one host read-back
   s = run_part(P, sp, b, x, nrhs, st, 0);
@@ -271,12 +296,27 @@ vc_status gmres(vc_problem* P, const SolveSpec& sp, const double* b, double* x, 
     if (cycle > 0) {
       // the steps segment by segment, until no column is still iterating
       for (int seg = 1; seg <= nseg; ++seg) {
-        s = run_part(P, sp, b, x, nrhs, st, seg);
+        SolveSpec ss = sp;
+        if (relax) {
+          seg32 = !force64 && est <= sp.relax_thr;
+          ss.mvp = seg32 ? VC_FP32 : VC_FP64;
+          if (seg == 1) start32 = seg32;
+        }
+        s = run_part(P, ss, b, x, nrhs, st, seg);
         if (s != VC_OK) return s;
         if (seg == nseg) break;
         int step_done = 0;
-        VC_HIP(hipMemcpyAsync(&step_done, c.skip + 1, sizeof(int), hipMemcpyDeviceToHost, st));
-        VC_HIP(hipStreamSynchronize(st));
+        if (relax) {
+          VC_HIP(hipMemcpyAsync(rx.data(), P->ws.rx, rx.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+          VC_HIP(hipStreamSynchronize(st));
+          est = rx[0];
+          step_done = rx[1] != 0.0;
+          for (int k = 0; k < nrhs; ++k) itv[k] = (int)rx[2 + k];
+          count32(itv.data(), seg32);
+        } else {
+          VC_HIP(hipMemcpyAsync(&step_done, c.skip + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+          VC_HIP(hipStreamSynchronize(st));
+        }
         if (step_done) break;
       }
       s = run_part(P, sp, b, x, nrhs, st, nseg + 1);
@@ -290,6 +330,17 @@ vc_status gmres(vc_problem* P, const SolveSpec& sp, const double* b, double* x, 
     VC_HIP(hipMemcpyAsync(&bad, c.bad, sizeof(int), hipMemcpyDeviceToHost, st));
     VC_HIP(hipStreamSynchronize(st));
     iters = it;
+    if (relax) {
+      if (cycle > 0) count32(it.data(), seg32);   // the cycle's last segment
+      // the next cycle's columns are those above rtol; their worst true residual
+      double worst = 0.0;
+      for (int k = 0; k < nrhs; ++k)
+        if (rre[k] > sp.rtol) worst = std::max(worst, rre[k]);
+      if (cycle > 0 && start32 && !(worst <= 0.5 * start_prev)) force64 = true;
+      start_prev = worst;
+      est = worst;
+    }
+    if (steps32) *steps32 = relax ? n32 : (sp.mvp == VC_FP32 ? *std::max_element(it.begin(), it.end()) : 0);
     for (int k = 0; k < nrhs; ++k)
       if (!std::isfinite(rre[k])) { set_error("non-finite residual in column %d", k); return VC_ERR_NUMERIC; }
     if (bad) { set_error("non-finite Arnoldi coefficient"); return VC_ERR_NUMERIC; }
@@ -311,7 +362,8 @@ hipStream_t get_solve_stream(vc_problem* P) {
   return P->solve_stream;
 }
 
-// FP64 solve, or FP32-product GMRES inside FP64 refinement (VC_MIXED).
+// FP64 solve, or VC_MIXED: FP32-product GMRES inside FP64 refinement, or the relaxed
+// form (one GMRES whose Arnoldi products turn FP32 as the residual shrinks).
 vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const double* b, double* x, int nrhs,
                        vc_stats* stats, hipStream_t st, std::vector<int>* it_out, std::vector<double>* rre_out) {
   const int64_t N = npanels(P);
@@ -337,13 +389,34 @@ vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const doub
     const vc_status bs = build_precond_full(P, st);
     if (bs != VC_OK) return bs;
   }
+  if (o.mixed_form < 0 || o.mixed_form > VC_MIXED_RELAXED) {
+    set_error("mixed_form must be 0 (automatic), 1 (refinement) or 2 (relaxed)");
+    return VC_ERR_ARG;
+  }
   VC_HIP(hipMemsetAsync(x, 0, (size_t)nrhs * N * sizeof(double), st));
-  int ir_steps = 0;
+  int ir_steps = 0, n32 = 0, form = 0;
   vc_status s;
+  if (o.prec == VC_MIXED) {
+    form = o.mixed_form;
+    if (form == 0) {
+      // relaxed where FP64 products are small enough to be bound by latency and cache
+      const double b64 = P->pack ? pack_product_bytes(P, 8) : product_bytes_model(P, 8, nrhs);
+      form = b64 <= VC_MIXED_RELAXED_MAX_BYTES ? VC_MIXED_RELAXED : VC_MIXED_REFINEMENT;
+    }
+  }
   if (o.prec != VC_MIXED) {
     sp.mvp = o.prec == VC_FP32 ? VC_FP32 : VC_FP64;
     sp.rtol = o.rtol;
-    s = gmres(P, sp, b, x, nrhs, it, rre, st);
+    s = gmres(P, sp, b, x, nrhs, it, rre, st, &n32);
+  } else if (form == VC_MIXED_RELAXED) {
+    // one GMRES on the FP64 system: FP64 residuals at the restarts, FP32 Arnoldi
+    // products once the residual estimate is below rtol / inner_rtol (an FP32 product's
+    // relative error is taken as inner_rtol)
+    sp.mvp = VC_FP64;
+    sp.rtol = o.rtol;
+    sp.relax = 1;
+    sp.relax_thr = o.rtol / o.inner_rtol;
+    s = gmres(P, sp, b, x, nrhs, it, rre, st, &n32);
   } else {
     // outer FP64 refinement: r = b - A x (FP64 product), inner FP32 GMRES on A d = r, x += d
     s = ensure_workspace(P, nrhs, o.restart);
@@ -368,8 +441,10 @@ vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const doub
       s32.rtol = std::max(o.inner_rtol, 0.5 * o.rtol / worst);
       s32.max_iter = std::min(o.max_iter, 4 * o.restart);
       VC_HIP(hipMemsetAsync(ddp, 0, (size_t)nrhs * N * sizeof(double), st));
-      vc_status si = gmres(P, s32, rrp, ddp, nrhs, it, rre, st);
+      int k32 = 0;
+      vc_status si = gmres(P, s32, rrp, ddp, nrhs, it, rre, st, &k32);
       if (si != VC_OK && si != VC_ERR_NOT_CONVERGED) return si;
+      n32 += k32;
       for (int c = 0; c < nrhs; ++c) tot[c] += it[c];
       VC_HIP(hipMemcpyAsync(P->ws.norm + nrhs, ones.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
       VC_HIP(launch_axpy_cols(x, ddp, N, nrhs, P->ws.norm + nrhs, 0, st));
@@ -402,6 +477,8 @@ vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const doub
       stats->final_rre[c] = c < (int)rre.size() ? rre[c] : 0.0;
     }
     stats->ir_steps = ir_steps;
+    stats->mixed_form = form;
+    stats->steps_fp32 = n32;
   }
   return s;
 }

@@ -17,6 +17,11 @@ struct SolveSpec {
   int precond;          // 0 none, 1 block-diagonal-diagonal, 2 diagonal
   double rtol;
   int restart, max_iter;
+  // relaxed mixed form: the product precision is chosen per segment of Arnoldi steps
+  // (FP32 once every iterating column's residual estimate is <= relax_thr); cycle
+  // starts (residuals) and updates use mvp, which is then VC_FP64
+  int relax = 0;
+  double relax_thr = 0.0;
 };
 
 // views of the cycle state for one (nrhs, restart) solve
@@ -39,7 +44,7 @@ vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, doubl
 vc_status cycle_graph(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs, hipStream_t st,
                       int part, hipGraph_t* g_out, hipGraphExec_t* e_out);
 vc_status gmres(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs, std::vector<int>& iters,
-                std::vector<double>& rre, hipStream_t st);
+                std::vector<double>& rre, hipStream_t st, int* steps32 = nullptr);
 hipStream_t get_solve_stream(vc_problem* P);
 vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const double* b, double* x, int nrhs,
                 vc_stats* stats, hipStream_t st, std::vector<int>* it_out = nullptr,

@@ -412,6 +412,42 @@ hipError_t launch_cycle_start(int nrhs, int m, const double* rn, const double* b
   return hipGetLastError();
 }
 
+// State the host reads after a segment of Arnoldi steps in the relaxed mixed form, in
+// one copy: out[0] = the largest residual estimate |g(kd)| / |b| over the columns still
+// iterating (0 if none), out[1] = the step-level skip flag, out[2 + c] = iters[c].
+__global__ void k_relax_state(int nrhs, int m, const double* __restrict__ g, const int* __restrict__ kd,
+                              const int* __restrict__ act_step, const double* __restrict__ bn,
+                              const int* __restrict__ iters, const int* __restrict__ skip, double* __restrict__ out) {
+  __shared__ double red[kCycleMax];
+  const int c = threadIdx.x;
+  double e = 0.0;
+  if (c < nrhs) {
+    if (act_step[c] && bn[c] > 0.0) {
+      e = fabs(g[(int64_t)c * (m + 1) + kd[c]]) / bn[c];
+      if (!(e == e)) e = INFINITY;   // a NaN estimate keeps FP64 products
+    }
+    out[2 + c] = (double)iters[c];
+  }
+  red[c] = e;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (c < s) red[c] = fmax(red[c], red[c + s]);
+    __syncthreads();
+  }
+  if (c == 0) {
+    out[0] = red[0];
+    out[1] = (double)skip[1];
+  }
+}
+
+hipError_t launch_relax_state(int nrhs, int m, const double* g, const int* kd, const int* act_step, const double* bn,
+                              const int* iters, const int* skip, double* out, hipStream_t st) {
+  if (nrhs > kCycleMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_relax_state, dim3(1), dim3(cycle_threads(nrhs)), 0, st, nrhs, m, g, kd, act_step, bn, iters,
+                     skip, out);
+  return hipGetLastError();
+}
+
 // Arnoldi step j: H(:, j) = h1 + h2 (classical Gram-Schmidt, twice), H(j+1, j) = |w|,
 // previous rotations applied, new rotation from (H(j,j), H(j+1,j)), g rotated; a column
 // freezes when its residual estimate |g(j+1)| / |b| <= rtol / 2, on breakdown, or at

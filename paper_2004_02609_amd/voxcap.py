@@ -55,13 +55,14 @@ class vc_setup_opts(C.Structure):
 class vc_solve_opts(C.Structure):
     _fields_ = [("prec", C.c_int), ("rtol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
                 ("inner_rtol", C.c_double), ("ir_max", C.c_int32), ("use_precond", C.c_int32),
-                ("graph", C.c_int32)]
+                ("graph", C.c_int32), ("mixed_form", C.c_int32)]
 
 
 class vc_stats(C.Structure):
     _fields_ = [("iters", C.c_int32 * 64), ("final_rre", C.c_double * 64), ("ir_steps", C.c_int32),
                 ("mvp_count", C.c_int32), ("t_setup_s", C.c_double), ("t_solve_s", C.c_double),
-                ("spectra_bytes", C.c_double), ("tucker_rank_max", C.c_int32), ("bytes_model", C.c_double)]
+                ("spectra_bytes", C.c_double), ("tucker_rank_max", C.c_int32), ("bytes_model", C.c_double),
+                ("mixed_form", C.c_int32), ("steps_fp32", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -477,8 +478,15 @@ def vc_pass_times(h):
     return list(ms), list(n), list(b)
 
 
-def _solve_opts(prec="fp64", rtol=0.0, restart=0, max_iter=0, inner_rtol=0.0, ir_max=0, use_precond=1, graph=True):
+# VC_MIXED forms (vc_solve_opts.mixed_form)
+_MIXED_FORM = {"auto": 0, "refinement": 1, "relaxed": 2}
+MIXED_FORM_NAMES = {1: "refinement", 2: "relaxed"}
+
+
+def _solve_opts(prec="fp64", rtol=0.0, restart=0, max_iter=0, inner_rtol=0.0, ir_max=0, use_precond=1, graph=True,
+                mixed_form="auto"):
     o = vc_solve_opts()
+    o.mixed_form = _MIXED_FORM[mixed_form]
     o.prec = _PREC[prec]
     o.rtol = rtol
     o.restart = restart
@@ -525,7 +533,8 @@ def vc_capacitance_grad_eps(h, m, block_of_voxel, nblocks, **solve):
 def stats_dict(st, nrhs):
     return {"iters": list(st.iters[:nrhs]), "final_rre": list(st.final_rre[:nrhs]), "ir_steps": st.ir_steps,
             "mvp_count": st.mvp_count, "t_setup_s": st.t_setup_s, "t_solve_s": st.t_solve_s,
-            "spectra_bytes": st.spectra_bytes, "bytes_model": st.bytes_model}
+            "spectra_bytes": st.spectra_bytes, "bytes_model": st.bytes_model,
+            "mixed_form": MIXED_FORM_NAMES.get(st.mixed_form), "steps_fp32": st.steps_fp32}
 
 
 def capacitance_batch(problems, **solve):

@@ -149,15 +149,18 @@ def test_capacitance_fp64(dev, name, make):
 
 
 @pytest.mark.parametrize("name,make", SCENES[2:4])
-def test_capacitance_mixed(dev, name, make):
+@pytest.mark.parametrize("form", ["refinement", "relaxed"])
+def test_capacitance_mixed(dev, name, make, form):
     s = make()
     P = _problem(s)
-    C, st = P.capacitance(prec="mixed", rtol=1e-10)
+    C, st = P.capacitance(prec="mixed", rtol=1e-10, mixed_form=form)
+    assert st["mixed_form"] == form
     C_ref = oracle.solve_capacitance(s)
     d = np.abs(np.diag(C_ref)).max()
     gate = np.abs(C_ref) >= 1e-3 * d
     rel = np.abs(C - C_ref)[gate] / np.abs(C_ref)[gate]
-    print(name, "C mixed max entry rel err", rel.max(), "ir", st["ir_steps"], st["iters"], flush=True)
+    print(name, form, "C mixed max entry rel err", rel.max(), "ir", st["ir_steps"], st["iters"],
+          "fp32 steps", st["steps_fp32"], flush=True)
     assert rel.max() < 1e-6
 
 
