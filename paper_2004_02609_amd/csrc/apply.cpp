@@ -368,6 +368,8 @@ static vc_status run_apply(vc_problem* P, int transpose, const double* x, double
   const int tk_np = (int)P->tk.size();
   xa.tk = tk_np > 0 ? P->tk_dev[sizeof(T) == 8 ? 1 : 0].as<TkPairDev>() : nullptr;
   xa.npairs = tk_np;
+  xa.tk_r1max = 0;
+  for (const TuckerPair& tp : P->tk) xa.tk_r1max = std::max(xa.tk_r1max, tp.r[0]);
   CompSet cout{};
   if (!transpose) {
     xa.nin = 3;

@@ -94,9 +94,10 @@ bool ypass_config(int L, int elem, int ncols, size_t budget, YArgs* a, int* nthr
 // row-major) and the strip T2 = S x2 U2 x3 U3 (Hy x H x r1p, r fastest), in the
 // product's precision; r1p = r1 rounded up to 4, zero past r1 in both
 struct TkPairDev {
-  const void* U1;
-  const void* T2;
-  int r1, r1p;
+  const void* U1;    // [Hx][r1p] (FP64 table)
+  const void* T2;    // [Hy][H][r1p]
+  const void* U1t;   // FP32 table: U1 transposed, [r1q][hxp] (zero filled)
+  int r1, r1p, r1q, hxp;
 };
 
 struct SandArgs {
@@ -118,6 +119,7 @@ struct SandArgs {
   // (device table of npairs entries); one workgroup per tile runs every right-hand side
   const TkPairDev* tk;
   int npairs;
+  int tk_r1max;   // largest x-mode rank r1 over the pairs
 };
 // dynamic LDS of the sandwich: twiddle table (+ the x phases in FP32) + one [L][ncol]
 // tile + 3 n1x plane flags

@@ -73,10 +73,11 @@ struct PrecTables {
 struct TuckerPair {
   int r[3] = {0, 0, 0};
   DevMem S64, U64[3], S32, U32[3];
-  // the fused x pass's copies of U1 with rows padded to r1p = r1 rounded up to 4 (zero
-  // filled), so a row is read as whole 16-byte vectors
-  int r1p = 0;
-  DevMem U1p64, U1p32;
+  // the fused x pass's copies of U1: FP64 with rows padded to r1p = r1 rounded up to 4
+  // (zero filled; a row is read as whole 16-byte vectors), FP32 transposed, [r1q][hxp]
+  // (r1q = r1 rounded up to 16, hxp = Hx rounded up to 64, zero filled)
+  int r1p = 0, r1q = 0, hxp = 0;
+  DevMem U1p64, U1t32;
 };
 
 // The conventional block-diagonal preconditioner the paper compares against (Sec. III.A):

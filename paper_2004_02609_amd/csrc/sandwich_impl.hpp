@@ -283,68 +283,202 @@ __device__ __forceinline__ int sw_pair(int o, int b) {
 // The fused form's tile spectra (eq. 13, the x-mode product): for every stored pair q
 // and tile column cc, X[q][kx'][cc] = sum_r U1_q[kx'][r] T2_q[ky'][kz][r] into LDS
 // (xt: [npairs][Hx][ncol]).  Column cc of tile `tile` is (ky, kz) of the flattened
-// column index, and ky' = min(ky, My - ky) its folded row.  U1 rows and T2 columns are r1p long (r1
-// rounded up to 4, zero past r1), read as whole 16-byte vectors.  The caller
-// synchronizes before reading xt.
+// column index, and ky' = min(ky, My - ky) its folded row.  The caller synchronizes
+// before reading xt.
 //
 // FP32 on the matrix cores: V_MFMA_F32_4X4X1_16B (16 blocks of 4 x 4 x 1 per wave).
 // One wave takes one unit (pair, group of 64 kx' rows, group of 4 columns): lane l
 // feeds row 64g + l of U1 as A and column 4cg + (l & 3) of T2 as B, so block b = l / 4
 // forms rows 64g + 4b .. 64g + 4b + 3 of those four columns, accumulating over r (one
-// r per instruction).  Lane 4b + j then holds D_b[i][j] in accumulator element i.  The
-// next pass's operands (16 values of r per pass) are loaded while the current one runs.
+// r per instruction).  Lane 4b + j then holds D_b[i][j] in accumulator element i.  A
+// pass covers 16 values of r: A from U1 transposed ([r][kx'], rows of hxp = Hx rounded
+// up to 64, r1q = r1 rounded up to 16 rows, zero filled), so each of its 16 loads reads
+// 256 contiguous bytes; B from T2 ([ky'][kz][r], rows r1p = r1 rounded up to 4, zero
+// past r1) as 16-byte vectors, four columns per wave.  The next pass's operands are
+// loaded while the current one runs.
+// A pair's table entry with every field in scalar registers (readfirstlane): the
+// buffer views built from it are then uniform, so each buffer load is one instruction
+// rather than a loop over the distinct descriptors of the wave.
+__device__ __forceinline__ const void* uniform_ptr(const void* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return reinterpret_cast<const void*>(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ TkPairDev tk_entry(const TkPairDev* __restrict__ tab, int q) {
+  TkPairDev t = tab[q];
+  t.U1 = uniform_ptr(t.U1);
+  t.T2 = uniform_ptr(t.T2);
+  t.U1t = uniform_ptr(t.U1t);
+  t.r1 = __builtin_amdgcn_readfirstlane(t.r1);
+  t.r1p = __builtin_amdgcn_readfirstlane(t.r1p);
+  t.r1q = __builtin_amdgcn_readfirstlane(t.r1q);
+  t.hxp = __builtin_amdgcn_readfirstlane(t.hxp);
+  return t;
+}
+
+// FP32 tile spectra when every pair's r1 <= 32 (the usual ranks): the matrix-core
+// product of tk_tile_spectra with few operand loads and little scalar work per unit.
+// A unit is (pair q, column group cg, row group g), ordered with g fastest; each wave
+// takes a contiguous range of units, so consecutive units share (q, cg) and the B
+// operand (the tile's T2 columns, r < 32, eight 16-byte vectors per lane) is loaded once
+// per (q, cg).  A unit's A operand is rows 0..31 of U1 transposed at its 64 kx' (32
+// dword loads of 256 contiguous bytes; rows past r1q read zero), all loaded one unit
+// ahead into the other of two buffers, unconditionally (the last repeats a valid unit),
+// so the wait before a unit covers that unit's loads only.  The unit counters advance by
+// increments (no divisions per unit), and the 8-rank chunks past r1 are skipped.
+__device__ __forceinline__ void tk_tile_spectra_r32(float* __restrict__ xt, const SandArgs& a, int tile, int ncol,
+                                                    int lane, int wave, int nwave, int ngr, int ncg, int units,
+                                                    int Hy) {
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  const int ncols = a.My * a.H;
+  const int u_beg = (int)((int64_t)units * wave / nwave), u_end = (int)((int64_t)units * (wave + 1) / nwave);
+  if (u_beg >= u_end) return;
+  f32x4 bv[8];
+  auto loadB = [&](const TkPairDev& tp, int cg) {
+    const int colb = cg * 4 + (lane & 3);
+    const int colq = tile * ncol + colb;
+    const bool bok = colb < ncol && colq < ncols;
+    const int jq = bok ? colq / a.H : 0, kzq = bok ? colq - jq * a.H : 0;
+    // descriptors from scalar registers at the point of use (a loop-carried entry may
+    // otherwise be kept in vector registers, which turns each load into a loop)
+    const int r1p = __builtin_amdgcn_readfirstlane(tp.r1p);
+    const Buf tb = make_buf(uniform_ptr(tp.T2), (uint32_t)__builtin_amdgcn_readfirstlane(Hy * a.H * r1p * 4));
+    const uint32_t to = (uint32_t)(min(jq, a.My - jq) * a.H + kzq) * (uint32_t)r1p * 4u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const bool in = bok && 4 * k < r1p;
+      bv[k] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(tb.r, in ? to + 16u * k : kOob, 0, 0));
+    }
+  };
+  auto loadA = [&](const TkPairDev& tp, int g, float* av) {
+    const int hxp = __builtin_amdgcn_readfirstlane(tp.hxp);
+    const Buf ub = make_buf(uniform_ptr(tp.U1t), (uint32_t)__builtin_amdgcn_readfirstlane(tp.r1q * hxp * 4));
+    const uint32_t ho = (uint32_t)hxp * 4u;
+    uint32_t uo = ((uint32_t)__builtin_amdgcn_readfirstlane(g * 64) + (uint32_t)lane) * 4u;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      av[k] = bld1<float>(ub, uo);
+      uo += ho;
+    }
+  };
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  int q = u_beg / (ngr * ncg);
+  int cg = (u_beg - q * ngr * ncg) / ngr;
+  int g = u_beg - q * ngr * ncg - cg * ngr;
+  int u = u_beg;
+  TkPairDev tp = tk_entry(a.tk, q);
+  loadB(tp, cg);
+  float A0[32], A1[32];
+  loadA(tp, g, A0);
+  // one unit from `cur`, the next one's A loads issued into `nx` first
+  auto unit = [&](const float* cur, float* nx) -> bool {
+    int q1 = q, cg1 = cg, g1 = g + 1;
+    if (g1 == ngr) {
+      g1 = 0;
+      if (++cg1 == ncg) { cg1 = 0; ++q1; }
+    }
+    const bool more = u + 1 < u_end;
+    const bool newq = more && q1 != q;
+    const TkPairDev tn = newq ? tk_entry(a.tk, q1) : tp;
+    loadA(tn, more ? g1 : g, nx);
+    const int nch = __builtin_amdgcn_readfirstlane((tp.r1 + 7) >> 3);
+    acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#define VC_TK_CHUNK(CC)                                                                                     \
+  _Pragma("unroll") for (int e = 0; e < 4; ++e) acc =                                                       \
+      __builtin_amdgcn_mfma_f32_4x4x1f32(cur[8 * (CC) + e], bv[2 * (CC)][e], acc, 0, 0, 0);                 \
+  _Pragma("unroll") for (int e = 0; e < 4; ++e) acc =                                                       \
+      __builtin_amdgcn_mfma_f32_4x4x1f32(cur[8 * (CC) + 4 + e], bv[2 * (CC) + 1][e], acc, 0, 0, 0);
+    VC_TK_CHUNK(0)
+    if (nch > 1) { VC_TK_CHUNK(1) }
+    if (nch > 2) { VC_TK_CHUNK(2) }
+    if (nch > 3) { VC_TK_CHUNK(3) }
+#undef VC_TK_CHUNK
+    const int b = lane >> 2, col = cg * 4 + (lane & 3);
+    if (col < ncol) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int rw = g * 64 + 4 * b + i;
+        if (rw < a.Hx) xt[((int64_t)q * a.Hx + rw) * ncol + col] = acc[i];
+      }
+    }
+    if (!more) return false;
+    if (newq || cg1 != cg) loadB(tn, cg1);   // a new pair or column group
+    q = q1;
+    cg = cg1;
+    g = g1;
+    tp = tn;
+    ++u;
+    return true;
+  };
+  for (;;) {
+    if (!unit(A0, A1)) break;
+    if (!unit(A1, A0)) break;
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void tk_tile_spectra(T* __restrict__ xt, const SandArgs& a, int tile, int ncol) {
   const int ncols = a.My * a.H;
   if constexpr (sizeof(T) == 4) {
     typedef float f32x4 __attribute__((ext_vector_type(4)));
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    // the wave index is uniform: the unit indices below live in scalar registers and a
+    // pair's table entry comes through the scalar cache
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nwave = blockDim.x >> 6;
     const int ngr = (a.Hx + 63) >> 6, ncg = (ncol + 3) >> 2;
     const int units = a.npairs * ngr * ncg;
-    // operands of unit u, r in [r0, r0 + 16): 4 vectors each (zero past r1p or outside)
-    auto load = [&](int u, int r0, f32x4* av, f32x4* bv, int* r1p_out) {
+    const int Hy = a.My / 2 + 1;
+    if (a.tk_r1max <= 32) {
+      tk_tile_spectra_r32(xt, a, tile, ncol, lane, wave, nwave, ngr, ncg, units, Hy);
+      return;
+    }
+    struct Ops {
+      float av[16];
+      f32x4 bv[4];
+      int r1q;
+    };
+    // operands of the pass (unit u, r in [r0, r0 + 16)) through buffer views, zero past
+    // r1 or outside the tile (T2 offsets past the row or for absent columns are sent out
+    // of range; U1t is zero filled)
+    auto load = [&](int u, int r0, Ops& o) {
       const int q = u / (ngr * ncg);
       const int rem = u - q * ngr * ncg;
       const int g = rem / ncg, cg = rem - g * ncg;
-      const TkPairDev tp = a.tk[q];
-      const int row = g * 64 + lane;
-      const bool aok = row < a.Hx;
+      const TkPairDev tp = tk_entry(a.tk, q);
+      const int hxp = __builtin_amdgcn_readfirstlane(tp.hxp);
+      const Buf ub = make_buf(uniform_ptr(tp.U1t), (uint32_t)__builtin_amdgcn_readfirstlane(tp.r1q * hxp * 4));
+      const uint32_t ho = (uint32_t)hxp * 4u;
+      uint32_t uo = ((uint32_t)__builtin_amdgcn_readfirstlane(r0 * hxp + g * 64) + (uint32_t)lane) * 4u;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        o.av[k] = bld1<float>(ub, uo);
+        uo += ho;
+      }
       const int colb = cg * 4 + (lane & 3);
       const int colq = tile * ncol + colb;
       const bool bok = colb < ncol && colq < ncols;
       const int jq = bok ? colq / a.H : 0, kzq = bok ? colq - jq * a.H : 0;
-      const f32x4* __restrict__ u1 =
-          reinterpret_cast<const f32x4*>(static_cast<const float*>(tp.U1) + (int64_t)(aok ? row : 0) * tp.r1p);
-      const f32x4* __restrict__ t2 = reinterpret_cast<const f32x4*>(
-          static_cast<const float*>(tp.T2) + ((int64_t)min(jq, a.My - jq) * a.H + kzq) * tp.r1p);
-      const int nv = tp.r1p >> 2;
+      const int r1p = __builtin_amdgcn_readfirstlane(tp.r1p);
+      const Buf tb = make_buf(uniform_ptr(tp.T2), (uint32_t)__builtin_amdgcn_readfirstlane(Hy * a.H * r1p * 4));
+      const uint32_t to = ((uint32_t)(min(jq, a.My - jq) * a.H + kzq) * (uint32_t)r1p + (uint32_t)r0) * 4u;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const int v = (r0 >> 2) + k;
-        const bool in = v < nv;
-        const int vc = in ? v : nv - 1;   // clamped: every address stays inside the row
-        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-        av[k] = (in && aok) ? u1[vc] : z;
-        bv[k] = (in && bok) ? t2[vc] : z;
+        const bool in = bok && r0 + 4 * k < tp.r1p;
+        o.bv[k] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(tb.r, in ? to + 16u * k : kOob, 0, 0));
       }
-      *r1p_out = tp.r1p;
+      o.r1q = tp.r1q;
     };
-    // passes (unit, r0) of this wave: units wave, wave + nwave, ...; r0 = 0, 16, ... < r1p
-    f32x4 av[4], bv[4], acc = {0.f, 0.f, 0.f, 0.f};
-    int u = wave, r0 = 0, r1p = 4;
-    if (u < units) load(u, 0, av, bv, &r1p);
-    while (u < units) {
-      int un = u, rn = r0 + 16, r1pn = r1p;
-      if (rn >= r1p) { un = u + nwave; rn = 0; }
-      f32x4 an[4], bn[4];
-      if (un < units) load(un, rn, an, bn, &r1pn);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    // one pass: 16 rank-one updates; the unit's block goes to LDS after its last pass
+    auto run = [&](const Ops& o, int u, int r0, bool last) {
       if (r0 == 0) acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_4x4x1f32(av[k][e], bv[k][e], acc, 0, 0, 0);
+        for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_4x4x1f32(o.av[4 * k + e], o.bv[k][e], acc, 0, 0, 0);
       }
-      if (rn == 0) {   // this unit is complete
+      if (last) {
         const int q = u / (ngr * ncg);
         const int rem = u - q * ngr * ncg;
         const int g = rem / ncg, cg = rem - g * ncg;
@@ -357,11 +491,33 @@ __device__ __forceinline__ void tk_tile_spectra(T* __restrict__ xt, const SandAr
           }
         }
       }
-      u = un;
-      r0 = rn;
-      r1p = r1pn;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) { av[k] = an[k]; bv[k] = bn[k]; }
+    };
+    // passes of this wave: units wave, wave + nwave, ..., each r0 = 0, 16, ... < r1q.
+    // Two operand sets in turn: the loads of the next pass are in flight while the
+    // current pass runs; they are issued unconditionally (the last repeats a valid
+    // pass) so the wait before each pass covers only that pass's loads.
+    if (wave < units) {
+      Ops A, B;
+      int u = wave, r0 = 0;
+      load(u, r0, A);
+      for (;;) {
+        int u1 = u, r1 = r0 + 16;
+        if (r1 >= A.r1q) { u1 = u + nwave; r1 = 0; }
+        const bool more1 = u1 < units;
+        load(more1 ? u1 : u, more1 ? r1 : r0, B);
+        run(A, u, r0, r1 == 0);
+        if (!more1) break;
+        u = u1;
+        r0 = r1;
+        int u2 = u, r2 = r0 + 16;
+        if (r2 >= B.r1q) { u2 = u + nwave; r2 = 0; }
+        const bool more2 = u2 < units;
+        load(more2 ? u2 : u, more2 ? r2 : r0, A);
+        run(B, u, r0, r2 == 0);
+        if (!more2) break;
+        u = u2;
+        r0 = r2;
+      }
     }
   } else {
     // FP64 (the refinement's residual products) on the vector units, 16-byte loads

@@ -288,7 +288,7 @@ vc_status build_spectra(vc_problem* P, int want64, int want32, double tucker_tol
     // resident: every device buffer of the Tucker form (cores and factors in FP64 and
     // FP32, the padded U1 copies) and the rebuild's T1 / T2 strips
     for (const TuckerPair& tp : P->tk) {
-      P->spectra_bytes += (double)(tp.S64.bytes + tp.S32.bytes + tp.U1p64.bytes + tp.U1p32.bytes);
+      P->spectra_bytes += (double)(tp.S64.bytes + tp.S32.bytes + tp.U1p64.bytes + tp.U1t32.bytes);
       for (int m = 0; m < 3; ++m) P->spectra_bytes += (double)(tp.U64[m].bytes + tp.U32[m].bytes);
     }
     P->spectra_bytes += (double)(P->tk_T1.bytes + P->tk_T2[0].bytes + P->tk_T2[1].bytes);

@@ -158,22 +158,25 @@ vc_status tucker_compress_pair(vc_problem* P, const double* X, hipStream_t st) {
     VC_HIP(tp.U32[m].alloc((size_t)nu * sizeof(float)));
     VC_HIP(launch_to_f32(tp.U64[m].as<double>(), tp.U32[m].as<float>(), nu, st));
   }
-  // U1 with rows padded to a multiple of 4 (FP64 and FP32) for the fused x pass
+  // U1 for the fused x pass: FP64 with rows padded to a multiple of 4, FP32 transposed
+  // with r1 padded to a multiple of 16 and Hx to a multiple of 64 (zero filled)
   const int r1 = tp.r[0];
   tp.r1p = (r1 + 3) & ~3;
+  tp.r1q = (r1 + 15) & ~15;
+  tp.hxp = (D[0] + 63) & ~63;
   std::vector<double> u((size_t)D[0] * r1), u64((size_t)D[0] * tp.r1p, 0.0);
   VC_HIP(hipMemcpyAsync(u.data(), tp.U64[0].p, u.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   VC_HIP(hipStreamSynchronize(st));
-  std::vector<float> u32(u64.size(), 0.0f);
+  std::vector<float> u32t((size_t)tp.r1q * tp.hxp, 0.0f);
   for (int x = 0; x < D[0]; ++x)
     for (int a = 0; a < r1; ++a) {
       u64[(size_t)x * tp.r1p + a] = u[(size_t)x * r1 + a];
-      u32[(size_t)x * tp.r1p + a] = (float)u[(size_t)x * r1 + a];
+      u32t[(size_t)a * tp.hxp + x] = (float)u[(size_t)x * r1 + a];
     }
   VC_HIP(tp.U1p64.alloc(u64.size() * sizeof(double)));
-  VC_HIP(tp.U1p32.alloc(u32.size() * sizeof(float)));
+  VC_HIP(tp.U1t32.alloc(u32t.size() * sizeof(float)));
   VC_HIP(hipMemcpy(tp.U1p64.p, u64.data(), u64.size() * sizeof(double), hipMemcpyHostToDevice));
-  VC_HIP(hipMemcpy(tp.U1p32.p, u32.data(), u32.size() * sizeof(float), hipMemcpyHostToDevice));
+  VC_HIP(hipMemcpy(tp.U1t32.p, u32t.data(), u32t.size() * sizeof(float), hipMemcpyHostToDevice));
   return VC_OK;
 }
 
@@ -202,7 +205,10 @@ vc_status tucker_end(vc_problem* P) {
     std::vector<TkPairDev> v(P->tk.size());
     for (size_t q = 0; q < P->tk.size(); ++q) {
       const TuckerPair& tp = P->tk[q];
-      v[q].U1 = f64 ? tp.U1p64.p : tp.U1p32.p;
+      v[q].U1 = tp.U1p64.p;
+      v[q].U1t = tp.U1t32.p;
+      v[q].r1q = tp.r1q;
+      v[q].hxp = tp.hxp;
       v[q].T2 = f64 ? (const void*)(P->tk_T2[1].as<double>() + P->tk_o2[q])
                     : (const void*)(P->tk_T2[0].as<float>() + P->tk_o2[q]);
       v[q].r1 = tp.r[0];

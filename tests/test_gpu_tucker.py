@@ -46,15 +46,16 @@ def test_tucker_product_matches_dense(dev, name, make, tol):
     print(name, tol, "ranks", info["ranks"], "CR", info["compression_ratio"], flush=True)
     assert info["npairs"] == (15 if P.n_diel else 6)
     # nothing of the size of the spectra is resident: exactly the cores and factors (FP64
-    # and FP32, U1 in FP64 only), the copies of U1 with rows padded to r1p = r1 rounded
-    # up to 4 (both precisions), the strip T1 (r1 r2 x H, FP64 elements) and T2
-    # (Hy x H x r1p) in each precision
+    # and FP32, U1 in FP64 only), the FP64 copy of U1 with rows padded to r1p = r1
+    # rounded up to 4, the FP32 copy transposed with r1 rounded up to 16 and Hx to 64,
+    # the strip T1 (r1 r2 x H, FP64 elements) and T2 (Hy x H x r1p) in each precision
     Mx, My, Mz = P.fft_size()
     Hx, Hy, H = Mx // 2 + 1, My // 2 + 1, Mz // 2 + 1
     expect = 0.0
     for r1, r2, r3 in info["ranks"]:
         r1p = (r1 + 3) // 4 * 4
-        expect += (r1 * r2 * r3 + Hy * r2 + H * r3) * 12.0 + Hx * r1 * 8.0 + Hx * r1p * 12.0
+        r1q, hxp = (r1 + 15) // 16 * 16, (Hx + 63) // 64 * 64
+        expect += (r1 * r2 * r3 + Hy * r2 + H * r3) * 12.0 + Hx * r1 * 8.0 + Hx * r1p * 8.0 + r1q * hxp * 4.0
         expect += r1 * r2 * H * 8.0 + Hy * H * r1p * 12.0
     resident = P.spectra_bytes()
     print(name, tol, f"resident {resident:.0f} B, uncompressed {info['full_numbers'] * 12:.0f} B", flush=True)
