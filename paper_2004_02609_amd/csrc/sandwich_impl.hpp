@@ -767,12 +767,16 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
         }
       }
     };
-    if (valid) load_spectra(0);
+    // stored spectra come from HBM and are loaded one output component ahead; the fused
+    // form's come from LDS and are loaded just before their use (no registers held
+    // through the inverse transforms)
+    if (valid && !FU) load_spectra(0);
 #pragma unroll 1
     for (int o = 0; o < NOUT; ++o) {
       const int oax = NIN == 3 ? (o < 3 ? o : o - 3) : o;
       C2<T> z[RS];
       if (valid) {
+        if (FU) load_spectra(o);
 #pragma unroll
         for (int m = 0; m < RS; ++m) {
           C2<T> acc = {T(0), T(0)};
@@ -800,7 +804,7 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
           // output phase: conj of the half-voxel shift of the output component
           z[m] = oax == 0 ? cmul(acc, cconj(phase_x(m))) : acc;
         }
-        if (o + 1 < NOUT) load_spectra(o + 1);
+        if (!FU && o + 1 < NOUT) load_spectra(o + 1);
       }
       const int msk = NIN == 3 ? (o < 3 ? 1 : 2) : 3;
       const Buf dst = make_buf(Fout + o * a.comp_stride + rhs * a.rhs_stride, slab);
