@@ -356,10 +356,17 @@ __device__ __forceinline__ void tk_tile_spectra_r32(float* __restrict__ xt, cons
     const Buf ub = make_buf(uniform_ptr(tp.U1t), (uint32_t)__builtin_amdgcn_readfirstlane(tp.r1q * hxp * 4));
     const uint32_t ho = (uint32_t)hxp * 4u;
     uint32_t uo = ((uint32_t)__builtin_amdgcn_readfirstlane(g * 64) + (uint32_t)lane) * 4u;
+    // rows of the 8-rank chunks the pair's r1 reaches (the others are never used)
+    const int nch = __builtin_amdgcn_readfirstlane((tp.r1 + 7) >> 3);
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-      av[k] = bld1<float>(ub, uo);
-      uo += ho;
+    for (int cc = 0; cc < 4; ++cc) {
+      if (cc == 0 || cc < nch) {
+#pragma unroll
+        for (int k = 8 * cc; k < 8 * cc + 8; ++k) {
+          av[k] = bld1<float>(ub, uo);
+          uo += ho;
+        }
+      }
     }
   };
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
