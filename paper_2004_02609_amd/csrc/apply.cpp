@@ -160,8 +160,11 @@ bool ypass_config(int L, int elem, int ncols, size_t budget, YArgs* a, int* nthr
 
 // Default without timing: fewest stages, then the largest register radix, then the
 // widest power-of-two tile of at most 256 threads (several workgroups per CU), else
-// the narrowest.  (Tiles of other widths are left to the autotuner: they fill waves
-// better but their gains and losses depend on the shape.)
+// the narrowest.  The Tucker-fused form takes the widest power-of-two tile up to 4
+// columns instead: its matrix-core build handles 4 columns per unit and reads the
+// factor U1 once per tile, so narrower tiles pay for it again per column (meander:
+// 3.1 ms at 4 columns, 5.3 ms at 1).  (Tiles of other widths are left to the autotuner:
+// they fill waves better but their gains and losses depend on the shape.)
 bool sandwich_default(int L, int elem, int nin, int n1x, size_t budget, SandCfg* cfg, int tk_npairs, int Hx) {
   const std::vector<SandCfg> cand = sandwich_candidates(L, elem, nin, n1x, budget, tk_npairs, Hx);
   int best = -1;
@@ -172,7 +175,7 @@ bool sandwich_default(int L, int elem, int nin, int n1x, size_t budget, SandCfg*
     const int rs = (int)((g.radpack >> (5 * (g.nst - 1))) & 31u);
     int lg = 0;
     while ((1 << (lg + 1)) <= g.ncol) ++lg;
-    const double fit = g.nthr <= 256 ? 10.0 * lg : -10.0 * lg;
+    const double fit = tk_npairs > 0 ? (g.ncol <= 4 ? 10.0 * lg : -10.0 * lg) : (g.nthr <= 256 ? 10.0 * lg : -10.0 * lg);
     const double score = -1e6 * g.nst + 1e3 * rs + fit;
     if (score > bscore) { bscore = score; best = (int)k; }
   }
@@ -234,7 +237,10 @@ static vc_status y_pass(vc_problem* P, PrecTables& tb, void* data, void* scratch
   const int key = (nrhs << 3) | (transpose << 2) | (inverse << 1) | (sizeof(T) == 8 ? 1 : 0);
   auto it = P->y_choice.find(key);
   if (it == P->y_choice.end()) {
-    vc_problem::YChoice ch{(yok && ydef * eb >= 32) ? 1 : 0, false, {0.0, 0.0}, 0, 1};
+    // untimed default: the register-edge kernel, its tiles narrower than a 128-byte
+    // line in whole-row XCD groups (the tiles sharing a line read it from one L2); on
+    // meander (16-byte tiles) it takes 0.46 ms against 1.28 ms for the LDS tiles
+    vc_problem::YChoice ch{yok ? 1 : 0, false, {0.0, 0.0}, 0, (yok && ydef * eb < 128) ? -1 : 1};
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     VC_HIP(hipStreamIsCapturing(st, &cap));
     if (P->autotune && yok && cap == hipStreamCaptureStatusNone) {

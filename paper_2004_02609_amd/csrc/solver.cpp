@@ -138,6 +138,7 @@ vc_status col_norms(vc_problem* P, const double* w, int64_t N, int nrhs, double*
 // residual, and a cycle whose columns all converge early stops issuing steps:
 //   part 0:            residual and its norms, cycle start (masks, g, skip flags),
 //                      V_0 = r / |r|;
+//   part -1:           the same for a zero x (r = b, no product: a solve's first cycle);
 //   parts 1..nseg:     Arnoldi steps [kCycleSeg (part - 1), kCycleSeg part) with
 //                      classical Gram-Schmidt applied twice and the Givens update;
 //   part nseg + 1:     x += R V y for the columns that were active at the start.
@@ -159,9 +160,14 @@ vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, doubl
   const int64_t ldv = (int64_t)nrhs * N;
   const int ldh = m + 2;
   vc_status s;
-  if (part == 0) {
-    s = residual(P, sp, b, x, r, nrhs, st, c.skip + 2);
-    if (s != VC_OK) return s;
+  if (part == 0 || part == -1) {
+    if (part == 0) {
+      s = residual(P, sp, b, x, r, nrhs, st, c.skip + 2);
+      if (s != VC_OK) return s;
+    } else {
+      VC_HIP(launch_zero(r, (int64_t)nrhs * N, st));
+      VC_HIP(launch_axpy_cols(r, b, N, nrhs, nullptr, 1, st, c.skip + 2));   // r = b - 0
+    }
     VC_HIP(launch_colnorm(r, N, N, nrhs, c.rn, P->ws.partial, st, c.skip + 2));
     VC_HIP(launch_cycle_start(nrhs, m, c.rn, c.bn, c.rtol, c.act_cycle, c.act_step, c.g, c.scal, c.kd, c.skip, c.rre,
                               st));
@@ -211,8 +217,10 @@ vc_status cycle_graph(vc_problem* P, const SolveSpec& sp, const double* b, doubl
       *e_out = e.exec;
       return VC_OK;
     }
-  vc_status s = apply_op(P, sp.transpose, sp.mvp, b, P->ws.tmp, nrhs, st);
-  if (s != VC_OK) return s;
+  if (part != -1) {   // (part -1 has no product)
+    vc_status s = apply_op(P, sp.transpose, sp.mvp, b, P->ws.tmp, nrhs, st);
+    if (s != VC_OK) return s;
+  }
   VC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   vc_status sc = issue_cycle(P, sp, b, x, nrhs, st, part);
   hipGraph_t gr = nullptr;
@@ -258,7 +266,7 @@ static vc_status run_part(vc_problem* P, const SolveSpec& sp, const double* b, d
 // and does not halve the largest true residual sends the rest of the solve to FP64.
 // steps32: Arnoldi steps taken with FP32 products (largest over columns, per segment).
 vc_status gmres(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs,
-                       std::vector<int>& iters, std::vector<double>& rre, hipStream_t st, int* steps32) {
+                       std::vector<int>& iters, std::vector<double>& rre, hipStream_t st, int* steps32, bool x_zero) {
   const int64_t N = npanels(P);
   const int m = sp.restart;
   vc_status s = ensure_workspace(P, nrhs, m);
@@ -287,9 +295,9 @@ vc_status gmres(vc_problem* P, const SolveSpec& sp, const double* b, double* x, 
     std::copy(now, now + nrhs, it_seg.begin());
   };
   std::vector<int> itv(nrhs);
-  // start of the first cycle; each later round runs the previous cycle's steps and
-  // the next cycle's start before one host read-back
-  s = run_part(P, sp, b, x, nrhs, st, 0);
+  // start of the first cycle (x = 0 given: r = b without a product); each later round
+  // runs the previous cycle's steps and the next cycle's start before one host read-back
+  s = run_part(P, sp, b, x, nrhs, st, x_zero ? -1 : 0);
   if (s != VC_OK) return s;
   const int nseg = cycle_segments(m);
   for (int cycle = 0;; ++cycle) {
@@ -407,7 +415,7 @@ vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const doub
   if (o.prec != VC_MIXED) {
     sp.mvp = o.prec == VC_FP32 ? VC_FP32 : VC_FP64;
     sp.rtol = o.rtol;
-    s = gmres(P, sp, b, x, nrhs, it, rre, st, &n32);
+    s = gmres(P, sp, b, x, nrhs, it, rre, st, &n32, true);   // x was zeroed above
   } else if (form == VC_MIXED_RELAXED) {
     // one GMRES on the FP64 system: FP64 residuals at the restarts, FP32 Arnoldi
     // products once the residual estimate is below rtol / inner_rtol (an FP32 product's
@@ -416,7 +424,7 @@ vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const doub
     sp.rtol = o.rtol;
     sp.relax = 1;
     sp.relax_thr = o.rtol / o.inner_rtol;
-    s = gmres(P, sp, b, x, nrhs, it, rre, st, &n32);
+    s = gmres(P, sp, b, x, nrhs, it, rre, st, &n32, true);
   } else {
     // outer FP64 refinement: r = b - A x (FP64 product), inner FP32 GMRES on A d = r, x += d
     s = ensure_workspace(P, nrhs, o.restart);
@@ -442,7 +450,7 @@ vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const doub
       s32.max_iter = std::min(o.max_iter, 4 * o.restart);
       VC_HIP(hipMemsetAsync(ddp, 0, (size_t)nrhs * N * sizeof(double), st));
       int k32 = 0;
-      vc_status si = gmres(P, s32, rrp, ddp, nrhs, it, rre, st, &k32);
+      vc_status si = gmres(P, s32, rrp, ddp, nrhs, it, rre, st, &k32, true);   // ddp zeroed above
       if (si != VC_OK && si != VC_ERR_NOT_CONVERGED) return si;
       n32 += k32;
       for (int c = 0; c < nrhs; ++c) tot[c] += it[c];

@@ -44,7 +44,7 @@ vc_status issue_cycle(vc_problem* P, const SolveSpec& sp, const double* b, doubl
 vc_status cycle_graph(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs, hipStream_t st,
                       int part, hipGraph_t* g_out, hipGraphExec_t* e_out);
 vc_status gmres(vc_problem* P, const SolveSpec& sp, const double* b, double* x, int nrhs, std::vector<int>& iters,
-                std::vector<double>& rre, hipStream_t st, int* steps32 = nullptr);
+                std::vector<double>& rre, hipStream_t st, int* steps32 = nullptr, bool x_zero = false);
 hipStream_t get_solve_stream(vc_problem* P);
 vc_status solve(vc_problem* P, const vc_solve_opts& o, int transpose, const double* b, double* x, int nrhs,
                 vc_stats* stats, hipStream_t st, std::vector<int>* it_out = nullptr,
