@@ -714,24 +714,45 @@ int64_t cgs_partial_size(int64_t N, int kmax, int nrhs) {
 // out[i] = sum over the chunk's rows t < rows of V_i[n0 + t] wl[t] for i < k, with the
 // chunk of w in LDS (wl).  Wave v takes the basis vectors in groups of kCgsGroup:
 // [G v, G v + G), then G nw further on, and so on; each lane adds the rows lane,
-// lane + 64, ... in order, then one wave reduction per vector (no cross-wave step).
+// lane + 128, ... and lane + 64, lane + 192, ... in two sums (two rows' loads of every
+// vector in flight per iteration), then one wave reduction per vector (no cross-wave
+// step).
 constexpr int kCgsGroup = 4;
 __device__ __forceinline__ void chunk_dots(const double* __restrict__ vr, int64_t ldv, int64_t n0, int rows, int k,
                                            const double* __restrict__ wl, double* __restrict__ out) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int i0 = wv * kCgsGroup; i0 < k; i0 += nw * kCgsGroup) {
-    double acc[kCgsGroup];
+    double acc[kCgsGroup], acc2[kCgsGroup];
+    const double* vq[kCgsGroup];
 #pragma unroll
-    for (int q = 0; q < kCgsGroup; ++q) acc[q] = 0.0;
-    for (int t = lane; t < rows; t += 64) {
+    for (int q = 0; q < kCgsGroup; ++q) {
+      acc[q] = 0.0;
+      acc2[q] = 0.0;
+      vq[q] = vr + (int64_t)(i0 + q < k ? i0 + q : i0) * ldv + n0;   // (an absent vector reads a present one)
+    }
+    int t = lane;
+    for (; t + 64 < rows; t += 128) {
+      const double wt = wl[t], wt2 = wl[t + 64];
+      double a[kCgsGroup], b[kCgsGroup];
+#pragma unroll
+      for (int q = 0; q < kCgsGroup; ++q) {
+        a[q] = vq[q][t];
+        b[q] = vq[q][t + 64];
+      }
+#pragma unroll
+      for (int q = 0; q < kCgsGroup; ++q) {
+        acc[q] += a[q] * wt;
+        acc2[q] += b[q] * wt2;
+      }
+    }
+    if (t < rows) {
       const double wt = wl[t];
 #pragma unroll
-      for (int q = 0; q < kCgsGroup; ++q)
-        if (i0 + q < k) acc[q] += vr[(int64_t)(i0 + q) * ldv + n0 + t] * wt;
+      for (int q = 0; q < kCgsGroup; ++q) acc[q] += vq[q][t] * wt;
     }
 #pragma unroll
     for (int q = 0; q < kCgsGroup; ++q) {
-      const double sum = wave_sum(acc[q]);
+      const double sum = wave_sum(acc[q] + acc2[q]);
       if (lane == 0 && i0 + q < k) out[i0 + q] = sum;
     }
   }
@@ -817,6 +838,7 @@ k_cgs_update_dot(const double* __restrict__ V, int64_t ldv, int64_t N, int64_t c
   for (int t = threadIdx.x; t < rows; t += blockDim.x) {
     const int64_t n = n0 + t;
     double acc = 0.0;
+#pragma unroll 4
     for (int i = 0; i < k; ++i) acc += vr[(int64_t)i * ldv + n] * hr[i];
     const double wn = wr[n] - acc;
     wr[n] = wn;
@@ -850,6 +872,7 @@ k_cgs_update_norm_step(const double* __restrict__ V, int64_t ldv, int64_t N, int
     double sq = 0.0;
     for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
       double acc = 0.0;
+#pragma unroll 4
       for (int i = 0; i < k; ++i) acc += vr[(int64_t)i * ldv + n] * hr[i];
       const double wn = wr[n] - acc;
       wr[n] = wn;
