@@ -530,6 +530,11 @@ def main():
                          "--calib-copy-mib into profiles/traffic_<config>_<prec>.json, then exit")
     ap.add_argument("--oracle-table", action="store_true",
                     help="(no GPU) time the FP64 oracle's assembly, LU and dense product on this host, then exit")
+    ap.add_argument("--solve-once", choices=["mixed", "fp64"],
+                    help="set the workload up, run one untimed and one timed capacitance solve in this precision "
+                         "(rtol --solve-rtol), print its time and iterations as one JSON line, then exit (the last "
+                         "solve of the run is the timed one, e.g. for a kernel trace)")
+    ap.add_argument("--solve-rtol", type=float, default=1e-7)
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(args)
@@ -572,6 +577,16 @@ def main():
     x = torch.randn(B, N, dtype=torch.float64, device=dev, generator=g)
     y = torch.empty_like(x)
     log(f"# {args.config}: N={N} m={B} fft={P.fft_size()} tucker_tol={tucker_tol:g} setup {t_setup:.2f}s")
+    if args.solve_once:
+        P.capacitance(prec=args.solve_once, rtol=args.solve_rtol)   # captures the cycle graphs
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = P.capacitance(prec=args.solve_once, rtol=args.solve_rtol)
+        torch.cuda.synchronize()
+        print(json.dumps({"config": args.config, "prec": args.solve_once, "rtol": args.solve_rtol,
+                          "time_s": time.perf_counter() - t0, "iters": st["iters"], "ir_steps": st["ir_steps"],
+                          "mixed_form": st["mixed_form"], "steps_fp32": st["steps_fp32"]}), flush=True)
+        return
 
     # the step: timed with events around the x pass on every `every`-th step
     every = max(1, min(10, args.steps // 10))
