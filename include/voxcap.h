@@ -334,8 +334,11 @@ vc_status vc_tuning_report(vc_problem *p, char *buf, int32_t len);
 
 /* Launch configurations of the x pass available for a precision and direction, as
  * rows of 8 int32: {nst, r_0, ..., r_5, cols} (radices r_0 >= ... >= r_{nst-1}, unused
- * ones 0; cols = columns per workgroup).  Writes at most max_rows rows to out and the
- * number available to *n_rows.  Requires vc_setup. */
+ * ones 0; cols = columns per workgroup).  With stored (uncompressed) spectra, cols < 0
+ * is the staged form of |cols| columns: one workgroup per column tile copies the tile's
+ * stored spectra into LDS once and runs every right-hand side against them (cols > 0:
+ * one workgroup per tile and right-hand side, spectra read from memory).  Writes at
+ * most max_rows rows to out and the number available to *n_rows.  Requires vc_setup. */
 vc_status vc_xpass_candidates(vc_problem *p, vc_precision prec, int transpose, int32_t *out,
                               int32_t max_rows, int32_t *n_rows);
 

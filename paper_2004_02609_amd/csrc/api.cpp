@@ -578,14 +578,14 @@ vc_status vc_xpass_candidates(vc_problem* p, vc_precision prec, int transpose, i
   if (prec != VC_FP64 && prec != VC_FP32) { set_error("prec must be VC_FP64 or VC_FP32"); return VC_ERR_ARG; }
   const int elem = prec == VC_FP32 ? 4 : 8;
   const int nin = (transpose && p->n_diel > 0) ? 6 : 3;
-  const std::vector<vc::SandCfg> cand = vc::sandwich_candidates(p->M[0], elem, nin, p->n1[0], vc::kLdsBudget, (int)p->tk.size(), p->Hx);
+  const std::vector<vc::SandCfg> cand = vc::xpass_candidate_list(p, elem, nin);
   *n_rows = (int32_t)cand.size();
   for (int32_t r = 0; r < (int32_t)cand.size() && r < max_rows; ++r) {
     int32_t* row = out + 8 * r;
     for (int k = 0; k < 8; ++k) row[k] = 0;
     row[0] = cand[r].nst;
     for (int s2 = 0; s2 < cand[r].nst; ++s2) row[1 + s2] = (int32_t)((cand[r].radpack >> (5 * s2)) & 31u);
-    row[7] = cand[r].ncol;
+    row[7] = cand[r].stage ? -cand[r].ncol : cand[r].ncol;   // negative: the staged form
   }
   return VC_OK;
 }
@@ -597,15 +597,16 @@ vc_status vc_xpass_set(vc_problem* p, vc_precision prec, int transpose, int32_t 
   if (prec != VC_FP64 && prec != VC_FP32) { set_error("prec must be VC_FP64 or VC_FP32"); return VC_ERR_ARG; }
   const int elem = prec == VC_FP32 ? 4 : 8;
   const int nin = (transpose && p->n_diel > 0) ? 6 : 3;
-  const std::vector<vc::SandCfg> cand = vc::sandwich_candidates(p->M[0], elem, nin, p->n1[0], vc::kLdsBudget, (int)p->tk.size(), p->Hx);
+  const std::vector<vc::SandCfg> cand = vc::xpass_candidate_list(p, elem, nin);
   for (const vc::SandCfg& g : cand) {
-    bool same = cfg[0] == g.nst && cfg[7] == g.ncol;
+    bool same = cfg[0] == g.nst && cfg[7] == (g.stage ? -g.ncol : g.ncol);
     for (int s2 = 0; s2 < 6 && same; ++s2)
       same = cfg[1 + s2] == (s2 < g.nst ? (int32_t)((g.radpack >> (5 * s2)) & 31u) : 0);
     if (!same) continue;
     const int t = (transpose && p->n_diel > 0) ? 1 : 0;   // without dielectric rows A is symmetric
     const int key = (nrhs << 2) | (t << 1) | (elem == 8 ? 1 : 0);
     p->sand_choice[key] = vc_problem::SandChoice{g.nst, g.tl, g.ncol, g.nthr, g.radpack, false, 0.0, 0.0};
+    p->sand_choice[key].stage = g.stage;
     return VC_OK;
   }
   set_error("not an x-pass configuration of this problem (see vc_xpass_candidates)");
@@ -642,9 +643,9 @@ vc_status vc_tuning_report(vc_problem* p, char* buf, int32_t len) {
       if (s) rad += "x";
       rad += std::to_string((int)((c.radpack >> (5 * s)) & 31u));
     }
-    std::snprintf(line, sizeof line, "x-pass %s %s nrhs=%d radices=%s cols=%d threads=%d %s", (kv.first & 1) ? "fp64" : "fp32",
+    std::snprintf(line, sizeof line, "x-pass %s %s nrhs=%d radices=%s cols=%d threads=%d%s %s", (kv.first & 1) ? "fp64" : "fp32",
                   (kv.first & 2) ? "transpose" : "forward", kv.first >> 2, rad.c_str(), c.ncol, c.nthr,
-                  c.from_file ? "cached" : (c.tuned ? "tuned" : "default"));
+                  c.stage ? " staged" : "", c.from_file ? "cached" : (c.tuned ? "tuned" : "default"));
     out += line;
     if (c.tuned) {
       std::snprintf(line, sizeof line, " best_ms=%.4f default_ms=%.4f", c.ms_best, c.ms_default);

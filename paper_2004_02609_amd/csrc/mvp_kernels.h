@@ -120,6 +120,10 @@ struct SandArgs {
   const TkPairDev* tk;
   int npairs;
   int tk_r1max;   // largest x-mode rank r1 over the pairs
+  // staged form (stored spectra, tk null): one workgroup per tile copies the tile's
+  // stored spectra of the npairs pairs into LDS once and runs every right-hand side
+  // against them (the fused form's structure, with a copy in place of the build)
+  int stage;
 };
 // dynamic LDS of the sandwich: twiddle table (+ the x phases in FP32) + one [L][ncol]
 // tile + 3 n1x plane flags
@@ -197,6 +201,7 @@ hipError_t launch_sandwich(const void* Fin, void* Fout, const void* R, const San
 struct SandCfg {
   int nst, tl, ncol, nthr;
   uint32_t radpack;
+  int stage = 0;   // the staged form of the stored spectra (SandArgs::stage)
 };
 // one sandwich variant (NIN input / NOUT output components, TK: Tucker-fused), last-stage
 // radix rs

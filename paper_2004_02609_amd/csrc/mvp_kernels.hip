@@ -416,10 +416,15 @@ bool sandwich_args_ok(const SandArgs& a, int nthr) {
   if ((uint64_t)a.n1x * a.My * a.H * 2 * sizeof(T) > 0xFFFFFF00ull ||
       (!a.tk && (uint64_t)a.pair_stride * sizeof(T) > 0xFFFFFF00ull))
     return false;
-  // the fused form: its stored pairs, and the tile's spectra within the device's LDS
-  if (a.tk && (a.npairs < 1 || a.npairs > 15 ||
-               sandwich_tk_lds_bytes(a.Mx, a.ncol, (int)sizeof(T), a.n1x, a.npairs, a.Hx) > lds_ext_budget()))
+  // the fused and staged forms: their stored pairs, and the tile's spectra within the
+  // device's LDS (the staged form copies the stored octants: all npairs of them in the
+  // buffer view, whose byte size must fit the view's 32-bit range)
+  if (a.tk && a.stage) return false;
+  if ((a.tk || a.stage) &&
+      (a.npairs < 1 || a.npairs > 15 ||
+       sandwich_tk_lds_bytes(a.Mx, a.ncol, (int)sizeof(T), a.n1x, a.npairs, a.Hx) > lds_ext_budget()))
     return false;
+  if (a.stage && (uint64_t)a.npairs * a.pair_stride * sizeof(T) > 0xFFFFFF00ull) return false;
   return true;
 }
 
@@ -429,7 +434,7 @@ hipError_t launch_sandwich(const void* Fin, void* Fout, const void* R, const San
                            hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (!sandwich_args_ok<T>(a, nthr)) return hipErrorInvalidValue;
   const int rs = (int)((a.radpack >> (5 * (a.nst - 1))) & 31u);
-  if (a.tk) {
+  if (a.tk || a.stage) {
     const size_t lds = sandwich_tk_lds_bytes(a.Mx, a.ncol, (int)sizeof(T), a.n1x, a.npairs, a.Hx);
     if (!a.adjoint && a.nin == 3 && a.nout == 6)
       return launch_sandwich_v<T, 3, 6, 1>(Fin, Fout, R, a, tw, phx, pflag, nthr, lds, rs, st, e0, e1);

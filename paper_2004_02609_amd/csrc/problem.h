@@ -20,6 +20,10 @@ struct SandCfg;
 std::vector<SandCfg> sandwich_candidates(int L, int elem, int nin, int n1x, size_t budget, int tk_npairs = 0,
                                          int Hx = 0);
 bool sandwich_default(int L, int elem, int nin, int n1x, size_t budget, SandCfg* cfg, int tk_npairs = 0, int Hx = 0);
+// every x-pass configuration a problem's product can use in precision elem with nin
+// input components: the fused form's (Tucker spectra), or the per-RHS workgroups' and
+// then the staged form's (stored spectra; SandCfg::stage)
+std::vector<SandCfg> xpass_candidate_list(::vc_problem* p, int elem, int nin);
 
 // Owning device allocation.
 struct DevMem {
@@ -256,6 +260,7 @@ struct vc_problem {
     bool tuned;
     double ms_best, ms_default;
     bool from_file = false;   // read from a tuning cache (vc_tuning_load)
+    int stage = 0;            // the staged form (SandArgs::stage)
   };
   std::map<int, SandChoice> sand_choice;
   // y-pass kernel per (precision, direction, transposed product, nrhs) key:

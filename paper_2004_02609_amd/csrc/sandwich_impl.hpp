@@ -552,6 +552,51 @@ __device__ __forceinline__ void tk_tile_spectra(T* __restrict__ xt, const SandAr
   }
 }
 
+// The staged form's tile spectra: the stored octants of the npairs pairs at the tile's
+// columns copied into LDS (xt: [npairs][Hx][ncol], the fused form's layout), so every
+// right-hand side reads them from LDS and HBM delivers them once per tile.  Thread t
+// copies column t % ncol of the rows t / ncol, t / ncol + T, ... (T = threads / ncol)
+// over (pair, kx'), eight loads in flight before their stores; columns outside the grid
+// hold zero.  The caller synchronizes before reading xt.
+template <typename T>
+__device__ __forceinline__ void tk_stage_spectra(T* __restrict__ xt, const SandArgs& a, const T* __restrict__ R,
+                                                 int tile, int ncol) {
+  const int ncols = a.My * a.H;
+  const int rstep = (int)blockDim.x / ncol;
+  const int r0 = (int)threadIdx.x / ncol, c = (int)threadIdx.x - r0 * ncol;
+  if (r0 >= rstep) return;
+  const int col = tile * ncol + c;
+  const bool cok = col < ncols;
+  const int colc = cok ? col : 0;
+  const int ky = colc / a.H, kz = colc - ky * a.H;
+  const int kyp = min(ky, a.My - ky);
+  const Buf rb = make_buf(R, (uint32_t)((uint64_t)a.npairs * (uint64_t)a.pair_stride * sizeof(T)));
+  const uint32_t cofs = (uint32_t)(kyp * a.H + kz) * (uint32_t)sizeof(T);
+  const uint32_t rowb = (uint32_t)(a.Hy * a.H) * (uint32_t)sizeof(T);        // bytes per kx' row
+  const uint32_t pairb = (uint32_t)a.pair_stride * (uint32_t)sizeof(T);
+  const int rows = a.npairs * a.Hx;
+  int row = r0, q = r0 / a.Hx, kxp = r0 - (r0 / a.Hx) * a.Hx;
+  while (row < rows) {
+    T v[8];
+    int dst[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool in = row < rows;
+      v[u] = bld1<T>(rb, (in && cok) ? (uint32_t)q * pairb + (uint32_t)kxp * rowb + cofs : kOob);
+      dst[u] = in ? (q * a.Hx + kxp) * ncol + c : -1;
+      row += rstep;
+      kxp += rstep;
+      while (kxp >= a.Hx) {
+        kxp -= a.Hx;
+        ++q;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (dst[u] >= 0) xt[dst[u]] = v[u];
+  }
+}
+
 // one column tile of the pass for right-hand sides rhs0 .. rhs0 + nrhs_loop - 1; PID > 0
 // takes the plan from kSandFixed[PID] as compile-time constants (the launcher checks
 // that it is a.radpack's).
@@ -600,7 +645,10 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
     }
   }
   for (int t = tid; t < 3 * a.n1x; t += blockDim.x) sflag[t] = pflag[t];
-  if (FU) tk_tile_spectra<T>(reinterpret_cast<T*>(smem_raw), a, tile, ncol);
+  if (FU) {
+    if (a.tk) tk_tile_spectra<T>(reinterpret_cast<T*>(smem_raw), a, tile, ncol);
+    else tk_stage_spectra<T>(reinterpret_cast<T*>(smem_raw), a, R, tile, ncol);
+  }
   __syncthreads();
 
   // right-hand sides of this workgroup (one, except in the fused form)

@@ -94,7 +94,7 @@ vc_status vc_tuning_save(vc_problem* p, const char* path, int32_t* n_saved) {
     Entry e = shape_of(p, arch, kv.first);
     e.nst = c.nst;
     for (int s = 0; s < c.nst && s < 6; ++s) e.rad[s] = (int)((c.radpack >> (5 * s)) & 31u);
-    e.cols = c.ncol;
+    e.cols = c.stage ? -c.ncol : c.ncol;   // negative: the staged form
     e.ms = c.ms_best;
     mine.push_back(e);
   }
@@ -142,14 +142,15 @@ vc_status vc_tuning_load(vc_problem* p, const char* path, int32_t* n_loaded) {
     const int key = (e.nrhs << 2) | (e.transpose << 1) | (e.elem == 8 ? 1 : 0);
     if (!shape_of(p, arch, key).same_key(e)) continue;
     // accept it only as one of this problem's own candidates
-    const std::vector<SandCfg> cand = sandwich_candidates(p->M[0], e.elem, e.nin, p->n1[0], kLdsBudget, (int)p->tk.size(), p->Hx);
+    const std::vector<SandCfg> cand = xpass_candidate_list(p, e.elem, e.nin);
     for (const SandCfg& g : cand) {
-      bool same = e.nst == g.nst && e.cols == g.ncol;
+      bool same = e.nst == g.nst && e.cols == (g.stage ? -g.ncol : g.ncol);
       for (int s = 0; s < 6 && same; ++s)
         same = e.rad[s] == (s < g.nst ? (int)((g.radpack >> (5 * s)) & 31u) : 0);
       if (!same) continue;
       vc_problem::SandChoice ch{g.nst, g.tl, g.ncol, g.nthr, g.radpack, true, e.ms, 0.0};
       ch.from_file = true;
+      ch.stage = g.stage;
       p->sand_choice[key] = ch;
       ++count;
       break;

@@ -254,8 +254,9 @@ def test_ypass_xcd_groups_match_dense(dev):
 
 @pytest.mark.parametrize("name,make", XPASS_SCENES)
 def test_every_xpass_configuration_matches_dense(dev, name, make):
-    """Each launch configuration the autotuner may pick (radix plan x column tile) gives
-    the dense product of eq. (4), forward and transposed, in both precisions."""
+    """Each launch configuration the autotuner may pick (radix plan x column tile, per-RHS
+    workgroups or the staged form) gives the dense product of eq. (4), forward and
+    transposed, in both precisions."""
     s = make()
     P = _problem(s, max_rhs=2)
     A, po, perm = oracle_matrix_library_order(s, P.panels())
@@ -268,6 +269,8 @@ def test_every_xpass_configuration_matches_dense(dev, name, make):
             ref = ((A.T if transpose else A) @ x.T).T
             cands = P.xpass_candidates(prec, transpose)
             assert cands, (name, prec, transpose)
+            # stored spectra: the staged form (negative column count) is among them
+            assert any(c[7] < 0 for c in cands), (name, prec, transpose, cands)
             for cfg in cands:
                 nplans.add(cfg[0])
                 P.xpass_set(cfg, prec, transpose, nrhs=2)
