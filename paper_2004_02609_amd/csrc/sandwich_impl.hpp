@@ -831,6 +831,16 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
       const int oax = NIN == 3 ? (o < 3 ? o : o - 3) : o;
       C2<T> z[RS];
       if (valid) {
+        // the fused form's wide kernels load the output's half-voxel phases (x-normal
+        // outputs only) from global memory together before the multiply: one memory
+        // latency rather than one per frequency (the other kernels have no registers to
+        // spare for them, or read them from LDS)
+        constexpr bool PHO = FU && NIN == 3 && kSandFixed[PID].wide;
+        C2<T> pho[RS];
+        if (PHO && oax == 0) {
+#pragma unroll
+          for (int m = 0; m < RS; ++m) pho[m] = phase_x(m);
+        }
         if (FU) load_spectra(o);
 #pragma unroll
         for (int m = 0; m < RS; ++m) {
@@ -857,7 +867,7 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
             acc.y -= accE.x;
           }
           // output phase: conj of the half-voxel shift of the output component
-          z[m] = oax == 0 ? cmul(acc, cconj(phase_x(m))) : acc;
+          z[m] = oax == 0 ? cmul(acc, cconj(PHO ? pho[m] : phase_x(m))) : acc;
         }
         if (!FU && o + 1 < NOUT) load_spectra(o + 1);
       }
