@@ -605,7 +605,9 @@ __device__ __forceinline__ void tk_stage_spectra(T* __restrict__ xt, const SandA
 // into LDS (the x-mode product, from the factor U1 and the strip T2 = S x2 U2 x3 U3),
 // then runs every right-hand side against them; the twiddles and x phases are read from
 // their tables in global memory (the LDS holds the spectra instead).
-template <typename T, int NIN, int NOUT, int RS, int PID = 0, int TK = 0>
+// NC > 0: the tile width as a compile-time constant (must equal a.ncol), so the LDS and
+// HBM strides derived from it fold into the instructions.
+template <typename T, int NIN, int NOUT, int RS, int PID = 0, int TK = 0, int NC = 0>
 __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout,
                                               const T* __restrict__ R, const SandArgs& a,
                                               const C2<T>* __restrict__ twg, const C2<T>* __restrict__ phx,
@@ -619,7 +621,7 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
   constexpr SandFixedPlan PD = kSandFixed[PID];
   const int L = FX ? PD.L : a.Mx, tl = FX ? PD.L / RS : a.tl, S = FX ? PD.nst : a.nst;
   auto rad = [&](int s) -> int { return FX ? PD.r[s] : srad(a, s); };
-  int ncol = a.ncol;
+  int ncol = NC > 0 ? NC : a.ncol;
   uint32_t ncolpE = (uint32_t)ncol * E;   // unpadded rows: measured faster than a pitch of ncol + 1 or + 2
   // FP32 keeps the x half-voxel phases in LDS beside the twiddles; FP64 (whose tiles are
   // twice as large, and whose registers are full) reads them from the cached table
@@ -666,8 +668,9 @@ __device__ __forceinline__ void sandwich_body(const C2<T>* __restrict__ Fin, C2<
     }
     // the tile width too, so the per-stage strides derived from it are not all computed
     // once before the loop and held in scalar registers across it
-    if (FU) asm volatile("" : "+s"(ncol), "+s"(ncolpE));
-    const int i = fdiv(tidv, 1.0f / (float)ncol), c = tidv - i * ncol;   // column fastest
+    if (FU && NC == 0) asm volatile("" : "+s"(ncol), "+s"(ncolpE));
+    const int i = NC > 0 ? tidv / NC : fdiv(tidv, 1.0f / (float)ncol);
+    const int c = tidv - i * ncol;   // column fastest
     const bool valid = i < tl;
     const int col = tile * ncol + c;
     const bool colok = col < ncols;
@@ -942,7 +945,7 @@ k_xsandwich(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T* __
 // spectra are built once into LDS and shared by them: the factor U1 is read once per
 // tile, not once per right-hand side); tiles XCD-contiguous in the column
 // order.
-template <typename T, int NIN, int NOUT, int RS, int PID = 0>
+template <typename T, int NIN, int NOUT, int RS, int PID = 0, int NC = 0>
 __global__ void __launch_bounds__(sand_max_threads_fixed(PID, (int)sizeof(T), NIN),
                                   sand_max_threads_fixed(PID, (int)sizeof(T), NIN) == 1024
                                       ? 4
@@ -953,8 +956,9 @@ k_xsandwich_tk(const C2<T>* __restrict__ Fin, C2<T>* __restrict__ Fout, const T*
   if (PID > 0 && (a.Mx != kSandFixed[PID].L || a.nst != kSandFixed[PID].nst || a.radpack != sand_fixed_pack(PID) ||
                   a.tl * RS != a.Mx))
     return;
+  if (NC > 0 && a.ncol != NC) return;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  sandwich_body<T, NIN, NOUT, RS, PID, 1>(Fin, Fout, R, a, twg, phx, pflag, tile, 0, a.nrhs);
+  sandwich_body<T, NIN, NOUT, RS, PID, 1, NC>(Fin, Fout, R, a, twg, phx, pflag, tile, 0, a.nrhs);
 }
 
 // several scenes in one launch: linear workgroup -> (scene, tile, rhs), XCD-contiguous
@@ -1007,7 +1011,12 @@ hipError_t launch_sandwich_rs(const void* Fin, void* Fout, const void* R, const 
     if constexpr (sand_fixed_last(ID) == RR) {
       if (a.Mx == kSandFixed[ID].L && a.nst == kSandFixed[ID].nst && a.radpack == sand_fixed_pack(ID) &&
           a.tl * RR == a.Mx) {
-        if constexpr (TK) return go(k_xsandwich_tk<T, NIN, NOUT, RR, ID>);
+        if constexpr (TK) {
+          // the FP32 three-input wide kernels also come with the 4-column tile compiled in
+          if constexpr (sizeof(T) == 4 && NIN == 3 && kSandFixed[ID].wide)
+            if (a.ncol == 4) return go(k_xsandwich_tk<T, NIN, NOUT, RR, ID, 4>);
+          return go(k_xsandwich_tk<T, NIN, NOUT, RR, ID>);
+        }
         else return go(k_xsandwich<T, NIN, NOUT, RR, ID>);
       }
     }
