@@ -226,11 +226,18 @@ static vc_status y_pass(vc_problem* P, PrecTables& tb, void* data, void* scratch
   int ythr = 0;
   const bool yok = ypass_config(My, (int)sizeof(T), H, kLdsBudget, &ya, &ythr);
   const int ydef = ya.ncol;
-  // register-edge tile of c columns: threads c L/RS rounded up to waves (<= 1024), LDS
-  // twiddles + [L][c + 1] tile within the budget
+  // threads of a tile of c columns: L/RS per column, or per pair of columns where the
+  // kernel gives each thread two (compiled FP32 plans, even widths), rounded up to waves
+  auto ythreads = [&](int c) -> int {
+    const int cpt = ypass_cols_per_thread(ya.L, ya.nst, ya.radpack, ya.tl, c, (int)sizeof(T));
+    return (c / cpt * ya.tl + 63) / 64 * 64;
+  };
+  if (yok) ythr = ythreads(ydef);
+  // register-edge tile of c columns: at most 1024 threads, LDS twiddles + [L][c + 1]
+  // tile within the budget
   auto ytile = [&](int c, int* thr) -> bool {
     if (!yok || c < 1 || c > 32 || c > H) return false;
-    const int t = (c * ya.tl + 63) / 64 * 64;
+    const int t = ythreads(c);
     if (t > 1024 || (size_t)eb * ((size_t)My + (size_t)My * (c + 1)) > kLdsBudget) return false;
     *thr = t;
     return true;

@@ -81,7 +81,9 @@ struct YScene {
   int c0, gx, gy, blk0;   // first column; tiles, planes; first linear workgroup
 };
 template <typename T>
-bool ypass_args_ok(const YArgs& a, int nthr, bool flags, size_t* lds);
+// cpt: columns per thread of the kernel that will run (ypass_cols_per_thread; the
+// multi-scene kernel always takes 1)
+bool ypass_args_ok(const YArgs& a, int nthr, bool flags, size_t* lds, int cpt = 1);
 template <typename T>
 hipError_t launch_ypass_multi(const YScene* tab, int nscene, int nblocks, int rs, int nthr, size_t lds,
                               const int* skip, const int* act, hipStream_t st);
@@ -181,6 +183,13 @@ constexpr int sand_max_threads_fixed(int id, int elem, int nin) {
 }
 inline int sand_max_threads(int L, int nst, uint32_t radpack, int elem, int nin) {
   return sand_max_threads_fixed(sand_fixed_id(L, nst, radpack), elem, nin);
+}
+// Columns per thread of the single-scene register-edge y pass: 2 for FP32 tiles of even
+// width whose plan is compiled (each thread transforms two adjacent columns, so a tile
+// needs half the threads), else 1.
+inline int ypass_cols_per_thread(int L, int nst, uint32_t radpack, int tl, int ncol, int elem) {
+  const int id = sand_fixed_id(L, nst, radpack);
+  return (elem == 4 && id > 0 && ncol % 2 == 0 && tl * sand_fixed_last(id) == L) ? 2 : 1;
 }
 
 template <typename T>

@@ -195,6 +195,228 @@ __device__ __forceinline__ void ypass_body(C2<T>* __restrict__ data, const YArgs
   }
 }
 
+// Two adjacent columns per thread (FP32, compiled plans, even tile widths): thread
+// (i, cp) owns butterfly i of columns 2 cp and 2 cp + 1, so the index arithmetic, row
+// flags and twiddles of a butterfly serve both columns and a tile needs half the waves.
+// Same stages, masks and phases as ypass_body.
+template <typename T, int R>
+__device__ __forceinline__ void tw_mul2(C2<T>* v0, C2<T>* v1, const char* __restrict__ twb, uint32_t tsb, T sg) {
+  C2<T> w[R];
+  uint32_t o = 0;
+#pragma unroll
+  for (int q = 1; q < R; ++q) {
+    o += tsb;
+    w[q] = lds_ld<T>(twb, o);
+  }
+#pragma unroll
+  for (int q = 1; q < R; ++q) {
+    w[q].y *= -sg;
+    v0[q] = cmul(v0[q], w[q]);
+    v1[q] = cmul(v1[q], w[q]);
+  }
+}
+
+// a middle Stockham stage of radix R (p = product of the earlier radices) on both
+// columns, in place in LDS: reads, barrier, writes, barrier
+template <typename T, int L, int R, int P>
+__device__ __forceinline__ void yp_mid2(char* __restrict__ lds, const char* __restrict__ twb, int i, uint32_t rbase,
+                                        uint32_t cE, uint32_t ncolpE, T sg) {
+  constexpr uint32_t E = sizeof(C2<T>);
+  constexpr int LR = L / R;
+  asm volatile("" : "+v"(i), "+v"(rbase));   // keep this stage's address arithmetic here
+  const bool act = i < LR;
+  C2<T> v0[R], v1[R];
+  uint32_t wb = 0;
+  if (act) {
+    const uint32_t rstride = (uint32_t)LR * ncolpE;
+    uint32_t o = rbase;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      v0[q] = lds_ld<T>(lds, o);
+      v1[q] = lds_ld<T>(lds, o + E);
+      o += rstride;
+    }
+    const int ip = i / P, k = i - ip * P;
+    tw_mul2<T, R>(v0, v1, twb, (uint32_t)(k * (LR / P)) * E, sg);
+    Dft<T, R>::run(v0, sg);
+    Dft<T, R>::run(v1, sg);
+    wb = (uint32_t)(ip * P * R + k) * ncolpE + cE;
+  }
+  __syncthreads();
+  if (act) {
+    const uint32_t wstride = (uint32_t)P * ncolpE;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      lds_st<T>(lds, wb, v0[Dft<T, R>::pos(q)]);
+      lds_st<T>(lds, wb + E, v1[Dft<T, R>::pos(q)]);
+      wb += wstride;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int RS, int PID>
+__device__ __forceinline__ void ypass_body2(C2<T>* __restrict__ data, const YArgs& a, const C2<T>* __restrict__ twg,
+                                            const uint8_t* __restrict__ lflag, const uint8_t* __restrict__ pflag,
+                                            const int* __restrict__ act, int tile, int plane, int bz) {
+  constexpr SandFixedPlan PD = kSandFixed[PID];
+  constexpr int L = PD.L, TL = PD.L / RS, S = PD.nst, R0 = PD.r[0], LR0 = PD.L / PD.r[0];
+  static_assert(PID > 0 && S >= 2 && S <= 4 && PD.r[S - 1] == RS, "compiled plans of 2 to 4 stages");
+  constexpr uint32_t E = sizeof(C2<T>);
+  const int cz = bz / a.nrhs, rhs = bz - cz * a.nrhs;
+  if (act && !act[rhs]) return;   // uniform per workgroup
+  const int comp = a.cs.comp[cz], axis = a.cs.axis[cz];
+  const int min_ = a.cs.min_[cz], mout = a.cs.mout[cz];
+  const int need = a.inverse ? mout : min_;
+  if (pflag && need && !(pflag[axis * a.n1x + plane] & need)) return;   // uniform per workgroup
+  extern __shared__ char smem_raw[];
+  const T sg = a.inverse ? T(1) : T(-1);
+  const int ncol = a.ncol, npair = ncol >> 1;
+  const uint32_t ncolpE = (uint32_t)(ncol + 1) * E;
+  char* twb = smem_raw;                       // L twiddles
+  char* lds = smem_raw + (size_t)L * E;       // [L][ncol + 1] tile
+  const int tid = threadIdx.x;
+  const int i = fdiv(tid, 1.0f / (float)npair), cp = tid - i * npair;   // column pairs fastest
+  const bool valid = i < TL;
+  const int c0 = 2 * cp;
+  const int col0 = tile * ncol + c0;
+  const bool ok0 = col0 < a.ncols, ok1 = col0 + 1 < a.ncols;
+  const int colc = ok0 ? col0 : a.ncols - 1;
+  const Buf base = make_buf(data + comp * a.comp_stride + rhs * a.rhs_stride + plane * a.plane_stride,
+                            (uint32_t)a.plane_stride * E);
+  const uint8_t* lf = lflag ? lflag + ((int64_t)axis * a.n1x + plane) * a.n1y : nullptr;
+  const C2<T>* __restrict__ ph = (a.ph && axis == a.phax) ? static_cast<const C2<T>*>(a.ph) : nullptr;
+  const uint32_t rowb = (uint32_t)a.row_stride * E;
+  const bool act0 = i < LR0;
+  for (int t = tid; t < L; t += blockDim.x) lds_st<T>(twb, (uint32_t)t * E, twg[t]);
+  // rows of the first stage's inputs that are stored and of the last stage's outputs
+  // that are needed (the same rows for both columns; a column past the end has none)
+  uint32_t inmask = 0u, outmask = 0u;
+  if (ok0) {
+    if (act0)
+#pragma unroll
+      for (int q = 0; q < R0; ++q) {
+        const int r = i + q * LR0;
+        if (r < a.nin && (!lf || !min_ || (lf[r] & min_))) inmask |= 1u << q;
+      }
+    if (valid)
+#pragma unroll
+      for (int m = 0; m < RS; ++m) {
+        const int r = i + m * TL;
+        if (r < a.nout && (!lf || !mout || (lf[r] & mout))) outmask |= 1u << m;
+      }
+  }
+  const uint32_t inmask1 = ok1 ? inmask : 0u, outmask1 = ok1 ? outmask : 0u;
+  const uint32_t cE = (uint32_t)c0 * E;
+  const uint32_t rbase = (uint32_t)i * ncolpE + cE;
+  const uint32_t gbase = (uint32_t)colc * E + (uint32_t)i * rowb;
+  // first stage (radix R0, p = 1): HBM rows i + q L/R0 -> registers -> LDS rows i R0 + q
+  C2<T> u0[R0], u1[R0];
+  if (act0) {
+    const uint32_t gstride = (uint32_t)LR0 * rowb;
+    uint32_t o = gbase;
+#pragma unroll
+    for (int q = 0; q < R0; ++q) {
+      u0[q] = bld<T>(base, (inmask & (1u << q)) ? o : kOob);
+      u1[q] = bld<T>(base, (inmask1 & (1u << q)) ? o + E : kOob);
+      o += gstride;
+    }
+  }
+  __syncthreads();   // twiddles in LDS
+  if (act0) {
+    if (ph && a.inverse) {
+#pragma unroll
+      for (int q = 0; q < R0; ++q) {
+        const C2<T> w = cconj(ph[i + q * LR0]);
+        u0[q] = cmul(u0[q], w);
+        u1[q] = cmul(u1[q], w);
+      }
+    }
+    Dft<T, R0>::run(u0, sg);
+    Dft<T, R0>::run(u1, sg);
+    uint32_t o = (uint32_t)i * (uint32_t)R0 * ncolpE + cE;
+    asm volatile("" : "+v"(o));
+#pragma unroll
+    for (int q = 0; q < R0; ++q) {
+      lds_st<T>(lds, o, u0[Dft<T, R0>::pos(q)]);
+      lds_st<T>(lds, o + E, u1[Dft<T, R0>::pos(q)]);
+      o += ncolpE;
+    }
+  }
+  __syncthreads();
+  if constexpr (S >= 3) yp_mid2<T, L, PD.r[1], PD.r[0]>(lds, twb, i, rbase, cE, ncolpE, sg);
+  if constexpr (S >= 4) yp_mid2<T, L, PD.r[2], PD.r[0] * PD.r[1]>(lds, twb, i, rbase, cE, ncolpE, sg);
+  if (valid) {
+    // last stage (radix RS, p = L/RS): rows i + m TL, twiddle exponent m i, outputs
+    // X[i + m TL] straight to HBM
+    C2<T> v0[RS], v1[RS];
+    const uint32_t st = (uint32_t)TL * ncolpE;
+    uint32_t o = rbase;
+#pragma unroll
+    for (int m = 0; m < RS; ++m) {
+      v0[m] = lds_ld<T>(lds, o);
+      v1[m] = lds_ld<T>(lds, o + E);
+      o += st;
+    }
+    tw_mul2<T, RS>(v0, v1, twb, (uint32_t)i * E, sg);
+    Dft<T, RS>::run(v0, sg);
+    Dft<T, RS>::run(v1, sg);
+    if (ph && !a.inverse) {
+#pragma unroll
+      for (int m = 0; m < RS; ++m) {
+        const C2<T> w = ph[i + m * TL];
+        v0[Dft<T, RS>::pos(m)] = cmul(v0[Dft<T, RS>::pos(m)], w);
+        v1[Dft<T, RS>::pos(m)] = cmul(v1[Dft<T, RS>::pos(m)], w);
+      }
+    }
+    uint32_t og = gbase;
+    const uint32_t gs = (uint32_t)TL * rowb;
+#pragma unroll
+    for (int m = 0; m < RS; ++m) {
+      bst<T>(base, (outmask & (1u << m)) ? og : kOob, v0[Dft<T, RS>::pos(m)]);
+      bst<T>(base, (outmask1 & (1u << m)) ? og + E : kOob, v1[Dft<T, RS>::pos(m)]);
+      og += gs;
+    }
+  }
+}
+
+// workgroup -> (tile, plane, component x rhs); with XCD grouping (a.xg) the G
+// consecutive tiles of a row, whose rows share cache lines, go to workgroups w, w + 8,
+// ..., w + 8 (G - 1), which sit on one XCD and start together (a bijection on the
+// largest multiple of 8 G; the rest keep their order); xg < 0: G = every tile of the row
+__device__ __forceinline__ void ypass_coords(const YArgs& a, int* tile, int* plane, int* bz) {
+  *tile = blockIdx.x;
+  *plane = blockIdx.y;
+  *bz = blockIdx.z;
+  if (a.xg > 1 || (a.xg < 0 && gridDim.x > 1)) {
+    const uint32_t gx = gridDim.x, gy = gridDim.y, G = a.xg > 0 ? (uint32_t)a.xg : gx, span = 8u * G;
+    const uint32_t W = gx * gy * gridDim.z;
+    const uint32_t w = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    uint32_t l = w;
+    if (w < W / span * span) {
+      const uint32_t k = w >> 3;
+      l = (k / G) * span + (w & 7u) * G + k % G;
+    }
+    *tile = (int)(l % gx);
+    const uint32_t r = l / gx;
+    *plane = (int)(r % gy);
+    *bz = (int)(r / gy);
+  }
+}
+
+template <typename T, int RS, int PID>
+__global__ void __launch_bounds__(1024)
+k_ypass2(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const uint8_t* __restrict__ lflag,
+         const uint8_t* __restrict__ pflag) {
+  if (a.skip && *a.skip) return;
+  if (a.L != kSandFixed[PID].L || a.nst != kSandFixed[PID].nst || a.radpack != sand_fixed_pack(PID) ||
+      a.tl * RS != a.L || (a.ncol & 1))
+    return;
+  int tile, plane, bz;
+  ypass_coords(a, &tile, &plane, &bz);
+  ypass_body2<T, RS, PID>(data, a, twg, lflag, pflag, a.act, tile, plane, bz);
+}
+
 template <typename T, int RS, int PID = 0>
 __global__ void __launch_bounds__(1024)
 k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const uint8_t* __restrict__ lflag,
@@ -247,11 +469,24 @@ k_ypass_multi(const YScene* __restrict__ tab, int nscene, const int* __restrict_
 // equals the runtime plan, else the generic one
 template <typename T, int RR, int ID>
 hipError_t launch_ypass_rs(void* data, const YArgs& a, const void* tw, const uint8_t* lflag, const uint8_t* pflag,
-                           dim3 grid, int nthr, size_t lds, hipStream_t st) {
+                           dim3 grid, int nthr, size_t lds, int cpt, hipStream_t st) {
   if constexpr (ID < kSandNumFixed) {
     if constexpr (sand_fixed_last(ID) == RR) {
       if (a.L == kSandFixed[ID].L && a.nst == kSandFixed[ID].nst && a.radpack == sand_fixed_pack(ID) &&
           a.tl * RR == a.L) {
+        if constexpr (sizeof(T) == 4 && kSandFixed[ID].nst >= 2 && kSandFixed[ID].nst <= 4) {
+          if (cpt == 2) {
+            if (lds > kLdsBudget) {
+              const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ypass2<T, RR, ID>),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+              if (e != hipSuccess) return e;
+            }
+            hipLaunchKernelGGL((k_ypass2<T, RR, ID>), grid, dim3(nthr), lds, st, (C2<T>*)data, a,
+                               (const C2<T>*)tw, lflag, pflag);
+            return hipGetLastError();
+          }
+        }
+        if (cpt != 1) return hipErrorInvalidValue;
         if (lds > kLdsBudget) {
           const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ypass<T, RR, ID>),
                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -262,8 +497,9 @@ hipError_t launch_ypass_rs(void* data, const YArgs& a, const void* tw, const uin
         return hipGetLastError();
       }
     }
-    return launch_ypass_rs<T, RR, ID + 1>(data, a, tw, lflag, pflag, grid, nthr, lds, st);
+    return launch_ypass_rs<T, RR, ID + 1>(data, a, tw, lflag, pflag, grid, nthr, lds, cpt, st);
   } else {
+    if (cpt != 1) return hipErrorInvalidValue;
     if (lds > kLdsBudget) {
       const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ypass<T, RR, 0>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -277,7 +513,7 @@ hipError_t launch_ypass_rs(void* data, const YArgs& a, const void* tw, const uin
 
 // every assumption of the kernel on its arguments, the LDS bytes it needs in *lds
 template <typename T>
-bool ypass_args_ok(const YArgs& a, int nthr, bool flags, size_t* lds_out) {
+bool ypass_args_ok(const YArgs& a, int nthr, bool flags, size_t* lds_out, int cpt) {
   if (a.nst < 1 || a.nst > kSandMaxStages || a.ncol < 1 || a.ncol > 32 || nthr < 64 || nthr > 1024 || (nthr & 63) ||
       a.cs.n < 1 || a.cs.n > 6 || a.nrhs < 1 || !(a.xg >= -1 && a.xg <= 4 && a.xg != 3))
     return false;
@@ -289,7 +525,8 @@ bool ypass_args_ok(const YArgs& a, int nthr, bool flags, size_t* lds_out) {
     prev = r;
     prod *= r;
   }
-  if (prod != a.L || (long)a.tl * prev != a.L || (long)a.tl * a.ncol > nthr) return false;
+  if (cpt != 1 && (cpt != 2 || a.ncol % 2 != 0)) return false;
+  if (prod != a.L || (long)a.tl * prev != a.L || (long)a.tl * (a.ncol / cpt) > nthr) return false;
   if (a.nin > a.L || a.nout > a.L) return false;
   if (flags)
     for (int q = 0; q < a.cs.n; ++q)
@@ -328,12 +565,13 @@ hipError_t launch_ypass(void* data, const YArgs& a, const void* tw, const uint8_
                         int nplanes, int nthr, hipStream_t st) {
   // every assumption of the kernel (plan, tile, flag rows, 32-bit slab offsets, LDS)
   size_t lds = 0;
-  if (!ypass_args_ok<T>(a, nthr, lflag != nullptr, &lds)) return hipErrorInvalidValue;
+  const int cpt = ypass_cols_per_thread(a.L, a.nst, a.radpack, a.tl, a.ncol, (int)sizeof(T));
+  if (!ypass_args_ok<T>(a, nthr, lflag != nullptr, &lds, cpt)) return hipErrorInvalidValue;
   const int rs = (int)((a.radpack >> (5 * (a.nst - 1))) & 31u);
   dim3 grid((a.ncols + a.ncol - 1) / a.ncol, nplanes, a.cs.n * a.nrhs);
 #define VC_RS(RR)                                                                                \
   case RR:                                                                                       \
-    return launch_ypass_rs<T, RR, 1>(data, a, tw, lflag, pflag, grid, nthr, lds, st);
+    return launch_ypass_rs<T, RR, 1>(data, a, tw, lflag, pflag, grid, nthr, lds, cpt, st);
   switch (rs) {
     VC_RS(2) VC_RS(3) VC_RS(4) VC_RS(5) VC_RS(6) VC_RS(7) VC_RS(8) VC_RS(9) VC_RS(10)
     default: break;

@@ -222,6 +222,18 @@ def test_ypass_compiled_plans_match_dense(dev, name, make):
     # the default there is the LDS-tile kernel (the autotuner may still pick one column)
     need = [l for l in rep if name != "y1050" or "fp32" in l]
     assert need and all("register-edge" in l for l in need), rep
+    # pinned tile widths: one column per thread, and (FP32, even widths) two adjacent
+    # columns per thread; a width that does not fit falls back to the default tile
+    for prec, tol in (("fp64", 1e-11), ("fp32", 2e-5)):
+        for transpose in (False, True):
+            ref = ((A.T if transpose else A) @ x.T).T
+            for cols in (1, 2, 4, 8):
+                for inverse in (False, True):
+                    P.ypass_set(1, cols, -1, prec=prec, transpose=transpose, inverse=inverse, nrhs=2)
+                y = P.apply(xt, transpose=transpose, prec=prec).cpu().numpy()
+                err = np.abs(y - ref).max() / np.abs(ref).max()
+                assert err < tol, (name, prec, transpose, cols, err)
+        print(name, prec, "pinned widths 1, 2, 4, 8 within", tol, flush=True)
 
 
 def test_ypass_xcd_groups_match_dense(dev):
