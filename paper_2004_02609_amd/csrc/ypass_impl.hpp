@@ -195,12 +195,13 @@ __device__ __forceinline__ void ypass_body(C2<T>* __restrict__ data, const YArgs
   }
 }
 
-// Two adjacent columns per thread (FP32, compiled plans, even tile widths): thread
-// (i, cp) owns butterfly i of columns 2 cp and 2 cp + 1, so the index arithmetic, row
-// flags and twiddles of a butterfly serve both columns and a tile needs half the waves.
-// Same stages, masks and phases as ypass_body.
-template <typename T, int R>
-__device__ __forceinline__ void tw_mul2(C2<T>* v0, C2<T>* v1, const char* __restrict__ twb, uint32_t tsb, T sg) {
+// Several adjacent columns per thread (FP32, compiled plans, tile widths a multiple of
+// CPT): thread (i, g) owns butterfly i of columns CPT g .. CPT g + CPT - 1, so the index
+// arithmetic, row flags and twiddle reads of a butterfly serve all of them and a tile
+// needs 1/CPT of the waves.  Same stages, masks and phases as ypass_body.  Launched with
+// CPT = 2 (four columns per thread measured slower: 80-110 VGPRs, 4-6 waves per SIMD).
+template <typename T, int R, int CPT>
+__device__ __forceinline__ void tw_mul_n(C2<T> (&v)[CPT][R], const char* __restrict__ twb, uint32_t tsb, T sg) {
   C2<T> w[R];
   uint32_t o = 0;
 #pragma unroll
@@ -211,35 +212,35 @@ __device__ __forceinline__ void tw_mul2(C2<T>* v0, C2<T>* v1, const char* __rest
 #pragma unroll
   for (int q = 1; q < R; ++q) {
     w[q].y *= -sg;
-    v0[q] = cmul(v0[q], w[q]);
-    v1[q] = cmul(v1[q], w[q]);
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) v[j][q] = cmul(v[j][q], w[q]);
   }
 }
 
-// a middle Stockham stage of radix R (p = product of the earlier radices) on both
-// columns, in place in LDS: reads, barrier, writes, barrier
-template <typename T, int L, int R, int P>
-__device__ __forceinline__ void yp_mid2(char* __restrict__ lds, const char* __restrict__ twb, int i, uint32_t rbase,
-                                        uint32_t cE, uint32_t ncolpE, T sg) {
+// a middle Stockham stage of radix R (p = product of the earlier radices) on the
+// thread's columns, in place in LDS: reads, barrier, writes, barrier
+template <typename T, int L, int R, int P, int CPT>
+__device__ __forceinline__ void yp_mid_n(char* __restrict__ lds, const char* __restrict__ twb, int i, uint32_t rbase,
+                                         uint32_t cE, uint32_t ncolpE, T sg) {
   constexpr uint32_t E = sizeof(C2<T>);
   constexpr int LR = L / R;
   asm volatile("" : "+v"(i), "+v"(rbase));   // keep this stage's address arithmetic here
   const bool act = i < LR;
-  C2<T> v0[R], v1[R];
+  C2<T> v[CPT][R];
   uint32_t wb = 0;
   if (act) {
     const uint32_t rstride = (uint32_t)LR * ncolpE;
     uint32_t o = rbase;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      v0[q] = lds_ld<T>(lds, o);
-      v1[q] = lds_ld<T>(lds, o + E);
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) v[j][q] = lds_ld<T>(lds, o + j * E);
       o += rstride;
     }
     const int ip = i / P, k = i - ip * P;
-    tw_mul2<T, R>(v0, v1, twb, (uint32_t)(k * (LR / P)) * E, sg);
-    Dft<T, R>::run(v0, sg);
-    Dft<T, R>::run(v1, sg);
+    tw_mul_n<T, R, CPT>(v, twb, (uint32_t)(k * (LR / P)) * E, sg);
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) Dft<T, R>::run(v[j], sg);
     wb = (uint32_t)(ip * P * R + k) * ncolpE + cE;
   }
   __syncthreads();
@@ -247,18 +248,18 @@ __device__ __forceinline__ void yp_mid2(char* __restrict__ lds, const char* __re
     const uint32_t wstride = (uint32_t)P * ncolpE;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      lds_st<T>(lds, wb, v0[Dft<T, R>::pos(q)]);
-      lds_st<T>(lds, wb + E, v1[Dft<T, R>::pos(q)]);
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) lds_st<T>(lds, wb + j * E, v[j][Dft<T, R>::pos(q)]);
       wb += wstride;
     }
   }
   __syncthreads();
 }
 
-template <typename T, int RS, int PID>
-__device__ __forceinline__ void ypass_body2(C2<T>* __restrict__ data, const YArgs& a, const C2<T>* __restrict__ twg,
-                                            const uint8_t* __restrict__ lflag, const uint8_t* __restrict__ pflag,
-                                            const int* __restrict__ act, int tile, int plane, int bz) {
+template <typename T, int RS, int PID, int CPT>
+__device__ __forceinline__ void ypass_body_n(C2<T>* __restrict__ data, const YArgs& a, const C2<T>* __restrict__ twg,
+                                             const uint8_t* __restrict__ lflag, const uint8_t* __restrict__ pflag,
+                                             const int* __restrict__ act, int tile, int plane, int bz) {
   constexpr SandFixedPlan PD = kSandFixed[PID];
   constexpr int L = PD.L, TL = PD.L / RS, S = PD.nst, R0 = PD.r[0], LR0 = PD.L / PD.r[0];
   static_assert(PID > 0 && S >= 2 && S <= 4 && PD.r[S - 1] == RS, "compiled plans of 2 to 4 stages");
@@ -271,17 +272,16 @@ __device__ __forceinline__ void ypass_body2(C2<T>* __restrict__ data, const YArg
   if (pflag && need && !(pflag[axis * a.n1x + plane] & need)) return;   // uniform per workgroup
   extern __shared__ char smem_raw[];
   const T sg = a.inverse ? T(1) : T(-1);
-  const int ncol = a.ncol, npair = ncol >> 1;
+  const int ncol = a.ncol, ngrp = ncol / CPT;
   const uint32_t ncolpE = (uint32_t)(ncol + 1) * E;
   char* twb = smem_raw;                       // L twiddles
   char* lds = smem_raw + (size_t)L * E;       // [L][ncol + 1] tile
   const int tid = threadIdx.x;
-  const int i = fdiv(tid, 1.0f / (float)npair), cp = tid - i * npair;   // column pairs fastest
+  const int i = fdiv(tid, 1.0f / (float)ngrp), cg = tid - i * ngrp;   // column groups fastest
   const bool valid = i < TL;
-  const int c0 = 2 * cp;
+  const int c0 = CPT * cg;
   const int col0 = tile * ncol + c0;
-  const bool ok0 = col0 < a.ncols, ok1 = col0 + 1 < a.ncols;
-  const int colc = ok0 ? col0 : a.ncols - 1;
+  const int colc = col0 < a.ncols ? col0 : a.ncols - 1;
   const Buf base = make_buf(data + comp * a.comp_stride + rhs * a.rhs_stride + plane * a.plane_stride,
                             (uint32_t)a.plane_stride * E);
   const uint8_t* lf = lflag ? lflag + ((int64_t)axis * a.n1x + plane) * a.n1y : nullptr;
@@ -290,9 +290,9 @@ __device__ __forceinline__ void ypass_body2(C2<T>* __restrict__ data, const YArg
   const bool act0 = i < LR0;
   for (int t = tid; t < L; t += blockDim.x) lds_st<T>(twb, (uint32_t)t * E, twg[t]);
   // rows of the first stage's inputs that are stored and of the last stage's outputs
-  // that are needed (the same rows for both columns; a column past the end has none)
+  // that are needed (the same rows for every column of the thread)
   uint32_t inmask = 0u, outmask = 0u;
-  if (ok0) {
+  if (col0 < a.ncols) {
     if (act0)
 #pragma unroll
       for (int q = 0; q < R0; ++q) {
@@ -306,19 +306,26 @@ __device__ __forceinline__ void ypass_body2(C2<T>* __restrict__ data, const YArg
         if (r < a.nout && (!lf || !mout || (lf[r] & mout))) outmask |= 1u << m;
       }
   }
-  const uint32_t inmask1 = ok1 ? inmask : 0u, outmask1 = ok1 ? outmask : 0u;
+  // columns past the end read zero and store nothing
+  uint32_t cin[CPT], cout[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    const bool ok = col0 + j < a.ncols;
+    cin[j] = ok ? inmask : 0u;
+    cout[j] = ok ? outmask : 0u;
+  }
   const uint32_t cE = (uint32_t)c0 * E;
   const uint32_t rbase = (uint32_t)i * ncolpE + cE;
   const uint32_t gbase = (uint32_t)colc * E + (uint32_t)i * rowb;
   // first stage (radix R0, p = 1): HBM rows i + q L/R0 -> registers -> LDS rows i R0 + q
-  C2<T> u0[R0], u1[R0];
+  C2<T> u[CPT][R0];
   if (act0) {
     const uint32_t gstride = (uint32_t)LR0 * rowb;
     uint32_t o = gbase;
 #pragma unroll
     for (int q = 0; q < R0; ++q) {
-      u0[q] = bld<T>(base, (inmask & (1u << q)) ? o : kOob);
-      u1[q] = bld<T>(base, (inmask1 & (1u << q)) ? o + E : kOob);
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) u[j][q] = bld<T>(base, (cin[j] & (1u << q)) ? o + j * E : kOob);
       o += gstride;
     }
   }
@@ -328,53 +335,54 @@ __device__ __forceinline__ void ypass_body2(C2<T>* __restrict__ data, const YArg
 #pragma unroll
       for (int q = 0; q < R0; ++q) {
         const C2<T> w = cconj(ph[i + q * LR0]);
-        u0[q] = cmul(u0[q], w);
-        u1[q] = cmul(u1[q], w);
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) u[j][q] = cmul(u[j][q], w);
       }
     }
-    Dft<T, R0>::run(u0, sg);
-    Dft<T, R0>::run(u1, sg);
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) Dft<T, R0>::run(u[j], sg);
     uint32_t o = (uint32_t)i * (uint32_t)R0 * ncolpE + cE;
     asm volatile("" : "+v"(o));
 #pragma unroll
     for (int q = 0; q < R0; ++q) {
-      lds_st<T>(lds, o, u0[Dft<T, R0>::pos(q)]);
-      lds_st<T>(lds, o + E, u1[Dft<T, R0>::pos(q)]);
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) lds_st<T>(lds, o + j * E, u[j][Dft<T, R0>::pos(q)]);
       o += ncolpE;
     }
   }
   __syncthreads();
-  if constexpr (S >= 3) yp_mid2<T, L, PD.r[1], PD.r[0]>(lds, twb, i, rbase, cE, ncolpE, sg);
-  if constexpr (S >= 4) yp_mid2<T, L, PD.r[2], PD.r[0] * PD.r[1]>(lds, twb, i, rbase, cE, ncolpE, sg);
+  if constexpr (S >= 3) yp_mid_n<T, L, PD.r[1], PD.r[0], CPT>(lds, twb, i, rbase, cE, ncolpE, sg);
+  if constexpr (S >= 4) yp_mid_n<T, L, PD.r[2], PD.r[0] * PD.r[1], CPT>(lds, twb, i, rbase, cE, ncolpE, sg);
   if (valid) {
     // last stage (radix RS, p = L/RS): rows i + m TL, twiddle exponent m i, outputs
     // X[i + m TL] straight to HBM
-    C2<T> v0[RS], v1[RS];
+    C2<T> v[CPT][RS];
     const uint32_t st = (uint32_t)TL * ncolpE;
     uint32_t o = rbase;
 #pragma unroll
     for (int m = 0; m < RS; ++m) {
-      v0[m] = lds_ld<T>(lds, o);
-      v1[m] = lds_ld<T>(lds, o + E);
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) v[j][m] = lds_ld<T>(lds, o + j * E);
       o += st;
     }
-    tw_mul2<T, RS>(v0, v1, twb, (uint32_t)i * E, sg);
-    Dft<T, RS>::run(v0, sg);
-    Dft<T, RS>::run(v1, sg);
+    tw_mul_n<T, RS, CPT>(v, twb, (uint32_t)i * E, sg);
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) Dft<T, RS>::run(v[j], sg);
     if (ph && !a.inverse) {
 #pragma unroll
       for (int m = 0; m < RS; ++m) {
         const C2<T> w = ph[i + m * TL];
-        v0[Dft<T, RS>::pos(m)] = cmul(v0[Dft<T, RS>::pos(m)], w);
-        v1[Dft<T, RS>::pos(m)] = cmul(v1[Dft<T, RS>::pos(m)], w);
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) v[j][Dft<T, RS>::pos(m)] = cmul(v[j][Dft<T, RS>::pos(m)], w);
       }
     }
     uint32_t og = gbase;
     const uint32_t gs = (uint32_t)TL * rowb;
 #pragma unroll
     for (int m = 0; m < RS; ++m) {
-      bst<T>(base, (outmask & (1u << m)) ? og : kOob, v0[Dft<T, RS>::pos(m)]);
-      bst<T>(base, (outmask1 & (1u << m)) ? og + E : kOob, v1[Dft<T, RS>::pos(m)]);
+#pragma unroll
+      for (int j = 0; j < CPT; ++j)
+        bst<T>(base, (cout[j] & (1u << m)) ? og + j * E : kOob, v[j][Dft<T, RS>::pos(m)]);
       og += gs;
     }
   }
@@ -404,17 +412,17 @@ __device__ __forceinline__ void ypass_coords(const YArgs& a, int* tile, int* pla
   }
 }
 
-template <typename T, int RS, int PID>
+template <typename T, int RS, int PID, int CPT>
 __global__ void __launch_bounds__(1024)
-k_ypass2(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const uint8_t* __restrict__ lflag,
-         const uint8_t* __restrict__ pflag) {
+k_ypass_n(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const uint8_t* __restrict__ lflag,
+          const uint8_t* __restrict__ pflag) {
   if (a.skip && *a.skip) return;
   if (a.L != kSandFixed[PID].L || a.nst != kSandFixed[PID].nst || a.radpack != sand_fixed_pack(PID) ||
-      a.tl * RS != a.L || (a.ncol & 1))
+      a.tl * RS != a.L || a.ncol % CPT != 0)
     return;
   int tile, plane, bz;
   ypass_coords(a, &tile, &plane, &bz);
-  ypass_body2<T, RS, PID>(data, a, twg, lflag, pflag, a.act, tile, plane, bz);
+  ypass_body_n<T, RS, PID, CPT>(data, a, twg, lflag, pflag, a.act, tile, plane, bz);
 }
 
 template <typename T, int RS, int PID = 0>
@@ -475,16 +483,16 @@ hipError_t launch_ypass_rs(void* data, const YArgs& a, const void* tw, const uin
       if (a.L == kSandFixed[ID].L && a.nst == kSandFixed[ID].nst && a.radpack == sand_fixed_pack(ID) &&
           a.tl * RR == a.L) {
         if constexpr (sizeof(T) == 4 && kSandFixed[ID].nst >= 2 && kSandFixed[ID].nst <= 4) {
-          if (cpt == 2) {
+          auto go = [&](auto kernel) -> hipError_t {
             if (lds > kLdsBudget) {
-              const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ypass2<T, RR, ID>),
+              const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
               if (e != hipSuccess) return e;
             }
-            hipLaunchKernelGGL((k_ypass2<T, RR, ID>), grid, dim3(nthr), lds, st, (C2<T>*)data, a,
-                               (const C2<T>*)tw, lflag, pflag);
+            hipLaunchKernelGGL(kernel, grid, dim3(nthr), lds, st, (C2<T>*)data, a, (const C2<T>*)tw, lflag, pflag);
             return hipGetLastError();
-          }
+          };
+          if (cpt == 2) return go(k_ypass_n<T, RR, ID, 2>);
         }
         if (cpt != 1) return hipErrorInvalidValue;
         if (lds > kLdsBudget) {
@@ -525,7 +533,7 @@ bool ypass_args_ok(const YArgs& a, int nthr, bool flags, size_t* lds_out, int cp
     prev = r;
     prod *= r;
   }
-  if (cpt != 1 && (cpt != 2 || a.ncol % 2 != 0)) return false;
+  if (!(cpt == 1 || cpt == 2) || a.ncol % cpt != 0) return false;
   if (prod != a.L || (long)a.tl * prev != a.L || (long)a.tl * (a.ncol / cpt) > nthr) return false;
   if (a.nin > a.L || a.nout > a.L) return false;
   if (flags)
