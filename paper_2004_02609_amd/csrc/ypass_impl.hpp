@@ -388,10 +388,11 @@ __device__ __forceinline__ void ypass_body_n(C2<T>* __restrict__ data, const YAr
   }
 }
 
-// workgroup -> (tile, plane, component x rhs); with XCD grouping (a.xg) the G
-// consecutive tiles of a row, whose rows share cache lines, go to workgroups w, w + 8,
-// ..., w + 8 (G - 1), which sit on one XCD and start together (a bijection on the
-// largest multiple of 8 G; the rest keep their order); xg < 0: G = every tile of the row
+// workgroup -> (tile, plane, component x rhs).  Workgroups are issued to the 8 XCDs in
+// turn by linear id w; with XCD grouping (a.xg) the G consecutive tiles of a row, whose
+// rows share cache lines, go to w, w + 8, ..., w + 8 (G - 1), which sit on one XCD and
+// start together (a bijection on the largest multiple of 8 G; the rest keep their
+// order); xg < 0: G = every tile of the row.
 __device__ __forceinline__ void ypass_coords(const YArgs& a, int* tile, int* plane, int* bz) {
   *tile = blockIdx.x;
   *plane = blockIdx.y;
@@ -433,25 +434,8 @@ k_ypass(C2<T>* __restrict__ data, YArgs a, const C2<T>* __restrict__ twg, const 
   if (PID > 0 && (a.L != kSandFixed[PID].L || a.nst != kSandFixed[PID].nst || a.radpack != sand_fixed_pack(PID) ||
                   a.tl * RS != a.L))
     return;
-  int tile = blockIdx.x, plane = blockIdx.y, bz = blockIdx.z;
-  if (a.xg > 1 || (a.xg < 0 && gridDim.x > 1)) {
-    // workgroups are issued to the 8 XCDs in turn by linear id w: hand the G consecutive
-    // tiles of a row, whose rows share cache lines, to w, w + 8, ..., w + 8 (G - 1), which
-    // sit on one XCD and start together (a bijection on the largest multiple of 8 G; the
-    // rest keep their order).  xg < 0: G = every tile of the row.
-    const uint32_t gx = gridDim.x, gy = gridDim.y, G = a.xg > 0 ? (uint32_t)a.xg : gx, span = 8u * G;
-    const uint32_t W = gx * gy * gridDim.z;
-    const uint32_t w = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-    uint32_t l = w;
-    if (w < W / span * span) {
-      const uint32_t k = w >> 3;
-      l = (k / G) * span + (w & 7u) * G + k % G;
-    }
-    tile = (int)(l % gx);
-    const uint32_t r = l / gx;
-    plane = (int)(r % gy);
-    bz = (int)(r / gy);
-  }
+  int tile, plane, bz;
+  ypass_coords(a, &tile, &plane, &bz);
   ypass_body<T, RS, PID>(data, a, twg, lflag, pflag, a.act, tile, plane, bz);
 }
 
