@@ -220,9 +220,11 @@ def write_traffic(args):
     if copy_bytes <= 0:
         raise SystemExit("--write-traffic needs the --calib-copy-mib of the profiled runs")
     tname = "float" if args.prec == "fp32" else "double"
-    # the y pass runs on one of two kernels (the autotuner's choice): the timed steps'
-    # y launches are the last 2 x steps of either, alternating forward / inverse
-    kern = {"zfwd_scatter": ("k_zfwd<" + tname,), "y": ("k_strided<" + tname, "k_ypass<" + tname),
+    # the y pass runs on one of three kernels (the autotuner's choice; the register-edge
+    # kernel with one or two columns per thread): the timed steps' y launches are the
+    # last 2 x steps of them, alternating forward / inverse
+    kern = {"zfwd_scatter": ("k_zfwd<" + tname,),
+            "y": ("k_strided<" + tname, "k_ypass<" + tname, "k_ypass_n<" + tname),
             "x_sandwich_multiply": ("k_xsandwich<" + tname, "k_xsandwich_tk<" + tname),
             "zinv_gather": ("k_zinv<" + tname,)}
 
