@@ -101,9 +101,9 @@ typedef struct {
                           stream is being captured into a graph.                    */
   const char *tune_cache; /* optional tuning cache file (NULL: none): its matching
                           entries are loaded at setup (as vc_tuning_load; a missing
-                          file loads nothing), and every x-pass choice the autotuner
-                          makes afterwards is merged into it (as vc_tuning_save).
-                          The string is copied.                                      */
+                          file loads nothing), and every x- and y-pass choice the
+                          autotuner makes afterwards is merged into it (as
+                          vc_tuning_save).  The string is copied.                    */
 } vc_setup_opts;
 
 /* Solve options.  GMRES(restart) with the block-diagonal-diagonal preconditioner
@@ -361,12 +361,14 @@ vc_status vc_ypass_set(vc_problem *p, vc_precision prec, int transpose, int inve
                        int32_t kernel, int32_t cols, int32_t xcd_group);
 
 /* Tuning cache file (text, one line per choice).  vc_tuning_save merges this problem's
- * timed x-pass choices into `path` (replacing entries of the same shape, precision,
- * direction, nrhs and GPU architecture; written to path.tmp, then renamed) and reports
- * how many it wrote.  vc_tuning_load adopts every entry of `path` that matches this
- * problem's shape and architecture and is one of its own candidates (as if pinned by
- * vc_xpass_set, so those products skip the timing); a missing file loads nothing.
- * Both require vc_setup; a later vc_setup forgets what was loaded. */
+ * timed x-pass and y-pass choices into `path` (replacing entries of the same shape,
+ * precision, direction, nrhs and GPU architecture; written to path.tmp, then renamed)
+ * and reports how many it wrote.  vc_tuning_load adopts every entry of `path` that
+ * matches this problem's shape and architecture (an x-pass entry only if it is one of
+ * this problem's own candidates), as if pinned by vc_xpass_set / vc_ypass_set, so those
+ * passes skip the timing and a problem of the same shape computes bitwise the same
+ * products; it reports how many it adopted, and a missing file loads nothing.  Both
+ * require vc_setup; a later vc_setup forgets what was loaded. */
 vc_status vc_tuning_save(vc_problem *p, const char *path, int32_t *n_saved);
 vc_status vc_tuning_load(vc_problem *p, const char *path, int32_t *n_loaded);
 

@@ -662,9 +662,9 @@ vc_status vc_tuning_report(vc_problem* p, char* buf, int32_t len) {
                       (c.impl && (c.xg > 1 || c.xg < 0)) ? (c.xg < 0 ? std::string(" xcd_group=row")
                                                                     : " xcd_group=" + std::to_string(c.xg))
                                                          : std::string()).c_str(),
-                  c.tuned ? "tuned" : "default");
+                  c.from_file ? "cached" : (c.tuned ? "tuned" : "default"));
     out += line;
-    if (c.tuned) {
+    if (c.tuned || c.from_file) {
       std::snprintf(line, sizeof line, " lds_ms=%.4f register_ms=%.4f", c.ms[0], c.ms[1]);
       out += line;
     }

@@ -304,6 +304,12 @@ static vc_status y_pass(vc_problem* P, PrecTables& tb, void* data, void* scratch
       ch.tuned = true;
     }
     it = P->y_choice.emplace(key, ch).first;
+    // a tuning cache file given at setup takes every timed choice
+    if (ch.tuned && !P->tune_cache.empty()) {
+      int32_t ns = 0;
+      const vc_status ts = vc_tuning_save(P, P->tune_cache.c_str(), &ns);
+      if (ts != VC_OK) return ts;
+    }
   }
   VC_HIP(launch(it->second.impl, it->second.ncol, it->second.xg, data));
   return VC_OK;

@@ -271,6 +271,7 @@ struct vc_problem {
     double ms[2];
     int ncol;   // register-edge tile width (0: the heuristic's)
     int xg;     // consecutive tiles per XCD (YArgs::xg)
+    bool from_file = false;   // read from the tuning cache file
   };
   std::map<int, YChoice> y_choice;
   std::string tune_cache;   // tuning cache file of vc_setup_opts (empty: none)

@@ -711,11 +711,11 @@ class Problem:
         return vc_tuning_report(self._h)
 
     def save_tuning(self, path):
-        """Merge the timed x-pass choices into the cache file `path`; returns how many."""
+        """Merge the timed x- and y-pass choices into the cache file `path`; returns how many."""
         return vc_tuning_save(self._h, path)
 
     def load_tuning(self, path):
-        """Adopt the cached x-pass choices of `path` that fit this problem; returns how many."""
+        """Adopt the cached x- and y-pass choices of `path` that fit this problem; returns how many."""
         return vc_tuning_load(self._h, path)
 
     def pass_times(self):

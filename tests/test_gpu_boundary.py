@@ -24,9 +24,9 @@ def dev():
 
 
 def test_setup_tune_cache_saves_and_loads(dev):
-    """tune_cache in the setup options: the first problem's timed x-pass choices land in
-    the file; a second problem of the same shape loads them at setup (no timing) and
-    computes bitwise the same products."""
+    """tune_cache in the setup options: the first problem's timed x- and y-pass choices
+    land in the file; a second problem of the same shape loads them at setup (no timing)
+    and computes bitwise the same products."""
     from paper_2004_02609_amd import voxcap
     s = scenes.random_small(9, shape=(11, 7, 13), n_cond=3, n_diel=2)
     with tempfile.TemporaryDirectory() as d:
@@ -38,13 +38,18 @@ def test_setup_tune_cache_saves_and_loads(dev):
             for transpose in (False, True):
                 yp[prec, transpose] = P.apply(x, transpose=transpose, prec=prec).cpu().numpy()
         assert os.path.exists(path)
-        assert len(open(path).read().splitlines()) == 4
+        lines = open(path).read().splitlines()
+        # x: 2 precisions x 2 directions; y: the same x forward / inverse transforms
+        assert sum(l.startswith("vc-xpass") for l in lines) == 4, lines
+        assert sum(l.startswith("vc-ypass") for l in lines) == 8, lines
         Q = voxcap.Problem.from_scene(s).setup(max_rhs=2, autotune=True, tune_cache=path)
         for (prec, transpose), y in yp.items():
             assert np.array_equal(Q.apply(x, transpose=transpose, prec=prec).cpu().numpy(), y)
         rq = Q.tuning_report()
         xq = [l for l in rq.splitlines() if l.startswith("x-pass")]
+        yq = [l for l in rq.splitlines() if l.startswith("y-pass")]
         assert sum("cached" in l for l in xq) == 4 and sum("tuned" in l for l in xq) == 0, rq
+        assert sum("cached" in l for l in yq) == 8 and sum("tuned" in l for l in yq) == 0, rq
 
 
 def test_stats_bytes_model_is_the_pass_model(dev):

@@ -312,17 +312,17 @@ def test_autotuned_product_matches_dense(dev):
     xlines = [l for l in rep.splitlines() if l.startswith("x-pass")]
     assert sum("tuned" in l for l in xlines) == 4, rep
     assert any(l.startswith("y-pass") for l in rep.splitlines()), rep
-    # the tuning cache file: a second problem of the same shape adopts the four choices
-    # without timing and computes the same products
+    # the tuning cache file: a second problem of the same shape adopts the four x-pass
+    # and eight y-pass choices without timing and computes bitwise the same products
     import os
     import tempfile
     with tempfile.TemporaryDirectory() as d:
-        path = os.path.join(d, "xpass.txt")
-        assert P.save_tuning(path) == 4
-        assert P.save_tuning(path) == 4                      # merge replaces, never duplicates
-        assert len(open(path).read().splitlines()) == 4
+        path = os.path.join(d, "tuning.txt")
+        assert P.save_tuning(path) == 12
+        assert P.save_tuning(path) == 12                     # merge replaces, never duplicates
+        assert len(open(path).read().splitlines()) == 12
         Q = _problem(s, max_rhs=2, autotune=True)
-        assert Q.load_tuning(path) == 4
+        assert Q.load_tuning(path) == 12
         other = _problem(scenes.random_small(21, shape=(2, 6, 5), n_cond=1, n_diel=1), max_rhs=2)
         assert other.load_tuning(path) == 0                  # another shape takes nothing
         assert Q.load_tuning(os.path.join(d, "missing.txt")) == 0
@@ -334,7 +334,9 @@ def test_autotuned_product_matches_dense(dev):
     rq = Q.tuning_report()
     print(rq, flush=True)
     xq = [l for l in rq.splitlines() if l.startswith("x-pass")]
+    yq = [l for l in rq.splitlines() if l.startswith("y-pass")]
     assert sum("cached" in l for l in xq) == 4 and sum("tuned" in l for l in xq) == 0, rq
+    assert sum("cached" in l for l in yq) == 8 and sum("tuned" in l for l in yq) == 0, rq
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
