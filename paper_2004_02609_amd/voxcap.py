@@ -707,7 +707,7 @@ class Problem:
         return vc_tucker_info(self._h)
 
     def tuning_report(self):
-        """Launch configurations of the x pass in use (and what the autotuner measured)."""
+        """Launch configurations of the x and y passes in use (and what the autotuner measured)."""
         return vc_tuning_report(self._h)
 
     def save_tuning(self, path):
